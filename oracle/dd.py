@@ -1,0 +1,215 @@
+"""Non-overlapping checkerboard decomposition and the interface problem (paper Secs. 3-4).
+
+Subdomain i = (i1, i2) (1-based, i1 = column in x, i2 = row in y) owns the nodes
+ix in [(i1-1) snx, i1 snx), iy in [(i2-1) sny, i2 sny), numbered locally
+ly * snx + lx.  Its local problem (Sec. 3, eq. (2)) is the 5-point operator on
+its own nodes with the Robin face template (see ``oracle.fd``) on every face:
+outer faces carry the absorbing condition (data 0, alpha = k sqrt(m_p)) and
+interface faces carry the transmission data g received from the neighbour, with
+alpha_f = k sqrt((m_p + m_q)/2), the same value seen from both sides.
+
+The data that i sends to a neighbour j through face (p in i, q in j) is the
+Robin data j's own condition would see, (-d_{n_ij} - T) u_i, which with the face
+template is  out_q = -rho g_p - sigma u_p  (g_p the data i received on the same
+face).  Summed over the faces of i this is the local scattering operator of
+Sec. 4, including the reflection term k = j.
+
+Pins (tests/test_oracle_dd.py): the reconstructed u equals the global direct
+solve to round-off on every decomposition (1 x 1 included); the traces of the
+global solution satisfy (I - S) g = b exactly; the dense S has the group
+structure of Sec. 5; GMRES agrees with a dense solve of (I - S) g = b.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .fd import Grid, robin_coeffs
+from .layout import Layout, neighbours, norm1, subdomains
+
+# face identifiers: west (lx = 0), east (lx = snx-1), south (ly = 0), north (ly = sny-1)
+FACES = ("W", "E", "S", "N")
+
+
+class Subdomain:
+    def __init__(self, dd, i):
+        self.i = i
+        g = dd.grid
+        snx, sny = dd.snx, dd.sny
+        self.x0 = (i[0] - 1) * snx
+        self.y0 = (i[1] - 1) * sny
+        self.snx, self.sny = snx, sny
+        i1, i2 = i
+        nb = {"W": (i1 - 1, i2), "E": (i1 + 1, i2), "S": (i1, i2 - 1), "N": (i1, i2 + 1)}
+        self.nbr = {}
+        for f, j in nb.items():
+            if 1 <= j[0] <= dd.n1 and 1 <= j[1] <= dd.n2:
+                self.nbr[f] = j
+        lx = np.arange(snx)
+        ly = np.arange(sny)
+        # local indices of the edge nodes of each face, ordered along the interface
+        self.edge = {
+            "W": ly * snx + 0,
+            "E": ly * snx + (snx - 1),
+            "S": 0 * snx + lx,
+            "N": (sny - 1) * snx + lx,
+        }
+        m_loc = g.m[self.y0:self.y0 + sny, self.x0:self.x0 + snx]
+        self.m_loc = m_loc
+        # face alpha for every face node: outer -> k sqrt(m_p); interface -> k sqrt(mean)
+        self.alpha = {}
+        for f in FACES:
+            mp = m_loc.ravel()[self.edge[f]]
+            if f in self.nbr:
+                if f == "W":
+                    mq = g.m[self.y0:self.y0 + sny, self.x0 - 1]
+                elif f == "E":
+                    mq = g.m[self.y0:self.y0 + sny, self.x0 + snx]
+                elif f == "S":
+                    mq = g.m[self.y0 - 1, self.x0:self.x0 + snx]
+                else:
+                    mq = g.m[self.y0 + sny, self.x0:self.x0 + snx]
+                self.alpha[f] = g.k * np.sqrt(0.5 * (mp + mq))
+            else:
+                self.alpha[f] = g.k * np.sqrt(mp)
+        self.coef = {f: robin_coeffs(self.alpha[f], g.h) for f in FACES}
+        self.A = self._matrix(g)
+        self._lu = None
+
+    def _matrix(self, g):
+        """Local operator A_i: 5-point stencil + the Robin closure on all four faces."""
+        snx, sny, h, k = self.snx, self.sny, g.h, g.k
+        n = snx * sny
+        diag = (4.0 / h**2 - k * k * self.m_loc.ravel()).astype(np.complex128)
+        for f in FACES:
+            rho = self.coef[f][2]
+            np.add.at(diag, self.edge[f], -rho / h**2)
+        idx = np.arange(n).reshape(sny, snx)
+        rows, cols, vals = [np.arange(n)], [np.arange(n)], [diag]
+        off = -1.0 / h**2
+        for a, b in ((idx[:, :-1].ravel(), idx[:, 1:].ravel()), (idx[:-1, :].ravel(), idx[1:, :].ravel())):
+            rows += [a, b]
+            cols += [b, a]
+            vals += [np.full(a.size, off, np.complex128)] * 2
+        return sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+
+    @property
+    def lu(self):
+        if self._lu is None:
+            self._lu = spla.splu(self.A)
+        return self._lu
+
+    def restrict(self, u_global):
+        """Owned part of a global [ny, nx] field, flattened in local order."""
+        return u_global[self.y0:self.y0 + self.sny, self.x0:self.x0 + self.snx].ravel()
+
+
+class Decomposition:
+    """The n1 x n2 checkerboard of a grid (Sec. 2) with its interface layout."""
+
+    def __init__(self, grid: Grid, n1: int, n2: int):
+        if grid.nx % n1 or grid.ny % n2:
+            raise ValueError("grid size must be divisible by the decomposition")
+        self.grid, self.n1, self.n2 = grid, n1, n2
+        self.snx, self.sny = grid.nx // n1, grid.ny // n2
+        self.layout = Layout(n1, n2, self.snx, self.sny)
+        self.nif = self.layout.nif
+        self.sub = {i: Subdomain(self, i) for i in subdomains(n1, n2)}
+
+    # -- local solves and traces (Sec. 4) ---------------------------------
+    def local_rhs(self, i, g, f_loc=None):
+        """f_i + B_i g: source plus injected incoming Robin data of every interface face."""
+        s = self.sub[i]
+        r = np.zeros(s.snx * s.sny, dtype=np.complex128) if f_loc is None else np.array(f_loc, dtype=np.complex128)
+        if g is not None:
+            for f, j in s.nbr.items():
+                inj = s.coef[f][4]
+                r[s.edge[f]] += inj * g[self.layout.block(i, j)]
+        return r
+
+    def local_solve(self, i, g, f_loc=None):
+        """u_i = A_i^{-1} (f_i + B_i g)  (Sec. 3 eq. (2); with g = 0 the lifting, eq. (3))."""
+        return self.sub[i].lu.solve(self.local_rhs(i, g, f_loc))
+
+    def outgoing(self, i, u_loc, g):
+        """Data sent by i to every neighbour j: {j: (-d_{n_ij} - T) u_i on Gamma_ij} (Sec. 4).
+
+        out = -rho g_p - sigma u_p, where g_p is the data i received on that face (0 if g is None)."""
+        s = self.sub[i]
+        out = {}
+        for f, j in s.nbr.items():
+            _, _, rho, sigma, _ = s.coef[f]
+            gin = 0.0 if g is None else g[self.layout.block(i, j)]
+            out[j] = -rho * gin - sigma * u_loc[s.edge[f]]
+        return out
+
+    def scatter_subdomain(self, i, g):
+        """The local scattering operators of i applied to its incoming data (f = 0):
+        {j: sum_k S_{m(j,i), m(i,k)} g_{m(i,k)}} over all k in D_i (Sec. 4)."""
+        return self.outgoing(i, self.local_solve(i, g), g)
+
+    # -- global interface operators ----------------------------------------
+    def apply_S(self, g):
+        """S g: every block m(j,i) receives the scattered data of its sender i (Sec. 4)."""
+        out = np.zeros(self.nif, dtype=np.complex128)
+        for i in self.sub:
+            for j, v in self.scatter_subdomain(i, g).items():
+                out[self.layout.block(j, i)] = v
+        return out
+
+    def apply_operator(self, g):
+        """(I - S) g, Sec. 4 eq. (5)."""
+        return g - self.apply_S(g)
+
+    def lifting(self, f):
+        """b_{m(j,i)} = (-d_{n_ij} - T) w_i with w_i the lifting of the source (Sec. 4, eq. (3))."""
+        b = np.zeros(self.nif, dtype=np.complex128)
+        for i, s in self.sub.items():
+            w = self.local_solve(i, None, s.restrict(f))
+            for j, v in self.outgoing(i, w, None).items():
+                b[self.layout.block(j, i)] = v
+        return b
+
+    def reconstruct(self, f, g):
+        """u_i = A_i^{-1}(f_i + B_i g) on every subdomain, assembled into a global [ny, nx] field."""
+        u = np.zeros((self.grid.ny, self.grid.nx), dtype=np.complex128)
+        for i, s in self.sub.items():
+            ui = self.local_solve(i, g, s.restrict(f))
+            u[s.y0:s.y0 + s.sny, s.x0:s.x0 + s.snx] = ui.reshape(s.sny, s.snx)
+        return u
+
+    def traces_of(self, u):
+        """Incoming data g*_{m(i,j)} of a global field u: the Robin data that makes i's ghost
+        value equal u at j's node, g = (u_q - u_p)/h - i alpha (u_p + u_q)/2."""
+        h = self.grid.h
+        g = np.zeros(self.nif, dtype=np.complex128)
+        for i, s in self.sub.items():
+            uloc = s.restrict(u)
+            for f, j in s.nbr.items():
+                t = self.sub[j]
+                fq = {"W": "E", "E": "W", "S": "N", "N": "S"}[f]
+                up = uloc[s.edge[f]]
+                uq = t.restrict(u)[t.edge[fq]]
+                g[self.layout.block(i, j)] = (uq - up) / h - 0.5j * s.alpha[f] * (up + uq)
+        return g
+
+    def dense_S(self):
+        """S assembled column by column from unit vectors (tiny problems only)."""
+        n = self.nif
+        S = np.zeros((n, n), dtype=np.complex128)
+        e = np.zeros(n, dtype=np.complex128)
+        for c in range(n):
+            e[:] = 0
+            e[c] = 1
+            S[:, c] = self.apply_S(e)
+        return S
+
+    def group_antidiagonals(self):
+        return list(range(2, self.layout.n_g + 2))
+
+    def subdomains_on(self, a):
+        return [i for i in self.sub if norm1(i) == a]
+
+    def neighbours(self, i):
+        return neighbours(i, self.n1, self.n2)
