@@ -1,0 +1,243 @@
+/*
+ * hbj.h - C ABI of the MI355X (gfx950) block-Jacobi sweeping preconditioner for
+ * the 2-D Helmholtz equation (R. Dai, "A Block Jacobi Sweeping Preconditioner
+ * for the Helmholtz Equation", arXiv 2209.10886).
+ *
+ * Problem (paper Sec. 3, eq. (1)): (-Lap - k^2 m) u = f on the unit square with
+ * the first-order absorbing condition (d_n - i alpha) u = 0 on the outer boundary,
+ * m = 1/c^2, time dependence e^{-i omega t}.  Discretisation: 5-point finite
+ * differences on an nx x ny interior grid, nodes ((ix+1) h, (iy+1) h), with a
+ * Robin face template (u_q - u_p)/h - i alpha (u_p + u_q)/2 = g imposed at each
+ * face midpoint; alpha = k sqrt(m_p) on outer faces and k sqrt((m_p + m_q)/2) on
+ * interfaces.
+ *
+ * Method: a non-overlapping n1 x n2 checkerboard (Sec. 2) with Robin
+ * transmission conditions (Sec. 3, eq. (2)); GMRES on the interface system
+ * (I - S) g = b (Sec. 4, eq. (5)), right-preconditioned by the SGS sweeping
+ * preconditioner (Sec. 5, eq. (7)) or the block-Jacobi sweeping preconditioner
+ * (Sec. 6); every local problem is solved with a batched banded LU on the GPU.
+ *
+ * Conventions (all entry points):
+ *  - Array arguments are DEVICE pointers, read and written in stream order on the
+ *    stream given to hbj_setup.  The caller owns every buffer it passes; the
+ *    library owns the factors and its workspace (allocated by hbj_setup and
+ *    hbj_factor, freed by hbj_destroy).
+ *  - Fields (c, m, f, u, gradients) are [ny][nx] row-major (x fastest); a batch of
+ *    nrhs fields is [nrhs][ny][nx].
+ *  - Interface vectors (g, b, residuals) are in the paper's m order (Sec. 2,
+ *    Definitions 1-2): block m(i, j) holds the data subdomain i RECEIVES from its
+ *    neighbour j; blocks on vertical interfaces hold sub_ny entries ordered by
+ *    increasing y, blocks on horizontal interfaces sub_nx entries ordered by
+ *    increasing x.  A batch is [nrhs][n_if] with n_if = hbj_interface_len().
+ *  - hbj_c128 is {double re, im}, the memory layout of torch.complex128.
+ *  - Return codes: 0 on success; negative = error (nothing useful was written);
+ *    positive = numerical outcome (outputs are written).  hbj_last_error() gives
+ *    a message for the last failure on the calling thread.
+ *  - A context is not thread-safe; use one context per stream.
+ */
+#ifndef HBJ_H
+#define HBJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hbj_ctx hbj_ctx;
+typedef struct { double re, im; } hbj_c128;
+
+/* return codes */
+enum {
+  HBJ_OK = 0,
+  HBJ_EINVAL = -1,         /* bad size, option, pointer or non-finite medium   */
+  HBJ_ESTATE = -2,         /* call out of order (e.g. solve before factor)     */
+  HBJ_EHIP = -3,           /* a HIP runtime call failed                        */
+  HBJ_ENOMEM = -4,         /* device allocation failed                         */
+  HBJ_ZERO_PIVOT = 1,      /* exactly singular local matrix (see hbj_factor)   */
+  HBJ_NOT_CONVERGED = 2    /* GMRES hit maxit; outputs hold the last iterate   */
+};
+
+/* precision of the subdomain factors */
+enum { HBJ_FP64 = 0,       /* complex128 factors everywhere                      */
+       HBJ_MIXED = 1 };    /* complex64 factors: preconditioner in complex64, the
+                              operator's local solves refined to FP64 accuracy
+                              (iterative refinement with an FP64 residual),
+                              flexible GMRES, Arnoldi and residuals in FP64     */
+/* preconditioner */
+enum { HBJ_PC_NONE = 0, HBJ_PC_SGS = 1, HBJ_PC_BJ = 2 };
+/* how block-Jacobi intervals combine at their shared anti-diagonal group */
+enum { HBJ_BJ_RESTRICTED = 0,   /* upstream interval owns the shared group        */
+       HBJ_BJ_ADDITIVE = 1 };   /* both contributions summed (literal Sec. 6 sum) */
+/* how the forward and backward block-Jacobi passes compose */
+enum { HBJ_BJ_PRODUCT = 0,      /* z = B_U^{-1} B_L^{-1} r, like SGS              */
+       HBJ_BJ_RESIDUAL = 1 };   /* additive-projection half steps (Sec. 6)        */
+
+typedef struct {
+  int32_t nx, ny;        /* interior grid; both divisible by the decomposition      */
+  double  h;             /* grid spacing; 0 selects 1/(nx+1)                        */
+  double  k;             /* reference wavenumber (kappa = k sqrt(m))                */
+  int32_t n1, n2;        /* checkerboard: n1 columns (x), n2 rows (y), Sec. 2       */
+  int32_t precision;     /* HBJ_FP64 | HBJ_MIXED                                    */
+  int32_t precond;       /* HBJ_PC_NONE | HBJ_PC_SGS | HBJ_PC_BJ                    */
+  int32_t bj_width;      /* anti-diagonals per partial sweep; 0 = n1 (Sec. 6)      */
+  int32_t bj_combine;    /* HBJ_BJ_RESTRICTED | HBJ_BJ_ADDITIVE                     */
+  int32_t bj_compose;    /* HBJ_BJ_PRODUCT | HBJ_BJ_RESIDUAL                        */
+} hbj_problem;
+
+typedef struct {
+  double  tol;           /* stop at ||b - (I-S) g|| <= tol ||b|| (Sec. 7: 1e-6)     */
+  int32_t restart;       /* GMRES restart length (50)                               */
+  int32_t maxit;         /* total iteration cap                                     */
+  int32_t flexible;      /* 1 = FGMRES (forced on for HBJ_MIXED)                    */
+} hbj_solve_opts;
+
+typedef struct {
+  int32_t iters;         /* GMRES iterations (max over right-hand sides)            */
+  int32_t steps_per_pc;  /* sequential sweep steps per preconditioner application  */
+  int32_t local_ir_max;  /* HBJ_MIXED: max refinement steps of a local solve        */
+  int32_t converged;     /* number of right-hand sides that reached tol             */
+  double  relres;        /* max over right-hand sides of the final true residual    */
+  double  seconds;       /* wall time of the call                                   */
+  int64_t local_solves;  /* subdomain solves performed (per right-hand side)        */
+  double* res_hist;      /* caller-owned HOST buffer or NULL: Givens residual
+                            estimates relative to ||b|| of right-hand side 0,
+                            entry 0 = 1.0                                          */
+  int32_t res_hist_len;  /* capacity of res_hist on input, entries written on output */
+} hbj_solve_stats;
+
+typedef struct {         /* per kernel class, accumulated while profiling is on     */
+  int64_t launches;
+  double  ms;            /* summed kernel time between HIP events on the stream     */
+  double  bytes;         /* summed algorithmic bytes (factor entries + vectors)     */
+  double  flops;         /* summed algorithmic flops                                */
+} hbj_kernel_stat;
+
+/* kernel classes for hbj_kernel_stats */
+enum { HBJ_K_FWD = 0, HBJ_K_BWD = 1, HBJ_K_FACTOR = 2, HBJ_K_KRYLOV = 3, HBJ_K_SCATTER = 4, HBJ_K_NCLASS = 5 };
+
+/*
+ * hbj_setup - describe the problem and build the decomposition (paper Secs. 2-3).
+ *   prob    host pointer, copied.
+ *   c_dev   device [ny][nx] float64 wave speed c > 0, finite; m = 1/c^2 is kept.
+ *   stream  hipStream_t (as void*) on which every later call of the context runs;
+ *           NULL = the null stream.
+ *   out     receives the new context.
+ * Assembles the local operators A_i (5-point stencil + Robin faces, eq. (2)) in
+ * LAPACK band storage (kl = ku = sub_nx).  Errors: HBJ_EINVAL for sizes not
+ * divisible by n1 / n2, subdomains smaller than 2 x 2, a non-finite or
+ * non-positive c, or unknown options; HBJ_ENOMEM.
+ */
+int hbj_setup(const hbj_problem* prob, const double* c_dev, void* stream, hbj_ctx** out);
+
+/*
+ * hbj_set_slowness2 - replace the medium by m = 1/c^2 directly (device [ny][nx]
+ * float64, finite, > 0).  Invalidates the factors (hbj_factor must run again).
+ */
+int hbj_set_slowness2(hbj_ctx* ctx, const double* m_dev);
+
+/*
+ * hbj_factor - batched banded LU with partial pivoting of every local matrix
+ * (the paper's "sparse direct solver" of the sub-problems, Sec. 7), LAPACK
+ * zgbtrf semantics (pivot = first max of |re| + |im|), followed by the repack
+ * into the blocked solve layout and, for HBJ_MIXED, the rounding to complex64.
+ * Returns HBJ_ZERO_PIVOT if some U(j,j) is exactly zero (the factors are then
+ * unusable); hbj_zero_pivot() reports the first (subdomain, row).
+ */
+int hbj_factor(hbj_ctx* ctx);
+int hbj_zero_pivot(const hbj_ctx* ctx, int32_t* subdomain, int32_t* row);
+
+/*
+ * hbj_apply_operator - out = (I - S) g for nrhs interface vectors (Sec. 4, eq. (5)):
+ * one local solve per subdomain with its incoming data as Robin data, then the
+ * outgoing traces -rho g - sigma u written into the receivers' blocks.
+ *   g, out  device [nrhs][n_if] hbj_c128; may not alias.
+ */
+int hbj_apply_operator(hbj_ctx* ctx, const hbj_c128* g, hbj_c128* out, int32_t nrhs);
+
+/*
+ * hbj_apply_preconditioner - z = P^{-1} r with the context's preconditioner:
+ * SGS (Sec. 5, eq. (7)) or block Jacobi (Sec. 6; intervals of bj_width
+ * anti-diagonals swept concurrently in lockstep).  PC_NONE copies r.
+ *   r, z    device [nrhs][n_if] hbj_c128; may not alias.
+ */
+int hbj_apply_preconditioner(hbj_ctx* ctx, const hbj_c128* r, hbj_c128* z, int32_t nrhs);
+
+/*
+ * hbj_lifting - b = outgoing traces of the lifting w_i (Sec. 4, eq. (3)):
+ * local solves with the source and zero transmission data.
+ *   f device [nrhs][ny][nx], b device [nrhs][n_if].
+ */
+int hbj_lifting(hbj_ctx* ctx, const hbj_c128* f, hbj_c128* b, int32_t nrhs);
+
+/*
+ * hbj_reconstruct - u_i = A_i^{-1}(f_i + B_i g) on every subdomain (Sec. 4).
+ *   f, u device [nrhs][ny][nx]; g device [nrhs][n_if].
+ */
+int hbj_reconstruct(hbj_ctx* ctx, const hbj_c128* f, const hbj_c128* g, hbj_c128* u, int32_t nrhs);
+
+/*
+ * hbj_solve - u = A^{-1} f for nrhs sources: lifting, (F)GMRES on (I - S) g = b
+ * with the preconditioner, reconstruction.  The right-hand sides iterate in
+ * lockstep, each with its own Krylov recurrence.  Synchronises with the host
+ * once per iteration and returns after completion.
+ *   f, u   device [nrhs][ny][nx] (may not alias); opts host (NULL = defaults
+ *          tol 1e-6, restart 50, maxit 1000); stats host or NULL.
+ * Returns HBJ_NOT_CONVERGED (u = last iterate) when maxit is reached.
+ */
+int hbj_solve(hbj_ctx* ctx, const hbj_c128* f, hbj_c128* u, int32_t nrhs,
+              const hbj_solve_opts* opts, hbj_solve_stats* stats);
+
+/*
+ * hbj_gradient - loss L = 1/2 sum_s ||P u_s - d_s||^2 and dL/dm (m = 1/c^2) by
+ * the adjoint state: forward solves A u_s = f_s, adjoint solves A mu_s =
+ * conj(P^T r_s) with the same factors and preconditioner (A is complex symmetric,
+ * lambda_s = conj(mu_s)), grad_p = -sum_s Re(conj(lambda_p) dA_pp/dm_p u_p).
+ *   f       device [nsrc][ny][nx] sources
+ *   rec_idx device [nrec] int32 flat node indices iy*nx + ix of the receivers (P)
+ *   d       device [nsrc][nrec] observed data
+ *   grad_m  device [ny][nx] float64, overwritten with dL/dm
+ *   loss    HOST double, receives L
+ *   u_out   device [nsrc][ny][nx] or NULL: the forward fields
+ */
+int hbj_gradient(hbj_ctx* ctx, const hbj_c128* f, int32_t nsrc, const int32_t* rec_idx, int32_t nrec,
+                 const hbj_c128* d, double* grad_m, double* loss, hbj_c128* u_out,
+                 const hbj_solve_opts* opts, hbj_solve_stats* stats);
+
+/*
+ * hbj_local_solve - x_e = A_{s_e}^{-1} rhs_e for a batch of subdomains (the unit
+ * of work of every operator above), using the factored band.
+ *   sub_host  HOST [nbatch] int32 subdomain indices s = (i2-1) n1 + (i1-1)
+ *   rhs, x    device [nbatch][sub_nx*sub_ny] hbj_c128 in local order ly*sub_nx+lx.
+ *   precision HBJ_FP64 or HBJ_MIXED (complex64 factors; needs a mixed context).
+ */
+int hbj_local_solve(hbj_ctx* ctx, int32_t nbatch, const int32_t* sub_host, const hbj_c128* rhs,
+                    hbj_c128* x, int32_t precision);
+
+/*
+ * hbj_band_factors - copy the LAPACK-layout band LU of subdomain s (after
+ * hbj_factor) into caller buffers: ab device [n_loc][2kl+ku+1] (column-major
+ * band, A(i,j) at ab[j][kl+ku+i-j]) and ipiv device [n_loc] int32 (0-based).
+ */
+int hbj_band_factors(hbj_ctx* ctx, int32_t s, hbj_c128* ab, int32_t* ipiv);
+
+/* sizes: n_if, sub_nx, sub_ny, n_loc, kl (= ku), number of subdomains */
+int32_t hbj_interface_len(const hbj_ctx* ctx);
+int hbj_sizes(const hbj_ctx* ctx, int32_t* sub_nx, int32_t* sub_ny, int32_t* n_loc, int32_t* kl, int32_t* ndom);
+
+/* sequential steps of one preconditioner application and of its passes */
+int32_t hbj_steps_per_preconditioner(const hbj_ctx* ctx);
+
+/* kernel timing with HIP events on the context stream (adds events; off by default) */
+int hbj_set_profiling(hbj_ctx* ctx, int32_t on);
+int hbj_kernel_stats(hbj_ctx* ctx, int32_t kclass, hbj_kernel_stat* out);
+int hbj_reset_kernel_stats(hbj_ctx* ctx);
+
+const char* hbj_strerror(int code);
+const char* hbj_last_error(void);
+void hbj_destroy(hbj_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HBJ_H */

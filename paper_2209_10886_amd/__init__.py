@@ -1,0 +1,287 @@
+"""Python binding of libhbj, the MI355X block-Jacobi sweeping Helmholtz solver.
+
+Argument marshalling only: every computation runs in the HIP library behind the C
+ABI of ``include/hbj.h``.  torch supplies device memory (tensors on ``cuda``) and
+the stream.  Importing this package fails loudly when the library is not built.
+
+    import paper_2209_10886_amd as hbj
+    ctx = hbj.setup(nx=1024, ny=1024, k=k, n1=8, n2=8, c=c_tensor)
+    ctx.factor()
+    u, stats = ctx.solve(f, tol=1e-6)
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libhbj.so")
+
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is missing: build it with `python -m paper_2209_10886_amd.build` "
+                      "(or __graft_entry__.build()); there is no fallback implementation")
+
+_lib = ctypes.CDLL(_LIB_PATH)
+
+FP64, MIXED = 0, 1
+PC_NONE, PC_SGS, PC_BJ = 0, 1, 2
+BJ_RESTRICTED, BJ_ADDITIVE = 0, 1
+BJ_PRODUCT, BJ_RESIDUAL = 0, 1
+OK, EINVAL, ESTATE, EHIP, ENOMEM, ZERO_PIVOT, NOT_CONVERGED = 0, -1, -2, -3, -4, 1, 2
+K_FWD, K_BWD, K_FACTOR, K_KRYLOV, K_SCATTER = 0, 1, 2, 3, 4
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("h", ctypes.c_double), ("k", ctypes.c_double),
+                ("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("bj_width", ctypes.c_int32), ("bj_combine", ctypes.c_int32),
+                ("bj_compose", ctypes.c_int32)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
+                ("flexible", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("steps_per_pc", ctypes.c_int32), ("local_ir_max", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("relres", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("local_solves", ctypes.c_int64), ("res_hist", ctypes.POINTER(ctypes.c_double)),
+                ("res_hist_len", ctypes.c_int32)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("flops", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_I32 = ctypes.c_int32
+_SIGS = {
+    "hbj_setup": (_I, [ctypes.POINTER(Problem), _P, _P, ctypes.POINTER(_P)]),
+    "hbj_set_slowness2": (_I, [_P, _P]),
+    "hbj_factor": (_I, [_P]),
+    "hbj_zero_pivot": (_I, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
+    "hbj_apply_operator": (_I, [_P, _P, _P, _I32]),
+    "hbj_apply_preconditioner": (_I, [_P, _P, _P, _I32]),
+    "hbj_lifting": (_I, [_P, _P, _P, _I32]),
+    "hbj_reconstruct": (_I, [_P, _P, _P, _P, _I32]),
+    "hbj_solve": (_I, [_P, _P, _P, _I32, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)]),
+    "hbj_gradient": (_I, [_P, _P, _I32, _P, _I32, _P, _P, ctypes.POINTER(ctypes.c_double), _P,
+                          ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)]),
+    "hbj_local_solve": (_I, [_P, _I32, ctypes.POINTER(_I32), _P, _P, _I32]),
+    "hbj_band_factors": (_I, [_P, _I32, _P, _P]),
+    "hbj_interface_len": (_I32, [_P]),
+    "hbj_sizes": (_I, [_P] + [ctypes.POINTER(_I32)] * 5),
+    "hbj_steps_per_preconditioner": (_I32, [_P]),
+    "hbj_set_profiling": (_I, [_P, _I32]),
+    "hbj_kernel_stats": (_I, [_P, _I32, ctypes.POINTER(KernelStat)]),
+    "hbj_reset_kernel_stats": (_I, [_P]),
+    "hbj_strerror": (ctypes.c_char_p, [_I]),
+    "hbj_last_error": (ctypes.c_char_p, []),
+    "hbj_destroy": (None, [_P]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+EXPORTED = tuple(_SIGS)
+
+
+class HbjError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_lib.hbj_strerror(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def _check(code, allow=()):
+    if code != OK and code not in allow:
+        raise HbjError(code, _lib.hbj_last_error().decode())
+    return code
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return _P(t.data_ptr())
+
+
+@dataclasses.dataclass
+class Stats:
+    iters: int
+    steps_per_pc: int
+    local_ir_max: int
+    converged: int
+    relres: float
+    seconds: float
+    local_solves: int
+    history: list
+    code: int
+
+
+def _stats(st: SolveStats, hist, code) -> Stats:
+    return Stats(st.iters, st.steps_per_pc, st.local_ir_max, st.converged, st.relres, st.seconds, st.local_solves,
+                 list(hist[: st.res_hist_len]), code)
+
+
+class Context:
+    """One problem on one stream (hbj_ctx)."""
+
+    def __init__(self, prob: Problem, c: torch.Tensor, stream=None):
+        self.nx, self.ny = prob.nx, prob.ny
+        self.device = c.device
+        s = torch.cuda.current_stream(c.device) if stream is None else stream
+        self._stream = s
+        h = _P()
+        _check(_lib.hbj_setup(ctypes.byref(prob), _dev(c, torch.float64, "c"), _P(s.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.prob = prob
+        self.nif = int(_lib.hbj_interface_len(h))
+        a = [_I32() for _ in range(5)]
+        _check(_lib.hbj_sizes(h, *[ctypes.byref(x) for x in a]))
+        self.sub_nx, self.sub_ny, self.n_loc, self.kl, self.ndom = (int(x.value) for x in a)
+
+    # -- lifecycle -------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.hbj_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- operations --------------------------------------------------------
+    def set_slowness2(self, m: torch.Tensor):
+        _check(_lib.hbj_set_slowness2(self._h, _dev(m, torch.float64, "m")))
+
+    def factor(self):
+        code = _lib.hbj_factor(self._h)
+        if code == ZERO_PIVOT:
+            s, r = _I32(), _I32()
+            _lib.hbj_zero_pivot(self._h, ctypes.byref(s), ctypes.byref(r))
+            raise HbjError(code, f"subdomain {s.value} row {r.value}")
+        _check(code)
+
+    def _vec(self, nrhs):
+        return torch.empty((nrhs, self.nif), dtype=torch.complex128, device=self.device)
+
+    def _field(self, nrhs):
+        return torch.empty((nrhs, self.ny, self.nx), dtype=torch.complex128, device=self.device)
+
+    @staticmethod
+    def _nrhs(t, trailing):
+        return 1 if t.dim() == trailing else t.shape[0]
+
+    def apply_operator(self, g, out=None):
+        n = self._nrhs(g, 1)
+        out = self._vec(n).view(g.shape) if out is None else out
+        _check(_lib.hbj_apply_operator(self._h, _dev(g, torch.complex128, "g"), _dev(out, torch.complex128, "out"), n))
+        return out
+
+    def apply_preconditioner(self, r, out=None):
+        n = self._nrhs(r, 1)
+        out = self._vec(n).view(r.shape) if out is None else out
+        _check(_lib.hbj_apply_preconditioner(self._h, _dev(r, torch.complex128, "r"),
+                                             _dev(out, torch.complex128, "z"), n))
+        return out
+
+    def lifting(self, f, out=None):
+        n = self._nrhs(f, 2)
+        out = (self._vec(n) if f.dim() == 3 else self._vec(1)[0]) if out is None else out
+        _check(_lib.hbj_lifting(self._h, _dev(f, torch.complex128, "f"), _dev(out, torch.complex128, "b"), n))
+        return out
+
+    def reconstruct(self, f, g, out=None):
+        n = self._nrhs(f, 2)
+        out = torch.empty_like(f) if out is None else out
+        gp = _dev(g, torch.complex128, "g") if self.nif else _P(0)
+        _check(_lib.hbj_reconstruct(self._h, _dev(f, torch.complex128, "f"), gp, _dev(out, torch.complex128, "u"), n))
+        return out
+
+    def solve(self, f, tol=1e-6, restart=50, maxit=1000, flexible=False, out=None, hist_len=4096, check=True):
+        n = self._nrhs(f, 2)
+        out = torch.empty_like(f) if out is None else out
+        opts = SolveOpts(tol, restart, maxit, 1 if flexible else 0)
+        hist = (ctypes.c_double * hist_len)()
+        st = SolveStats()
+        st.res_hist = ctypes.cast(hist, ctypes.POINTER(ctypes.c_double))
+        st.res_hist_len = hist_len
+        code = _lib.hbj_solve(self._h, _dev(f, torch.complex128, "f"), _dev(out, torch.complex128, "u"), n,
+                              ctypes.byref(opts), ctypes.byref(st))
+        _check(code, allow=() if check else (NOT_CONVERGED,))
+        return out, _stats(st, hist, code)
+
+    def gradient(self, f, rec_idx, d, tol=1e-10, restart=50, maxit=2000, flexible=False, return_u=False):
+        """(loss, dL/dm [ny, nx] float64[, u]) by forward + adjoint solves."""
+        n = self._nrhs(f, 2)
+        grad = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        u = torch.empty_like(f) if return_u else None
+        loss = ctypes.c_double()
+        opts = SolveOpts(tol, restart, maxit, 1 if flexible else 0)
+        st = SolveStats()
+        _check(_lib.hbj_gradient(self._h, _dev(f, torch.complex128, "f"), n, _dev(rec_idx, torch.int32, "rec_idx"),
+                                 rec_idx.numel(), _dev(d, torch.complex128, "d"), _dev(grad, torch.float64, "grad"),
+                                 ctypes.byref(loss), _dev(u, torch.complex128, "u") if u is not None else _P(0),
+                                 ctypes.byref(opts), ctypes.byref(st)))
+        return (loss.value, grad, u) if return_u else (loss.value, grad)
+
+    def local_solve(self, subs, rhs, precision=FP64, out=None):
+        subs = [int(s) for s in subs]
+        arr = (_I32 * len(subs))(*subs)
+        out = torch.empty_like(rhs) if out is None else out
+        _check(_lib.hbj_local_solve(self._h, len(subs), arr, _dev(rhs, torch.complex128, "rhs"),
+                                    _dev(out, torch.complex128, "x"), precision))
+        return out
+
+    def band_factors(self, s):
+        ldab = 3 * self.kl + 1
+        ab = torch.empty((self.n_loc, ldab), dtype=torch.complex128, device=self.device)
+        ip = torch.empty(self.n_loc, dtype=torch.int32, device=self.device)
+        _check(_lib.hbj_band_factors(self._h, s, _dev(ab, torch.complex128, "ab"), _dev(ip, torch.int32, "ipiv")))
+        return ab, ip
+
+    def steps_per_preconditioner(self):
+        return int(_lib.hbj_steps_per_preconditioner(self._h))
+
+    def set_profiling(self, on=True):
+        _check(_lib.hbj_set_profiling(self._h, 1 if on else 0))
+
+    def kernel_stats(self, kclass):
+        ks = KernelStat()
+        _check(_lib.hbj_kernel_stats(self._h, kclass, ctypes.byref(ks)))
+        return {"launches": ks.launches, "ms": ks.ms, "bytes": ks.bytes, "flops": ks.flops}
+
+    def reset_kernel_stats(self):
+        _check(_lib.hbj_reset_kernel_stats(self._h))
+
+
+def setup(nx, ny, k, n1, n2, c=None, m=None, h=0.0, precision=FP64, precond=PC_BJ, bj_width=0,
+          bj_combine=BJ_RESTRICTED, bj_compose=BJ_PRODUCT, device="cuda", stream=None) -> Context:
+    """hbj_setup with a wave speed c (or squared slowness m) given as a [ny, nx] float64 tensor."""
+    prob = Problem(nx, ny, h, k, n1, n2, precision, precond, bj_width, bj_combine, bj_compose)
+    if c is None and m is None:
+        raise ValueError("give c or m")
+    if c is None:
+        m = m.to(device=device, dtype=torch.float64).contiguous()
+        ctx = Context(prob, torch.ones_like(m), stream)
+        ctx.set_slowness2(m)
+        return ctx
+    return Context(prob, c.to(device=device, dtype=torch.float64).contiguous(), stream)

@@ -1,0 +1,164 @@
+// Internal declarations shared by the HIP kernels and the host runtime of libhbj.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hbj.h"
+
+// ---------------------------------------------------------------------------
+// complex arithmetic on HIP vector types (x = real, y = imaginary)
+// ---------------------------------------------------------------------------
+template <typename R> struct Cplx;
+template <> struct Cplx<double> { typedef double2 T; };
+template <> struct Cplx<float> { typedef float2 T; };
+
+__host__ __device__ inline double2 mk(double a, double b) { return make_double2(a, b); }
+__host__ __device__ inline float2 mkf(float a, float b) { return make_float2(a, b); }
+
+template <typename V> __host__ __device__ inline V cadd(V a, V b) { a.x += b.x; a.y += b.y; return a; }
+template <typename V> __host__ __device__ inline V csub(V a, V b) { a.x -= b.x; a.y -= b.y; return a; }
+template <typename V> __host__ __device__ inline V cmul(V a, V b) {
+  V r; r.x = a.x * b.x - a.y * b.y; r.y = a.x * b.y + a.y * b.x; return r;
+}
+template <typename V> __host__ __device__ inline V cconj(V a) { a.y = -a.y; return a; }
+// acc += a * b
+template <typename V> __host__ __device__ inline void cfma(V& acc, V a, V b) {
+  acc.x = fma(a.x, b.x, acc.x); acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y); acc.y = fma(a.y, b.x, acc.y);
+}
+// acc += conj(a) * b
+template <typename V> __host__ __device__ inline void cfma_conj(V& acc, V a, V b) {
+  acc.x = fma(a.x, b.x, acc.x); acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y); acc.y = fma(-a.y, b.x, acc.y);
+}
+__host__ __device__ inline double2 cdiv(double2 a, double2 b) {
+  // Smith's algorithm
+  if (fabs(b.x) >= fabs(b.y)) {
+    double r = b.y / b.x, d = b.x + b.y * r;
+    return mk((a.x + a.y * r) / d, (a.y - a.x * r) / d);
+  }
+  double r = b.x / b.y, d = b.y + b.x * r;
+  return mk((a.x * r + a.y) / d, (a.y * r - a.x) / d);
+}
+__host__ __device__ inline double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
+
+template <typename V> __device__ inline V to_c(double2 a);
+template <> __device__ inline double2 to_c<double2>(double2 a) { return a; }
+template <> __device__ inline float2 to_c<float2>(double2 a) { return make_float2((float)a.x, (float)a.y); }
+__device__ inline double2 to_d(double2 a) { return a; }
+__device__ inline double2 to_d(float2 a) { return make_double2((double)a.x, (double)a.y); }
+
+// ---------------------------------------------------------------------------
+// problem geometry as seen by the kernels
+// ---------------------------------------------------------------------------
+enum { FACE_W = 0, FACE_E = 1, FACE_S = 2, FACE_N = 3 };
+
+struct Geom {
+  int nx, ny;        // global interior grid
+  int n1, n2;        // checkerboard
+  int snx, sny;      // subdomain size
+  int nloc;          // snx * sny
+  int kl, ku, kv;    // band: kl = ku = snx, kv = kl + ku
+  int ldab;          // 2 kl + ku + 1
+  int nif;           // interface length
+  double h, k;
+};
+
+// solve layout of the blocked triangular solves
+struct SolveLayout {
+  int nb;            // block (panel) width
+  int nblk;          // ceil(nloc / nb)
+  int wf;            // forward window rows  = nb + kl
+  int wb;            // backward window rows = nb + kv
+  size_t mf_per_sub; // entries of the forward M per subdomain  = nblk * nb * wf
+  size_t mb_per_sub; // entries of the backward M per subdomain = nblk * nb * wb
+  size_t pf_per_sub; // int16 permutation entries per subdomain  = nblk * wf
+};
+
+// one local solve of a batched launch
+struct Entry {
+  int32_t s;      // subdomain index (i2-1)*n1 + (i1-1)
+  int32_t rhs;    // right-hand-side column
+  int32_t src;    // 0: incoming data from g_a, 1: from g_b
+  int32_t mask;   // bit f set: write the outgoing trace of face f
+};
+
+// per-subdomain face table: offsets into the interface vector (-1 = outer face)
+struct FaceTab {
+  int32_t in_off[4];   // block m(i, j): data received by i through face f
+  int32_t out_off[4];  // block m(j, i): data sent by i through face f
+};
+
+// interface coefficients of every interface position (same on both sides of a face)
+struct IfCoef {
+  double2 rho;    // beta+ / beta-
+  double2 sigma;  // 2 i alpha / (h beta-)
+  double2 inj;    // 1 / (beta- h^2)
+};
+
+// How a local-solve launch obtains its right-hand side and where results go.
+struct SolveIO {
+  // right-hand side: (f restricted) + injected Robin data, or an explicit buffer
+  const double2* f;       // [nrhs][ny][nx] or null
+  const double2* g_a;     // incoming data, [nrhs][nif] or null
+  const double2* g_b;     // second source (entries with src = 1)
+  const double2* rhs64;   // explicit local right-hand sides [entry][nloc] (overrides f/g)
+  // outputs
+  double2* u;             // global field [nrhs][ny][nx] or null
+  double2* x64;           // local solutions [entry][nloc] (complex128) or null
+  double2* tr_dst;        // trace destination [nrhs][nif] or null
+  const double2* tr_base; // dst = base + sign * out ; null = 0
+  double tr_sign;
+  int tr_reflect;         // include -rho g (the incoming data) in the outgoing trace
+};
+
+// ---------------------------------------------------------------------------
+// launchers (each returns hipError_t of the launch)
+// ---------------------------------------------------------------------------
+hipError_t launch_check_medium(const double* c, int n, int* bad, hipStream_t st);
+hipError_t launch_c_to_m(const double* c, double* m, int n, hipStream_t st);
+hipError_t launch_if_coef(const Geom& g, const double* m, const int32_t* pos_tab, IfCoef* coef, hipStream_t st);
+hipError_t launch_local_diag(const Geom& g, const double* m, const FaceTab* ft, const IfCoef* coef,
+                             double2* diag, hipStream_t st);
+hipError_t launch_band_assemble(const Geom& g, const double2* diag, double2* ab, int nsub, hipStream_t st);
+hipError_t launch_band_lu(const Geom& g, double2* ab, int32_t* ipiv, int32_t* info, int nsub, hipStream_t st);
+hipError_t launch_repack(const Geom& g, const SolveLayout& L, const double2* ab, const int32_t* ipiv,
+                         double2* mf, int16_t* pf, double2* mb, int nsub, hipStream_t st);
+hipError_t launch_cast_c64(const double2* src, float2* dst, size_t n, hipStream_t st);
+
+template <typename R>
+hipError_t launch_fwd(const Geom& g, const SolveLayout& L, const Entry* ent, int nent, const FaceTab* ft,
+                      const IfCoef* coef, const typename Cplx<R>::T* mf, const int16_t* pf, const SolveIO& io,
+                      typename Cplx<R>::T* ybuf, hipStream_t st);
+template <typename R>
+hipError_t launch_bwd(const Geom& g, const SolveLayout& L, const Entry* ent, int nent, const FaceTab* ft,
+                      const IfCoef* coef, const typename Cplx<R>::T* mb, const SolveIO& io,
+                      typename Cplx<R>::T* ybuf, hipStream_t st);
+
+// Krylov helpers on [ncol][n] column blocks (complex128)
+hipError_t launch_multidot(const double2* V, size_t vstride, int nvec, const double2* w, int n, int ncol,
+                           double2* partial, int nchunk, hipStream_t st);
+hipError_t launch_reduce_partials(const double2* partial, int nvec, int ncol, int nchunk, double2* out,
+                                  size_t out_stride, double2 scale, hipStream_t st);
+hipError_t launch_update(double2* w, const double2* V, size_t vstride, int nvec, const double2* h,
+                         size_t h_stride, double2 alpha, int n, int ncol, hipStream_t st);
+hipError_t launch_norms(const double2* w, int n, int ncol, double* partial, int nchunk, hipStream_t st);
+hipError_t launch_reduce_norms(const double* partial, int ncol, int nchunk, double* out, hipStream_t st);
+hipError_t launch_scale_by_inv(double2* dst, const double2* src, const double* nrm, int n, int ncol,
+                               hipStream_t st);
+hipError_t launch_axpby(double2* y, const double2* x, double2 a, double2 b, size_t n, hipStream_t st);
+hipError_t launch_copy(double2* dst, const double2* src, size_t n, hipStream_t st);
+hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t st);
+hipError_t launch_add_ranges(double2* y, const double2* x, const int32_t* ranges, int nranges, int nif, int ncol,
+                             hipStream_t st);
+
+// gradient / misc
+hipError_t launch_gather_receivers(const double2* u, const int32_t* rec, int nrec, int npts, const double2* d,
+                                   double2* resid, int nsrc, hipStream_t st);
+hipError_t launch_spread_adjoint(const double2* resid, const int32_t* rec, int nrec, int npts, double2* f_adj,
+                                 int nsrc, hipStream_t st);
+hipError_t launch_grad_accumulate(const Geom& g, const double* m, const double2* u, const double2* mu, int nsrc,
+                                  double* grad, hipStream_t st);
+hipError_t launch_local_residual(const Geom& g, const Entry* ent, int nent, const double2* diag,
+                                 const double2* rhs64, const double2* x64, double2* r64, hipStream_t st);

@@ -1,0 +1,1169 @@
+// Host runtime of libhbj: decomposition tables, sweep scheduler, (F)GMRES driver, C ABI.
+//
+// Layout (paper Sec. 2).  Subdomains are multi-indices i = (i1, i2), 1-based, ordered
+// by the lexicographic order of Definition 1 (|i|_1 first, then i1).  Ordered pairs
+// (i, j), j a neighbour of i, are ordered by Definition 2; the map m numbers them and
+// block m(i, j) of the interface vector holds the data i receives from j.  Groups V_a
+// (receiver on anti-diagonal a, Sec. 5) are contiguous ranges of that order.
+//
+// Sweeps (Secs. 5-6).  A pass is a list of lockstep steps; each step is one batched
+// launch of local solves over the subdomains of the active anti-diagonals, whose
+// outgoing traces are added into the blocks of the next anti-diagonal.  SGS is the
+// single interval [2, N_g + 1]; block Jacobi cuts it into closed intervals of
+// bj_width anti-diagonals that advance together (2 bj_width steps per application).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "hbj_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(HBJ_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+typedef std::complex<double> zc;
+
+struct Step {
+  size_t first;  // offset into the schedule's device entry array
+  int count;
+};
+
+// All launches for a given number of right-hand sides.
+struct Schedule {
+  int nrhs = 0;
+  Entry* dev = nullptr;
+  size_t all_first = 0;  // every subdomain, all faces
+  int all_count = 0;
+  std::vector<Step> fwd, bwd;  // preconditioner passes
+};
+
+template <typename T>
+hipError_t dalloc(T** p, size_t n) {
+  *p = nullptr;
+  if (n == 0) return hipSuccess;
+  return hipMalloc((void**)p, n * sizeof(T));
+}
+
+}  // namespace
+
+struct hbj_ctx {
+  hbj_problem P{};
+  hipStream_t st = nullptr;
+  Geom g{};
+  SolveLayout L{};
+  int ndom = 0, ne = 0, ng = 0;
+  int bj_width = 0;
+  std::vector<std::pair<int, int>> fblocks, bblocks;  // intervals of anti-diagonals
+  std::vector<FaceTab> ft_host;
+  std::vector<int> grp_lo, grp_hi;  // interface positions of group a (index a)
+  // device tables
+  FaceTab* ft = nullptr;
+  IfCoef* coef = nullptr;
+  int32_t* pos_tab = nullptr;
+  double* m = nullptr;
+  double2* diag = nullptr;
+  int32_t* ranges_f = nullptr;  // additive reading: shared groups of the forward intervals
+  int32_t* ranges_b = nullptr;
+  int nranges_f = 0, nranges_b = 0;
+  // factors
+  double2* ab = nullptr;
+  int32_t* ipiv = nullptr;
+  int32_t* info = nullptr;
+  double2* mf64 = nullptr;
+  double2* mb64 = nullptr;
+  int16_t* pf = nullptr;
+  float2* mf32 = nullptr;
+  float2* mb32 = nullptr;
+  bool factored = false;
+  int zero_sub = -1, zero_row = -1;
+  // schedules
+  std::map<int, std::unique_ptr<Schedule>> sched;
+  // workspace
+  void* ybuf = nullptr;
+  size_t ybuf_bytes = 0;
+  double2* rhs64 = nullptr;  // mixed: local right-hand sides / residuals
+  double2* x64 = nullptr;
+  double2* r64 = nullptr;
+  size_t loc64_entries = 0;
+  double2* pc_y = nullptr;  // preconditioner pass buffers [nrhs][nif]
+  double2* pc_t = nullptr;
+  size_t pc_cols = 0;
+  // profiling
+  bool prof = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hbj_kernel_stat ks[HBJ_K_NCLASS]{};
+  int64_t local_solves = 0;
+  int last_ir = 0;
+
+  ~hbj_ctx();
+};
+
+namespace {
+
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+hbj_ctx::~hbj_ctx() {
+  for (auto& kv : sched) dfree(kv.second->dev);
+  for (void* p : {(void*)ft, (void*)coef, (void*)pos_tab, (void*)m, (void*)diag, (void*)ranges_f, (void*)ranges_b,
+                  (void*)ab, (void*)ipiv, (void*)info, (void*)mf64, (void*)mb64, (void*)pf, (void*)mf32, (void*)mb32,
+                  ybuf, (void*)rhs64, (void*)x64, (void*)r64, (void*)pc_y, (void*)pc_t})
+    dfree(p);
+  if (ev0) (void)hipEventDestroy(ev0);
+  if (ev1) (void)hipEventDestroy(ev1);
+}
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// paper Sec. 2: orders and the pair map m
+// ---------------------------------------------------------------------------
+struct MI {
+  int i1, i2;
+};
+inline bool mi_less(MI a, MI b) {  // Definition 1
+  const int na = a.i1 + a.i2, nb = b.i1 + b.i2;
+  return na < nb || (na == nb && a.i1 < b.i1);
+}
+inline bool mi_eq(MI a, MI b) { return a.i1 == b.i1 && a.i2 == b.i2; }
+inline int sub_index(const hbj_ctx* c, MI a) { return (a.i2 - 1) * c->P.n1 + (a.i1 - 1); }
+
+// Builds face tables, pos_tab and group ranges on the host.
+void build_layout(hbj_ctx* c, std::vector<int32_t>& pos_tab) {
+  const int n1 = c->P.n1, n2 = c->P.n2;
+  struct Pair {
+    MI i, j;
+    int face;  // face of i through which j is seen
+  };
+  std::vector<Pair> pairs;
+  for (int i1 = 1; i1 <= n1; ++i1)
+    for (int i2 = 1; i2 <= n2; ++i2) {
+      const MI i{i1, i2};
+      const MI nb[4] = {{i1 - 1, i2}, {i1 + 1, i2}, {i1, i2 - 1}, {i1, i2 + 1}};
+      for (int f = 0; f < 4; ++f)
+        if (nb[f].i1 >= 1 && nb[f].i1 <= n1 && nb[f].i2 >= 1 && nb[f].i2 <= n2) pairs.push_back({i, nb[f], f});
+    }
+  std::sort(pairs.begin(), pairs.end(), [](const Pair& a, const Pair& b) {  // Definition 2
+    if (!mi_eq(a.i, b.i)) return mi_less(a.i, b.i);
+    return mi_less(a.j, b.j);
+  });
+  c->ft_host.assign(c->ndom, FaceTab{{-1, -1, -1, -1}, {-1, -1, -1, -1}});
+  std::map<std::pair<int, int>, int> off;  // (receiver, sender) -> offset
+  int pos = 0;
+  c->grp_lo.assign(c->ng + 3, -1);
+  c->grp_hi.assign(c->ng + 3, -1);
+  pos_tab.clear();
+  for (const Pair& p : pairs) {
+    const int len = (p.face < 2) ? c->g.sny : c->g.snx;
+    const int si = sub_index(c, p.i), sj = sub_index(c, p.j);
+    off[{si, sj}] = pos;
+    c->ft_host[si].in_off[p.face] = pos;
+    const int a = p.i.i1 + p.i.i2;
+    if (c->grp_lo[a] < 0) c->grp_lo[a] = pos;
+    c->grp_hi[a] = pos + len;
+    for (int e = 0; e < len; ++e) {
+      pos_tab.push_back(si);
+      pos_tab.push_back(p.face);
+      pos_tab.push_back(e);
+      pos_tab.push_back(0);
+    }
+    pos += len;
+  }
+  c->g.nif = pos;
+  // out offsets: face f of i sends into block m(j, i)
+  for (int s = 0; s < c->ndom; ++s) {
+    const int i1 = s % n1 + 1, i2 = s / n1 + 1;
+    const MI nb[4] = {{i1 - 1, i2}, {i1 + 1, i2}, {i1, i2 - 1}, {i1, i2 + 1}};
+    for (int f = 0; f < 4; ++f) {
+      if (c->ft_host[s].in_off[f] < 0) continue;
+      c->ft_host[s].out_off[f] = off[{sub_index(c, nb[f]), s}];
+    }
+  }
+}
+
+std::vector<int> antidiag_subdomains(const hbj_ctx* c, int a) {
+  std::vector<int> out;
+  for (int i1 = 1; i1 <= c->P.n1; ++i1) {
+    const int i2 = a - i1;
+    if (i2 >= 1 && i2 <= c->P.n2) out.push_back(sub_index(c, MI{i1, i2}));
+  }
+  return out;
+}
+
+// closed intervals of Sec. 6
+void build_blocks(hbj_ctx* c) {
+  const int w = c->bj_width;
+  const int p = (c->ng - 1 + w - 1) / w;
+  c->fblocks.clear();
+  c->bblocks.clear();
+  for (int b = 1; b <= p; ++b) {
+    c->fblocks.push_back({2 + (b - 1) * w, std::min(2 + b * w, c->ng + 1)});
+    c->bblocks.push_back({std::max(2, (1 + c->ng) - b * w), (1 + c->ng) - (b - 1) * w});
+  }
+}
+
+int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
+  auto it = c->sched.find(nrhs);
+  if (it != c->sched.end()) {
+    *out = it->second.get();
+    return HBJ_OK;
+  }
+  auto S = std::make_unique<Schedule>();
+  S->nrhs = nrhs;
+  std::vector<Entry> ent;
+  S->all_first = 0;
+  for (int s = 0; s < c->ndom; ++s)
+    for (int r = 0; r < nrhs; ++r) ent.push_back(Entry{s, r, 0, 0xF});
+  S->all_count = (int)ent.size();
+  const int maskF = (1 << FACE_E) | (1 << FACE_N), maskB = (1 << FACE_W) | (1 << FACE_S);
+  if (c->P.precond != HBJ_PC_NONE && c->ndom > 1) {
+    int nsteps = 0;
+    for (auto& b : c->fblocks) nsteps = std::max(nsteps, b.second - b.first);
+    for (int t = 1; t <= nsteps; ++t) {
+      Step st{ent.size(), 0};
+      for (auto& b : c->fblocks) {
+        if (b.first + t > b.second) continue;
+        for (int s : antidiag_subdomains(c, b.first + t - 1))
+          for (int r = 0; r < nrhs; ++r) ent.push_back(Entry{s, r, t == 1 ? 0 : 1, maskF});
+      }
+      st.count = (int)(ent.size() - st.first);
+      S->fwd.push_back(st);
+    }
+    nsteps = 0;
+    for (auto& b : c->bblocks) nsteps = std::max(nsteps, b.second - b.first);
+    for (int t = 1; t <= nsteps; ++t) {
+      Step st{ent.size(), 0};
+      for (auto& b : c->bblocks) {
+        if (b.second - t < b.first) continue;
+        for (int s : antidiag_subdomains(c, b.second - t + 1))
+          for (int r = 0; r < nrhs; ++r) ent.push_back(Entry{s, r, t == 1 ? 0 : 1, maskB});
+      }
+      st.count = (int)(ent.size() - st.first);
+      S->bwd.push_back(st);
+    }
+  }
+  HIPCHK(dalloc(&S->dev, ent.size()));
+  HIPCHK(hipMemcpyAsync(S->dev, ent.data(), ent.size() * sizeof(Entry), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  *out = S.get();
+  c->sched[nrhs] = std::move(S);
+  return HBJ_OK;
+}
+
+int ensure_ybuf(hbj_ctx* c, size_t entries, size_t elem_bytes) {
+  const size_t need = entries * (size_t)c->L.nblk * c->L.nb * elem_bytes;
+  if (need <= c->ybuf_bytes) return HBJ_OK;
+  dfree(c->ybuf);
+  c->ybuf = nullptr;
+  c->ybuf_bytes = 0;
+  if (hipMalloc(&c->ybuf, need) != hipSuccess) return fail(HBJ_ENOMEM, "workspace allocation failed");
+  c->ybuf_bytes = need;
+  return HBJ_OK;
+}
+
+int ensure_loc64(hbj_ctx* c, size_t entries) {
+  if (entries <= c->loc64_entries) return HBJ_OK;
+  dfree(c->rhs64);
+  dfree(c->x64);
+  dfree(c->r64);
+  c->rhs64 = c->x64 = c->r64 = nullptr;
+  c->loc64_entries = 0;
+  const size_t n = entries * (size_t)c->g.nloc;
+  if (dalloc(&c->rhs64, n) != hipSuccess || dalloc(&c->x64, n) != hipSuccess || dalloc(&c->r64, n) != hipSuccess)
+    return fail(HBJ_ENOMEM, "local workspace allocation failed");
+  c->loc64_entries = entries;
+  return HBJ_OK;
+}
+
+int ensure_pc(hbj_ctx* c, size_t ncol) {
+  if (ncol <= c->pc_cols) return HBJ_OK;
+  dfree(c->pc_y);
+  dfree(c->pc_t);
+  c->pc_y = c->pc_t = nullptr;
+  c->pc_cols = 0;
+  const size_t n = ncol * (size_t)c->g.nif;
+  if (dalloc(&c->pc_y, n) != hipSuccess || dalloc(&c->pc_t, n) != hipSuccess)
+    return fail(HBJ_ENOMEM, "preconditioner workspace allocation failed");
+  c->pc_cols = ncol;
+  return HBJ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// profiling: HIP events around a launch group on the context stream
+// ---------------------------------------------------------------------------
+struct ProfScope {
+  hbj_ctx* c;
+  int kclass;
+  double bytes, flops;
+  ProfScope(hbj_ctx* c_, int k, double b, double f) : c(c_), kclass(k), bytes(b), flops(f) {
+    if (c->prof) (void)hipEventRecord(c->ev0, c->st);
+  }
+  ~ProfScope() {
+    if (!c->prof) return;
+    (void)hipEventRecord(c->ev1, c->st);
+    (void)hipEventSynchronize(c->ev1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, c->ev0, c->ev1);
+    c->ks[kclass].launches += 1;
+    c->ks[kclass].ms += ms;
+    c->ks[kclass].bytes += bytes;
+    c->ks[kclass].flops += flops;
+  }
+};
+
+// algorithmic bytes of one local solve: factor entries of the band (n_loc (2 kl + ku + 1)),
+// the pivot vector, and the solution vector written
+double fwd_bytes(const hbj_ctx* c, size_t elem) { return (double)c->g.nloc * c->g.kl * elem + 4.0 * c->g.nloc; }
+double bwd_bytes(const hbj_ctx* c, size_t elem) { return (double)c->g.nloc * (c->g.kv + 1) * elem; }
+
+// ---------------------------------------------------------------------------
+// batched local solves
+// ---------------------------------------------------------------------------
+template <typename R>
+int run_solves(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io) {
+  typedef typename Cplx<R>::T C;
+  if (nent == 0) return HBJ_OK;
+  int rc = ensure_ybuf(c, nent, sizeof(C));
+  if (rc) return rc;
+  const C* mf;
+  const C* mb;
+  if constexpr (sizeof(R) == 8) {
+    mf = c->mf64;
+    mb = c->mb64;
+  } else {
+    mf = c->mf32;
+    mb = c->mb32;
+  }
+  {
+    ProfScope ps(c, HBJ_K_FWD, nent * fwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * c->g.kl);
+    HIPCHK((launch_fwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mf, c->pf, io, (C*)c->ybuf, c->st)));
+  }
+  {
+    ProfScope ps(c, HBJ_K_BWD, nent * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1));
+    HIPCHK((launch_bwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st)));
+  }
+  c->local_solves += nent;
+  return HBJ_OK;
+}
+
+int check_ready(hbj_ctx* c) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  if (!c->factored) return fail(HBJ_ESTATE, "hbj_factor has not run (or the medium changed)");
+  return HBJ_OK;
+}
+
+// out = (I - S) g, FP64 local solves
+int op_fp64(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
+  SolveIO io{};
+  io.g_a = g;
+  io.tr_dst = out;
+  io.tr_base = g;
+  io.tr_sign = -1.0;
+  io.tr_reflect = 1;
+  return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+}
+
+// sweeps over the precomputed steps; in = pass input, out = pass output (pre-filled with in)
+template <typename R>
+int run_pass(hbj_ctx* c, const std::vector<Step>& steps, Entry* dev, const double2* in, double2* out) {
+  for (const Step& s : steps) {
+    SolveIO io{};
+    io.g_a = in;
+    io.g_b = out;
+    io.tr_dst = out;
+    io.tr_base = out;
+    io.tr_sign = 1.0;
+    io.tr_reflect = 1;
+    int rc = run_solves<R>(c, dev + s.first, s.count, io);
+    if (rc) return rc;
+  }
+  return HBJ_OK;
+}
+
+int op_apply(hbj_ctx* c, Schedule* S, const double2* g, double2* out);
+
+template <typename R>
+int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs) {
+  const size_t n = (size_t)nrhs * c->g.nif;
+  int rc = ensure_pc(c, nrhs);
+  if (rc) return rc;
+  double2* y = c->pc_y;
+  HIPCHK(launch_copy(y, r, n, c->st));
+  rc = run_pass<R>(c, S->fwd, S->dev, r, y);
+  if (rc) return rc;
+  if (c->P.bj_combine == HBJ_BJ_ADDITIVE) HIPCHK(launch_add_ranges(y, r, c->ranges_f, c->nranges_f, c->g.nif, nrhs, c->st));
+  if (c->P.bj_compose == HBJ_BJ_RESIDUAL && c->fblocks.size() > 1) {
+    // r_half = r - (I - S) y ; z = y + B_U^{-1} r_half
+    double2* t = c->pc_t;
+    rc = op_apply(c, S, y, t);
+    if (rc) return rc;
+    HIPCHK(launch_axpby(t, r, mk(1.0, 0.0), mk(-1.0, 0.0), n, c->st));  // t = r - t
+    HIPCHK(launch_copy(z, t, n, c->st));
+    rc = run_pass<R>(c, S->bwd, S->dev, t, z);
+    if (rc) return rc;
+    if (c->P.bj_combine == HBJ_BJ_ADDITIVE)
+      HIPCHK(launch_add_ranges(z, t, c->ranges_b, c->nranges_b, c->g.nif, nrhs, c->st));
+    HIPCHK(launch_axpby(z, y, mk(1.0, 0.0), mk(1.0, 0.0), n, c->st));
+    return HBJ_OK;
+  }
+  HIPCHK(launch_copy(z, y, n, c->st));
+  rc = run_pass<R>(c, S->bwd, S->dev, y, z);
+  if (rc) return rc;
+  if (c->P.bj_combine == HBJ_BJ_ADDITIVE) HIPCHK(launch_add_ranges(z, y, c->ranges_b, c->nranges_b, c->g.nif, nrhs, c->st));
+  return HBJ_OK;
+}
+
+int precond(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs) {
+  const size_t n = (size_t)nrhs * c->g.nif;
+  if (c->P.precond == HBJ_PC_NONE || c->ndom == 1) {
+    HIPCHK(launch_copy(z, r, n, c->st));
+    return HBJ_OK;
+  }
+  if (c->P.precision == HBJ_MIXED) return precond_impl<float>(c, S, r, z, nrhs);
+  return precond_impl<double>(c, S, r, z, nrhs);
+}
+
+}  // namespace
+
+// mixed-precision operator: local solves with complex64 factors refined to FP64 accuracy
+int op_mixed(hbj_ctx* c, Schedule* S, const double2* g, double2* out);
+
+namespace {
+int op_apply(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
+  if (c->P.precision == HBJ_MIXED) return op_mixed(c, S, g, out);
+  return op_fp64(c, S, g, out);
+}
+}  // namespace
+
+// ===========================================================================
+// mixed precision: iterative refinement of the operator's local solves
+// ===========================================================================
+hipError_t launch_build_rhs(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
+                            const SolveIO& io, double2* rhs64, hipStream_t st);
+hipError_t launch_emit_traces(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
+                              const SolveIO& io, const double2* x64, hipStream_t st);
+hipError_t launch_axpy_c64(double2* x64, const float2* dx, const Geom& g, const SolveLayout& L, int nent,
+                           hipStream_t st);
+
+static const int kLocalRefine = 3;
+
+int op_mixed(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
+  const Entry* ent = S->dev + S->all_first;
+  const int nent = S->all_count;
+  int rc = ensure_loc64(c, nent);
+  if (rc) return rc;
+  rc = ensure_ybuf(c, nent, sizeof(float2));
+  if (rc) return rc;
+  SolveIO io{};
+  io.g_a = g;
+  HIPCHK(launch_build_rhs(c->g, ent, nent, c->ft, c->coef, io, c->rhs64, c->st));
+  HIPCHK(launch_fill_zero(c->x64, (size_t)nent * c->g.nloc * sizeof(double2), c->st));
+  HIPCHK(launch_copy(c->r64, c->rhs64, (size_t)nent * c->g.nloc, c->st));
+  for (int it = 0; it <= kLocalRefine; ++it) {
+    SolveIO lio{};
+    lio.rhs64 = c->r64;
+    {
+      ProfScope ps(c, HBJ_K_FWD, nent * fwd_bytes(c, 8), nent * 8.0 * c->g.nloc * c->g.kl);
+      HIPCHK(launch_fwd<float>(c->g, c->L, ent, nent, c->ft, c->coef, c->mf32, c->pf, lio, (float2*)c->ybuf, c->st));
+    }
+    {
+      ProfScope ps(c, HBJ_K_BWD, nent * bwd_bytes(c, 8), nent * 8.0 * c->g.nloc * (c->g.kv + 1));
+      HIPCHK(launch_bwd<float>(c->g, c->L, ent, nent, c->ft, c->coef, c->mb32, lio, (float2*)c->ybuf, c->st));
+    }
+    c->local_solves += nent;
+    HIPCHK(launch_axpy_c64(c->x64, (const float2*)c->ybuf, c->g, c->L, nent, c->st));
+    HIPCHK(launch_local_residual(c->g, ent, nent, c->diag, c->rhs64, c->x64, c->r64, c->st));
+  }
+  c->last_ir = kLocalRefine + 1;
+  SolveIO tio{};
+  tio.g_a = g;
+  tio.tr_dst = out;
+  tio.tr_base = g;
+  tio.tr_sign = -1.0;
+  tio.tr_reflect = 1;
+  HIPCHK(launch_emit_traces(c->g, ent, nent, c->ft, c->coef, tio, c->x64, c->st));
+  return HBJ_OK;
+}
+
+// ===========================================================================
+// GMRES / FGMRES, right preconditioned, columns in lockstep
+// ===========================================================================
+namespace {
+
+struct Gmres {
+  hbj_ctx* c;
+  Schedule* S;
+  int ncol, nif, m;
+  bool flexible;
+  // device
+  double2 *V = nullptr, *Z = nullptr, *w = nullptr, *b = nullptr, *x = nullptr, *r = nullptr, *zt = nullptr;
+  double2 *h1 = nullptr, *h2 = nullptr, *ydev = nullptr, *partial = nullptr;
+  double *nrm = nullptr, *npartial = nullptr;
+  int nchunk = 0;
+  ~Gmres() {
+    for (void* p : {(void*)V, (void*)Z, (void*)w, (void*)b, (void*)x, (void*)r, (void*)zt, (void*)h1, (void*)h2,
+                    (void*)ydev, (void*)partial, (void*)nrm, (void*)npartial})
+      dfree(p);
+  }
+  size_t vs() const { return (size_t)ncol * nif; }
+  double2* Vi(int i) { return V + (size_t)i * vs(); }
+  double2* Zi(int i) { return Z + (size_t)i * vs(); }
+
+  int alloc() {
+    nchunk = std::max(1, std::min(256, (nif + 2047) / 2048));
+    if (dalloc(&V, (size_t)(m + 1) * vs()) || (flexible && dalloc(&Z, (size_t)m * vs())) || dalloc(&w, vs()) ||
+        dalloc(&b, vs()) || dalloc(&x, vs()) || dalloc(&r, vs()) || dalloc(&zt, vs()) ||
+        dalloc(&h1, (size_t)ncol * (m + 1)) || dalloc(&h2, (size_t)ncol * (m + 1)) ||
+        dalloc(&ydev, (size_t)ncol * (m + 1)) || dalloc(&partial, (size_t)ncol * (m + 1) * nchunk) ||
+        dalloc(&nrm, (size_t)ncol) || dalloc(&npartial, (size_t)ncol * nchunk))
+      return fail(HBJ_ENOMEM, "GMRES workspace allocation failed");
+    return HBJ_OK;
+  }
+
+  int norms(const double2* v, std::vector<double>& out) {
+    HIPCHK(launch_norms(v, nif, ncol, npartial, nchunk, c->st));
+    HIPCHK(launch_reduce_norms(npartial, ncol, nchunk, nrm, c->st));
+    out.resize(ncol);
+    HIPCHK(hipMemcpyAsync(out.data(), nrm, ncol * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    return HBJ_OK;
+  }
+};
+
+void givens(zc a, zc b, double& cs, zc& sn) {
+  if (std::abs(b) == 0.0) { cs = 1.0; sn = 0.0; return; }
+  if (std::abs(a) == 0.0) { cs = 0.0; sn = std::conj(b) / std::abs(b); return; }
+  const double rr = std::hypot(std::abs(a), std::abs(b));
+  cs = std::abs(a) / rr;
+  sn = (a / std::abs(a)) * std::conj(b) / rr;
+}
+
+}  // namespace
+
+static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& o, hbj_solve_stats* stats,
+                       std::vector<int>& col_iters, std::vector<double>& col_relres, std::vector<char>& col_conv,
+                       std::vector<double>& hist) {
+  const int ncol = G.ncol, nif = G.nif, m = G.m;
+  const size_t vs = G.vs();
+  std::vector<double> bnorm, rnorm;
+  int rc = G.norms(G.b, bnorm);
+  if (rc) return rc;
+  col_iters.assign(ncol, 0);
+  col_relres.assign(ncol, 0.0);
+  col_conv.assign(ncol, 0);
+  for (int k = 0; k < ncol; ++k)
+    if (bnorm[k] == 0.0) col_conv[k] = 1;
+  HIPCHK(launch_fill_zero(G.x, vs * sizeof(double2), c->st));
+  HIPCHK(launch_copy(G.r, G.b, vs, c->st));
+  rnorm = bnorm;
+  hist.assign(1, 1.0);
+  int total = 0;
+  std::vector<zc> H((size_t)ncol * (m + 1) * m), e1((size_t)ncol * (m + 1)), sn((size_t)ncol * m);
+  std::vector<double> cs((size_t)ncol * m);
+  std::vector<double2> hh1((size_t)ncol * (m + 1)), hh2((size_t)ncol * (m + 1));
+  std::vector<double> hn(ncol);
+  std::vector<int> jc(ncol);
+  std::vector<double2> yh((size_t)ncol * (m + 1));
+  auto Hc = [&](int k, int i, int j) -> zc& { return H[((size_t)k * (m + 1) + i) * m + j]; };
+  while (true) {
+    bool any = false;
+    for (int k = 0; k < ncol; ++k) any |= !col_conv[k];
+    if (!any || total >= o.maxit) break;
+    // V_0 = r / ||r|| (zero for finished columns)
+    std::vector<double> inv(ncol);
+    for (int k = 0; k < ncol; ++k) inv[k] = col_conv[k] ? 0.0 : rnorm[k];
+    HIPCHK(hipMemcpyAsync(G.nrm, inv.data(), ncol * sizeof(double), hipMemcpyHostToDevice, c->st));
+    HIPCHK(launch_scale_by_inv(G.Vi(0), G.r, G.nrm, nif, ncol, c->st));
+    std::vector<char> active(ncol);
+    for (int k = 0; k < ncol; ++k) {
+      active[k] = !col_conv[k];
+      jc[k] = 0;
+      std::fill(&e1[(size_t)k * (m + 1)], &e1[(size_t)k * (m + 1)] + m + 1, zc(0.0));
+      e1[(size_t)k * (m + 1)] = rnorm[k];
+    }
+    int j = 0;
+    for (; j < m && total < o.maxit; ++j) {
+      double2* z = G.flexible ? G.Zi(j) : G.zt;
+      rc = precond(c, S, G.Vi(j), z, ncol);
+      if (rc) return rc;
+      rc = op_apply(c, S, z, G.w);
+      if (rc) return rc;
+      {
+        ProfScope ps(c, HBJ_K_KRYLOV, 4.0 * (j + 1) * vs * 16.0 + 2.0 * vs * 16.0, 16.0 * (j + 1) * vs);
+        // classical Gram-Schmidt with one reorthogonalisation
+        HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
+        HIPCHK(launch_reduce_partials(G.partial, j + 1, ncol, G.nchunk, G.h1, m + 1, mk(1.0, 0.0), c->st));
+        HIPCHK(launch_update(G.w, G.V, vs, j + 1, G.h1, m + 1, mk(-1.0, 0.0), nif, ncol, c->st));
+        HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
+        HIPCHK(launch_reduce_partials(G.partial, j + 1, ncol, G.nchunk, G.h2, m + 1, mk(1.0, 0.0), c->st));
+        HIPCHK(launch_update(G.w, G.V, vs, j + 1, G.h2, m + 1, mk(-1.0, 0.0), nif, ncol, c->st));
+        HIPCHK(launch_norms(G.w, nif, ncol, G.npartial, G.nchunk, c->st));
+        HIPCHK(launch_reduce_norms(G.npartial, ncol, G.nchunk, G.nrm, c->st));
+        HIPCHK(launch_scale_by_inv(G.Vi(j + 1), G.w, G.nrm, nif, ncol, c->st));
+      }
+      HIPCHK(hipMemcpyAsync(hh1.data(), G.h1, hh1.size() * sizeof(double2), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipMemcpyAsync(hh2.data(), G.h2, hh2.size() * sizeof(double2), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipMemcpyAsync(hn.data(), G.nrm, ncol * sizeof(double), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipStreamSynchronize(c->st));
+      ++total;
+      bool any_active = false;
+      for (int k = 0; k < ncol; ++k) {
+        if (!active[k]) continue;
+        for (int i = 0; i <= j; ++i) {
+          const double2 a = hh1[(size_t)k * (m + 1) + i], bb = hh2[(size_t)k * (m + 1) + i];
+          Hc(k, i, j) = zc(a.x + bb.x, a.y + bb.y);
+        }
+        Hc(k, j + 1, j) = hn[k];
+        double* csk = &cs[(size_t)k * m];
+        zc* snk = &sn[(size_t)k * m];
+        for (int i = 0; i < j; ++i) {
+          const zc t = csk[i] * Hc(k, i, j) + snk[i] * Hc(k, i + 1, j);
+          Hc(k, i + 1, j) = -std::conj(snk[i]) * Hc(k, i, j) + csk[i] * Hc(k, i + 1, j);
+          Hc(k, i, j) = t;
+        }
+        givens(Hc(k, j, j), Hc(k, j + 1, j), csk[j], snk[j]);
+        Hc(k, j, j) = csk[j] * Hc(k, j, j) + snk[j] * Hc(k, j + 1, j);
+        Hc(k, j + 1, j) = 0.0;
+        zc* ek = &e1[(size_t)k * (m + 1)];
+        ek[j + 1] = -std::conj(snk[j]) * ek[j];
+        ek[j] = csk[j] * ek[j];
+        jc[k] = j + 1;
+        col_iters[k] += 1;
+        const double est = std::abs(ek[j + 1]) / bnorm[k];
+        if (k == 0) hist.push_back(est);
+        if (est <= o.tol || hn[k] == 0.0 || std::abs(Hc(k, j, j)) == 0.0) active[k] = 0;
+        any_active |= active[k];
+      }
+      if (!any_active) {
+        ++j;
+        break;
+      }
+    }
+    // y = H^{-1} e1 per column, x += Z y (or P^{-1} V y)
+    int jmax = 0;
+    std::fill(yh.begin(), yh.end(), mk(0.0, 0.0));
+    for (int k = 0; k < ncol; ++k) {
+      if (col_conv[k] || jc[k] == 0) continue;
+      const int jj = jc[k];
+      std::vector<zc> y(jj);
+      const zc* ek = &e1[(size_t)k * (m + 1)];
+      for (int i = jj - 1; i >= 0; --i) {
+        zc acc = ek[i];
+        for (int l = i + 1; l < jj; ++l) acc -= Hc(k, i, l) * y[l];
+        y[i] = acc / Hc(k, i, i);
+      }
+      for (int i = 0; i < jj; ++i) yh[(size_t)k * (m + 1) + i] = mk(y[i].real(), y[i].imag());
+      jmax = std::max(jmax, jj);
+    }
+    if (jmax > 0) {
+      HIPCHK(hipMemcpyAsync(G.ydev, yh.data(), yh.size() * sizeof(double2), hipMemcpyHostToDevice, c->st));
+      if (G.flexible) {
+        HIPCHK(launch_update(G.x, G.Z, vs, jmax, G.ydev, m + 1, mk(1.0, 0.0), nif, ncol, c->st));
+      } else {
+        HIPCHK(launch_fill_zero(G.w, vs * sizeof(double2), c->st));
+        HIPCHK(launch_update(G.w, G.V, vs, jmax, G.ydev, m + 1, mk(1.0, 0.0), nif, ncol, c->st));
+        rc = precond(c, S, G.w, G.zt, ncol);
+        if (rc) return rc;
+        HIPCHK(launch_axpby(G.x, G.zt, mk(1.0, 0.0), mk(1.0, 0.0), vs, c->st));
+      }
+    }
+    // true residual
+    rc = op_apply(c, S, G.x, G.w);
+    if (rc) return rc;
+    HIPCHK(launch_copy(G.r, G.b, vs, c->st));
+    HIPCHK(launch_axpby(G.r, G.w, mk(-1.0, 0.0), mk(1.0, 0.0), vs, c->st));
+    rc = G.norms(G.r, rnorm);
+    if (rc) return rc;
+    for (int k = 0; k < ncol; ++k) {
+      if (col_conv[k]) continue;
+      col_relres[k] = rnorm[k] / bnorm[k];
+      if (col_relres[k] <= o.tol) col_conv[k] = 1;
+    }
+  }
+  (void)stats;
+  return HBJ_OK;
+}
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* hbj_last_error(void) { return g_last_error.c_str(); }
+
+const char* hbj_strerror(int code) {
+  switch (code) {
+    case HBJ_OK: return "ok";
+    case HBJ_EINVAL: return "invalid argument";
+    case HBJ_ESTATE: return "call out of order";
+    case HBJ_EHIP: return "HIP runtime error";
+    case HBJ_ENOMEM: return "out of device memory";
+    case HBJ_ZERO_PIVOT: return "exactly singular local matrix";
+    case HBJ_NOT_CONVERGED: return "GMRES did not converge";
+    default: return "unknown code";
+  }
+}
+
+static int assemble_medium(hbj_ctx* c) {
+  Geom& g = c->g;
+  HIPCHK(launch_if_coef(g, c->m, c->pos_tab, c->coef, c->st));
+  HIPCHK(launch_local_diag(g, c->m, c->ft, c->coef, c->diag, c->st));
+  c->factored = false;
+  return HBJ_OK;
+}
+
+int hbj_setup(const hbj_problem* prob, const double* c_dev, void* stream, hbj_ctx** out) {
+  if (!prob || !out || !c_dev) return fail(HBJ_EINVAL, "null argument");
+  *out = nullptr;
+  const hbj_problem& P = *prob;
+  if (P.nx < 2 || P.ny < 2 || P.n1 < 1 || P.n2 < 1 || P.nx % P.n1 || P.ny % P.n2)
+    return fail(HBJ_EINVAL, "grid must be divisible by the decomposition");
+  if (P.nx / P.n1 < 2 || P.ny / P.n2 < 2) return fail(HBJ_EINVAL, "subdomains must be at least 2 x 2");
+  if (P.nx / P.n1 > 256) return fail(HBJ_EINVAL, "subdomain width above 256 is not supported");
+  if (!(P.k >= 0.0) || !std::isfinite(P.k)) return fail(HBJ_EINVAL, "k must be finite and >= 0");
+  if (P.precision != HBJ_FP64 && P.precision != HBJ_MIXED) return fail(HBJ_EINVAL, "bad precision");
+  if (P.precond < HBJ_PC_NONE || P.precond > HBJ_PC_BJ) return fail(HBJ_EINVAL, "bad preconditioner");
+  if (P.bj_combine < 0 || P.bj_combine > 1 || P.bj_compose < 0 || P.bj_compose > 1 || P.bj_width < 0)
+    return fail(HBJ_EINVAL, "bad block-Jacobi option");
+  if ((size_t)P.nx * P.ny > (size_t)1 << 31) return fail(HBJ_EINVAL, "grid too large");
+  std::unique_ptr<hbj_ctx> c(new hbj_ctx());
+  c->P = P;
+  c->st = (hipStream_t)stream;
+  Geom& g = c->g;
+  g.nx = P.nx;
+  g.ny = P.ny;
+  g.n1 = P.n1;
+  g.n2 = P.n2;
+  g.snx = P.nx / P.n1;
+  g.sny = P.ny / P.n2;
+  g.nloc = g.snx * g.sny;
+  g.kl = g.ku = g.snx;
+  g.kv = g.kl + g.ku;
+  g.ldab = 2 * g.kl + g.ku + 1;
+  g.h = (P.h > 0.0) ? P.h : 1.0 / (P.nx + 1);
+  g.k = P.k;
+  c->ndom = P.n1 * P.n2;
+  c->ne = 2 * P.n1 * P.n2 - P.n1 - P.n2;
+  c->ng = P.n1 + P.n2 - 1;
+  if (P.precond == HBJ_PC_SGS) c->bj_width = std::max(1, c->ng - 1);
+  else c->bj_width = (P.bj_width > 0) ? P.bj_width : P.n1;
+  if (c->ng >= 2) build_blocks(c.get());
+  std::vector<int32_t> pos_tab;
+  build_layout(c.get(), pos_tab);
+  SolveLayout& L = c->L;
+  L.nb = 32;
+  L.nblk = (g.nloc + L.nb - 1) / L.nb;
+  L.wf = L.nb + g.kl;
+  L.wb = L.nb + g.kv;
+  L.mf_per_sub = (size_t)L.nblk * L.nb * L.wf;
+  L.mb_per_sub = (size_t)L.nblk * L.nb * L.wb;
+  L.pf_per_sub = (size_t)L.nblk * L.wf;
+  // additive reading: the shared groups (start of every forward interval but the first;
+  // top of every backward interval but the first)
+  std::vector<int32_t> rf, rb;
+  for (size_t b = 1; b < c->fblocks.size(); ++b) {
+    const int a = c->fblocks[b].first;
+    rf.push_back(c->grp_lo[a]);
+    rf.push_back(c->grp_hi[a]);
+  }
+  for (size_t b = 1; b < c->bblocks.size(); ++b) {
+    const int a = c->bblocks[b].second;
+    rb.push_back(c->grp_lo[a]);
+    rb.push_back(c->grp_hi[a]);
+  }
+  c->nranges_f = (int)rf.size() / 2;
+  c->nranges_b = (int)rb.size() / 2;
+  const size_t npts = (size_t)g.nx * g.ny;
+  int* bad = nullptr;
+  if (dalloc(&c->ft, c->ndom) || dalloc(&c->coef, (size_t)g.nif) || dalloc(&c->pos_tab, pos_tab.size()) ||
+      dalloc(&c->m, npts) || dalloc(&c->diag, (size_t)c->ndom * g.nloc) || dalloc(&c->ranges_f, rf.size()) ||
+      dalloc(&c->ranges_b, rb.size()) || dalloc(&c->info, (size_t)c->ndom) || dalloc(&bad, 1))
+    return fail(HBJ_ENOMEM, "setup allocation failed");
+  HIPCHK(hipMemcpyAsync(c->ft, c->ft_host.data(), c->ndom * sizeof(FaceTab), hipMemcpyHostToDevice, c->st));
+  if (!pos_tab.empty())
+    HIPCHK(hipMemcpyAsync(c->pos_tab, pos_tab.data(), pos_tab.size() * 4, hipMemcpyHostToDevice, c->st));
+  if (!rf.empty()) HIPCHK(hipMemcpyAsync(c->ranges_f, rf.data(), rf.size() * 4, hipMemcpyHostToDevice, c->st));
+  if (!rb.empty()) HIPCHK(hipMemcpyAsync(c->ranges_b, rb.data(), rb.size() * 4, hipMemcpyHostToDevice, c->st));
+  HIPCHK(launch_fill_zero(bad, 4, c->st));
+  HIPCHK(launch_check_medium(c_dev, (int)npts, bad, c->st));
+  int nbad = 0;
+  HIPCHK(hipMemcpyAsync(&nbad, bad, 4, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  dfree(bad);
+  if (nbad) return fail(HBJ_EINVAL, "wave speed must be finite and positive");
+  HIPCHK(launch_c_to_m(c_dev, c->m, (int)npts, c->st));
+  int rc = assemble_medium(c.get());
+  if (rc) return rc;
+  HIPCHK(hipEventCreate(&c->ev0));
+  HIPCHK(hipEventCreate(&c->ev1));
+  HIPCHK(hipStreamSynchronize(c->st));
+  *out = c.release();
+  return HBJ_OK;
+}
+
+int hbj_set_slowness2(hbj_ctx* c, const double* m_dev) {
+  if (!c || !m_dev) return fail(HBJ_EINVAL, "null argument");
+  const size_t npts = (size_t)c->g.nx * c->g.ny;
+  // validate through c = m^{-1/2} > 0: reuse the positivity check on m directly
+  int* bad = nullptr;
+  HIPCHK(dalloc(&bad, 1));
+  HIPCHK(launch_fill_zero(bad, 4, c->st));
+  HIPCHK(launch_check_medium(m_dev, (int)npts, bad, c->st));
+  int nbad = 0;
+  HIPCHK(hipMemcpyAsync(&nbad, bad, 4, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  dfree(bad);
+  if (nbad) return fail(HBJ_EINVAL, "squared slowness must be finite and positive");
+  HIPCHK(hipMemcpyAsync(c->m, m_dev, npts * sizeof(double), hipMemcpyDeviceToDevice, c->st));
+  return assemble_medium(c);
+}
+
+int hbj_factor(hbj_ctx* c) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  const Geom& g = c->g;
+  const SolveLayout& L = c->L;
+  const size_t nband = (size_t)c->ndom * g.nloc * g.ldab;
+  if (!c->ab) {
+    if (dalloc(&c->ab, nband) || dalloc(&c->ipiv, (size_t)c->ndom * g.nloc) ||
+        dalloc(&c->mf64, L.mf_per_sub * c->ndom) || dalloc(&c->mb64, L.mb_per_sub * c->ndom) ||
+        dalloc(&c->pf, L.pf_per_sub * c->ndom))
+      return fail(HBJ_ENOMEM, "factor allocation failed");
+    if (c->P.precision == HBJ_MIXED &&
+        (dalloc(&c->mf32, L.mf_per_sub * c->ndom) || dalloc(&c->mb32, L.mb_per_sub * c->ndom)))
+      return fail(HBJ_ENOMEM, "factor allocation failed");
+  }
+  c->factored = false;
+  {
+    ProfScope ps(c, HBJ_K_FACTOR, (double)nband * 16.0, 8.0 * c->ndom * (double)g.nloc * g.kl * g.kv);
+    HIPCHK(launch_band_assemble(g, c->diag, c->ab, c->ndom, c->st));
+    HIPCHK(launch_band_lu(g, c->ab, c->ipiv, c->info, c->ndom, c->st));
+  }
+  std::vector<int32_t> info(c->ndom);
+  HIPCHK(hipMemcpyAsync(info.data(), c->info, c->ndom * 4, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  c->zero_sub = c->zero_row = -1;
+  for (int s = 0; s < c->ndom; ++s)
+    if (info[s]) {
+      c->zero_sub = s;
+      c->zero_row = info[s] - 1;
+      return fail(HBJ_ZERO_PIVOT, "exactly zero pivot in subdomain " + std::to_string(s) + " row " +
+                                      std::to_string(info[s] - 1));
+    }
+  HIPCHK(launch_repack(g, L, c->ab, c->ipiv, c->mf64, c->pf, c->mb64, c->ndom, c->st));
+  if (c->P.precision == HBJ_MIXED) {
+    HIPCHK(launch_cast_c64(c->mf64, c->mf32, L.mf_per_sub * c->ndom, c->st));
+    HIPCHK(launch_cast_c64(c->mb64, c->mb32, L.mb_per_sub * c->ndom, c->st));
+  }
+  HIPCHK(hipStreamSynchronize(c->st));
+  c->factored = true;
+  return HBJ_OK;
+}
+
+int hbj_zero_pivot(const hbj_ctx* c, int32_t* subdomain, int32_t* row) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  if (subdomain) *subdomain = c->zero_sub;
+  if (row) *row = c->zero_row;
+  return HBJ_OK;
+}
+
+int hbj_apply_operator(hbj_ctx* c, const hbj_c128* g, hbj_c128* out, int32_t nrhs) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (nrhs < 1 || !g || !out) return fail(HBJ_EINVAL, "bad arguments");
+  Schedule* S;
+  rc = build_schedule(c, nrhs, &S);
+  if (rc) return rc;
+  return op_apply(c, S, (const double2*)g, (double2*)out);
+}
+
+int hbj_apply_preconditioner(hbj_ctx* c, const hbj_c128* r, hbj_c128* z, int32_t nrhs) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (nrhs < 1 || !r || !z) return fail(HBJ_EINVAL, "bad arguments");
+  Schedule* S;
+  rc = build_schedule(c, nrhs, &S);
+  if (rc) return rc;
+  return precond(c, S, (const double2*)r, (double2*)z, nrhs);
+}
+
+int hbj_lifting(hbj_ctx* c, const hbj_c128* f, hbj_c128* b, int32_t nrhs) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (nrhs < 1 || !f || !b) return fail(HBJ_EINVAL, "bad arguments");
+  Schedule* S;
+  rc = build_schedule(c, nrhs, &S);
+  if (rc) return rc;
+  if (c->g.nif == 0) return HBJ_OK;
+  SolveIO io{};
+  io.f = (const double2*)f;
+  io.tr_dst = (double2*)b;
+  io.tr_sign = 1.0;
+  io.tr_reflect = 0;
+  return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+}
+
+int hbj_reconstruct(hbj_ctx* c, const hbj_c128* f, const hbj_c128* g, hbj_c128* u, int32_t nrhs) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (nrhs < 1 || !f || !u) return fail(HBJ_EINVAL, "bad arguments");
+  Schedule* S;
+  rc = build_schedule(c, nrhs, &S);
+  if (rc) return rc;
+  SolveIO io{};
+  io.f = (const double2*)f;
+  io.g_a = (c->g.nif > 0) ? (const double2*)g : nullptr;
+  io.u = (double2*)u;
+  return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+}
+
+static int solve_impl(hbj_ctx* c, const double2* f, double2* u, int nrhs, const hbj_solve_opts* opts,
+                      hbj_solve_stats* stats) {
+  auto t0 = std::chrono::steady_clock::now();
+  hbj_solve_opts o{1e-6, 50, 1000, 0};
+  if (opts) o = *opts;
+  if (!(o.tol > 0.0) || o.restart < 1 || o.maxit < 0) return fail(HBJ_EINVAL, "bad solve options");
+  if (c->P.precision == HBJ_MIXED) o.flexible = 1;
+  Schedule* S;
+  int rc = build_schedule(c, nrhs, &S);
+  if (rc) return rc;
+  const int64_t ls0 = c->local_solves;
+  std::vector<int> iters;
+  std::vector<double> relres, hist;
+  std::vector<char> conv;
+  if (c->g.nif == 0) {  // one subdomain: the lifting is the solution
+    SolveIO io{};
+    io.f = f;
+    io.u = u;
+    rc = run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(c->st));
+    iters.assign(nrhs, 0);
+    relres.assign(nrhs, 0.0);
+    conv.assign(nrhs, 1);
+    hist.assign(1, 0.0);
+  } else {
+    Gmres G;
+    G.c = c;
+    G.S = S;
+    G.ncol = nrhs;
+    G.nif = c->g.nif;
+    G.m = o.restart;
+    G.flexible = o.flexible != 0;
+    rc = G.alloc();
+    if (rc) return rc;
+    {
+      SolveIO io{};
+      io.f = f;
+      io.tr_dst = G.b;
+      io.tr_sign = 1.0;
+      rc = run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+      if (rc) return rc;
+    }
+    rc = gmres_solve(c, S, G, o, stats, iters, relres, conv, hist);
+    if (rc) return rc;
+    SolveIO io{};
+    io.f = f;
+    io.g_a = G.x;
+    io.u = u;
+    rc = run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(c->st));
+  }
+  int nconv = 0, itmax = 0;
+  double rmax = 0.0;
+  for (int k = 0; k < nrhs; ++k) {
+    nconv += conv[k] ? 1 : 0;
+    itmax = std::max(itmax, iters[k]);
+    rmax = std::max(rmax, relres[k]);
+  }
+  if (stats) {
+    stats->iters = itmax;
+    stats->steps_per_pc = hbj_steps_per_preconditioner(c);
+    stats->local_ir_max = (c->P.precision == HBJ_MIXED) ? c->last_ir : 0;
+    stats->converged = nconv;
+    stats->relres = rmax;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    stats->local_solves = (c->local_solves - ls0) / std::max(1, nrhs);
+    if (stats->res_hist) {
+      const int nh = std::min<int>(stats->res_hist_len, (int)hist.size());
+      for (int i = 0; i < nh; ++i) stats->res_hist[i] = hist[i];
+      stats->res_hist_len = nh;
+    } else {
+      stats->res_hist_len = 0;
+    }
+  }
+  return (nconv == nrhs) ? HBJ_OK : HBJ_NOT_CONVERGED;
+}
+
+int hbj_solve(hbj_ctx* c, const hbj_c128* f, hbj_c128* u, int32_t nrhs, const hbj_solve_opts* opts,
+              hbj_solve_stats* stats) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (nrhs < 1 || !f || !u || (const void*)f == (const void*)u) return fail(HBJ_EINVAL, "bad arguments");
+  return solve_impl(c, (const double2*)f, (double2*)u, nrhs, opts, stats);
+}
+
+int hbj_gradient(hbj_ctx* c, const hbj_c128* f, int32_t nsrc, const int32_t* rec_idx, int32_t nrec,
+                 const hbj_c128* d, double* grad_m, double* loss, hbj_c128* u_out, const hbj_solve_opts* opts,
+                 hbj_solve_stats* stats) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (nsrc < 1 || nrec < 1 || !f || !rec_idx || !d || !grad_m || !loss) return fail(HBJ_EINVAL, "bad arguments");
+  const Geom& g = c->g;
+  const int npts = g.nx * g.ny;
+  std::vector<int32_t> rec(nrec);
+  HIPCHK(hipMemcpyAsync(rec.data(), rec_idx, nrec * 4, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  {
+    std::vector<int32_t> sr(rec);
+    std::sort(sr.begin(), sr.end());
+    if (sr.front() < 0 || sr.back() >= npts || std::adjacent_find(sr.begin(), sr.end()) != sr.end())
+      return fail(HBJ_EINVAL, "receiver indices must be distinct nodes of the grid");
+  }
+  double2 *u = nullptr, *fa = nullptr, *mu = nullptr, *res = nullptr;
+  auto cleanup = [&]() {
+    if (!u_out) dfree(u);
+    dfree(fa);
+    dfree(mu);
+    dfree(res);
+  };
+  if ((!u_out && dalloc(&u, (size_t)nsrc * npts)) || dalloc(&fa, (size_t)nsrc * npts) ||
+      dalloc(&mu, (size_t)nsrc * npts) || dalloc(&res, (size_t)nsrc * nrec)) {
+    cleanup();
+    return fail(HBJ_ENOMEM, "gradient workspace allocation failed");
+  }
+  if (u_out) u = (double2*)u_out;
+  hbj_solve_stats s1{}, s2{};
+  rc = solve_impl(c, (const double2*)f, u, nsrc, opts, &s1);
+  if (rc < 0) { cleanup(); return rc; }
+  int rc_fwd = rc;
+  hipError_t he = launch_gather_receivers(u, rec_idx, nrec, npts, (const double2*)d, res, nsrc, c->st);
+  if (he == hipSuccess) he = launch_fill_zero(fa, (size_t)nsrc * npts * sizeof(double2), c->st);
+  if (he == hipSuccess) he = launch_spread_adjoint(res, rec_idx, nrec, npts, fa, nsrc, c->st);
+  if (he != hipSuccess) { cleanup(); return fail(HBJ_EHIP, hipGetErrorString(he)); }
+  std::vector<double2> rh((size_t)nsrc * nrec);
+  he = hipMemcpyAsync(rh.data(), res, rh.size() * sizeof(double2), hipMemcpyDeviceToHost, c->st);
+  if (he == hipSuccess) he = hipStreamSynchronize(c->st);
+  if (he != hipSuccess) { cleanup(); return fail(HBJ_EHIP, hipGetErrorString(he)); }
+  double L = 0.0;
+  for (const double2& v : rh) L += v.x * v.x + v.y * v.y;
+  *loss = 0.5 * L;
+  rc = solve_impl(c, fa, mu, nsrc, opts, &s2);
+  if (rc < 0) { cleanup(); return rc; }
+  he = launch_grad_accumulate(g, c->m, u, mu, nsrc, grad_m, c->st);
+  if (he == hipSuccess) he = hipStreamSynchronize(c->st);
+  cleanup();
+  if (he != hipSuccess) return fail(HBJ_EHIP, hipGetErrorString(he));
+  if (stats) {
+    *stats = s1;
+    stats->iters = std::max(s1.iters, s2.iters);
+    stats->relres = std::max(s1.relres, s2.relres);
+    stats->seconds = s1.seconds + s2.seconds;
+    stats->converged = std::min(s1.converged, s2.converged);
+  }
+  return (rc_fwd == HBJ_OK && rc == HBJ_OK) ? HBJ_OK : HBJ_NOT_CONVERGED;
+}
+
+int hbj_local_solve(hbj_ctx* c, int32_t nbatch, const int32_t* sub_host, const hbj_c128* rhs, hbj_c128* x,
+                    int32_t precision) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (nbatch < 1 || !sub_host || !rhs || !x) return fail(HBJ_EINVAL, "bad arguments");
+  if (precision == HBJ_MIXED && !c->mf32) return fail(HBJ_EINVAL, "context has no complex64 factors");
+  std::vector<Entry> ent(nbatch);
+  for (int i = 0; i < nbatch; ++i) {
+    if (sub_host[i] < 0 || sub_host[i] >= c->ndom) return fail(HBJ_EINVAL, "subdomain index out of range");
+    ent[i] = Entry{sub_host[i], 0, 0, 0};
+  }
+  Entry* dev = nullptr;
+  HIPCHK(dalloc(&dev, nbatch));
+  HIPCHK(hipMemcpyAsync(dev, ent.data(), nbatch * sizeof(Entry), hipMemcpyHostToDevice, c->st));
+  SolveIO io{};
+  io.rhs64 = (const double2*)rhs;
+  io.x64 = (double2*)x;
+  if (precision == HBJ_MIXED) rc = run_solves<float>(c, dev, nbatch, io);
+  else rc = run_solves<double>(c, dev, nbatch, io);
+  hipError_t he = hipStreamSynchronize(c->st);
+  dfree(dev);
+  if (rc) return rc;
+  if (he != hipSuccess) return fail(HBJ_EHIP, hipGetErrorString(he));
+  return HBJ_OK;
+}
+
+int hbj_band_factors(hbj_ctx* c, int32_t s, hbj_c128* ab, int32_t* ipiv) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (s < 0 || s >= c->ndom || !ab || !ipiv) return fail(HBJ_EINVAL, "bad arguments");
+  const size_t nb = (size_t)c->g.nloc * c->g.ldab;
+  HIPCHK(hipMemcpyAsync(ab, c->ab + (size_t)s * nb, nb * sizeof(double2), hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(hipMemcpyAsync(ipiv, c->ipiv + (size_t)s * c->g.nloc, c->g.nloc * 4, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return HBJ_OK;
+}
+
+int32_t hbj_interface_len(const hbj_ctx* c) { return c ? c->g.nif : -1; }
+
+int hbj_sizes(const hbj_ctx* c, int32_t* sub_nx, int32_t* sub_ny, int32_t* n_loc, int32_t* kl, int32_t* ndom) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  if (sub_nx) *sub_nx = c->g.snx;
+  if (sub_ny) *sub_ny = c->g.sny;
+  if (n_loc) *n_loc = c->g.nloc;
+  if (kl) *kl = c->g.kl;
+  if (ndom) *ndom = c->ndom;
+  return HBJ_OK;
+}
+
+int32_t hbj_steps_per_preconditioner(const hbj_ctx* c) {
+  if (!c) return -1;
+  if (c->P.precond == HBJ_PC_NONE || c->ndom == 1) return 0;
+  int f = 0, b = 0;
+  for (auto& x : c->fblocks) f = std::max(f, x.second - x.first);
+  for (auto& x : c->bblocks) b = std::max(b, x.second - x.first);
+  return f + b;
+}
+
+int hbj_set_profiling(hbj_ctx* c, int32_t on) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  c->prof = on != 0;
+  return HBJ_OK;
+}
+
+int hbj_kernel_stats(hbj_ctx* c, int32_t k, hbj_kernel_stat* out) {
+  if (!c || !out || k < 0 || k >= HBJ_K_NCLASS) return fail(HBJ_EINVAL, "bad arguments");
+  *out = c->ks[k];
+  return HBJ_OK;
+}
+
+int hbj_reset_kernel_stats(hbj_ctx* c) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  for (auto& k : c->ks) k = hbj_kernel_stat{};
+  return HBJ_OK;
+}
+
+void hbj_destroy(hbj_ctx* c) {
+  if (!c) return;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  delete c;
+}
+
+}  // extern "C"
