@@ -71,10 +71,20 @@ struct SolveLayout {
   int nblk;          // ceil(nloc / nb)
   int wf;            // forward window rows  = nb + kl
   int wb;            // backward window rows = nb + kv
+  int cgf, cgb;      // lanes sharing one window row (column groups) in the forward / backward kernels
   size_t mf_per_sub; // entries of the forward M per subdomain  = nblk * nb * wf
   size_t mb_per_sub; // entries of the backward M per subdomain = nblk * nb * wb
   size_t pf_per_sub; // int16 permutation entries per subdomain  = nblk * wf
 };
+
+// Position of entry (column c, window row r) of one block's solve matrix in the
+// thread-tiled layout [k][r][cg] with c = cg * (nb / cg) + k: lane (r, cg) of the solve
+// kernel reads its k-th value at ((k * rows + r) * cg_count + cg), so every load
+// instruction of a wavefront is one contiguous run.
+__host__ __device__ inline size_t tile_index(int c, int r, int rows, int nb, int cg) {
+  const int nc = nb / cg;
+  return ((size_t)(c % nc) * rows + r) * cg + c / nc;
+}
 
 // one local solve of a batched launch
 struct Entry {
@@ -124,12 +134,14 @@ hipError_t launch_local_diag(const Geom& g, const double* m, const FaceTab* ft, 
 hipError_t launch_band_assemble(const Geom& g, const double2* diag, double2* ab, int nsub, hipStream_t st);
 hipError_t launch_band_lu(const Geom& g, double2* ab, int32_t* ipiv, int32_t* info, int nsub, hipStream_t st);
 hipError_t launch_repack(const Geom& g, const SolveLayout& L, const double2* ab, const int32_t* ipiv,
-                         double2* mf, int16_t* pf, double2* mb, int nsub, hipStream_t st);
+                         double2* mf, int16_t* pf, int32_t* pflag, double2* mb, int nsub, hipStream_t st);
 hipError_t launch_cast_c64(const double2* src, float2* dst, size_t n, hipStream_t st);
 
+void solve_column_groups(int wf, int wb, int* cgf, int* cgb);
 template <typename R>
 hipError_t launch_fwd(const Geom& g, const SolveLayout& L, const Entry* ent, int nent, const FaceTab* ft,
-                      const IfCoef* coef, const typename Cplx<R>::T* mf, const int16_t* pf, const SolveIO& io,
+                      const IfCoef* coef, const typename Cplx<R>::T* mf, const int16_t* pf, const int32_t* pflag,
+                      const SolveIO& io,
                       typename Cplx<R>::T* ybuf, hipStream_t st);
 template <typename R>
 hipError_t launch_bwd(const Geom& g, const SolveLayout& L, const Entry* ent, int nent, const FaceTab* ft,

@@ -111,15 +111,18 @@ __global__ __launch_bounds__(LU_THREADS) void k_band_lu(double2* AB, int32_t* ip
 // for the permuted multipliers before overwriting it with Mf.
 template <int NB>
 __global__ __launch_bounds__(256) void k_repack(Geom g, SolveLayout L, const double2* AB, const int32_t* ipiv,
-                                                double2* MF, int16_t* PF, double2* MB) {
+                                                double2* MF, int16_t* PF, int32_t* PFLAG, double2* MB) {
   const int b = blockIdx.x, s = blockIdx.y;
   const int n = g.nloc, kl = g.kl, kv = g.kv, ldab = g.ldab;
   const int wf = L.wf, wb = L.wb;
   const double2* ab = AB + (size_t)s * n * ldab;
   const int32_t* ip = ipiv + (size_t)s * n;
-  double2* mf = MF + (size_t)s * L.mf_per_sub + (size_t)b * NB * wf;  // column-major [NB][wf]
+  double2* mf = MF + (size_t)s * L.mf_per_sub + (size_t)b * NB * wf;  // tiled, see tile_index
   int16_t* pf = PF + (size_t)s * L.pf_per_sub + (size_t)b * wf;
-  double2* mb = MB + (size_t)s * L.mb_per_sub + (size_t)b * NB * wb;  // column-major [NB][wb]
+  double2* mb = MB + (size_t)s * L.mb_per_sub + (size_t)b * NB * wb;  // tiled, see tile_index
+  const int cgf = L.cgf, cgb = L.cgb;
+#define MF(c, r) mf[tile_index((c), (r), wf, NB, cgf)]
+#define MBX(c, q) mb[tile_index((c), (q), wb, NB, cgb)]
   const int j0 = b * NB;
   const int tid = threadIdx.x, nt = blockDim.x;
 
@@ -145,26 +148,30 @@ __global__ __launch_bounds__(256) void k_repack(Geom g, SolveLayout L, const dou
     const int c = t / wf, r = t - c * wf;
     double2 v = mk(0.0, 0.0);
     if (j0 + c < n && r > c && r <= c + kl && j0 + r < n) v = ab[(size_t)(j0 + c) * ldab + kv + (r - c)];
-    mf[t] = v;
+    MF(c, r) = v;
   }
   __syncthreads();
   for (int r = tid; r < wf; r += nt) pf[r] = src[r];
+  if (tid == 0) {
+    int ident = 1;
+    for (int c = 0; c < NB; ++c) ident &= (piv[c] == c);
+    PFLAG[(size_t)s * L.nblk + b] = ident;
+  }
   // later interchanges act on the earlier columns' multipliers
   for (int c = tid; c < NB; c += nt) {
-    double2* col = mf + (size_t)c * wf;
     for (int c2 = c + 1; c2 < NB; ++c2) {
       const int p = piv[c2];
       if (p != c2) {
-        const double2 a = col[c2];
-        col[c2] = col[p];
-        col[p] = a;
+        const double2 a = MF(c, c2);
+        MF(c, c2) = MF(c, p);
+        MF(c, p) = a;
       }
     }
   }
   __syncthreads();
   for (int t = tid; t < NB * NB; t += nt) {
     const int c = t / NB, r = t - c * NB;
-    T[r][c] = (r > c) ? mf[(size_t)c * wf + r] : mk(r == c ? 1.0 : 0.0, 0.0);
+    T[r][c] = (r > c) ? MF(c, r) : mk(r == c ? 1.0 : 0.0, 0.0);
   }
   __syncthreads();
   // X = T^{-1} (unit lower), one column per thread
@@ -182,17 +189,17 @@ __global__ __launch_bounds__(256) void k_repack(Geom g, SolveLayout L, const dou
   for (int r = NB + tid; r < wf; r += nt) {
     double2 row[NB];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) row[c] = mf[(size_t)c * wf + r];
+    for (int c = 0; c < NB; ++c) row[c] = MF(c, r);
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
       double2 acc = mk(0.0, 0.0);
       for (int k = c; k < NB; ++k) cfma(acc, row[k], X[k][c]);
-      mf[(size_t)c * wf + r] = mk(-acc.x, -acc.y);
+      MF(c, r) = mk(-acc.x, -acc.y);
     }
   }
   for (int t = tid; t < NB * NB; t += nt) {
     const int c = t / NB, r = t - c * NB;
-    mf[(size_t)c * wf + r] = X[r][c];
+    MF(c, r) = X[r][c];
   }
   __syncthreads();
   // ---------------- backward ----------------
@@ -231,13 +238,15 @@ __global__ __launch_bounds__(256) void k_repack(Geom g, SolveLayout L, const dou
     for (int c = 0; c < NB; ++c) {
       double2 acc = mk(0.0, 0.0);
       for (int k = 0; k <= c; ++k) cfma(acc, urow[k], X[k][c]);
-      mb[(size_t)c * wb + q] = mk(-acc.x, -acc.y);
+      MBX(c, q) = mk(-acc.x, -acc.y);
     }
   }
   for (int t = tid; t < NB * NB; t += nt) {
     const int c = t / NB, r = t - c * NB;
-    mb[(size_t)c * wb + kv + r] = X[r][c];
+    MBX(c, kv + r) = X[r][c];
   }
+#undef MF
+#undef MBX
 }
 
 __global__ void k_cast_c64(const double2* src, float2* dst, size_t n) {
@@ -254,9 +263,9 @@ hipError_t launch_band_lu(const Geom& g, double2* ab, int32_t* ipiv, int32_t* in
 }
 
 hipError_t launch_repack(const Geom& g, const SolveLayout& L, const double2* ab, const int32_t* ipiv, double2* mf,
-                         int16_t* pf, double2* mb, int nsub, hipStream_t st) {
-  if (L.nb != 32 || g.kl > 256) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_repack<32>, dim3(L.nblk, nsub), dim3(256), 0, st, g, L, ab, ipiv, mf, pf, mb);
+                         int16_t* pf, int32_t* pflag, double2* mb, int nsub, hipStream_t st) {
+  if (L.nb != 16 || g.kl > 256) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_repack<16>, dim3(L.nblk, nsub), dim3(256), 0, st, g, L, ab, ipiv, mf, pf, pflag, mb);
   return hipGetLastError();
 }
 

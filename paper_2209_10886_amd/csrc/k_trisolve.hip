@@ -54,125 +54,246 @@ struct RhsCtx {
 template <typename C>
 __device__ inline C czero() { C z; z.x = 0; z.y = 0; return z; }
 
-// Final value x of local row l: write it where the launch asks for it.
-__device__ inline void emit(const Geom& g, const Entry& e, const FaceTab& F, const IfCoef* coef, const SolveIO& io,
-                            const double2* gin, int slot, int l, double2 x) {
+// Field outputs of the final value x of local row l.
+__device__ inline void emit_field(const Geom& g, const Entry& e, const SolveIO& io, int slot, int l, double2 x) {
   if (l >= g.nloc) return;
   if (io.x64) io.x64[(size_t)slot * g.nloc + l] = x;
-  const int ly = l / g.snx, lx = l - ly * g.snx;
   if (io.u) {
+    const int ly = l / g.snx, lx = l - ly * g.snx;
     const int x0 = (e.s % g.n1) * g.snx, y0 = (e.s / g.n1) * g.sny;
     io.u[(size_t)e.rhs * g.nx * g.ny + (size_t)(y0 + ly) * g.nx + x0 + lx] = x;
   }
-  if (io.tr_dst) {
-    const bool on[4] = {lx == 0, lx == g.snx - 1, ly == 0, ly == g.sny - 1};
+}
+
+// Outgoing traces -rho g - sigma x of every face of the subdomain that contains local row l.
+__device__ inline void emit_traces(const Geom& g, const Entry& e, const FaceTab& F, const IfCoef* coef,
+                                   const SolveIO& io, const double2* gin, int l, double2 x) {
+  const int ly = l / g.snx, lx = l - ly * g.snx;
+  const bool on[4] = {lx == 0, lx == g.snx - 1, ly == 0, ly == g.sny - 1};
 #pragma unroll
-    for (int f = 0; f < 4; ++f) {
-      if (!on[f] || !((e.mask >> f) & 1) || F.out_off[f] < 0) continue;
-      const int ee = (f < 2) ? ly : lx;
-      const int qi = F.in_off[f] + ee, qo = F.out_off[f] + ee;
-      const IfCoef c = coef[qi];
-      double2 val = cmul(c.sigma, x);
-      if (io.tr_reflect && gin) cfma(val, c.rho, gin[qi]);
-      // out = -rho g - sigma u
-      val = mk(-val.x, -val.y);
-      const size_t o = (size_t)e.rhs * g.nif + qo;
-      double2 base = io.tr_base ? io.tr_base[o] : mk(0.0, 0.0);
-      base.x += io.tr_sign * val.x;
-      base.y += io.tr_sign * val.y;
-      io.tr_dst[o] = base;
-    }
+  for (int f = 0; f < 4; ++f) {
+    if (!on[f] || !((e.mask >> f) & 1) || F.out_off[f] < 0) continue;
+    const int ee = (f < 2) ? ly : lx;
+    const int qi = F.in_off[f] + ee, qo = F.out_off[f] + ee;
+    const IfCoef c = coef[qi];
+    double2 val = cmul(c.sigma, x);
+    if (io.tr_reflect && gin) cfma(val, c.rho, gin[qi]);
+    val = mk(-val.x, -val.y);
+    const size_t o = (size_t)e.rhs * g.nif + qo;
+    double2 base = io.tr_base ? io.tr_base[o] : mk(0.0, 0.0);
+    base.x += io.tr_sign * val.x;
+    base.y += io.tr_sign * val.y;
+    io.tr_dst[o] = base;
   }
 }
 
-template <typename R, int NB>
-__global__ __launch_bounds__(320) void k_fwd(Geom g, SolveLayout L, const Entry* ent, const FaceTab* ft,
+__device__ inline void emit(const Geom& g, const Entry& e, const FaceTab& F, const IfCoef* coef, const SolveIO& io,
+                            const double2* gin, int slot, int l, double2 x) {
+  if (l >= g.nloc) return;
+  emit_field(g, e, io, slot, l, x);
+  if (io.tr_dst) emit_traces(g, e, F, coef, io, gin, l, x);
+}
+
+// q-th edge row of a subdomain: south row, north row, then the west and east columns
+// without their corners (2 snx + 2 (sny - 2) rows in all).
+__device__ inline int edge_row(const Geom& g, int q) {
+  if (q < g.snx) return q;
+  q -= g.snx;
+  if (q < g.snx) return (g.sny - 1) * g.snx + q;
+  q -= g.snx;
+  if (q < g.sny - 2) return (1 + q) * g.snx;
+  q -= g.sny - 2;
+  return (1 + q) * g.snx + g.snx - 1;
+}
+
+template <typename C>
+__device__ inline C shfl_xor_c(C v, int m) {
+  v.x = __shfl_xor(v.x, m);
+  v.y = __shfl_xor(v.y, m);
+  return v;
+}
+
+// sum over the CG adjacent lanes that share one window row
+template <int CG, typename C>
+__device__ inline C row_reduce(C acc) {
+  if (CG >= 2) acc = cadd(acc, shfl_xor_c(acc, 1));
+  if (CG >= 4) acc = cadd(acc, shfl_xor_c(acc, 2));
+  if (CG >= 8) acc = cadd(acc, shfl_xor_c(acc, 4));
+  return acc;
+}
+
+// Forward solve y = T_{nblk-1} ... T_0 rhs.  Lane (r, cg) owns window row r and the
+// columns [cg*NC, cg*NC + NC) of every block matrix; the matrices of the next D blocks and
+// the right-hand-side rows entering the window are prefetched into registers, so a block's
+// critical path is LDS reads, FMAs, a cross-lane sum and one barrier.  Prefetch loads are
+// issued unconditionally (indices clamped into range) so that the wait before a block's
+// FMAs only covers that block's own loads.
+template <typename R, int NB, int CG, int D>
+__global__ __launch_bounds__(576) void k_fwd(Geom g, SolveLayout L, const Entry* ent, const FaceTab* ft,
                                              const IfCoef* coef, const typename Cplx<R>::T* __restrict__ MF,
-                                             const int16_t* __restrict__ PF, SolveIO io,
-                                             typename Cplx<R>::T* __restrict__ ybuf) {
+                                             const int16_t* __restrict__ PF, const int32_t* __restrict__ PFL,
+                                             SolveIO io, typename Cplx<R>::T* __restrict__ ybuf) {
   typedef typename Cplx<R>::T C;
+  constexpr int NC = NB / CG;
   extern __shared__ unsigned char smem_raw[];
+  const int wf = L.wf, kl = g.kl, nt = blockDim.x, tid = threadIdx.x, nblk = L.nblk;
   C* bufA = reinterpret_cast<C*>(smem_raw);
-  C* bufB = bufA + L.wf;
+  C* bufB = bufA + wf;
+  int* ident = reinterpret_cast<int*>(bufB + wf);
   const Entry e = ent[blockIdx.x];
   const FaceTab F = ft[e.s];
   const RhsCtx rhs(g, e, F, coef, io, blockIdx.x);
+  const int ylen = nblk * NB;
+  C* y = ybuf + (size_t)blockIdx.x * ylen;
   const C* M = MF + (size_t)e.s * L.mf_per_sub;
   const int16_t* P = PF + (size_t)e.s * L.pf_per_sub;
-  C* y = ybuf + (size_t)blockIdx.x * L.nblk * NB;
-  const int wf = L.wf, kl = g.kl, nt = blockDim.x, tid = threadIdx.x;
+  const int32_t* PI = PFL + (size_t)e.s * nblk;
+  const int cg = tid % CG, r = tid / CG;
+  const bool act = r < wf;
+  const size_t bstride = (size_t)NB * wf;
+  const int kstride = wf * CG, toff = act ? r * CG + cg : 0;
+  const int frow = min(tid, NB - 1);
 
-  for (int r = tid; r < wf; r += nt) bufA[r] = to_c<C>(rhs(r));
+  for (int l = tid; l < ylen; l += nt) y[l] = to_c<C>(rhs(l));
+  for (int b = tid; b < nblk; b += nt) ident[b] = PI[b];
   __syncthreads();
-  for (int b = 0; b < L.nblk; ++b) {
-    const C* Mb = M + (size_t)b * NB * wf;
-    const int16_t* Pb = P + (size_t)b * wf;
-    C t[NB];
+  for (int q = tid; q < wf; q += nt) bufA[q] = (q < ylen) ? y[q] : czero<C>();
+  // ring of D blocks: matrix slices and the window rows entering at the end of the block,
+  // loaded together so that one in-order wait covers exactly one block
+  C mr[D][NC];
+  C fr[D];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) t[c] = bufA[Pb[c]];
-    for (int r = tid; r < wf; r += nt) {
-      C acc = (r >= NB) ? bufA[Pb[r]] : czero<C>();
+  for (int d = 0; d < D; ++d) {
+    const C* Mb = M + (size_t)min(d, nblk - 1) * bstride + toff;
 #pragma unroll
-      for (int c = 0; c < NB; ++c) cfma(acc, Mb[(size_t)c * wf + r], t[c]);
-      if (r < NB) y[b * NB + r] = acc;
-      else bufB[r - NB] = acc;
-    }
-    for (int i = tid; i < NB; i += nt) bufB[kl + i] = to_c<C>(rhs((b + 1) * NB + kl + i));
-    __syncthreads();
-    C* tmp = bufA;
-    bufA = bufB;
-    bufB = tmp;
+    for (int k = 0; k < NC; ++k) mr[d][k] = Mb[k * kstride];
+    fr[d] = y[min((d + 1) * NB + kl + frow, ylen - 1)];
   }
+  __syncthreads();
+
+  auto step = [&](int b, C(&m)[NC], C& f) {
+    if (!ident[b]) {  // row interchanges inside this block: gather the window first
+      const int16_t* Pb = P + (size_t)b * wf;
+      for (int q = tid; q < wf; q += nt) bufB[q] = bufA[Pb[q]];
+      __syncthreads();
+      C* t = bufA;
+      bufA = bufB;
+      bufB = t;
+    }
+    // the rows entering the next window go in first, so the register is free for the
+    // next prefetch (no copy of an in-flight register at the loop back-edge)
+    if (tid < NB) bufB[kl + tid] = ((b + 1) * NB + kl + tid < ylen) ? f : czero<C>();
+    C acc = czero<C>();
+#pragma unroll
+    for (int k = 0; k < NC; ++k) cfma(acc, m[k], bufA[cg * NC + k]);
+    acc = row_reduce<CG>(acc);
+    {
+      const C* Mb = M + (size_t)min(b + D, nblk - 1) * bstride + toff;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) m[k] = Mb[k * kstride];
+      f = y[min((b + D + 1) * NB + kl + frow, ylen - 1)];
+    }
+    if (act && cg == 0) {
+      if (r < NB) y[b * NB + r] = acc;
+      else bufB[r - NB] = cadd(acc, bufA[r]);
+    }
+    __syncthreads();
+    C* t = bufA;
+    bufA = bufB;
+    bufB = t;
+  };
+  const int nmain = (nblk / D) * D;
+  for (int b0 = 0; b0 < nmain; b0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) step(b0 + d, mr[d], fr[d]);
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (nmain + d < nblk) step(nmain + d, mr[d], fr[d]);
 }
 
-template <typename R, int NB>
-__global__ __launch_bounds__(320) void k_bwd(Geom g, SolveLayout L, const Entry* ent, const FaceTab* ft,
+// Backward solve x = U^{-1} y, blocks from the last one; the window holds the block rows
+// and the kl + ku rows above them that still await this block's contribution.
+template <typename R, int NB, int CG, int D>
+__global__ __launch_bounds__(576) void k_bwd(Geom g, SolveLayout L, const Entry* ent, const FaceTab* ft,
                                              const IfCoef* coef, const typename Cplx<R>::T* __restrict__ MB,
                                              SolveIO io, typename Cplx<R>::T* __restrict__ ybuf) {
   typedef typename Cplx<R>::T C;
+  constexpr int NC = NB / CG;
   extern __shared__ unsigned char smem_raw[];
+  const int wb = L.wb, kv = g.kv, nt = blockDim.x, tid = threadIdx.x, nblk = L.nblk;
   C* bufA = reinterpret_cast<C*>(smem_raw);
-  C* bufB = bufA + L.wb;
+  C* bufB = bufA + wb;
   const Entry e = ent[blockIdx.x];
   const FaceTab F = ft[e.s];
+  const int ylen = nblk * NB;
+  C* y = ybuf + (size_t)blockIdx.x * ylen;
   const C* M = MB + (size_t)e.s * L.mb_per_sub;
-  C* y = ybuf + (size_t)blockIdx.x * L.nblk * NB;
   const double2* gin = e.src ? io.g_b : io.g_a;
   if (gin) gin += (size_t)e.rhs * g.nif;
-  const int wb = L.wb, kv = g.kv, nt = blockDim.x, tid = threadIdx.x;
+  const int cg = tid % CG, r = tid / CG;
+  const bool act = r < wb;
+  const size_t bstride = (size_t)NB * wb;
+  const int kstride = wb * CG, toff = act ? r * CG + cg : 0;
+  const int frow = min(tid, NB - 1);
 
-  int j0 = (L.nblk - 1) * NB;
-  for (int q = tid; q < wb; q += nt) {
-    const int row = j0 - kv + q;
-    bufA[q] = (row >= 0) ? y[row] : czero<C>();
+  {
+    const int j0 = (nblk - 1) * NB;
+    for (int q = tid; q < wb; q += nt) {
+      const int row = j0 - kv + q;
+      bufA[q] = (row >= 0) ? y[row] : czero<C>();
+    }
+  }
+  C mr[D][NC];
+  C fr[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const C* Mb = M + (size_t)max(nblk - 1 - d, 0) * bstride + toff;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) mr[d][k] = Mb[k * kstride];
+    fr[d] = y[max((nblk - 2 - d) * NB - kv + frow, 0)];
   }
   __syncthreads();
-  for (int b = L.nblk - 1; b >= 0; --b) {
-    j0 = b * NB;
-    const C* Mb = M + (size_t)b * NB * wb;
-    C t[NB];
+
+  auto step = [&](int b, C(&m)[NC], C& f) {
+    if (tid < NB) bufB[tid] = ((b - 1) * NB - kv + tid >= 0) ? f : czero<C>();
+    C acc = czero<C>();
 #pragma unroll
-    for (int c = 0; c < NB; ++c) t[c] = bufA[kv + c];
-    for (int q = tid; q < wb; q += nt) {
-      C acc = (q < kv) ? bufA[q] : czero<C>();
+    for (int k = 0; k < NC; ++k) cfma(acc, m[k], bufA[kv + cg * NC + k]);
+    acc = row_reduce<CG>(acc);
+    {
+      const C* Mb = M + (size_t)max(b - D, 0) * bstride + toff;
 #pragma unroll
-      for (int c = 0; c < NB; ++c) cfma(acc, Mb[(size_t)c * wb + q], t[c]);
-      if (q >= kv) {
-        const int row = j0 + q - kv;
-        y[row] = acc;
-        emit(g, e, F, coef, io, gin, blockIdx.x, row, to_d(acc));
-      } else {
-        bufB[q + NB] = acc;
-      }
+      for (int k = 0; k < NC; ++k) m[k] = Mb[k * kstride];
+      f = y[max((b - D - 1) * NB - kv + frow, 0)];
     }
-    for (int i = tid; i < NB; i += nt) {
-      const int row = j0 - NB - kv + i;
-      bufB[i] = (row >= 0) ? y[row] : czero<C>();
+    if (act && cg == 0) {
+      if (r >= kv) y[b * NB + r - kv] = acc;
+      else bufB[r + NB] = cadd(acc, bufA[r]);
     }
     __syncthreads();
-    C* tmp = bufA;
+    C* t = bufA;
     bufA = bufB;
-    bufB = tmp;
+    bufB = t;
+  };
+  const int nmain = (nblk / D) * D;
+  for (int i0 = 0; i0 < nmain; i0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) step(nblk - 1 - (i0 + d), mr[d], fr[d]);
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (nmain + d < nblk) step(nblk - 1 - (nmain + d), mr[d], fr[d]);
+  // the solution is final: write the requested outputs
+  if (io.u || io.x64) {
+    for (int l = tid; l < g.nloc; l += nt) emit_field(g, e, io, blockIdx.x, l, to_d(y[l]));
+  }
+  if (io.tr_dst) {
+    const int nedge = 2 * g.snx + 2 * (g.sny - 2);
+    for (int q = tid; q < nedge; q += nt) {
+      const int l = edge_row(g, q);
+      emit_traces(g, e, F, coef, io, gin, l, to_d(y[l]));
+    }
   }
 }
 
@@ -214,22 +335,29 @@ __global__ void k_axpy_c64(double2* x64, const float2* dx, int nloc, int stride)
   x.y += (double)d.y;
 }
 
-inline int threads_for(int rows) {
-  int t = ((rows + 63) / 64) * 64;
-  return t > 320 ? 320 : t;
-}
-
 }  // namespace
+
+// column groups per window row (must match the tiled layout written by the repack)
+void solve_column_groups(int wf, int wb, int* cgf, int* cgb) {
+  *cgf = (wf * 4 <= 576) ? 4 : 1;
+  *cgb = (wb * 2 <= 576) ? 2 : 1;
+}
 
 template <typename R>
 hipError_t launch_fwd(const Geom& g, const SolveLayout& L, const Entry* ent, int nent, const FaceTab* ft,
-                      const IfCoef* coef, const typename Cplx<R>::T* mf, const int16_t* pf, const SolveIO& io,
-                      typename Cplx<R>::T* ybuf, hipStream_t st) {
+                      const IfCoef* coef, const typename Cplx<R>::T* mf, const int16_t* pf, const int32_t* pflag,
+                      const SolveIO& io, typename Cplx<R>::T* ybuf, hipStream_t st) {
+  typedef typename Cplx<R>::T C;
   if (nent == 0) return hipSuccess;
-  if (L.nb != 32) return hipErrorInvalidValue;
-  const size_t shm = 2 * (size_t)L.wf * sizeof(typename Cplx<R>::T);
-  hipLaunchKernelGGL((k_fwd<R, 32>), dim3(nent), dim3(threads_for(L.wf)), shm, st, g, L, ent, ft, coef, mf, pf, io,
-                     ybuf);
+  if (L.nb != 16 || L.wf > 576) return hipErrorInvalidValue;
+  const size_t shm = 2 * (size_t)L.wf * sizeof(C) + (size_t)L.nblk * sizeof(int);
+  const int rows = L.wf * L.cgf;
+  const dim3 blk(((rows + 63) / 64) * 64);
+  if (L.cgf == 4)
+    hipLaunchKernelGGL((k_fwd<R, 16, 4, (sizeof(R) == 8 ? 5 : 8)>), dim3(nent), blk, shm, st, g, L, ent, ft, coef, mf,
+                       pf, pflag, io, ybuf);
+  else
+    hipLaunchKernelGGL((k_fwd<R, 16, 1, 1>), dim3(nent), blk, shm, st, g, L, ent, ft, coef, mf, pf, pflag, io, ybuf);
   return hipGetLastError();
 }
 
@@ -237,20 +365,26 @@ template <typename R>
 hipError_t launch_bwd(const Geom& g, const SolveLayout& L, const Entry* ent, int nent, const FaceTab* ft,
                       const IfCoef* coef, const typename Cplx<R>::T* mb, const SolveIO& io,
                       typename Cplx<R>::T* ybuf, hipStream_t st) {
+  typedef typename Cplx<R>::T C;
   if (nent == 0) return hipSuccess;
-  if (L.nb != 32) return hipErrorInvalidValue;
-  const size_t shm = 2 * (size_t)L.wb * sizeof(typename Cplx<R>::T);
-  hipLaunchKernelGGL((k_bwd<R, 32>), dim3(nent), dim3(threads_for(L.wb)), shm, st, g, L, ent, ft, coef, mb, io,
-                     ybuf);
+  if (L.nb != 16 || L.wb > 576) return hipErrorInvalidValue;
+  const size_t shm = 2 * (size_t)L.wb * sizeof(C);
+  const int rows = L.wb * L.cgb;
+  const dim3 blk(((rows + 63) / 64) * 64);
+  if (L.cgb == 2)
+    hipLaunchKernelGGL((k_bwd<R, 16, 2, (sizeof(R) == 8 ? 3 : 4)>), dim3(nent), blk, shm, st, g, L, ent, ft, coef, mb,
+                       io, ybuf);
+  else
+    hipLaunchKernelGGL((k_bwd<R, 16, 1, 1>), dim3(nent), blk, shm, st, g, L, ent, ft, coef, mb, io, ybuf);
   return hipGetLastError();
 }
 
 template hipError_t launch_fwd<double>(const Geom&, const SolveLayout&, const Entry*, int, const FaceTab*,
-                                       const IfCoef*, const double2*, const int16_t*, const SolveIO&, double2*,
-                                       hipStream_t);
+                                       const IfCoef*, const double2*, const int16_t*, const int32_t*, const SolveIO&,
+                                       double2*, hipStream_t);
 template hipError_t launch_fwd<float>(const Geom&, const SolveLayout&, const Entry*, int, const FaceTab*,
-                                      const IfCoef*, const float2*, const int16_t*, const SolveIO&, float2*,
-                                      hipStream_t);
+                                      const IfCoef*, const float2*, const int16_t*, const int32_t*, const SolveIO&,
+                                      float2*, hipStream_t);
 template hipError_t launch_bwd<double>(const Geom&, const SolveLayout&, const Entry*, int, const FaceTab*,
                                        const IfCoef*, const double2*, const SolveIO&, double2*, hipStream_t);
 template hipError_t launch_bwd<float>(const Geom&, const SolveLayout&, const Entry*, int, const FaceTab*,

@@ -89,6 +89,7 @@ struct hbj_ctx {
   double2* mf64 = nullptr;
   double2* mb64 = nullptr;
   int16_t* pf = nullptr;
+  int32_t* pflag = nullptr;
   float2* mf32 = nullptr;
   float2* mb32 = nullptr;
   bool factored = false;
@@ -126,7 +127,7 @@ void dfree(void* p) {
 hbj_ctx::~hbj_ctx() {
   for (auto& kv : sched) dfree(kv.second->dev);
   for (void* p : {(void*)ft, (void*)coef, (void*)pos_tab, (void*)m, (void*)diag, (void*)ranges_f, (void*)ranges_b,
-                  (void*)ab, (void*)ipiv, (void*)info, (void*)mf64, (void*)mb64, (void*)pf, (void*)mf32, (void*)mb32,
+                  (void*)ab, (void*)ipiv, (void*)info, (void*)mf64, (void*)mb64, (void*)pf, (void*)pflag, (void*)mf32, (void*)mb32,
                   ybuf, (void*)rhs64, (void*)x64, (void*)r64, (void*)pc_y, (void*)pc_t})
     dfree(p);
   if (ev0) (void)hipEventDestroy(ev0);
@@ -356,7 +357,7 @@ int run_solves(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io) {
   }
   {
     ProfScope ps(c, HBJ_K_FWD, nent * fwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * c->g.kl);
-    HIPCHK((launch_fwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mf, c->pf, io, (C*)c->ybuf, c->st)));
+    HIPCHK((launch_fwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mf, c->pf, c->pflag, io, (C*)c->ybuf, c->st)));
   }
   {
     ProfScope ps(c, HBJ_K_BWD, nent * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1));
@@ -484,7 +485,8 @@ int op_mixed(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
     lio.rhs64 = c->r64;
     {
       ProfScope ps(c, HBJ_K_FWD, nent * fwd_bytes(c, 8), nent * 8.0 * c->g.nloc * c->g.kl);
-      HIPCHK(launch_fwd<float>(c->g, c->L, ent, nent, c->ft, c->coef, c->mf32, c->pf, lio, (float2*)c->ybuf, c->st));
+      HIPCHK(launch_fwd<float>(c->g, c->L, ent, nent, c->ft, c->coef, c->mf32, c->pf, c->pflag, lio, (float2*)c->ybuf,
+                              c->st));
     }
     {
       ProfScope ps(c, HBJ_K_BWD, nent * bwd_bytes(c, 8), nent * 8.0 * c->g.nloc * (c->g.kv + 1));
@@ -771,13 +773,14 @@ int hbj_setup(const hbj_problem* prob, const double* c_dev, void* stream, hbj_ct
   std::vector<int32_t> pos_tab;
   build_layout(c.get(), pos_tab);
   SolveLayout& L = c->L;
-  L.nb = 32;
+  L.nb = 16;
   L.nblk = (g.nloc + L.nb - 1) / L.nb;
   L.wf = L.nb + g.kl;
   L.wb = L.nb + g.kv;
   L.mf_per_sub = (size_t)L.nblk * L.nb * L.wf;
   L.mb_per_sub = (size_t)L.nblk * L.nb * L.wb;
   L.pf_per_sub = (size_t)L.nblk * L.wf;
+  solve_column_groups(L.wf, L.wb, &L.cgf, &L.cgb);
   // additive reading: the shared groups (start of every forward interval but the first;
   // top of every backward interval but the first)
   std::vector<int32_t> rf, rb;
@@ -846,7 +849,7 @@ int hbj_factor(hbj_ctx* c) {
   if (!c->ab) {
     if (dalloc(&c->ab, nband) || dalloc(&c->ipiv, (size_t)c->ndom * g.nloc) ||
         dalloc(&c->mf64, L.mf_per_sub * c->ndom) || dalloc(&c->mb64, L.mb_per_sub * c->ndom) ||
-        dalloc(&c->pf, L.pf_per_sub * c->ndom))
+        dalloc(&c->pf, L.pf_per_sub * c->ndom) || dalloc(&c->pflag, (size_t)L.nblk * c->ndom))
       return fail(HBJ_ENOMEM, "factor allocation failed");
     if (c->P.precision == HBJ_MIXED &&
         (dalloc(&c->mf32, L.mf_per_sub * c->ndom) || dalloc(&c->mb32, L.mb_per_sub * c->ndom)))
@@ -869,7 +872,7 @@ int hbj_factor(hbj_ctx* c) {
       return fail(HBJ_ZERO_PIVOT, "exactly zero pivot in subdomain " + std::to_string(s) + " row " +
                                       std::to_string(info[s] - 1));
     }
-  HIPCHK(launch_repack(g, L, c->ab, c->ipiv, c->mf64, c->pf, c->mb64, c->ndom, c->st));
+  HIPCHK(launch_repack(g, L, c->ab, c->ipiv, c->mf64, c->pf, c->pflag, c->mb64, c->ndom, c->st));
   if (c->P.precision == HBJ_MIXED) {
     HIPCHK(launch_cast_c64(c->mf64, c->mf32, L.mf_per_sub * c->ndom, c->st));
     HIPCHK(launch_cast_c64(c->mb64, c->mb32, L.mb_per_sub * c->ndom, c->st));
