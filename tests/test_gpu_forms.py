@@ -1,0 +1,209 @@
+"""GPU tests of the mixed-precision form and the adjoint gradient against the oracle.
+
+Mixed precision: complex64 factors for the preconditioner; the operator's local
+solves are refined with an FP64 residual, so the operator agrees with the FP64 one
+to near double precision, and FGMRES reaches FP64 residuals.  The errors against
+the FP64 oracle are printed for every result.
+
+Gradient: dL/dm from forward + adjoint GPU solves against the oracle's direct-solve
+gradient and against central finite differences of the misfit.
+"""
+import numpy as np
+import pytest
+
+import workload as W
+from cases import CASES, gpu_context, oracle_problem, rel, say, sub_index
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def mixed(hbj):
+    wl = CASES["grf256"].wl
+    m, g, dd = oracle_problem(wl)
+    say("[setup] mixed grf256")
+    ctx = gpu_context(hbj, wl, m, precision=hbj.MIXED)
+    ctx.factor()
+    ref = gpu_context(hbj, wl, m, precision=hbj.FP64)
+    ref.factor()
+    yield wl, m, g, dd, ctx, ref
+    ctx.close()
+    ref.close()
+
+
+def test_mixed_local_solve_error(hbj, mixed):
+    wl, m, g, dd, ctx, ref = mixed
+    subs = list(dd.sub)[:8]
+    rng = np.random.default_rng(3)
+    rhs = rng.standard_normal((len(subs), ctx.n_loc)) + 1j * rng.standard_normal((len(subs), ctx.n_loc))
+    say("[mixed local_solve]")
+    x = _np(ctx.local_solve([sub_index(wl, i) for i in subs], torch.as_tensor(rhs, device="cuda"),
+                            precision=hbj.MIXED))
+    errs = [rel(x[k], dd.sub[i].lu.solve(rhs[k])) for k, i in enumerate(subs)]
+    say(f"  complex64 local solve error vs FP64 oracle: max {max(errs):.2e}")
+    assert max(errs) < 1e-4
+
+
+def test_mixed_operator_is_refined_to_fp64(mixed):
+    wl, m, g, dd, ctx, ref = mixed
+    gv = W.random_interface_vector(ctx.nif, seed=4)
+    say("[mixed operator]")
+    w = _np(ctx.apply_operator(torch.as_tensor(gv, device="cuda")))
+    e = rel(w, dd.apply_operator(gv))
+    say(f"  refined operator error vs oracle: {e:.2e}")
+    assert e < 1e-10
+
+
+def test_mixed_preconditioner_error(mixed):
+    from oracle import sweep
+
+    wl, m, g, dd, ctx, ref = mixed
+    r = W.random_interface_vector(ctx.nif, seed=5)
+    say("[mixed preconditioner]")
+    z = _np(ctx.apply_preconditioner(torch.as_tensor(r, device="cuda")))
+    e = rel(z, sweep.apply_bj(dd, r))
+    say(f"  complex64 preconditioner error vs oracle: {e:.2e}")
+    assert e < 1e-3
+
+
+@pytest.mark.parametrize("tol", [1e-6, 1e-8])
+def test_mixed_solve_reaches_fp64_residual(mixed, tol):
+    from oracle import solver
+
+    wl, m, g, dd, ctx, ref = mixed
+    f = W.sources(wl)[0]
+    say(f"[mixed solve] tol={tol}")
+    u, st = ctx.solve(torch.as_tensor(f, device="cuda"), tol=tol, maxit=500)
+    u64, st64 = ref.solve(torch.as_tensor(f, device="cuda"), tol=tol, maxit=500)
+    ud = solver.direct(g, f)
+    e, e64 = rel(_np(u), ud), rel(_np(u64), ud)
+    say(f"  mixed: iters {st.iters} relres {st.relres:.2e} err vs oracle {e:.2e}; "
+        f"fp64: iters {st64.iters} err {e64:.2e}")
+    assert st.relres <= tol
+    assert abs(st.iters - st64.iters) <= 3
+    # the same solution quality as the FP64 solver at the same tolerance
+    assert e < 10 * max(e64, tol)
+
+
+# ---------------------------------------------------------------------------
+# adjoint gradient
+# ---------------------------------------------------------------------------
+
+def _gradient_problem(nx, n1, nsrc, seed=2):
+    base = W.GRAD_512
+    wl = W.scaled(base, nx, n1=n1, n2=n1, sources=W.sources_along_line(nsrc, 0.05))
+    m_true = W.slowness2(W.scaled(base, nx, medium="grf_m"))
+    m0 = W.smoothed_model(m_true, 20.0 * nx / 512)
+    f = W.sources(wl)
+    rec = W.receiver_row(wl)
+    return wl, m_true, m0, f, rec
+
+
+def _data(wl, m_true, f, rec):
+    from oracle.fd import Grid
+    from oracle import solver
+
+    g = Grid(wl.nx, wl.ny, wl.h, wl.k, m_true)
+    u = solver.direct(g, f)
+    return np.ascontiguousarray(u.reshape(f.shape[0], -1)[:, rec])
+
+
+@pytest.mark.parametrize("nx,n1,nsrc", [(64, 4, 3), (512, 8, 16)])
+def test_gradient_matches_oracle_direct(hbj, nx, n1, nsrc):
+    from oracle import gradient
+    from oracle.fd import Grid
+
+    wl, m_true, m0, f, rec = _gradient_problem(nx, n1, nsrc)
+    d = _data(wl, m_true, f, rec)
+    say(f"[gradient] nx={nx} {n1}x{n1} sources={nsrc}")
+    ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=torch.as_tensor(m0, device="cuda"))
+    ctx.factor()
+    loss, grad = ctx.gradient(torch.as_tensor(f, device="cuda"), torch.as_tensor(rec, device="cuda"),
+                              torch.as_tensor(d, device="cuda"), tol=1e-12)
+    grad = _np(grad)
+    ctx.close()
+    L0, g0 = gradient.misfit_and_gradient(Grid(wl.nx, wl.ny, wl.h, wl.k, m0), f, rec.astype(np.int64), d)
+    e = rel(grad, g0)
+    say(f"  loss {loss:.6e} vs oracle {L0:.6e}; gradient error vs direct-solve gradient {e:.2e}")
+    assert abs(loss - L0) <= 1e-8 * abs(L0)
+    assert e < 1e-8
+
+
+def test_gradient_central_differences_oracle_loss(hbj):
+    """Directional derivatives <grad, dm> against central differences of the oracle's direct misfit."""
+    from oracle import gradient
+    from oracle.fd import Grid
+
+    wl, m_true, m0, f, rec = _gradient_problem(64, 4, 3)
+    d = _data(wl, m_true, f, rec)
+    ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=torch.as_tensor(m0, device="cuda"))
+    ctx.factor()
+    say("[gradient fd] nx=64")
+    loss, grad = ctx.gradient(torch.as_tensor(f, device="cuda"), torch.as_tensor(rec, device="cuda"),
+                              torch.as_tensor(d, device="cuda"), tol=1e-12)
+    grad = _np(grad)
+    ctx.close()
+    eps = 1e-6
+    worst = 0.0
+    for j in range(20):
+        dm = np.random.default_rng(100 + j).standard_normal(m0.shape)
+        dm /= np.abs(dm).max()
+        Lp = gradient.misfit(Grid(wl.nx, wl.ny, wl.h, wl.k, m0 + eps * dm), f, rec, d)
+        Lm = gradient.misfit(Grid(wl.nx, wl.ny, wl.h, wl.k, m0 - eps * dm), f, rec, d)
+        fd = (Lp - Lm) / (2 * eps)
+        an = float(np.sum(grad * dm))
+        worst = max(worst, abs(fd - an) / abs(an))
+    say(f"  worst relative FD error over 20 directions: {worst:.2e}")
+    assert worst < 1e-5
+
+
+def test_gradient_full_size_central_differences_gpu_loss(hbj):
+    """512^2, 8 x 8 of 64^2, 16 sources: central differences of the GPU misfit (solves at tol
+    1e-12) on seeded directions against the GPU adjoint gradient."""
+    wl, m_true, m0, f, rec = _gradient_problem(512, 8, 16)
+    d = _data(wl, m_true, f, rec)
+    ft, rt, dt = (torch.as_tensor(x, device="cuda") for x in (f, rec, d))
+    ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=torch.as_tensor(m0, device="cuda"))
+    ctx.factor()
+    say("[gradient fd] nx=512 16 sources")
+    loss, grad = ctx.gradient(ft, rt, dt, tol=1e-12)
+    grad = _np(grad)
+    eps = 1e-6
+    worst = 0.0
+    for j in range(4):
+        dm = np.random.default_rng(100 + j).standard_normal(m0.shape)
+        dm /= np.abs(dm).max()
+        L = []
+        for sgn in (1, -1):
+            ctx.set_slowness2(torch.as_tensor(m0 + sgn * eps * dm, device="cuda"))
+            ctx.factor()
+            L.append(ctx.gradient(ft, rt, dt, tol=1e-13)[0])
+        fd = (L[0] - L[1]) / (2 * eps)
+        an = float(np.sum(grad * dm))
+        worst = max(worst, abs(fd - an) / abs(an))
+        say(f"  direction {j}: fd {fd:.8e} adjoint {an:.8e}")
+    ctx.close()
+    assert worst < 1e-5
+
+
+def test_autograd_function(hbj):
+    from paper_2209_10886_amd.autograd import misfit
+
+    wl, m_true, m0, f, rec = _gradient_problem(64, 4, 2)
+    d = _data(wl, m_true, f, rec)
+    ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=torch.as_tensor(m0, device="cuda"))
+    m = torch.as_tensor(m0, device="cuda").requires_grad_(True)
+    say("[autograd]")
+    L = misfit(m, ctx, torch.as_tensor(f, device="cuda"), torch.as_tensor(rec, device="cuda"),
+               torch.as_tensor(d, device="cuda"), 1e-12)
+    (2.0 * L).backward()
+    loss, grad = ctx.gradient(torch.as_tensor(f, device="cuda"), torch.as_tensor(rec, device="cuda"),
+                              torch.as_tensor(d, device="cuda"), tol=1e-12)
+    ctx.close()
+    assert abs(L.item() - loss) <= 1e-12 * abs(loss)
+    assert torch.allclose(m.grad, 2.0 * grad, rtol=1e-9, atol=0)
