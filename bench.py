@@ -40,29 +40,15 @@ def log(*a):
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=3)
+    p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="fp64_1024_8x8_grf")
     p.add_argument("--tol", type=float, default=1e-6)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
+    p.add_argument("--no-banded", action="store_true", help="skip the banded-operator comparison")
     p.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle sample")
     return p.parse_args()
-
-
-def kernel_roofline(ctx, hbj, name_by_class):
-    best = None
-    for kc, name in name_by_class.items():
-        ks = ctx.kernel_stats(kc)
-        if ks["launches"] == 0:
-            continue
-        if best is None or ks["ms"] > best[1]["ms"]:
-            best = (name, ks)
-    name, ks = best
-    avg_ms = ks["ms"] / ks["launches"]
-    bytes_per_launch = ks["bytes"] / ks["launches"]
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    return name, ks, avg_ms, bytes_per_launch, achieved
 
 
 def traffic_from_profiles(kernel_symbol):
@@ -126,13 +112,58 @@ def cpu_baseline(wl, m, f, iters_gpu, target_s):
     }
 
 
+def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, profile_names):
+    """Setup + factor (untimed), warmup solves, timed solves, one profiled solve."""
+    import torch
+
+    ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=mt, precision=precision, precond=hbj.PC_BJ,
+                    operator_form=operator_form, device=mt.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.factor()
+    torch.cuda.synchronize()
+    t_factor = time.perf_counter() - t0
+    st = None
+    for _ in range(warmup):
+        _, st = ctx.solve(ft, tol=tol, out=u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = ctx.solve(ft, tol=tol, out=u)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.reset_kernel_stats()
+    ctx.set_profiling(True)
+    ctx.solve(ft, tol=tol, out=u)
+    ctx.set_profiling(False)
+    stats = {name: ctx.kernel_stats(kc) for kc, name in profile_names.items()}
+    ctx.close()
+    return {"seconds": dt, "steps": steps, "factor_s": t_factor, "stats": st, "kernels": stats}
+
+
+def roofline_of(kernels):
+    name, ks = max(kernels.items(), key=lambda kv: kv[1]["ms"])
+    avg_ms = ks["ms"] / ks["launches"]
+    bpl = ks["bytes"] / ks["launches"]
+    achieved = bpl / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(name), "bytes_per_launch": bpl,
+            "avg_launch_ms": avg_ms, "launches": ks["launches"],
+            "share_of_kernel_time": ks["ms"] / max(1e-12, sum(k["ms"] for k in kernels.values()))}
+
+
+def solve_gbs(kernels, names):
+    b = sum(kernels[n]["bytes"] for n in names)
+    t = sum(kernels[n]["ms"] for n in names)
+    return b / (t * 1e-3) / 1e9 if t > 0 else None
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form of the sweep is a "
               "design, not a measured configuration", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     import paper_2209_10886_amd as hbj
@@ -146,46 +177,23 @@ def main():
     mt = torch.as_tensor(m, device=dev)
     ft = torch.as_tensor(f, device=dev)
     u = torch.empty_like(ft)
+    names64 = {hbj.K_FWD: "k_fwd<double,16,4,5>", hbj.K_BWD: "k_bwd<double,16,2,3>",
+               hbj.K_SCATTER: "k_scatter_apply<double2>", hbj.K_KRYLOV: "krylov"}
+    names32 = {hbj.K_FWD: "k_fwd<float,16,4,8>", hbj.K_BWD: "k_bwd<float,16,2,4>",
+               hbj.K_SCATTER: "k_scatter_apply<float2>", hbj.K_KRYLOV: "krylov"}
 
-    def make(precision):
-        ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=mt, precision=precision, precond=hbj.PC_BJ, device=dev)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ctx.factor()
-        torch.cuda.synchronize()
-        return ctx, time.perf_counter() - t0
-
-    log("[bench] setup + factor (FP64)")
-    ctx, t_factor = make(hbj.FP64)
-    log(f"[bench] factor {t_factor:.3f} s; warmup {args.warmup}")
-    st = None
-    for _ in range(args.warmup):
-        _, st = ctx.solve(ft, tol=args.tol, out=u)
-    log(f"[bench] timed {args.steps} solves")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, st = ctx.solve(ft, tol=args.tol, out=u)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = dt / max(args.steps, 1) * 1e3
-    log(f"[bench] {ms_per_step:.1f} ms/solve, iters {st.iters}, relres {st.relres:.2e}")
-
-    # profiled solve (HIP events around every launch group on the solver stream)
-    ctx.reset_kernel_stats()
-    ctx.set_profiling(True)
-    ctx.solve(ft, tol=args.tol, out=u)
-    ctx.set_profiling(False)
-    names = {hbj.K_FWD: "k_fwd<double,32>", hbj.K_BWD: "k_bwd<double,32>"}
-    kname, ks, avg_ms, bpl, achieved = kernel_roofline(ctx, hbj, names)
-    fwd, bwd = ctx.kernel_stats(hbj.K_FWD), ctx.kernel_stats(hbj.K_BWD)
-    solve_gbs = (fwd["bytes"] + bwd["bytes"]) / ((fwd["ms"] + bwd["ms"]) * 1e-3) / 1e9
-    traffic = traffic_from_profiles(kname)
-    log(f"[bench] dominant {kname}: {ks['launches']} launches, {avg_ms:.3f} ms avg, {achieved:.1f} GB/s")
+    log("[bench] FP64, dense scattering operators (headline)")
+    main_run = run_form(hbj, wl, mt, ft, u, hbj.FP64, hbj.OP_DENSE, args.steps, args.warmup, args.tol, names64)
+    st = main_run["stats"]
+    ms_per_step = main_run["seconds"] / max(args.steps, 1) * 1e3
+    log(f"[bench] {ms_per_step:.2f} ms/solve, iters {st.iters}, relres {st.relres:.2e}, "
+        f"factor {main_run['factor_s']:.2f} s")
+    roof = roofline_of(main_run["kernels"])
+    log(f"[bench] dominant {roof['kernel']}: {roof['avg_launch_ms']:.4f} ms avg, {roof['achieved']:.1f} GB/s")
 
     result = {
         "metric": "Helmholtz solves/s at rel-res 1e-6; subdomain-solve HBM GB/s (FP64 vs mixed)",
-        "value": args.steps / dt,
+        "value": args.steps / main_run["seconds"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -199,37 +207,35 @@ def main():
         "config": {"workload": wl.name, "grid": [wl.nx, wl.ny], "decomposition": [wl.n1, wl.n2],
                    "subdomain": [wl.sub_nx, wl.sub_ny], "points_per_wavelength": wl.ppw, "k": wl.k,
                    "medium": "seeded smooth random c in [0.8, 1.2]", "sources": 1, "tol": args.tol,
-                   "krylov": "GMRES(50), right-preconditioned", "preconditioner": "block Jacobi, width N1"},
+                   "krylov": "GMRES(50), right-preconditioned", "preconditioner": "block Jacobi, width N1",
+                   "operator_form": "dense local scattering operators (formed at factor time)"},
         "iters": st.iters,
         "relres": st.relres,
         "steps_per_pc": st.steps_per_pc,
-        "factor_s": t_factor,
-        "subdomain_solve_gbs": solve_gbs,
-        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "bytes_per_launch": bpl, "avg_launch_ms": avg_ms, "launches": ks["launches"]},
+        "factor_s": main_run["factor_s"],
+        "subdomain_solve_gbs": solve_gbs(main_run["kernels"], [names64[hbj.K_FWD], names64[hbj.K_BWD]]),
+        "roofline": roof,
     }
-    ctx.close()
+
+    if not args.no_banded:
+        log("[bench] FP64, banded local solves inside GMRES")
+        br = run_form(hbj, wl, mt, ft, u, hbj.FP64, hbj.OP_BANDED, 1, 0, args.tol, names64)
+        result["banded_fp64"] = {
+            "solves_per_s": 1.0 / br["seconds"], "iters": br["stats"].iters, "relres": br["stats"].relres,
+            "subdomain_solve_gbs": solve_gbs(br["kernels"], [names64[hbj.K_FWD], names64[hbj.K_BWD]]),
+            "roofline": roofline_of(br["kernels"])}
 
     if not args.no_mixed:
-        log("[bench] mixed precision (complex64 factors)")
-        cm, tfm = make(hbj.MIXED)
-        _, stm = cm.solve(ft, tol=args.tol, out=u)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            _, stm = cm.solve(ft, tol=args.tol, out=u)
-        torch.cuda.synchronize()
-        dtm = time.perf_counter() - t0
-        cm.reset_kernel_stats()
-        cm.set_profiling(True)
-        cm.solve(ft, tol=args.tol, out=u)
-        cm.set_profiling(False)
-        mf, mb = cm.kernel_stats(hbj.K_FWD), cm.kernel_stats(hbj.K_BWD)
-        result["mixed"] = {"solves_per_s": args.steps / dtm, "iters": stm.iters, "relres": stm.relres,
-                           "factor_s": tfm,
-                           "subdomain_solve_gbs": (mf["bytes"] + mb["bytes"]) / ((mf["ms"] + mb["ms"]) * 1e-3) / 1e9}
-        cm.close()
+        log("[bench] mixed precision (complex64 factors and preconditioner operators)")
+        mr = run_form(hbj, wl, mt, ft, u, hbj.MIXED, hbj.OP_DENSE, args.steps, 1, args.tol, names32)
+        result["mixed"] = {"solves_per_s": args.steps / mr["seconds"], "iters": mr["stats"].iters,
+                           "relres": mr["stats"].relres, "factor_s": mr["factor_s"],
+                           "roofline": roofline_of(mr["kernels"])}
+        if not args.no_banded:
+            mb = run_form(hbj, wl, mt, ft, u, hbj.MIXED, hbj.OP_BANDED, 1, 0, args.tol, names32)
+            result["banded_mixed"] = {
+                "solves_per_s": 1.0 / mb["seconds"], "iters": mb["stats"].iters,
+                "subdomain_solve_gbs": solve_gbs(mb["kernels"], [names32[hbj.K_FWD], names32[hbj.K_BWD]])}
 
     if not args.no_cpu:
         log("[bench] CPU oracle sample")

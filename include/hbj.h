@@ -69,6 +69,12 @@ enum { HBJ_PC_NONE = 0, HBJ_PC_SGS = 1, HBJ_PC_BJ = 2 };
 /* how block-Jacobi intervals combine at their shared anti-diagonal group */
 enum { HBJ_BJ_RESTRICTED = 0,   /* upstream interval owns the shared group        */
        HBJ_BJ_ADDITIVE = 1 };   /* both contributions summed (literal Sec. 6 sum) */
+/* how the scattering operators are applied inside GMRES */
+enum { HBJ_OP_BANDED = 0,       /* a banded local solve per application (Sec. 4)   */
+       HBJ_OP_DENSE = 1 };      /* each subdomain's local scattering operator formed
+                                   once as a dense L x L matrix (L = 2 sub_nx +
+                                   2 sub_ny) at factor time; every application is
+                                   then a batched matrix-vector product           */
 /* how the forward and backward block-Jacobi passes compose */
 enum { HBJ_BJ_PRODUCT = 0,      /* z = B_U^{-1} B_L^{-1} r, like SGS              */
        HBJ_BJ_RESIDUAL = 1 };   /* additive-projection half steps (Sec. 6)        */
@@ -83,6 +89,7 @@ typedef struct {
   int32_t bj_width;      /* anti-diagonals per partial sweep; 0 = n1 (Sec. 6)      */
   int32_t bj_combine;    /* HBJ_BJ_RESTRICTED | HBJ_BJ_ADDITIVE                     */
   int32_t bj_compose;    /* HBJ_BJ_PRODUCT | HBJ_BJ_RESIDUAL                        */
+  int32_t operator_form; /* HBJ_OP_BANDED | HBJ_OP_DENSE                            */
 } hbj_problem;
 
 typedef struct {

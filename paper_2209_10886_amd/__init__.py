@@ -30,6 +30,7 @@ FP64, MIXED = 0, 1
 PC_NONE, PC_SGS, PC_BJ = 0, 1, 2
 BJ_RESTRICTED, BJ_ADDITIVE = 0, 1
 BJ_PRODUCT, BJ_RESIDUAL = 0, 1
+OP_BANDED, OP_DENSE = 0, 1
 OK, EINVAL, ESTATE, EHIP, ENOMEM, ZERO_PIVOT, NOT_CONVERGED = 0, -1, -2, -3, -4, 1, 2
 K_FWD, K_BWD, K_FACTOR, K_KRYLOV, K_SCATTER = 0, 1, 2, 3, 4
 
@@ -38,7 +39,7 @@ class Problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("h", ctypes.c_double), ("k", ctypes.c_double),
                 ("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("bj_width", ctypes.c_int32), ("bj_combine", ctypes.c_int32),
-                ("bj_compose", ctypes.c_int32)]
+                ("bj_compose", ctypes.c_int32), ("operator_form", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -274,9 +275,10 @@ class Context:
 
 
 def setup(nx, ny, k, n1, n2, c=None, m=None, h=0.0, precision=FP64, precond=PC_BJ, bj_width=0,
-          bj_combine=BJ_RESTRICTED, bj_compose=BJ_PRODUCT, device="cuda", stream=None) -> Context:
+          bj_combine=BJ_RESTRICTED, bj_compose=BJ_PRODUCT, operator_form=OP_BANDED, device="cuda",
+          stream=None) -> Context:
     """hbj_setup with a wave speed c (or squared slowness m) given as a [ny, nx] float64 tensor."""
-    prob = Problem(nx, ny, h, k, n1, n2, precision, precond, bj_width, bj_combine, bj_compose)
+    prob = Problem(nx, ny, h, k, n1, n2, precision, precond, bj_width, bj_combine, bj_compose, operator_form)
     if c is None and m is None:
         raise ValueError("give c or m")
     if c is None:

@@ -121,7 +121,25 @@ struct SolveIO {
   const double2* tr_base; // dst = base + sign * out ; null = 0
   double tr_sign;
   int tr_reflect;         // include -rho g (the incoming data) in the outgoing trace
+  int unit;               // right-hand side = unit Robin datum at local interface position entry.rhs
 };
+
+// Local interface positions of a subdomain: faces W, E, S, N in this order, each with
+// its entries ordered along the face; L = 2 sny + 2 snx.
+__host__ __device__ inline int face_len(const Geom& g, int f) { return f < 2 ? g.sny : g.snx; }
+__host__ __device__ inline int face_off(const Geom& g, int f) {
+  return f == 0 ? 0 : f == 1 ? g.sny : f == 2 ? 2 * g.sny : 2 * g.sny + g.snx;
+}
+__host__ __device__ inline int local_if_len(const Geom& g) { return 2 * g.sny + 2 * g.snx; }
+__host__ __device__ inline void local_if_face(const Geom& g, int q, int* f, int* ee) {
+  int ff = (q < g.sny) ? 0 : (q < 2 * g.sny) ? 1 : (q < 2 * g.sny + g.snx) ? 2 : 3;
+  *f = ff;
+  *ee = q - face_off(g, ff);
+}
+// local row of the edge node of face f, entry ee
+__host__ __device__ inline int face_node(const Geom& g, int f, int ee) {
+  return f == 0 ? ee * g.snx : f == 1 ? ee * g.snx + g.snx - 1 : f == 2 ? ee : (g.sny - 1) * g.snx + ee;
+}
 
 // ---------------------------------------------------------------------------
 // launchers (each returns hipError_t of the launch)
@@ -164,6 +182,13 @@ hipError_t launch_copy(double2* dst, const double2* src, size_t n, hipStream_t s
 hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t st);
 hipError_t launch_add_ranges(double2* y, const double2* x, const int32_t* ranges, int nranges, int nif, int ncol,
                              hipStream_t st);
+
+// dense scattering operators T[s][col][row] (column-major, L x L per subdomain)
+hipError_t launch_build_T(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
+                          const double2* ybuf, size_t ystride, double2* T, hipStream_t st);
+template <typename C>
+hipError_t launch_scatter_apply(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const C* T,
+                                const SolveIO& io, hipStream_t st);
 
 // gradient / misc
 hipError_t launch_gather_receivers(const double2* u, const int32_t* rec, int nrec, int npts, const double2* d,

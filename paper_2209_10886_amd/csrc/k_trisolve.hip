@@ -38,6 +38,11 @@ struct RhsCtx {
   __device__ double2 operator()(int l) const {
     if (l >= g.nloc) return mk(0.0, 0.0);
     if (io.rhs64) return io.rhs64[(size_t)slot * g.nloc + l];
+    if (io.unit) {  // unit Robin datum at local interface position e.rhs
+      int f, ee;
+      local_if_face(g, e.rhs, &f, &ee);
+      return (l == face_node(g, f, ee) && F.in_off[f] >= 0) ? coef[F.in_off[f] + ee].inj : mk(0.0, 0.0);
+    }
     const int ly = l / g.snx, lx = l - ly * g.snx;
     double2 v = mk(0.0, 0.0);
     if (io.f) v = io.f[(size_t)e.rhs * g.nx * g.ny + (size_t)(y0 + ly) * g.nx + x0 + lx];

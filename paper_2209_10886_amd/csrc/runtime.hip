@@ -43,6 +43,7 @@ typedef std::complex<double> zc;
 struct Step {
   size_t first;  // offset into the schedule's device entry array
   int count;
+  double dense_elems = 0;  // dense operator entries read by the step (rows x columns)
 };
 
 // All launches for a given number of right-hand sides.
@@ -51,6 +52,7 @@ struct Schedule {
   Entry* dev = nullptr;
   size_t all_first = 0;  // every subdomain, all faces
   int all_count = 0;
+  double all_dense_elems = 0;
   std::vector<Step> fwd, bwd;  // preconditioner passes
 };
 
@@ -92,6 +94,9 @@ struct hbj_ctx {
   int32_t* pflag = nullptr;
   float2* mf32 = nullptr;
   float2* mb32 = nullptr;
+  double2* T64 = nullptr;  // dense scattering operators [ndom][L][L] (column-major)
+  float2* T32 = nullptr;
+  bool dense = false;
   bool factored = false;
   int zero_sub = -1, zero_row = -1;
   // schedules
@@ -127,7 +132,7 @@ void dfree(void* p) {
 hbj_ctx::~hbj_ctx() {
   for (auto& kv : sched) dfree(kv.second->dev);
   for (void* p : {(void*)ft, (void*)coef, (void*)pos_tab, (void*)m, (void*)diag, (void*)ranges_f, (void*)ranges_b,
-                  (void*)ab, (void*)ipiv, (void*)info, (void*)mf64, (void*)mb64, (void*)pf, (void*)pflag, (void*)mf32, (void*)mb32,
+                  (void*)ab, (void*)ipiv, (void*)info, (void*)mf64, (void*)mb64, (void*)pf, (void*)pflag, (void*)mf32, (void*)mb32, (void*)T64, (void*)T32,
                   ybuf, (void*)rhs64, (void*)x64, (void*)r64, (void*)pc_y, (void*)pc_t})
     dfree(p);
   if (ev0) (void)hipEventDestroy(ev0);
@@ -233,9 +238,20 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
   S->nrhs = nrhs;
   std::vector<Entry> ent;
   S->all_first = 0;
+  auto dense_elems = [&](const Entry& e) {
+    const FaceTab& F = c->ft_host[e.s];
+    double rows = 0, cols = 0;
+    for (int f = 0; f < 4; ++f) {
+      if (F.in_off[f] < 0) continue;
+      cols += face_len(c->g, f);
+      if ((e.mask >> f) & 1) rows += face_len(c->g, f);
+    }
+    return rows * cols;
+  };
   for (int s = 0; s < c->ndom; ++s)
     for (int r = 0; r < nrhs; ++r) ent.push_back(Entry{s, r, 0, 0xF});
   S->all_count = (int)ent.size();
+  for (const Entry& e : ent) S->all_dense_elems += dense_elems(e);
   const int maskF = (1 << FACE_E) | (1 << FACE_N), maskB = (1 << FACE_W) | (1 << FACE_S);
   if (c->P.precond != HBJ_PC_NONE && c->ndom > 1) {
     int nsteps = 0;
@@ -248,6 +264,7 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
           for (int r = 0; r < nrhs; ++r) ent.push_back(Entry{s, r, t == 1 ? 0 : 1, maskF});
       }
       st.count = (int)(ent.size() - st.first);
+      for (size_t q = st.first; q < ent.size(); ++q) st.dense_elems += dense_elems(ent[q]);
       S->fwd.push_back(st);
     }
     nsteps = 0;
@@ -260,6 +277,7 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
           for (int r = 0; r < nrhs; ++r) ent.push_back(Entry{s, r, t == 1 ? 0 : 1, maskB});
       }
       st.count = (int)(ent.size() - st.first);
+      for (size_t q = st.first; q < ent.size(); ++q) st.dense_elems += dense_elems(ent[q]);
       S->bwd.push_back(st);
     }
   }
@@ -367,6 +385,15 @@ int run_solves(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io) {
   return HBJ_OK;
 }
 
+// batched application of the dense scattering operators (complex128 or complex64 storage)
+int run_dense(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io, bool c64, double elems) {
+  if (nent == 0) return HBJ_OK;
+  ProfScope ps(c, HBJ_K_SCATTER, elems * (c64 ? 8.0 : 16.0), elems * 8.0);
+  if (c64) HIPCHK(launch_scatter_apply<float2>(c->g, ent, nent, c->ft, c->T32, io, c->st));
+  else HIPCHK(launch_scatter_apply<double2>(c->g, ent, nent, c->ft, c->T64, io, c->st));
+  return HBJ_OK;
+}
+
 int check_ready(hbj_ctx* c) {
   if (!c) return fail(HBJ_EINVAL, "null context");
   if (!c->factored) return fail(HBJ_ESTATE, "hbj_factor has not run (or the medium changed)");
@@ -381,6 +408,7 @@ int op_fp64(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
   io.tr_base = g;
   io.tr_sign = -1.0;
   io.tr_reflect = 1;
+  if (c->dense) return run_dense(c, S->dev + S->all_first, S->all_count, io, false, S->all_dense_elems);
   return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
 }
 
@@ -395,7 +423,8 @@ int run_pass(hbj_ctx* c, const std::vector<Step>& steps, Entry* dev, const doubl
     io.tr_base = out;
     io.tr_sign = 1.0;
     io.tr_reflect = 1;
-    int rc = run_solves<R>(c, dev + s.first, s.count, io);
+    int rc = c->dense ? run_dense(c, dev + s.first, s.count, io, sizeof(R) == 4, s.dense_elems)
+                      : run_solves<R>(c, dev + s.first, s.count, io);
     if (rc) return rc;
   }
   return HBJ_OK;
@@ -469,6 +498,7 @@ hipError_t launch_axpy_c64(double2* x64, const float2* dx, const Geom& g, const 
 static const int kLocalRefine = 3;
 
 int op_mixed(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
+  if (c->dense) return op_fp64(c, S, g, out);  // the complex128 dense operator is exact already
   const Entry* ent = S->dev + S->all_first;
   const int nent = S->all_count;
   int rc = ensure_loc64(c, nent);
@@ -747,6 +777,10 @@ int hbj_setup(const hbj_problem* prob, const double* c_dev, void* stream, hbj_ct
   if (P.precond < HBJ_PC_NONE || P.precond > HBJ_PC_BJ) return fail(HBJ_EINVAL, "bad preconditioner");
   if (P.bj_combine < 0 || P.bj_combine > 1 || P.bj_compose < 0 || P.bj_compose > 1 || P.bj_width < 0)
     return fail(HBJ_EINVAL, "bad block-Jacobi option");
+  if (P.operator_form != HBJ_OP_BANDED && P.operator_form != HBJ_OP_DENSE)
+    return fail(HBJ_EINVAL, "bad operator form");
+  if (P.operator_form == HBJ_OP_DENSE && 2 * (P.nx / P.n1 + P.ny / P.n2) > 1024)
+    return fail(HBJ_EINVAL, "dense operators need 2 (sub_nx + sub_ny) <= 1024");
   if ((size_t)P.nx * P.ny > (size_t)1 << 31) return fail(HBJ_EINVAL, "grid too large");
   std::unique_ptr<hbj_ctx> c(new hbj_ctx());
   c->P = P;
@@ -841,6 +875,47 @@ int hbj_set_slowness2(hbj_ctx* c, const double* m_dev) {
   return assemble_medium(c);
 }
 
+// Dense scattering operators: one unit-datum local solve per (subdomain, interface
+// position), in chunks, then T[s][col][row] = -sigma x_row - rho delta_{row,col}.
+static int build_dense(hbj_ctx* c) {
+  const Geom& g = c->g;
+  const int L = local_if_len(g);
+  const size_t per = (size_t)L * L;
+  if (!c->T64 && dalloc(&c->T64, per * c->ndom)) return fail(HBJ_ENOMEM, "dense operator allocation failed");
+  if (c->P.precision == HBJ_MIXED && !c->T32 && dalloc(&c->T32, per * c->ndom))
+    return fail(HBJ_ENOMEM, "dense operator allocation failed");
+  HIPCHK(launch_fill_zero(c->T64, per * c->ndom * sizeof(double2), c->st));
+  std::vector<Entry> all;
+  for (int s = 0; s < c->ndom; ++s)
+    for (int col = 0; col < L; ++col) {
+      int f, ee;
+      local_if_face(g, col, &f, &ee);
+      if (c->ft_host[s].in_off[f] >= 0) all.push_back(Entry{s, col, 0, 0});
+    }
+  const int chunk = (int)std::min<size_t>(4096, all.size());
+  Entry* dev = nullptr;
+  HIPCHK(dalloc(&dev, (size_t)chunk));
+  SolveIO io{};
+  io.unit = 1;
+  int rc = HBJ_OK;
+  for (size_t off = 0; off < all.size() && rc == HBJ_OK; off += chunk) {
+    const int n = (int)std::min<size_t>(chunk, all.size() - off);
+    hipError_t he = hipMemcpyAsync(dev, all.data() + off, n * sizeof(Entry), hipMemcpyHostToDevice, c->st);
+    if (he != hipSuccess) { rc = fail(HBJ_EHIP, hipGetErrorString(he)); break; }
+    rc = run_solves<double>(c, dev, n, io);
+    if (rc) break;
+    he = launch_build_T(g, dev, n, c->ft, c->coef, (const double2*)c->ybuf, (size_t)c->L.nblk * c->L.nb, c->T64,
+                        c->st);
+    if (he != hipSuccess) rc = fail(HBJ_EHIP, hipGetErrorString(he));
+  }
+  hipError_t he = hipStreamSynchronize(c->st);
+  dfree(dev);
+  if (rc) return rc;
+  if (he != hipSuccess) return fail(HBJ_EHIP, hipGetErrorString(he));
+  if (c->T32) HIPCHK(launch_cast_c64(c->T64, c->T32, per * c->ndom, c->st));
+  return HBJ_OK;
+}
+
 int hbj_factor(hbj_ctx* c) {
   if (!c) return fail(HBJ_EINVAL, "null context");
   const Geom& g = c->g;
@@ -876,6 +951,12 @@ int hbj_factor(hbj_ctx* c) {
   if (c->P.precision == HBJ_MIXED) {
     HIPCHK(launch_cast_c64(c->mf64, c->mf32, L.mf_per_sub * c->ndom, c->st));
     HIPCHK(launch_cast_c64(c->mb64, c->mb32, L.mb_per_sub * c->ndom, c->st));
+  }
+  c->dense = false;
+  if (c->P.operator_form == HBJ_OP_DENSE && c->g.nif > 0) {
+    const int rc = build_dense(c);
+    if (rc) return rc;
+    c->dense = true;
   }
   HIPCHK(hipStreamSynchronize(c->st));
   c->factored = true;

@@ -49,8 +49,8 @@ def test_setup_rejects_bad_sizes_before_touching_the_gpu():
     lib = hbj._lib
     out = ctypes.c_void_p()
     for (nx, ny, n1, n2) in [(10, 10, 3, 2), (4, 4, 4, 1), (0, 8, 1, 1)]:
-        p = hbj.Problem(nx, ny, 0.0, 10.0, n1, n2, 0, 2, 0, 0, 0)
+        p = hbj.Problem(nx, ny, 0.0, 10.0, n1, n2, 0, 2, 0, 0, 0, 0)
         code = lib.hbj_setup(ctypes.byref(p), ctypes.c_void_p(16), None, ctypes.byref(out))
         assert code == hbj.EINVAL
-    p = hbj.Problem(16, 16, 0.0, 10.0, 2, 2, 7, 2, 0, 0, 0)  # bad precision
+    p = hbj.Problem(16, 16, 0.0, 10.0, 2, 2, 7, 2, 0, 0, 0, 0)  # bad precision
     assert lib.hbj_setup(ctypes.byref(p), ctypes.c_void_p(16), None, ctypes.byref(out)) == hbj.EINVAL

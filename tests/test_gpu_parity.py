@@ -168,3 +168,49 @@ def test_zero_rhs(ctxs):
     say("[zero rhs]")
     u, st = ctx.solve(f)
     assert st.iters == 0 and torch.count_nonzero(u).item() == 0
+
+
+# ---------------------------------------------------------------------------
+# dense scattering operators (formed at factor time) must reproduce the same operators
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["small", "ragged", "rect", "grf256", "strip", "pivot"])
+def test_dense_operator(ctxs, name):
+    wl, m, g, dd, ctx = ctxs(name, operator_form=1)
+    gv = W.random_interface_vector(ctx.nif, seed=1)
+    say(f"[dense operator] case={name}")
+    w = _to_np(ctx.apply_operator(torch.as_tensor(gv, device="cuda")))
+    assert rel(w, dd.apply_operator(gv)) < 1e-12
+
+
+@pytest.mark.parametrize("name,kw,okw", [
+    ("small", dict(precond=2), dict(kind="bj")),
+    ("grf256", dict(precond=1), dict(kind="sgs")),
+    ("grf256", dict(precond=2), dict(kind="bj")),
+    ("grf256", dict(precond=2, bj_combine=1, bj_compose=1), dict(kind="bj", combine="additive", compose="residual")),
+    ("strip", dict(precond=2, bj_width=2), dict(kind="bj", width=2)),
+    ("rect", dict(precond=2), dict(kind="bj")),
+])
+def test_dense_preconditioner(ctxs, name, kw, okw):
+    from oracle import sweep
+
+    wl, m, g, dd, ctx = ctxs(name, operator_form=1, **kw)
+    r = W.random_interface_vector(ctx.nif, seed=2)
+    say(f"[dense precond] case={name} {kw}")
+    z = _to_np(ctx.apply_preconditioner(torch.as_tensor(r, device="cuda")))
+    assert rel(z, sweep.apply_preconditioner(dd, r, **okw)) < 1e-11
+
+
+@pytest.mark.parametrize("name,kw", [("small", {}), ("grf256", {}), ("strip", {}), ("pivot", {}),
+                                     ("grf256", dict(precision=1))])
+def test_dense_solve(ctxs, name, kw):
+    from oracle import solver
+
+    wl, m, g, dd, ctx = ctxs(name, operator_form=1, **kw)
+    f = W.sources(wl)[0]
+    say(f"[dense solve] case={name} {kw}")
+    u, st = ctx.solve(torch.as_tensor(f, device="cuda"), tol=1e-12, maxit=3000)
+    ud = solver.direct(g, f)
+    e = rel(_to_np(u), ud)
+    say(f"  iters {st.iters} relres {st.relres:.2e} err vs direct {e:.2e}")
+    assert e < 1e-8
+    assert st.relres <= 1e-12
