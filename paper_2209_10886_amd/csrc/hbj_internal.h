@@ -122,6 +122,8 @@ struct SolveIO {
   double tr_sign;
   int tr_reflect;         // include -rho g (the incoming data) in the outgoing trace
   int unit;               // right-hand side = unit Robin datum at local interface position entry.rhs
+  const int32_t* nz;      // [nrhs][ndom] 0 = the entry's source restriction is identically zero and
+                          // the entry has no incoming data: its solution is 0 (the solve is skipped)
 };
 
 // Local interface positions of a subdomain: faces W, E, S, N in this order, each with
@@ -183,11 +185,13 @@ hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t st);
 hipError_t launch_add_ranges(double2* y, const double2* x, const int32_t* ranges, int nranges, int nif, int ncol,
                              hipStream_t st);
 
-// dense scattering operators T[s][col][row] (column-major, L x L per subdomain)
+hipError_t launch_source_flags(const Geom& g, const double2* f, int nrhs, int32_t* nz, hipStream_t st);
+// dense scattering operators T[s][col][row] (column-major, L x L per subdomain); every entry of
+// one launch carries the same face mask
 hipError_t launch_build_T(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
                           const double2* ybuf, size_t ystride, double2* T, hipStream_t st);
 template <typename C>
-hipError_t launch_scatter_apply(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const C* T,
+hipError_t launch_scatter_apply(const Geom& g, const Entry* ent, int nent, int mask, const FaceTab* ft, const C* T,
                                 const SolveIO& io, hipStream_t st);
 
 // gradient / misc

@@ -111,19 +111,32 @@ __device__ inline int edge_row(const Geom& g, int q) {
   return (1 + q) * g.snx + g.snx - 1;
 }
 
-template <typename C>
-__device__ inline C shfl_xor_c(C v, int m) {
-  v.x = __shfl_xor(v.x, m);
-  v.y = __shfl_xor(v.y, m);
+// Cross-lane exchange inside a quad of lanes (DPP quad_perm: no LDS round trip).
+// CTRL 0xB1 swaps lanes 0<->1 and 2<->3; 0x4E swaps the pairs (lanes 0,1 <-> 2,3).
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+template <int CTRL>
+__device__ inline float dpp_d(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL, typename C>
+__device__ inline C dpp_c(C v) {
+  v.x = dpp_d<CTRL>(v.x);
+  v.y = dpp_d<CTRL>(v.y);
   return v;
 }
 
-// sum over the CG adjacent lanes that share one window row
+// sum over the CG adjacent lanes (CG = 1, 2 or 4, aligned in a quad) that share one window row
 template <int CG, typename C>
 __device__ inline C row_reduce(C acc) {
-  if (CG >= 2) acc = cadd(acc, shfl_xor_c(acc, 1));
-  if (CG >= 4) acc = cadd(acc, shfl_xor_c(acc, 2));
-  if (CG >= 8) acc = cadd(acc, shfl_xor_c(acc, 4));
+  static_assert(CG == 1 || CG == 2 || CG == 4, "column groups must fit a quad of lanes");
+  if (CG >= 2) acc = cadd(acc, dpp_c<0xB1>(acc));
+  if (CG >= 4) acc = cadd(acc, dpp_c<0x4E>(acc));
   return acc;
 }
 
@@ -146,6 +159,7 @@ __global__ __launch_bounds__(576) void k_fwd(Geom g, SolveLayout L, const Entry*
   C* bufB = bufA + wf;
   int* ident = reinterpret_cast<int*>(bufB + wf);
   const Entry e = ent[blockIdx.x];
+  if (io.nz && !io.nz[(size_t)e.rhs * g.n1 * g.n2 + e.s]) return;  // zero right-hand side: x = 0
   const FaceTab F = ft[e.s];
   const RhsCtx rhs(g, e, F, coef, io, blockIdx.x);
   const int ylen = nblk * NB;
@@ -236,6 +250,16 @@ __global__ __launch_bounds__(576) void k_bwd(Geom g, SolveLayout L, const Entry*
   const C* M = MB + (size_t)e.s * L.mb_per_sub;
   const double2* gin = e.src ? io.g_b : io.g_a;
   if (gin) gin += (size_t)e.rhs * g.nif;
+  if (io.nz && !io.nz[(size_t)e.rhs * g.n1 * g.n2 + e.s]) {  // zero right-hand side: x = 0
+    if (io.u || io.x64)
+      for (int l = threadIdx.x; l < g.nloc; l += blockDim.x) emit_field(g, e, io, blockIdx.x, l, mk(0.0, 0.0));
+    if (io.tr_dst) {
+      const int nedge = 2 * g.snx + 2 * (g.sny - 2);
+      for (int q = threadIdx.x; q < nedge; q += blockDim.x)
+        emit_traces(g, e, F, coef, io, gin, edge_row(g, q), mk(0.0, 0.0));
+    }
+    return;
+  }
   const int cg = tid % CG, r = tid / CG;
   const bool act = r < wb;
   const size_t bstride = (size_t)NB * wb;
@@ -300,6 +324,21 @@ __global__ __launch_bounds__(576) void k_bwd(Geom g, SolveLayout L, const Entry*
       emit_traces(g, e, F, coef, io, gin, l, to_d(y[l]));
     }
   }
+}
+
+// nz[rhs][s] = 1 if the source restricted to subdomain s is not identically zero
+__global__ void k_source_flags(Geom g, const double2* f, int32_t* nz) {
+  const int s = blockIdx.x, rhs = blockIdx.y;
+  const int x0 = (s % g.n1) * g.snx, y0 = (s / g.n1) * g.sny;
+  const double2* fr = f + (size_t)rhs * g.nx * g.ny;
+  int any = 0;
+  for (int l = threadIdx.x; l < g.nloc && !any; l += blockDim.x) {
+    const int ly = l / g.snx, lx = l - ly * g.snx;
+    const double2 v = fr[(size_t)(y0 + ly) * g.nx + x0 + lx];
+    any = (v.x != 0.0 || v.y != 0.0);
+  }
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0) nz[(size_t)rhs * g.n1 * g.n2 + s] = any;
 }
 
 // explicit complex128 right-hand sides (source + injected Robin data) of a batch
@@ -414,5 +453,10 @@ hipError_t launch_axpy_c64(double2* x64, const float2* dx, const Geom& g, const 
   if (nent == 0) return hipSuccess;
   hipLaunchKernelGGL(k_axpy_c64, dim3((g.nloc + 255) / 256, nent), dim3(256), 0, st, x64, dx, g.nloc,
                      L.nblk * L.nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_source_flags(const Geom& g, const double2* f, int nrhs, int32_t* nz, hipStream_t st) {
+  hipLaunchKernelGGL(k_source_flags, dim3(g.n1 * g.n2, nrhs), dim3(256), 0, st, g, f, nz);
   return hipGetLastError();
 }

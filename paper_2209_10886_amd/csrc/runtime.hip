@@ -40,6 +40,10 @@ int fail(int code, const std::string& msg) {
 
 typedef std::complex<double> zc;
 
+// faces written by a forward sweep step (toward +x, +y) and by a backward step (toward -x, -y)
+constexpr int kMaskFwd = (1 << FACE_E) | (1 << FACE_N);
+constexpr int kMaskBwd = (1 << FACE_W) | (1 << FACE_S);
+
 struct Step {
   size_t first;  // offset into the schedule's device entry array
   int count;
@@ -108,6 +112,8 @@ struct hbj_ctx {
   double2* x64 = nullptr;
   double2* r64 = nullptr;
   size_t loc64_entries = 0;
+  int32_t* nzf = nullptr;   // per (rhs, subdomain) nonzero-source flags for the lifting
+  size_t nzf_cap = 0;
   double2* pc_y = nullptr;  // preconditioner pass buffers [nrhs][nif]
   double2* pc_t = nullptr;
   size_t pc_cols = 0;
@@ -133,7 +139,7 @@ hbj_ctx::~hbj_ctx() {
   for (auto& kv : sched) dfree(kv.second->dev);
   for (void* p : {(void*)ft, (void*)coef, (void*)pos_tab, (void*)m, (void*)diag, (void*)ranges_f, (void*)ranges_b,
                   (void*)ab, (void*)ipiv, (void*)info, (void*)mf64, (void*)mb64, (void*)pf, (void*)pflag, (void*)mf32, (void*)mb32, (void*)T64, (void*)T32,
-                  ybuf, (void*)rhs64, (void*)x64, (void*)r64, (void*)pc_y, (void*)pc_t})
+                  ybuf, (void*)nzf, (void*)rhs64, (void*)x64, (void*)r64, (void*)pc_y, (void*)pc_t})
     dfree(p);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
@@ -252,7 +258,7 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
     for (int r = 0; r < nrhs; ++r) ent.push_back(Entry{s, r, 0, 0xF});
   S->all_count = (int)ent.size();
   for (const Entry& e : ent) S->all_dense_elems += dense_elems(e);
-  const int maskF = (1 << FACE_E) | (1 << FACE_N), maskB = (1 << FACE_W) | (1 << FACE_S);
+  const int maskF = kMaskFwd, maskB = kMaskBwd;
   if (c->P.precond != HBJ_PC_NONE && c->ndom > 1) {
     int nsteps = 0;
     for (auto& b : c->fblocks) nsteps = std::max(nsteps, b.second - b.first);
@@ -386,12 +392,33 @@ int run_solves(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io) {
 }
 
 // batched application of the dense scattering operators (complex128 or complex64 storage)
-int run_dense(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io, bool c64, double elems) {
+int run_dense(hbj_ctx* c, const Entry* ent, int nent, int mask, const SolveIO& io, bool c64, double elems) {
   if (nent == 0) return HBJ_OK;
   ProfScope ps(c, HBJ_K_SCATTER, elems * (c64 ? 8.0 : 16.0), elems * 8.0);
-  if (c64) HIPCHK(launch_scatter_apply<float2>(c->g, ent, nent, c->ft, c->T32, io, c->st));
-  else HIPCHK(launch_scatter_apply<double2>(c->g, ent, nent, c->ft, c->T64, io, c->st));
+  if (c64) HIPCHK(launch_scatter_apply<float2>(c->g, ent, nent, mask, c->ft, c->T32, io, c->st));
+  else HIPCHK(launch_scatter_apply<double2>(c->g, ent, nent, mask, c->ft, c->T64, io, c->st));
   return HBJ_OK;
+}
+
+// lifting b = traces of A^{-1} f: subdomains whose source restriction is identically zero
+// contribute exactly zero and skip their solves
+int run_lifting(hbj_ctx* c, Schedule* S, const double2* f, double2* b, int nrhs) {
+  const size_t need = (size_t)nrhs * c->ndom;
+  if (need > c->nzf_cap) {
+    dfree(c->nzf);
+    c->nzf = nullptr;
+    c->nzf_cap = 0;
+    if (dalloc(&c->nzf, need)) return fail(HBJ_ENOMEM, "flag allocation failed");
+    c->nzf_cap = need;
+  }
+  HIPCHK(launch_source_flags(c->g, f, nrhs, c->nzf, c->st));
+  SolveIO io{};
+  io.f = f;
+  io.nz = c->nzf;
+  io.tr_dst = b;
+  io.tr_sign = 1.0;
+  io.tr_reflect = 0;
+  return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
 }
 
 int check_ready(hbj_ctx* c) {
@@ -408,13 +435,13 @@ int op_fp64(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
   io.tr_base = g;
   io.tr_sign = -1.0;
   io.tr_reflect = 1;
-  if (c->dense) return run_dense(c, S->dev + S->all_first, S->all_count, io, false, S->all_dense_elems);
+  if (c->dense) return run_dense(c, S->dev + S->all_first, S->all_count, 0xF, io, false, S->all_dense_elems);
   return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
 }
 
 // sweeps over the precomputed steps; in = pass input, out = pass output (pre-filled with in)
 template <typename R>
-int run_pass(hbj_ctx* c, const std::vector<Step>& steps, Entry* dev, const double2* in, double2* out) {
+int run_pass(hbj_ctx* c, const std::vector<Step>& steps, Entry* dev, const double2* in, double2* out, int mask) {
   for (const Step& s : steps) {
     SolveIO io{};
     io.g_a = in;
@@ -423,7 +450,7 @@ int run_pass(hbj_ctx* c, const std::vector<Step>& steps, Entry* dev, const doubl
     io.tr_base = out;
     io.tr_sign = 1.0;
     io.tr_reflect = 1;
-    int rc = c->dense ? run_dense(c, dev + s.first, s.count, io, sizeof(R) == 4, s.dense_elems)
+    int rc = c->dense ? run_dense(c, dev + s.first, s.count, mask, io, sizeof(R) == 4, s.dense_elems)
                       : run_solves<R>(c, dev + s.first, s.count, io);
     if (rc) return rc;
   }
@@ -439,7 +466,7 @@ int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs
   if (rc) return rc;
   double2* y = c->pc_y;
   HIPCHK(launch_copy(y, r, n, c->st));
-  rc = run_pass<R>(c, S->fwd, S->dev, r, y);
+  rc = run_pass<R>(c, S->fwd, S->dev, r, y, kMaskFwd);
   if (rc) return rc;
   if (c->P.bj_combine == HBJ_BJ_ADDITIVE) HIPCHK(launch_add_ranges(y, r, c->ranges_f, c->nranges_f, c->g.nif, nrhs, c->st));
   if (c->P.bj_compose == HBJ_BJ_RESIDUAL && c->fblocks.size() > 1) {
@@ -449,7 +476,7 @@ int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs
     if (rc) return rc;
     HIPCHK(launch_axpby(t, r, mk(1.0, 0.0), mk(-1.0, 0.0), n, c->st));  // t = r - t
     HIPCHK(launch_copy(z, t, n, c->st));
-    rc = run_pass<R>(c, S->bwd, S->dev, t, z);
+    rc = run_pass<R>(c, S->bwd, S->dev, t, z, kMaskBwd);
     if (rc) return rc;
     if (c->P.bj_combine == HBJ_BJ_ADDITIVE)
       HIPCHK(launch_add_ranges(z, t, c->ranges_b, c->nranges_b, c->g.nif, nrhs, c->st));
@@ -457,7 +484,7 @@ int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs
     return HBJ_OK;
   }
   HIPCHK(launch_copy(z, y, n, c->st));
-  rc = run_pass<R>(c, S->bwd, S->dev, y, z);
+  rc = run_pass<R>(c, S->bwd, S->dev, y, z, kMaskBwd);
   if (rc) return rc;
   if (c->P.bj_combine == HBJ_BJ_ADDITIVE) HIPCHK(launch_add_ranges(z, y, c->ranges_b, c->nranges_b, c->g.nif, nrhs, c->st));
   return HBJ_OK;
@@ -998,12 +1025,7 @@ int hbj_lifting(hbj_ctx* c, const hbj_c128* f, hbj_c128* b, int32_t nrhs) {
   rc = build_schedule(c, nrhs, &S);
   if (rc) return rc;
   if (c->g.nif == 0) return HBJ_OK;
-  SolveIO io{};
-  io.f = (const double2*)f;
-  io.tr_dst = (double2*)b;
-  io.tr_sign = 1.0;
-  io.tr_reflect = 0;
-  return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+  return run_lifting(c, S, (const double2*)f, (double2*)b, nrhs);
 }
 
 int hbj_reconstruct(hbj_ctx* c, const hbj_c128* f, const hbj_c128* g, hbj_c128* u, int32_t nrhs) {
@@ -1055,14 +1077,8 @@ static int solve_impl(hbj_ctx* c, const double2* f, double2* u, int nrhs, const 
     G.flexible = o.flexible != 0;
     rc = G.alloc();
     if (rc) return rc;
-    {
-      SolveIO io{};
-      io.f = f;
-      io.tr_dst = G.b;
-      io.tr_sign = 1.0;
-      rc = run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
-      if (rc) return rc;
-    }
+    rc = run_lifting(c, S, f, G.b, nrhs);
+    if (rc) return rc;
     rc = gmres_solve(c, S, G, o, stats, iters, relres, conv, hist);
     if (rc) return rc;
     SolveIO io{};
