@@ -194,6 +194,14 @@ template <typename C>
 hipError_t launch_scatter_apply(const Geom& g, const Entry* ent, int nent, int mask, const FaceTab* ft, const C* T,
                                 const SolveIO& io, hipStream_t st);
 
+// many right-hand sides: gather the incoming data G[j][col][r] of subdomains subs[j], then
+// OUT = T_s[masked rows, :] G_s on MFMA (complex128 operators on f64 MFMA, complex64 on f32)
+hipError_t launch_gather_incoming(const Geom& g, const int32_t* subs, int nsub, const FaceTab* ft, const double2* gin,
+                                  int nrhs, int rpad, double2* G, hipStream_t st);
+template <typename C>
+hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int mask, const FaceTab* ft, const C* T,
+                             const double2* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st);
+
 // gradient / misc
 hipError_t launch_gather_receivers(const double2* u, const int32_t* rec, int nrec, int npts, const double2* d,
                                    double2* resid, int nsrc, hipStream_t st);

@@ -31,19 +31,54 @@ __device__ inline double2 block_sum(double2 v, double2* sh) {
   return s;
 }
 
-// partial[(col * nvec + i) * nchunk + chunk] = sum_{q in chunk} conj(V_i[col][q]) w[col][q]
+// partial[(col * nvec + i) * nchunk + chunk] = sum_{q in chunk} conj(V_i[col][q]) w[col][q].
+// One workgroup per (chunk, group of VG basis vectors, column): the chunk of w is read once per
+// group, the VG dot products accumulate in registers and meet in one block reduction.
+constexpr int MD_PER_THREAD = 4;  // chunk = 1024 elements
+constexpr int VG = 8;
 __global__ __launch_bounds__(RT) void k_multidot(const double2* V, size_t vstride, int nvec, const double2* w,
                                                  int n, double2* partial, int nchunk) {
-  const int chunk = blockIdx.x, i = blockIdx.y, col = blockIdx.z;
+  const int chunk = blockIdx.x, i0 = blockIdx.y * VG, col = blockIdx.z;
   const int len = (n + nchunk - 1) / nchunk;
   const int q0 = chunk * len, q1 = min(n, q0 + len);
-  const double2* v = V + (size_t)i * vstride + (size_t)col * n;
   const double2* ww = w + (size_t)col * n;
-  double2 acc = mk(0.0, 0.0);
-  for (int q = q0 + threadIdx.x; q < q1; q += RT) cfma_conj(acc, v[q], ww[q]);
-  __shared__ double2 sh[RT / 64];
-  const double2 s = block_sum(acc, sh);
-  if (threadIdx.x == 0) partial[((size_t)col * nvec + i) * nchunk + chunk] = s;
+  double2 wl[MD_PER_THREAD];
+#pragma unroll
+  for (int k = 0; k < MD_PER_THREAD; ++k) {
+    const int q = q0 + threadIdx.x + k * RT;
+    wl[k] = (q < q1) ? ww[q] : mk(0.0, 0.0);
+  }
+  double2 acc[VG];
+#pragma unroll
+  for (int v = 0; v < VG; ++v) {
+    acc[v] = mk(0.0, 0.0);
+    if (i0 + v < nvec) {
+      const double2* vp = V + (size_t)(i0 + v) * vstride + (size_t)col * n;
+#pragma unroll
+      for (int k = 0; k < MD_PER_THREAD; ++k) {
+        const int q = q0 + threadIdx.x + k * RT;
+        if (q < q1) cfma_conj(acc[v], vp[q], wl[k]);
+      }
+    }
+  }
+  __shared__ double2 sh[RT / 64][VG];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < VG; ++v) {
+    double2 a = acc[v];
+    for (int off = 32; off > 0; off >>= 1) {
+      const double2 o = shfl_down2(a, off);
+      a.x += o.x;
+      a.y += o.y;
+    }
+    if (lane == 0) sh[wid][v] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < VG && i0 + (int)threadIdx.x < nvec) {
+    double2 t = mk(0.0, 0.0);
+    for (int q = 0; q < RT / 64; ++q) t = cadd(t, sh[q][threadIdx.x]);
+    partial[((size_t)col * nvec + i0 + threadIdx.x) * nchunk + chunk] = t;
+  }
 }
 
 __global__ void k_reduce_partials(const double2* partial, int nvec, int ncol, int nchunk, double2* out,
@@ -137,7 +172,9 @@ inline dim3 grid1(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 hipError_t launch_multidot(const double2* V, size_t vstride, int nvec, const double2* w, int n, int ncol,
                            double2* partial, int nchunk, hipStream_t st) {
-  hipLaunchKernelGGL(k_multidot, dim3(nchunk, nvec, ncol), dim3(RT), 0, st, V, vstride, nvec, w, n, partial, nchunk);
+  if ((size_t)nchunk * RT * MD_PER_THREAD < (size_t)n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_multidot, dim3(nchunk, (nvec + VG - 1) / VG, ncol), dim3(RT), 0, st, V, vstride, nvec, w, n,
+                     partial, nchunk);
   return hipGetLastError();
 }
 

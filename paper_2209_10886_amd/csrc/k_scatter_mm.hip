@@ -1,0 +1,192 @@
+// Dense local scattering operators applied to many right-hand sides at once:
+//   OUT_s (rows x R) = T_s[rows, :] (L x L, masked rows) * G_s (L x R)
+// a complex matrix product per subdomain, on MFMA.  Complex products use four real
+// products per k-step: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.
+//
+// Operand layouts of the 16x16x4 MFMA on gfx950 (lane l, k = l / 16):
+//   A[i][k] at lane i + 16 k, B[k][j] at lane j + 16 k;
+//   f64: D[i][j] in lane j + 16 (i % 4), register i / 4;
+//   f32: D[i][j] in lane j + 16 (i / 4), register i % 4.
+#include "hbj_internal.h"
+
+namespace {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+// G[j][col][r] = incoming datum of subdomain subs[j] at local interface position col, column r
+__global__ void k_gather_incoming(Geom g, const int32_t* subs, const FaceTab* ft, const double2* gin, int nrhs,
+                                  int rpad, double2* G) {
+  const int j = blockIdx.y;
+  const int s = subs[j];
+  const FaceTab F = ft[s];
+  const int L = local_if_len(g);
+  const size_t n = (size_t)L * rpad;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(t / rpad), r = (int)(t % rpad);
+    int f, ee;
+    local_if_face(g, col, &f, &ee);
+    double2 v = mk(0.0, 0.0);
+    if (r < nrhs && F.in_off[f] >= 0) v = gin[(size_t)r * g.nif + F.in_off[f] + ee];
+    G[(size_t)j * n + t] = v;
+  }
+}
+
+__device__ inline int masked_row_mm(const Geom& g, int mask, int r) {
+  for (int f = 0; f < 4; ++f) {
+    if (!((mask >> f) & 1)) continue;
+    const int len = face_len(g, f);
+    if (r < len) return face_off(g, f) + r;
+    r -= len;
+  }
+  return -1;
+}
+
+template <typename M> struct MfmaAcc;
+template <> struct MfmaAcc<double> {
+  typedef d4v T;
+  static __device__ inline T mma(double a, double b, T c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  static __device__ inline int row_of(int lane, int reg) { return (lane >> 4) + 4 * reg; }
+};
+template <> struct MfmaAcc<float> {
+  typedef f4v T;
+  static __device__ inline T mma(float a, float b, T c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int row_of(int lane, int reg) { return 4 * (lane >> 4) + reg; }
+};
+
+constexpr int TB = 4;  // 16-column right-hand-side blocks per wavefront (64 right-hand sides)
+constexpr int KW = 4;  // wavefronts splitting the k range of one tile
+
+// grid: (ceil(masked rows / 16), nsub, ceil(R / 64)).  One 16-row x 64-column output tile per
+// workgroup; wavefront w takes every KW-th group of 4 columns, and the four partial tiles are
+// summed in LDS.  Each wavefront issues the loads of two k-steps before their 16 MFMAs, which go
+// to eight independent accumulators.
+template <typename C, typename M>
+__global__ __launch_bounds__(64 * KW) void k_scatter_mm(Geom g, const int32_t* subs, int mask, const FaceTab* ft,
+                                                        const C* __restrict__ T, const double2* __restrict__ G,
+                                                        int nrhs, int rpad, SolveIO io) {
+  typedef MfmaAcc<M> A;
+  typedef typename A::T V4;
+  const int j = blockIdx.y;
+  const int s = subs[j];
+  const FaceTab F = ft[s];
+  const int L = local_if_len(g);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, k = lane >> 4;
+  const int mrow = masked_row_mm(g, mask, blockIdx.x * 16 + i);  // this lane's A row
+  const int rb0 = blockIdx.z * 16 * TB;
+  const C* Ts = T + (size_t)s * L * L + (mrow < 0 ? 0 : mrow);
+  const double2* Gs = G + (size_t)j * L * rpad + rb0 + i;
+  V4 cr[TB], ci[TB];
+#pragma unroll
+  for (int t = 0; t < TB; ++t) {
+    cr[t] = V4{0, 0, 0, 0};
+    ci[t] = V4{0, 0, 0, 0};
+  }
+  auto load = [&](int col, bool ok, M& ar, M& ai, M (&br)[TB], M (&bi)[TB]) {
+    ar = 0;
+    ai = 0;
+    if (ok && mrow >= 0) {
+      const C tv = Ts[(size_t)col * L];
+      ar = (M)tv.x;
+      ai = (M)tv.y;
+    }
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+      br[t] = 0;
+      bi[t] = 0;
+      if (ok) {
+        const double2 gv = Gs[(size_t)col * rpad + 16 * t];
+        br[t] = (M)gv.x;
+        bi[t] = (M)gv.y;
+      }
+    }
+  };
+  auto mma = [&](M ar, M ai, const M (&br)[TB], const M (&bi)[TB]) {
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+      cr[t] = A::mma(ar, br[t], cr[t]);
+      ci[t] = A::mma(ar, bi[t], ci[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+      cr[t] = A::mma(-ai, bi[t], cr[t]);
+      ci[t] = A::mma(ai, br[t], ci[t]);
+    }
+  };
+  for (int f = 0; f < 4; ++f) {
+    if (F.in_off[f] < 0) continue;
+    const int c0 = face_off(g, f), c1 = c0 + face_len(g, f);
+    // this wavefront's k-steps: c0 + 4 (w + KW q)
+    for (int c = c0 + 4 * w; c < c1; c += 8 * KW) {
+      M ar0, ai0, br0[TB], bi0[TB], ar1, ai1, br1[TB], bi1[TB];
+      const int col0 = c + k, col1 = c + 4 * KW + k;
+      load(col0, col0 < c1, ar0, ai0, br0, bi0);
+      load(col1, col1 < c1, ar1, ai1, br1, bi1);
+      mma(ar0, ai0, br0, bi0);
+      mma(ar1, ai1, br1, bi1);
+    }
+  }
+  // sum the KW partial tiles: wavefront w finishes right-hand-side block t = w
+  __shared__ M red[KW][TB][2][4][64];
+#pragma unroll
+  for (int t = 0; t < TB; ++t)
+#pragma unroll
+    for (int reg = 0; reg < 4; ++reg) {
+      red[w][t][0][reg][lane] = cr[t][reg];
+      red[w][t][1][reg][lane] = ci[t][reg];
+    }
+  __syncthreads();
+  const int t = w;  // KW == TB
+#pragma unroll
+  for (int reg = 0; reg < 4; ++reg) {
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int q = 0; q < KW; ++q) {
+      sr += (double)red[q][t][0][reg][lane];
+      si += (double)red[q][t][1][reg][lane];
+    }
+    const int ii = A::row_of(lane, reg), jj = lane & 15;
+    const int row = masked_row_mm(g, mask, blockIdx.x * 16 + ii);
+    const int rhs = rb0 + 16 * t + jj;
+    if (row < 0 || rhs >= nrhs) continue;
+    int rf, re;
+    local_if_face(g, row, &rf, &re);
+    if (F.out_off[rf] < 0) continue;
+    const size_t o = (size_t)rhs * g.nif + F.out_off[rf] + re;
+    double2 base = io.tr_base ? io.tr_base[o] : mk(0.0, 0.0);
+    base.x += io.tr_sign * sr;
+    base.y += io.tr_sign * si;
+    io.tr_dst[o] = base;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_gather_incoming(const Geom& g, const int32_t* subs, int nsub, const FaceTab* ft, const double2* gin,
+                                  int nrhs, int rpad, double2* G, hipStream_t st) {
+  if (nsub == 0) return hipSuccess;
+  const size_t n = (size_t)local_if_len(g) * rpad;
+  const int bx = (int)std::min<size_t>(64, (n + 255) / 256);
+  hipLaunchKernelGGL(k_gather_incoming, dim3(bx, nsub), dim3(256), 0, st, g, subs, ft, gin, nrhs, rpad, G);
+  return hipGetLastError();
+}
+
+template <typename C>
+hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int mask, const FaceTab* ft, const C* T,
+                             const double2* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st) {
+  if (nsub == 0) return hipSuccess;
+  int rows = 0;
+  for (int f = 0; f < 4; ++f)
+    if ((mask >> f) & 1) rows += face_len(g, f);
+  static_assert(KW == TB, "one right-hand-side block per wavefront in the epilogue");
+  const dim3 grid((rows + 15) / 16, nsub, (nrhs + 16 * TB - 1) / (16 * TB));
+  typedef typename std::conditional<sizeof(C) == 16, double, float>::type M;
+  hipLaunchKernelGGL((k_scatter_mm<C, M>), grid, dim3(64 * KW), 0, st, g, subs, mask, ft, T, G, nrhs, rpad, io);
+  return hipGetLastError();
+}
+
+template hipError_t launch_scatter_mm<double2>(const Geom&, const int32_t*, int, int, const FaceTab*, const double2*,
+                                               const double2*, int, int, const SolveIO&, hipStream_t);
+template hipError_t launch_scatter_mm<float2>(const Geom&, const int32_t*, int, int, const FaceTab*, const float2*,
+                                              const double2*, int, int, const SolveIO&, hipStream_t);

@@ -48,6 +48,8 @@ struct Step {
   size_t first;  // offset into the schedule's device entry array
   int count;
   double dense_elems = 0;  // dense operator entries read by the step (rows x columns)
+  size_t sub_first = 0;    // offset into the schedule's subdomain list (one per subdomain)
+  int sub_count = 0;
 };
 
 // All launches for a given number of right-hand sides.
@@ -57,6 +59,9 @@ struct Schedule {
   size_t all_first = 0;  // every subdomain, all faces
   int all_count = 0;
   double all_dense_elems = 0;
+  int32_t* subs = nullptr;  // device subdomain lists of the steps (many right-hand sides)
+  size_t all_sub_first = 0;
+  int all_sub_count = 0;
   std::vector<Step> fwd, bwd;  // preconditioner passes
 };
 
@@ -112,6 +117,8 @@ struct hbj_ctx {
   double2* x64 = nullptr;
   double2* r64 = nullptr;
   size_t loc64_entries = 0;
+  double2* Gbuf = nullptr;  // gathered incoming data for the many-right-hand-side operators
+  size_t Gbuf_cap = 0;
   int32_t* nzf = nullptr;   // per (rhs, subdomain) nonzero-source flags for the lifting
   size_t nzf_cap = 0;
   double2* pc_y = nullptr;  // preconditioner pass buffers [nrhs][nif]
@@ -136,10 +143,13 @@ void dfree(void* p) {
 }  // namespace
 
 hbj_ctx::~hbj_ctx() {
-  for (auto& kv : sched) dfree(kv.second->dev);
+  for (auto& kv : sched) {
+    dfree(kv.second->dev);
+    dfree(kv.second->subs);
+  }
   for (void* p : {(void*)ft, (void*)coef, (void*)pos_tab, (void*)m, (void*)diag, (void*)ranges_f, (void*)ranges_b,
                   (void*)ab, (void*)ipiv, (void*)info, (void*)mf64, (void*)mb64, (void*)pf, (void*)pflag, (void*)mf32, (void*)mb32, (void*)T64, (void*)T32,
-                  ybuf, (void*)nzf, (void*)rhs64, (void*)x64, (void*)r64, (void*)pc_y, (void*)pc_t})
+                  ybuf, (void*)nzf, (void*)Gbuf, (void*)rhs64, (void*)x64, (void*)r64, (void*)pc_y, (void*)pc_t})
     dfree(p);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
@@ -254,9 +264,13 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
     }
     return rows * cols;
   };
+  std::vector<int32_t> subs;
   for (int s = 0; s < c->ndom; ++s)
     for (int r = 0; r < nrhs; ++r) ent.push_back(Entry{s, r, 0, 0xF});
   S->all_count = (int)ent.size();
+  S->all_sub_first = 0;
+  for (int s = 0; s < c->ndom; ++s) subs.push_back(s);
+  S->all_sub_count = c->ndom;
   for (const Entry& e : ent) S->all_dense_elems += dense_elems(e);
   const int maskF = kMaskFwd, maskB = kMaskBwd;
   if (c->P.precond != HBJ_PC_NONE && c->ndom > 1) {
@@ -264,11 +278,15 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
     for (auto& b : c->fblocks) nsteps = std::max(nsteps, b.second - b.first);
     for (int t = 1; t <= nsteps; ++t) {
       Step st{ent.size(), 0};
+      st.sub_first = subs.size();
       for (auto& b : c->fblocks) {
         if (b.first + t > b.second) continue;
-        for (int s : antidiag_subdomains(c, b.first + t - 1))
+        for (int s : antidiag_subdomains(c, b.first + t - 1)) {
+          subs.push_back(s);
           for (int r = 0; r < nrhs; ++r) ent.push_back(Entry{s, r, t == 1 ? 0 : 1, maskF});
+        }
       }
+      st.sub_count = (int)(subs.size() - st.sub_first);
       st.count = (int)(ent.size() - st.first);
       for (size_t q = st.first; q < ent.size(); ++q) st.dense_elems += dense_elems(ent[q]);
       S->fwd.push_back(st);
@@ -277,11 +295,15 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
     for (auto& b : c->bblocks) nsteps = std::max(nsteps, b.second - b.first);
     for (int t = 1; t <= nsteps; ++t) {
       Step st{ent.size(), 0};
+      st.sub_first = subs.size();
       for (auto& b : c->bblocks) {
         if (b.second - t < b.first) continue;
-        for (int s : antidiag_subdomains(c, b.second - t + 1))
+        for (int s : antidiag_subdomains(c, b.second - t + 1)) {
+          subs.push_back(s);
           for (int r = 0; r < nrhs; ++r) ent.push_back(Entry{s, r, t == 1 ? 0 : 1, maskB});
+        }
       }
+      st.sub_count = (int)(subs.size() - st.sub_first);
       st.count = (int)(ent.size() - st.first);
       for (size_t q = st.first; q < ent.size(); ++q) st.dense_elems += dense_elems(ent[q]);
       S->bwd.push_back(st);
@@ -289,6 +311,8 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
   }
   HIPCHK(dalloc(&S->dev, ent.size()));
   HIPCHK(hipMemcpyAsync(S->dev, ent.data(), ent.size() * sizeof(Entry), hipMemcpyHostToDevice, c->st));
+  HIPCHK(dalloc(&S->subs, subs.size()));
+  HIPCHK(hipMemcpyAsync(S->subs, subs.data(), subs.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
   *out = S.get();
   c->sched[nrhs] = std::move(S);
@@ -392,8 +416,31 @@ int run_solves(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io) {
 }
 
 // batched application of the dense scattering operators (complex128 or complex64 storage)
-int run_dense(hbj_ctx* c, const Entry* ent, int nent, int mask, const SolveIO& io, bool c64, double elems) {
+constexpr int kMatrixRhs = 4;  // from this many right-hand sides on, the operators run as MFMA products
+
+int run_dense(hbj_ctx* c, const Entry* ent, int nent, int mask, const SolveIO& io, bool c64, double elems,
+              const int32_t* subs = nullptr, int nsub = 0, int nrhs = 1, int src = 0) {
   if (nent == 0) return HBJ_OK;
+  if (subs && nrhs >= kMatrixRhs) {
+    const int rpad = (nrhs + 15) / 16 * 16;
+    const size_t need = (size_t)nsub * local_if_len(c->g) * rpad;
+    if (need > c->Gbuf_cap) {
+      dfree(c->Gbuf);
+      c->Gbuf = nullptr;
+      c->Gbuf_cap = 0;
+      if (dalloc(&c->Gbuf, need)) return fail(HBJ_ENOMEM, "operator workspace allocation failed");
+      c->Gbuf_cap = need;
+    }
+    // per subdomain the operator is read once for all right-hand sides
+    const double tbytes = elems / nrhs * (c64 ? 8.0 : 16.0);
+    ProfScope ps(c, HBJ_K_SCATTER, tbytes, elems * 8.0);
+    HIPCHK(launch_gather_incoming(c->g, subs, nsub, c->ft, src ? io.g_b : io.g_a, nrhs, rpad, c->Gbuf, c->st));
+    if (c64)
+      HIPCHK(launch_scatter_mm<float2>(c->g, subs, nsub, mask, c->ft, c->T32, c->Gbuf, nrhs, rpad, io, c->st));
+    else
+      HIPCHK(launch_scatter_mm<double2>(c->g, subs, nsub, mask, c->ft, c->T64, c->Gbuf, nrhs, rpad, io, c->st));
+    return HBJ_OK;
+  }
   ProfScope ps(c, HBJ_K_SCATTER, elems * (c64 ? 8.0 : 16.0), elems * 8.0);
   if (c64) HIPCHK(launch_scatter_apply<float2>(c->g, ent, nent, mask, c->ft, c->T32, io, c->st));
   else HIPCHK(launch_scatter_apply<double2>(c->g, ent, nent, mask, c->ft, c->T64, io, c->st));
@@ -435,14 +482,19 @@ int op_fp64(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
   io.tr_base = g;
   io.tr_sign = -1.0;
   io.tr_reflect = 1;
-  if (c->dense) return run_dense(c, S->dev + S->all_first, S->all_count, 0xF, io, false, S->all_dense_elems);
+  if (c->dense)
+    return run_dense(c, S->dev + S->all_first, S->all_count, 0xF, io, false, S->all_dense_elems,
+                     S->subs + S->all_sub_first, S->all_sub_count, S->nrhs, 0);
   return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
 }
 
 // sweeps over the precomputed steps; in = pass input, out = pass output (pre-filled with in)
 template <typename R>
-int run_pass(hbj_ctx* c, const std::vector<Step>& steps, Entry* dev, const double2* in, double2* out, int mask) {
-  for (const Step& s : steps) {
+int run_pass(hbj_ctx* c, const Schedule* S, const std::vector<Step>& steps, const double2* in, double2* out,
+             int mask) {
+  Entry* dev = S->dev;
+  for (size_t si = 0; si < steps.size(); ++si) {
+    const Step& s = steps[si];
     SolveIO io{};
     io.g_a = in;
     io.g_b = out;
@@ -450,7 +502,8 @@ int run_pass(hbj_ctx* c, const std::vector<Step>& steps, Entry* dev, const doubl
     io.tr_base = out;
     io.tr_sign = 1.0;
     io.tr_reflect = 1;
-    int rc = c->dense ? run_dense(c, dev + s.first, s.count, mask, io, sizeof(R) == 4, s.dense_elems)
+    int rc = c->dense ? run_dense(c, dev + s.first, s.count, mask, io, sizeof(R) == 4, s.dense_elems,
+                                  S->subs + s.sub_first, s.sub_count, S->nrhs, si == 0 ? 0 : 1)
                       : run_solves<R>(c, dev + s.first, s.count, io);
     if (rc) return rc;
   }
@@ -466,7 +519,7 @@ int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs
   if (rc) return rc;
   double2* y = c->pc_y;
   HIPCHK(launch_copy(y, r, n, c->st));
-  rc = run_pass<R>(c, S->fwd, S->dev, r, y, kMaskFwd);
+  rc = run_pass<R>(c, S, S->fwd, r, y, kMaskFwd);
   if (rc) return rc;
   if (c->P.bj_combine == HBJ_BJ_ADDITIVE) HIPCHK(launch_add_ranges(y, r, c->ranges_f, c->nranges_f, c->g.nif, nrhs, c->st));
   if (c->P.bj_compose == HBJ_BJ_RESIDUAL && c->fblocks.size() > 1) {
@@ -476,7 +529,7 @@ int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs
     if (rc) return rc;
     HIPCHK(launch_axpby(t, r, mk(1.0, 0.0), mk(-1.0, 0.0), n, c->st));  // t = r - t
     HIPCHK(launch_copy(z, t, n, c->st));
-    rc = run_pass<R>(c, S->bwd, S->dev, t, z, kMaskBwd);
+    rc = run_pass<R>(c, S, S->bwd, t, z, kMaskBwd);
     if (rc) return rc;
     if (c->P.bj_combine == HBJ_BJ_ADDITIVE)
       HIPCHK(launch_add_ranges(z, t, c->ranges_b, c->nranges_b, c->g.nif, nrhs, c->st));
@@ -484,7 +537,7 @@ int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs
     return HBJ_OK;
   }
   HIPCHK(launch_copy(z, y, n, c->st));
-  rc = run_pass<R>(c, S->bwd, S->dev, y, z, kMaskBwd);
+  rc = run_pass<R>(c, S, S->bwd, y, z, kMaskBwd);
   if (rc) return rc;
   if (c->P.bj_combine == HBJ_BJ_ADDITIVE) HIPCHK(launch_add_ranges(z, y, c->ranges_b, c->nranges_b, c->g.nif, nrhs, c->st));
   return HBJ_OK;
@@ -589,7 +642,8 @@ struct Gmres {
   double2* Zi(int i) { return Z + (size_t)i * vs(); }
 
   int alloc() {
-    nchunk = std::max(1, std::min(256, (nif + 2047) / 2048));
+    // every chunk fits one workgroup's registers in the fused dot kernel (256 threads x 4)
+    nchunk = std::max(1, (nif + 1023) / 1024);
     if (dalloc(&V, (size_t)(m + 1) * vs()) || (flexible && dalloc(&Z, (size_t)m * vs())) || dalloc(&w, vs()) ||
         dalloc(&b, vs()) || dalloc(&x, vs()) || dalloc(&r, vs()) || dalloc(&zt, vs()) ||
         dalloc(&h1, (size_t)ncol * (m + 1)) || dalloc(&h2, (size_t)ncol * (m + 1)) ||

@@ -214,3 +214,34 @@ def test_dense_solve(ctxs, name, kw):
     say(f"  iters {st.iters} relres {st.relres:.2e} err vs direct {e:.2e}")
     assert e < 1e-8
     assert st.relres <= 1e-12
+
+
+# ---------------------------------------------------------------------------
+# many right-hand sides: the dense operators run as MFMA products (>= 4 columns)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name,kw", [("grf256", {}), ("rect", {}), ("ragged", {}), ("grf256", dict(precision=1))])
+def test_dense_operators_many_rhs(ctxs, name, kw):
+    from oracle import sweep
+
+    wl, m, g, dd, ctx = ctxs(name, operator_form=1, **kw)
+    nr = 5
+    gv = W.random_interface_vector(ctx.nif, seed=7, nrhs=nr)
+    say(f"[dense many-rhs] case={name} {kw} nrhs={nr}")
+    w = _to_np(ctx.apply_operator(torch.as_tensor(gv, device="cuda")))
+    z = _to_np(ctx.apply_preconditioner(torch.as_tensor(gv, device="cuda")))
+    tol_pc = 1e-11 if not kw else 1e-5  # complex64 operators inside the mixed preconditioner
+    for k in range(nr):
+        assert rel(w[k], dd.apply_operator(gv[k])) < 1e-12
+        assert rel(z[k], sweep.apply_bj(dd, gv[k])) < tol_pc
+
+
+def test_dense_solve_many_rhs(ctxs):
+    from oracle import solver
+
+    wl, m, g, dd, ctx = ctxs("grf256", operator_form=1)
+    f = np.stack([W.gaussian_source(wl.nx, wl.ny, wl.h, x, 0.3) for x in np.linspace(0.1, 0.9, 6)])
+    say("[dense solve nrhs=6]")
+    u, st = ctx.solve(torch.as_tensor(f, device="cuda"), tol=1e-12, maxit=3000)
+    u = _to_np(u)
+    for k in range(6):
+        assert rel(u[k], solver.direct(g, f[k])) < 1e-8
