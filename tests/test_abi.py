@@ -54,3 +54,17 @@ def test_setup_rejects_bad_sizes_before_touching_the_gpu():
         assert code == hbj.EINVAL
     p = hbj.Problem(16, 16, 0.0, 10.0, 2, 2, 7, 2, 0, 0, 0, 0)  # bad precision
     assert lib.hbj_setup(ctypes.byref(p), ctypes.c_void_p(16), None, ctypes.byref(out)) == hbj.EINVAL
+
+
+def test_setup_rejects_bad_options_on_the_host():
+    import paper_2209_10886_amd as hbj
+
+    lib = hbj._lib
+    out = ctypes.c_void_p()
+    bad = [dict(precond=5), dict(bj_width=-1), dict(bj_combine=2), dict(bj_compose=3), dict(operator_form=2)]
+    for kw in bad:
+        args = dict(precision=0, precond=2, bj_width=0, bj_combine=0, bj_compose=0, operator_form=0)
+        args.update(kw)
+        p = hbj.Problem(16, 16, 0.0, 10.0, 2, 2, args["precision"], args["precond"], args["bj_width"],
+                        args["bj_combine"], args["bj_compose"], args["operator_form"])
+        assert lib.hbj_setup(ctypes.byref(p), ctypes.c_void_p(16), None, ctypes.byref(out)) == hbj.EINVAL
