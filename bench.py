@@ -186,9 +186,12 @@ def main():
         args.no_cpu = args.no_cpu or nsrc > 1
         args.no_mixed = True
     names64 = {hbj.K_FWD: "k_fwd<double,16,4,5>", hbj.K_BWD: "k_bwd<double,16,2,3>",
-               hbj.K_SCATTER: "k_scatter_apply<double2>", hbj.K_KRYLOV: "krylov"}
+               hbj.K_SCATTER: "k_scatter_apply<double2>", hbj.K_SWEEP: "k_sweep_df<double2,16>",
+               hbj.K_KRYLOV: "krylov"}
     names32 = {hbj.K_FWD: "k_fwd (lifting/reconstruction FP64, sweeps complex64)", hbj.K_BWD: "k_bwd (idem)",
-               hbj.K_SCATTER: "k_scatter_apply<float2>", hbj.K_KRYLOV: "krylov"}
+               hbj.K_SCATTER: "k_scatter_apply<float2>",
+               hbj.K_SWEEP: "k_sweep_df<float2,16> (preconditioner) + k_sweep_df<double2,16> (operator)",
+               hbj.K_KRYLOV: "krylov"}
 
     log(f"[bench] {'FP64' if headline_prec == hbj.FP64 else 'mixed'}, dense scattering operators (headline), "
         f"{nsrc} right-hand side(s)")

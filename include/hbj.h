@@ -54,6 +54,8 @@ enum {
   HBJ_ESTATE = -2,         /* call out of order (e.g. solve before factor)     */
   HBJ_EHIP = -3,           /* a HIP runtime call failed                        */
   HBJ_ENOMEM = -4,         /* device allocation failed                         */
+  HBJ_EWAIT = -5,          /* a dataflow sweep's dependency wait exceeded its
+                              poll limit; the outputs of the call are invalid  */
   HBJ_ZERO_PIVOT = 1,      /* exactly singular local matrix (see hbj_factor)   */
   HBJ_NOT_CONVERGED = 2    /* GMRES hit maxit; outputs hold the last iterate   */
 };
@@ -75,6 +77,16 @@ enum { HBJ_OP_BANDED = 0,       /* a banded local solve per application (Sec. 4)
                                    once as a dense L x L matrix (L = 2 sub_nx +
                                    2 sub_ny) at factor time; every application is
                                    then a batched matrix-vector product           */
+/* how the sweep steps of the dense form are launched */
+enum { HBJ_SWEEP_STEPPED = 0,   /* one launch per sweep step (Sec. 5-6 order)     */
+       HBJ_SWEEP_DATAFLOW = 1 };/* one launch per preconditioner application (plus
+                                   the operator inside GMRES): tasks = row blocks
+                                   of (subdomain, right-hand side), each waiting
+                                   only on the tasks that produce its data.  The
+                                   hand-off between tasks costs several device-
+                                   coherent memory round trips per step, more than
+                                   a launch boundary on MI355X, so this form is
+                                   slower; kept as an option and for comparison  */
 /* how the forward and backward block-Jacobi passes compose */
 enum { HBJ_BJ_PRODUCT = 0,      /* z = B_U^{-1} B_L^{-1} r, like SGS              */
        HBJ_BJ_RESIDUAL = 1 };   /* additive-projection half steps (Sec. 6)        */
@@ -90,6 +102,9 @@ typedef struct {
   int32_t bj_combine;    /* HBJ_BJ_RESTRICTED | HBJ_BJ_ADDITIVE                     */
   int32_t bj_compose;    /* HBJ_BJ_PRODUCT | HBJ_BJ_RESIDUAL                        */
   int32_t operator_form; /* HBJ_OP_BANDED | HBJ_OP_DENSE                            */
+  int32_t sweep_exec;    /* HBJ_SWEEP_STEPPED | HBJ_SWEEP_DATAFLOW (dense form, fewer
+                            than 4 right-hand sides; identical results up to the
+                            order of floating-point sums)                         */
 } hbj_problem;
 
 typedef struct {
@@ -121,7 +136,9 @@ typedef struct {         /* per kernel class, accumulated while profiling is on 
 } hbj_kernel_stat;
 
 /* kernel classes for hbj_kernel_stats */
-enum { HBJ_K_FWD = 0, HBJ_K_BWD = 1, HBJ_K_FACTOR = 2, HBJ_K_KRYLOV = 3, HBJ_K_SCATTER = 4, HBJ_K_NCLASS = 5 };
+enum { HBJ_K_FWD = 0, HBJ_K_BWD = 1, HBJ_K_FACTOR = 2, HBJ_K_KRYLOV = 3, HBJ_K_SCATTER = 4,
+       HBJ_K_SWEEP = 5,     /* dataflow sweep launches (HBJ_SWEEP_DATAFLOW)      */
+       HBJ_K_NCLASS = 6 };
 
 /*
  * hbj_setup - describe the problem and build the decomposition (paper Secs. 2-3).
@@ -239,6 +256,17 @@ int32_t hbj_steps_per_preconditioner(const hbj_ctx* ctx);
 int hbj_set_profiling(hbj_ctx* ctx, int32_t on);
 int hbj_kernel_stats(hbj_ctx* ctx, int32_t kclass, hbj_kernel_stat* out);
 int hbj_reset_kernel_stats(hbj_ctx* ctx);
+
+/*
+ * hbj_set_sweep_wait - bounds of the dataflow sweeps' dependency waits, for tests
+ * of the error path.  max_polls: polls of a completion counter before the wait
+ * gives up (<= 0 restores the default, about a second); stall_task: index of a
+ * task whose waits require one completion more than can ever happen (-1 = none),
+ * so that a launch deterministically reports HBJ_EWAIT.  Every wave still exits:
+ * a wait that gives up sets the error flag and the task completes with invalid
+ * data.  The next call that synchronises returns HBJ_EWAIT and clears the flag.
+ */
+int hbj_set_sweep_wait(hbj_ctx* ctx, int32_t max_polls, int32_t stall_task);
 
 const char* hbj_strerror(int code);
 const char* hbj_last_error(void);

@@ -31,15 +31,16 @@ PC_NONE, PC_SGS, PC_BJ = 0, 1, 2
 BJ_RESTRICTED, BJ_ADDITIVE = 0, 1
 BJ_PRODUCT, BJ_RESIDUAL = 0, 1
 OP_BANDED, OP_DENSE = 0, 1
-OK, EINVAL, ESTATE, EHIP, ENOMEM, ZERO_PIVOT, NOT_CONVERGED = 0, -1, -2, -3, -4, 1, 2
-K_FWD, K_BWD, K_FACTOR, K_KRYLOV, K_SCATTER = 0, 1, 2, 3, 4
+SWEEP_STEPPED, SWEEP_DATAFLOW = 0, 1
+OK, EINVAL, ESTATE, EHIP, ENOMEM, EWAIT, ZERO_PIVOT, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, 1, 2
+K_FWD, K_BWD, K_FACTOR, K_KRYLOV, K_SCATTER, K_SWEEP = 0, 1, 2, 3, 4, 5
 
 
 class Problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("h", ctypes.c_double), ("k", ctypes.c_double),
                 ("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("bj_width", ctypes.c_int32), ("bj_combine", ctypes.c_int32),
-                ("bj_compose", ctypes.c_int32), ("operator_form", ctypes.c_int32)]
+                ("bj_compose", ctypes.c_int32), ("operator_form", ctypes.c_int32), ("sweep_exec", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -82,6 +83,7 @@ _SIGS = {
     "hbj_set_profiling": (_I, [_P, _I32]),
     "hbj_kernel_stats": (_I, [_P, _I32, ctypes.POINTER(KernelStat)]),
     "hbj_reset_kernel_stats": (_I, [_P]),
+    "hbj_set_sweep_wait": (_I, [_P, _I32, _I32]),
     "hbj_strerror": (ctypes.c_char_p, [_I]),
     "hbj_last_error": (ctypes.c_char_p, []),
     "hbj_destroy": (None, [_P]),
@@ -273,12 +275,17 @@ class Context:
     def reset_kernel_stats(self):
         _check(_lib.hbj_reset_kernel_stats(self._h))
 
+    def set_sweep_wait(self, max_polls=0, stall_task=-1):
+        """Bounds of the dataflow sweeps' dependency waits (error-path tests)."""
+        _check(_lib.hbj_set_sweep_wait(self._h, max_polls, stall_task))
+
 
 def setup(nx, ny, k, n1, n2, c=None, m=None, h=0.0, precision=FP64, precond=PC_BJ, bj_width=0,
-          bj_combine=BJ_RESTRICTED, bj_compose=BJ_PRODUCT, operator_form=OP_BANDED, device="cuda",
-          stream=None) -> Context:
+          bj_combine=BJ_RESTRICTED, bj_compose=BJ_PRODUCT, operator_form=OP_BANDED, sweep_exec=SWEEP_STEPPED,
+          device="cuda", stream=None) -> Context:
     """hbj_setup with a wave speed c (or squared slowness m) given as a [ny, nx] float64 tensor."""
-    prob = Problem(nx, ny, h, k, n1, n2, precision, precond, bj_width, bj_combine, bj_compose, operator_form)
+    prob = Problem(nx, ny, h, k, n1, n2, precision, precond, bj_width, bj_combine, bj_compose, operator_form,
+                   sweep_exec)
     if c is None and m is None:
         raise ValueError("give c or m")
     if c is None:

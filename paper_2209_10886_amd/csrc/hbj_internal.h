@@ -143,6 +143,50 @@ __host__ __device__ inline int face_node(const Geom& g, int f, int ee) {
   return f == 0 ? ee * g.snx : f == 1 ? ee * g.snx + g.snx - 1 : f == 2 ? ee : (g.sny - 1) * g.snx + ee;
 }
 
+// Dense scattering operators T_s (L x L): blocks of kTR rows, T[s][row / kTR][col][row % kTR],
+// the row count padded to a multiple of kTR (padding rows are zero).  A workgroup that owns a
+// row block streams one contiguous run of kTR * L entries.
+constexpr int kTR = 8;
+__host__ __device__ inline int t_rows(const Geom& g) { return (local_if_len(g) + kTR - 1) / kTR * kTR; }
+__host__ __device__ inline size_t t_per_sub(const Geom& g) { return (size_t)t_rows(g) * local_if_len(g); }
+__host__ __device__ inline size_t t_index(int L, int row, int col) {
+  return ((size_t)(row / kTR) * L + col) * kTR + (row % kTR);
+}
+__host__ __device__ inline int pick4(const int32_t (&a)[4], int f) {
+  return f == 0 ? a[0] : f == 1 ? a[1] : f == 2 ? a[2] : a[3];
+}
+
+// Dataflow sweeps: every sweep step of a preconditioner application (and the operator that
+// follows it) in one launch.  A task is one row block of one (stage, subdomain, right-hand
+// side); workgroups claim tasks in a fixed topological order from a ticket counter and wait
+// only on tasks of smaller tickets, through per-(stage, subdomain, rhs) completion counters.
+constexpr int kDfMaxDeps = 5;
+constexpr int kDfMaxStages = 3;
+struct DfTask {
+  int32_t stage, s, rhs, rb;
+  int32_t first;             // 1: every face is read from the stage input (first step of an interval)
+  int32_t slot;              // completion counter incremented when the task is done
+  int32_t ndep;
+  int32_t dep[kDfMaxDeps];   // counters waited for
+  int32_t need[kDfMaxDeps];  // value each must reach (the number of tasks behind it)
+  int32_t pad;
+};
+// One stage: dst[o] = base[o] + sign (T_s g_s)[row] for the rows of the faces in `mask`,
+// g_s read from `out` on the faces in `out_read` (after the first step) and from `in` elsewhere;
+// with `copy`, dst = in on the subdomain's own incoming positions of the faces in `mask`
+// (positions no task of the stage writes).
+struct DfStage {
+  const double2* in;
+  const double2* out;
+  double2* dst;
+  const double2* base;
+  double sign;
+  int32_t mask, out_read, copy, pad;
+};
+struct DfArgs {
+  DfStage st[kDfMaxStages];
+};
+
 // ---------------------------------------------------------------------------
 // launchers (each returns hipError_t of the launch)
 // ---------------------------------------------------------------------------
@@ -186,13 +230,21 @@ hipError_t launch_add_ranges(double2* y, const double2* x, const int32_t* ranges
                              hipStream_t st);
 
 hipError_t launch_source_flags(const Geom& g, const double2* f, int nrhs, int32_t* nz, hipStream_t st);
-// dense scattering operators T[s][col][row] (column-major, L x L per subdomain); every entry of
-// one launch carries the same face mask
+// dense scattering operators (row-block layout t_index); every entry of one launch carries the
+// same face mask; rblist: distinct row blocks holding rows of the masked faces
 hipError_t launch_build_T(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
                           const double2* ybuf, size_t ystride, double2* T, hipStream_t st);
 template <typename C>
-hipError_t launch_scatter_apply(const Geom& g, const Entry* ent, int nent, int mask, const FaceTab* ft, const C* T,
-                                const SolveIO& io, hipStream_t st);
+hipError_t launch_scatter_apply(const Geom& g, const Entry* ent, int nent, int mask, const int32_t* rblist, int nrb,
+                                const FaceTab* ft, const C* T, const SolveIO& io, hipStream_t st);
+// dataflow sweep launch: ctr = [ticket, counters...] (zero at entry), ctr_next is zeroed for the
+// next launch; err receives 1 if a dependency wait exceeded spin_limit polls; the waits of
+// task stall_task (-1: none) need one completion more than exists (error-path tests)
+template <typename C>
+hipError_t launch_sweep_df(const Geom& g, const DfTask* tasks, int ntasks, const FaceTab* ft, const C* T,
+                           const DfArgs& A, int32_t* ctr, int32_t* ctr_next, int nctr, int32_t* err, int spin_limit,
+                           int stall_task, int grid, hipStream_t st);
+int sweep_df_occupancy(int L, bool c64);
 
 // many right-hand sides: gather the incoming data G[j][col][r] of subdomains subs[j], then
 // OUT = T_s[masked rows, :] G_s on MFMA (complex128 operators on f64 MFMA, complex64 on f32)

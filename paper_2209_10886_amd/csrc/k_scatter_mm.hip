@@ -75,7 +75,7 @@ __global__ __launch_bounds__(64 * KW) void k_scatter_mm(Geom g, const int32_t* s
   const int i = lane & 15, k = lane >> 4;
   const int mrow = masked_row_mm(g, mask, blockIdx.x * 16 + i);  // this lane's A row
   const int rb0 = blockIdx.z * 16 * TB;
-  const C* Ts = T + (size_t)s * L * L + (mrow < 0 ? 0 : mrow);
+  const C* Ts = T + (size_t)s * t_per_sub(g) + t_index(L, mrow < 0 ? 0 : mrow, 0);
   const double2* Gs = G + (size_t)j * L * rpad + rb0 + i;
   V4 cr[TB], ci[TB];
 #pragma unroll
@@ -87,7 +87,7 @@ __global__ __launch_bounds__(64 * KW) void k_scatter_mm(Geom g, const int32_t* s
     ar = 0;
     ai = 0;
     if (ok && mrow >= 0) {
-      const C tv = Ts[(size_t)col * L];
+      const C tv = Ts[(size_t)col * kTR];
       ar = (M)tv.x;
       ai = (M)tv.y;
     }

@@ -63,7 +63,22 @@ struct Schedule {
   size_t all_sub_first = 0;
   int all_sub_count = 0;
   std::vector<Step> fwd, bwd;  // preconditioner passes
+  // dataflow launches (dense form): task lists per kind, double-buffered completion counters
+  struct DfPlan {
+    bool built = false;
+    DfTask* dev = nullptr;
+    int ntasks = 0;
+    double tbytes = 0;  // operator bytes streamed by the launch
+    double flops = 0;
+  };
+  DfPlan df[5];
+  int32_t* df_ctr = nullptr;  // two regions of df_nctr ints: [ticket, counters...]
+  int df_nctr = 0;
+  int df_parity = 0;
 };
+// dataflow plan kinds
+enum { DF_FWD = 0, DF_BWD = 1, DF_PC = 2, DF_PC_OP = 3, DF_OP = 4 };
+constexpr int kDfSpinDefault = 1 << 19;  // polls of about 1 us: well under a second
 
 template <typename T>
 hipError_t dalloc(T** p, size_t n) {
@@ -103,8 +118,14 @@ struct hbj_ctx {
   int32_t* pflag = nullptr;
   float2* mf32 = nullptr;
   float2* mb32 = nullptr;
-  double2* T64 = nullptr;  // dense scattering operators [ndom][L][L] (column-major)
+  double2* T64 = nullptr;  // dense scattering operators [ndom][t_rows][L] (row blocks, t_index)
   float2* T32 = nullptr;
+  int32_t* rbl = nullptr;  // stepped launches: row blocks of the forward, backward and full masks
+  int rbl_off[3] = {0, 0, 0}, rbl_n[3] = {0, 0, 0};
+  int32_t* df_err = nullptr;  // dataflow dependency-wait error flag
+  int df_grid = 0;            // persistent workgroups per dataflow launch
+  int df_spin = kDfSpinDefault;
+  int df_stall = -1;
   bool dense = false;
   bool factored = false;
   int zero_sub = -1, zero_row = -1;
@@ -146,7 +167,11 @@ hbj_ctx::~hbj_ctx() {
   for (auto& kv : sched) {
     dfree(kv.second->dev);
     dfree(kv.second->subs);
+    for (auto& pl : kv.second->df) dfree(pl.dev);
+    dfree(kv.second->df_ctr);
   }
+  dfree(rbl);
+  dfree(df_err);
   for (void* p : {(void*)ft, (void*)coef, (void*)pos_tab, (void*)m, (void*)diag, (void*)ranges_f, (void*)ranges_b,
                   (void*)ab, (void*)ipiv, (void*)info, (void*)mf64, (void*)mb64, (void*)pf, (void*)pflag, (void*)mf32, (void*)mb32, (void*)T64, (void*)T32,
                   ybuf, (void*)nzf, (void*)Gbuf, (void*)rhs64, (void*)x64, (void*)r64, (void*)pc_y, (void*)pc_t})
@@ -441,10 +466,237 @@ int run_dense(hbj_ctx* c, const Entry* ent, int nent, int mask, const SolveIO& i
       HIPCHK(launch_scatter_mm<double2>(c->g, subs, nsub, mask, c->ft, c->T64, c->Gbuf, nrhs, rpad, io, c->st));
     return HBJ_OK;
   }
+  const int li = mask == kMaskFwd ? 0 : mask == kMaskBwd ? 1 : 2;
+  const int32_t* rbl = c->rbl + c->rbl_off[li];
   ProfScope ps(c, HBJ_K_SCATTER, elems * (c64 ? 8.0 : 16.0), elems * 8.0);
-  if (c64) HIPCHK(launch_scatter_apply<float2>(c->g, ent, nent, mask, c->ft, c->T32, io, c->st));
-  else HIPCHK(launch_scatter_apply<double2>(c->g, ent, nent, mask, c->ft, c->T64, io, c->st));
+  if (c64) HIPCHK(launch_scatter_apply<float2>(c->g, ent, nent, mask, rbl, c->rbl_n[li], c->ft, c->T32, io, c->st));
+  else HIPCHK(launch_scatter_apply<double2>(c->g, ent, nent, mask, rbl, c->rbl_n[li], c->ft, c->T64, io, c->st));
   return HBJ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// dataflow sweeps (dense form, few right-hand sides)
+// ---------------------------------------------------------------------------
+// row blocks of subdomain s holding a row of a face in mask that writes an outgoing datum (or,
+// with copy, passes an incoming datum through)
+std::vector<int> df_row_blocks(const hbj_ctx* c, int s, int mask, bool copy) {
+  const int L = local_if_len(c->g);
+  const FaceTab& F = c->ft_host[s];
+  std::vector<int> out;
+  for (int rb = 0; rb * kTR < L; ++rb) {
+    bool use = false;
+    for (int row = rb * kTR; row < std::min(L, rb * kTR + kTR); ++row) {
+      int f, e;
+      local_if_face(c->g, row, &f, &e);
+      if (((mask >> f) & 1) && (F.out_off[f] >= 0 || (copy && F.in_off[f] >= 0))) use = true;
+    }
+    if (use) out.push_back(rb);
+  }
+  return out;
+}
+
+// Task lists in topological order.  Stage 0 = forward pass, 1 = backward pass, 2 = operator.
+// Dependencies (data written by another task of the same launch):
+//  forward, after the first step of an interval: the forward tasks of the W and S neighbours
+//    (they write this subdomain's W and S incoming blocks);
+//  backward, after the first step: the backward tasks of the E and N neighbours; in a launch
+//    that also runs the forward pass, the forward tasks of the subdomain and of its W and S
+//    neighbours (they write or pass through every block the backward task reads);
+//  operator after the backward pass: the backward tasks of the subdomain and of its E and N
+//    neighbours.
+int build_df(hbj_ctx* c, Schedule* S, int kind) {
+  Schedule::DfPlan& P = S->df[kind];
+  if (P.built) return HBJ_OK;
+  const int nd = c->ndom, nrhs = S->nrhs, n1 = c->P.n1, n2 = c->P.n2;
+  const bool has[3] = {kind == DF_FWD || kind == DF_PC || kind == DF_PC_OP,
+                       kind == DF_BWD || kind == DF_PC || kind == DF_PC_OP, kind == DF_PC_OP || kind == DF_OP};
+  const int smask[3] = {kMaskFwd, kMaskBwd, 0xF};
+  const int scopy[3] = {1, 1, 0};
+  // (subdomain, first) per step of each stage, in sweep order
+  std::vector<std::vector<std::pair<int, int>>> order[3];
+  if (has[0] || has[1]) {
+    int nsteps = 0;
+    for (auto& b : c->fblocks) nsteps = std::max(nsteps, b.second - b.first);
+    for (int t = 1; t <= nsteps; ++t) {
+      std::vector<std::pair<int, int>> step;
+      for (auto& b : c->fblocks) {
+        if (b.first + t > b.second) continue;
+        for (int s : antidiag_subdomains(c, b.first + t - 1)) step.push_back({s, t == 1});
+      }
+      order[0].push_back(step);
+    }
+    nsteps = 0;
+    for (auto& b : c->bblocks) nsteps = std::max(nsteps, b.second - b.first);
+    for (int t = 1; t <= nsteps; ++t) {
+      std::vector<std::pair<int, int>> step;
+      for (auto& b : c->bblocks) {
+        if (b.second - t < b.first) continue;
+        for (int s : antidiag_subdomains(c, b.second - t + 1)) step.push_back({s, t == 1});
+      }
+      order[1].push_back(step);
+    }
+  }
+  std::vector<std::pair<int, int>> all;
+  for (int s = 0; s < nd; ++s) all.push_back({s, 1});
+  order[2].push_back(all);
+  std::vector<std::vector<int>> rbs[3];
+  std::vector<int> ntk[3];
+  for (int st = 0; st < 3; ++st) {
+    rbs[st].assign(nd, {});
+    ntk[st].assign(nd, 0);
+    if (!has[st]) continue;
+    for (auto& step : order[st])
+      for (auto& it : step) {
+        rbs[st][it.first] = df_row_blocks(c, it.first, smask[st], scopy[st]);
+        ntk[st][it.first] = (int)rbs[st][it.first].size();
+      }
+  }
+  auto slot = [&](int st, int s, int r) { return (st * nd + s) * nrhs + r; };
+  auto nb = [&](int s, int f) {  // neighbour through face f (W, E, S, N) or -1
+    const int i1 = s % n1, i2 = s / n1;
+    if (f == FACE_W) return i1 > 0 ? s - 1 : -1;
+    if (f == FACE_E) return i1 < n1 - 1 ? s + 1 : -1;
+    if (f == FACE_S) return i2 > 0 ? s - n1 : -1;
+    return i2 < n2 - 1 ? s + n1 : -1;
+  };
+  std::vector<DfTask> tasks;
+  double tbytes = 0, flops = 0;
+  // operator bytes of one task: complex64 in the preconditioner of the mixed form, complex128 else
+  const double row_elems = (double)local_if_len(c->g) * kTR;
+  const double pc_eb = c->P.precision == HBJ_MIXED ? 8.0 : 16.0;
+  for (int st = 0; st < 3; ++st) {
+    if (!has[st]) continue;
+    for (auto& step : order[st])
+      for (auto& it : step) {
+        const int s = it.first, first = it.second;
+        for (int r = 0; r < nrhs; ++r) {
+          std::vector<std::pair<int, int>> deps;
+          auto dep_on = [&](int dst, int q) {
+            if (q >= 0 && ntk[dst][q] > 0) deps.push_back({slot(dst, q, r), ntk[dst][q]});
+          };
+          if (st == 0 && !first) {
+            dep_on(0, nb(s, FACE_W));
+            dep_on(0, nb(s, FACE_S));
+          }
+          if (st == 1) {
+            if (!first) {
+              dep_on(1, nb(s, FACE_E));
+              dep_on(1, nb(s, FACE_N));
+            }
+            if (has[0]) {
+              dep_on(0, s);
+              dep_on(0, nb(s, FACE_W));
+              dep_on(0, nb(s, FACE_S));
+            }
+          }
+          if (st == 2 && has[1]) {
+            dep_on(1, s);
+            dep_on(1, nb(s, FACE_E));
+            dep_on(1, nb(s, FACE_N));
+          }
+          if (deps.size() > (size_t)kDfMaxDeps) return fail(HBJ_EINVAL, "dataflow plan: too many dependencies");
+          for (int rb : rbs[st][s]) {
+            DfTask t{};
+            t.stage = st;
+            t.s = s;
+            t.rhs = r;
+            t.rb = rb;
+            t.first = first;
+            t.slot = slot(st, s, r);
+            t.ndep = (int)deps.size();
+            for (size_t d = 0; d < deps.size(); ++d) {
+              t.dep[d] = deps[d].first;
+              t.need[d] = deps[d].second;
+            }
+            tasks.push_back(t);
+            tbytes += row_elems * (st == 2 ? 16.0 : pc_eb);
+            flops += row_elems * 8.0;
+          }
+        }
+      }
+  }
+  // every wait must be on tasks with smaller tickets, for exactly the number of tasks behind
+  // the counter: checked here so that a plan that could stall is never launched
+  {
+    std::vector<int> last(3 * (size_t)nd * nrhs, -1), count(3 * (size_t)nd * nrhs, 0);
+    for (size_t i = 0; i < tasks.size(); ++i) {
+      last[tasks[i].slot] = (int)i;
+      count[tasks[i].slot] += 1;
+    }
+    for (size_t i = 0; i < tasks.size(); ++i)
+      for (int d = 0; d < tasks[i].ndep; ++d) {
+        const int q = tasks[i].dep[d];
+        if (last[q] < 0 || last[q] >= (int)i || count[q] != tasks[i].need[d])
+          return fail(HBJ_EINVAL, "dataflow plan: a task would wait on a later or miscounted task");
+      }
+  }
+  if (!S->df_ctr) {
+    S->df_nctr = 1 + 3 * nd * nrhs;
+    if (dalloc(&S->df_ctr, 2 * (size_t)S->df_nctr)) return fail(HBJ_ENOMEM, "dataflow counter allocation failed");
+    HIPCHK(launch_fill_zero(S->df_ctr, 2 * (size_t)S->df_nctr * sizeof(int32_t), c->st));
+    S->df_parity = 0;
+  }
+  if (dalloc(&P.dev, tasks.size())) return fail(HBJ_ENOMEM, "dataflow plan allocation failed");
+  HIPCHK(hipMemcpyAsync(P.dev, tasks.data(), tasks.size() * sizeof(DfTask), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  P.ntasks = (int)tasks.size();
+  P.tbytes = tbytes;
+  P.flops = flops;
+  P.built = true;
+  return HBJ_OK;
+}
+
+bool df_enabled(const hbj_ctx* c, const Schedule* S) {
+  return c->dense && c->P.sweep_exec == HBJ_SWEEP_DATAFLOW && S->nrhs < kMatrixRhs;
+}
+
+DfStage df_stage(const double2* in, const double2* out, double2* dst, const double2* base, double sign, int mask,
+                 int copy) {
+  DfStage st{};
+  st.in = in;
+  st.out = out;
+  st.dst = dst;
+  st.base = base;
+  st.sign = sign;
+  st.mask = mask;
+  st.out_read = (~mask) & 0xF;
+  st.copy = copy;
+  return st;
+}
+
+template <typename C>
+int run_df(hbj_ctx* c, Schedule* S, int kind, const DfArgs& A, const C* T) {
+  int rc = build_df(c, S, kind);
+  if (rc) return rc;
+  const Schedule::DfPlan& P = S->df[kind];
+  if (P.ntasks == 0) return HBJ_OK;
+  int32_t* cur = S->df_ctr + (size_t)S->df_parity * S->df_nctr;
+  int32_t* nxt = S->df_ctr + (size_t)(1 - S->df_parity) * S->df_nctr;
+  const int grid = std::min(P.ntasks, c->df_grid);
+  {
+    ProfScope ps(c, HBJ_K_SWEEP, P.tbytes, P.flops);
+    HIPCHK(launch_sweep_df<C>(c->g, P.dev, P.ntasks, c->ft, T, A, cur, nxt, S->df_nctr, c->df_err, c->df_spin,
+                              c->df_stall, grid, c->st));
+  }
+  S->df_parity ^= 1;
+  return HBJ_OK;
+}
+
+// dependency-wait failures of earlier dataflow launches (synchronises the stream)
+int df_check(hbj_ctx* c) {
+  if (!c->df_err) return HBJ_OK;
+  int32_t e = 0;
+  HIPCHK(hipMemcpyAsync(&e, c->df_err, sizeof(e), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  if (!e) return HBJ_OK;
+  HIPCHK(launch_fill_zero(c->df_err, sizeof(int32_t), c->st));
+  for (auto& kv : c->sched) {
+    Schedule* S = kv.second.get();
+    if (S->df_ctr) HIPCHK(launch_fill_zero(S->df_ctr, 2 * (size_t)S->df_nctr * sizeof(int32_t), c->st));
+    S->df_parity = 0;
+  }
+  HIPCHK(hipStreamSynchronize(c->st));
+  return fail(HBJ_EWAIT, "dataflow sweep: a dependency wait exceeded its poll limit");
 }
 
 // lifting b = traces of A^{-1} f: subdomains whose source restriction is identically zero
@@ -482,6 +734,11 @@ int op_fp64(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
   io.tr_base = g;
   io.tr_sign = -1.0;
   io.tr_reflect = 1;
+  if (c->dense && df_enabled(c, S)) {
+    DfArgs A{};
+    A.st[2] = df_stage(g, g, out, g, -1.0, 0xF, 0);
+    return run_df<double2>(c, S, DF_OP, A, c->T64);
+  }
   if (c->dense)
     return run_dense(c, S->dev + S->all_first, S->all_count, 0xF, io, false, S->all_dense_elems,
                      S->subs + S->all_sub_first, S->all_sub_count, S->nrhs, 0);
@@ -518,6 +775,37 @@ int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs
   int rc = ensure_pc(c, nrhs);
   if (rc) return rc;
   double2* y = c->pc_y;
+  if (df_enabled(c, S)) {
+    typedef typename Cplx<R>::T C;
+    const C* T;
+    if constexpr (sizeof(R) == 8) T = c->T64;
+    else T = c->T32;
+    const bool additive = c->P.bj_combine == HBJ_BJ_ADDITIVE;
+    const bool residual = c->P.bj_compose == HBJ_BJ_RESIDUAL && c->fblocks.size() > 1;
+    DfArgs A{};
+    A.st[0] = df_stage(r, y, y, r, 1.0, kMaskFwd, 1);
+    if (!additive && !residual) {
+      A.st[1] = df_stage(y, z, z, y, 1.0, kMaskBwd, 1);
+      return run_df<C>(c, S, DF_PC, A, T);
+    }
+    rc = run_df<C>(c, S, DF_FWD, A, T);
+    if (rc) return rc;
+    if (additive) HIPCHK(launch_add_ranges(y, r, c->ranges_f, c->nranges_f, c->g.nif, nrhs, c->st));
+    const double2* bin = y;
+    if (residual) {
+      double2* t = c->pc_t;
+      rc = op_apply(c, S, y, t);
+      if (rc) return rc;
+      HIPCHK(launch_axpby(t, r, mk(1.0, 0.0), mk(-1.0, 0.0), n, c->st));  // t = r - (I - S) y
+      bin = t;
+    }
+    A.st[1] = df_stage(bin, z, z, bin, 1.0, kMaskBwd, 1);
+    rc = run_df<C>(c, S, DF_BWD, A, T);
+    if (rc) return rc;
+    if (additive) HIPCHK(launch_add_ranges(z, bin, c->ranges_b, c->nranges_b, c->g.nif, nrhs, c->st));
+    if (residual) HIPCHK(launch_axpby(z, y, mk(1.0, 0.0), mk(1.0, 0.0), n, c->st));
+    return HBJ_OK;
+  }
   HIPCHK(launch_copy(y, r, n, c->st));
   rc = run_pass<R>(c, S, S->fwd, r, y, kMaskFwd);
   if (rc) return rc;
@@ -562,6 +850,27 @@ namespace {
 int op_apply(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
   if (c->P.precision == HBJ_MIXED) return op_mixed(c, S, g, out);
   return op_fp64(c, S, g, out);
+}
+
+// z = P^{-1} v, w = (I - S) z: one dataflow launch for the FP64 dense form with the default
+// readings, the two calls otherwise
+int pc_op(hbj_ctx* c, Schedule* S, const double2* v, double2* z, double2* w, int nrhs) {
+  const bool fused = df_enabled(c, S) && c->P.precision == HBJ_FP64 && c->P.precond != HBJ_PC_NONE &&
+                     c->ndom > 1 && c->P.bj_combine == HBJ_BJ_RESTRICTED &&
+                     !(c->P.bj_compose == HBJ_BJ_RESIDUAL && c->fblocks.size() > 1);
+  if (!fused) {
+    int rc = precond(c, S, v, z, nrhs);
+    if (rc) return rc;
+    return op_apply(c, S, z, w);
+  }
+  int rc = ensure_pc(c, nrhs);
+  if (rc) return rc;
+  double2* y = c->pc_y;
+  DfArgs A{};
+  A.st[0] = df_stage(v, y, y, v, 1.0, kMaskFwd, 1);
+  A.st[1] = df_stage(y, z, z, y, 1.0, kMaskBwd, 1);
+  A.st[2] = df_stage(z, z, w, z, -1.0, 0xF, 0);
+  return run_df<double2>(c, S, DF_PC_OP, A, c->T64);
 }
 }  // namespace
 
@@ -717,9 +1026,7 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
     int j = 0;
     for (; j < m && total < o.maxit; ++j) {
       double2* z = G.flexible ? G.Zi(j) : G.zt;
-      rc = precond(c, S, G.Vi(j), z, ncol);
-      if (rc) return rc;
-      rc = op_apply(c, S, z, G.w);
+      rc = pc_op(c, S, G.Vi(j), z, G.w, ncol);
       if (rc) return rc;
       {
         ProfScope ps(c, HBJ_K_KRYLOV, 4.0 * (j + 1) * vs * 16.0 + 2.0 * vs * 16.0, 16.0 * (j + 1) * vs);
@@ -830,6 +1137,7 @@ const char* hbj_strerror(int code) {
     case HBJ_EINVAL: return "invalid argument";
     case HBJ_ESTATE: return "call out of order";
     case HBJ_EHIP: return "HIP runtime error";
+    case HBJ_EWAIT: return "dataflow dependency wait exceeded its limit";
     case HBJ_ENOMEM: return "out of device memory";
     case HBJ_ZERO_PIVOT: return "exactly singular local matrix";
     case HBJ_NOT_CONVERGED: return "GMRES did not converge";
@@ -860,6 +1168,8 @@ int hbj_setup(const hbj_problem* prob, const double* c_dev, void* stream, hbj_ct
     return fail(HBJ_EINVAL, "bad block-Jacobi option");
   if (P.operator_form != HBJ_OP_BANDED && P.operator_form != HBJ_OP_DENSE)
     return fail(HBJ_EINVAL, "bad operator form");
+  if (P.sweep_exec != HBJ_SWEEP_DATAFLOW && P.sweep_exec != HBJ_SWEEP_STEPPED)
+    return fail(HBJ_EINVAL, "bad sweep execution option");
   if (P.operator_form == HBJ_OP_DENSE && 2 * (P.nx / P.n1 + P.ny / P.n2) > 1024)
     return fail(HBJ_EINVAL, "dense operators need 2 (sub_nx + sub_ny) <= 1024");
   if ((size_t)P.nx * P.ny > (size_t)1 << 31) return fail(HBJ_EINVAL, "grid too large");
@@ -932,6 +1242,32 @@ int hbj_setup(const hbj_problem* prob, const double* c_dev, void* stream, hbj_ct
   HIPCHK(launch_c_to_m(c_dev, c->m, (int)npts, c->st));
   int rc = assemble_medium(c.get());
   if (rc) return rc;
+  if (P.operator_form == HBJ_OP_DENSE) {
+    // row blocks of the stepped launches (forward, backward, every face)
+    std::vector<int32_t> rbl;
+    const int masks[3] = {kMaskFwd, kMaskBwd, 0xF};
+    const int Lif = local_if_len(g);
+    for (int i = 0; i < 3; ++i) {
+      c->rbl_off[i] = (int)rbl.size();
+      for (int rb = 0; rb * kTR < Lif; ++rb) {
+        bool use = false;
+        for (int row = rb * kTR; row < std::min(Lif, rb * kTR + kTR); ++row) {
+          int f, e;
+          local_if_face(g, row, &f, &e);
+          use |= ((masks[i] >> f) & 1) != 0;
+        }
+        if (use) rbl.push_back(rb);
+      }
+      c->rbl_n[i] = (int)rbl.size() - c->rbl_off[i];
+    }
+    if (dalloc(&c->rbl, rbl.size()) || dalloc(&c->df_err, 1)) return fail(HBJ_ENOMEM, "setup allocation failed");
+    HIPCHK(hipMemcpyAsync(c->rbl, rbl.data(), rbl.size() * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(launch_fill_zero(c->df_err, sizeof(int32_t), c->st));
+    int dev = 0, ncu = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    c->df_grid = std::max(1, ncu) * sweep_df_occupancy(Lif, P.precision == HBJ_MIXED);
+  }
   HIPCHK(hipEventCreate(&c->ev0));
   HIPCHK(hipEventCreate(&c->ev1));
   HIPCHK(hipStreamSynchronize(c->st));
@@ -957,11 +1293,11 @@ int hbj_set_slowness2(hbj_ctx* c, const double* m_dev) {
 }
 
 // Dense scattering operators: one unit-datum local solve per (subdomain, interface
-// position), in chunks, then T[s][col][row] = -sigma x_row - rho delta_{row,col}.
+// position), in chunks, then T_s[row][col] = -sigma x_row - rho delta_{row,col} (row blocks).
 static int build_dense(hbj_ctx* c) {
   const Geom& g = c->g;
   const int L = local_if_len(g);
-  const size_t per = (size_t)L * L;
+  const size_t per = t_per_sub(g);
   if (!c->T64 && dalloc(&c->T64, per * c->ndom)) return fail(HBJ_ENOMEM, "dense operator allocation failed");
   if (c->P.precision == HBJ_MIXED && !c->T32 && dalloc(&c->T32, per * c->ndom))
     return fail(HBJ_ENOMEM, "dense operator allocation failed");
@@ -1058,7 +1394,9 @@ int hbj_apply_operator(hbj_ctx* c, const hbj_c128* g, hbj_c128* out, int32_t nrh
   Schedule* S;
   rc = build_schedule(c, nrhs, &S);
   if (rc) return rc;
-  return op_apply(c, S, (const double2*)g, (double2*)out);
+  rc = op_apply(c, S, (const double2*)g, (double2*)out);
+  if (rc == HBJ_OK && df_enabled(c, S)) rc = df_check(c);
+  return rc;
 }
 
 int hbj_apply_preconditioner(hbj_ctx* c, const hbj_c128* r, hbj_c128* z, int32_t nrhs) {
@@ -1068,7 +1406,9 @@ int hbj_apply_preconditioner(hbj_ctx* c, const hbj_c128* r, hbj_c128* z, int32_t
   Schedule* S;
   rc = build_schedule(c, nrhs, &S);
   if (rc) return rc;
-  return precond(c, S, (const double2*)r, (double2*)z, nrhs);
+  rc = precond(c, S, (const double2*)r, (double2*)z, nrhs);
+  if (rc == HBJ_OK && df_enabled(c, S)) rc = df_check(c);
+  return rc;
 }
 
 int hbj_lifting(hbj_ctx* c, const hbj_c128* f, hbj_c128* b, int32_t nrhs) {
@@ -1174,7 +1514,12 @@ int hbj_solve(hbj_ctx* c, const hbj_c128* f, hbj_c128* u, int32_t nrhs, const hb
   int rc = check_ready(c);
   if (rc) return rc;
   if (nrhs < 1 || !f || !u || (const void*)f == (const void*)u) return fail(HBJ_EINVAL, "bad arguments");
-  return solve_impl(c, (const double2*)f, (double2*)u, nrhs, opts, stats);
+  rc = solve_impl(c, (const double2*)f, (double2*)u, nrhs, opts, stats);
+  if (rc >= 0) {
+    const int rw = df_check(c);
+    if (rw) return rw;
+  }
+  return rc;
 }
 
 int hbj_gradient(hbj_ctx* c, const hbj_c128* f, int32_t nsrc, const int32_t* rec_idx, int32_t nrec,
@@ -1228,6 +1573,8 @@ int hbj_gradient(hbj_ctx* c, const hbj_c128* f, int32_t nsrc, const int32_t* rec
   if (he == hipSuccess) he = hipStreamSynchronize(c->st);
   cleanup();
   if (he != hipSuccess) return fail(HBJ_EHIP, hipGetErrorString(he));
+  const int rw = df_check(c);
+  if (rw) return rw;
   if (stats) {
     *stats = s1;
     stats->iters = std::max(s1.iters, s2.iters);
@@ -1305,6 +1652,13 @@ int hbj_set_profiling(hbj_ctx* c, int32_t on) {
 int hbj_kernel_stats(hbj_ctx* c, int32_t k, hbj_kernel_stat* out) {
   if (!c || !out || k < 0 || k >= HBJ_K_NCLASS) return fail(HBJ_EINVAL, "bad arguments");
   *out = c->ks[k];
+  return HBJ_OK;
+}
+
+int hbj_set_sweep_wait(hbj_ctx* c, int32_t max_polls, int32_t stall_task) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  c->df_spin = max_polls > 0 ? max_polls : kDfSpinDefault;
+  c->df_stall = stall_task >= 0 ? stall_task : -1;
   return HBJ_OK;
 }
 

@@ -49,10 +49,10 @@ def test_setup_rejects_bad_sizes_before_touching_the_gpu():
     lib = hbj._lib
     out = ctypes.c_void_p()
     for (nx, ny, n1, n2) in [(10, 10, 3, 2), (4, 4, 4, 1), (0, 8, 1, 1)]:
-        p = hbj.Problem(nx, ny, 0.0, 10.0, n1, n2, 0, 2, 0, 0, 0, 0)
+        p = hbj.Problem(nx, ny, 0.0, 10.0, n1, n2, 0, 2, 0, 0, 0, 0, 0)
         code = lib.hbj_setup(ctypes.byref(p), ctypes.c_void_p(16), None, ctypes.byref(out))
         assert code == hbj.EINVAL
-    p = hbj.Problem(16, 16, 0.0, 10.0, 2, 2, 7, 2, 0, 0, 0, 0)  # bad precision
+    p = hbj.Problem(16, 16, 0.0, 10.0, 2, 2, 7, 2, 0, 0, 0, 0, 0)  # bad precision
     assert lib.hbj_setup(ctypes.byref(p), ctypes.c_void_p(16), None, ctypes.byref(out)) == hbj.EINVAL
 
 
@@ -61,10 +61,11 @@ def test_setup_rejects_bad_options_on_the_host():
 
     lib = hbj._lib
     out = ctypes.c_void_p()
-    bad = [dict(precond=5), dict(bj_width=-1), dict(bj_combine=2), dict(bj_compose=3), dict(operator_form=2)]
+    bad = [dict(precond=5), dict(bj_width=-1), dict(bj_combine=2), dict(bj_compose=3), dict(operator_form=2),
+           dict(sweep_exec=2), dict(sweep_exec=-1)]
     for kw in bad:
-        args = dict(precision=0, precond=2, bj_width=0, bj_combine=0, bj_compose=0, operator_form=0)
+        args = dict(precision=0, precond=2, bj_width=0, bj_combine=0, bj_compose=0, operator_form=0, sweep_exec=0)
         args.update(kw)
         p = hbj.Problem(16, 16, 0.0, 10.0, 2, 2, args["precision"], args["precond"], args["bj_width"],
-                        args["bj_combine"], args["bj_compose"], args["operator_form"])
+                        args["bj_combine"], args["bj_compose"], args["operator_form"], args["sweep_exec"])
         assert lib.hbj_setup(ctypes.byref(p), ctypes.c_void_p(16), None, ctypes.byref(out)) == hbj.EINVAL
