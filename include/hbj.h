@@ -138,7 +138,8 @@ typedef struct {         /* per kernel class, accumulated while profiling is on 
 /* kernel classes for hbj_kernel_stats */
 enum { HBJ_K_FWD = 0, HBJ_K_BWD = 1, HBJ_K_FACTOR = 2, HBJ_K_KRYLOV = 3, HBJ_K_SCATTER = 4,
        HBJ_K_SWEEP = 5,     /* dataflow sweep launches (HBJ_SWEEP_DATAFLOW)      */
-       HBJ_K_NCLASS = 6 };
+       HBJ_K_LIFT = 6,      /* dense lifting products (HBJ_OP_DENSE)             */
+       HBJ_K_NCLASS = 7 };
 
 /*
  * hbj_setup - describe the problem and build the decomposition (paper Secs. 2-3).
@@ -189,7 +190,10 @@ int hbj_apply_preconditioner(hbj_ctx* ctx, const hbj_c128* r, hbj_c128* z, int32
 
 /*
  * hbj_lifting - b = outgoing traces of the lifting w_i (Sec. 4, eq. (3)):
- * local solves with the source and zero transmission data.
+ * local solves with the source and zero transmission data.  In the dense form
+ * (HBJ_OP_DENSE, when the n_loc x L lifting operators fit in memory) each
+ * subdomain with a nonzero source is one matrix-vector product with the rows of
+ * A_i^{-1} at its edge nodes, taken from the unit-datum solves of hbj_factor.
  *   f device [nrhs][ny][nx], b device [nrhs][n_if].
  */
 int hbj_lifting(hbj_ctx* ctx, const hbj_c128* f, hbj_c128* b, int32_t nrhs);

@@ -124,6 +124,11 @@ struct SolveIO {
   int unit;               // right-hand side = unit Robin datum at local interface position entry.rhs
   const int32_t* nz;      // [nrhs][ndom] 0 = the entry's source restriction is identically zero and
                           // the entry has no incoming data: its solution is 0 (the solve is skipped)
+  // dense operators only: faces always read from g_a (also for entries with src = 1), and
+  // copy = 1 writes tr_dst = g_a on the entry's own incoming positions of the faces in its
+  // mask (a pass then needs no pre-filled output)
+  int in_faces;
+  int copy;
 };
 
 // Local interface positions of a subdomain: faces W, E, S, N in this order, each with
@@ -219,6 +224,14 @@ hipError_t launch_reduce_partials(const double2* partial, int nvec, int ncol, in
                                   size_t out_stride, double2 scale, hipStream_t st);
 hipError_t launch_update(double2* w, const double2* V, size_t vstride, int nvec, const double2* h,
                          size_t h_stride, double2 alpha, int n, int ncol, hipStream_t st);
+// fused forms: h = sum of the partials (chunk order) inside the update, |w|^2 partials per
+// update workgroup, then the norm and the scaling in one launch
+bool krylov_fusable(int nvec, int nchunk, int n);
+hipError_t launch_update_reduce(double2* w, const double2* V, size_t vstride, int nvec, const double2* partial,
+                                int nchunk, double2* h_out, size_t h_stride, double2 alpha, int n, int ncol,
+                                double* npart, hipStream_t st);
+hipError_t launch_scale_reduce(double2* dst, const double2* src, const double* npart, double* nrm_out, int n, int ncol,
+                               hipStream_t st);
 hipError_t launch_norms(const double2* w, int n, int ncol, double* partial, int nchunk, hipStream_t st);
 hipError_t launch_reduce_norms(const double* partial, int ncol, int nchunk, double* out, hipStream_t st);
 hipError_t launch_scale_by_inv(double2* dst, const double2* src, const double* nrm, int n, int ncol,
@@ -245,6 +258,14 @@ hipError_t launch_sweep_df(const Geom& g, const DfTask* tasks, int ntasks, const
                            const DfArgs& A, int32_t* ctr, int32_t* ctr_next, int nctr, int32_t* err, int spin_limit,
                            int stall_task, int grid, hipStream_t st);
 int sweep_df_occupancy(int L, bool c64);
+
+// dense lifting operators W[s][p][row] = -sigma_row x_row[p] / inj_row from the unit-datum
+// solves of a batch of entries (s, col = row); b = W_s^T f_s for the (s, rhs) with a source
+hipError_t launch_build_W(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
+                          const double2* ybuf, size_t ystride, double2* W, hipStream_t st);
+int lift_chunks(const Geom& g, int pchunk);
+hipError_t launch_lift_dense(const Geom& g, const FaceTab* ft, const double2* W, const double2* f, const int32_t* nz,
+                             int nrhs, int pchunk, double2* part, double2* b, hipStream_t st);
 
 // many right-hand sides: gather the incoming data G[j][col][r] of subdomains subs[j], then
 // OUT = T_s[masked rows, :] G_s on MFMA (complex128 operators on f64 MFMA, complex64 on f32)

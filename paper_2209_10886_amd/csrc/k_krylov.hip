@@ -34,7 +34,6 @@ __device__ inline double2 block_sum(double2 v, double2* sh) {
 // partial[(col * nvec + i) * nchunk + chunk] = sum_{q in chunk} conj(V_i[col][q]) w[col][q].
 // One workgroup per (chunk, group of VG basis vectors, column): the chunk of w is read once per
 // group, the VG dot products accumulate in registers and meet in one block reduction.
-constexpr int MD_PER_THREAD = 4;  // chunk = 1024 elements
 constexpr int VG = 8;
 __global__ __launch_bounds__(RT) void k_multidot(const double2* V, size_t vstride, int nvec, const double2* w,
                                                  int n, double2* partial, int nchunk) {
@@ -42,24 +41,14 @@ __global__ __launch_bounds__(RT) void k_multidot(const double2* V, size_t vstrid
   const int len = (n + nchunk - 1) / nchunk;
   const int q0 = chunk * len, q1 = min(n, q0 + len);
   const double2* ww = w + (size_t)col * n;
-  double2 wl[MD_PER_THREAD];
-#pragma unroll
-  for (int k = 0; k < MD_PER_THREAD; ++k) {
-    const int q = q0 + threadIdx.x + k * RT;
-    wl[k] = (q < q1) ? ww[q] : mk(0.0, 0.0);
-  }
   double2 acc[VG];
 #pragma unroll
-  for (int v = 0; v < VG; ++v) {
-    acc[v] = mk(0.0, 0.0);
-    if (i0 + v < nvec) {
-      const double2* vp = V + (size_t)(i0 + v) * vstride + (size_t)col * n;
+  for (int v = 0; v < VG; ++v) acc[v] = mk(0.0, 0.0);
+  for (int q = q0 + threadIdx.x; q < q1; q += RT) {
+    const double2 wv = ww[q];
 #pragma unroll
-      for (int k = 0; k < MD_PER_THREAD; ++k) {
-        const int q = q0 + threadIdx.x + k * RT;
-        if (q < q1) cfma_conj(acc[v], vp[q], wl[k]);
-      }
-    }
+    for (int v = 0; v < VG; ++v)
+      if (i0 + v < nvec) cfma_conj(acc[v], V[(size_t)(i0 + v) * vstride + (size_t)col * n + q], wv);
   }
   __shared__ double2 sh[RT / 64][VG];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -78,6 +67,74 @@ __global__ __launch_bounds__(RT) void k_multidot(const double2* V, size_t vstrid
     double2 t = mk(0.0, 0.0);
     for (int q = 0; q < RT / 64; ++q) t = cadd(t, sh[q][threadIdx.x]);
     partial[((size_t)col * nvec + i0 + threadIdx.x) * nchunk + chunk] = t;
+  }
+}
+
+// Fused Gram-Schmidt update: every workgroup first adds the dot-product partials of its column
+// in chunk order (the same sums in every workgroup), workgroup 0 publishes h for the host, then
+//   w[col][q] += alpha sum_i V_i[col][q] h_i
+// and, if npart is given, the workgroup's partial sum of |w_new|^2 goes to npart[col][block].
+constexpr int kFuseMax = 2048;  // nvec * nchunk held in LDS (32 KB)
+__global__ __launch_bounds__(RT) void k_update_reduce(double2* w, const double2* V, size_t vstride, int nvec,
+                                                      const double2* partial, int nchunk, double2* h_out,
+                                                      size_t h_stride, double2 alpha, int n, double* npart) {
+  const int col = blockIdx.y;
+  __shared__ double2 sp[kFuseMax];
+  __shared__ double2 hl[kFuseMax / 16];
+  __shared__ double sn[RT / 64];
+  const double2* pc = partial + (size_t)col * nvec * nchunk;
+  for (int t = threadIdx.x; t < nvec * nchunk; t += RT) sp[t] = pc[t];
+  __syncthreads();
+  if (threadIdx.x < nvec) {
+    double2 h = mk(0.0, 0.0);
+    for (int c = 0; c < nchunk; ++c) h = cadd(h, sp[threadIdx.x * nchunk + c]);
+    hl[threadIdx.x] = h;
+    if (blockIdx.x == 0) h_out[(size_t)col * h_stride + threadIdx.x] = h;
+  }
+  __syncthreads();
+  const int q = blockIdx.x * RT + threadIdx.x;
+  double sq = 0.0;
+  if (q < n) {
+    const size_t t = (size_t)col * n + q;
+    double2 acc = mk(0.0, 0.0);
+    for (int i = 0; i < nvec; ++i) cfma(acc, V[(size_t)i * vstride + t], hl[i]);
+    double2 r = w[t];
+    cfma(r, alpha, acc);
+    w[t] = r;
+    sq = r.x * r.x + r.y * r.y;
+  }
+  if (npart) {
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_down(sq, off);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sn[wid] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int k = 0; k < RT / 64; ++k) t += sn[k];
+      npart[(size_t)col * gridDim.x + blockIdx.x] = t;
+    }
+  }
+}
+
+// nrm[col] = sqrt(sum_b npart[col][b]) (fixed pairwise order), dst = src / nrm (0 if nrm = 0);
+// workgroup 0 publishes nrm for the host
+__global__ __launch_bounds__(RT) void k_scale_reduce(double2* dst, const double2* src, const double* npart,
+                                                     int nblk, double* nrm_out, int n) {
+  const int col = blockIdx.y;
+  __shared__ double sp[1024];
+  for (int t = threadIdx.x; t < 1024; t += RT) sp[t] = (t < nblk) ? npart[(size_t)col * nblk + t] : 0.0;
+  __syncthreads();
+  for (int half = 512; half > 0; half >>= 1) {
+    for (int t = threadIdx.x; t < half; t += RT) sp[t] += sp[t + half];
+    __syncthreads();
+  }
+  const double a = sqrt(sp[0]);
+  if (blockIdx.x == 0 && threadIdx.x == 0) nrm_out[col] = a;
+  const int q = blockIdx.x * RT + threadIdx.x;
+  if (q < n) {
+    const size_t t = (size_t)col * n + q;
+    const double2 v = src[t];
+    dst[t] = (a > 0.0) ? mk(v.x / a, v.y / a) : mk(0.0, 0.0);
   }
 }
 
@@ -172,9 +229,30 @@ inline dim3 grid1(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 hipError_t launch_multidot(const double2* V, size_t vstride, int nvec, const double2* w, int n, int ncol,
                            double2* partial, int nchunk, hipStream_t st) {
-  if ((size_t)nchunk * RT * MD_PER_THREAD < (size_t)n) return hipErrorInvalidValue;
+  if (nchunk < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_multidot, dim3(nchunk, (nvec + VG - 1) / VG, ncol), dim3(RT), 0, st, V, vstride, nvec, w, n,
                      partial, nchunk);
+  return hipGetLastError();
+}
+
+bool krylov_fusable(int nvec, int nchunk, int n) {
+  return nvec * nchunk <= kFuseMax && nvec <= kFuseMax / 16 && (n + RT - 1) / RT <= 1024;
+}
+
+hipError_t launch_update_reduce(double2* w, const double2* V, size_t vstride, int nvec, const double2* partial,
+                                int nchunk, double2* h_out, size_t h_stride, double2 alpha, int n, int ncol,
+                                double* npart, hipStream_t st) {
+  if (!krylov_fusable(nvec, nchunk, n)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_update_reduce, dim3((n + RT - 1) / RT, ncol), dim3(RT), 0, st, w, V, vstride, nvec, partial,
+                     nchunk, h_out, h_stride, alpha, n, npart);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_reduce(double2* dst, const double2* src, const double* npart, double* nrm_out, int n, int ncol,
+                               hipStream_t st) {
+  const int nblk = (n + RT - 1) / RT;
+  if (nblk > 1024) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scale_reduce, dim3(nblk, ncol), dim3(RT), 0, st, dst, src, npart, nblk, nrm_out, n);
   return hipGetLastError();
 }
 

@@ -1,0 +1,173 @@
+// Dense lifting operators (paper Sec. 4, eq. (3)): the outgoing data b of the lifting
+// w_s = A_s^{-1} f_s with zero transmission data, as one matrix-vector product per subdomain
+// with a source, instead of a sequential banded solve on one compute unit.
+//
+// A_s is complex symmetric (A = A^T), so the row of A_s^{-1} at edge node n(row) equals the
+// column A_s^{-1} e_{n(row)} = x_row / inj_row, where x_row = A_s^{-1} B e_row is the unit-datum
+// solve already computed for the dense scattering operators.  The outgoing datum of row is
+// -sigma_row w_s[n(row)], hence
+//   b_row = sum_p W_s[p][row] f_s[p],   W_s[p][row] = -sigma_row x_row[p] / inj_row.
+// Layout [s][p][row] (L rows contiguous per node p): a workgroup owns a chunk of nodes and
+// accumulates full L-vectors with coalesced loads and no cross-thread reduction; a second pass
+// adds the chunk partials in chunk order (deterministic).
+#include "hbj_internal.h"
+
+namespace {
+
+constexpr int TE = 32;  // entries (interface positions) per transpose tile
+constexpr int TP = 32;  // nodes per transpose tile
+
+// W[s][p][col] = -sigma_col / inj_col * x_e[p] for the entries e = (s, col) of a batch.
+// Tile of 32 entries x 32 nodes through LDS: coalesced reads along p, writes along col.
+__global__ __launch_bounds__(256) void k_build_W(Geom g, const Entry* ent, int nent, const FaceTab* ft,
+                                                 const IfCoef* coef, const double2* ybuf, size_t ystride,
+                                                 double2* W) {
+  __shared__ double2 tile[TE][TP + 1];
+  __shared__ double2 scale[TE];
+  __shared__ int ss[TE], cc[TE];
+  const int e0 = blockIdx.x * TE, p0 = blockIdx.y * TP;
+  const int L = local_if_len(g);
+  if (threadIdx.x < TE) {
+    const int e = e0 + threadIdx.x;
+    int s = -1, col = 0;
+    double2 sc = mk(0.0, 0.0);
+    if (e < nent) {
+      const Entry en = ent[e];
+      s = en.s;
+      col = en.rhs;
+      int f, ee;
+      local_if_face(g, col, &f, &ee);
+      const int io = pick4(ft[s].in_off, f);
+      if (io >= 0) {
+        const IfCoef c = coef[io + ee];
+        sc = cdiv(c.sigma, c.inj);
+        sc = mk(-sc.x, -sc.y);
+      }
+    }
+    ss[threadIdx.x] = s;
+    cc[threadIdx.x] = col;
+    scale[threadIdx.x] = sc;
+  }
+  // load: threads along p
+  for (int t = threadIdx.x; t < TE * TP; t += blockDim.x) {
+    const int j = t / TP, q = t % TP;
+    const int e = e0 + j, p = p0 + q;
+    tile[j][q] = (e < nent && p < g.nloc) ? ybuf[(size_t)e * ystride + p] : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  // store: threads along the entries (consecutive interface positions of one subdomain)
+  for (int t = threadIdx.x; t < TE * TP; t += blockDim.x) {
+    const int q = t / TE, j = t % TE;
+    const int p = p0 + q, s = ss[j];
+    if (s < 0 || p >= g.nloc) continue;
+    W[((size_t)s * g.nloc + p) * L + cc[j]] = cmul(scale[j], tile[j][q]);
+  }
+}
+
+constexpr int RT = 256;
+
+// part[(r * ndom + s) * nchunk + chunk][row] = sum_{p in chunk} W[s][p][row] f_s[p]
+// for the (subdomain, rhs) pairs with a nonzero source; a chunk whose source values are all
+// exactly zero contributes exactly zero without reading W.
+template <int RPT>
+__global__ __launch_bounds__(RT) void k_lift_partial(Geom g, const double2* __restrict__ W, const double2* f,
+                                                     const int32_t* nz, int pchunk, int nchunk, double2* part) {
+  const int chunk = blockIdx.x, s = blockIdx.y, r = blockIdx.z;
+  const int ndom = g.n1 * g.n2;
+  if (!nz[(size_t)r * ndom + s]) return;
+  const int L = local_if_len(g);
+  __shared__ double2 fl[1024];
+  const int pa = chunk * pchunk, pb = min(g.nloc, pa + pchunk);
+  const int x0 = (s % g.n1) * g.snx, y0 = (s / g.n1) * g.sny;
+  const double2* fr = f + (size_t)r * g.nx * g.ny;
+  int any = 0;
+  for (int p = pa + threadIdx.x; p < pb; p += RT) {
+    const int ly = p / g.snx, lx = p - ly * g.snx;
+    const double2 v = fr[(size_t)(y0 + ly) * g.nx + x0 + lx];
+    fl[p - pa] = v;
+    any |= (v.x != 0.0 || v.y != 0.0);
+  }
+  any = __syncthreads_or(any);
+  double2* out = part + ((size_t)(r * ndom + s) * nchunk + chunk) * L;
+  double2 acc[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) acc[k] = mk(0.0, 0.0);
+  if (any) {
+    const double2* Ws = W + (size_t)s * g.nloc * L;
+#pragma unroll 4
+    for (int p = pa; p < pb; ++p) {
+      const double2 fv = fl[p - pa];
+      const double2* wp = Ws + (size_t)p * L;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int row = threadIdx.x + k * RT;
+        if (row < L) cfma(acc[k], wp[row], fv);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int row = threadIdx.x + k * RT;
+    if (row < L) out[row] = acc[k];
+  }
+}
+
+// b[r][out position of row] = sum of the chunk partials; zero for subdomains without a source.
+// Workgroup = 32 rows x 8 chunk groups: group k adds chunks k, k + 8, ... in order, then the 8
+// group sums are added in group order (a fixed order: the result is deterministic).
+__global__ __launch_bounds__(RT) void k_lift_reduce(Geom g, const FaceTab* ft, const int32_t* nz,
+                                                    const double2* part, int nchunk, double2* b) {
+  const int s = blockIdx.y, r = blockIdx.z;
+  const int ndom = g.n1 * g.n2;
+  const int L = local_if_len(g);
+  const int lr = threadIdx.x % 32, k = threadIdx.x / 32;
+  const int row = blockIdx.x * 32 + lr;
+  const bool has = nz[(size_t)r * ndom + s] != 0;
+  __shared__ double2 red[8][33];
+  double2 acc = mk(0.0, 0.0);
+  if (has && row < L) {
+    const double2* ps = part + (size_t)(r * ndom + s) * nchunk * L + row;
+    for (int c = k; c < nchunk; c += 8) acc = cadd(acc, ps[(size_t)c * L]);
+  }
+  red[k][lr] = acc;
+  __syncthreads();
+  if (k == 0 && row < L) {
+    int f, e;
+    local_if_face(g, row, &f, &e);
+    const int oo = pick4(ft[s].out_off, f);
+    if (oo >= 0) {
+      double2 t = red[0][lr];
+      for (int q = 1; q < 8; ++q) t = cadd(t, red[q][lr]);
+      b[(size_t)r * g.nif + oo + e] = t;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_build_W(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
+                          const double2* ybuf, size_t ystride, double2* W, hipStream_t st) {
+  if (nent == 0) return hipSuccess;
+  const dim3 grid((nent + TE - 1) / TE, (g.nloc + TP - 1) / TP);
+  hipLaunchKernelGGL(k_build_W, grid, dim3(256), 0, st, g, ent, nent, ft, coef, ybuf, ystride, W);
+  return hipGetLastError();
+}
+
+int lift_chunks(const Geom& g, int pchunk) { return (g.nloc + pchunk - 1) / pchunk; }
+
+hipError_t launch_lift_dense(const Geom& g, const FaceTab* ft, const double2* W, const double2* f, const int32_t* nz,
+                             int nrhs, int pchunk, double2* part, double2* b, hipStream_t st) {
+  const int L = local_if_len(g);
+  if (pchunk > 1024 || L > 1024) return hipErrorInvalidValue;
+  const int nchunk = lift_chunks(g, pchunk);
+  const dim3 grid(nchunk, g.n1 * g.n2, nrhs);
+  if (L <= RT) hipLaunchKernelGGL((k_lift_partial<1>), grid, dim3(RT), 0, st, g, W, f, nz, pchunk, nchunk, part);
+  else if (L <= 2 * RT)
+    hipLaunchKernelGGL((k_lift_partial<2>), grid, dim3(RT), 0, st, g, W, f, nz, pchunk, nchunk, part);
+  else hipLaunchKernelGGL((k_lift_partial<4>), grid, dim3(RT), 0, st, g, W, f, nz, pchunk, nchunk, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_lift_reduce, dim3((L + 31) / 32, g.n1 * g.n2, nrhs), dim3(RT), 0, st, g, ft, nz, part, nchunk,
+                     b);
+  return hipGetLastError();
+}

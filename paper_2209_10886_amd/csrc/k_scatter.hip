@@ -65,12 +65,13 @@ __global__ __launch_bounds__(kTR * CG) void k_scatter_apply(Geom g, const Entry*
   }
   __shared__ double2 gl[LMAX];
   __shared__ double2 red[kTR * CG / 64][kTR];
-  const double2* gin = (e.src ? io.g_b : io.g_a) + (size_t)e.rhs * g.nif;
+  const size_t cb = (size_t)e.rhs * g.nif;
+  const int from_b = e.src ? (~io.in_faces & 0xF) : 0;
   for (int q = threadIdx.x; q < L; q += blockDim.x) {  // absent faces read as zero data
     int f, ee;
     local_if_face(g, q, &f, &ee);
     const int o = pick4(F.in_off, f);
-    gl[q] = (o >= 0) ? gin[o + ee] : mk(0.0, 0.0);
+    gl[q] = (o >= 0) ? (((from_b >> f) & 1) ? io.g_b : io.g_a)[cb + o + ee] : mk(0.0, 0.0);
   }
   __syncthreads();
   double2 acc = mk(0.0, 0.0);
@@ -95,12 +96,14 @@ __global__ __launch_bounds__(kTR * CG) void k_scatter_apply(Geom g, const Entry*
       double2 sum = red[0][r];
 #pragma unroll
       for (int w = 1; w < kTR * CG / 64; ++w) sum = cadd(sum, red[w][r]);
-      const size_t o = (size_t)e.rhs * g.nif + oo + re;
+      const size_t o = cb + oo + re;
       double2 base = io.tr_base ? io.tr_base[o] : mk(0.0, 0.0);
       base.x += io.tr_sign * sum.x;
       base.y += io.tr_sign * sum.y;
       io.tr_dst[o] = base;
     }
+    const int io_ = pick4(F.in_off, rf);
+    if (io.copy && ((e.mask >> rf) & 1) && io_ >= 0) io.tr_dst[cb + io_ + re] = io.g_a[cb + io_ + re];
   }
 }
 

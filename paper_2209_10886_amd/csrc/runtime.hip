@@ -76,6 +76,8 @@ struct Schedule {
   int df_nctr = 0;
   int df_parity = 0;
 };
+constexpr int kLiftChunk = 128;                         // nodes per lifting workgroup
+constexpr size_t kLiftPartialElems = (size_t)16 << 20;  // lifting partials per batch (256 MB)
 // dataflow plan kinds
 enum { DF_FWD = 0, DF_BWD = 1, DF_PC = 2, DF_PC_OP = 3, DF_OP = 4 };
 constexpr int kDfSpinDefault = 1 << 19;  // polls of about 1 us: well under a second
@@ -118,6 +120,9 @@ struct hbj_ctx {
   int32_t* pflag = nullptr;
   float2* mf32 = nullptr;
   float2* mb32 = nullptr;
+  double2* Wl = nullptr;    // dense lifting operators [ndom][n_loc][L] (null: banded lifting)
+  double2* lpart = nullptr; // lifting partial sums
+  size_t lpart_cap = 0;
   double2* T64 = nullptr;  // dense scattering operators [ndom][t_rows][L] (row blocks, t_index)
   float2* T32 = nullptr;
   int32_t* rbl = nullptr;  // stepped launches: row blocks of the forward, backward and full masks
@@ -173,7 +178,7 @@ hbj_ctx::~hbj_ctx() {
   dfree(rbl);
   dfree(df_err);
   for (void* p : {(void*)ft, (void*)coef, (void*)pos_tab, (void*)m, (void*)diag, (void*)ranges_f, (void*)ranges_b,
-                  (void*)ab, (void*)ipiv, (void*)info, (void*)mf64, (void*)mb64, (void*)pf, (void*)pflag, (void*)mf32, (void*)mb32, (void*)T64, (void*)T32,
+                  (void*)ab, (void*)ipiv, (void*)info, (void*)mf64, (void*)mb64, (void*)pf, (void*)pflag, (void*)mf32, (void*)mb32, (void*)T64, (void*)T32, (void*)Wl, (void*)lpart,
                   ybuf, (void*)nzf, (void*)Gbuf, (void*)rhs64, (void*)x64, (void*)r64, (void*)pc_y, (void*)pc_t})
     dfree(p);
   if (ev0) (void)hipEventDestroy(ev0);
@@ -711,6 +716,32 @@ int run_lifting(hbj_ctx* c, Schedule* S, const double2* f, double2* b, int nrhs)
     c->nzf_cap = need;
   }
   HIPCHK(launch_source_flags(c->g, f, nrhs, c->nzf, c->st));
+  if (c->Wl) {
+    // dense lifting operators: one matrix-vector product per (subdomain, rhs) with a source
+    std::vector<int32_t> nzh(need);
+    HIPCHK(hipMemcpyAsync(nzh.data(), c->nzf, need * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    const int L = local_if_len(c->g);
+    const int nchunk = lift_chunks(c->g, kLiftChunk);
+    const size_t per_rhs = (size_t)c->ndom * nchunk * L;
+    const int batch = (int)std::max<size_t>(1, std::min<size_t>(nrhs, kLiftPartialElems / per_rhs));
+    if ((size_t)batch * per_rhs > c->lpart_cap) {
+      dfree(c->lpart);
+      c->lpart = nullptr;
+      c->lpart_cap = 0;
+      if (dalloc(&c->lpart, (size_t)batch * per_rhs)) return fail(HBJ_ENOMEM, "lifting workspace allocation failed");
+      c->lpart_cap = (size_t)batch * per_rhs;
+    }
+    for (int r0 = 0; r0 < nrhs; r0 += batch) {
+      const int nb = std::min(batch, nrhs - r0);
+      double pairs = 0;
+      for (size_t q = (size_t)r0 * c->ndom; q < (size_t)(r0 + nb) * c->ndom; ++q) pairs += nzh[q] != 0;
+      ProfScope ps(c, HBJ_K_LIFT, pairs * (double)c->g.nloc * L * 16.0, pairs * 8.0 * c->g.nloc * L);
+      HIPCHK(launch_lift_dense(c->g, c->ft, c->Wl, f + (size_t)r0 * c->g.nx * c->g.ny, c->nzf + (size_t)r0 * c->ndom,
+                               nb, kLiftChunk, c->lpart, b + (size_t)r0 * c->g.nif, c->st));
+    }
+    return HBJ_OK;
+  }
   SolveIO io{};
   io.f = f;
   io.nz = c->nzf;
@@ -746,17 +777,24 @@ int op_fp64(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
 }
 
 // sweeps over the precomputed steps; in = pass input, out = pass output (pre-filled with in)
+// A pass whose output needs no pre-filling: dense operators on few right-hand sides write
+// out = in + contribution and pass the other incoming positions through (copy mode).
+bool pass_copies(const hbj_ctx* c, const Schedule* S) { return c->dense && S->nrhs < kMatrixRhs; }
+
 template <typename R>
 int run_pass(hbj_ctx* c, const Schedule* S, const std::vector<Step>& steps, const double2* in, double2* out,
              int mask) {
   Entry* dev = S->dev;
+  const bool cp = pass_copies(c, S);
   for (size_t si = 0; si < steps.size(); ++si) {
     const Step& s = steps[si];
     SolveIO io{};
     io.g_a = in;
     io.g_b = out;
     io.tr_dst = out;
-    io.tr_base = out;
+    io.tr_base = cp ? in : out;
+    io.in_faces = cp ? mask : 0;
+    io.copy = cp ? 1 : 0;
     io.tr_sign = 1.0;
     io.tr_reflect = 1;
     int rc = c->dense ? run_dense(c, dev + s.first, s.count, mask, io, sizeof(R) == 4, s.dense_elems,
@@ -806,7 +844,8 @@ int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs
     if (residual) HIPCHK(launch_axpby(z, y, mk(1.0, 0.0), mk(1.0, 0.0), n, c->st));
     return HBJ_OK;
   }
-  HIPCHK(launch_copy(y, r, n, c->st));
+  const bool cp = pass_copies(c, S);
+  if (!cp) HIPCHK(launch_copy(y, r, n, c->st));
   rc = run_pass<R>(c, S, S->fwd, r, y, kMaskFwd);
   if (rc) return rc;
   if (c->P.bj_combine == HBJ_BJ_ADDITIVE) HIPCHK(launch_add_ranges(y, r, c->ranges_f, c->nranges_f, c->g.nif, nrhs, c->st));
@@ -816,7 +855,7 @@ int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs
     rc = op_apply(c, S, y, t);
     if (rc) return rc;
     HIPCHK(launch_axpby(t, r, mk(1.0, 0.0), mk(-1.0, 0.0), n, c->st));  // t = r - t
-    HIPCHK(launch_copy(z, t, n, c->st));
+    if (!cp) HIPCHK(launch_copy(z, t, n, c->st));
     rc = run_pass<R>(c, S, S->bwd, t, z, kMaskBwd);
     if (rc) return rc;
     if (c->P.bj_combine == HBJ_BJ_ADDITIVE)
@@ -824,7 +863,7 @@ int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs
     HIPCHK(launch_axpby(z, y, mk(1.0, 0.0), mk(1.0, 0.0), n, c->st));
     return HBJ_OK;
   }
-  HIPCHK(launch_copy(z, y, n, c->st));
+  if (!cp) HIPCHK(launch_copy(z, y, n, c->st));
   rc = run_pass<R>(c, S, S->bwd, y, z, kMaskBwd);
   if (rc) return rc;
   if (c->P.bj_combine == HBJ_BJ_ADDITIVE) HIPCHK(launch_add_ranges(z, y, c->ranges_b, c->nranges_b, c->g.nif, nrhs, c->st));
@@ -938,12 +977,13 @@ struct Gmres {
   bool flexible;
   // device
   double2 *V = nullptr, *Z = nullptr, *w = nullptr, *b = nullptr, *x = nullptr, *r = nullptr, *zt = nullptr;
-  double2 *h1 = nullptr, *h2 = nullptr, *ydev = nullptr, *partial = nullptr;
+  double2 *hbuf = nullptr, *h1 = nullptr, *h2 = nullptr, *ydev = nullptr, *partial = nullptr;
   double *nrm = nullptr, *npartial = nullptr;
+  size_t hbuf_len = 0;
   int nchunk = 0;
   ~Gmres() {
-    for (void* p : {(void*)V, (void*)Z, (void*)w, (void*)b, (void*)x, (void*)r, (void*)zt, (void*)h1, (void*)h2,
-                    (void*)ydev, (void*)partial, (void*)nrm, (void*)npartial})
+    for (void* p : {(void*)V, (void*)Z, (void*)w, (void*)b, (void*)x, (void*)r, (void*)zt, (void*)hbuf,
+                    (void*)ydev, (void*)partial, (void*)npartial})
       dfree(p);
   }
   size_t vs() const { return (size_t)ncol * nif; }
@@ -952,13 +992,19 @@ struct Gmres {
 
   int alloc() {
     // every chunk fits one workgroup's registers in the fused dot kernel (256 threads x 4)
-    nchunk = std::max(1, (nif + 1023) / 1024);
+    // chunks of about 1024 entries, few enough that the fused update holds all partials
+    nchunk = std::max(1, std::min((nif + 1023) / 1024, 2048 / (m + 1)));
+    hbuf_len = 2 * (size_t)ncol * (m + 1) + (ncol + 1) / 2;
+    const size_t nblk = ((size_t)nif + 255) / 256;
     if (dalloc(&V, (size_t)(m + 1) * vs()) || (flexible && dalloc(&Z, (size_t)m * vs())) || dalloc(&w, vs()) ||
-        dalloc(&b, vs()) || dalloc(&x, vs()) || dalloc(&r, vs()) || dalloc(&zt, vs()) ||
-        dalloc(&h1, (size_t)ncol * (m + 1)) || dalloc(&h2, (size_t)ncol * (m + 1)) ||
+        dalloc(&b, vs()) || dalloc(&x, vs()) || dalloc(&r, vs()) || dalloc(&zt, vs()) || dalloc(&hbuf, hbuf_len) ||
         dalloc(&ydev, (size_t)ncol * (m + 1)) || dalloc(&partial, (size_t)ncol * (m + 1) * nchunk) ||
-        dalloc(&nrm, (size_t)ncol) || dalloc(&npartial, (size_t)ncol * nchunk))
+        dalloc(&npartial, (size_t)ncol * std::max<size_t>(nchunk, nblk)))
       return fail(HBJ_ENOMEM, "GMRES workspace allocation failed");
+    // h1 | h2 | norms in one buffer: one copy to the host per iteration
+    h1 = hbuf;
+    h2 = hbuf + (size_t)ncol * (m + 1);
+    nrm = (double*)(hbuf + 2 * (size_t)ncol * (m + 1));
     return HBJ_OK;
   }
 
@@ -1002,7 +1048,7 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
   int total = 0;
   std::vector<zc> H((size_t)ncol * (m + 1) * m), e1((size_t)ncol * (m + 1)), sn((size_t)ncol * m);
   std::vector<double> cs((size_t)ncol * m);
-  std::vector<double2> hh1((size_t)ncol * (m + 1)), hh2((size_t)ncol * (m + 1));
+  std::vector<double2> hh1((size_t)ncol * (m + 1)), hh2((size_t)ncol * (m + 1)), hbuf_host(G.hbuf_len);
   std::vector<double> hn(ncol);
   std::vector<int> jc(ncol);
   std::vector<double2> yh((size_t)ncol * (m + 1));
@@ -1031,20 +1077,32 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
       {
         ProfScope ps(c, HBJ_K_KRYLOV, 4.0 * (j + 1) * vs * 16.0 + 2.0 * vs * 16.0, 16.0 * (j + 1) * vs);
         // classical Gram-Schmidt with one reorthogonalisation
-        HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
-        HIPCHK(launch_reduce_partials(G.partial, j + 1, ncol, G.nchunk, G.h1, m + 1, mk(1.0, 0.0), c->st));
-        HIPCHK(launch_update(G.w, G.V, vs, j + 1, G.h1, m + 1, mk(-1.0, 0.0), nif, ncol, c->st));
-        HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
-        HIPCHK(launch_reduce_partials(G.partial, j + 1, ncol, G.nchunk, G.h2, m + 1, mk(1.0, 0.0), c->st));
-        HIPCHK(launch_update(G.w, G.V, vs, j + 1, G.h2, m + 1, mk(-1.0, 0.0), nif, ncol, c->st));
-        HIPCHK(launch_norms(G.w, nif, ncol, G.npartial, G.nchunk, c->st));
-        HIPCHK(launch_reduce_norms(G.npartial, ncol, G.nchunk, G.nrm, c->st));
-        HIPCHK(launch_scale_by_inv(G.Vi(j + 1), G.w, G.nrm, nif, ncol, c->st));
+        if (krylov_fusable(j + 1, G.nchunk, nif)) {
+          // 5 launches: dots, update (+ h1), dots, update (+ h2, |w|^2 partials), norm + scaling
+          HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
+          HIPCHK(launch_update_reduce(G.w, G.V, vs, j + 1, G.partial, G.nchunk, G.h1, m + 1, mk(-1.0, 0.0), nif,
+                                      ncol, nullptr, c->st));
+          HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
+          HIPCHK(launch_update_reduce(G.w, G.V, vs, j + 1, G.partial, G.nchunk, G.h2, m + 1, mk(-1.0, 0.0), nif,
+                                      ncol, G.npartial, c->st));
+          HIPCHK(launch_scale_reduce(G.Vi(j + 1), G.w, G.npartial, G.nrm, nif, ncol, c->st));
+        } else {
+          HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
+          HIPCHK(launch_reduce_partials(G.partial, j + 1, ncol, G.nchunk, G.h1, m + 1, mk(1.0, 0.0), c->st));
+          HIPCHK(launch_update(G.w, G.V, vs, j + 1, G.h1, m + 1, mk(-1.0, 0.0), nif, ncol, c->st));
+          HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
+          HIPCHK(launch_reduce_partials(G.partial, j + 1, ncol, G.nchunk, G.h2, m + 1, mk(1.0, 0.0), c->st));
+          HIPCHK(launch_update(G.w, G.V, vs, j + 1, G.h2, m + 1, mk(-1.0, 0.0), nif, ncol, c->st));
+          HIPCHK(launch_norms(G.w, nif, ncol, G.npartial, G.nchunk, c->st));
+          HIPCHK(launch_reduce_norms(G.npartial, ncol, G.nchunk, G.nrm, c->st));
+          HIPCHK(launch_scale_by_inv(G.Vi(j + 1), G.w, G.nrm, nif, ncol, c->st));
+        }
       }
-      HIPCHK(hipMemcpyAsync(hh1.data(), G.h1, hh1.size() * sizeof(double2), hipMemcpyDeviceToHost, c->st));
-      HIPCHK(hipMemcpyAsync(hh2.data(), G.h2, hh2.size() * sizeof(double2), hipMemcpyDeviceToHost, c->st));
-      HIPCHK(hipMemcpyAsync(hn.data(), G.nrm, ncol * sizeof(double), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipMemcpyAsync(hbuf_host.data(), G.hbuf, G.hbuf_len * sizeof(double2), hipMemcpyDeviceToHost, c->st));
       HIPCHK(hipStreamSynchronize(c->st));
+      std::copy(hbuf_host.begin(), hbuf_host.begin() + hh1.size(), hh1.begin());
+      std::copy(hbuf_host.begin() + hh1.size(), hbuf_host.begin() + 2 * hh1.size(), hh2.begin());
+      std::memcpy(hn.data(), hbuf_host.data() + 2 * hh1.size(), ncol * sizeof(double));
       ++total;
       bool any_active = false;
       for (int k = 0; k < ncol; ++k) {
@@ -1301,6 +1359,12 @@ static int build_dense(hbj_ctx* c) {
   if (!c->T64 && dalloc(&c->T64, per * c->ndom)) return fail(HBJ_ENOMEM, "dense operator allocation failed");
   if (c->P.precision == HBJ_MIXED && !c->T32 && dalloc(&c->T32, per * c->ndom))
     return fail(HBJ_ENOMEM, "dense operator allocation failed");
+  // dense lifting operators when memory allows (else the lifting stays banded)
+  if (!c->Wl && dalloc(&c->Wl, (size_t)c->ndom * g.nloc * L) != hipSuccess) {
+    c->Wl = nullptr;
+    (void)hipGetLastError();
+  }
+  if (c->Wl) HIPCHK(launch_fill_zero(c->Wl, (size_t)c->ndom * g.nloc * L * sizeof(double2), c->st));
   HIPCHK(launch_fill_zero(c->T64, per * c->ndom * sizeof(double2), c->st));
   std::vector<Entry> all;
   for (int s = 0; s < c->ndom; ++s)
@@ -1323,6 +1387,9 @@ static int build_dense(hbj_ctx* c) {
     if (rc) break;
     he = launch_build_T(g, dev, n, c->ft, c->coef, (const double2*)c->ybuf, (size_t)c->L.nblk * c->L.nb, c->T64,
                         c->st);
+    if (he == hipSuccess && c->Wl)
+      he = launch_build_W(g, dev, n, c->ft, c->coef, (const double2*)c->ybuf, (size_t)c->L.nblk * c->L.nb, c->Wl,
+                          c->st);
     if (he != hipSuccess) rc = fail(HBJ_EHIP, hipGetErrorString(he));
   }
   hipError_t he = hipStreamSynchronize(c->st);

@@ -182,6 +182,23 @@ def test_dense_operator(ctxs, name):
     assert rel(w, dd.apply_operator(gv)) < 1e-12
 
 
+@pytest.mark.parametrize("name", ["small", "ragged", "rect", "grf256", "strip", "pivot"])
+def test_dense_lifting(ctxs, name):
+    """Dense lifting operators (rows of A_s^{-1} at the edge nodes, from the unit-datum
+    solves): the lifting data of a Gaussian source, of a random field (every subdomain has a
+    source), and of an all-zero right-hand side."""
+    wl, m, g, dd, ctx = ctxs(name, operator_form=1)
+    rng = np.random.default_rng(21)
+    f0 = W.sources(wl)[0]
+    f1 = (rng.standard_normal((wl.ny, wl.nx)) + 1j * rng.standard_normal((wl.ny, wl.nx))).astype(np.complex128)
+    f = np.stack([f0, f1, np.zeros_like(f0)])
+    say(f"[dense lifting] case={name}")
+    b = _to_np(ctx.lifting(torch.as_tensor(f, device="cuda")))
+    assert rel(b[0], dd.lifting(f0)) < 1e-12
+    assert rel(b[1], dd.lifting(f1)) < 1e-12
+    assert np.count_nonzero(b[2]) == 0
+
+
 @pytest.mark.parametrize("name,kw,okw", [
     ("small", dict(precond=2), dict(kind="bj")),
     ("grf256", dict(precond=1), dict(kind="sgs")),
