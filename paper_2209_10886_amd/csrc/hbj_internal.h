@@ -266,6 +266,10 @@ hipError_t launch_build_W(const Geom& g, const Entry* ent, int nent, const FaceT
 int lift_chunks(const Geom& g, int pchunk);
 hipError_t launch_lift_dense(const Geom& g, const FaceTab* ft, const double2* W, const double2* f, const int32_t* nz,
                              int nrhs, int pchunk, double2* part, double2* b, hipStream_t st);
+// u += A_s^{-1} B_s g through W (u is read only where nz marks a source: it then holds
+// A_s^{-1} f_s; elsewhere it is overwritten)
+hipError_t launch_recon_dense(const Geom& g, const FaceTab* ft, const IfCoef* coef, const double2* W,
+                              const double2* gin, const int32_t* nz, int nrhs, double2* u, hipStream_t st);
 
 // many right-hand sides: gather the incoming data G[j][col][r] of subdomains subs[j], then
 // OUT = T_s[masked rows, :] G_s on MFMA (complex128 operators on f64 MFMA, complex64 on f32)

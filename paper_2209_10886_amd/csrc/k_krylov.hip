@@ -35,7 +35,7 @@ __device__ inline double2 block_sum(double2 v, double2* sh) {
 // One workgroup per (chunk, group of VG basis vectors, column): the chunk of w is read once per
 // group, the VG dot products accumulate in registers and meet in one block reduction.
 constexpr int VG = 8;
-__global__ __launch_bounds__(RT) void k_multidot(const double2* V, size_t vstride, int nvec, const double2* w,
+__global__ __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_multidot(const double2* V, size_t vstride, int nvec, const double2* w,
                                                  int n, double2* partial, int nchunk) {
   const int chunk = blockIdx.x, i0 = blockIdx.y * VG, col = blockIdx.z;
   const int len = (n + nchunk - 1) / nchunk;
@@ -44,11 +44,31 @@ __global__ __launch_bounds__(RT) void k_multidot(const double2* V, size_t vstrid
   double2 acc[VG];
 #pragma unroll
   for (int v = 0; v < VG; ++v) acc[v] = mk(0.0, 0.0);
-  for (int q = q0 + threadIdx.x; q < q1; q += RT) {
-    const double2 wv = ww[q];
+  // sub-blocks of 4 x RT entries; every load of a sub-block is issued before its products:
+  // indices past the chunk or past the last vector are clamped (in bounds) and their
+  // contributions are zeroed through w or dropped with the accumulator
+  constexpr int U = 4;
+  for (int qb = q0; qb < q1; qb += U * RT) {
+    double2 wl[U];
+    int qi[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int q = qb + threadIdx.x + k * RT;
+      qi[k] = q < q1 ? q : q1 - 1;
+      wl[k] = ww[qi[k]];
+      if (q >= q1) wl[k] = mk(0.0, 0.0);
+    }
+    double2 vl[VG][U];
+#pragma unroll
+    for (int v = 0; v < VG; ++v) {
+      const double2* vp = V + (size_t)min(i0 + v, nvec - 1) * vstride + (size_t)col * n;
+#pragma unroll
+      for (int k = 0; k < U; ++k) vl[v][k] = vp[qi[k]];
+    }
 #pragma unroll
     for (int v = 0; v < VG; ++v)
-      if (i0 + v < nvec) cfma_conj(acc[v], V[(size_t)(i0 + v) * vstride + (size_t)col * n + q], wv);
+#pragma unroll
+      for (int k = 0; k < U; ++k) cfma_conj(acc[v], vl[v][k], wl[k]);
   }
   __shared__ double2 sh[RT / 64][VG];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -83,21 +103,41 @@ __global__ __launch_bounds__(RT) void k_update_reduce(double2* w, const double2*
   __shared__ double2 hl[kFuseMax / 16];
   __shared__ double sn[RT / 64];
   const double2* pc = partial + (size_t)col * nvec * nchunk;
-  for (int t = threadIdx.x; t < nvec * nchunk; t += RT) sp[t] = pc[t];
+  const int np = nvec * nchunk;  // <= kFuseMax = 8 RT: one batch of loads per thread
+  {
+    double2 pv[kFuseMax / RT];
+#pragma unroll
+    for (int k = 0; k < kFuseMax / RT; ++k) {
+      const int t = threadIdx.x + k * RT;
+      pv[k] = pc[t < np ? t : np - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < kFuseMax / RT; ++k) sp[threadIdx.x + k * RT] = pv[k];  // entries >= np unused
+  }
   __syncthreads();
-  if (threadIdx.x < nvec) {
+  constexpr int UB = 8;  // basis vectors per batch of loads
+  const int nv8 = (nvec + UB - 1) / UB * UB;
+  if (threadIdx.x < nv8) {
     double2 h = mk(0.0, 0.0);
-    for (int c = 0; c < nchunk; ++c) h = cadd(h, sp[threadIdx.x * nchunk + c]);
-    hl[threadIdx.x] = h;
-    if (blockIdx.x == 0) h_out[(size_t)col * h_stride + threadIdx.x] = h;
+    if ((int)threadIdx.x < nvec) {
+      for (int c = 0; c < nchunk; ++c) h = cadd(h, sp[threadIdx.x * nchunk + c]);
+      if (blockIdx.x == 0) h_out[(size_t)col * h_stride + threadIdx.x] = h;
+    }
+    hl[threadIdx.x] = h;  // zero weights pad the last batch
   }
   __syncthreads();
   const int q = blockIdx.x * RT + threadIdx.x;
   double sq = 0.0;
+  const size_t t = (size_t)col * n + (q < n ? q : n - 1);
+  double2 acc = mk(0.0, 0.0);
+  for (int i0 = 0; i0 < nv8; i0 += UB) {
+    double2 vl[UB];
+#pragma unroll
+    for (int k = 0; k < UB; ++k) vl[k] = V[(size_t)min(i0 + k, nvec - 1) * vstride + t];
+#pragma unroll
+    for (int k = 0; k < UB; ++k) cfma(acc, vl[k], hl[i0 + k]);
+  }
   if (q < n) {
-    const size_t t = (size_t)col * n + q;
-    double2 acc = mk(0.0, 0.0);
-    for (int i = 0; i < nvec; ++i) cfma(acc, V[(size_t)i * vstride + t], hl[i]);
     double2 r = w[t];
     cfma(r, alpha, acc);
     w[t] = r;
@@ -121,11 +161,18 @@ __global__ __launch_bounds__(RT) void k_update_reduce(double2* w, const double2*
 __global__ __launch_bounds__(RT) void k_scale_reduce(double2* dst, const double2* src, const double* npart,
                                                      int nblk, double* nrm_out, int n) {
   const int col = blockIdx.y;
-  __shared__ double sp[1024];
-  for (int t = threadIdx.x; t < 1024; t += RT) sp[t] = (t < nblk) ? npart[(size_t)col * nblk + t] : 0.0;
+  __shared__ double sp[RT];
+  double pv[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {  // clamped loads, all issued before use
+    const int t = threadIdx.x + k * RT;
+    pv[k] = npart[(size_t)col * nblk + (t < nblk ? t : nblk - 1)];
+    if (t >= nblk) pv[k] = 0.0;
+  }
+  sp[threadIdx.x] = (pv[0] + pv[1]) + (pv[2] + pv[3]);
   __syncthreads();
-  for (int half = 512; half > 0; half >>= 1) {
-    for (int t = threadIdx.x; t < half; t += RT) sp[t] += sp[t + half];
+  for (int half = RT / 2; half > 0; half >>= 1) {
+    if ((int)threadIdx.x < half) sp[threadIdx.x] += sp[threadIdx.x + half];
     __syncthreads();
   }
   const double a = sqrt(sp[0]);
@@ -236,7 +283,7 @@ hipError_t launch_multidot(const double2* V, size_t vstride, int nvec, const dou
 }
 
 bool krylov_fusable(int nvec, int nchunk, int n) {
-  return nvec * nchunk <= kFuseMax && nvec <= kFuseMax / 16 && (n + RT - 1) / RT <= 1024;
+  return nvec * nchunk <= kFuseMax && nvec + 8 <= kFuseMax / 16 && (n + RT - 1) / RT <= 1024;
 }
 
 hipError_t launch_update_reduce(double2* w, const double2* V, size_t vstride, int nvec, const double2* partial,

@@ -1,6 +1,8 @@
 // Dense lifting operators (paper Sec. 4, eq. (3)): the outgoing data b of the lifting
 // w_s = A_s^{-1} f_s with zero transmission data, as one matrix-vector product per subdomain
-// with a source, instead of a sequential banded solve on one compute unit.
+// with a source, instead of a sequential banded solve on one compute unit.  The same matrices
+// give the transmission part of the reconstruction u_s = A_s^{-1} (f_s + B_s g) (Sec. 4):
+// A_s^{-1} B_s g = sum_row x_row g_row = sum_row W_s[.][row] (-inj_row / sigma_row) g_row.
 //
 // A_s is complex symmetric (A = A^T), so the row of A_s^{-1} at edge node n(row) equals the
 // column A_s^{-1} e_{n(row)} = x_row / inj_row, where x_row = A_s^{-1} B e_row is the unit-datum
@@ -93,15 +95,25 @@ __global__ __launch_bounds__(RT) void k_lift_partial(Geom g, const double2* __re
 #pragma unroll
   for (int k = 0; k < RPT; ++k) acc[k] = mk(0.0, 0.0);
   if (any) {
+    // batches of 8 nodes: all their loads (clamped, in bounds) are issued before the products
+    constexpr int PB = 8;
     const double2* Ws = W + (size_t)s * g.nloc * L;
-#pragma unroll 4
-    for (int p = pa; p < pb; ++p) {
-      const double2 fv = fl[p - pa];
-      const double2* wp = Ws + (size_t)p * L;
+    for (int p0 = pa; p0 < pb; p0 += PB) {
+      double2 wl[PB][RPT];
 #pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int row = threadIdx.x + k * RT;
-        if (row < L) cfma(acc[k], wp[row], fv);
+      for (int i = 0; i < PB; ++i) {
+        const int p = min(p0 + i, pb - 1);
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) {
+          const int row = threadIdx.x + k * RT;
+          wl[i][k] = Ws[(size_t)p * L + (row < L ? row : L - 1)];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        const double2 fv = (p0 + i < pb) ? fl[p0 + i - pa] : mk(0.0, 0.0);
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) cfma(acc[k], wl[i][k], fv);
       }
     }
   }
@@ -143,7 +155,85 @@ __global__ __launch_bounds__(RT) void k_lift_reduce(Geom g, const FaceTab* ft, c
   }
 }
 
+// u_s[p] = (nz ? u_s[p] : 0) + sum_row W_s[p][row] gs_row with gs_row = -inj_row / sigma_row * g_row
+// (the incoming datum of the row's face; 0 on outer faces).  u_s already holds A_s^{-1} f_s for
+// the subdomains with a source.  A wavefront per node p reads its 8 KB row of W coalesced
+// (KL entries per lane) and reduces across lanes; each wavefront takes 8 nodes, 32 / KL at a time.
+template <int KL>
+__global__ __launch_bounds__(RT) void k_recon_dense(Geom g, const FaceTab* ft, const IfCoef* coef,
+                                                    const double2* __restrict__ W, const double2* gin,
+                                                    const int32_t* nz, double2* u) {
+  constexpr int PW = 8, PB = 32 / KL;  // nodes per wavefront, nodes in flight
+  const int s = blockIdx.y, r = blockIdx.z;
+  const int ndom = g.n1 * g.n2;
+  const int L = local_if_len(g);
+  const FaceTab F = ft[s];
+  __shared__ double2 gs[KL * 64];
+  for (int col = threadIdx.x; col < KL * 64; col += RT) {
+    double2 v = mk(0.0, 0.0);
+    if (col < L) {
+      int f, e;
+      local_if_face(g, col, &f, &e);
+      const int io = pick4(F.in_off, f);
+      if (io >= 0) {
+        const IfCoef c = coef[io + e];
+        double2 sc = cdiv(c.inj, c.sigma);
+        sc = mk(-sc.x, -sc.y);
+        v = cmul(sc, gin[(size_t)r * g.nif + io + e]);
+      }
+    }
+    gs[col] = v;
+  }
+  __syncthreads();
+  const bool has = nz[(size_t)r * ndom + s] != 0;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int x0 = (s % g.n1) * g.snx, y0 = (s / g.n1) * g.sny;
+  const double2* Ws = W + (size_t)s * g.nloc * L;
+  double2* ur = u + (size_t)r * g.nx * g.ny;
+  const int pbase = blockIdx.x * (RT / 64) * PW + wv * PW;
+  for (int i0 = 0; i0 < PW; i0 += PB) {
+    double2 wl[PB][KL];
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
+      const int p = min(pbase + i0 + i, g.nloc - 1);
+#pragma unroll
+      for (int k = 0; k < KL; ++k) {
+        const int col = lane + 64 * k;
+        wl[i][k] = Ws[(size_t)p * L + (col < L ? col : L - 1)];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PB; ++i) {
+      double2 acc = mk(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < KL; ++k) cfma(acc, wl[i][k], gs[lane + 64 * k]);  // gs is 0 past L
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        acc.x += __shfl_xor(acc.x, off);
+        acc.y += __shfl_xor(acc.y, off);
+      }
+      const int p = pbase + i0 + i;
+      if (lane == 0 && p < g.nloc) {
+        const int ly = p / g.snx, lx = p - ly * g.snx;
+        const size_t o = (size_t)(y0 + ly) * g.nx + x0 + lx;
+        double2 b = has ? ur[o] : mk(0.0, 0.0);
+        ur[o] = cadd(b, acc);
+      }
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_recon_dense(const Geom& g, const FaceTab* ft, const IfCoef* coef, const double2* W,
+                              const double2* gin, const int32_t* nz, int nrhs, double2* u, hipStream_t st) {
+  const int L = local_if_len(g);
+  if (L > 1024) return hipErrorInvalidValue;
+  const dim3 grid((g.nloc + 31) / 32, g.n1 * g.n2, nrhs);
+  if (L <= 512) hipLaunchKernelGGL((k_recon_dense<8>), grid, dim3(RT), 0, st, g, ft, coef, W, gin, nz, u);
+  else hipLaunchKernelGGL((k_recon_dense<16>), grid, dim3(RT), 0, st, g, ft, coef, W, gin, nz, u);
+  return hipGetLastError();
+}
 
 hipError_t launch_build_W(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
                           const double2* ybuf, size_t ystride, double2* W, hipStream_t st) {

@@ -49,30 +49,52 @@ constexpr int LMAX = 1024;   // local interface length limit (sub_nx, sub_ny <= 
 template <typename C, int KMAX>
 __global__ __launch_bounds__(kTR * CG) void k_scatter_apply(Geom g, const Entry* ent, const int32_t* rblist,
                                                             const FaceTab* ft, const C* __restrict__ T, SolveIO io) {
+  constexpr int NT = kTR * CG;
+  constexpr int GLP = LMAX / NT;  // incoming data per thread
   const Entry e = ent[blockIdx.y];
   const int rb = rblist[blockIdx.x];
   const int L = local_if_len(g);
   const int r = threadIdx.x % kTR, grp = threadIdx.x / kTR;
   const FaceTab F = ft[e.s];
+  __shared__ double2 gl[LMAX];
+  __shared__ double2 red[NT / 64][kTR];
+  // 1. incoming data first (absent faces and padding read as zero): every load is issued,
+  //    with in-bounds indices, before any is used
+  const size_t cb = (size_t)e.rhs * g.nif;
+  const int from_b = e.src ? (~io.in_faces & 0xF) : 0;
+  double2 gv[GLP];
+#pragma unroll
+  for (int k = 0; k < GLP; ++k) {
+    const int q = threadIdx.x + k * NT;
+    int f, ee;
+    local_if_face(g, q < L ? q : 0, &f, &ee);
+    const int o = pick4(F.in_off, f);
+    const bool ok = q < L && o >= 0;
+    const double2* src = ((from_b >> f) & 1) ? io.g_b : io.g_a;
+    gv[k] = src[ok ? cb + o + ee : cb];
+    if (!ok) gv[k] = mk(0.0, 0.0);
+  }
+  // the output row of this thread (threads 0-7): its base value and pass-through datum are
+  // loaded up front as well
+  const int row = rb * kTR + (int)threadIdx.x;
+  int rf = 0, re = 0;
+  local_if_face(g, row < L ? row : 0, &rf, &re);
+  const bool mine = threadIdx.x < kTR && row < L && ((e.mask >> rf) & 1);
+  const int oo = pick4(F.out_off, rf), io_ = pick4(F.in_off, rf);
+  const bool wr = mine && oo >= 0, cp = mine && io.copy && io_ >= 0;
+  double2 bv = mk(0.0, 0.0), cv = mk(0.0, 0.0);
+  if (wr && io.tr_base) bv = io.tr_base[cb + oo + re];
+  if (cp) cv = io.g_a[cb + io_ + re];
+  // 2. the operator rows
   const C* Tb = T + (size_t)e.s * t_per_sub(g) + (size_t)rb * L * kTR + r;
   C v[KMAX];
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
+  for (int k = 0; k < KMAX; ++k) {  // clamped column: unconditional loads (its product is zeroed)
     const int col = grp + CG * k;
-    v[k].x = 0;
-    v[k].y = 0;
-    if (col < L) v[k] = Tb[(size_t)col * kTR];
+    v[k] = Tb[(size_t)(col < L ? col : L - 1) * kTR];
   }
-  __shared__ double2 gl[LMAX];
-  __shared__ double2 red[kTR * CG / 64][kTR];
-  const size_t cb = (size_t)e.rhs * g.nif;
-  const int from_b = e.src ? (~io.in_faces & 0xF) : 0;
-  for (int q = threadIdx.x; q < L; q += blockDim.x) {  // absent faces read as zero data
-    int f, ee;
-    local_if_face(g, q, &f, &ee);
-    const int o = pick4(F.in_off, f);
-    gl[q] = (o >= 0) ? (((from_b >> f) & 1) ? io.g_b : io.g_a)[cb + o + ee] : mk(0.0, 0.0);
-  }
+#pragma unroll
+  for (int k = 0; k < GLP; ++k) gl[threadIdx.x + k * NT] = gv[k];
   __syncthreads();
   double2 acc = mk(0.0, 0.0);
 #pragma unroll
@@ -87,24 +109,15 @@ __global__ __launch_bounds__(kTR * CG) void k_scatter_apply(Geom g, const Entry*
   }
   if ((threadIdx.x & 63) < kTR) red[threadIdx.x >> 6][r] = acc;
   __syncthreads();
-  const int row = rb * kTR + (int)threadIdx.x;
-  if (threadIdx.x < kTR && row < L) {
-    int rf, re;
-    local_if_face(g, row, &rf, &re);
-    const int oo = pick4(F.out_off, rf);
-    if (((e.mask >> rf) & 1) && oo >= 0) {
-      double2 sum = red[0][r];
+  if (wr) {
+    double2 sum = red[0][r];
 #pragma unroll
-      for (int w = 1; w < kTR * CG / 64; ++w) sum = cadd(sum, red[w][r]);
-      const size_t o = cb + oo + re;
-      double2 base = io.tr_base ? io.tr_base[o] : mk(0.0, 0.0);
-      base.x += io.tr_sign * sum.x;
-      base.y += io.tr_sign * sum.y;
-      io.tr_dst[o] = base;
-    }
-    const int io_ = pick4(F.in_off, rf);
-    if (io.copy && ((e.mask >> rf) & 1) && io_ >= 0) io.tr_dst[cb + io_ + re] = io.g_a[cb + io_ + re];
+    for (int w = 1; w < NT / 64; ++w) sum = cadd(sum, red[w][r]);
+    bv.x += io.tr_sign * sum.x;
+    bv.y += io.tr_sign * sum.y;
+    io.tr_dst[cb + oo + re] = bv;
   }
+  if (cp) io.tr_dst[cb + io_ + re] = cv;
 }
 
 }  // namespace

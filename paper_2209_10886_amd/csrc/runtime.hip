@@ -121,6 +121,10 @@ struct hbj_ctx {
   float2* mf32 = nullptr;
   float2* mb32 = nullptr;
   double2* Wl = nullptr;    // dense lifting operators [ndom][n_loc][L] (null: banded lifting)
+  hipStream_t side = nullptr;  // source part of the reconstruction, overlapped with GMRES
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  void* ybuf_side = nullptr;
+  size_t ybuf_side_bytes = 0;
   double2* lpart = nullptr; // lifting partial sums
   size_t lpart_cap = 0;
   double2* T64 = nullptr;  // dense scattering operators [ndom][t_rows][L] (row blocks, t_index)
@@ -183,6 +187,13 @@ hbj_ctx::~hbj_ctx() {
     dfree(p);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
+  if (side) {
+    (void)hipStreamSynchronize(side);
+    (void)hipStreamDestroy(side);
+  }
+  if (ev_fork) (void)hipEventDestroy(ev_fork);
+  if (ev_join) (void)hipEventDestroy(ev_join);
+  dfree(ybuf_side);
 }
 
 namespace {
@@ -441,6 +452,24 @@ int run_solves(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io) {
     ProfScope ps(c, HBJ_K_BWD, nent * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1));
     HIPCHK((launch_bwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st)));
   }
+  c->local_solves += nent;
+  return HBJ_OK;
+}
+
+// FP64 local solves of a batch on the side stream (own workspace, not profiled)
+int run_solves_side(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io) {
+  if (nent == 0) return HBJ_OK;
+  const size_t need = (size_t)nent * c->L.nblk * c->L.nb * sizeof(double2);
+  if (need > c->ybuf_side_bytes) {
+    dfree(c->ybuf_side);
+    c->ybuf_side = nullptr;
+    c->ybuf_side_bytes = 0;
+    if (hipMalloc(&c->ybuf_side, need) != hipSuccess) return fail(HBJ_ENOMEM, "workspace allocation failed");
+    c->ybuf_side_bytes = need;
+  }
+  HIPCHK((launch_fwd<double>(c->g, c->L, ent, nent, c->ft, c->coef, c->mf64, c->pf, c->pflag, io,
+                             (double2*)c->ybuf_side, c->side)));
+  HIPCHK((launch_bwd<double>(c->g, c->L, ent, nent, c->ft, c->coef, c->mb64, io, (double2*)c->ybuf_side, c->side)));
   c->local_solves += nent;
   return HBJ_OK;
 }
@@ -748,6 +777,63 @@ int run_lifting(hbj_ctx* c, Schedule* S, const double2* f, double2* b, int nrhs)
   io.tr_dst = b;
   io.tr_sign = 1.0;
   io.tr_reflect = 0;
+  return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+}
+
+// Source part of the reconstruction, u_s = A_s^{-1} f_s (zero where f_s = 0), on the side
+// stream once the flags of run_lifting are known; the main stream goes on with GMRES.
+int fork_source_part(hbj_ctx* c, Schedule* S, const double2* f, double2* u) {
+  if (!c->side) {
+    HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  }
+  HIPCHK(hipEventRecord(c->ev_fork, c->st));
+  HIPCHK(hipStreamWaitEvent(c->side, c->ev_fork, 0));
+  SolveIO io{};
+  io.f = f;
+  io.nz = c->nzf;
+  io.u = u;
+  int rc = run_solves_side(c, S->dev + S->all_first, S->all_count, io);
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(c->ev_join, c->side));
+  return HBJ_OK;
+}
+
+// u = A^{-1}(f + B g) on every subdomain.  Dense form: u holds the source part (from the side
+// stream when source_done, else computed here) and the transmission part is one product with
+// the lifting matrices per subdomain; banded form: one local solve per subdomain.
+int run_reconstruct(hbj_ctx* c, Schedule* S, const double2* f, const double2* g, double2* u, int nrhs,
+                    bool source_done) {
+  if (c->Wl && c->g.nif > 0 && g) {
+    if (source_done) {
+      HIPCHK(hipStreamWaitEvent(c->st, c->ev_join, 0));
+    } else {
+      const size_t need = (size_t)nrhs * c->ndom;
+      if (need > c->nzf_cap) {
+        dfree(c->nzf);
+        c->nzf = nullptr;
+        c->nzf_cap = 0;
+        if (dalloc(&c->nzf, need)) return fail(HBJ_ENOMEM, "flag allocation failed");
+        c->nzf_cap = need;
+      }
+      HIPCHK(launch_source_flags(c->g, f, nrhs, c->nzf, c->st));
+      SolveIO io{};
+      io.f = f;
+      io.nz = c->nzf;
+      io.u = u;
+      int rc = run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+      if (rc) return rc;
+    }
+    const double elems = (double)nrhs * c->ndom * c->g.nloc * local_if_len(c->g);
+    ProfScope ps(c, HBJ_K_LIFT, elems * 16.0, elems * 8.0);
+    HIPCHK(launch_recon_dense(c->g, c->ft, c->coef, c->Wl, g, c->nzf, nrhs, u, c->st));
+    return HBJ_OK;
+  }
+  SolveIO io{};
+  io.f = f;
+  io.g_a = (c->g.nif > 0) ? g : nullptr;
+  io.u = u;
   return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
 }
 
@@ -1496,11 +1582,7 @@ int hbj_reconstruct(hbj_ctx* c, const hbj_c128* f, const hbj_c128* g, hbj_c128* 
   Schedule* S;
   rc = build_schedule(c, nrhs, &S);
   if (rc) return rc;
-  SolveIO io{};
-  io.f = (const double2*)f;
-  io.g_a = (c->g.nif > 0) ? (const double2*)g : nullptr;
-  io.u = (double2*)u;
-  return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+  return run_reconstruct(c, S, (const double2*)f, (const double2*)g, (double2*)u, nrhs, false);
 }
 
 static int solve_impl(hbj_ctx* c, const double2* f, double2* u, int nrhs, const hbj_solve_opts* opts,
@@ -1540,13 +1622,17 @@ static int solve_impl(hbj_ctx* c, const double2* f, double2* u, int nrhs, const 
     if (rc) return rc;
     rc = run_lifting(c, S, f, G.b, nrhs);
     if (rc) return rc;
+    const bool forked = c->Wl != nullptr;
+    if (forked) {
+      rc = fork_source_part(c, S, f, u);
+      if (rc) return rc;
+    }
     rc = gmres_solve(c, S, G, o, stats, iters, relres, conv, hist);
-    if (rc) return rc;
-    SolveIO io{};
-    io.f = f;
-    io.g_a = G.x;
-    io.u = u;
-    rc = run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+    if (rc) {
+      if (forked) (void)hipStreamSynchronize(c->side);
+      return rc;
+    }
+    rc = run_reconstruct(c, S, f, G.x, u, nrhs, forked);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(c->st));
   }

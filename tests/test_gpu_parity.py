@@ -199,6 +199,24 @@ def test_dense_lifting(ctxs, name):
     assert np.count_nonzero(b[2]) == 0
 
 
+@pytest.mark.parametrize("name", ["small", "ragged", "rect", "grf256", "pivot"])
+@pytest.mark.parametrize("form", [0, 1])
+def test_reconstruct(ctxs, name, form):
+    """u = A_s^{-1}(f_s + B_s g) on every subdomain, banded (one local solve each) or dense
+    (source part by local solves, transmission part through the lifting matrices); a Gaussian
+    source, a random source and a zero source, each with random interface data."""
+    wl, m, g, dd, ctx = ctxs(name, operator_form=form)
+    rng = np.random.default_rng(23)
+    f0 = W.sources(wl)[0]
+    f1 = (rng.standard_normal((wl.ny, wl.nx)) + 1j * rng.standard_normal((wl.ny, wl.nx))).astype(np.complex128)
+    f = np.stack([f0, f1, np.zeros_like(f0)])
+    gv = W.random_interface_vector(ctx.nif, seed=24, nrhs=3)
+    say(f"[reconstruct] case={name} form={form}")
+    u = _to_np(ctx.reconstruct(torch.as_tensor(f, device="cuda"), torch.as_tensor(gv, device="cuda")))
+    for k in range(3):
+        assert rel(u[k], dd.reconstruct(f[k], gv[k])) < 1e-12
+
+
 @pytest.mark.parametrize("name,kw,okw", [
     ("small", dict(precond=2), dict(kind="bj")),
     ("grf256", dict(precond=1), dict(kind="sgs")),
