@@ -51,17 +51,20 @@ def parse():
     return p.parse_args()
 
 
-def traffic_from_profiles(kernel_symbol):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they match this source."""
+def traffic_from_profiles(kernel_symbol, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary (FETCH_SIZE and
+    WRITE_SIZE, scaled by a copy of known size), if it was taken on this workload from the
+    current source of the kernel; None otherwise."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
-        data = json.load(open(path))
-        src = os.path.join(ROOT, "paper_2209_10886_amd", "csrc", "k_trisolve.hip")
+        ent = json.load(open(path)).get(f"{workload}/{kernel_symbol}")
+        if not ent:
+            return None
+        src = os.path.join(ROOT, "paper_2209_10886_amd", "csrc", ent["source"])
         sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-        ent = data.get(kernel_symbol)
-        if not ent or ent.get("source_sha") != sha:
+        if ent.get("source_sha") != sha:
             return None
         return ent["bytes_per_launch"]
     except Exception:
@@ -141,15 +144,33 @@ def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, p
     return {"seconds": dt, "steps": steps, "factor_s": t_factor, "stats": st, "kernels": stats}
 
 
-def roofline_of(kernels):
-    name, ks = max(kernels.items(), key=lambda kv: kv[1]["ms"])
+def merge_kernels(kernels):
+    """Classes that time the same kernel symbol are merged (its launches, time and bytes)."""
+    out = {}
+    for name, ks in kernels.items():
+        sym = name.split(" (")[0]
+        m = out.setdefault(sym, {"launches": 0, "ms": 0.0, "bytes": 0.0, "flops": 0.0, "classes": []})
+        for k in ("launches", "ms", "bytes", "flops"):
+            m[k] += ks[k]
+        m["classes"].append(name)
+    return out
+
+
+def roofline_of(kernels, workload):
+    merged = merge_kernels(kernels)
+    name, ks = max(merged.items(), key=lambda kv: kv[1]["ms"])
     avg_ms = ks["ms"] / ks["launches"]
     bpl = ks["bytes"] / ks["launches"]
     achieved = bpl / (avg_ms * 1e-3) / 1e9
+    detail = {c: {"launches": kernels[c]["launches"], "avg_launch_ms": kernels[c]["ms"] / max(1, kernels[c]["launches"]),
+                  "bytes_per_launch": kernels[c]["bytes"] / max(1, kernels[c]["launches"]),
+                  "GB/s": kernels[c]["bytes"] / max(1e-12, kernels[c]["ms"] * 1e-3) / 1e9}
+              for c in ks["classes"]}
     return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(name), "bytes_per_launch": bpl,
-            "avg_launch_ms": avg_ms, "launches": ks["launches"],
-            "share_of_kernel_time": ks["ms"] / max(1e-12, sum(k["ms"] for k in kernels.values()))}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(name, workload),
+            "bytes_per_launch": bpl, "avg_launch_ms": avg_ms, "launches": ks["launches"],
+            "share_of_kernel_time": ks["ms"] / max(1e-12, sum(k["ms"] for k in kernels.values())),
+            "launch_kinds": detail}
 
 
 def solve_gbs(kernels, names):
@@ -186,12 +207,15 @@ def main():
         args.no_cpu = args.no_cpu or nsrc > 1
         args.no_mixed = True
     names64 = {hbj.K_FWD: "k_fwd<double,16,4,5>", hbj.K_BWD: "k_bwd<double,16,2,3>",
-               hbj.K_SCATTER: "k_scatter_apply<double2>", hbj.K_SWEEP: "k_sweep_df<double2,16>",
-               hbj.K_KRYLOV: "krylov"}
-    names32 = {hbj.K_FWD: "k_fwd (lifting/reconstruction FP64, sweeps complex64)", hbj.K_BWD: "k_bwd (idem)",
-               hbj.K_SCATTER: "k_scatter_apply<float2>",
-               hbj.K_SWEEP: "k_sweep_df<float2,16> (preconditioner) + k_sweep_df<double2,16> (operator)",
-               hbj.K_KRYLOV: "krylov"}
+               hbj.K_SCATTER: "k_scatter_apply<double2,16> (sweep steps)",
+               hbj.K_OPERATOR: "k_scatter_apply<double2,16> (operator)",
+               hbj.K_SWEEP: "k_sweep_df<double2,16>", hbj.K_LIFT: "k_lift_partial+k_recon_dense",
+               hbj.K_KRYLOV: "krylov (5 launches per iteration)"}
+    names32 = {hbj.K_FWD: "k_fwd<float,16,4,8>", hbj.K_BWD: "k_bwd<float,16,2,4>",
+               hbj.K_SCATTER: "k_scatter_apply<float2,16> (sweep steps)",
+               hbj.K_OPERATOR: "k_scatter_apply<double2,16> (operator)",
+               hbj.K_SWEEP: "k_sweep_df", hbj.K_LIFT: "k_lift_partial+k_recon_dense",
+               hbj.K_KRYLOV: "krylov (5 launches per iteration)"}
 
     log(f"[bench] {'FP64' if headline_prec == hbj.FP64 else 'mixed'}, dense scattering operators (headline), "
         f"{nsrc} right-hand side(s)")
@@ -201,7 +225,7 @@ def main():
     ms_per_step = main_run["seconds"] / max(args.steps, 1) * 1e3
     log(f"[bench] {ms_per_step:.2f} ms/solve, iters {st.iters}, relres {st.relres:.2e}, "
         f"factor {main_run['factor_s']:.2f} s")
-    roof = roofline_of(main_run["kernels"])
+    roof = roofline_of(main_run["kernels"], wl.name)
     log(f"[bench] dominant {roof['kernel']}: {roof['avg_launch_ms']:.4f} ms avg, {roof['achieved']:.1f} GB/s")
 
     result = {
@@ -237,14 +261,14 @@ def main():
         result["banded_fp64"] = {
             "solves_per_s": 1.0 / br["seconds"], "iters": br["stats"].iters, "relres": br["stats"].relres,
             "subdomain_solve_gbs": solve_gbs(br["kernels"], [names64[hbj.K_FWD], names64[hbj.K_BWD]]),
-            "roofline": roofline_of(br["kernels"])}
+            "roofline": roofline_of(br["kernels"], wl.name + "/banded")}
 
     if not args.no_mixed:
         log("[bench] mixed precision (complex64 factors and preconditioner operators)")
         mr = run_form(hbj, wl, mt, ft, u, hbj.MIXED, hbj.OP_DENSE, args.steps, 1, args.tol, names32)
         result["mixed"] = {"solves_per_s": args.steps / mr["seconds"], "iters": mr["stats"].iters,
                            "relres": mr["stats"].relres, "factor_s": mr["factor_s"],
-                           "roofline": roofline_of(mr["kernels"])}
+                           "roofline": roofline_of(mr["kernels"], wl.name + "/mixed")}
         if not args.no_banded:
             mb = run_form(hbj, wl, mt, ft, u, hbj.MIXED, hbj.OP_BANDED, 1, 0, args.tol, names32)
             result["banded_mixed"] = {

@@ -130,7 +130,9 @@ typedef struct {
 
 typedef struct {         /* per kernel class, accumulated while profiling is on     */
   int64_t launches;
-  double  ms;            /* summed kernel time between HIP events on the stream     */
+  double  ms;            /* summed kernel time between HIP events on the stream (the
+                            dense single-launch classes use the dispatch's own start
+                            and stop times)                                        */
   double  bytes;         /* summed algorithmic bytes (factor entries + vectors)     */
   double  flops;         /* summed algorithmic flops                                */
 } hbj_kernel_stat;
@@ -138,8 +140,10 @@ typedef struct {         /* per kernel class, accumulated while profiling is on 
 /* kernel classes for hbj_kernel_stats */
 enum { HBJ_K_FWD = 0, HBJ_K_BWD = 1, HBJ_K_FACTOR = 2, HBJ_K_KRYLOV = 3, HBJ_K_SCATTER = 4,
        HBJ_K_SWEEP = 5,     /* dataflow sweep launches (HBJ_SWEEP_DATAFLOW)      */
-       HBJ_K_LIFT = 6,      /* dense lifting products (HBJ_OP_DENSE)             */
-       HBJ_K_NCLASS = 7 };
+       HBJ_K_LIFT = 6,      /* dense lifting and reconstruction products         */
+       HBJ_K_OPERATOR = 7,  /* dense operator (I - S) applications; HBJ_K_SCATTER
+                               then counts the preconditioner's sweep steps      */
+       HBJ_K_NCLASS = 8 };
 
 /*
  * hbj_setup - describe the problem and build the decomposition (paper Secs. 2-3).

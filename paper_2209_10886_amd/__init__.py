@@ -33,7 +33,7 @@ BJ_PRODUCT, BJ_RESIDUAL = 0, 1
 OP_BANDED, OP_DENSE = 0, 1
 SWEEP_STEPPED, SWEEP_DATAFLOW = 0, 1
 OK, EINVAL, ESTATE, EHIP, ENOMEM, EWAIT, ZERO_PIVOT, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, 1, 2
-K_FWD, K_BWD, K_FACTOR, K_KRYLOV, K_SCATTER, K_SWEEP, K_LIFT = 0, 1, 2, 3, 4, 5, 6
+K_FWD, K_BWD, K_FACTOR, K_KRYLOV, K_SCATTER, K_SWEEP, K_LIFT, K_OPERATOR = 0, 1, 2, 3, 4, 5, 6, 7
 
 
 class Problem(ctypes.Structure):

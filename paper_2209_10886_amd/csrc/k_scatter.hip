@@ -8,6 +8,8 @@
 // edge nodes.  Column c of T_s is built from one local solve with a unit datum at
 // position c.  Applying T_s is then a dense matrix-vector product whose rows can be
 // spread over many workgroups, instead of one workgroup walking the whole band.
+#include <hip/hip_ext.h>
+
 #include "hbj_internal.h"
 
 namespace {
@@ -131,20 +133,25 @@ hipError_t launch_build_T(const Geom& g, const Entry* ent, int nent, const FaceT
 
 template <typename C>
 hipError_t launch_scatter_apply(const Geom& g, const Entry* ent, int nent, int mask, const int32_t* rblist, int nrb,
-                                const FaceTab* ft, const C* T, const SolveIO& io, hipStream_t st) {
+                                const FaceTab* ft, const C* T, const SolveIO& io, hipStream_t st, hipEvent_t t0,
+                                hipEvent_t t1) {
   (void)mask;  // carried by every entry
   if (nent == 0 || nrb == 0) return hipSuccess;
   const int L = local_if_len(g);
   if (L > LMAX) return hipErrorInvalidValue;
   const dim3 grid(nrb, nent);
+  // with events, the start and stop times are those of the dispatch itself
   if (L <= 16 * CG)
-    hipLaunchKernelGGL((k_scatter_apply<C, 16>), grid, dim3(kTR * CG), 0, st, g, ent, rblist, ft, T, io);
+    hipExtLaunchKernelGGL((k_scatter_apply<C, 16>), grid, dim3(kTR * CG), 0, st, t0, t1, 0, g, ent, rblist, ft, T, io);
   else
-    hipLaunchKernelGGL((k_scatter_apply<C, LMAX / CG>), grid, dim3(kTR * CG), 0, st, g, ent, rblist, ft, T, io);
+    hipExtLaunchKernelGGL((k_scatter_apply<C, LMAX / CG>), grid, dim3(kTR * CG), 0, st, t0, t1, 0, g, ent, rblist, ft,
+                          T, io);
   return hipGetLastError();
 }
 
 template hipError_t launch_scatter_apply<double2>(const Geom&, const Entry*, int, int, const int32_t*, int,
-                                                  const FaceTab*, const double2*, const SolveIO&, hipStream_t);
+                                                  const FaceTab*, const double2*, const SolveIO&, hipStream_t,
+                                                  hipEvent_t, hipEvent_t);
 template hipError_t launch_scatter_apply<float2>(const Geom&, const Entry*, int, int, const int32_t*, int,
-                                                 const FaceTab*, const float2*, const SolveIO&, hipStream_t);
+                                                 const FaceTab*, const float2*, const SolveIO&, hipStream_t, hipEvent_t,
+                                                 hipEvent_t);
