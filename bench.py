@@ -140,8 +140,9 @@ def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, p
     ctx.solve(ft, tol=tol, out=u)
     ctx.set_profiling(False)
     stats = {name: ctx.kernel_stats(kc) for kc, name in profile_names.items()}
+    tuning = {k: v for k, v in ctx.tuning().items() if v["k_steps_per_batch"] is not None}
     ctx.close()
-    return {"seconds": dt, "steps": steps, "factor_s": t_factor, "stats": st, "kernels": stats}
+    return {"seconds": dt, "steps": steps, "factor_s": t_factor, "stats": st, "kernels": stats, "tuning": tuning}
 
 
 def merge_kernels(kernels):
@@ -254,6 +255,8 @@ def main():
         if headline_prec == hbj.FP64 else None,
         "roofline": roof,
     }
+    if main_run["tuning"]:
+        result["autotuned_operator_tiles"] = main_run["tuning"]
 
     if not args.no_banded:
         log("[bench] FP64, banded local solves inside GMRES")

@@ -266,6 +266,17 @@ int hbj_kernel_stats(hbj_ctx* ctx, int32_t kclass, hbj_kernel_stat* out);
 int hbj_reset_kernel_stats(hbj_ctx* ctx);
 
 /*
+ * hbj_get_tuning - choices of the autotuner of the many-right-hand-side operator
+ * kernel (dense form, 4 or more right-hand sides).  On its first launch of each
+ * kind the library times every tile depth (k-steps per batch of loads: 2, 4, 8)
+ * on that launch's own data, writing into scratch, and keeps the fastest.
+ *   variants  HOST [4]: complex128 sweep steps, complex128 operator, complex64
+ *             sweep steps, complex64 operator; -1 = not tuned yet.
+ *   us        HOST [4][3] or NULL: the measured microseconds per launch.
+ */
+int hbj_get_tuning(const hbj_ctx* ctx, int32_t* variants, float* us);
+
+/*
  * hbj_set_sweep_wait - bounds of the dataflow sweeps' dependency waits, for tests
  * of the error path.  max_polls: polls of a completion counter before the wait
  * gives up (<= 0 restores the default, about a second); stall_task: index of a

@@ -84,6 +84,7 @@ _SIGS = {
     "hbj_kernel_stats": (_I, [_P, _I32, ctypes.POINTER(KernelStat)]),
     "hbj_reset_kernel_stats": (_I, [_P]),
     "hbj_set_sweep_wait": (_I, [_P, _I32, _I32]),
+    "hbj_get_tuning": (_I, [_P, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)]),
     "hbj_strerror": (ctypes.c_char_p, [_I]),
     "hbj_last_error": (ctypes.c_char_p, []),
     "hbj_destroy": (None, [_P]),
@@ -274,6 +275,17 @@ class Context:
 
     def reset_kernel_stats(self):
         _check(_lib.hbj_reset_kernel_stats(self._h))
+
+    def tuning(self):
+        """Autotuned tile depths of the many-RHS operator kernel and their measured us per launch."""
+        v = (_I32 * 4)()
+        us = (ctypes.c_float * 12)()
+        _check(_lib.hbj_get_tuning(self._h, v, us))
+        kinds = ("c128 steps", "c128 operator", "c64 steps", "c64 operator")
+        depths = (2, 4, 8)
+        return {k: {"k_steps_per_batch": depths[v[i]] if v[i] >= 0 else None,
+                    "us": {d: round(us[i * 3 + j], 2) for j, d in enumerate(depths)} if v[i] >= 0 else None}
+                for i, k in enumerate(kinds)}
 
     def set_sweep_wait(self, max_polls=0, stall_task=-1):
         """Bounds of the dataflow sweeps' dependency waits (error-path tests)."""

@@ -278,7 +278,8 @@ hipError_t launch_gather_incoming(const Geom& g, const int32_t* subs, int nsub, 
                                   int nrhs, int rpad, double2* G, hipStream_t st);
 template <typename C>
 hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int mask, const FaceTab* ft, const C* T,
-                             const double2* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st);
+                             const double2* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st, int variant);
+constexpr int kMmVariants = 3;  // k-steps per batch of loads: 2, 4, 8
 
 // gradient / misc
 hipError_t launch_gather_receivers(const double2* u, const int32_t* rec, int nrec, int npts, const double2* d,

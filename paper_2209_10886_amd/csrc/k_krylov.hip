@@ -252,9 +252,9 @@ __global__ void k_copy(double2* dst, const double2* src, size_t n) {
   if (t < n) dst[t] = src[t];
 }
 
-__global__ void k_zero_bytes(uint32_t* dst, size_t nwords) {
-  const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < nwords) dst[t] = 0u;
+__global__ void k_zero_bytes(uint32_t* dst, size_t nwords) {  // grid-stride: any size
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < nwords; t += (size_t)gridDim.x * blockDim.x)
+    dst[t] = 0u;
 }
 
 // y[col][q] += x[col][q] for q in any of the [start, end) ranges
@@ -347,7 +347,8 @@ hipError_t launch_copy(double2* dst, const double2* src, size_t n, hipStream_t s
 hipError_t launch_fill_zero(void* dst, size_t bytes, hipStream_t st) {
   if (bytes == 0) return hipSuccess;
   const size_t nw = bytes / 4;
-  hipLaunchKernelGGL(k_zero_bytes, grid1(nw), dim3(256), 0, st, (uint32_t*)dst, nw);
+  const size_t nb = std::min<size_t>((nw + 255) / 256, (size_t)1 << 16);
+  hipLaunchKernelGGL(k_zero_bytes, dim3((unsigned)nb), dim3(256), 0, st, (uint32_t*)dst, nw);
   return hipGetLastError();
 }
 

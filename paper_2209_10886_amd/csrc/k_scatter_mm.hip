@@ -58,11 +58,12 @@ constexpr int TB = 4;  // 16-column right-hand-side blocks per wavefront (64 rig
 constexpr int KW = 4;  // wavefronts splitting the k range of one tile
 
 // grid: (ceil(masked rows / 16), nsub, ceil(R / 64)).  One 16-row x 64-column output tile per
-// workgroup; wavefront w takes every KW-th group of 4 columns, and the four partial tiles are
-// summed in LDS.  Each wavefront issues the loads of two k-steps before their 16 MFMAs, which go
-// to eight independent accumulators.
-template <typename C, typename M>
-__global__ __launch_bounds__(64 * KW) void k_scatter_mm(Geom g, const int32_t* subs, int mask, const FaceTab* ft,
+// workgroup; wavefront w takes every KW-th group of 4 columns of each existing face, and the four
+// partial tiles are summed in LDS.  Each wavefront issues the loads of KB k-steps (column indices
+// clamped into the face, out-of-range steps zeroed after the load) before their MFMAs, which go to
+// eight independent accumulators; KB is the tile depth chosen by the autotuner.
+template <typename C, typename M, int KB>
+__global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_scatter_mm(Geom g, const int32_t* subs, int mask, const FaceTab* ft,
                                                         const C* __restrict__ T, const double2* __restrict__ G,
                                                         int nrhs, int rpad, SolveIO io) {
   typedef MfmaAcc<M> A;
@@ -74,6 +75,7 @@ __global__ __launch_bounds__(64 * KW) void k_scatter_mm(Geom g, const int32_t* s
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int i = lane & 15, k = lane >> 4;
   const int mrow = masked_row_mm(g, mask, blockIdx.x * 16 + i);  // this lane's A row
+  const M amask = mrow >= 0 ? (M)1 : (M)0;
   const int rb0 = blockIdx.z * 16 * TB;
   const C* Ts = T + (size_t)s * t_per_sub(g) + t_index(L, mrow < 0 ? 0 : mrow, 0);
   const double2* Gs = G + (size_t)j * L * rpad + rb0 + i;
@@ -83,48 +85,37 @@ __global__ __launch_bounds__(64 * KW) void k_scatter_mm(Geom g, const int32_t* s
     cr[t] = V4{0, 0, 0, 0};
     ci[t] = V4{0, 0, 0, 0};
   }
-  auto load = [&](int col, bool ok, M& ar, M& ai, M (&br)[TB], M (&bi)[TB]) {
-    ar = 0;
-    ai = 0;
-    if (ok && mrow >= 0) {
-      const C tv = Ts[(size_t)col * kTR];
-      ar = (M)tv.x;
-      ai = (M)tv.y;
-    }
+  const int present[4] = {F.in_off[0] >= 0, F.in_off[1] >= 0, F.in_off[2] >= 0, F.in_off[3] >= 0};
 #pragma unroll
-    for (int t = 0; t < TB; ++t) {
-      br[t] = 0;
-      bi[t] = 0;
-      if (ok) {
-        const double2 gv = Gs[(size_t)col * rpad + 16 * t];
-        br[t] = (M)gv.x;
-        bi[t] = (M)gv.y;
-      }
-    }
-  };
-  auto mma = [&](M ar, M ai, const M (&br)[TB], const M (&bi)[TB]) {
-#pragma unroll
-    for (int t = 0; t < TB; ++t) {
-      cr[t] = A::mma(ar, br[t], cr[t]);
-      ci[t] = A::mma(ar, bi[t], ci[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < TB; ++t) {
-      cr[t] = A::mma(-ai, bi[t], cr[t]);
-      ci[t] = A::mma(ai, br[t], ci[t]);
-    }
-  };
   for (int f = 0; f < 4; ++f) {
-    if (F.in_off[f] < 0) continue;
+    if (!present[f]) continue;
     const int c0 = face_off(g, f), c1 = c0 + face_len(g, f);
-    // this wavefront's k-steps: c0 + 4 (w + KW q)
-    for (int c = c0 + 4 * w; c < c1; c += 8 * KW) {
-      M ar0, ai0, br0[TB], bi0[TB], ar1, ai1, br1[TB], bi1[TB];
-      const int col0 = c + k, col1 = c + 4 * KW + k;
-      load(col0, col0 < c1, ar0, ai0, br0, bi0);
-      load(col1, col1 < c1, ar1, ai1, br1, bi1);
-      mma(ar0, ai0, br0, bi0);
-      mma(ar1, ai1, br1, bi1);
+    // this wavefront's k-steps: c0 + 4 (w + KW q), KB of them per batch
+    for (int c = c0 + 4 * w; c < c1; c += 4 * KW * KB) {
+      C tv[KB];
+      double2 gv[KB][TB];
+#pragma unroll
+      for (int b = 0; b < KB; ++b) {
+        const int col = c + 4 * KW * b + k;
+        const int cc = col < c1 ? col : c1 - 1;
+        tv[b] = Ts[(size_t)cc * kTR];
+#pragma unroll
+        for (int t = 0; t < TB; ++t) gv[b][t] = Gs[(size_t)cc * rpad + 16 * t];
+      }
+      __builtin_amdgcn_sched_barrier(0);  // keep the whole batch of loads ahead of the MFMAs
+#pragma unroll
+      for (int b = 0; b < KB; ++b) {
+        const M ok = (c + 4 * KW * b + k < c1) ? amask : (M)0;
+        const M ar = (M)tv[b].x * ok, ai = (M)tv[b].y * ok;
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+          const M br = (M)gv[b][t].x, bi = (M)gv[b][t].y;
+          cr[t] = A::mma(ar, br, cr[t]);
+          ci[t] = A::mma(ar, bi, ci[t]);
+          cr[t] = A::mma(-ai, bi, cr[t]);
+          ci[t] = A::mma(ai, br, ci[t]);
+        }
+      }
     }
   }
   // sum the KW partial tiles: wavefront w finishes right-hand-side block t = w
@@ -174,7 +165,7 @@ hipError_t launch_gather_incoming(const Geom& g, const int32_t* subs, int nsub, 
 
 template <typename C>
 hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int mask, const FaceTab* ft, const C* T,
-                             const double2* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st) {
+                             const double2* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st, int variant) {
   if (nsub == 0) return hipSuccess;
   int rows = 0;
   for (int f = 0; f < 4; ++f)
@@ -182,11 +173,22 @@ hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int m
   static_assert(KW == TB, "one right-hand-side block per wavefront in the epilogue");
   const dim3 grid((rows + 15) / 16, nsub, (nrhs + 16 * TB - 1) / (16 * TB));
   typedef typename std::conditional<sizeof(C) == 16, double, float>::type M;
-  hipLaunchKernelGGL((k_scatter_mm<C, M>), grid, dim3(64 * KW), 0, st, g, subs, mask, ft, T, G, nrhs, rpad, io);
+  switch (variant) {
+    case 0:
+      hipLaunchKernelGGL((k_scatter_mm<C, M, 2>), grid, dim3(64 * KW), 0, st, g, subs, mask, ft, T, G, nrhs, rpad, io);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_scatter_mm<C, M, 4>), grid, dim3(64 * KW), 0, st, g, subs, mask, ft, T, G, nrhs, rpad, io);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_scatter_mm<C, M, 8>), grid, dim3(64 * KW), 0, st, g, subs, mask, ft, T, G, nrhs, rpad, io);
+      break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
 template hipError_t launch_scatter_mm<double2>(const Geom&, const int32_t*, int, int, const FaceTab*, const double2*,
-                                               const double2*, int, int, const SolveIO&, hipStream_t);
+                                               const double2*, int, int, const SolveIO&, hipStream_t, int);
 template hipError_t launch_scatter_mm<float2>(const Geom&, const int32_t*, int, int, const FaceTab*, const float2*,
-                                              const double2*, int, int, const SolveIO&, hipStream_t);
+                                              const double2*, int, int, const SolveIO&, hipStream_t, int);

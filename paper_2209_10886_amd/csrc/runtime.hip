@@ -149,6 +149,10 @@ struct hbj_ctx {
   size_t loc64_entries = 0;
   double2* Gbuf = nullptr;  // gathered incoming data for the many-right-hand-side operators
   size_t Gbuf_cap = 0;
+  // autotuned tile depth of the many-right-hand-side operator kernel, per (precision, stage kind):
+  // [complex128 steps, complex128 operator, complex64 steps, complex64 operator]; -1 = not tuned
+  int mm_variant[4] = {-1, -1, -1, -1};
+  float mm_us[4][kMmVariants] = {};
   int32_t* nzf = nullptr;   // per (rhs, subdomain) nonzero-source flags for the lifting
   size_t nzf_cap = 0;
   double2* pc_y = nullptr;  // preconditioner pass buffers [nrhs][nif]
@@ -492,12 +496,44 @@ int run_dense(hbj_ctx* c, const Entry* ent, int nent, int mask, const SolveIO& i
     }
     // per subdomain the operator is read once for all right-hand sides
     const double tbytes = elems / nrhs * (c64 ? 8.0 : 16.0);
-    ProfScope ps(c, HBJ_K_SCATTER, tbytes, elems * 8.0);
     HIPCHK(launch_gather_incoming(c->g, subs, nsub, c->ft, src ? io.g_b : io.g_a, nrhs, rpad, c->Gbuf, c->st));
-    if (c64)
-      HIPCHK(launch_scatter_mm<float2>(c->g, subs, nsub, mask, c->ft, c->T32, c->Gbuf, nrhs, rpad, io, c->st));
-    else
-      HIPCHK(launch_scatter_mm<double2>(c->g, subs, nsub, mask, c->ft, c->T64, c->Gbuf, nrhs, rpad, io, c->st));
+    const int slot = (c64 ? 2 : 0) + (mask == 0xF ? 1 : 0);
+    auto launch = [&](int v, const SolveIO& lio) -> hipError_t {
+      return c64 ? launch_scatter_mm<float2>(c->g, subs, nsub, mask, c->ft, c->T32, c->Gbuf, nrhs, rpad, lio, c->st, v)
+                 : launch_scatter_mm<double2>(c->g, subs, nsub, mask, c->ft, c->T64, c->Gbuf, nrhs, rpad, lio, c->st,
+                                              v);
+    };
+    if (c->mm_variant[slot] < 0) {
+      // autotuner: time every tile depth on this very launch, writing into scratch, keep the fastest
+      double2* scratch = nullptr;
+      if (dalloc(&scratch, (size_t)nrhs * c->g.nif)) return fail(HBJ_ENOMEM, "tuning workspace allocation failed");
+      SolveIO tio = io;
+      tio.tr_dst = scratch;
+      tio.tr_base = nullptr;
+      int best = 0;
+      float best_ms = 1e30f;
+      hipError_t he = hipSuccess;
+      for (int v = 0; v < kMmVariants && he == hipSuccess; ++v) {
+        he = launch(v, tio);  // warm-up
+        if (he == hipSuccess) he = hipEventRecord(c->ev0, c->st);
+        for (int rep = 0; rep < 3 && he == hipSuccess; ++rep) he = launch(v, tio);
+        if (he == hipSuccess) he = hipEventRecord(c->ev1, c->st);
+        if (he == hipSuccess) he = hipEventSynchronize(c->ev1);
+        float ms = 0.f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&ms, c->ev0, c->ev1);
+        c->mm_us[slot][v] = ms / 3.0f * 1e3f;
+        if (he == hipSuccess && ms < best_ms) {
+          best_ms = ms;
+          best = v;
+        }
+      }
+      (void)hipStreamSynchronize(c->st);
+      dfree(scratch);
+      if (he != hipSuccess) return fail(HBJ_EHIP, hipGetErrorString(he));
+      c->mm_variant[slot] = best;
+    }
+    ProfScope ps(c, mask == 0xF ? HBJ_K_OPERATOR : HBJ_K_SCATTER, tbytes, elems * 8.0);
+    HIPCHK(launch(c->mm_variant[slot], io));
     return HBJ_OK;
   }
   const int li = mask == kMaskFwd ? 0 : mask == kMaskBwd ? 1 : 2;
@@ -1829,6 +1865,16 @@ int hbj_set_sweep_wait(hbj_ctx* c, int32_t max_polls, int32_t stall_task) {
   if (!c) return fail(HBJ_EINVAL, "null context");
   c->df_spin = max_polls > 0 ? max_polls : kDfSpinDefault;
   c->df_stall = stall_task >= 0 ? stall_task : -1;
+  return HBJ_OK;
+}
+
+int hbj_get_tuning(const hbj_ctx* c, int32_t* variants, float* us) {
+  if (!c || !variants) return fail(HBJ_EINVAL, "bad arguments");
+  for (int i = 0; i < 4; ++i) {
+    variants[i] = c->mm_variant[i];
+    if (us)
+      for (int v = 0; v < kMmVariants; ++v) us[i * kMmVariants + v] = c->mm_us[i][v];
+  }
   return HBJ_OK;
 }
 

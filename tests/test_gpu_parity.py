@@ -268,6 +268,11 @@ def test_dense_operators_many_rhs(ctxs, name, kw):
     for k in range(nr):
         assert rel(w[k], dd.apply_operator(gv[k])) < 1e-12
         assert rel(z[k], sweep.apply_bj(dd, gv[k])) < tol_pc
+    # the autotuner timed every tile depth on the first launch of each kind and kept one
+    tun = ctx.tuning()
+    used = ("c64" if kw else "c128") + " steps"
+    assert tun[used]["k_steps_per_batch"] in (2, 4, 8)
+    assert all(v > 0 for v in tun[used]["us"].values())
 
 
 def test_dense_solve_many_rhs(ctxs):
