@@ -58,22 +58,33 @@ __global__ __launch_bounds__(kTR * CG) void k_scatter_apply(Geom g, const Entry*
   const int L = local_if_len(g);
   const int r = threadIdx.x % kTR, grp = threadIdx.x / kTR;
   const FaceTab F = ft[e.s];
+  // faces present (a neighbour exists: both the incoming and the outgoing block exist)
+  const int pm = (F.in_off[0] >= 0) | (F.in_off[1] >= 0) << 1 | (F.in_off[2] >= 0) << 2 | (F.in_off[3] >= 0) << 3;
+  const int b1 = g.sny, b2 = 2 * g.sny, b3 = 2 * g.sny + g.snx;  // first rows / columns of faces E, S, N
+  // a row block with nothing to write or pass through (only rows of outer or unmasked faces) is
+  // skipped whole: the faces it spans are f_lo..f_hi
+  {
+    const int r0 = rb * kTR, r1 = min(L, r0 + kTR) - 1;
+    const int f_lo = (r0 >= b1) + (r0 >= b2) + (r0 >= b3), f_hi = (r1 >= b1) + (r1 >= b2) + (r1 >= b3);
+    if ((((e.mask & pm) >> f_lo) & ((2 << (f_hi - f_lo)) - 1)) == 0) return;
+  }
   __shared__ double2 gl[LMAX];
   __shared__ double2 red[NT / 64][kTR];
   // 1. incoming data first (absent faces and padding read as zero): every load is issued,
   //    with in-bounds indices, before any is used
   const size_t cb = (size_t)e.rhs * g.nif;
   const int from_b = e.src ? (~io.in_faces & 0xF) : 0;
+  // position q of face f sits at in_off[f] + (q - first[f]) of the interface vector
+  const int ib0 = F.in_off[0], ib1 = F.in_off[1] - b1, ib2 = F.in_off[2] - b2, ib3 = F.in_off[3] - b3;
   double2 gv[GLP];
 #pragma unroll
   for (int k = 0; k < GLP; ++k) {
     const int q = threadIdx.x + k * NT;
-    int f, ee;
-    local_if_face(g, q < L ? q : 0, &f, &ee);
-    const int o = pick4(F.in_off, f);
-    const bool ok = q < L && o >= 0;
+    const int f = (q >= b1) + (q >= b2) + (q >= b3);
+    const int ib = f == 0 ? ib0 : f == 1 ? ib1 : f == 2 ? ib2 : ib3;
+    const bool ok = q < L && ((pm >> f) & 1);
     const double2* src = ((from_b >> f) & 1) ? io.g_b : io.g_a;
-    gv[k] = src[ok ? cb + o + ee : cb];
+    gv[k] = src[ok ? cb + ib + q : cb];
     if (!ok) gv[k] = mk(0.0, 0.0);
   }
   // the output row of this thread (threads 0-7): its base value and pass-through datum are
@@ -89,11 +100,15 @@ __global__ __launch_bounds__(kTR * CG) void k_scatter_apply(Geom g, const Entry*
   if (cp) cv = io.g_a[cb + io_ + re];
   // 2. the operator rows
   const C* Tb = T + (size_t)e.s * t_per_sub(g) + (size_t)rb * L * kTR + r;
+  // columns of absent faces and past L hold no data (their incoming datum is zero): they load the
+  // block's column 0 instead, one cached line, so every load stays unconditional
   C v[KMAX];
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) {  // clamped column: unconditional loads (its product is zeroed)
+  for (int k = 0; k < KMAX; ++k) {
     const int col = grp + CG * k;
-    v[k] = Tb[(size_t)(col < L ? col : L - 1) * kTR];
+    const int f = (col >= b1) + (col >= b2) + (col >= b3);
+    const bool live = col < L && ((pm >> f) & 1);
+    v[k] = Tb[(size_t)(live ? col : 0) * kTR];
   }
 #pragma unroll
   for (int k = 0; k < GLP; ++k) gl[threadIdx.x + k * NT] = gv[k];
