@@ -266,6 +266,18 @@ int hbj_kernel_stats(hbj_ctx* ctx, int32_t kclass, hbj_kernel_stat* out);
 int hbj_reset_kernel_stats(hbj_ctx* ctx);
 
 /*
+ * hbj_set_graphs - replay GMRES iterations as HIP graphs (default on).  With the
+ * dense operators, stepped sweeps and fewer than 4 right-hand sides, each Arnoldi
+ * step (preconditioner, operator and the Gram-Schmidt kernels: about 22 launches)
+ * is captured once per step index into a graph on a capture stream and replayed
+ * with one launch on the context stream; the results are identical.  Profiling
+ * (hbj_set_profiling) runs the launches one by one.  Captured graphs are dropped
+ * by hbj_factor and with the GMRES workspace (a different restart length or
+ * number of right-hand sides).
+ */
+int hbj_set_graphs(hbj_ctx* ctx, int32_t on);
+
+/*
  * hbj_get_tuning - choices of the autotuner of the many-right-hand-side operator
  * kernel (dense form, 4 or more right-hand sides).  On its first launch of each
  * kind the library times every tile depth (k-steps per batch of loads: 2, 4, 8)

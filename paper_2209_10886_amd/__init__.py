@@ -85,6 +85,7 @@ _SIGS = {
     "hbj_reset_kernel_stats": (_I, [_P]),
     "hbj_set_sweep_wait": (_I, [_P, _I32, _I32]),
     "hbj_get_tuning": (_I, [_P, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)]),
+    "hbj_set_graphs": (_I, [_P, _I32]),
     "hbj_strerror": (ctypes.c_char_p, [_I]),
     "hbj_last_error": (ctypes.c_char_p, []),
     "hbj_destroy": (None, [_P]),
@@ -275,6 +276,10 @@ class Context:
 
     def reset_kernel_stats(self):
         _check(_lib.hbj_reset_kernel_stats(self._h))
+
+    def set_graphs(self, on=True):
+        """Replay GMRES iterations as HIP graphs (default on)."""
+        _check(_lib.hbj_set_graphs(self._h, 1 if on else 0))
 
     def tuning(self):
         """Autotuned tile depths of the many-RHS operator kernel and their measured us per launch."""

@@ -156,11 +156,17 @@ hipError_t launch_scatter_apply(const Geom& g, const Entry* ent, int nent, int m
   if (L > LMAX) return hipErrorInvalidValue;
   const dim3 grid(nrb, nent);
   // with events, the start and stop times are those of the dispatch itself
-  if (L <= 16 * CG)
-    hipExtLaunchKernelGGL((k_scatter_apply<C, 16>), grid, dim3(kTR * CG), 0, st, t0, t1, 0, g, ent, rblist, ft, T, io);
-  else
-    hipExtLaunchKernelGGL((k_scatter_apply<C, LMAX / CG>), grid, dim3(kTR * CG), 0, st, t0, t1, 0, g, ent, rblist, ft,
-                          T, io);
+  if (t0 || t1) {
+    if (L <= 16 * CG)
+      hipExtLaunchKernelGGL((k_scatter_apply<C, 16>), grid, dim3(kTR * CG), 0, st, t0, t1, 0, g, ent, rblist, ft, T, io);
+    else
+      hipExtLaunchKernelGGL((k_scatter_apply<C, LMAX / CG>), grid, dim3(kTR * CG), 0, st, t0, t1, 0, g, ent, rblist,
+                            ft, T, io);
+  } else if (L <= 16 * CG) {
+    hipLaunchKernelGGL((k_scatter_apply<C, 16>), grid, dim3(kTR * CG), 0, st, g, ent, rblist, ft, T, io);
+  } else {
+    hipLaunchKernelGGL((k_scatter_apply<C, LMAX / CG>), grid, dim3(kTR * CG), 0, st, g, ent, rblist, ft, T, io);
+  }
   return hipGetLastError();
 }
 

@@ -89,6 +89,9 @@ hipError_t dalloc(T** p, size_t n) {
   return hipMalloc((void**)p, n * sizeof(T));
 }
 
+struct Gmres;
+void destroy_gmres(Gmres* g);
+
 }  // namespace
 
 struct hbj_ctx {
@@ -158,6 +161,11 @@ struct hbj_ctx {
   double2* pc_y = nullptr;  // preconditioner pass buffers [nrhs][nif]
   double2* pc_t = nullptr;
   size_t pc_cols = 0;
+  // GMRES workspace kept across solves, and the HIP graphs of its iterations
+  Gmres* gm = nullptr;
+  bool use_graphs = true;
+  int graph_epoch = 0;           // bumped when captured operands change (a new factorisation)
+  hipStream_t cap = nullptr;     // capture stream (graphs are replayed on st)
   // profiling
   bool prof = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -177,6 +185,9 @@ void dfree(void* p) {
 }  // namespace
 
 hbj_ctx::~hbj_ctx() {
+  destroy_gmres(gm);
+  gm = nullptr;
+  if (cap) (void)hipStreamDestroy(cap);
   for (auto& kv : sched) {
     dfree(kv.second->dev);
     dfree(kv.second->subs);
@@ -1120,7 +1131,20 @@ struct Gmres {
   double *nrm = nullptr, *npartial = nullptr;
   size_t hbuf_len = 0;
   int nchunk = 0;
+  std::vector<hipGraphExec_t> graphs;  // iteration j of a restart cycle, captured at first use
+  int graph_epoch = -1;
+  double2* hbuf_host = nullptr;        // pinned host copy of h1 | h2 | norms
+  void drop_graphs() {
+    for (auto& ge : graphs)
+      if (ge) (void)hipGraphExecDestroy(ge);
+    graphs.assign(graphs.size(), nullptr);
+  }
+  bool matches(const Schedule* S_, int ncol_, int nif_, int m_, bool flexible_) const {
+    return S == S_ && ncol == ncol_ && nif == nif_ && m == m_ && flexible == flexible_;
+  }
   ~Gmres() {
+    drop_graphs();
+    if (hbuf_host) (void)hipHostFree(hbuf_host);
     for (void* p : {(void*)V, (void*)Z, (void*)w, (void*)b, (void*)x, (void*)r, (void*)zt, (void*)hbuf,
                     (void*)ydev, (void*)partial, (void*)npartial})
       dfree(p);
@@ -1140,6 +1164,9 @@ struct Gmres {
         dalloc(&ydev, (size_t)ncol * (m + 1)) || dalloc(&partial, (size_t)ncol * (m + 1) * nchunk) ||
         dalloc(&npartial, (size_t)ncol * std::max<size_t>(nchunk, nblk)))
       return fail(HBJ_ENOMEM, "GMRES workspace allocation failed");
+    if (hipHostMalloc((void**)&hbuf_host, hbuf_len * sizeof(double2)) != hipSuccess)
+      return fail(HBJ_ENOMEM, "GMRES host buffer allocation failed");
+    graphs.assign(m, nullptr);
     // h1 | h2 | norms in one buffer: one copy to the host per iteration
     h1 = hbuf;
     h2 = hbuf + (size_t)ncol * (m + 1);
@@ -1156,6 +1183,80 @@ struct Gmres {
     return HBJ_OK;
   }
 };
+
+void destroy_gmres(Gmres* g) { delete g; }
+
+// One Arnoldi step for column block j: z = P^{-1} V_j, w = (I - S) z, classical Gram-Schmidt with
+// one reorthogonalisation, V_{j+1} = w / ||w||; h1, h2 and the norm land in G.hbuf.
+int arnoldi_kernels(hbj_ctx* c, Schedule* S, Gmres& G, int j) {
+  const int ncol = G.ncol, nif = G.nif, m = G.m;
+  const size_t vs = G.vs();
+  double2* z = G.flexible ? G.Zi(j) : G.zt;
+  int rc = pc_op(c, S, G.Vi(j), z, G.w, ncol);
+  if (rc) return rc;
+  ProfScope ps(c, HBJ_K_KRYLOV, 4.0 * (j + 1) * vs * 16.0 + 2.0 * vs * 16.0, 16.0 * (j + 1) * vs);
+  if (krylov_fusable(j + 1, G.nchunk, nif)) {
+    // 5 launches: dots, update (+ h1), dots, update (+ h2, |w|^2 partials), norm + scaling
+    HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
+    HIPCHK(launch_update_reduce(G.w, G.V, vs, j + 1, G.partial, G.nchunk, G.h1, m + 1, mk(-1.0, 0.0), nif, ncol,
+                                nullptr, c->st));
+    HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
+    HIPCHK(launch_update_reduce(G.w, G.V, vs, j + 1, G.partial, G.nchunk, G.h2, m + 1, mk(-1.0, 0.0), nif, ncol,
+                                G.npartial, c->st));
+    HIPCHK(launch_scale_reduce(G.Vi(j + 1), G.w, G.npartial, G.nrm, nif, ncol, c->st));
+  } else {
+    HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
+    HIPCHK(launch_reduce_partials(G.partial, j + 1, ncol, G.nchunk, G.h1, m + 1, mk(1.0, 0.0), c->st));
+    HIPCHK(launch_update(G.w, G.V, vs, j + 1, G.h1, m + 1, mk(-1.0, 0.0), nif, ncol, c->st));
+    HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
+    HIPCHK(launch_reduce_partials(G.partial, j + 1, ncol, G.nchunk, G.h2, m + 1, mk(1.0, 0.0), c->st));
+    HIPCHK(launch_update(G.w, G.V, vs, j + 1, G.h2, m + 1, mk(-1.0, 0.0), nif, ncol, c->st));
+    HIPCHK(launch_norms(G.w, nif, ncol, G.npartial, G.nchunk, c->st));
+    HIPCHK(launch_reduce_norms(G.npartial, ncol, G.nchunk, G.nrm, c->st));
+    HIPCHK(launch_scale_by_inv(G.Vi(j + 1), G.w, G.nrm, nif, ncol, c->st));
+  }
+  return HBJ_OK;
+}
+
+// Iterations that are pure kernel launches on fixed buffers (dense operators, stepped sweeps,
+// few right-hand sides: no allocation, tuning or host synchronisation inside) are captured
+// once per step index j and replayed as one graph launch.
+bool graphable(const hbj_ctx* c, const Schedule* S) {
+  return c->use_graphs && !c->prof && c->dense && c->P.sweep_exec == HBJ_SWEEP_STEPPED && S->nrhs < kMatrixRhs;
+}
+
+int arnoldi_step(hbj_ctx* c, Schedule* S, Gmres& G, int j) {
+  if (!graphable(c, S)) return arnoldi_kernels(c, S, G, j);
+  if (G.graph_epoch != c->graph_epoch) {
+    G.drop_graphs();
+    G.graph_epoch = c->graph_epoch;
+  }
+  if (!G.graphs[j]) {
+    if (!c->cap) HIPCHK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+    // the capture stream starts after everything queued so far on the context stream
+    HIPCHK(hipEventRecord(c->ev0, c->st));
+    HIPCHK(hipStreamWaitEvent(c->cap, c->ev0, 0));
+    hipStream_t keep = c->st;
+    c->st = c->cap;
+    hipError_t he = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+    int rc = (he == hipSuccess) ? arnoldi_kernels(c, S, G, j) : HBJ_OK;
+    hipGraph_t gr = nullptr;
+    const hipError_t he2 = (he == hipSuccess) ? hipStreamEndCapture(c->cap, &gr) : he;
+    c->st = keep;
+    if (rc) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    if (he2 != hipSuccess) return fail(HBJ_EHIP, hipGetErrorString(he2));
+    hipGraphExec_t ex = nullptr;
+    he = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (he != hipSuccess) return fail(HBJ_EHIP, hipGetErrorString(he));
+    G.graphs[j] = ex;
+  }
+  HIPCHK(hipGraphLaunch(G.graphs[j], c->st));
+  return HBJ_OK;
+}
 
 void givens(zc a, zc b, double& cs, zc& sn) {
   if (std::abs(b) == 0.0) { cs = 1.0; sn = 0.0; return; }
@@ -1187,7 +1288,7 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
   int total = 0;
   std::vector<zc> H((size_t)ncol * (m + 1) * m), e1((size_t)ncol * (m + 1)), sn((size_t)ncol * m);
   std::vector<double> cs((size_t)ncol * m);
-  std::vector<double2> hh1((size_t)ncol * (m + 1)), hh2((size_t)ncol * (m + 1)), hbuf_host(G.hbuf_len);
+  std::vector<double2> hh1((size_t)ncol * (m + 1)), hh2((size_t)ncol * (m + 1));
   std::vector<double> hn(ncol);
   std::vector<int> jc(ncol);
   std::vector<double2> yh((size_t)ncol * (m + 1));
@@ -1210,38 +1311,13 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
     }
     int j = 0;
     for (; j < m && total < o.maxit; ++j) {
-      double2* z = G.flexible ? G.Zi(j) : G.zt;
-      rc = pc_op(c, S, G.Vi(j), z, G.w, ncol);
+      rc = arnoldi_step(c, S, G, j);
       if (rc) return rc;
-      {
-        ProfScope ps(c, HBJ_K_KRYLOV, 4.0 * (j + 1) * vs * 16.0 + 2.0 * vs * 16.0, 16.0 * (j + 1) * vs);
-        // classical Gram-Schmidt with one reorthogonalisation
-        if (krylov_fusable(j + 1, G.nchunk, nif)) {
-          // 5 launches: dots, update (+ h1), dots, update (+ h2, |w|^2 partials), norm + scaling
-          HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
-          HIPCHK(launch_update_reduce(G.w, G.V, vs, j + 1, G.partial, G.nchunk, G.h1, m + 1, mk(-1.0, 0.0), nif,
-                                      ncol, nullptr, c->st));
-          HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
-          HIPCHK(launch_update_reduce(G.w, G.V, vs, j + 1, G.partial, G.nchunk, G.h2, m + 1, mk(-1.0, 0.0), nif,
-                                      ncol, G.npartial, c->st));
-          HIPCHK(launch_scale_reduce(G.Vi(j + 1), G.w, G.npartial, G.nrm, nif, ncol, c->st));
-        } else {
-          HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
-          HIPCHK(launch_reduce_partials(G.partial, j + 1, ncol, G.nchunk, G.h1, m + 1, mk(1.0, 0.0), c->st));
-          HIPCHK(launch_update(G.w, G.V, vs, j + 1, G.h1, m + 1, mk(-1.0, 0.0), nif, ncol, c->st));
-          HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
-          HIPCHK(launch_reduce_partials(G.partial, j + 1, ncol, G.nchunk, G.h2, m + 1, mk(1.0, 0.0), c->st));
-          HIPCHK(launch_update(G.w, G.V, vs, j + 1, G.h2, m + 1, mk(-1.0, 0.0), nif, ncol, c->st));
-          HIPCHK(launch_norms(G.w, nif, ncol, G.npartial, G.nchunk, c->st));
-          HIPCHK(launch_reduce_norms(G.npartial, ncol, G.nchunk, G.nrm, c->st));
-          HIPCHK(launch_scale_by_inv(G.Vi(j + 1), G.w, G.nrm, nif, ncol, c->st));
-        }
-      }
-      HIPCHK(hipMemcpyAsync(hbuf_host.data(), G.hbuf, G.hbuf_len * sizeof(double2), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipMemcpyAsync(G.hbuf_host, G.hbuf, G.hbuf_len * sizeof(double2), hipMemcpyDeviceToHost, c->st));
       HIPCHK(hipStreamSynchronize(c->st));
-      std::copy(hbuf_host.begin(), hbuf_host.begin() + hh1.size(), hh1.begin());
-      std::copy(hbuf_host.begin() + hh1.size(), hbuf_host.begin() + 2 * hh1.size(), hh2.begin());
-      std::memcpy(hn.data(), hbuf_host.data() + 2 * hh1.size(), ncol * sizeof(double));
+      std::copy(G.hbuf_host, G.hbuf_host + hh1.size(), hh1.begin());
+      std::copy(G.hbuf_host + hh1.size(), G.hbuf_host + 2 * hh1.size(), hh2.begin());
+      std::memcpy(hn.data(), G.hbuf_host + 2 * hh1.size(), ncol * sizeof(double));
       ++total;
       bool any_active = false;
       for (int k = 0; k < ncol; ++k) {
@@ -1541,6 +1617,7 @@ static int build_dense(hbj_ctx* c) {
 
 int hbj_factor(hbj_ctx* c) {
   if (!c) return fail(HBJ_EINVAL, "null context");
+  c->graph_epoch++;  // captured iterations refer to the operators being rebuilt
   const Geom& g = c->g;
   const SolveLayout& L = c->L;
   const size_t nband = (size_t)c->ndom * g.nloc * g.ldab;
@@ -1664,14 +1741,24 @@ static int solve_impl(hbj_ctx* c, const double2* f, double2* u, int nrhs, const 
     conv.assign(nrhs, 1);
     hist.assign(1, 0.0);
   } else {
-    Gmres G;
-    G.c = c;
-    G.S = S;
-    G.ncol = nrhs;
-    G.nif = c->g.nif;
-    G.m = o.restart;
-    G.flexible = o.flexible != 0;
-    rc = G.alloc();
+    if (!c->gm || !c->gm->matches(S, nrhs, c->g.nif, o.restart, o.flexible != 0)) {
+      destroy_gmres(c->gm);
+      c->gm = new Gmres();
+      c->gm->c = c;
+      c->gm->S = S;
+      c->gm->ncol = nrhs;
+      c->gm->nif = c->g.nif;
+      c->gm->m = o.restart;
+      c->gm->flexible = o.flexible != 0;
+      rc = c->gm->alloc();
+      if (rc) {
+        destroy_gmres(c->gm);
+        c->gm = nullptr;
+        return rc;
+      }
+    }
+    Gmres& G = *c->gm;
+    rc = ensure_pc(c, nrhs);  // every buffer an iteration uses exists before any capture
     if (rc) return rc;
     rc = run_lifting(c, S, f, G.b, nrhs);
     if (rc) return rc;
@@ -1865,6 +1952,12 @@ int hbj_set_sweep_wait(hbj_ctx* c, int32_t max_polls, int32_t stall_task) {
   if (!c) return fail(HBJ_EINVAL, "null context");
   c->df_spin = max_polls > 0 ? max_polls : kDfSpinDefault;
   c->df_stall = stall_task >= 0 ? stall_task : -1;
+  return HBJ_OK;
+}
+
+int hbj_set_graphs(hbj_ctx* c, int32_t on) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  c->use_graphs = on != 0;
   return HBJ_OK;
 }
 
