@@ -1133,7 +1133,9 @@ struct Gmres {
   int nchunk = 0;
   std::vector<hipGraphExec_t> graphs;  // iteration j of a restart cycle, captured at first use
   int graph_epoch = -1;
-  double2* hbuf_host = nullptr;        // pinned host copy of h1 | h2 | norms
+  double2* hbuf_host = nullptr;        // pinned host copies of h1 | h2 | norms, two slots
+  hipEvent_t ev_h[2] = {nullptr, nullptr};
+  double2* slot(int j) { return hbuf_host + (size_t)(j & 1) * hbuf_len; }
   void drop_graphs() {
     for (auto& ge : graphs)
       if (ge) (void)hipGraphExecDestroy(ge);
@@ -1144,6 +1146,8 @@ struct Gmres {
   }
   ~Gmres() {
     drop_graphs();
+    for (auto& e : ev_h)
+      if (e) (void)hipEventDestroy(e);
     if (hbuf_host) (void)hipHostFree(hbuf_host);
     for (void* p : {(void*)V, (void*)Z, (void*)w, (void*)b, (void*)x, (void*)r, (void*)zt, (void*)hbuf,
                     (void*)ydev, (void*)partial, (void*)npartial})
@@ -1164,8 +1168,11 @@ struct Gmres {
         dalloc(&ydev, (size_t)ncol * (m + 1)) || dalloc(&partial, (size_t)ncol * (m + 1) * nchunk) ||
         dalloc(&npartial, (size_t)ncol * std::max<size_t>(nchunk, nblk)))
       return fail(HBJ_ENOMEM, "GMRES workspace allocation failed");
-    if (hipHostMalloc((void**)&hbuf_host, hbuf_len * sizeof(double2)) != hipSuccess)
+    if (hipHostMalloc((void**)&hbuf_host, 2 * hbuf_len * sizeof(double2)) != hipSuccess)
       return fail(HBJ_ENOMEM, "GMRES host buffer allocation failed");
+    for (auto& e : ev_h)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+        return fail(HBJ_EHIP, "event creation failed");
     graphs.assign(m, nullptr);
     // h1 | h2 | norms in one buffer: one copy to the host per iteration
     h1 = hbuf;
@@ -1309,15 +1316,31 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
       std::fill(&e1[(size_t)k * (m + 1)], &e1[(size_t)k * (m + 1)] + m + 1, zc(0.0));
       e1[(size_t)k * (m + 1)] = rnorm[k];
     }
+    // Step j + 1 is queued before the host reads step j back: it needs only V_{j+1}, already on
+    // the device, so the GPU never waits for the host's Givens rotations. When the host finds
+    // that every column has converged at step j, the queued step's results are simply unused.
+    auto launch_step = [&](int jj) -> int {
+      int r2 = arnoldi_step(c, S, G, jj);
+      if (r2) return r2;
+      HIPCHK(hipMemcpyAsync(G.slot(jj), G.hbuf, G.hbuf_len * sizeof(double2), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(hipEventRecord(G.ev_h[jj & 1], c->st));
+      return HBJ_OK;
+    };
     int j = 0;
-    for (; j < m && total < o.maxit; ++j) {
-      rc = arnoldi_step(c, S, G, j);
+    if (m > 0 && total < o.maxit) {
+      rc = launch_step(0);
       if (rc) return rc;
-      HIPCHK(hipMemcpyAsync(G.hbuf_host, G.hbuf, G.hbuf_len * sizeof(double2), hipMemcpyDeviceToHost, c->st));
-      HIPCHK(hipStreamSynchronize(c->st));
-      std::copy(G.hbuf_host, G.hbuf_host + hh1.size(), hh1.begin());
-      std::copy(G.hbuf_host + hh1.size(), G.hbuf_host + 2 * hh1.size(), hh2.begin());
-      std::memcpy(hn.data(), G.hbuf_host + 2 * hh1.size(), ncol * sizeof(double));
+    }
+    for (; j < m && total < o.maxit; ++j) {
+      if (j + 1 < m && total + 1 < o.maxit) {
+        rc = launch_step(j + 1);
+        if (rc) return rc;
+      }
+      HIPCHK(hipEventSynchronize(G.ev_h[j & 1]));
+      const double2* hs = G.slot(j);
+      std::copy(hs, hs + hh1.size(), hh1.begin());
+      std::copy(hs + hh1.size(), hs + 2 * hh1.size(), hh2.begin());
+      std::memcpy(hn.data(), hs + 2 * hh1.size(), ncol * sizeof(double));
       ++total;
       bool any_active = false;
       for (int k = 0; k < ncol; ++k) {
