@@ -129,6 +129,8 @@ struct SolveIO {
   // mask (a pass then needs no pre-filled output)
   int in_faces;
   int copy;
+  // with nz: entries without a source write nothing at all (their field is rebuilt elsewhere)
+  int nz_skip_out;
 };
 
 // Local interface positions of a subdomain: faces W, E, S, N in this order, each with
@@ -267,6 +269,10 @@ hipError_t launch_build_W(const Geom& g, const Entry* ent, int nent, const FaceT
 int lift_chunks(const Geom& g, int pchunk);
 hipError_t launch_lift_dense(const Geom& g, const FaceTab* ft, const double2* W, const double2* f, const int32_t* nz,
                              int nrhs, int pchunk, double2* part, double2* b, hipStream_t st);
+// many right-hand sides: the same transmission part as one complex matrix product per
+// subdomain on MFMA (Gbuf: ndom * L * round16(nrhs) entries of workspace)
+hipError_t launch_recon_mm(const Geom& g, const IfCoef* coef, const FaceTab* ft, const double2* W, const double2* gin,
+                           const int32_t* nz, int nrhs, double2* Gbuf, double2* u, hipStream_t st);
 // u += A_s^{-1} B_s g through W (u is read only where nz marks a source: it then holds
 // A_s^{-1} f_s; elsewhere it is overwritten)
 hipError_t launch_recon_dense(const Geom& g, const FaceTab* ft, const IfCoef* coef, const double2* W,

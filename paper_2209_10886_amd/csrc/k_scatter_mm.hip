@@ -15,10 +15,12 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 // G[j][col][r] = incoming datum of subdomain subs[j] at local interface position col, column r
+// With coef, every datum is scaled by -inj / sigma of its position: the incoming data in the
+// form the lifting matrices W_s take for the reconstruction (x_col = W_s[.][col] (-inj / sigma)).
 __global__ void k_gather_incoming(Geom g, const int32_t* subs, const FaceTab* ft, const double2* gin, int nrhs,
-                                  int rpad, double2* G) {
+                                  int rpad, double2* G, const IfCoef* coef) {
   const int j = blockIdx.y;
-  const int s = subs[j];
+  const int s = subs ? subs[j] : j;
   const FaceTab F = ft[s];
   const int L = local_if_len(g);
   const size_t n = (size_t)L * rpad;
@@ -26,8 +28,16 @@ __global__ void k_gather_incoming(Geom g, const int32_t* subs, const FaceTab* ft
     const int col = (int)(t / rpad), r = (int)(t % rpad);
     int f, ee;
     local_if_face(g, col, &f, &ee);
+    const int io = pick4(F.in_off, f);
     double2 v = mk(0.0, 0.0);
-    if (r < nrhs && F.in_off[f] >= 0) v = gin[(size_t)r * g.nif + F.in_off[f] + ee];
+    if (r < nrhs && io >= 0) {
+      v = gin[(size_t)r * g.nif + io + ee];
+      if (coef) {
+        const IfCoef c = coef[io + ee];
+        double2 sc = cdiv(c.inj, c.sigma);
+        v = cmul(mk(-sc.x, -sc.y), v);
+      }
+    }
     G[(size_t)j * n + t] = v;
   }
 }
@@ -78,7 +88,12 @@ __global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2)))
   const M amask = mrow >= 0 ? (M)1 : (M)0;
   const int rb0 = blockIdx.z * 16 * TB;
   const C* Ts = T + (size_t)s * t_per_sub(g) + t_index(L, mrow < 0 ? 0 : mrow, 0);
-  const double2* Gs = G + (size_t)j * L * rpad + rb0 + i;
+  // right-hand-side columns of this lane's B operands, clamped into the padded width (with fewer
+  // than 64 right-hand sides the upper blocks of the tile do not exist; their results are dropped)
+  const double2* Gs = G + (size_t)j * L * rpad;
+  int jr[TB];
+#pragma unroll
+  for (int t = 0; t < TB; ++t) jr[t] = min(rb0 + 16 * t + i, rpad - 1);
   V4 cr[TB], ci[TB];
 #pragma unroll
   for (int t = 0; t < TB; ++t) {
@@ -100,7 +115,7 @@ __global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2)))
         const int cc = col < c1 ? col : c1 - 1;
         tv[b] = Ts[(size_t)cc * kTR];
 #pragma unroll
-        for (int t = 0; t < TB; ++t) gv[b][t] = Gs[(size_t)cc * rpad + 16 * t];
+        for (int t = 0; t < TB; ++t) gv[b][t] = Gs[(size_t)cc * rpad + jr[t]];
       }
       __builtin_amdgcn_sched_barrier(0);  // keep the whole batch of loads ahead of the MFMAs
 #pragma unroll
@@ -152,14 +167,100 @@ __global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2)))
   }
 }
 
+// Reconstruction for many right-hand sides on MFMA (complex128 on f64 16x16x4):
+//   U_s[p][r] = sum_col W_s[p][col] Gs[col][r]   (Gs: incoming data scaled by -inj / sigma)
+// and u[r] at node p of subdomain s = (nz ? u : 0) + U_s[p][r].  Workgroup = 4 wavefronts, each a
+// 16-node x 64-RHS tile (4 blocks of 16 RHS) over the whole k range; the loads of KB k-steps are
+// issued (clamped, unconditional) before their MFMAs.
+template <int KB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_recon_mm(
+    Geom g, const double2* __restrict__ W, const double2* __restrict__ Gs, int nrhs, int rpad, const int32_t* nz,
+    double2* u) {
+  typedef MfmaAcc<double> A;
+  typedef A::T V4;
+  const int s = blockIdx.y;
+  const int L = local_if_len(g);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, k = lane >> 4;
+  const int p0 = (blockIdx.x * 4 + w) * 16;
+  const int prow = min(p0 + i, g.nloc - 1);  // this lane's A row (clamped; tail rows are not stored)
+  const int rb0 = blockIdx.z * 16 * TB;
+  const double2* Wr = W + ((size_t)s * g.nloc + prow) * L;
+  const double2* Gr = Gs + (size_t)s * L * rpad;
+  int jr[TB];  // right-hand-side columns clamped into the padded width (see k_scatter_mm)
+#pragma unroll
+  for (int t = 0; t < TB; ++t) jr[t] = min(rb0 + 16 * t + i, rpad - 1);
+  V4 cr[TB], ci[TB];
+#pragma unroll
+  for (int t = 0; t < TB; ++t) {
+    cr[t] = V4{0, 0, 0, 0};
+    ci[t] = V4{0, 0, 0, 0};
+  }
+  for (int c = 0; c < L; c += 4 * KB) {
+    double2 av[KB], bv[KB][TB];
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      const int col = c + 4 * b + k;
+      const int cc = col < L ? col : L - 1;
+      av[b] = Wr[cc];
+#pragma unroll
+      for (int t = 0; t < TB; ++t) bv[b][t] = Gr[(size_t)cc * rpad + jr[t]];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      const double ok = (c + 4 * b + k < L) ? 1.0 : 0.0;
+      const double ar = av[b].x * ok, ai = av[b].y * ok;
+#pragma unroll
+      for (int t = 0; t < TB; ++t) {
+        cr[t] = A::mma(ar, bv[b][t].x, cr[t]);
+        ci[t] = A::mma(ar, bv[b][t].y, ci[t]);
+        cr[t] = A::mma(-ai, bv[b][t].y, cr[t]);
+        ci[t] = A::mma(ai, bv[b][t].x, ci[t]);
+      }
+    }
+  }
+  const int ndom = g.n1 * g.n2;
+  const int x0 = (s % g.n1) * g.snx, y0 = (s / g.n1) * g.sny;
+#pragma unroll
+  for (int t = 0; t < TB; ++t)
+#pragma unroll
+    for (int reg = 0; reg < 4; ++reg) {
+      const int p = p0 + A::row_of(lane, reg), r = rb0 + 16 * t + (lane & 15);
+      if (p >= g.nloc || r >= nrhs) continue;
+      const int ly = p / g.snx, lx = p - ly * g.snx;
+      double2* up = u + (size_t)r * g.nx * g.ny + (size_t)(y0 + ly) * g.nx + x0 + lx;
+      double2 b = nz[(size_t)r * ndom + s] ? *up : mk(0.0, 0.0);
+      b.x += cr[t][reg];
+      b.y += ci[t][reg];
+      *up = b;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_recon_mm(const Geom& g, const IfCoef* coef, const FaceTab* ft, const double2* W, const double2* gin,
+                           const int32_t* nz, int nrhs, double2* Gbuf, double2* u, hipStream_t st) {
+  const int rpad = (nrhs + 15) / 16 * 16;
+  const int ndom = g.n1 * g.n2;
+  const size_t n = (size_t)local_if_len(g) * rpad;
+  const int bx = (int)std::min<size_t>(64, (n + 255) / 256);
+  hipLaunchKernelGGL(k_gather_incoming, dim3(bx, ndom), dim3(256), 0, st, g, (const int32_t*)nullptr, ft, gin, nrhs,
+                     rpad, Gbuf, coef);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 grid((g.nloc + 63) / 64, ndom, (nrhs + 16 * TB - 1) / (16 * TB));
+  hipLaunchKernelGGL((k_recon_mm<4>), grid, dim3(256), 0, st, g, W, Gbuf, nrhs, rpad, nz, u);
+  return hipGetLastError();
+}
 
 hipError_t launch_gather_incoming(const Geom& g, const int32_t* subs, int nsub, const FaceTab* ft, const double2* gin,
                                   int nrhs, int rpad, double2* G, hipStream_t st) {
   if (nsub == 0) return hipSuccess;
   const size_t n = (size_t)local_if_len(g) * rpad;
   const int bx = (int)std::min<size_t>(64, (n + 255) / 256);
-  hipLaunchKernelGGL(k_gather_incoming, dim3(bx, nsub), dim3(256), 0, st, g, subs, ft, gin, nrhs, rpad, G);
+  hipLaunchKernelGGL(k_gather_incoming, dim3(bx, nsub), dim3(256), 0, st, g, subs, ft, gin, nrhs, rpad, G,
+                     (const IfCoef*)nullptr);
   return hipGetLastError();
 }
 

@@ -251,6 +251,7 @@ __global__ __launch_bounds__(576) void k_bwd(Geom g, SolveLayout L, const Entry*
   const double2* gin = e.src ? io.g_b : io.g_a;
   if (gin) gin += (size_t)e.rhs * g.nif;
   if (io.nz && !io.nz[(size_t)e.rhs * g.n1 * g.n2 + e.s]) {  // zero right-hand side: x = 0
+    if (io.nz_skip_out) return;
     if (io.u || io.x64)
       for (int l = threadIdx.x; l < g.nloc; l += blockDim.x) emit_field(g, e, io, blockIdx.x, l, mk(0.0, 0.0));
     if (io.tr_dst) {

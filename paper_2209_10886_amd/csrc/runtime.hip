@@ -857,6 +857,7 @@ int fork_source_part(hbj_ctx* c, Schedule* S, const double2* f, double2* u) {
   SolveIO io{};
   io.f = f;
   io.nz = c->nzf;
+  io.nz_skip_out = 1;
   io.u = u;
   int rc = run_solves_side(c, S->dev + S->all_first, S->all_count, io);
   if (rc) return rc;
@@ -869,7 +870,7 @@ int fork_source_part(hbj_ctx* c, Schedule* S, const double2* f, double2* u) {
 // the lifting matrices per subdomain; banded form: one local solve per subdomain.
 int run_reconstruct(hbj_ctx* c, Schedule* S, const double2* f, const double2* g, double2* u, int nrhs,
                     bool source_done) {
-  if (dense_lift(c, nrhs) && c->g.nif > 0 && g) {
+  if (c->Wl && c->g.nif > 0 && g) {
     if (source_done) {
       HIPCHK(hipStreamWaitEvent(c->st, c->ev_join, 0));
     } else {
@@ -885,13 +886,29 @@ int run_reconstruct(hbj_ctx* c, Schedule* S, const double2* f, const double2* g,
       SolveIO io{};
       io.f = f;
       io.nz = c->nzf;
+      io.nz_skip_out = 1;
       io.u = u;
       int rc = run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
       if (rc) return rc;
     }
-    const double elems = (double)nrhs * c->ndom * c->g.nloc * local_if_len(c->g);
-    ProfScope ps(c, HBJ_K_LIFT, elems * 16.0, elems * 8.0);
-    HIPCHK(launch_recon_dense(c->g, c->ft, c->coef, c->Wl, g, c->nzf, nrhs, u, c->st));
+    const double elems = (double)c->ndom * c->g.nloc * local_if_len(c->g);
+    if (nrhs < kMatrixRhs) {
+      ProfScope ps(c, HBJ_K_LIFT, nrhs * elems * 16.0, nrhs * elems * 8.0);
+      HIPCHK(launch_recon_dense(c->g, c->ft, c->coef, c->Wl, g, c->nzf, nrhs, u, c->st));
+      return HBJ_OK;
+    }
+    // many right-hand sides: W_s is read once per subdomain for all of them (MFMA products)
+    const int rpad = (nrhs + 15) / 16 * 16;
+    const size_t need = (size_t)c->ndom * local_if_len(c->g) * rpad;
+    if (need > c->Gbuf_cap) {
+      dfree(c->Gbuf);
+      c->Gbuf = nullptr;
+      c->Gbuf_cap = 0;
+      if (dalloc(&c->Gbuf, need)) return fail(HBJ_ENOMEM, "reconstruction workspace allocation failed");
+      c->Gbuf_cap = need;
+    }
+    ProfScope ps(c, HBJ_K_LIFT, elems * 16.0, nrhs * elems * 8.0);
+    HIPCHK(launch_recon_mm(c->g, c->coef, c->ft, c->Wl, g, c->nzf, nrhs, c->Gbuf, u, c->st));
     return HBJ_OK;
   }
   SolveIO io{};
@@ -1785,7 +1802,7 @@ static int solve_impl(hbj_ctx* c, const double2* f, double2* u, int nrhs, const 
     if (rc) return rc;
     rc = run_lifting(c, S, f, G.b, nrhs);
     if (rc) return rc;
-    const bool forked = dense_lift(c, nrhs);
+    const bool forked = c->Wl != nullptr;
     if (forked) {
       rc = fork_source_part(c, S, f, u);
       if (rc) return rc;

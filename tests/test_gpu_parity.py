@@ -215,6 +215,13 @@ def test_reconstruct(ctxs, name, form):
     u = _to_np(ctx.reconstruct(torch.as_tensor(f, device="cuda"), torch.as_tensor(gv, device="cuda")))
     for k in range(3):
         assert rel(u[k], dd.reconstruct(f[k], gv[k])) < 1e-12
+    if form == 1:
+        # five columns: the transmission part as MFMA products (one read of W_s for all columns)
+        f5 = np.concatenate([f, f[:2] * (1 + 1j)])
+        g5 = W.random_interface_vector(ctx.nif, seed=25, nrhs=5)
+        u5 = _to_np(ctx.reconstruct(torch.as_tensor(f5, device="cuda"), torch.as_tensor(g5, device="cuda")))
+        for k in range(5):
+            assert rel(u5[k], dd.reconstruct(f5[k], g5[k])) < 1e-12
 
 
 @pytest.mark.parametrize("name,kw,okw", [
