@@ -211,12 +211,12 @@ def main():
                hbj.K_SCATTER: "k_scatter_apply<double2,16> (sweep steps)",
                hbj.K_OPERATOR: "k_scatter_apply<double2,16> (operator)",
                hbj.K_SWEEP: "k_sweep_df<double2,16>", hbj.K_LIFT: "k_lift_partial+k_recon_dense",
-               hbj.K_KRYLOV: "krylov (5 launches per iteration)"}
+               hbj.K_KRYLOV: "krylov (Gram-Schmidt kernels of one iteration)"}
     names32 = {hbj.K_FWD: "k_fwd<float,16,4,8>", hbj.K_BWD: "k_bwd<float,16,2,4>",
                hbj.K_SCATTER: "k_scatter_apply<float2,16> (sweep steps)",
                hbj.K_OPERATOR: "k_scatter_apply<double2,16> (operator)",
                hbj.K_SWEEP: "k_sweep_df", hbj.K_LIFT: "k_lift_partial+k_recon_dense",
-               hbj.K_KRYLOV: "krylov (5 launches per iteration)"}
+               hbj.K_KRYLOV: "krylov (Gram-Schmidt kernels of one iteration)"}
 
     log(f"[bench] {'FP64' if headline_prec == hbj.FP64 else 'mixed'}, dense scattering operators (headline), "
         f"{nsrc} right-hand side(s)")
@@ -245,7 +245,7 @@ def main():
         "config": {"workload": wl.name, "grid": [wl.nx, wl.ny], "decomposition": [wl.n1, wl.n2],
                    "subdomain": [wl.sub_nx, wl.sub_ny], "points_per_wavelength": wl.ppw, "k": wl.k,
                    "medium": wl.medium, "sources": nsrc, "tol": args.tol,
-                   "krylov": "GMRES(50), right-preconditioned", "preconditioner": "block Jacobi, width N1",
+                   "krylov": "GMRES(50), right-preconditioned, delayed reorthogonalisation", "preconditioner": "block Jacobi, width N1",
                    "operator_form": "dense local scattering operators (formed at factor time)"},
         "iters": st.iters,
         "relres": st.relres,

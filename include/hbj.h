@@ -278,6 +278,24 @@ int hbj_reset_kernel_stats(hbj_ctx* ctx);
 int hbj_set_graphs(hbj_ctx* ctx, int32_t on);
 
 /*
+ * Gram-Schmidt variant of the Arnoldi steps (the paper leaves the orthogonalisation of
+ * its GMRES open; Sec. 7 uses GMRES(50)).  Both keep the basis orthonormal to working
+ * precision; they differ in passes over the basis per step:
+ *   HBJ_ORTH_CGS2   classical Gram-Schmidt applied twice: two inner-product passes and
+ *                   two update passes (five launches);
+ *   HBJ_ORTH_DCGS2  Gram-Schmidt with delayed reorthogonalisation (Bielich, Langou,
+ *                   Thomas, Swirydowicz, Yamazaki and Boman, Parallel Computing 2022):
+ *                   the second pass for step j's vector is merged into step j + 1, so
+ *                   one inner-product pass and one update pass (two launches); Hessenberg
+ *                   column j is completed one step later, and convergence is tested on a
+ *                   provisional column so that no extra step runs.  Default.
+ * Restart lengths above 255 use HBJ_ORTH_CGS2.  A change drops captured graphs.
+ * Returns HBJ_EINVAL for any other value.
+ */
+enum { HBJ_ORTH_CGS2 = 0, HBJ_ORTH_DCGS2 = 1 };
+int hbj_set_orthogonalization(hbj_ctx* ctx, int32_t mode);
+
+/*
  * hbj_get_tuning - choices of the autotuner of the many-right-hand-side operator
  * kernel (dense form, 4 or more right-hand sides).  On its first launch of each
  * kind the library times every tile depth (k-steps per batch of loads: 2, 4, 8)

@@ -234,6 +234,13 @@ hipError_t launch_update_reduce(double2* w, const double2* V, size_t vstride, in
                                 double* npart, hipStream_t st);
 hipError_t launch_scale_reduce(double2* dst, const double2* src, const double* npart, double* nrm_out, int n, int ncol,
                                hipStream_t st);
+// Gram-Schmidt with delayed reorthogonalisation: one pass of inner products, one update pass
+bool dcgs_fits(int m, int nchunk);
+hipError_t launch_dots2(const double2* V, size_t vstride, int nv, const double2* x, const double2* w, int n, int ncol,
+                        double2* partial, int nchunk, hipStream_t st);
+hipError_t launch_dcgs_update(const double2* V, size_t vstride, int nv, double2* x, double2* xn, const double2* w,
+                              const double2* partial, int nchunk, double2* hout, int ld, int n, int ncol,
+                              bool publish_only, hipStream_t st);
 hipError_t launch_norms(const double2* w, int n, int ncol, double* partial, int nchunk, hipStream_t st);
 hipError_t launch_reduce_norms(const double* partial, int ncol, int nchunk, double* out, hipStream_t st);
 hipError_t launch_scale_by_inv(double2* dst, const double2* src, const double* nrm, int n, int ncol,

@@ -185,6 +185,223 @@ __global__ __launch_bounds__(RT) void k_scale_reduce(double2* dst, const double2
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Gram-Schmidt with delayed reorthogonalisation (Bielich, Langou, Thomas, Swirydowicz, Yamazaki
+// and Boman, 2022): Arnoldi step j receives x, the vector that went through one Gram-Schmidt pass
+// at step j - 1, and w = (I - S) P^{-1} x.  One pass over the finished basis V_0..V_{nv-1}
+// (nv = j) gives every inner product the step needs; one more pass finishes v_j (the second,
+// delayed pass for x, with Pythagoras for its norm) and makes the next x from w.  The basis is
+// read twice per step instead of four times.
+
+// partial[(col * np + i) * nchunk + chunk], np = 2 nv + 3:
+//   i < nv: V_i^H x;  nv + i: V_i^H w;  2 nv: x^H x;  2 nv + 1: x^H w;  2 nv + 2: w^H w.
+// Grid (nchunk, max(1, ceil(nv / VG)), ncol); group 0 also sums the three products of x and w.
+constexpr int VG2 = 8;
+__global__ __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_dots2(
+    const double2* V, size_t vstride, int nv, const double2* x, const double2* w, int n, double2* partial,
+    int nchunk) {
+  const int chunk = blockIdx.x, i0 = blockIdx.y * VG2, col = blockIdx.z;
+  const int len = (n + nchunk - 1) / nchunk;
+  const int q0 = chunk * len, q1 = min(n, q0 + len);
+  const double2* xx = x + (size_t)col * n;
+  const double2* ww = w + (size_t)col * n;
+  const bool g0 = blockIdx.y == 0;
+  double2 aa[VG2], ab[VG2];
+#pragma unroll
+  for (int v = 0; v < VG2; ++v) aa[v] = ab[v] = mk(0.0, 0.0);
+  double sxx = 0.0, sww = 0.0;
+  double2 sxw = mk(0.0, 0.0);
+  constexpr int U = 2;
+  for (int qb = q0; qb < q1; qb += U * RT) {
+    double2 xl[U], wl[U];
+    int qi[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {  // clamped loads; entries past the chunk are zeroed
+      const int q = qb + threadIdx.x + k * RT;
+      qi[k] = q < q1 ? q : q1 - 1;
+      xl[k] = xx[qi[k]];
+      wl[k] = ww[qi[k]];
+      if (q >= q1) xl[k] = wl[k] = mk(0.0, 0.0);
+    }
+    if (nv > 0) {
+      double2 vl[VG2][U];
+#pragma unroll
+      for (int v = 0; v < VG2; ++v) {
+        const double2* vp = V + (size_t)min(i0 + v, nv - 1) * vstride + (size_t)col * n;
+#pragma unroll
+        for (int k = 0; k < U; ++k) vl[v][k] = vp[qi[k]];
+      }
+#pragma unroll
+      for (int v = 0; v < VG2; ++v)
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          cfma_conj(aa[v], vl[v][k], xl[k]);
+          cfma_conj(ab[v], vl[v][k], wl[k]);
+        }
+    }
+    if (g0) {
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        sxx += xl[k].x * xl[k].x + xl[k].y * xl[k].y;
+        sww += wl[k].x * wl[k].x + wl[k].y * wl[k].y;
+        cfma_conj(sxw, xl[k], wl[k]);
+      }
+    }
+  }
+  constexpr int NS = 2 * VG2 + 2;  // a, b, then (xx, ww) and xw
+  __shared__ double2 sh[RT / 64][NS];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double2 vals[NS];
+#pragma unroll
+  for (int v = 0; v < VG2; ++v) {
+    vals[v] = aa[v];
+    vals[VG2 + v] = ab[v];
+  }
+  vals[2 * VG2] = mk(sxx, sww);
+  vals[2 * VG2 + 1] = sxw;
+#pragma unroll
+  for (int v = 0; v < NS; ++v) {
+    double2 a = vals[v];
+    for (int off = 32; off > 0; off >>= 1) {
+      const double2 o = shfl_down2(a, off);
+      a.x += o.x;
+      a.y += o.y;
+    }
+    if (lane == 0) sh[wid][v] = a;
+  }
+  __syncthreads();
+  const int np = 2 * nv + 3;
+  double2* pc = partial + (size_t)col * np * nchunk + chunk;
+  if (threadIdx.x < NS) {
+    double2 t = mk(0.0, 0.0);
+    for (int q = 0; q < RT / 64; ++q) t = cadd(t, sh[q][threadIdx.x]);
+    const int v = threadIdx.x;
+    if (v < VG2) {
+      if (i0 + v < nv) pc[(size_t)(i0 + v) * nchunk] = t;
+    } else if (v < 2 * VG2) {
+      if (i0 + v - VG2 < nv) pc[(size_t)(nv + i0 + v - VG2) * nchunk] = t;
+    } else if (g0 && v == 2 * VG2) {
+      pc[(size_t)(2 * nv) * nchunk] = mk(t.x, 0.0);
+      pc[(size_t)(2 * nv + 2) * nchunk] = mk(t.y, 0.0);
+    } else if (g0) {
+      pc[(size_t)(2 * nv + 1) * nchunk] = t;
+    }
+  }
+}
+
+// Second pass of step j.  Every workgroup adds the partials of its column in chunk order (the same
+// sums everywhere) and forms
+//   a = V^H x,  nu = sqrt(x^H x - |a|^2),  v_j = (x - V a) / nu,
+//   c_i = V_i^H w (i < j),  c_j = v_j^H w = (x^H w - a^H V^H w) / nu,  s = |w|,
+//   x_next = (w - V c - v_j c_j) / s;
+// v_j overwrites x in place and x_next goes to xn.  Workgroup 0 stores, per column, a (nv values)
+// at hout[col * ld], c (nv + 1 values) at hout[(ncol + col) * ld] and (nu, s, |w|^2) as doubles at
+// hout + 2 ncol ld + 2 col, for the host, which completes Hessenberg column j - 1 with them.
+// publish_only: only the coefficients (the last step of a restart cycle, which needs a and nu).
+constexpr int kDcgsMaxV = 256;
+__global__ __launch_bounds__(RT) void k_dcgs_update(const double2* V, size_t vstride, int nv, double2* x,
+                                                    double2* xn, const double2* w, const double2* partial,
+                                                    int nchunk, double2* hout, int ld, int n, int publish_only) {
+  const int col = blockIdx.y, ncol = gridDim.y;
+  __shared__ double2 sp[kFuseMax];
+  __shared__ double2 ca[kDcgsMaxV], cb[kDcgsMaxV];
+  __shared__ double sc[8];
+  __shared__ double2 scj[1];
+  const int np = 2 * nv + 3;
+  const double2* pc = partial + (size_t)col * np * nchunk;
+  const int nt = np * nchunk;  // <= kFuseMax
+  {
+    double2 pv[kFuseMax / RT];
+#pragma unroll
+    for (int k = 0; k < kFuseMax / RT; ++k) {
+      const int t = threadIdx.x + k * RT;
+      pv[k] = pc[t < nt ? t : nt - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < kFuseMax / RT; ++k) sp[threadIdx.x + k * RT] = pv[k];
+  }
+  __syncthreads();
+  const int nv8 = (nv + 7) / 8 * 8;
+  constexpr int kRows = (2 * kDcgsMaxV + 3 + RT - 1) / RT;  // rows of sums per thread
+  double2 tsum[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int i = threadIdx.x + r * RT;
+    tsum[r] = mk(0.0, 0.0);
+    if (i < np)
+      for (int c = 0; c < nchunk; ++c) tsum[r] = cadd(tsum[r], sp[i * nchunk + c]);
+  }
+  __syncthreads();  // sp is reused below for the sums
+#pragma unroll
+  for (int r = 0; r < kRows; ++r)
+    if ((int)threadIdx.x + r * RT < np) sp[threadIdx.x + r * RT] = tsum[r];
+  __syncthreads();
+  for (int i = threadIdx.x; i < nv8; i += RT) {  // zero weights pad the last batch
+    ca[i] = i < nv ? sp[i] : mk(0.0, 0.0);
+    cb[i] = i < nv ? sp[nv + i] : mk(0.0, 0.0);
+  }
+  if (threadIdx.x == 0) {
+    double na = 0.0;
+    double2 ab = mk(0.0, 0.0);
+    for (int i = 0; i < nv; ++i) {
+      const double2 a = sp[i];
+      na += a.x * a.x + a.y * a.y;
+      cfma_conj(ab, a, sp[nv + i]);
+    }
+    const double xx = sp[2 * nv].x, ww = sp[2 * nv + 2].x;
+    const double2 xw = sp[2 * nv + 1];
+    const double nu2 = xx - na;
+    const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+    const double s = ww > 0.0 ? sqrt(ww) : 0.0;
+    sc[0] = nu;
+    sc[1] = s;
+    sc[2] = ww;
+    sc[3] = nu > 0.0 ? 1.0 / nu : 0.0;
+    sc[4] = s > 0.0 ? 1.0 / s : 0.0;
+    scj[0] = nu > 0.0 ? mk((xw.x - ab.x) / nu, (xw.y - ab.y) / nu) : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i <= nv; i += RT) {
+      if (i < nv) hout[(size_t)col * ld + i] = ca[i];
+      hout[((size_t)ncol + col) * ld + i] = i < nv ? cb[i] : scj[0];
+    }
+    if (threadIdx.x == 0) {
+      double* hs = (double*)(hout + 2 * (size_t)ncol * ld) + 4 * (size_t)col;
+      hs[0] = sc[0];
+      hs[1] = sc[1];
+      hs[2] = sc[2];
+      hs[3] = 0.0;
+    }
+  }
+  if (publish_only) return;
+  const int q = blockIdx.x * RT + threadIdx.x;
+  const size_t t = (size_t)col * n + (q < n ? q : n - 1);
+  const double2 xv = x[t], wv = w[t];
+  double2 accA = mk(0.0, 0.0), accB = mk(0.0, 0.0);
+  constexpr int UB = 8;  // basis vectors per batch of loads
+  for (int i0 = 0; i0 < nv8; i0 += UB) {
+    double2 vl[UB];
+#pragma unroll
+    for (int k = 0; k < UB; ++k) vl[k] = V[(size_t)min(i0 + k, nv - 1) * vstride + t];
+#pragma unroll
+    for (int k = 0; k < UB; ++k) {
+      cfma(accA, vl[k], ca[i0 + k]);
+      cfma(accB, vl[k], cb[i0 + k]);
+    }
+  }
+  if (q < n) {
+    const double inu = sc[3], is = sc[4];
+    const double2 v = mk((xv.x - accA.x) * inu, (xv.y - accA.y) * inu);
+    double2 r = mk(wv.x - accB.x, wv.y - accB.y);
+    const double2 cj = scj[0];
+    r.x -= v.x * cj.x - v.y * cj.y;
+    r.y -= v.x * cj.y + v.y * cj.x;
+    x[t] = v;
+    xn[t] = mk(r.x * is, r.y * is);
+  }
+}
+
 __global__ void k_reduce_partials(const double2* partial, int nvec, int ncol, int nchunk, double2* out,
                                   size_t out_stride, double2 scale) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -300,6 +517,26 @@ hipError_t launch_scale_reduce(double2* dst, const double2* src, const double* n
   const int nblk = (n + RT - 1) / RT;
   if (nblk > 1024) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_scale_reduce, dim3(nblk, ncol), dim3(RT), 0, st, dst, src, npart, nblk, nrm_out, n);
+  return hipGetLastError();
+}
+
+bool dcgs_fits(int m, int nchunk) { return m + 1 <= kDcgsMaxV && (2 * m + 3) * nchunk <= kFuseMax; }
+
+hipError_t launch_dots2(const double2* V, size_t vstride, int nv, const double2* x, const double2* w, int n, int ncol,
+                        double2* partial, int nchunk, hipStream_t st) {
+  if (nchunk < 1 || (2 * nv + 3) * nchunk > kFuseMax || nv + 1 > kDcgsMaxV) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dots2, dim3(nchunk, std::max(1, (nv + VG2 - 1) / VG2), ncol), dim3(RT), 0, st, V, vstride, nv, x,
+                     w, n, partial, nchunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_dcgs_update(const double2* V, size_t vstride, int nv, double2* x, double2* xn, const double2* w,
+                              const double2* partial, int nchunk, double2* hout, int ld, int n, int ncol,
+                              bool publish_only, hipStream_t st) {
+  if (nchunk < 1 || (2 * nv + 3) * nchunk > kFuseMax || nv + 1 > kDcgsMaxV || nv + 1 > ld) return hipErrorInvalidValue;
+  const int nblk = publish_only ? 1 : (n + RT - 1) / RT;
+  hipLaunchKernelGGL(k_dcgs_update, dim3(nblk, ncol), dim3(RT), 0, st, V, vstride, nv, x, xn, w, partial, nchunk, hout,
+                     ld, n, publish_only ? 1 : 0);
   return hipGetLastError();
 }
 

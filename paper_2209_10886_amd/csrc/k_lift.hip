@@ -189,6 +189,17 @@ __global__ __launch_bounds__(RT) void k_recon_dense(Geom g, const FaceTab* ft, c
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int x0 = (s % g.n1) * g.snx, y0 = (s / g.n1) * g.sny;
   const double2* Ws = W + (size_t)s * g.nloc * L;
+  // columns of faces on the outer boundary carry no trace (gs = 0 there): their loads are
+  // redirected to column 0 of the same node, a line the wavefront reads anyway, so those
+  // matrix entries cost no memory traffic
+  int cidx[KL];
+#pragma unroll
+  for (int k = 0; k < KL; ++k) {
+    const int col = lane + 64 * k;
+    int f = 0, e = 0;
+    if (col < L) local_if_face(g, col, &f, &e);
+    cidx[k] = (col < L && pick4(F.in_off, f) >= 0) ? col : 0;
+  }
   double2* ur = u + (size_t)r * g.nx * g.ny;
   const int pbase = blockIdx.x * (RT / 64) * PW + wv * PW;
   for (int i0 = 0; i0 < PW; i0 += PB) {
@@ -198,8 +209,7 @@ __global__ __launch_bounds__(RT) void k_recon_dense(Geom g, const FaceTab* ft, c
       const int p = min(pbase + i0 + i, g.nloc - 1);
 #pragma unroll
       for (int k = 0; k < KL; ++k) {
-        const int col = lane + 64 * k;
-        wl[i][k] = Ws[(size_t)p * L + (col < L ? col : L - 1)];
+        wl[i][k] = Ws[(size_t)p * L + cidx[k]];
       }
     }
 #pragma unroll

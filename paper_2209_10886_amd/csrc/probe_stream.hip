@@ -3,8 +3,13 @@
 //  1. streaming reads: G workgroups each read their own contiguous chunk (8 independent 32-byte
 //     loads in flight per thread); prints aggregate and per-workgroup GB/s for G = 1 .. 2048;
 //  2. a plain copy of 1 GiB (the reference kernel whose FETCH_SIZE / WRITE_SIZE counters calibrate
-//     the counter-based traffic figures of the solver kernels).
+//     the counter-based traffic figures of the solver kernels);
+//  3. short launches: one launch reads S bytes (4 .. 212 MB) with G workgroups, timed from the
+//     launch's own start and end events and averaged over 16 launches; "cold" launches each read a
+//     different slice of a 2 GiB buffer (nothing left in the last-level cache), "warm" launches
+//     re-read one slice.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdio>
 
@@ -72,6 +77,41 @@ int main() {
   float ms = 0;
   CHECK(hipEventElapsedTime(&ms, e0, e1));
   std::printf("copy %zu bytes: %.1f GB/s (read + write)\n", copy, 2.0 * copy / (ms * 1e-3) / 1e9);
+  // 3. short launches
+  const double sizes_mb[] = {4.0, 12.5, 25.0, 50.0, 100.0, 212.0};
+  const int wgs[] = {256, 512, 1024, 2048};
+  constexpr int kReps = 16;
+  hipEvent_t s0[kReps], s1[kReps];
+  for (int r = 0; r < kReps; ++r) {
+    CHECK(hipEventCreate(&s0[r]));
+    CHECK(hipEventCreate(&s1[r]));
+  }
+  for (double mb : sizes_mb) {
+    for (int G : wgs) {
+      const size_t per4 = (size_t)(mb * 1e6 / 32.0) / G;  // double4 per workgroup
+      const size_t slice4 = per4 * G;
+      const size_t nslice = (total / 32) / slice4;  // disjoint slices in the 2 GiB buffer
+      if (per4 == 0 || nslice < 2) continue;
+      for (int warm = 0; warm < 2; ++warm) {
+        hipLaunchKernelGGL(k_stream_read, dim3(G), dim3(512), 0, 0, a, per4, o);
+        for (int r = 0; r < kReps; ++r) {
+          const double4* src = a + (warm ? 0 : ((size_t)(r + 1) % nslice) * slice4);
+          hipExtLaunchKernelGGL(k_stream_read, dim3(G), dim3(512), 0, 0, s0[r], s1[r], 0, src, per4, o);
+        }
+        CHECK(hipGetLastError());
+        CHECK(hipDeviceSynchronize());
+        double sum = 0;
+        for (int r = 0; r < kReps; ++r) {
+          float ms = 0;
+          CHECK(hipEventElapsedTime(&ms, s0[r], s1[r]));
+          sum += ms;
+        }
+        const double us = sum / kReps * 1e3;
+        std::printf("short %s S=%6.1f MB G=%5d  %7.2f us  %8.1f GB/s\n", warm ? "warm" : "cold",
+                    slice4 * 32.0 / 1e6, G, us, slice4 * 32.0 / (us * 1e-6) / 1e9);
+      }
+    }
+  }
   CHECK(hipFree(a));
   CHECK(hipFree(b));
   CHECK(hipFree(o));

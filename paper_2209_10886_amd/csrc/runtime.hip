@@ -164,6 +164,7 @@ struct hbj_ctx {
   // GMRES workspace kept across solves, and the HIP graphs of its iterations
   Gmres* gm = nullptr;
   bool use_graphs = true;
+  int orth = HBJ_ORTH_DCGS2;     // Gram-Schmidt variant of the Arnoldi steps
   int graph_epoch = 0;           // bumped when captured operands change (a new factorisation)
   hipStream_t cap = nullptr;     // capture stream (graphs are replayed on st)
   // profiling
@@ -893,7 +894,9 @@ int run_reconstruct(hbj_ctx* c, Schedule* S, const double2* f, const double2* g,
     }
     const double elems = (double)c->ndom * c->g.nloc * local_if_len(c->g);
     if (nrhs < kMatrixRhs) {
-      ProfScope ps(c, HBJ_K_LIFT, nrhs * elems * 16.0, nrhs * elems * 8.0);
+      // only the columns of faces that carry a trace are read: nloc entries per interface entry
+      const double used = (double)c->g.nloc * c->g.nif;
+      ProfScope ps(c, HBJ_K_LIFT, nrhs * used * 16.0, nrhs * used * 8.0);
       HIPCHK(launch_recon_dense(c->g, c->ft, c->coef, c->Wl, g, c->nzf, nrhs, u, c->st));
       return HBJ_OK;
     }
@@ -1147,12 +1150,15 @@ struct Gmres {
   double2 *hbuf = nullptr, *h1 = nullptr, *h2 = nullptr, *ydev = nullptr, *partial = nullptr;
   double *nrm = nullptr, *npartial = nullptr;
   size_t hbuf_len = 0;
-  int nchunk = 0;
+  int nchunk = 0;   // chunks of the inner-product pass (classical Gram-Schmidt twice)
+  int nchunk2 = 0;  // the same for the delayed-reorthogonalisation pass (twice as many products)
   std::vector<hipGraphExec_t> graphs;  // iteration j of a restart cycle, captured at first use
   int graph_epoch = -1;
-  double2* hbuf_host = nullptr;        // pinned host copies of h1 | h2 | norms, two slots
+  double2* hbuf_host = nullptr;        // pinned host h1 | h2 | norms, two slots (step j uses slot j & 1)
+  double2* hbuf_mapped = nullptr;      // the same memory as the kernels address it
   hipEvent_t ev_h[2] = {nullptr, nullptr};
   double2* slot(int j) { return hbuf_host + (size_t)(j & 1) * hbuf_len; }
+  double2* slot_dev(int j) { return hbuf_mapped + (size_t)(j & 1) * hbuf_len; }
   void drop_graphs() {
     for (auto& ge : graphs)
       if (ge) (void)hipGraphExecDestroy(ge);
@@ -1178,15 +1184,23 @@ struct Gmres {
     // every chunk fits one workgroup's registers in the fused dot kernel (256 threads x 4)
     // chunks of about 1024 entries, few enough that the fused update holds all partials
     nchunk = std::max(1, std::min((nif + 1023) / 1024, 2048 / (m + 1)));
-    hbuf_len = 2 * (size_t)ncol * (m + 1) + (ncol + 1) / 2;
+    nchunk2 = std::max(1, std::min((nif + 1023) / 1024, 2048 / (2 * m + 3)));
+    // h1 | h2 | norms (classical Gram-Schmidt twice) or a | c | (nu, s, |w|^2, 0) per column
+    hbuf_len = 2 * (size_t)ncol * (m + 1) + 2 * (size_t)ncol;
+    const size_t npart = std::max((size_t)(m + 1) * nchunk, (size_t)(2 * m + 3) * nchunk2);
     const size_t nblk = ((size_t)nif + 255) / 256;
     if (dalloc(&V, (size_t)(m + 1) * vs()) || (flexible && dalloc(&Z, (size_t)m * vs())) || dalloc(&w, vs()) ||
         dalloc(&b, vs()) || dalloc(&x, vs()) || dalloc(&r, vs()) || dalloc(&zt, vs()) || dalloc(&hbuf, hbuf_len) ||
-        dalloc(&ydev, (size_t)ncol * (m + 1)) || dalloc(&partial, (size_t)ncol * (m + 1) * nchunk) ||
+        dalloc(&ydev, (size_t)ncol * (m + 1)) || dalloc(&partial, (size_t)ncol * npart) ||
         dalloc(&npartial, (size_t)ncol * std::max<size_t>(nchunk, nblk)))
       return fail(HBJ_ENOMEM, "GMRES workspace allocation failed");
-    if (hipHostMalloc((void**)&hbuf_host, 2 * hbuf_len * sizeof(double2)) != hipSuccess)
+    // coherent pinned memory: the Gram-Schmidt kernels store h and the norms straight into it, and
+    // the stores are visible to the host once the step's completion event has fired
+    if (hipHostMalloc((void**)&hbuf_host, 2 * hbuf_len * sizeof(double2), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess)
       return fail(HBJ_ENOMEM, "GMRES host buffer allocation failed");
+    if (hipHostGetDevicePointer((void**)&hbuf_mapped, hbuf_host, 0) != hipSuccess)
+      return fail(HBJ_EHIP, "GMRES host buffer mapping failed");
     for (auto& e : ev_h)
       if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
         return fail(HBJ_EHIP, "event creation failed");
@@ -1210,8 +1224,13 @@ struct Gmres {
 
 void destroy_gmres(Gmres* g) { delete g; }
 
+// Whether step j stores h1 | h2 | norms straight into its pinned host slot (the fused kernels
+// publish them themselves) or into G.hbuf, from where the caller copies them.
+bool h_direct(const Gmres& G, int j) { return krylov_fusable(j + 1, G.nchunk, G.nif); }
+
 // One Arnoldi step for column block j: z = P^{-1} V_j, w = (I - S) z, classical Gram-Schmidt with
-// one reorthogonalisation, V_{j+1} = w / ||w||; h1, h2 and the norm land in G.hbuf.
+// one reorthogonalisation, V_{j+1} = w / ||w||; h1, h2 and the norm land in host slot j & 1
+// (h_direct) or in G.hbuf.
 int arnoldi_kernels(hbj_ctx* c, Schedule* S, Gmres& G, int j) {
   const int ncol = G.ncol, nif = G.nif, m = G.m;
   const size_t vs = G.vs();
@@ -1219,15 +1238,19 @@ int arnoldi_kernels(hbj_ctx* c, Schedule* S, Gmres& G, int j) {
   int rc = pc_op(c, S, G.Vi(j), z, G.w, ncol);
   if (rc) return rc;
   ProfScope ps(c, HBJ_K_KRYLOV, 4.0 * (j + 1) * vs * 16.0 + 2.0 * vs * 16.0, 16.0 * (j + 1) * vs);
-  if (krylov_fusable(j + 1, G.nchunk, nif)) {
+  if (h_direct(G, j)) {
     // 5 launches: dots, update (+ h1), dots, update (+ h2, |w|^2 partials), norm + scaling
+    double2* hs = G.slot_dev(j);
+    double2* h1 = hs;
+    double2* h2 = hs + (size_t)ncol * (m + 1);
+    double* nrm = (double*)(hs + 2 * (size_t)ncol * (m + 1));
     HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
-    HIPCHK(launch_update_reduce(G.w, G.V, vs, j + 1, G.partial, G.nchunk, G.h1, m + 1, mk(-1.0, 0.0), nif, ncol,
+    HIPCHK(launch_update_reduce(G.w, G.V, vs, j + 1, G.partial, G.nchunk, h1, m + 1, mk(-1.0, 0.0), nif, ncol,
                                 nullptr, c->st));
     HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
-    HIPCHK(launch_update_reduce(G.w, G.V, vs, j + 1, G.partial, G.nchunk, G.h2, m + 1, mk(-1.0, 0.0), nif, ncol,
+    HIPCHK(launch_update_reduce(G.w, G.V, vs, j + 1, G.partial, G.nchunk, h2, m + 1, mk(-1.0, 0.0), nif, ncol,
                                 G.npartial, c->st));
-    HIPCHK(launch_scale_reduce(G.Vi(j + 1), G.w, G.npartial, G.nrm, nif, ncol, c->st));
+    HIPCHK(launch_scale_reduce(G.Vi(j + 1), G.w, G.npartial, nrm, nif, ncol, c->st));
   } else {
     HIPCHK(launch_multidot(G.V, vs, j + 1, G.w, nif, ncol, G.partial, G.nchunk, c->st));
     HIPCHK(launch_reduce_partials(G.partial, j + 1, ncol, G.nchunk, G.h1, m + 1, mk(1.0, 0.0), c->st));
@@ -1242,6 +1265,37 @@ int arnoldi_kernels(hbj_ctx* c, Schedule* S, Gmres& G, int j) {
   return HBJ_OK;
 }
 
+// Delayed reorthogonalisation when asked for and when the restart length fits its fused kernels;
+// the choice holds for a whole solve.
+bool use_dcgs(const hbj_ctx* c, const Gmres& G) { return c->orth == HBJ_ORTH_DCGS2 && dcgs_fits(G.m, G.nchunk2); }
+
+// Arnoldi step j with delayed reorthogonalisation: z = P^{-1} x_j (x_j = V_j after one
+// Gram-Schmidt pass), w = (I - S) z, one inner-product pass and one update pass (v_j into V_j,
+// x_{j+1} into V_{j+1}); the coefficients go to host slot j & 1.  finish: the step that closes a
+// restart cycle, which only needs the coefficients of x_j (no preconditioner, operator or update).
+int arnoldi_kernels_dcgs(hbj_ctx* c, Schedule* S, Gmres& G, int j, bool finish) {
+  const int ncol = G.ncol, nif = G.nif, m = G.m;
+  const size_t vs = G.vs();
+  double2* x = G.Vi(j);
+  if (!finish) {
+    double2* z = G.flexible ? G.Zi(j) : G.zt;
+    int rc = pc_op(c, S, x, z, G.w, ncol);
+    if (rc) return rc;
+  }
+  // algorithmic bytes: the inner-product pass reads V_0..V_{j-1}, x and w; the update pass reads
+  // them again and writes v_j and x_{j+1}
+  ProfScope ps(c, HBJ_K_KRYLOV, (finish ? j + 1.0 : 2.0 * j + 6.0) * vs * 16.0, (finish ? 8.0 : 32.0) * j * vs);
+  const double2* w = finish ? x : G.w;
+  HIPCHK(launch_dots2(G.V, vs, j, x, w, nif, ncol, G.partial, G.nchunk2, c->st));
+  HIPCHK(launch_dcgs_update(G.V, vs, j, x, finish ? nullptr : G.Vi(j + 1), w, G.partial, G.nchunk2, G.slot_dev(j),
+                            m + 1, nif, ncol, finish, c->st));
+  return HBJ_OK;
+}
+
+int step_kernels(hbj_ctx* c, Schedule* S, Gmres& G, int j) {
+  return use_dcgs(c, G) ? arnoldi_kernels_dcgs(c, S, G, j, false) : arnoldi_kernels(c, S, G, j);
+}
+
 // Iterations that are pure kernel launches on fixed buffers (dense operators, stepped sweeps,
 // few right-hand sides: no allocation, tuning or host synchronisation inside) are captured
 // once per step index j and replayed as one graph launch.
@@ -1250,7 +1304,7 @@ bool graphable(const hbj_ctx* c, const Schedule* S) {
 }
 
 int arnoldi_step(hbj_ctx* c, Schedule* S, Gmres& G, int j) {
-  if (!graphable(c, S)) return arnoldi_kernels(c, S, G, j);
+  if (!graphable(c, S)) return step_kernels(c, S, G, j);
   if (G.graph_epoch != c->graph_epoch) {
     G.drop_graphs();
     G.graph_epoch = c->graph_epoch;
@@ -1263,7 +1317,7 @@ int arnoldi_step(hbj_ctx* c, Schedule* S, Gmres& G, int j) {
     hipStream_t keep = c->st;
     c->st = c->cap;
     hipError_t he = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
-    int rc = (he == hipSuccess) ? arnoldi_kernels(c, S, G, j) : HBJ_OK;
+    int rc = (he == hipSuccess) ? step_kernels(c, S, G, j) : HBJ_OK;
     hipGraph_t gr = nullptr;
     const hipError_t he2 = (he == hipSuccess) ? hipStreamEndCapture(c->cap, &gr) : he;
     c->st = keep;
@@ -1317,6 +1371,11 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
   std::vector<int> jc(ncol);
   std::vector<double2> yh((size_t)ncol * (m + 1));
   auto Hc = [&](int k, int i, int j) -> zc& { return H[((size_t)k * (m + 1) + i) * m + j]; };
+  const bool dcgs = use_dcgs(c, G);
+  // delayed reorthogonalisation: R (x_j = V R e_j), and c^(j), s_j, |w_j|^2 of the last step
+  std::vector<zc> R(dcgs ? (size_t)ncol * m * m : 0), cprev(dcgs ? (size_t)ncol * (m + 1) : 0);
+  std::vector<double> sprev(ncol), wwprev(ncol);
+  auto Rc = [&](int k, int i, int j) -> zc& { return R[((size_t)k * m + i) * m + j]; };
   while (true) {
     bool any = false;
     for (int k = 0; k < ncol; ++k) any |= !col_conv[k];
@@ -1333,63 +1392,164 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
       std::fill(&e1[(size_t)k * (m + 1)], &e1[(size_t)k * (m + 1)] + m + 1, zc(0.0));
       e1[(size_t)k * (m + 1)] = rnorm[k];
     }
-    // Step j + 1 is queued before the host reads step j back: it needs only V_{j+1}, already on
-    // the device, so the GPU never waits for the host's Givens rotations. When the host finds
-    // that every column has converged at step j, the queued step's results are simply unused.
-    auto launch_step = [&](int jj) -> int {
-      int r2 = arnoldi_step(c, S, G, jj);
-      if (r2) return r2;
-      HIPCHK(hipMemcpyAsync(G.slot(jj), G.hbuf, G.hbuf_len * sizeof(double2), hipMemcpyDeviceToHost, c->st));
-      HIPCHK(hipEventRecord(G.ev_h[jj & 1], c->st));
-      return HBJ_OK;
-    };
-    int j = 0;
-    if (m > 0 && total < o.maxit) {
-      rc = launch_step(0);
-      if (rc) return rc;
-    }
-    for (; j < m && total < o.maxit; ++j) {
-      if (j + 1 < m && total + 1 < o.maxit) {
-        rc = launch_step(j + 1);
+    if (!dcgs) {
+      // Step j + 1 is queued before the host reads step j back: it needs only V_{j+1}, already on
+      // the device, so the GPU never waits for the host's Givens rotations. When the host finds
+      // that every column has converged at step j, the queued step's results are simply unused.
+      auto launch_step = [&](int jj) -> int {
+        int r2 = arnoldi_step(c, S, G, jj);
+        if (r2) return r2;
+        if (!h_direct(G, jj))
+          HIPCHK(hipMemcpyAsync(G.slot(jj), G.hbuf, G.hbuf_len * sizeof(double2), hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipEventRecord(G.ev_h[jj & 1], c->st));
+        return HBJ_OK;
+      };
+      int j = 0;
+      if (m > 0 && total < o.maxit) {
+        rc = launch_step(0);
         if (rc) return rc;
       }
-      HIPCHK(hipEventSynchronize(G.ev_h[j & 1]));
-      const double2* hs = G.slot(j);
-      std::copy(hs, hs + hh1.size(), hh1.begin());
-      std::copy(hs + hh1.size(), hs + 2 * hh1.size(), hh2.begin());
-      std::memcpy(hn.data(), hs + 2 * hh1.size(), ncol * sizeof(double));
-      ++total;
-      bool any_active = false;
-      for (int k = 0; k < ncol; ++k) {
-        if (!active[k]) continue;
-        for (int i = 0; i <= j; ++i) {
-          const double2 a = hh1[(size_t)k * (m + 1) + i], bb = hh2[(size_t)k * (m + 1) + i];
-          Hc(k, i, j) = zc(a.x + bb.x, a.y + bb.y);
+      for (; j < m && total < o.maxit; ++j) {
+        if (j + 1 < m && total + 1 < o.maxit) {
+          rc = launch_step(j + 1);
+          if (rc) return rc;
         }
-        Hc(k, j + 1, j) = hn[k];
-        double* csk = &cs[(size_t)k * m];
-        zc* snk = &sn[(size_t)k * m];
-        for (int i = 0; i < j; ++i) {
-          const zc t = csk[i] * Hc(k, i, j) + snk[i] * Hc(k, i + 1, j);
-          Hc(k, i + 1, j) = -std::conj(snk[i]) * Hc(k, i, j) + csk[i] * Hc(k, i + 1, j);
-          Hc(k, i, j) = t;
+        HIPCHK(hipEventSynchronize(G.ev_h[j & 1]));
+        const double2* hs = G.slot(j);
+        std::copy(hs, hs + hh1.size(), hh1.begin());
+        std::copy(hs + hh1.size(), hs + 2 * hh1.size(), hh2.begin());
+        std::memcpy(hn.data(), hs + 2 * hh1.size(), ncol * sizeof(double));
+        ++total;
+        bool any_active = false;
+        for (int k = 0; k < ncol; ++k) {
+          if (!active[k]) continue;
+          for (int i = 0; i <= j; ++i) {
+            const double2 a = hh1[(size_t)k * (m + 1) + i], bb = hh2[(size_t)k * (m + 1) + i];
+            Hc(k, i, j) = zc(a.x + bb.x, a.y + bb.y);
+          }
+          Hc(k, j + 1, j) = hn[k];
+          double* csk = &cs[(size_t)k * m];
+          zc* snk = &sn[(size_t)k * m];
+          for (int i = 0; i < j; ++i) {
+            const zc t = csk[i] * Hc(k, i, j) + snk[i] * Hc(k, i + 1, j);
+            Hc(k, i + 1, j) = -std::conj(snk[i]) * Hc(k, i, j) + csk[i] * Hc(k, i + 1, j);
+            Hc(k, i, j) = t;
+          }
+          givens(Hc(k, j, j), Hc(k, j + 1, j), csk[j], snk[j]);
+          Hc(k, j, j) = csk[j] * Hc(k, j, j) + snk[j] * Hc(k, j + 1, j);
+          Hc(k, j + 1, j) = 0.0;
+          zc* ek = &e1[(size_t)k * (m + 1)];
+          ek[j + 1] = -std::conj(snk[j]) * ek[j];
+          ek[j] = csk[j] * ek[j];
+          jc[k] = j + 1;
+          col_iters[k] += 1;
+          const double est = std::abs(ek[j + 1]) / bnorm[k];
+          if (k == 0) hist.push_back(est);
+          if (est <= o.tol || hn[k] == 0.0 || std::abs(Hc(k, j, j)) == 0.0) active[k] = 0;
+          any_active |= active[k];
         }
-        givens(Hc(k, j, j), Hc(k, j + 1, j), csk[j], snk[j]);
-        Hc(k, j, j) = csk[j] * Hc(k, j, j) + snk[j] * Hc(k, j + 1, j);
-        Hc(k, j + 1, j) = 0.0;
-        zc* ek = &e1[(size_t)k * (m + 1)];
-        ek[j + 1] = -std::conj(snk[j]) * ek[j];
-        ek[j] = csk[j] * ek[j];
-        jc[k] = j + 1;
-        col_iters[k] += 1;
-        const double est = std::abs(ek[j + 1]) / bnorm[k];
-        if (k == 0) hist.push_back(est);
-        if (est <= o.tol || hn[k] == 0.0 || std::abs(Hc(k, j, j)) == 0.0) active[k] = 0;
-        any_active |= active[k];
+        if (!any_active) {
+          ++j;
+          break;
+        }
       }
-      if (!any_active) {
-        ++j;
-        break;
+    } else {
+      // Delayed reorthogonalisation: step j returns a^(j) = V_{<j}^H x_j and nu_j (x_j =
+      // nu_j v_j + V_{<j} a^(j)) together with c^(j) = V_{<=j}^H w_j and s_j = |w_j|, where
+      // x_{j+1} = (w_j - V_{<=j} c^(j)) / s_j.  Hence (I - S) z_j = w_j = V_{<=j} (c^(j) + s_j a^(j+1))
+      // + s_j nu_{j+1} v_{j+1}: Hessenberg column j is complete once step j + 1 has run.  The
+      // host stops on a provisional column j (its subdiagonal from Pythagoras, without the delayed
+      // correction) and then completes it from step j + 1, which is already queued: no more
+      // steps run than with the undelayed form.
+      const int kmax = std::min(m, o.maxit - total);  // columns of this cycle; step kmax only closes it
+      auto launch_dstep = [&](int jj) -> int {
+        int r2 = (jj < kmax) ? arnoldi_step(c, S, G, jj) : arnoldi_kernels_dcgs(c, S, G, jj, true);
+        if (r2) return r2;
+        HIPCHK(hipEventRecord(G.ev_h[jj & 1], c->st));
+        return HBJ_OK;
+      };
+      rc = launch_dstep(0);
+      if (rc) return rc;
+      bool stop_next = false;
+      std::vector<zc> hp(m + 2);
+      for (int j = 0;; ++j) {
+        if (!stop_next && j + 1 <= kmax) {
+          rc = launch_dstep(j + 1);
+          if (rc) return rc;
+        }
+        HIPCHK(hipEventSynchronize(G.ev_h[j & 1]));
+        const double2* hs = G.slot(j);
+        const double2* ha = hs;
+        const double2* hcv = hs + (size_t)ncol * (m + 1);
+        const double* hsc = (const double*)(hs + 2 * (size_t)ncol * (m + 1));
+        bool any_active = false;
+        for (int k = 0; k < ncol; ++k) {
+          if (!active[k]) continue;
+          const double nu = hsc[4 * k], sj = hsc[4 * k + 1], wwj = hsc[4 * k + 2];
+          const double2* ak = ha + (size_t)k * (m + 1);
+          if (j < kmax) {  // x_j is a search direction: column j of R
+            Rc(k, j, j) = nu;
+            for (int i = 0; i < j; ++i) Rc(k, i, j) = zc(ak[i].x, ak[i].y);
+          }
+          zc* ek = &e1[(size_t)k * (m + 1)];
+          if (j == 0) {
+            ek[0] = rnorm[k] * nu;
+          } else {
+            const int jm = j - 1;  // complete column j - 1
+            for (int i = 0; i < j; ++i) Hc(k, i, jm) = cprev[(size_t)k * (m + 1) + i] + sprev[k] * zc(ak[i].x, ak[i].y);
+            const double hn = sprev[k] * nu;
+            Hc(k, j, jm) = hn;
+            double* csk = &cs[(size_t)k * m];
+            zc* snk = &sn[(size_t)k * m];
+            for (int i = 0; i < jm; ++i) {
+              const zc t = csk[i] * Hc(k, i, jm) + snk[i] * Hc(k, i + 1, jm);
+              Hc(k, i + 1, jm) = -std::conj(snk[i]) * Hc(k, i, jm) + csk[i] * Hc(k, i + 1, jm);
+              Hc(k, i, jm) = t;
+            }
+            givens(Hc(k, jm, jm), Hc(k, j, jm), csk[jm], snk[jm]);
+            Hc(k, jm, jm) = csk[jm] * Hc(k, jm, jm) + snk[jm] * Hc(k, j, jm);
+            Hc(k, j, jm) = 0.0;
+            ek[j] = -std::conj(snk[jm]) * ek[jm];
+            ek[jm] = csk[jm] * ek[jm];
+            jc[k] = j;
+            col_iters[k] += 1;
+            const double est = std::abs(ek[j]) / bnorm[k];
+            if (k == 0) hist.push_back(est);
+            if (est <= o.tol || hn == 0.0 || std::abs(Hc(k, jm, jm)) == 0.0) active[k] = 0;
+          }
+          for (int i = 0; i <= j; ++i) {
+            const double2 cv = hcv[(size_t)k * (m + 1) + i];
+            cprev[(size_t)k * (m + 1) + i] = zc(cv.x, cv.y);
+          }
+          sprev[k] = sj;
+          wwprev[k] = wwj;
+          any_active |= active[k];
+        }
+        if (j >= 1) ++total;
+        if (j == kmax || stop_next || !any_active) break;
+        // provisional column j
+        bool all_done = true;
+        for (int k = 0; k < ncol && all_done; ++k) {
+          if (!active[k]) continue;
+          double cc = 0.0;
+          for (int i = 0; i <= j; ++i) {
+            hp[i] = cprev[(size_t)k * (m + 1) + i];
+            cc += std::norm(hp[i]);
+          }
+          hp[j + 1] = std::sqrt(std::max(wwprev[k] - cc, 0.0));
+          const double* csk = &cs[(size_t)k * m];
+          const zc* snk = &sn[(size_t)k * m];
+          for (int i = 0; i < j; ++i) {
+            const zc t = csk[i] * hp[i] + snk[i] * hp[i + 1];
+            hp[i + 1] = -std::conj(snk[i]) * hp[i] + csk[i] * hp[i + 1];
+            hp[i] = t;
+          }
+          double csp;
+          zc snp;
+          givens(hp[j], hp[j + 1], csp, snp);
+          if (std::abs(snp) * std::abs(e1[(size_t)k * (m + 1) + j]) / bnorm[k] > o.tol) all_done = false;
+        }
+        if (all_done) stop_next = true;
       }
     }
     // y = H^{-1} e1 per column, x += Z y (or P^{-1} V y)
@@ -1404,6 +1564,13 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
         zc acc = ek[i];
         for (int l = i + 1; l < jj; ++l) acc -= Hc(k, i, l) * y[l];
         y[i] = acc / Hc(k, i, i);
+      }
+      if (dcgs && !G.flexible) {
+        // the search directions were x_j = V R e_j: x += P^{-1} V (R y)
+        std::vector<zc> ry(jj, zc(0.0));
+        for (int i = 0; i < jj; ++i)
+          for (int l = i; l < jj; ++l) ry[i] += Rc(k, i, l) * y[l];
+        y.swap(ry);
       }
       for (int i = 0; i < jj; ++i) yh[(size_t)k * (m + 1) + i] = mk(y[i].real(), y[i].imag());
       jmax = std::max(jmax, jj);
@@ -1998,6 +2165,14 @@ int hbj_set_sweep_wait(hbj_ctx* c, int32_t max_polls, int32_t stall_task) {
 int hbj_set_graphs(hbj_ctx* c, int32_t on) {
   if (!c) return fail(HBJ_EINVAL, "null context");
   c->use_graphs = on != 0;
+  return HBJ_OK;
+}
+
+int hbj_set_orthogonalization(hbj_ctx* c, int32_t mode) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  if (mode != HBJ_ORTH_CGS2 && mode != HBJ_ORTH_DCGS2) return fail(HBJ_EINVAL, "unknown orthogonalisation");
+  if (mode != c->orth) ++c->graph_epoch;  // the captured steps hold the other kernels
+  c->orth = mode;
   return HBJ_OK;
 }
 

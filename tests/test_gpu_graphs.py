@@ -20,20 +20,22 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("name,kw,restart", [
-    ("grf256", dict(precond=2), 50),
-    ("grf256", dict(precond=2), 7),            # several restart cycles reuse the captured steps
-    ("grf256", dict(precond=2, precision=1), 50),  # mixed: complex64 preconditioner, FGMRES
-    ("grf256", dict(precond=2, bj_combine=1, bj_compose=1), 50),
-    ("strip", dict(precond=1), 50),
+@pytest.mark.parametrize("name,kw,restart,orth", [
+    ("grf256", dict(precond=2), 50, 1),
+    ("grf256", dict(precond=2), 7, 1),            # several restart cycles reuse the captured steps
+    ("grf256", dict(precond=2), 7, 0),            # classical Gram-Schmidt twice
+    ("grf256", dict(precond=2, precision=1), 50, 1),  # mixed: complex64 preconditioner, FGMRES
+    ("grf256", dict(precond=2, bj_combine=1, bj_compose=1), 50, 1),
+    ("strip", dict(precond=1), 50, 1),
 ])
-def test_graph_replays_match_eager(hbj, name, kw, restart):
+def test_graph_replays_match_eager(hbj, name, kw, restart, orth):
     from oracle import solver
 
     wl = CASES[name].wl
     m, g, dd = oracle_problem(wl)
     ctx = gpu_context(hbj, wl, m, operator_form=hbj.OP_DENSE, **kw)
     ctx.factor()
+    ctx.set_orthogonalization(orth)
     f = torch.as_tensor(W.sources(wl)[0], device="cuda")
     say(f"[graphs] case={name} {kw} restart={restart}: eager")
     ctx.set_graphs(False)
