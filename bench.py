@@ -47,6 +47,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     p.add_argument("--no-banded", action="store_true", help="skip the banded-operator comparison")
+    p.add_argument("--graphs", action="store_true", help="replay the GMRES iterations as HIP graphs")
     p.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle sample")
     return p.parse_args()
 
@@ -115,12 +116,13 @@ def cpu_baseline(wl, m, f, iters_gpu, target_s):
     }
 
 
-def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, profile_names):
+def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, profile_names, graphs=False):
     """Setup + factor (untimed), warmup solves, timed solves, one profiled solve."""
     import torch
 
     ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=mt, precision=precision, precond=hbj.PC_BJ,
                     operator_form=operator_form, device=mt.device)
+    ctx.set_graphs(graphs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.factor()
@@ -221,7 +223,7 @@ def main():
     log(f"[bench] {'FP64' if headline_prec == hbj.FP64 else 'mixed'}, dense scattering operators (headline), "
         f"{nsrc} right-hand side(s)")
     main_run = run_form(hbj, wl, mt, ft, u, headline_prec, hbj.OP_DENSE, args.steps, args.warmup, args.tol,
-                        names64 if headline_prec == hbj.FP64 else names32)
+                        names64 if headline_prec == hbj.FP64 else names32, graphs=args.graphs)
     st = main_run["stats"]
     ms_per_step = main_run["seconds"] / max(args.steps, 1) * 1e3
     log(f"[bench] {ms_per_step:.2f} ms/solve, iters {st.iters}, relres {st.relres:.2e}, "
@@ -268,7 +270,8 @@ def main():
 
     if not args.no_mixed:
         log("[bench] mixed precision (complex64 factors and preconditioner operators)")
-        mr = run_form(hbj, wl, mt, ft, u, hbj.MIXED, hbj.OP_DENSE, args.steps, 1, args.tol, names32)
+        mr = run_form(hbj, wl, mt, ft, u, hbj.MIXED, hbj.OP_DENSE, args.steps, 1, args.tol, names32,
+                      graphs=args.graphs)
         result["mixed"] = {"solves_per_s": args.steps / mr["seconds"], "iters": mr["stats"].iters,
                            "relres": mr["stats"].relres, "factor_s": mr["factor_s"],
                            "roofline": roofline_of(mr["kernels"], wl.name + "/mixed")}

@@ -280,7 +280,8 @@ class Context:
         _check(_lib.hbj_reset_kernel_stats(self._h))
 
     def set_graphs(self, on=True):
-        """Replay GMRES iterations as HIP graphs (default on)."""
+        """Replay GMRES iterations as HIP graphs (default off: one-by-one launches are faster once
+        the next step is queued ahead)."""
         _check(_lib.hbj_set_graphs(self._h, 1 if on else 0))
 
     def set_orthogonalization(self, mode):

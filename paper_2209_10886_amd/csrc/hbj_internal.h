@@ -258,7 +258,7 @@ hipError_t launch_build_T(const Geom& g, const Entry* ent, int nent, const FaceT
                           const double2* ybuf, size_t ystride, double2* T, hipStream_t st);
 template <typename C>
 hipError_t launch_scatter_apply(const Geom& g, const Entry* ent, int nent, int mask, const int32_t* rblist, int nrb,
-                                const FaceTab* ft, const C* T, const SolveIO& io, hipStream_t st,
+                                const FaceTab* eft, const C* T, const SolveIO& io, hipStream_t st,
                                 hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
 // dataflow sweep launch: ctr = [ticket, counters...] (zero at entry), ctr_next is zeroed for the
 // next launch; err receives 1 if a dependency wait exceeded spin_limit polls; the waits of

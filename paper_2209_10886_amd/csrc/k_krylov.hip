@@ -197,7 +197,8 @@ __global__ __launch_bounds__(RT) void k_scale_reduce(double2* dst, const double2
 //   i < nv: V_i^H x;  nv + i: V_i^H w;  2 nv: x^H x;  2 nv + 1: x^H w;  2 nv + 2: w^H w.
 // Grid (nchunk, max(1, ceil(nv / VG)), ncol); group 0 also sums the three products of x and w.
 constexpr int VG2 = 8;
-__global__ __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_dots2(
+template <int RT2, int U>  // threads, entries per thread and block of loads
+__global__ __launch_bounds__(RT2) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_dots2(
     const double2* V, size_t vstride, int nv, const double2* x, const double2* w, int n, double2* partial,
     int nchunk) {
   const int chunk = blockIdx.x, i0 = blockIdx.y * VG2, col = blockIdx.z;
@@ -211,34 +212,41 @@ __global__ __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
   for (int v = 0; v < VG2; ++v) aa[v] = ab[v] = mk(0.0, 0.0);
   double sxx = 0.0, sww = 0.0;
   double2 sxw = mk(0.0, 0.0);
-  constexpr int U = 2;
-  for (int qb = q0; qb < q1; qb += U * RT) {
+  for (int qb = q0; qb < q1; qb += U * RT2) {
+    // every load of the block is issued, with clamped (in-bounds) indices, before any is used;
+    // entries past the chunk are zeroed afterwards, and with nv = 0 the basis loads read V_0
+    // (products that are never stored)
     double2 xl[U], wl[U];
-    int qi[U];
+    int qi[U], vm = 0;
 #pragma unroll
-    for (int k = 0; k < U; ++k) {  // clamped loads; entries past the chunk are zeroed
-      const int q = qb + threadIdx.x + k * RT;
+    for (int k = 0; k < U; ++k) {
+      const int q = qb + threadIdx.x + k * RT2;
+      vm |= (int)(q < q1) << k;
       qi[k] = q < q1 ? q : q1 - 1;
       xl[k] = xx[qi[k]];
       wl[k] = ww[qi[k]];
-      if (q >= q1) xl[k] = wl[k] = mk(0.0, 0.0);
     }
-    if (nv > 0) {
-      double2 vl[VG2][U];
+    double2 vl[VG2][U];
 #pragma unroll
-      for (int v = 0; v < VG2; ++v) {
-        const double2* vp = V + (size_t)min(i0 + v, nv - 1) * vstride + (size_t)col * n;
+    for (int v = 0; v < VG2; ++v) {
+      const double2* vp = V + (size_t)max(0, min(i0 + v, nv - 1)) * vstride + (size_t)col * n;
 #pragma unroll
-        for (int k = 0; k < U; ++k) vl[v][k] = vp[qi[k]];
+      for (int k = 0; k < U; ++k) vl[v][k] = vp[qi[k]];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const bool in = (vm >> k) & 1;
+      xl[k] = in ? xl[k] : mk(0.0, 0.0);
+      wl[k] = in ? wl[k] : mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int v = 0; v < VG2; ++v)
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        cfma_conj(aa[v], vl[v][k], xl[k]);
+        cfma_conj(ab[v], vl[v][k], wl[k]);
       }
-#pragma unroll
-      for (int v = 0; v < VG2; ++v)
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-          cfma_conj(aa[v], vl[v][k], xl[k]);
-          cfma_conj(ab[v], vl[v][k], wl[k]);
-        }
-    }
     if (g0) {
 #pragma unroll
       for (int k = 0; k < U; ++k) {
@@ -249,7 +257,7 @@ __global__ __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
     }
   }
   constexpr int NS = 2 * VG2 + 2;  // a, b, then (xx, ww) and xw
-  __shared__ double2 sh[RT / 64][NS];
+  __shared__ double2 sh[RT2 / 64][NS];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double2 vals[NS];
 #pragma unroll
@@ -274,7 +282,7 @@ __global__ __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
   double2* pc = partial + (size_t)col * np * nchunk + chunk;
   if (threadIdx.x < NS) {
     double2 t = mk(0.0, 0.0);
-    for (int q = 0; q < RT / 64; ++q) t = cadd(t, sh[q][threadIdx.x]);
+    for (int q = 0; q < RT2 / 64; ++q) t = cadd(t, sh[q][threadIdx.x]);
     const int v = threadIdx.x;
     if (v < VG2) {
       if (i0 + v < nv) pc[(size_t)(i0 + v) * nchunk] = t;
@@ -299,6 +307,7 @@ __global__ __launch_bounds__(RT) __attribute__((amdgpu_waves_per_eu(1, 2))) void
 // hout + 2 ncol ld + 2 col, for the host, which completes Hessenberg column j - 1 with them.
 // publish_only: only the coefficients (the last step of a restart cycle, which needs a and nu).
 constexpr int kDcgsMaxV = 256;
+constexpr int kDotsThreads = 256, kDotsBlock = 2;  // fastest of a sweep over 128-1024 threads, 2-4 entries
 __global__ __launch_bounds__(RT) void k_dcgs_update(const double2* V, size_t vstride, int nv, double2* x,
                                                     double2* xn, const double2* w, const double2* partial,
                                                     int nchunk, double2* hout, int ld, int n, int publish_only) {
@@ -340,25 +349,33 @@ __global__ __launch_bounds__(RT) void k_dcgs_update(const double2* V, size_t vst
     ca[i] = i < nv ? sp[i] : mk(0.0, 0.0);
     cb[i] = i < nv ? sp[nv + i] : mk(0.0, 0.0);
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    // |a|^2 and a^H b over wavefront 0: strided per-lane sums, then a shuffle tree (fixed order)
     double na = 0.0;
     double2 ab = mk(0.0, 0.0);
-    for (int i = 0; i < nv; ++i) {
+    for (int i = threadIdx.x; i < nv; i += 64) {
       const double2 a = sp[i];
       na += a.x * a.x + a.y * a.y;
       cfma_conj(ab, a, sp[nv + i]);
     }
-    const double xx = sp[2 * nv].x, ww = sp[2 * nv + 2].x;
-    const double2 xw = sp[2 * nv + 1];
-    const double nu2 = xx - na;
-    const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
-    const double s = ww > 0.0 ? sqrt(ww) : 0.0;
-    sc[0] = nu;
-    sc[1] = s;
-    sc[2] = ww;
-    sc[3] = nu > 0.0 ? 1.0 / nu : 0.0;
-    sc[4] = s > 0.0 ? 1.0 / s : 0.0;
-    scj[0] = nu > 0.0 ? mk((xw.x - ab.x) / nu, (xw.y - ab.y) / nu) : mk(0.0, 0.0);
+    for (int off = 32; off > 0; off >>= 1) {
+      na += __shfl_down(na, off);
+      ab.x += __shfl_down(ab.x, off);
+      ab.y += __shfl_down(ab.y, off);
+    }
+    if (threadIdx.x == 0) {
+      const double xx = sp[2 * nv].x, ww = sp[2 * nv + 2].x;
+      const double2 xw = sp[2 * nv + 1];
+      const double nu2 = xx - na;
+      const double nu = nu2 > 0.0 ? sqrt(nu2) : 0.0;
+      const double s = ww > 0.0 ? sqrt(ww) : 0.0;
+      sc[0] = nu;
+      sc[1] = s;
+      sc[2] = ww;
+      sc[3] = nu > 0.0 ? 1.0 / nu : 0.0;
+      sc[4] = s > 0.0 ? 1.0 / s : 0.0;
+      scj[0] = nu > 0.0 ? mk((xw.x - ab.x) / nu, (xw.y - ab.y) / nu) : mk(0.0, 0.0);
+    }
   }
   __syncthreads();
   if (blockIdx.x == 0) {
@@ -525,8 +542,8 @@ bool dcgs_fits(int m, int nchunk) { return m + 1 <= kDcgsMaxV && (2 * m + 3) * n
 hipError_t launch_dots2(const double2* V, size_t vstride, int nv, const double2* x, const double2* w, int n, int ncol,
                         double2* partial, int nchunk, hipStream_t st) {
   if (nchunk < 1 || (2 * nv + 3) * nchunk > kFuseMax || nv + 1 > kDcgsMaxV) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_dots2, dim3(nchunk, std::max(1, (nv + VG2 - 1) / VG2), ncol), dim3(RT), 0, st, V, vstride, nv, x,
-                     w, n, partial, nchunk);
+  hipLaunchKernelGGL((k_dots2<kDotsThreads, kDotsBlock>), dim3(nchunk, std::max(1, (nv + VG2 - 1) / VG2), ncol),
+                     dim3(kDotsThreads), 0, st, V, vstride, nv, x, w, n, partial, nchunk);
   return hipGetLastError();
 }
 

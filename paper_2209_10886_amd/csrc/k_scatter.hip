@@ -48,16 +48,29 @@ constexpr int LMAX = 1024;   // local interface length limit (sub_nx, sub_ny <= 
 // columns grp + 32 k, so each load instruction of a wavefront reads 8 consecutive columns of the
 // block (1 KB contiguous); all its loads are issued before it waits for the incoming data.  The
 // column sums meet in a cross-lane tree (lanes r + 8 j) and then across the four wavefronts.
-template <typename C, int KMAX>
+// eft[i] is the face table of entry i's subdomain: the entry, its faces and the row block are
+// three independent loads, so the data loads wait for one round trip, not two.
+// ALIGNED: every face starts at a multiple of CG, so the CG columns of load k (grp + CG k over the
+// workgroup) lie on one face; whether they are needed is then the same in every lane and is
+// decided on the scalar unit (loads of faces without data read the block's first columns again).
+template <typename C, int KMAX, bool ALIGNED>
 __global__ __launch_bounds__(kTR * CG) void k_scatter_apply(Geom g, const Entry* ent, const int32_t* rblist,
-                                                            const FaceTab* ft, const C* __restrict__ T, SolveIO io) {
+                                                            const FaceTab* eft, const C* __restrict__ T, SolveIO io) {
   constexpr int NT = kTR * CG;
   constexpr int GLP = LMAX / NT;  // incoming data per thread
   const Entry e = ent[blockIdx.y];
+  const FaceTab F = eft[blockIdx.y];
   const int rb = rblist[blockIdx.x];
+  // every table value and kernel argument the workgroup needs is taken into registers here, before
+  // the idle-block test below: their scalar loads then go out together instead of one round after
+  // the other (the empty statements only name the registers)
+  asm volatile("" ::"s"(e.s), "s"(e.rhs), "s"(e.src), "s"(e.mask), "s"(rb));
+  asm volatile("" ::"s"(F.in_off[0]), "s"(F.in_off[1]), "s"(F.in_off[2]), "s"(F.in_off[3]));
+  asm volatile("" ::"s"(F.out_off[0]), "s"(F.out_off[1]), "s"(F.out_off[2]), "s"(F.out_off[3]));
+  asm volatile("" ::"s"(io.g_a), "s"(io.g_b), "s"(io.tr_dst), "s"(io.tr_base), "s"(io.in_faces), "s"(io.copy));
+  asm volatile("" ::"s"(T), "s"(g.nif), "s"(io.tr_sign));
   const int L = local_if_len(g);
   const int r = threadIdx.x % kTR, grp = threadIdx.x / kTR;
-  const FaceTab F = ft[e.s];
   // faces present (a neighbour exists: both the incoming and the outgoing block exist)
   const int pm = (F.in_off[0] >= 0) | (F.in_off[1] >= 0) << 1 | (F.in_off[2] >= 0) << 2 | (F.in_off[3] >= 0) << 3;
   const int b1 = g.sny, b2 = 2 * g.sny, b3 = 2 * g.sny + g.snx;  // first rows / columns of faces E, S, N
@@ -77,23 +90,51 @@ __global__ __launch_bounds__(kTR * CG) void k_scatter_apply(Geom g, const Entry*
   // position q of face f sits at in_off[f] + (q - first[f]) of the interface vector
   const int ib0 = F.in_off[0], ib1 = F.in_off[1] - b1, ib2 = F.in_off[2] - b2, ib3 = F.in_off[3] - b3;
   double2 gv[GLP];
+  int okm = 0;  // bit k: gv[k] holds data (the others are zeroed when they go to shared memory)
 #pragma unroll
   for (int k = 0; k < GLP; ++k) {
+    if (ALIGNED && k * NT >= L) {  // no position of this load is on the interface
+      gv[k] = mk(0.0, 0.0);
+      continue;
+    }
     const int q = threadIdx.x + k * NT;
-    const int f = (q >= b1) + (q >= b2) + (q >= b3);
-    const int ib = f == 0 ? ib0 : f == 1 ? ib1 : f == 2 ? ib2 : ib3;
-    const bool ok = q < L && ((pm >> f) & 1);
+    const bool c1 = q >= b1, c2 = q >= b2, c3 = q >= b3;
+    const int f = (int)c1 + (int)c2 + (int)c3;
+    int ib = c1 ? ib1 : ib0;  // selects, not branches
+    ib = c2 ? ib2 : ib;
+    ib = c3 ? ib3 : ib;
+    const bool ok = (q < L) & ((pm >> f) & 1);  // bitwise: no branch around the load
     const double2* src = ((from_b >> f) & 1) ? io.g_b : io.g_a;
     gv[k] = src[ok ? cb + ib + q : cb];
-    if (!ok) gv[k] = mk(0.0, 0.0);
+    okm |= (int)ok << k;
   }
   // the output row of this thread (threads 0-7): its base value and pass-through datum are
   // loaded up front as well
   const int row = rb * kTR + (int)threadIdx.x;
-  int rf = 0, re = 0;
-  local_if_face(g, row < L ? row : 0, &rf, &re);
-  const bool mine = threadIdx.x < kTR && row < L && ((e.mask >> rf) & 1);
-  const int oo = pick4(F.out_off, rf), io_ = pick4(F.in_off, rf);
+  int rf, re, oo, io_;
+  if constexpr (ALIGNED) {
+    // the kTR rows of the block lie on one face: face and block offsets are uniform
+    const int r0 = rb * kTR;
+    rf = __builtin_amdgcn_readfirstlane((r0 >= b1) + (r0 >= b2) + (r0 >= b3));
+    re = row - (rf == 0 ? 0 : rf == 1 ? b1 : rf == 2 ? b2 : b3);
+    oo = pick4(F.out_off, rf);
+    io_ = pick4(F.in_off, rf);
+  } else {
+    const int rr = row < L ? row : 0;
+    const bool c1 = rr >= b1, c2 = rr >= b2, c3 = rr >= b3;  // selects, not branches
+    rf = (int)c1 + (int)c2 + (int)c3;
+    int fo = c1 ? b1 : 0, o = c1 ? F.out_off[1] : F.out_off[0], i = c1 ? F.in_off[1] : F.in_off[0];
+    fo = c2 ? b2 : fo;
+    o = c2 ? F.out_off[2] : o;
+    i = c2 ? F.in_off[2] : i;
+    fo = c3 ? b3 : fo;
+    o = c3 ? F.out_off[3] : o;
+    i = c3 ? F.in_off[3] : i;
+    re = rr - fo;
+    oo = o;
+    io_ = i;
+  }
+  const bool mine = ((int)threadIdx.x < kTR) & (row < L) & ((e.mask >> rf) & 1);
   const bool wr = mine && oo >= 0, cp = mine && io.copy && io_ >= 0;
   double2 bv = mk(0.0, 0.0), cv = mk(0.0, 0.0);
   if (wr && io.tr_base) bv = io.tr_base[cb + oo + re];
@@ -103,15 +144,33 @@ __global__ __launch_bounds__(kTR * CG) void k_scatter_apply(Geom g, const Entry*
   // columns of absent faces and past L hold no data (their incoming datum is zero): they load the
   // block's column 0 instead, one cached line, so every load stays unconditional
   C v[KMAX];
+  if constexpr (ALIGNED) {
+    const C* Tl = Tb + (size_t)grp * kTR;
+    // bit k: load k reads a face with data (faces span loads [0, b1/CG), [b1/CG, b2/CG), ...)
+    auto span = [](int a, int b) -> uint64_t { return ((uint64_t(1) << b) - 1) & ~((uint64_t(1) << a) - 1); };
+    const int k1 = b1 / CG, k2 = b2 / CG, k3 = b3 / CG, k4 = L / CG;
+    const uint64_t lm64 = ((pm & 1) ? span(0, k1) : 0) | ((pm & 2) ? span(k1, k2) : 0) |
+                          ((pm & 4) ? span(k2, k3) : 0) | ((pm & 8) ? span(k3, k4) : 0);
+    // read through readfirstlane: a scalar the optimiser cannot see into (it would otherwise merge
+    // the redirected loads with the first one and wait for that before issuing the others)
+    const uint32_t lm = __builtin_amdgcn_readfirstlane((uint32_t)lm64);
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) {
-    const int col = grp + CG * k;
-    const int f = (col >= b1) + (col >= b2) + (col >= b3);
-    const bool live = col < L && ((pm >> f) & 1);
-    v[k] = Tb[(size_t)(live ? col : 0) * kTR];
+    for (int k = 0; k < KMAX; ++k) {
+      const int cc = ((lm >> k) & 1) ? CG * k : 0;  // uniform: a scalar select per load
+      v[k] = Tl[(size_t)cc * kTR];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int col = grp + CG * k;
+      const int f = (col >= b1) + (col >= b2) + (col >= b3);
+      const bool live = (col < L) & ((pm >> f) & 1);
+      v[k] = Tb[(size_t)(live ? col : 0) * kTR];
+    }
   }
+  __builtin_amdgcn_sched_barrier(0);  // every load above is issued before the first wait below
 #pragma unroll
-  for (int k = 0; k < GLP; ++k) gl[threadIdx.x + k * NT] = gv[k];
+  for (int k = 0; k < GLP; ++k) gl[threadIdx.x + k * NT] = ((okm >> k) & 1) ? gv[k] : mk(0.0, 0.0);
   __syncthreads();
   double2 acc = mk(0.0, 0.0);
 #pragma unroll
@@ -148,24 +207,27 @@ hipError_t launch_build_T(const Geom& g, const Entry* ent, int nent, const FaceT
 
 template <typename C>
 hipError_t launch_scatter_apply(const Geom& g, const Entry* ent, int nent, int mask, const int32_t* rblist, int nrb,
-                                const FaceTab* ft, const C* T, const SolveIO& io, hipStream_t st, hipEvent_t t0,
+                                const FaceTab* eft, const C* T, const SolveIO& io, hipStream_t st, hipEvent_t t0,
                                 hipEvent_t t1) {
   (void)mask;  // carried by every entry
   if (nent == 0 || nrb == 0) return hipSuccess;
   const int L = local_if_len(g);
   if (L > LMAX) return hipErrorInvalidValue;
   const dim3 grid(nrb, nent);
-  // with events, the start and stop times are those of the dispatch itself
-  if (t0 || t1) {
-    if (L <= 16 * CG)
-      hipExtLaunchKernelGGL((k_scatter_apply<C, 16>), grid, dim3(kTR * CG), 0, st, t0, t1, 0, g, ent, rblist, ft, T, io);
+  const bool aligned = g.snx % CG == 0 && g.sny % CG == 0;
+  auto go = [&](auto kern) {
+    // with events, the start and stop times are those of the dispatch itself
+    if (t0 || t1)
+      hipExtLaunchKernelGGL(kern, grid, dim3(kTR * CG), 0, st, t0, t1, 0, g, ent, rblist, eft, T, io);
     else
-      hipExtLaunchKernelGGL((k_scatter_apply<C, LMAX / CG>), grid, dim3(kTR * CG), 0, st, t0, t1, 0, g, ent, rblist,
-                            ft, T, io);
-  } else if (L <= 16 * CG) {
-    hipLaunchKernelGGL((k_scatter_apply<C, 16>), grid, dim3(kTR * CG), 0, st, g, ent, rblist, ft, T, io);
+      hipLaunchKernelGGL(kern, grid, dim3(kTR * CG), 0, st, g, ent, rblist, eft, T, io);
+  };
+  if (L <= 16 * CG) {
+    if (aligned) go(k_scatter_apply<C, 16, true>);
+    else go(k_scatter_apply<C, 16, false>);
   } else {
-    hipLaunchKernelGGL((k_scatter_apply<C, LMAX / CG>), grid, dim3(kTR * CG), 0, st, g, ent, rblist, ft, T, io);
+    if (aligned) go(k_scatter_apply<C, LMAX / CG, true>);
+    else go(k_scatter_apply<C, LMAX / CG, false>);
   }
   return hipGetLastError();
 }

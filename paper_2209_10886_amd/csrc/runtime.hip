@@ -56,6 +56,7 @@ struct Step {
 struct Schedule {
   int nrhs = 0;
   Entry* dev = nullptr;
+  FaceTab* eft = nullptr;  // the face table of each entry's subdomain, one per entry (same indexing)
   size_t all_first = 0;  // every subdomain, all faces
   int all_count = 0;
   double all_dense_elems = 0;
@@ -163,7 +164,7 @@ struct hbj_ctx {
   size_t pc_cols = 0;
   // GMRES workspace kept across solves, and the HIP graphs of its iterations
   Gmres* gm = nullptr;
-  bool use_graphs = true;
+  bool use_graphs = false;  // eager launches measured faster once step j+1 is queued ahead
   int orth = HBJ_ORTH_DCGS2;     // Gram-Schmidt variant of the Arnoldi steps
   int graph_epoch = 0;           // bumped when captured operands change (a new factorisation)
   hipStream_t cap = nullptr;     // capture stream (graphs are replayed on st)
@@ -191,6 +192,7 @@ hbj_ctx::~hbj_ctx() {
   if (cap) (void)hipStreamDestroy(cap);
   for (auto& kv : sched) {
     dfree(kv.second->dev);
+    dfree(kv.second->eft);
     dfree(kv.second->subs);
     for (auto& pl : kv.second->df) dfree(pl.dev);
     dfree(kv.second->df_ctr);
@@ -368,6 +370,10 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
   }
   HIPCHK(dalloc(&S->dev, ent.size()));
   HIPCHK(hipMemcpyAsync(S->dev, ent.data(), ent.size() * sizeof(Entry), hipMemcpyHostToDevice, c->st));
+  std::vector<FaceTab> eft(ent.size());
+  for (size_t q = 0; q < ent.size(); ++q) eft[q] = c->ft_host[ent[q].s];
+  HIPCHK(dalloc(&S->eft, eft.size()));
+  HIPCHK(hipMemcpyAsync(S->eft, eft.data(), eft.size() * sizeof(FaceTab), hipMemcpyHostToDevice, c->st));
   HIPCHK(dalloc(&S->subs, subs.size()));
   HIPCHK(hipMemcpyAsync(S->subs, subs.data(), subs.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
@@ -493,7 +499,8 @@ int run_solves_side(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io) {
 // batched application of the dense scattering operators (complex128 or complex64 storage)
 constexpr int kMatrixRhs = 4;  // from this many right-hand sides on, the operators run as MFMA products
 
-int run_dense(hbj_ctx* c, const Entry* ent, int nent, int mask, const SolveIO& io, bool c64, double elems,
+int run_dense(hbj_ctx* c, const Entry* ent, const FaceTab* eft, int nent, int mask, const SolveIO& io, bool c64,
+              double elems,
               const int32_t* subs = nullptr, int nsub = 0, int nrhs = 1, int src = 0) {
   if (nent == 0) return HBJ_OK;
   if (subs && nrhs >= kMatrixRhs) {
@@ -553,9 +560,9 @@ int run_dense(hbj_ctx* c, const Entry* ent, int nent, int mask, const SolveIO& i
   // profiling: the dispatch's own start and stop times (no event packets around the launch)
   hipEvent_t t0 = c->prof ? c->ev0 : nullptr, t1 = c->prof ? c->ev1 : nullptr;
   if (c64)
-    HIPCHK(launch_scatter_apply<float2>(c->g, ent, nent, mask, rbl, c->rbl_n[li], c->ft, c->T32, io, c->st, t0, t1));
+    HIPCHK(launch_scatter_apply<float2>(c->g, ent, nent, mask, rbl, c->rbl_n[li], eft, c->T32, io, c->st, t0, t1));
   else
-    HIPCHK(launch_scatter_apply<double2>(c->g, ent, nent, mask, rbl, c->rbl_n[li], c->ft, c->T64, io, c->st, t0, t1));
+    HIPCHK(launch_scatter_apply<double2>(c->g, ent, nent, mask, rbl, c->rbl_n[li], eft, c->T64, io, c->st, t0, t1));
   if (c->prof) {
     HIPCHK(hipEventSynchronize(c->ev1));
     float ms = 0.f;
@@ -941,7 +948,7 @@ int op_fp64(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
     return run_df<double2>(c, S, DF_OP, A, c->T64);
   }
   if (c->dense)
-    return run_dense(c, S->dev + S->all_first, S->all_count, 0xF, io, false, S->all_dense_elems,
+    return run_dense(c, S->dev + S->all_first, S->eft + S->all_first, S->all_count, 0xF, io, false, S->all_dense_elems,
                      S->subs + S->all_sub_first, S->all_sub_count, S->nrhs, 0);
   return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
 }
@@ -967,7 +974,7 @@ int run_pass(hbj_ctx* c, const Schedule* S, const std::vector<Step>& steps, cons
     io.copy = cp ? 1 : 0;
     io.tr_sign = 1.0;
     io.tr_reflect = 1;
-    int rc = c->dense ? run_dense(c, dev + s.first, s.count, mask, io, sizeof(R) == 4, s.dense_elems,
+    int rc = c->dense ? run_dense(c, dev + s.first, S->eft + s.first, s.count, mask, io, sizeof(R) == 4, s.dense_elems,
                                   S->subs + s.sub_first, s.sub_count, S->nrhs, si == 0 ? 0 : 1)
                       : run_solves<R>(c, dev + s.first, s.count, io);
     if (rc) return rc;
