@@ -12,7 +12,9 @@ before the timed region (reported separately).
 Prints one JSON line.  Besides the contract fields it carries
   roofline      the dominant kernel's algorithmic bytes per launch over its mean
                 launch time (HIP events on the solver stream, profiled solve after
-                the timed region), against 8 TB/s;
+                the timed region), against 8 TB/s; for many right-hand sides, where
+                the operators are matrix-core products, their flops per launch
+                against the FP32 / FP64 matrix peak;
   cpu_baseline  the CPU oracle (numpy/scipy, one core) timed on a bounded sample:
                 lifting + a few GMRES iterations + reconstruction, scaled to one
                 full solve with the GPU's iteration count;
@@ -159,21 +161,38 @@ def merge_kernels(kernels):
     return out
 
 
-def roofline_of(kernels, workload):
+# dense matrix-core peaks of MI355X (TFLOP/s) for the contractions of the many-right-hand-side form
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+
+
+def roofline_of(kernels, workload, mfma=None):
+    """Roofline of the kernel with the most time. mfma maps kernel symbols that are dense
+    contractions (the operator products for many right-hand sides) to their precision: those are
+    priced in TFLOP/s against the matrix-core peak, every other kernel in GB/s against HBM."""
+    mfma = mfma or {}
     merged = merge_kernels(kernels)
     name, ks = max(merged.items(), key=lambda kv: kv[1]["ms"])
     avg_ms = ks["ms"] / ks["launches"]
     bpl = ks["bytes"] / ks["launches"]
-    achieved = bpl / (avg_ms * 1e-3) / 1e9
+    fpl = ks["flops"] / ks["launches"]
     detail = {c: {"launches": kernels[c]["launches"], "avg_launch_ms": kernels[c]["ms"] / max(1, kernels[c]["launches"]),
                   "bytes_per_launch": kernels[c]["bytes"] / max(1, kernels[c]["launches"]),
-                  "GB/s": kernels[c]["bytes"] / max(1e-12, kernels[c]["ms"] * 1e-3) / 1e9}
+                  "GB/s": kernels[c]["bytes"] / max(1e-12, kernels[c]["ms"] * 1e-3) / 1e9,
+                  "TFLOP/s": kernels[c]["flops"] / max(1e-12, kernels[c]["ms"] * 1e-3) / 1e12}
               for c in ks["classes"]}
+    share = ks["ms"] / max(1e-12, sum(k["ms"] for k in kernels.values()))
+    if name in mfma:
+        peak = MFMA_PEAK_TFLOPS[mfma[name]]
+        achieved = fpl / (avg_ms * 1e-3) / 1e12
+        return {"bound": "mfma", "kernel": name, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": None, "flops_per_launch": fpl, "bytes_per_launch": bpl,
+                "avg_launch_ms": avg_ms, "launches": ks["launches"], "share_of_kernel_time": share,
+                "launch_kinds": detail}
+    achieved = bpl / (avg_ms * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(name, workload),
             "bytes_per_launch": bpl, "avg_launch_ms": avg_ms, "launches": ks["launches"],
-            "share_of_kernel_time": ks["ms"] / max(1e-12, sum(k["ms"] for k in kernels.values())),
-            "launch_kinds": detail}
+            "share_of_kernel_time": share, "launch_kinds": detail}
 
 
 def solve_gbs(kernels, names):
@@ -219,6 +238,15 @@ def main():
                hbj.K_OPERATOR: "k_scatter_apply<double2,16> (operator)",
                hbj.K_SWEEP: "k_sweep_df", hbj.K_LIFT: "k_lift_partial+k_recon_dense",
                hbj.K_KRYLOV: "krylov (Gram-Schmidt kernels of one iteration)"}
+    mfma = {}
+    if nsrc >= 4:
+        # from 4 right-hand sides on the operators run as matrix-core products (k_scatter_mm)
+        for nm_ in (names64, names32):
+            nm_[hbj.K_SCATTER] = ("k_scatter_mm<float2,float> (sweep steps)" if nm_ is names32
+                                  else "k_scatter_mm<double2,double> (sweep steps)")
+            nm_[hbj.K_OPERATOR] = "k_scatter_mm<double2,double> (operator)"
+            nm_[hbj.K_LIFT] = "k_lift_partial+k_recon_mm"
+        mfma = {"k_scatter_mm<float2,float>": "f32", "k_scatter_mm<double2,double>": "f64"}
 
     log(f"[bench] {'FP64' if headline_prec == hbj.FP64 else 'mixed'}, dense scattering operators (headline), "
         f"{nsrc} right-hand side(s)")
@@ -228,8 +256,8 @@ def main():
     ms_per_step = main_run["seconds"] / max(args.steps, 1) * 1e3
     log(f"[bench] {ms_per_step:.2f} ms/solve, iters {st.iters}, relres {st.relres:.2e}, "
         f"factor {main_run['factor_s']:.2f} s")
-    roof = roofline_of(main_run["kernels"], wl.name)
-    log(f"[bench] dominant {roof['kernel']}: {roof['avg_launch_ms']:.4f} ms avg, {roof['achieved']:.1f} GB/s")
+    roof = roofline_of(main_run["kernels"], wl.name, mfma)
+    log(f"[bench] dominant {roof['kernel']}: {roof['avg_launch_ms']:.4f} ms avg, {roof['achieved']:.1f} {roof['unit']}")
 
     result = {
         "metric": "Helmholtz solves/s at rel-res 1e-6; subdomain-solve HBM GB/s (FP64 vs mixed)",

@@ -11,6 +11,13 @@
         probe (1 GiB read + 1 GiB written); the entry is keyed by NAME and stamped with the hash of FILE
         so that a later change of the kernel's source invalidates it.
 
+    python -m paper_2209_10886_amd.profsum iteration DIR --start KERNEL --last KERNEL [--solve I]
+        one GMRES iteration from a kernel trace (--kernel-trace): solves begin at each launch of the
+        --start kernel, iterations end at each launch of the --last kernel; over the middle half of
+        the iterations of solve I (default: the middle solve) on the solver's queue, the launches
+        per iteration and mean duration of every kernel, the idle time between launches and the
+        iteration's wall time
+
 DIR is a rocprofv3 output directory (searched recursively for *_kernel_stats.csv or
 *_counter_collection.csv).
 """
@@ -127,6 +134,46 @@ def traffic(a):
     print(json.dumps(ent, indent=1))
 
 
+def iteration_markdown(d, start, last, solve=None):
+    rows = []
+    for path in _find(d, "_kernel_trace.csv"):
+        with open(path) as fh:
+            rows += [r for r in csv.DictReader(fh)]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    starts = [i for i, r in enumerate(rows) if start in r["Kernel_Name"]]
+    if len(starts) < 1:
+        raise SystemExit(f"no launch of {start}")
+    si = len(starts) // 2 if solve is None else solve
+    seg = rows[starts[si]:(starts[si + 1] if si + 1 < len(starts) else len(rows))]
+    queues = {}
+    for r in seg:
+        queues[r["Queue_Id"]] = queues.get(r["Queue_Id"], 0) + 1
+    q = max(queues, key=queues.get)
+    seg = [r for r in seg if r["Queue_Id"] == q]
+    ends = [i for i, r in enumerate(seg) if last in r["Kernel_Name"]]
+    its = [(a + 1, b + 1) for a, b in zip(ends, ends[1:])]
+    its = its[len(its) // 4: len(its) - len(its) // 4] or its
+    per, n = {}, len(its)
+    gap = wall = 0.0
+    for a, b in its:
+        it = seg[a:b]
+        for r in it:
+            nm = short_name(r["Kernel_Name"])
+            e = per.setdefault(nm, [0, 0.0])
+            e[0] += 1
+            e[1] += (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        for p_, r in zip(it, it[1:]):
+            gap += max(0, int(r["Start_Timestamp"]) - int(p_["End_Timestamp"])) / 1e3
+        wall += (int(it[-1]["End_Timestamp"]) - int(seg[a - 1]["End_Timestamp"])) / 1e3
+    out = [f"solve {si} of {len(starts)}, iterations {n} (middle half), solver queue {q}", "",
+           "| kernel | launches per iteration | mean us | us per iteration |", "|---|---|---|---|"]
+    for nm, (c, t) in sorted(per.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"| `{nm}` | {c / n:.1f} | {t / c:.2f} | {t / n:.1f} |")
+    out.append(f"| idle between launches | | | {gap / n:.1f} |")
+    out.append(f"| iteration (wall) | | | {wall / n:.1f} |")
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -138,11 +185,18 @@ def main(argv=None):
     for k in ("fetch", "write", "calib_fetch", "calib_write", "kernel", "name", "source"):
         t.add_argument("--" + k.replace("_", "-"), required=True)
     t.add_argument("--out", default=None)
+    it = sub.add_parser("iteration")
+    it.add_argument("dir")
+    it.add_argument("--start", required=True)
+    it.add_argument("--last", required=True)
+    it.add_argument("--solve", type=int, default=None)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats_markdown(a.dir))
     elif a.cmd == "counters":
         print(counters_markdown(a.dir))
+    elif a.cmd == "iteration":
+        print(iteration_markdown(a.dir, a.start, a.last, a.solve))
     else:
         traffic(a)
 
