@@ -14,10 +14,37 @@ template is  out_q = -rho g_p - sigma u_p  (g_p the data i received on the same
 face).  Summed over the faces of i this is the local scattering operator of
 Sec. 4, including the reflection term k = j.
 
+Higher-order transmission (transmission=2; the paper's own condition is a higher-order
+absorbing one, a Pade approximation with a rotated branch cut and auxiliary interface
+fields): on interface faces the condition gains a tangential second-derivative term,
+
+    d_n u - i alpha a u - (i b / alpha) d_tt u = g,
+
+the form of a second-order expansion of the one-way operator d_n - i alpha sqrt(1 +
+d_tt / alpha^2) (Taylor: a = 1, b = 1/2).  With the face template it reads
+
+    (u_q - u_p)/h - i alpha a (u_p + u_q)/2 - beta-_e (C u_p)_e = g_e,
+
+beta+- built from alpha a, where C is the symmetric tangential operator along the face
+with edge weights s_{e,e+1} = (kappa_e + kappa_{e+1}) / (2 h^2), kappa = (i b / alpha) /
+beta- (with constant alpha this is (i b / alpha) times the second difference), and
+homogeneous Neumann closure at the face ends.  The Taylor coefficients make S expand
+the grid-scale tangential modes on this 5-point grid (GMRES then stalls); the default
+(a, b) = (1 + 0.2 i, 0.15 exp(-i pi/4)) damps them (Re of the impedance negative for
+evanescent modes, as the rotated branch cut does) and was chosen by a sweep of block-
+Jacobi GMRES iterations at 10 and 15 points per wavelength.  The ghost becomes u_q = (g + beta+ u_p)/beta- +
+(C u_p)_e, so the row of p gains -(C u_p)_e / h^2: the local matrix stays banded and
+complex symmetric.  The data sent across the face keep the first-order form with
+matrices along the face: out = -R g - Sigma u_line with M = B+ + B- C, R = M B-^{-1},
+Sigma = M B-^{-1} M - B- (R = diag(rho), Sigma = diag(sigma) when C = 0).  The outer
+faces keep the first-order absorbing condition, so the global problem, and with it the
+solution, do not depend on the transmission order; only the convergence does.
+
 Pins (tests/test_oracle_dd.py): the reconstructed u equals the global direct
 solve to round-off on every decomposition (1 x 1 included); the traces of the
 global solution satisfy (I - S) g = b exactly; the dense S has the group
-structure of Sec. 5; GMRES agrees with a dense solve of (I - S) g = b.
+structure of Sec. 5; GMRES agrees with a dense solve of (I - S) g = b; for the
+second-order transmission the same identities and A = A^T.
 """
 from __future__ import annotations
 
@@ -30,6 +57,9 @@ from .layout import Layout, neighbours, norm1, subdomains
 
 # face identifiers: west (lx = 0), east (lx = snx-1), south (ly = 0), north (ly = sny-1)
 FACES = ("W", "E", "S", "N")
+
+# (a, b) of the second-order transmission condition d_n u - i alpha a u - (i b / alpha) d_tt u = g
+SECOND_ORDER = (1.0 + 0.2j, 0.15 * np.exp(-0.25j * np.pi))
 
 
 class Subdomain:
@@ -73,7 +103,24 @@ class Subdomain:
                 self.alpha[f] = g.k * np.sqrt(0.5 * (mp + mq))
             else:
                 self.alpha[f] = g.k * np.sqrt(mp)
-        self.coef = {f: robin_coeffs(self.alpha[f], g.h) for f in FACES}
+        # second-order transmission: zeroth-order impedance alpha a on interface faces
+        a0, b0 = (dd.tcoef if dd.transmission == 2 else (1.0, 0.0))
+        self.coef = {f: robin_coeffs(self.alpha[f] * (a0 if f in self.nbr else 1.0), g.h) for f in FACES}
+        # tangential operator C of every interface face (zero for first-order transmission)
+        self.tang = {}
+        for f in self.nbr:
+            bm = self.coef[f][0]
+            n_e = bm.size
+            C = np.zeros((n_e, n_e), dtype=np.complex128)
+            if dd.transmission == 2 and n_e > 1:
+                kappa = (1j * b0 / self.alpha[f]) / bm
+                s_e = (kappa[:-1] + kappa[1:]) / (2.0 * g.h * g.h)
+                e = np.arange(n_e - 1)
+                C[e, e + 1] = s_e
+                C[e + 1, e] = s_e
+                C[e, e] -= s_e
+                C[e + 1, e + 1] -= s_e
+            self.tang[f] = C
         self.A = self._matrix(g)
         self._lu = None
 
@@ -92,6 +139,15 @@ class Subdomain:
             rows += [a, b]
             cols += [b, a]
             vals += [np.full(a.size, off, np.complex128)] * 2
+        # second-order transmission: the row of each interface edge node gains -(C u_line)_e / h^2
+        for f, C in self.tang.items():
+            if not C.any():
+                continue
+            e = self.edge[f]
+            r, c = np.nonzero(C)
+            rows.append(e[r])
+            cols.append(e[c])
+            vals.append(-C[r, c] / h**2)
         return sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
 
     @property
@@ -108,10 +164,15 @@ class Subdomain:
 class Decomposition:
     """The n1 x n2 checkerboard of a grid (Sec. 2) with its interface layout."""
 
-    def __init__(self, grid: Grid, n1: int, n2: int):
+    def __init__(self, grid: Grid, n1: int, n2: int, transmission: int = 1, tcoef=None):
         if grid.nx % n1 or grid.ny % n2:
             raise ValueError("grid size must be divisible by the decomposition")
+        if transmission not in (1, 2):
+            raise ValueError("transmission order must be 1 or 2")
         self.grid, self.n1, self.n2 = grid, n1, n2
+        self.transmission = transmission
+        # (a, b) of the second-order condition d_n u - i alpha a u - (i b / alpha) d_tt u = g
+        self.tcoef = tcoef if tcoef is not None else SECOND_ORDER
         self.snx, self.sny = grid.nx // n1, grid.ny // n2
         self.layout = Layout(n1, n2, self.snx, self.sny)
         self.nif = self.layout.nif
@@ -132,16 +193,30 @@ class Decomposition:
         """u_i = A_i^{-1} (f_i + B_i g)  (Sec. 3 eq. (2); with g = 0 the lifting, eq. (3))."""
         return self.sub[i].lu.solve(self.local_rhs(i, g, f_loc))
 
+    def face_maps(self, i, f):
+        """R and Sigma of face f of subdomain i (out = -R g - Sigma u_line along the face)."""
+        s = self.sub[i]
+        bm, bp = s.coef[f][0], s.coef[f][1]
+        M = np.diag(bp) + bm[:, None] * s.tang[f]
+        R = M / bm[None, :]
+        Sig = R @ M - np.diag(bm)
+        return R, Sig
+
     def outgoing(self, i, u_loc, g):
         """Data sent by i to every neighbour j: {j: (-d_{n_ij} - T) u_i on Gamma_ij} (Sec. 4).
 
-        out = -rho g_p - sigma u_p, where g_p is the data i received on that face (0 if g is None)."""
+        out = -rho g_p - sigma u_p, where g_p is the data i received on that face (0 if g is None);
+        with the second-order transmission, out = -R g - Sigma u_line along the face."""
         s = self.sub[i]
         out = {}
         for f, j in s.nbr.items():
-            _, _, rho, sigma, _ = s.coef[f]
-            gin = 0.0 if g is None else g[self.layout.block(i, j)]
-            out[j] = -rho * gin - sigma * u_loc[s.edge[f]]
+            gin = np.zeros(s.edge[f].size, np.complex128) if g is None else g[self.layout.block(i, j)]
+            if not s.tang[f].any():
+                _, _, rho, sigma, _ = s.coef[f]
+                out[j] = -rho * gin - sigma * u_loc[s.edge[f]]
+            else:
+                R, Sig = self.face_maps(i, f)
+                out[j] = -R @ gin - Sig @ u_loc[s.edge[f]]
         return out
 
     def scatter_subdomain(self, i, g):
@@ -181,7 +256,8 @@ class Decomposition:
 
     def traces_of(self, u):
         """Incoming data g*_{m(i,j)} of a global field u: the Robin data that makes i's ghost
-        value equal u at j's node, g = (u_q - u_p)/h - i alpha (u_p + u_q)/2."""
+        value equal u at j's node, g = (u_q - u_p)/h - i alpha (u_p + u_q)/2 (minus
+        beta- C u_p along the face for the second-order transmission)."""
         h = self.grid.h
         g = np.zeros(self.nif, dtype=np.complex128)
         for i, s in self.sub.items():
@@ -191,7 +267,8 @@ class Decomposition:
                 fq = {"W": "E", "E": "W", "S": "N", "N": "S"}[f]
                 up = uloc[s.edge[f]]
                 uq = t.restrict(u)[t.edge[fq]]
-                g[self.layout.block(i, j)] = (uq - up) / h - 0.5j * s.alpha[f] * (up + uq)
+                bm, bp = s.coef[f][0], s.coef[f][1]  # (u_q - u_p)/h - i alpha a (u_p + u_q)/2 = bm u_q - bp u_p
+                g[self.layout.block(i, j)] = bm * uq - bp * up - bm * (s.tang[f] @ up)
         return g
 
     def dense_S(self):
