@@ -105,6 +105,17 @@ typedef struct {
   int32_t sweep_exec;    /* HBJ_SWEEP_STEPPED | HBJ_SWEEP_DATAFLOW (dense form, fewer
                             than 4 right-hand sides; identical results up to the
                             order of floating-point sums)                         */
+  int32_t transmission;  /* order of the transmission condition on interface faces:
+                            0 or 1 = the Robin condition (d_n - i alpha) u = g;
+                            2 = second order, d_n u - i alpha a u - (i b / alpha)
+                            d_tt u = g with a = 1 + 0.2 i, b = 0.15 exp(-i pi/4)
+                            (the paper's condition is a higher-order absorbing
+                            one, Sec. 7; the tangential term follows a second-order
+                            expansion of the one-way operator, with coefficients
+                            that damp the grid-scale modes).  The outer faces keep
+                            the absorbing condition, so the solution does not
+                            depend on it; 2 needs HBJ_OP_DENSE and device memory
+                            for the lifting matrices (HBJ_EINVAL / HBJ_ENOMEM)  */
 } hbj_problem;
 
 typedef struct {

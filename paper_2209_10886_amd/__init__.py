@@ -41,7 +41,8 @@ class Problem(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("h", ctypes.c_double), ("k", ctypes.c_double),
                 ("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("bj_width", ctypes.c_int32), ("bj_combine", ctypes.c_int32),
-                ("bj_compose", ctypes.c_int32), ("operator_form", ctypes.c_int32), ("sweep_exec", ctypes.c_int32)]
+                ("bj_compose", ctypes.c_int32), ("operator_form", ctypes.c_int32), ("sweep_exec", ctypes.c_int32),
+                ("transmission", ctypes.c_int32)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -307,10 +308,11 @@ class Context:
 
 def setup(nx, ny, k, n1, n2, c=None, m=None, h=0.0, precision=FP64, precond=PC_BJ, bj_width=0,
           bj_combine=BJ_RESTRICTED, bj_compose=BJ_PRODUCT, operator_form=OP_BANDED, sweep_exec=SWEEP_STEPPED,
-          device="cuda", stream=None) -> Context:
-    """hbj_setup with a wave speed c (or squared slowness m) given as a [ny, nx] float64 tensor."""
+          transmission=1, device="cuda", stream=None) -> Context:
+    """hbj_setup with a wave speed c (or squared slowness m) given as a [ny, nx] float64 tensor.
+    transmission: 1 (Robin) or 2 (second-order condition on interface faces, dense form)."""
     prob = Problem(nx, ny, h, k, n1, n2, precision, precond, bj_width, bj_combine, bj_compose, operator_form,
-                   sweep_exec)
+                   sweep_exec, transmission)
     if c is None and m is None:
         raise ValueError("give c or m")
     if c is None:

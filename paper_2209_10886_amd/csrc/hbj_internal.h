@@ -100,11 +100,24 @@ struct FaceTab {
   int32_t out_off[4];  // block m(j, i): data sent by i through face f
 };
 
-// interface coefficients of every interface position (same on both sides of a face)
+// interface coefficients of every interface position (same on both sides of a face); alpha
+// here is the impedance of the transmission condition (alpha a for the second-order one)
 struct IfCoef {
   double2 rho;    // beta+ / beta-
   double2 sigma;  // 2 i alpha / (h beta-)
   double2 inj;    // 1 / (beta- h^2)
+};
+
+// Face-line maps of the transmission condition at interface position q (entry e of its face):
+// the datum sent across the face at e is -sum_d r[d] g_{e+d-1} - sum_d sg[d] u_{e+d-2} over the
+// entries of the same face (r = R, sg = Sigma; first order: r = (0, rho, 0), sg = (0, 0, sigma,
+// 0, 0)), and t[0], t[1] are the tangential edge weights s_{e-1,e}, s_{e,e+1} of the second-order
+// condition (the row of the edge node gains -(C u)_e / h^2, C the tangential operator; zero for
+// the first-order condition).
+struct IfBand {
+  double2 r[3];
+  double2 sg[5];
+  double2 t[2];
 };
 
 // How a local-solve launch obtains its right-hand side and where results go.
@@ -199,10 +212,16 @@ struct DfArgs {
 // ---------------------------------------------------------------------------
 hipError_t launch_check_medium(const double* c, int n, int* bad, hipStream_t st);
 hipError_t launch_c_to_m(const double* c, double* m, int n, hipStream_t st);
-hipError_t launch_if_coef(const Geom& g, const double* m, const int32_t* pos_tab, IfCoef* coef, hipStream_t st);
-hipError_t launch_local_diag(const Geom& g, const double* m, const FaceTab* ft, const IfCoef* coef,
+// ta, tb: the (a, b) of the transmission condition d_n u - i alpha a u - (i b / alpha) d_tt u = g
+// ((1, 0) for the first-order condition)
+hipError_t launch_if_coef(const Geom& g, const double* m, const int32_t* pos_tab, double2 ta, IfCoef* coef,
+                          hipStream_t st);
+hipError_t launch_if_band(const Geom& g, const double* m, const int32_t* pos_tab, int order, double2 ta, double2 tb,
+                          const IfCoef* coef, IfBand* band, hipStream_t st);
+hipError_t launch_local_diag(const Geom& g, const double* m, const FaceTab* ft, const IfCoef* coef, const IfBand* band,
                              double2* diag, hipStream_t st);
-hipError_t launch_band_assemble(const Geom& g, const double2* diag, double2* ab, int nsub, hipStream_t st);
+hipError_t launch_band_assemble(const Geom& g, const double2* diag, const FaceTab* ft, const IfBand* band, double2* ab,
+                                int nsub, hipStream_t st);
 hipError_t launch_band_lu(const Geom& g, double2* ab, int32_t* ipiv, int32_t* info, int nsub, hipStream_t st);
 hipError_t launch_repack(const Geom& g, const SolveLayout& L, const double2* ab, const int32_t* ipiv,
                          double2* mf, int16_t* pf, int32_t* pflag, double2* mb, int nsub, hipStream_t st);
@@ -254,7 +273,7 @@ hipError_t launch_add_ranges(double2* y, const double2* x, const int32_t* ranges
 hipError_t launch_source_flags(const Geom& g, const double2* f, int nrhs, int32_t* nz, hipStream_t st);
 // dense scattering operators (row-block layout t_index); every entry of one launch carries the
 // same face mask; rblist: distinct row blocks holding rows of the masked faces
-hipError_t launch_build_T(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
+hipError_t launch_build_T(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfBand* band,
                           const double2* ybuf, size_t ystride, double2* T, hipStream_t st);
 template <typename C>
 hipError_t launch_scatter_apply(const Geom& g, const Entry* ent, int nent, int mask, const int32_t* rblist, int nrb,
@@ -274,8 +293,8 @@ int sweep_df_occupancy(int L, bool c64);
 hipError_t launch_build_W(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
                           const double2* ybuf, size_t ystride, double2* W, hipStream_t st);
 int lift_chunks(const Geom& g, int pchunk);
-hipError_t launch_lift_dense(const Geom& g, const FaceTab* ft, const double2* W, const double2* f, const int32_t* nz,
-                             int nrhs, int pchunk, double2* part, double2* b, hipStream_t st);
+hipError_t launch_lift_dense(const Geom& g, const FaceTab* ft, const IfBand* band, const double2* W, const double2* f,
+                             const int32_t* nz, int nrhs, int pchunk, double2* part, double2* b, hipStream_t st);
 // many right-hand sides: the same transmission part as one complex matrix product per
 // subdomain on MFMA (Gbuf: ndom * L * round16(nrhs) entries of workspace)
 hipError_t launch_recon_mm(const Geom& g, const IfCoef* coef, const FaceTab* ft, const double2* W, const double2* gin,

@@ -1,14 +1,15 @@
 // Dense lifting operators (paper Sec. 4, eq. (3)): the outgoing data b of the lifting
 // w_s = A_s^{-1} f_s with zero transmission data, as one matrix-vector product per subdomain
 // with a source, instead of a sequential banded solve on one compute unit.  The same matrices
-// give the transmission part of the reconstruction u_s = A_s^{-1} (f_s + B_s g) (Sec. 4):
-// A_s^{-1} B_s g = sum_row x_row g_row = sum_row W_s[.][row] (-inj_row / sigma_row) g_row.
+// give the transmission part of the reconstruction u_s = A_s^{-1} (f_s + B_s g) (Sec. 4).
 //
 // A_s is complex symmetric (A = A^T), so the row of A_s^{-1} at edge node n(row) equals the
 // column A_s^{-1} e_{n(row)} = x_row / inj_row, where x_row = A_s^{-1} B e_row is the unit-datum
-// solve already computed for the dense scattering operators.  The outgoing datum of row is
-// -sigma_row w_s[n(row)], hence
-//   b_row = sum_p W_s[p][row] f_s[p],   W_s[p][row] = -sigma_row x_row[p] / inj_row.
+// solve already computed for the dense scattering operators.  Stored: W_s[p][row] = x_row[p] /
+// inj_row.  Then
+//   lifting         y_row = sum_p W_s[p][row] f_s[p] = w_s[n(row)],  b = -Sigma y along each face
+//                   (first-order transmission: b_row = -sigma_row y_row);
+//   reconstruction  A_s^{-1} B_s g = sum_row x_row g_row = sum_row W_s[.][row] inj_row g_row.
 // Layout [s][p][row] (L rows contiguous per node p): a workgroup owns a chunk of nodes and
 // accumulates full L-vectors with coalesced loads and no cross-thread reduction; a second pass
 // adds the chunk partials in chunk order (deterministic).
@@ -19,7 +20,7 @@ namespace {
 constexpr int TE = 32;  // entries (interface positions) per transpose tile
 constexpr int TP = 32;  // nodes per transpose tile
 
-// W[s][p][col] = -sigma_col / inj_col * x_e[p] for the entries e = (s, col) of a batch.
+// W[s][p][col] = x_e[p] / inj_col for the entries e = (s, col) of a batch.
 // Tile of 32 entries x 32 nodes through LDS: coalesced reads along p, writes along col.
 __global__ __launch_bounds__(256) void k_build_W(Geom g, const Entry* ent, int nent, const FaceTab* ft,
                                                  const IfCoef* coef, const double2* ybuf, size_t ystride,
@@ -41,9 +42,7 @@ __global__ __launch_bounds__(256) void k_build_W(Geom g, const Entry* ent, int n
       local_if_face(g, col, &f, &ee);
       const int io = pick4(ft[s].in_off, f);
       if (io >= 0) {
-        const IfCoef c = coef[io + ee];
-        sc = cdiv(c.sigma, c.inj);
-        sc = mk(-sc.x, -sc.y);
+        sc = cdiv(mk(1.0, 0.0), coef[io + ee].inj);
       }
     }
     ss[threadIdx.x] = s;
@@ -124,38 +123,61 @@ __global__ __launch_bounds__(RT) void k_lift_partial(Geom g, const double2* __re
   }
 }
 
-// b[r][out position of row] = sum of the chunk partials; zero for subdomains without a source.
-// Workgroup = 32 rows x 8 chunk groups: group k adds chunks k, k + 8, ... in order, then the 8
-// group sums are added in group order (a fixed order: the result is deterministic).
-__global__ __launch_bounds__(RT) void k_lift_reduce(Geom g, const FaceTab* ft, const int32_t* nz,
+// b[r][out position of row] = -(Sigma y)_row along the row's face, y = the sum of the chunk
+// partials (w_s at the edge nodes); zero for subdomains without a source.  Workgroup = 32 output
+// rows; y is summed for those rows and two more on each side (Sigma reaches two entries along
+// the face) by 8 chunk groups: group k adds chunks k, k + 8, ... in order, then the 8 group sums
+// are added in group order (a fixed order: the result is deterministic).
+constexpr int kLiftHalo = 2;
+__global__ __launch_bounds__(RT) void k_lift_reduce(Geom g, const FaceTab* ft, const IfBand* band, const int32_t* nz,
                                                     const double2* part, int nchunk, double2* b) {
+  constexpr int NY = 32 + 2 * kLiftHalo;
   const int s = blockIdx.y, r = blockIdx.z;
   const int ndom = g.n1 * g.n2;
   const int L = local_if_len(g);
   const int lr = threadIdx.x % 32, k = threadIdx.x / 32;
-  const int row = blockIdx.x * 32 + lr;
+  const int r0 = blockIdx.x * 32 - kLiftHalo;  // first row of the y window
   const bool has = nz[(size_t)r * ndom + s] != 0;
-  __shared__ double2 red[8][33];
-  double2 acc = mk(0.0, 0.0);
-  if (has && row < L) {
-    const double2* ps = part + (size_t)(r * ndom + s) * nchunk * L + row;
-    for (int c = k; c < nchunk; c += 8) acc = cadd(acc, ps[(size_t)c * L]);
+  __shared__ double2 red[8][NY];
+  __shared__ double2 y[NY];
+  for (int w = lr; w < NY; w += 32) {
+    const int row = r0 + w;
+    double2 acc = mk(0.0, 0.0);
+    if (has && row >= 0 && row < L) {
+      const double2* ps = part + (size_t)(r * ndom + s) * nchunk * L + row;
+      for (int c = k; c < nchunk; c += 8) acc = cadd(acc, ps[(size_t)c * L]);
+    }
+    red[k][w] = acc;
   }
-  red[k][lr] = acc;
   __syncthreads();
+  if (k == 0) {
+    for (int w = lr; w < NY; w += 32) {
+      double2 t = red[0][w];
+      for (int q = 1; q < 8; ++q) t = cadd(t, red[q][w]);
+      y[w] = t;
+    }
+  }
+  __syncthreads();
+  const int row = blockIdx.x * 32 + lr;
   if (k == 0 && row < L) {
     int f, e;
     local_if_face(g, row, &f, &e);
-    const int oo = pick4(ft[s].out_off, f);
+    const FaceTab F = ft[s];
+    const int oo = pick4(F.out_off, f), io = pick4(F.in_off, f);
     if (oo >= 0) {
-      double2 t = red[0][lr];
-      for (int q = 1; q < 8; ++q) t = cadd(t, red[q][lr]);
-      b[(size_t)r * g.nif + oo + e] = t;
+      const IfBand B = band[io + e];
+      const int len = face_len(g, f);
+      double2 t = mk(0.0, 0.0);
+      for (int d = 0; d < 5; ++d) {
+        const int xx = e + d - 2;  // entry along the face; its row is row + d - 2
+        if (xx >= 0 && xx < len) cfma(t, B.sg[d], y[lr + d]);
+      }
+      b[(size_t)r * g.nif + oo + e] = mk(-t.x, -t.y);
     }
   }
 }
 
-// u_s[p] = (nz ? u_s[p] : 0) + sum_row W_s[p][row] gs_row with gs_row = -inj_row / sigma_row * g_row
+// u_s[p] = (nz ? u_s[p] : 0) + sum_row W_s[p][row] gs_row with gs_row = inj_row * g_row
 // (the incoming datum of the row's face; 0 on outer faces).  u_s already holds A_s^{-1} f_s for
 // the subdomains with a source.  A wavefront per node p reads its 8 KB row of W coalesced
 // (KL entries per lane) and reduces across lanes; each wavefront takes 8 nodes, 32 / KL at a time.
@@ -176,10 +198,7 @@ __global__ __launch_bounds__(RT) void k_recon_dense(Geom g, const FaceTab* ft, c
       local_if_face(g, col, &f, &e);
       const int io = pick4(F.in_off, f);
       if (io >= 0) {
-        const IfCoef c = coef[io + e];
-        double2 sc = cdiv(c.inj, c.sigma);
-        sc = mk(-sc.x, -sc.y);
-        v = cmul(sc, gin[(size_t)r * g.nif + io + e]);
+        v = cmul(coef[io + e].inj, gin[(size_t)r * g.nif + io + e]);
       }
     }
     gs[col] = v;
@@ -255,8 +274,8 @@ hipError_t launch_build_W(const Geom& g, const Entry* ent, int nent, const FaceT
 
 int lift_chunks(const Geom& g, int pchunk) { return (g.nloc + pchunk - 1) / pchunk; }
 
-hipError_t launch_lift_dense(const Geom& g, const FaceTab* ft, const double2* W, const double2* f, const int32_t* nz,
-                             int nrhs, int pchunk, double2* part, double2* b, hipStream_t st) {
+hipError_t launch_lift_dense(const Geom& g, const FaceTab* ft, const IfBand* band, const double2* W, const double2* f,
+                             const int32_t* nz, int nrhs, int pchunk, double2* part, double2* b, hipStream_t st) {
   const int L = local_if_len(g);
   if (pchunk > 1024 || L > 1024) return hipErrorInvalidValue;
   const int nchunk = lift_chunks(g, pchunk);
@@ -267,7 +286,7 @@ hipError_t launch_lift_dense(const Geom& g, const FaceTab* ft, const double2* W,
   else hipLaunchKernelGGL((k_lift_partial<4>), grid, dim3(RT), 0, st, g, W, f, nz, pchunk, nchunk, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_lift_reduce, dim3((L + 31) / 32, g.n1 * g.n2, nrhs), dim3(RT), 0, st, g, ft, nz, part, nchunk,
-                     b);
+  hipLaunchKernelGGL(k_lift_reduce, dim3((L + 31) / 32, g.n1 * g.n2, nrhs), dim3(RT), 0, st, g, ft, band, nz, part,
+                     nchunk, b);
   return hipGetLastError();
 }

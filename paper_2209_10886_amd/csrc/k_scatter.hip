@@ -14,8 +14,10 @@
 
 namespace {
 
-// Column e.rhs of T_s for every entry (s, col): x = A_s^{-1} B e_col is in ybuf[entry]
-__global__ void k_build_T(Geom g, const Entry* ent, const FaceTab* ft, const IfCoef* coef, const double2* ybuf,
+// Column e.rhs of T_s for every entry (s, col): x = A_s^{-1} B e_col is in ybuf[entry].  The
+// datum sent at the row's face entry ee is -sum_d R[ee][ee+d] g - sum_d Sigma[ee][ee+d] x along
+// that face (first order: -rho g - sigma x at ee only), with g the unit datum e_col.
+__global__ void k_build_T(Geom g, const Entry* ent, const FaceTab* ft, const IfBand* band, const double2* ybuf,
                           size_t ystride, double2* T) {
   const Entry e = ent[blockIdx.x];
   const FaceTab F = ft[e.s];
@@ -28,13 +30,15 @@ __global__ void k_build_T(Geom g, const Entry* ent, const FaceTab* ft, const IfC
     double2 v = mk(0.0, 0.0);
     const int io = pick4(F.in_off, f);
     if (io >= 0) {
-      const IfCoef c = coef[io + ee];
-      v = cmul(c.sigma, x[face_node(g, f, ee)]);
-      v = mk(-v.x, -v.y);
-      if (row == e.rhs) {
-        v.x -= c.rho.x;
-        v.y -= c.rho.y;
+      const IfBand B = band[io + ee];
+      const int len = face_len(g, f), c0 = face_off(g, f);
+      for (int d = 0; d < 5; ++d) {
+        const int xx = ee + d - 2;
+        if (xx >= 0 && xx < len) cfma(v, B.sg[d], x[face_node(g, f, xx)]);
       }
+      const int dc = e.rhs - c0 - ee + 1;  // the unit datum's entry relative to ee, shifted by 1
+      if (dc >= 0 && dc < 3) v = cadd(v, B.r[dc]);
+      v = mk(-v.x, -v.y);
     }
     Ts[t_index(L, row, e.rhs)] = v;
   }
@@ -198,10 +202,10 @@ __global__ __launch_bounds__(kTR * CG) void k_scatter_apply(Geom g, const Entry*
 
 }  // namespace
 
-hipError_t launch_build_T(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
+hipError_t launch_build_T(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfBand* band,
                           const double2* ybuf, size_t ystride, double2* T, hipStream_t st) {
   if (nent == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_build_T, dim3(nent), dim3(256), 0, st, g, ent, ft, coef, ybuf, ystride, T);
+  hipLaunchKernelGGL(k_build_T, dim3(nent), dim3(256), 0, st, g, ent, ft, band, ybuf, ystride, T);
   return hipGetLastError();
 }
 

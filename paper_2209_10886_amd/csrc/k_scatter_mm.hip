@@ -15,8 +15,8 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 typedef float f4v __attribute__((ext_vector_type(4)));
 
 // G[j][col][r] = incoming datum of subdomain subs[j] at local interface position col, column r
-// With coef, every datum is scaled by -inj / sigma of its position: the incoming data in the
-// form the lifting matrices W_s take for the reconstruction (x_col = W_s[.][col] (-inj / sigma)).
+// With coef, every datum is scaled by inj of its position: the incoming data in the form the
+// lifting matrices W_s take for the reconstruction (x_col = W_s[.][col] inj_col).
 __global__ void k_gather_incoming(Geom g, const int32_t* subs, const FaceTab* ft, const double2* gin, int nrhs,
                                   int rpad, double2* G, const IfCoef* coef) {
   const int j = blockIdx.y;
@@ -32,11 +32,7 @@ __global__ void k_gather_incoming(Geom g, const int32_t* subs, const FaceTab* ft
     double2 v = mk(0.0, 0.0);
     if (r < nrhs && io >= 0) {
       v = gin[(size_t)r * g.nif + io + ee];
-      if (coef) {
-        const IfCoef c = coef[io + ee];
-        double2 sc = cdiv(c.inj, c.sigma);
-        v = cmul(mk(-sc.x, -sc.y), v);
-      }
+      if (coef) v = cmul(coef[io + ee].inj, v);
     }
     G[(size_t)j * n + t] = v;
   }
@@ -168,7 +164,7 @@ __global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2)))
 }
 
 // Reconstruction for many right-hand sides on MFMA (complex128 on f64 16x16x4):
-//   U_s[p][r] = sum_col W_s[p][col] Gs[col][r]   (Gs: incoming data scaled by -inj / sigma)
+//   U_s[p][r] = sum_col W_s[p][col] Gs[col][r]   (Gs: incoming data scaled by inj)
 // and u[r] at node p of subdomain s = (nz ? u : 0) + U_s[p][r].  Workgroup = 4 wavefronts, each a
 // 16-node x 64-RHS tile (4 blocks of 16 RHS) over the whole k range; the loads of KB k-steps are
 // issued (clamped, unconditional) before their MFMAs.

@@ -108,6 +108,7 @@ struct hbj_ctx {
   // device tables
   FaceTab* ft = nullptr;
   IfCoef* coef = nullptr;
+  IfBand* band = nullptr;  // R / Sigma rows and tangential weights of the transmission condition
   int32_t* pos_tab = nullptr;
   double* m = nullptr;
   double2* diag = nullptr;
@@ -199,7 +200,7 @@ hbj_ctx::~hbj_ctx() {
   }
   dfree(rbl);
   dfree(df_err);
-  for (void* p : {(void*)ft, (void*)coef, (void*)pos_tab, (void*)m, (void*)diag, (void*)ranges_f, (void*)ranges_b,
+  for (void* p : {(void*)ft, (void*)coef, (void*)band, (void*)pos_tab, (void*)m, (void*)diag, (void*)ranges_f, (void*)ranges_b,
                   (void*)ab, (void*)ipiv, (void*)info, (void*)mf64, (void*)mb64, (void*)pf, (void*)pflag, (void*)mf32, (void*)mb32, (void*)T64, (void*)T32, (void*)Wl, (void*)lpart,
                   ybuf, (void*)nzf, (void*)Gbuf, (void*)rhs64, (void*)x64, (void*)r64, (void*)pc_y, (void*)pc_t})
     dfree(p);
@@ -803,7 +804,9 @@ int df_check(hbj_ctx* c) {
 
 // The lifting matrices serve few right-hand sides (one matrix-vector product each); many
 // right-hand sides keep the batched banded solves, which read each factor once per launch.
-bool dense_lift(const hbj_ctx* c, int nrhs) { return c->Wl && nrhs < kMatrixRhs; }
+// the second-order transmission's outgoing data need the field along whole faces, which only the
+// dense lifting provides (the banded trace extraction is first order)
+bool dense_lift(const hbj_ctx* c, int nrhs) { return c->Wl && (nrhs < kMatrixRhs || c->P.transmission == 2); }
 
 // lifting b = traces of A^{-1} f: subdomains whose source restriction is identically zero
 // contribute exactly zero and skip their solves
@@ -838,7 +841,8 @@ int run_lifting(hbj_ctx* c, Schedule* S, const double2* f, double2* b, int nrhs)
       double pairs = 0;
       for (size_t q = (size_t)r0 * c->ndom; q < (size_t)(r0 + nb) * c->ndom; ++q) pairs += nzh[q] != 0;
       ProfScope ps(c, HBJ_K_LIFT, pairs * (double)c->g.nloc * L * 16.0, pairs * 8.0 * c->g.nloc * L);
-      HIPCHK(launch_lift_dense(c->g, c->ft, c->Wl, f + (size_t)r0 * c->g.nx * c->g.ny, c->nzf + (size_t)r0 * c->ndom,
+      HIPCHK(launch_lift_dense(c->g, c->ft, c->band, c->Wl, f + (size_t)r0 * c->g.nx * c->g.ny,
+                               c->nzf + (size_t)r0 * c->ndom,
                                nb, kLiftChunk, c->lpart, b + (size_t)r0 * c->g.nif, c->st));
     }
     return HBJ_OK;
@@ -1632,10 +1636,22 @@ const char* hbj_strerror(int code) {
   }
 }
 
+// (a, b) of the second-order transmission condition d_n u - i alpha a u - (i b / alpha) d_tt u = g:
+// a = 1 + 0.2 i, b = 0.15 exp(-i pi / 4) (chosen by a sweep of block-Jacobi GMRES iterations on the
+// 5-point grid at 10 and 15 points per wavelength; the Taylor values (1, 1/2) let S expand the
+// grid-scale tangential modes)
+static const double2 kTransA = {1.0, 0.2};
+static const double2 kTransB = {0.15 * 0.70710678118654752, -0.15 * 0.70710678118654752};
+
+static int transmission_order(const hbj_ctx* c) { return c->P.transmission == 2 ? 2 : 1; }
+
 static int assemble_medium(hbj_ctx* c) {
   Geom& g = c->g;
-  HIPCHK(launch_if_coef(g, c->m, c->pos_tab, c->coef, c->st));
-  HIPCHK(launch_local_diag(g, c->m, c->ft, c->coef, c->diag, c->st));
+  const int order = transmission_order(c);
+  const double2 ta = order == 2 ? kTransA : mk(1.0, 0.0), tb = order == 2 ? kTransB : mk(0.0, 0.0);
+  HIPCHK(launch_if_coef(g, c->m, c->pos_tab, ta, c->coef, c->st));
+  HIPCHK(launch_if_band(g, c->m, c->pos_tab, order, ta, tb, c->coef, c->band, c->st));
+  HIPCHK(launch_local_diag(g, c->m, c->ft, c->coef, c->band, c->diag, c->st));
   c->factored = false;
   return HBJ_OK;
 }
@@ -1657,6 +1673,9 @@ int hbj_setup(const hbj_problem* prob, const double* c_dev, void* stream, hbj_ct
     return fail(HBJ_EINVAL, "bad operator form");
   if (P.sweep_exec != HBJ_SWEEP_DATAFLOW && P.sweep_exec != HBJ_SWEEP_STEPPED)
     return fail(HBJ_EINVAL, "bad sweep execution option");
+  if (P.transmission < 0 || P.transmission > 2) return fail(HBJ_EINVAL, "transmission order must be 0, 1 or 2");
+  if (P.transmission == 2 && P.operator_form != HBJ_OP_DENSE)
+    return fail(HBJ_EINVAL, "the second-order transmission needs the dense operator form");
   if (P.operator_form == HBJ_OP_DENSE && 2 * (P.nx / P.n1 + P.ny / P.n2) > 1024)
     return fail(HBJ_EINVAL, "dense operators need 2 (sub_nx + sub_ny) <= 1024");
   if ((size_t)P.nx * P.ny > (size_t)1 << 31) return fail(HBJ_EINVAL, "grid too large");
@@ -1710,7 +1729,8 @@ int hbj_setup(const hbj_problem* prob, const double* c_dev, void* stream, hbj_ct
   c->nranges_b = (int)rb.size() / 2;
   const size_t npts = (size_t)g.nx * g.ny;
   int* bad = nullptr;
-  if (dalloc(&c->ft, c->ndom) || dalloc(&c->coef, (size_t)g.nif) || dalloc(&c->pos_tab, pos_tab.size()) ||
+  if (dalloc(&c->ft, c->ndom) || dalloc(&c->coef, (size_t)g.nif) || dalloc(&c->band, (size_t)g.nif) ||
+      dalloc(&c->pos_tab, pos_tab.size()) ||
       dalloc(&c->m, npts) || dalloc(&c->diag, (size_t)c->ndom * g.nloc) || dalloc(&c->ranges_f, rf.size()) ||
       dalloc(&c->ranges_b, rb.size()) || dalloc(&c->info, (size_t)c->ndom) || dalloc(&bad, 1))
     return fail(HBJ_ENOMEM, "setup allocation failed");
@@ -1792,6 +1812,8 @@ static int build_dense(hbj_ctx* c) {
   if (!c->Wl && dalloc(&c->Wl, (size_t)c->ndom * g.nloc * L) != hipSuccess) {
     c->Wl = nullptr;
     (void)hipGetLastError();
+    if (c->P.transmission == 2)
+      return fail(HBJ_ENOMEM, "the second-order transmission needs the lifting matrices in device memory");
   }
   if (c->Wl) HIPCHK(launch_fill_zero(c->Wl, (size_t)c->ndom * g.nloc * L * sizeof(double2), c->st));
   HIPCHK(launch_fill_zero(c->T64, per * c->ndom * sizeof(double2), c->st));
@@ -1814,7 +1836,7 @@ static int build_dense(hbj_ctx* c) {
     if (he != hipSuccess) { rc = fail(HBJ_EHIP, hipGetErrorString(he)); break; }
     rc = run_solves<double>(c, dev, n, io);
     if (rc) break;
-    he = launch_build_T(g, dev, n, c->ft, c->coef, (const double2*)c->ybuf, (size_t)c->L.nblk * c->L.nb, c->T64,
+    he = launch_build_T(g, dev, n, c->ft, c->band, (const double2*)c->ybuf, (size_t)c->L.nblk * c->L.nb, c->T64,
                         c->st);
     if (he == hipSuccess && c->Wl)
       he = launch_build_W(g, dev, n, c->ft, c->coef, (const double2*)c->ybuf, (size_t)c->L.nblk * c->L.nb, c->Wl,
@@ -1847,7 +1869,7 @@ int hbj_factor(hbj_ctx* c) {
   c->factored = false;
   {
     ProfScope ps(c, HBJ_K_FACTOR, (double)nband * 16.0, 8.0 * c->ndom * (double)g.nloc * g.kl * g.kv);
-    HIPCHK(launch_band_assemble(g, c->diag, c->ab, c->ndom, c->st));
+    HIPCHK(launch_band_assemble(g, c->diag, c->ft, c->band, c->ab, c->ndom, c->st));
     HIPCHK(launch_band_lu(g, c->ab, c->ipiv, c->info, c->ndom, c->st));
   }
   std::vector<int32_t> info(c->ndom);

@@ -62,10 +62,13 @@ def test_setup_rejects_bad_options_on_the_host():
     lib = hbj._lib
     out = ctypes.c_void_p()
     bad = [dict(precond=5), dict(bj_width=-1), dict(bj_combine=2), dict(bj_compose=3), dict(operator_form=2),
-           dict(sweep_exec=2), dict(sweep_exec=-1)]
+           dict(sweep_exec=2), dict(sweep_exec=-1), dict(transmission=3), dict(transmission=-1),
+           dict(transmission=2, operator_form=0)]
     for kw in bad:
-        args = dict(precision=0, precond=2, bj_width=0, bj_combine=0, bj_compose=0, operator_form=0, sweep_exec=0)
+        args = dict(precision=0, precond=2, bj_width=0, bj_combine=0, bj_compose=0, operator_form=0, sweep_exec=0,
+                    transmission=0)
         args.update(kw)
         p = hbj.Problem(16, 16, 0.0, 10.0, 2, 2, args["precision"], args["precond"], args["bj_width"],
-                        args["bj_combine"], args["bj_compose"], args["operator_form"], args["sweep_exec"])
+                        args["bj_combine"], args["bj_compose"], args["operator_form"], args["sweep_exec"],
+                        args["transmission"])
         assert lib.hbj_setup(ctypes.byref(p), ctypes.c_void_p(16), None, ctypes.byref(out)) == hbj.EINVAL
