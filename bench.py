@@ -50,6 +50,8 @@ def parse():
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     p.add_argument("--no-banded", action="store_true", help="skip the banded-operator comparison")
     p.add_argument("--graphs", action="store_true", help="replay the GMRES iterations as HIP graphs")
+    p.add_argument("--no-second-order", action="store_true",
+                   help="skip the run with the second-order transmission condition")
     p.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle sample")
     return p.parse_args()
 
@@ -118,12 +120,13 @@ def cpu_baseline(wl, m, f, iters_gpu, target_s):
     }
 
 
-def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, profile_names, graphs=False):
+def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, profile_names, graphs=False,
+             transmission=1):
     """Setup + factor (untimed), warmup solves, timed solves, one profiled solve."""
     import torch
 
     ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=mt, precision=precision, precond=hbj.PC_BJ,
-                    operator_form=operator_form, device=mt.device)
+                    operator_form=operator_form, transmission=transmission, device=mt.device)
     ctx.set_graphs(graphs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -252,6 +255,7 @@ def main():
         f"{nsrc} right-hand side(s)")
     main_run = run_form(hbj, wl, mt, ft, u, headline_prec, hbj.OP_DENSE, args.steps, args.warmup, args.tol,
                         names64 if headline_prec == hbj.FP64 else names32, graphs=args.graphs)
+    u_main = u.clone()
     st = main_run["stats"]
     ms_per_step = main_run["seconds"] / max(args.steps, 1) * 1e3
     log(f"[bench] {ms_per_step:.2f} ms/solve, iters {st.iters}, relres {st.relres:.2e}, "
@@ -308,6 +312,20 @@ def main():
             result["banded_mixed"] = {
                 "solves_per_s": 1.0 / mb["seconds"], "iters": mb["stats"].iters,
                 "subdomain_solve_gbs": solve_gbs(mb["kernels"], [names32[hbj.K_FWD], names32[hbj.K_BWD]])}
+
+    if not args.no_second_order and nsrc == 1:
+        # the workload fixes the Robin transmission condition; the second-order one (interface faces
+        # only, same field) is measured beside it
+        log("[bench] second-order transmission condition (dense form, same precision)")
+        u1 = u_main
+        sr = run_form(hbj, wl, mt, ft, u, headline_prec, hbj.OP_DENSE, args.steps, 1, args.tol,
+                      names64 if headline_prec == hbj.FP64 else names32, graphs=args.graphs, transmission=2)
+        diff = float((torch.linalg.vector_norm(u - u1) / torch.linalg.vector_norm(u1)).item())
+        result["second_order_transmission"] = {
+            "solves_per_s": args.steps / sr["seconds"], "iters": sr["stats"].iters, "relres": sr["stats"].relres,
+            "factor_s": sr["factor_s"], "rel_diff_vs_robin_field": diff}
+        log(f"[bench] second order: {sr['seconds'] / args.steps * 1e3:.2f} ms/solve, iters {sr['stats'].iters}, "
+            f"field differs from the Robin run by {diff:.1e}")
 
     if not args.no_cpu:
         log("[bench] CPU oracle sample")

@@ -122,3 +122,41 @@ def test_fullsize_multi_source_sampled(hbj):
     say(f"  iters {st.iters}, relres {st.relres:.2e}, converged {st.converged}/64")
     assert st.converged == 64 and st.relres <= 1e-6
     ctx.close()
+
+
+@pytest.fixture(scope="module")
+def full2(hbj):
+    from oracle.dd import Decomposition
+    from oracle.fd import Grid
+
+    wl = W.FP64_1024
+    say(f"[fullsize order 2] {wl.name}: oracle decomposition with the second-order transmission")
+    m = W.slowness2(wl)
+    dd = Decomposition(Grid(wl.nx, wl.ny, wl.h, wl.k, m), wl.n1, wl.n2, transmission=2)
+    ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=torch.as_tensor(m, device="cuda"), precond=hbj.PC_BJ,
+                    operator_form=hbj.OP_DENSE, transmission=2)
+    ctx.factor()
+    torch.cuda.synchronize()
+    yield wl, m, dd, ctx
+    ctx.close()
+
+
+def test_fullsize_second_order(full2):
+    """Second-order transmission at 1024^2, 8 x 8: operator, lifting and reconstruction against the
+    oracle vector for vector; the FP64 solve to 1e-8 through the traces-residual property."""
+    wl, m, dd, ctx = full2
+    gv = W.random_interface_vector(ctx.nif, seed=44)
+    f = W.sources(wl)[0]
+    say("[fullsize order 2] operator, lifting, reconstruction")
+    assert rel(_np(ctx.apply_operator(torch.as_tensor(gv, device="cuda"))), dd.apply_operator(gv)) < 1e-12
+    assert rel(_np(ctx.lifting(torch.as_tensor(f, device="cuda"))), dd.lifting(f)) < 1e-12
+    u = _np(ctx.reconstruct(torch.as_tensor(f[None], device="cuda"), torch.as_tensor(gv[None], device="cuda")))[0]
+    assert rel(u, dd.reconstruct(f, gv)) < 1e-12
+    say("[fullsize order 2] FP64 solve, tol 1e-8")
+    u, st = ctx.solve(torch.as_tensor(f, device="cuda"), tol=1e-8)
+    assert st.relres <= 1e-8
+    gs = dd.traces_of(_np(u))
+    b = dd.lifting(f)
+    res = np.linalg.norm(dd.apply_operator(gs) - b) / np.linalg.norm(b)
+    say(f"  iters {st.iters}, relres {st.relres:.2e}, oracle interface residual of the traces {res:.2e}")
+    assert res < 1e-6
