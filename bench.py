@@ -52,6 +52,8 @@ def parse():
     p.add_argument("--graphs", action="store_true", help="replay the GMRES iterations as HIP graphs")
     p.add_argument("--no-second-order", action="store_true",
                    help="skip the run with the second-order transmission condition")
+    p.add_argument("--transmission", type=int, default=1, choices=(1, 2),
+                   help="transmission condition of the main run (1: Robin, as the workloads specify; 2: second order)")
     p.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle sample")
     return p.parse_args()
 
@@ -254,7 +256,8 @@ def main():
     log(f"[bench] {'FP64' if headline_prec == hbj.FP64 else 'mixed'}, dense scattering operators (headline), "
         f"{nsrc} right-hand side(s)")
     main_run = run_form(hbj, wl, mt, ft, u, headline_prec, hbj.OP_DENSE, args.steps, args.warmup, args.tol,
-                        names64 if headline_prec == hbj.FP64 else names32, graphs=args.graphs)
+                        names64 if headline_prec == hbj.FP64 else names32, graphs=args.graphs,
+                        transmission=args.transmission)
     u_main = u.clone()
     st = main_run["stats"]
     ms_per_step = main_run["seconds"] / max(args.steps, 1) * 1e3
@@ -280,7 +283,9 @@ def main():
                    "subdomain": [wl.sub_nx, wl.sub_ny], "points_per_wavelength": wl.ppw, "k": wl.k,
                    "medium": wl.medium, "sources": nsrc, "tol": args.tol,
                    "krylov": "GMRES(50), right-preconditioned, delayed reorthogonalisation", "preconditioner": "block Jacobi, width N1",
-                   "operator_form": "dense local scattering operators (formed at factor time)"},
+                   "operator_form": "dense local scattering operators (formed at factor time)",
+                   "transmission": "Robin (first order)" if args.transmission == 1 else
+                   "second order on interface faces"},
         "iters": st.iters,
         "relres": st.relres,
         "steps_per_pc": st.steps_per_pc,
@@ -313,7 +318,7 @@ def main():
                 "solves_per_s": 1.0 / mb["seconds"], "iters": mb["stats"].iters,
                 "subdomain_solve_gbs": solve_gbs(mb["kernels"], [names32[hbj.K_FWD], names32[hbj.K_BWD]])}
 
-    if not args.no_second_order and nsrc == 1:
+    if not args.no_second_order and nsrc == 1 and args.transmission == 1:
         # the workload fixes the Robin transmission condition; the second-order one (interface faces
         # only, same field) is measured beside it
         log("[bench] second-order transmission condition (dense form, same precision)")
