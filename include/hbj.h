@@ -114,8 +114,8 @@ typedef struct {
                             expansion of the one-way operator, with coefficients
                             that damp the grid-scale modes).  The outer faces keep
                             the absorbing condition, so the solution does not
-                            depend on it; 2 needs HBJ_OP_DENSE and device memory
-                            for the lifting matrices (HBJ_EINVAL / HBJ_ENOMEM)  */
+                            depend on it.  Any operator form; in the banded form the
+                            traces follow the solves in a second kernel            */
 } hbj_problem;
 
 typedef struct {

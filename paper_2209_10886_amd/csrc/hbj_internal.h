@@ -273,6 +273,10 @@ hipError_t launch_add_ranges(double2* y, const double2* x, const int32_t* ranges
 hipError_t launch_source_flags(const Geom& g, const double2* f, int nrhs, int32_t* nz, hipStream_t st);
 // dense scattering operators (row-block layout t_index); every entry of one launch carries the
 // same face mask; rblist: distinct row blocks holding rows of the masked faces
+// outgoing traces of masked faces from whole local fields x64 [entry][nloc] (the band rows of the
+// transmission condition), plus the field outputs of io
+hipError_t launch_emit_traces(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfBand* band,
+                              const SolveIO& io, const double2* x64, hipStream_t st);
 hipError_t launch_build_T(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfBand* band,
                           const double2* ybuf, size_t ystride, double2* T, hipStream_t st);
 template <typename C>
@@ -320,5 +324,6 @@ hipError_t launch_spread_adjoint(const double2* resid, const int32_t* rec, int n
                                  int nsrc, hipStream_t st);
 hipError_t launch_grad_accumulate(const Geom& g, const double* m, const double2* u, const double2* mu, int nsrc,
                                   double* grad, hipStream_t st);
-hipError_t launch_local_residual(const Geom& g, const Entry* ent, int nent, const double2* diag,
-                                 const double2* rhs64, const double2* x64, double2* r64, hipStream_t st);
+hipError_t launch_local_residual(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfBand* band,
+                                 const double2* diag, const double2* rhs64, const double2* x64, double2* r64,
+                                 hipStream_t st);

@@ -53,8 +53,11 @@ __global__ void k_grad_accumulate(Geom g, const double* m, const double2* u, con
 }
 
 // r = rhs - A_s x for every entry (complex128, matrix-free 5-point stencil + face diagonal)
-__global__ void k_local_residual(Geom g, const Entry* ent, const double2* diag, const double2* rhs64,
-                                 const double2* x64, double2* r64) {
+// r = rhs - A_s x with A_s the 5-point operator, the face diagonal terms (diag) and, for the
+// second-order transmission, the tangential couplings -s_{e,e+1} / h^2 between consecutive edge
+// nodes of each interface face (band weights; zero for the first-order condition).
+__global__ void k_local_residual(Geom g, const Entry* ent, const FaceTab* ft, const IfBand* band, const double2* diag,
+                                 const double2* rhs64, const double2* x64, double2* r64) {
   const int slot = blockIdx.y;
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= g.nloc) return;
@@ -70,6 +73,15 @@ __global__ void k_local_residual(Geom g, const Entry* ent, const double2* diag, 
   if (ly < g.sny - 1) nb = cadd(nb, x[l + g.snx]);
   ax.x += off * nb.x;
   ax.y += off * nb.y;
+  const FaceTab F = ft[s];
+  const bool on[4] = {lx == 0, lx == g.snx - 1, ly == 0, ly == g.sny - 1};
+  for (int f = 0; f < 4; ++f) {
+    if (!on[f] || F.in_off[f] < 0) continue;
+    const int e = f < 2 ? ly : lx, len = f < 2 ? g.sny : g.snx, step = f < 2 ? g.snx : 1;
+    const IfBand& B = band[F.in_off[f] + e];
+    if (e > 0) cfma(ax, mk(off * B.t[0].x, off * B.t[0].y), x[l - step]);
+    if (e < len - 1) cfma(ax, mk(off * B.t[1].x, off * B.t[1].y), x[l + step]);
+  }
   const double2 b = rhs64[(size_t)slot * g.nloc + l];
   r64[(size_t)slot * g.nloc + l] = mk(b.x - ax.x, b.y - ax.y);
 }
@@ -98,10 +110,11 @@ hipError_t launch_grad_accumulate(const Geom& g, const double* m, const double2*
   return hipGetLastError();
 }
 
-hipError_t launch_local_residual(const Geom& g, const Entry* ent, int nent, const double2* diag,
-                                 const double2* rhs64, const double2* x64, double2* r64, hipStream_t st) {
+hipError_t launch_local_residual(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfBand* band,
+                                 const double2* diag, const double2* rhs64, const double2* x64, double2* r64,
+                                 hipStream_t st) {
   if (nent == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_local_residual, dim3((g.nloc + 255) / 256, nent), dim3(256), 0, st, g, ent, diag, rhs64, x64,
-                     r64);
+  hipLaunchKernelGGL(k_local_residual, dim3((g.nloc + 255) / 256, nent), dim3(256), 0, st, g, ent, ft, band, diag,
+                     rhs64, x64, r64);
   return hipGetLastError();
 }

@@ -355,7 +355,10 @@ __global__ void k_build_rhs(Geom g, const Entry* ent, const FaceTab* ft, const I
 }
 
 // outgoing traces of complex128 local solutions x64 [entry][nloc]
-__global__ void k_emit_traces(Geom g, const Entry* ent, const FaceTab* ft, const IfCoef* coef, SolveIO io,
+// Outgoing traces of every masked face from whole local fields x64[slot] (after the solves):
+// -sum_d R[e][e+d] g - sum_d Sigma[e][e+d] x along the face (the band rows of the transmission
+// condition; first order: -rho g - sigma x at the node), then the field outputs of io.
+__global__ void k_emit_traces(Geom g, const Entry* ent, const FaceTab* ft, const IfBand* band, SolveIO io,
                               const double2* x64) {
   const int slot = blockIdx.y;
   const int l = blockIdx.x * blockDim.x + threadIdx.x;
@@ -366,7 +369,34 @@ __global__ void k_emit_traces(Geom g, const Entry* ent, const FaceTab* ft, const
   const FaceTab F = ft[e.s];
   const double2* gin = e.src ? io.g_b : io.g_a;
   if (gin) gin += (size_t)e.rhs * g.nif;
-  emit(g, e, F, coef, io, gin, slot, l, x64[(size_t)slot * g.nloc + l]);
+  const double2* xs = x64 + (size_t)slot * g.nloc;
+  emit_field(g, e, io, slot, l, xs[l]);
+  if (!io.tr_dst) return;
+  const bool on[4] = {lx == 0, lx == g.snx - 1, ly == 0, ly == g.sny - 1};
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    if (!on[f] || !((e.mask >> f) & 1) || F.out_off[f] < 0) continue;
+    const int ee = (f < 2) ? ly : lx;
+    const int len = f < 2 ? g.sny : g.snx;
+    const int qi = F.in_off[f] + ee, qo = F.out_off[f] + ee;
+    const IfBand B = band[qi];
+    double2 val = mk(0.0, 0.0);
+    for (int d = 0; d < 5; ++d) {
+      const int xx = ee + d - 2;
+      if (xx >= 0 && xx < len) cfma(val, B.sg[d], xs[face_node(g, f, xx)]);
+    }
+    if (io.tr_reflect && gin)
+      for (int d = 0; d < 3; ++d) {
+        const int xx = ee + d - 1;
+        if (xx >= 0 && xx < len) cfma(val, B.r[d], gin[F.in_off[f] + xx]);
+      }
+    val = mk(-val.x, -val.y);
+    const size_t o = (size_t)e.rhs * g.nif + qo;
+    double2 base = io.tr_base ? io.tr_base[o] : mk(0.0, 0.0);
+    base.x += io.tr_sign * val.x;
+    base.y += io.tr_sign * val.y;
+    io.tr_dst[o] = base;
+  }
 }
 
 // x64 += dx for complex64 corrections held in the solve buffer [entry][nblk * nb]
@@ -442,10 +472,10 @@ hipError_t launch_build_rhs(const Geom& g, const Entry* ent, int nent, const Fac
   return hipGetLastError();
 }
 
-hipError_t launch_emit_traces(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
+hipError_t launch_emit_traces(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfBand* band,
                               const SolveIO& io, const double2* x64, hipStream_t st) {
   if (nent == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_emit_traces, dim3((g.nloc + 255) / 256, nent), dim3(256), 0, st, g, ent, ft, coef, io, x64);
+  hipLaunchKernelGGL(k_emit_traces, dim3((g.nloc + 255) / 256, nent), dim3(256), 0, st, g, ent, ft, band, io, x64);
   return hipGetLastError();
 }
 

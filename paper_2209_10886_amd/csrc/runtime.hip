@@ -150,6 +150,8 @@ struct hbj_ctx {
   size_t ybuf_bytes = 0;
   double2* rhs64 = nullptr;  // mixed: local right-hand sides / residuals
   double2* x64 = nullptr;
+  double2* xtr = nullptr;  // local fields of a banded batch whose traces follow the second-order condition
+  size_t xtr_entries = 0;
   double2* r64 = nullptr;
   size_t loc64_entries = 0;
   double2* Gbuf = nullptr;  // gathered incoming data for the many-right-hand-side operators
@@ -202,7 +204,7 @@ hbj_ctx::~hbj_ctx() {
   dfree(df_err);
   for (void* p : {(void*)ft, (void*)coef, (void*)band, (void*)pos_tab, (void*)m, (void*)diag, (void*)ranges_f, (void*)ranges_b,
                   (void*)ab, (void*)ipiv, (void*)info, (void*)mf64, (void*)mb64, (void*)pf, (void*)pflag, (void*)mf32, (void*)mb32, (void*)T64, (void*)T32, (void*)Wl, (void*)lpart,
-                  ybuf, (void*)nzf, (void*)Gbuf, (void*)rhs64, (void*)x64, (void*)r64, (void*)pc_y, (void*)pc_t})
+                  ybuf, (void*)nzf, (void*)Gbuf, (void*)rhs64, (void*)x64, (void*)xtr, (void*)r64, (void*)pc_y, (void*)pc_t})
     dfree(p);
   if (ev0) (void)hipEventDestroy(ev0);
   if (ev1) (void)hipEventDestroy(ev1);
@@ -453,11 +455,30 @@ double bwd_bytes(const hbj_ctx* c, size_t elem) { return (double)c->g.nloc * (c-
 // batched local solves
 // ---------------------------------------------------------------------------
 template <typename R>
-int run_solves(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io) {
+int run_solves(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io_in) {
   typedef typename Cplx<R>::T C;
   if (nent == 0) return HBJ_OK;
   int rc = ensure_ybuf(c, nent, sizeof(C));
   if (rc) return rc;
+  // second-order transmission: the data sent across a face need the field along the whole face,
+  // so the solves write the local fields and the traces follow from them in a second kernel
+  SolveIO io = io_in;
+  double2* field = nullptr;
+  if (io_in.tr_dst && c->P.transmission == 2) {
+    field = io_in.x64;
+    if (!field) {
+      if ((size_t)nent > c->xtr_entries) {
+        dfree(c->xtr);
+        c->xtr = nullptr;
+        c->xtr_entries = 0;
+        if (dalloc(&c->xtr, (size_t)nent * c->g.nloc)) return fail(HBJ_ENOMEM, "trace workspace allocation failed");
+        c->xtr_entries = nent;
+      }
+      field = c->xtr;
+    }
+    io.tr_dst = nullptr;
+    io.x64 = field;
+  }
   const C* mf;
   const C* mb;
   if constexpr (sizeof(R) == 8) {
@@ -474,6 +495,12 @@ int run_solves(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io) {
   {
     ProfScope ps(c, HBJ_K_BWD, nent * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1));
     HIPCHK((launch_bwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st)));
+  }
+  if (field) {
+    SolveIO tio = io_in;
+    tio.u = nullptr;
+    tio.x64 = nullptr;
+    HIPCHK(launch_emit_traces(c->g, ent, nent, c->ft, c->band, tio, field, c->st));
   }
   c->local_solves += nent;
   return HBJ_OK;
@@ -804,9 +831,7 @@ int df_check(hbj_ctx* c) {
 
 // The lifting matrices serve few right-hand sides (one matrix-vector product each); many
 // right-hand sides keep the batched banded solves, which read each factor once per launch.
-// the second-order transmission's outgoing data need the field along whole faces, which only the
-// dense lifting provides (the banded trace extraction is first order)
-bool dense_lift(const hbj_ctx* c, int nrhs) { return c->Wl && (nrhs < kMatrixRhs || c->P.transmission == 2); }
+bool dense_lift(const hbj_ctx* c, int nrhs) { return c->Wl && nrhs < kMatrixRhs; }
 
 // lifting b = traces of A^{-1} f: subdomains whose source restriction is identically zero
 // contribute exactly zero and skip their solves
@@ -1099,8 +1124,6 @@ int pc_op(hbj_ctx* c, Schedule* S, const double2* v, double2* z, double2* w, int
 // ===========================================================================
 hipError_t launch_build_rhs(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
                             const SolveIO& io, double2* rhs64, hipStream_t st);
-hipError_t launch_emit_traces(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
-                              const SolveIO& io, const double2* x64, hipStream_t st);
 hipError_t launch_axpy_c64(double2* x64, const float2* dx, const Geom& g, const SolveLayout& L, int nent,
                            hipStream_t st);
 
@@ -1133,7 +1156,7 @@ int op_mixed(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
     }
     c->local_solves += nent;
     HIPCHK(launch_axpy_c64(c->x64, (const float2*)c->ybuf, c->g, c->L, nent, c->st));
-    HIPCHK(launch_local_residual(c->g, ent, nent, c->diag, c->rhs64, c->x64, c->r64, c->st));
+    HIPCHK(launch_local_residual(c->g, ent, nent, c->ft, c->band, c->diag, c->rhs64, c->x64, c->r64, c->st));
   }
   c->last_ir = kLocalRefine + 1;
   SolveIO tio{};
@@ -1142,7 +1165,7 @@ int op_mixed(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
   tio.tr_base = g;
   tio.tr_sign = -1.0;
   tio.tr_reflect = 1;
-  HIPCHK(launch_emit_traces(c->g, ent, nent, c->ft, c->coef, tio, c->x64, c->st));
+  HIPCHK(launch_emit_traces(c->g, ent, nent, c->ft, c->band, tio, c->x64, c->st));
   return HBJ_OK;
 }
 
@@ -1674,8 +1697,6 @@ int hbj_setup(const hbj_problem* prob, const double* c_dev, void* stream, hbj_ct
   if (P.sweep_exec != HBJ_SWEEP_DATAFLOW && P.sweep_exec != HBJ_SWEEP_STEPPED)
     return fail(HBJ_EINVAL, "bad sweep execution option");
   if (P.transmission < 0 || P.transmission > 2) return fail(HBJ_EINVAL, "transmission order must be 0, 1 or 2");
-  if (P.transmission == 2 && P.operator_form != HBJ_OP_DENSE)
-    return fail(HBJ_EINVAL, "the second-order transmission needs the dense operator form");
   if (P.operator_form == HBJ_OP_DENSE && 2 * (P.nx / P.n1 + P.ny / P.n2) > 1024)
     return fail(HBJ_EINVAL, "dense operators need 2 (sub_nx + sub_ny) <= 1024");
   if ((size_t)P.nx * P.ny > (size_t)1 << 31) return fail(HBJ_EINVAL, "grid too large");
@@ -1812,8 +1833,6 @@ static int build_dense(hbj_ctx* c) {
   if (!c->Wl && dalloc(&c->Wl, (size_t)c->ndom * g.nloc * L) != hipSuccess) {
     c->Wl = nullptr;
     (void)hipGetLastError();
-    if (c->P.transmission == 2)
-      return fail(HBJ_ENOMEM, "the second-order transmission needs the lifting matrices in device memory");
   }
   if (c->Wl) HIPCHK(launch_fill_zero(c->Wl, (size_t)c->ndom * g.nloc * L * sizeof(double2), c->st));
   HIPCHK(launch_fill_zero(c->T64, per * c->ndom * sizeof(double2), c->st));

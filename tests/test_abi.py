@@ -62,8 +62,7 @@ def test_setup_rejects_bad_options_on_the_host():
     lib = hbj._lib
     out = ctypes.c_void_p()
     bad = [dict(precond=5), dict(bj_width=-1), dict(bj_combine=2), dict(bj_compose=3), dict(operator_form=2),
-           dict(sweep_exec=2), dict(sweep_exec=-1), dict(transmission=3), dict(transmission=-1),
-           dict(transmission=2, operator_form=0)]
+           dict(sweep_exec=2), dict(sweep_exec=-1), dict(transmission=3), dict(transmission=-1)]
     for kw in bad:
         args = dict(precision=0, precond=2, bj_width=0, bj_combine=0, bj_compose=0, operator_form=0, sweep_exec=0,
                     transmission=0)

@@ -5,7 +5,8 @@ sent across faces (R and Sigma bands along each face) and, with them, the dense 
 lifting and the reconstruction. Each is compared with the oracle's decomposition built with the
 same condition, at the tolerances of the first-order tests; the solve is checked against the
 global direct solution (the condition does not change the global problem). Cases: aligned
-(32^2 subdomains), ragged (10 x 10), rectangular (16 x 12) and the 5 x 10 strip (8 x 8).
+(32^2 subdomains), ragged (10 x 10), rectangular (16 x 12) and the 5 x 10 strip (8 x 8), in the dense and
+the banded operator forms.
 """
 import numpy as np
 import pytest
@@ -37,7 +38,9 @@ def ctx2(hbj):
             m = W.slowness2(wl)
             g = Grid(wl.nx, wl.ny, wl.h, wl.k, m)
             dd = Decomposition(g, wl.n1, wl.n2, transmission=2)
-            ctx = gpu_context(hbj, wl, m, operator_form=hbj.OP_DENSE, transmission=2, **kw)
+            kw2 = dict(kw)
+            kw2.setdefault("operator_form", hbj.OP_DENSE)
+            ctx = gpu_context(hbj, wl, m, transmission=2, **kw2)
             ctx.factor()
             torch.cuda.synchronize()
             cache[key] = (wl, m, g, dd, ctx)
@@ -133,9 +136,21 @@ def test_second_order_needs_fewer_iterations(ctx2, hbj):
     c1.close()
 
 
-def test_second_order_rejected_for_banded_form(hbj):
-    wl = W.SMALL
-    with pytest.raises(hbj.HbjError) as ei:
-        hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=torch.as_tensor(W.slowness2(wl), device="cuda"),
-                  operator_form=hbj.OP_BANDED, transmission=2)
-    assert ei.value.code == hbj.EINVAL
+@pytest.mark.parametrize("name,precision", [("grf256", 0), ("ragged", 0), ("strip", 0), ("grf256", 1)])
+def test_second_order_banded_form(ctx2, hbj, name, precision):
+    """Banded local solves: the traces follow the solves in a second kernel (whole-face fields);
+    mixed precision refines the complex64 solves before the traces are taken."""
+    from oracle import solver, sweep
+
+    wl, m, g, dd, ctx = ctx2(name, operator_form=hbj.OP_BANDED, precision=precision)
+    gv = W.random_interface_vector(ctx.nif, seed=24)
+    f = W.sources(wl)[0]
+    say(f"[order 2 banded] case={name} precision={precision}")
+    assert rel(_np(ctx.apply_operator(torch.as_tensor(gv, device="cuda"))), dd.apply_operator(gv)) < 1e-11
+    assert rel(_np(ctx.lifting(torch.as_tensor(f, device="cuda"))), dd.lifting(f)) < 1e-12
+    if precision == 0:
+        z = _np(ctx.apply_preconditioner(torch.as_tensor(gv, device="cuda")))
+        assert rel(z, sweep.apply_bj(dd, gv)) < 1e-11
+    u, st = ctx.solve(torch.as_tensor(f, device="cuda"), tol=1e-12, maxit=3000)
+    assert st.relres <= 1e-12
+    assert rel(_np(u), solver.direct(g, f)) < 1e-8
