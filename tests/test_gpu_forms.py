@@ -113,15 +113,17 @@ def _data(wl, m_true, f, rec):
     return np.ascontiguousarray(u.reshape(f.shape[0], -1)[:, rec])
 
 
-@pytest.mark.parametrize("nx,n1,nsrc", [(64, 4, 3), (512, 8, 16)])
-def test_gradient_matches_oracle_direct(hbj, nx, n1, nsrc):
+@pytest.mark.parametrize("nx,n1,nsrc,transmission", [(64, 4, 3, 1), (512, 8, 16, 1), (128, 4, 3, 2)])
+def test_gradient_matches_oracle_direct(hbj, nx, n1, nsrc, transmission):
     from oracle import gradient
     from oracle.fd import Grid
 
     wl, m_true, m0, f, rec = _gradient_problem(nx, n1, nsrc)
     d = _data(wl, m_true, f, rec)
-    say(f"[gradient] nx={nx} {n1}x{n1} sources={nsrc}")
-    ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=torch.as_tensor(m0, device="cuda"))
+    say(f"[gradient] nx={nx} {n1}x{n1} sources={nsrc} transmission={transmission}")
+    # the interface condition changes the iteration, not the global problem nor its adjoint
+    ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=torch.as_tensor(m0, device="cuda"),
+                    transmission=transmission)
     ctx.factor()
     loss, grad = ctx.gradient(torch.as_tensor(f, device="cuda"), torch.as_tensor(rec, device="cuda"),
                               torch.as_tensor(d, device="cuda"), tol=1e-12)
