@@ -310,6 +310,25 @@ enum { HBJ_ORTH_CGS2 = 0, HBJ_ORTH_DCGS2 = 1 };
 int hbj_set_orthogonalization(hbj_ctx* ctx, int32_t mode);
 
 /*
+ * hbj_set_multi_solve - how the banded local solves (Sec. 4: every application of the
+ * operator, of the preconditioner, the lifting and the reconstruction is a batch of solves
+ * u = A_s^{-1} rhs) run when a batch holds many right-hand sides per subdomain:
+ *   HBJ_MSOLVE_CHAINS  one workgroup per (subdomain, right-hand side), vector FMAs;
+ *   HBJ_MSOLVE_MFMA    up to 16 right-hand sides of one subdomain per workgroup: each column
+ *                      block of the triangular solves is one complex matrix product on the
+ *                      matrix cores, and the factors are read once per 16 right-hand sides.
+ *                      Used where a batch averages at least 8 right-hand sides per
+ *                      subdomain (the formation of the dense operators at hbj_factor, with
+ *                      one right-hand side per interface position; solves of 8 or more
+ *                      sources in the banded form).  Default.
+ * Both give the same solutions up to rounding.  Takes effect at the next call (the dense
+ * operators: at the next hbj_factor).  A change drops captured graphs.  Returns HBJ_EINVAL
+ * for any other value.
+ */
+enum { HBJ_MSOLVE_CHAINS = 0, HBJ_MSOLVE_MFMA = 1 };
+int hbj_set_multi_solve(hbj_ctx* ctx, int32_t mode);
+
+/*
  * hbj_get_tuning - choices of the autotuner of the many-right-hand-side operator
  * kernel (dense form, 4 or more right-hand sides).  On its first launch of each
  * kind the library times every tile depth (k-steps per batch of loads: 2, 4, 8)

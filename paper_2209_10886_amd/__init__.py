@@ -33,6 +33,7 @@ BJ_PRODUCT, BJ_RESIDUAL = 0, 1
 OP_BANDED, OP_DENSE = 0, 1
 SWEEP_STEPPED, SWEEP_DATAFLOW = 0, 1
 ORTH_CGS2, ORTH_DCGS2 = 0, 1  # Gram-Schmidt variant of the Arnoldi steps
+MSOLVE_CHAINS, MSOLVE_MFMA = 0, 1  # banded solves of many right-hand sides per subdomain
 OK, EINVAL, ESTATE, EHIP, ENOMEM, EWAIT, ZERO_PIVOT, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, 1, 2
 K_FWD, K_BWD, K_FACTOR, K_KRYLOV, K_SCATTER, K_SWEEP, K_LIFT, K_OPERATOR = 0, 1, 2, 3, 4, 5, 6, 7
 
@@ -89,6 +90,7 @@ _SIGS = {
     "hbj_get_tuning": (_I, [_P, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)]),
     "hbj_set_graphs": (_I, [_P, _I32]),
     "hbj_set_orthogonalization": (_I, [_P, _I32]),
+    "hbj_set_multi_solve": (_I, [_P, _I32]),
     "hbj_strerror": (ctypes.c_char_p, [_I]),
     "hbj_last_error": (ctypes.c_char_p, []),
     "hbj_destroy": (None, [_P]),
@@ -289,6 +291,12 @@ class Context:
         """ORTH_CGS2 (classical Gram-Schmidt twice) or ORTH_DCGS2 (delayed reorthogonalisation,
         default) for the Arnoldi steps."""
         _check(_lib.hbj_set_orthogonalization(self._h, int(mode)))
+
+    def set_multi_solve(self, mode):
+        """MSOLVE_CHAINS (one workgroup per subdomain and right-hand side) or MSOLVE_MFMA (16
+        right-hand sides of one subdomain per workgroup on the matrix cores, default) for batches
+        of banded solves with many right-hand sides per subdomain."""
+        _check(_lib.hbj_set_multi_solve(self._h, int(mode)))
 
     def tuning(self):
         """Autotuned tile depths of the many-RHS operator kernel and their measured us per launch."""

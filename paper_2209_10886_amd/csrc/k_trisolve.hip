@@ -410,6 +410,357 @@ __global__ void k_axpy_c64(double2* x64, const float2* dx, int nloc, int stride)
   x.y += (double)d.y;
 }
 
+// ---------------------------------------------------------------------------
+// Many right-hand sides of one subdomain per workgroup, on MFMA.
+//
+// A tile is a run of up to 16 entries of a launch that share one subdomain.  For those right-hand
+// sides the block recurrence of k_fwd / k_bwd becomes one complex matrix product per column
+// block, acc = M_b (window rows x 16) * X_b (16 x 16 right-hand sides), X_b being the rows of the
+// window that the block eliminates; each complex k-step is four real 16x16x4 MFMAs (Re += Ar Br -
+// Ai Bi, Im += Ar Bi + Ai Br).  The window is padded to NT whole tiles of 16 rows (padding rows
+// have zero multipliers and only carry their values) and lives in the MFMA accumulators: physical
+// tile p belongs to wavefront p % 4 and the window slides by renaming (logical tile t of a block
+// is a fixed physical tile shifted by the block index modulo NT), so no row ever moves between
+// registers.  Per block every wavefront multiplies its tiles by X_b; the tile that becomes the
+// next block's X is written to LDS, double-buffered, so one barrier per block suffices.  Blocks
+// with row interchanges pass the window through LDS.  Lane l works on right-hand side l % 16; the
+// loads of the next block's multipliers and of the rows entering the window are issued before the
+// current block's products.
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename C, typename R>
+__device__ inline C mkc(R x, R y) {
+  C v;
+  v.x = x;
+  v.y = y;
+  return v;
+}
+
+template <typename R> struct TriMma;
+template <> struct TriMma<double> {
+  typedef d4v V;
+  static __device__ inline V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  // accumulator register r of lane l holds row row_of(l, r), column l % 16
+  static __device__ inline int row_of(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <> struct TriMma<float> {
+  typedef f4v V;
+  static __device__ inline V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ inline int row_of(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+// acc += A (16 x 16, this lane's row j and k-steps in a[]) * X (x[] = this lane's B operands)
+template <typename R>
+__device__ inline void tile_mma(const typename Cplx<R>::T (&a)[4], R ok, const R (&xr)[4], const R (&xi)[4],
+                                typename TriMma<R>::V& wr, typename TriMma<R>::V& wi) {
+  typedef TriMma<R> T;
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    const R ar = (R)a[ks].x * ok, ai = (R)a[ks].y * ok;
+    wr = T::mma(ar, xr[ks], wr);
+    wi = T::mma(ar, xi[ks], wi);
+    wr = T::mma(-ai, xi[ks], wr);
+    wi = T::mma(ai, xr[ks], wi);
+  }
+}
+
+template <typename R, int SPW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_fwd_mm(
+    Geom g, SolveLayout L, const Entry* ent, const int2* tiles, const FaceTab* ft, const IfCoef* coef,
+    const typename Cplx<R>::T* __restrict__ MF, const int16_t* __restrict__ PF, const int32_t* __restrict__ PFL,
+    SolveIO io, typename Cplx<R>::T* __restrict__ ybuf) {
+  typedef typename Cplx<R>::T C;
+  typedef TriMma<R> T;
+  typedef typename T::V V;
+  extern __shared__ unsigned char smem_raw[];
+  const int nblk = L.nblk, wf = L.wf, NT = (wf + 15) >> 4, ylen = nblk * 16;
+  C* xsh = reinterpret_cast<C*>(smem_raw);                   // [2][16 rows][16 right-hand sides]
+  int* ident = reinterpret_cast<int*>(xsh + 512);            // [nblk]
+  C* wsh = reinterpret_cast<C*>(ident + ((nblk + 3) & ~3));  // [NT * 16 rows][16]: interchanges
+  const int2 tl = make_int2(__builtin_amdgcn_readfirstlane(tiles[blockIdx.x].x),
+                            __builtin_amdgcn_readfirstlane(tiles[blockIdx.x].y));  // first entry, count (1..16)
+  const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool mine = j < tl.y;  // lanes past the count work on a copy of the first entry, unstored
+  const int slot = tl.x + (mine ? j : 0);
+  const Entry e = ent[slot];
+  const int s = __builtin_amdgcn_readfirstlane(ent[tl.x].s);
+  const FaceTab F = ft[s];
+  const bool zero = !mine || (io.nz && !io.nz[(size_t)e.rhs * g.n1 * g.n2 + e.s]);
+  const RhsCtx rhs(g, e, F, coef, io, slot);
+  const C* M = MF + (size_t)s * L.mf_per_sub;
+  const int16_t* P = PF + (size_t)s * L.pf_per_sub;
+  C* y = ybuf + (size_t)slot * ylen;
+  for (int b = threadIdx.x; b < nblk; b += 256) ident[b] = PFL[(size_t)s * nblk + b];
+
+  auto fresh = [&](int row0, C(&v)[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int l = row0 + T::row_of(lane, r);
+      v[r] = (zero || l >= ylen) ? czero<C>() : to_c<C>(rhs(l));
+    }
+  };
+  // multipliers of logical tile t of block b: row 16 t + j, columns 4 ks + q (clamped, masked at use)
+  auto load_a = [&](int b, int t, C(&a)[4]) {
+    const C* Mb = M + (size_t)b * 16 * wf;
+    const int r = min(16 * t + j, wf - 1);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) a[ks] = Mb[tile_index(4 * ks + q, r, wf, 16, L.cgf)];
+  };
+  auto logical = [&](int p, int bm) { return p >= bm ? p - bm : p - bm + NT; };
+
+  V wr[SPW], wi[SPW];
+  C acur[SPW][4], anxt[SPW][4];
+  C fr[4], frn[4];
+#pragma unroll
+  for (int si = 0; si < SPW; ++si) {
+    const int p = w + 4 * si;
+    if (p >= NT) continue;
+    C v[4];
+    fresh(16 * p, v);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      wr[si][r] = (R)v[r].x;
+      wi[si][r] = (R)v[r].y;
+    }
+    load_a(0, p, acur[si]);
+  }
+  fresh(NT * 16, fr);
+  if (w == 0) {  // X of block 0: logical tile 0 = physical tile 0 (wavefront 0, slot 0)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) xsh[T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[0][r], wi[0][r]);
+  }
+  __syncthreads();
+
+  int bm = 0;  // b mod NT
+  for (int b = 0; b < nblk; ++b) {
+    const int par = b & 1;
+    const int bn = min(b + 1, nblk - 1), bmn = (bm + 1 == NT) ? 0 : bm + 1;
+#pragma unroll
+    for (int si = 0; si < SPW; ++si) {
+      const int p = w + 4 * si;
+      if (p < NT) load_a(bn, logical(p, bmn), anxt[si]);
+    }
+    fresh((b + 1 + NT) * 16, frn);
+    R xr[4], xi[4];
+    if (!__builtin_amdgcn_readfirstlane(ident[b])) {  // row interchanges in this block: gather the window rows through LDS
+#pragma unroll
+      for (int si = 0; si < SPW; ++si) {
+        const int p = w + 4 * si;
+        if (p >= NT) continue;
+        const int t = logical(p, bm);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wsh[(16 * t + T::row_of(lane, r)) * 16 + j] = mkc<C, R>(wr[si][r], wi[si][r]);
+      }
+      __syncthreads();
+      const int16_t* Pb = P + (size_t)b * wf;
+#pragma unroll
+      for (int si = 0; si < SPW; ++si) {
+        const int p = w + 4 * si;
+        if (p >= NT) continue;
+        const int t = logical(p, bm);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * t + T::row_of(lane, r);
+          const C v = wsh[(row < wf ? (int)Pb[row] : row) * 16 + j];
+          wr[si][r] = (R)v.x;
+          wi[si][r] = (R)v.y;
+        }
+      }
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const C v = wsh[(int)Pb[4 * ks + q] * 16 + j];
+        xr[ks] = (R)v.x;
+        xi[ks] = (R)v.y;
+      }
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const C v = xsh[par * 256 + (4 * ks + q) * 16 + j];
+        xr[ks] = (R)v.x;
+        xi[ks] = (R)v.y;
+      }
+    }
+#pragma unroll
+    for (int si = 0; si < SPW; ++si) {
+      const int p = w + 4 * si;
+      if (p >= NT) continue;
+      const int t = logical(p, bm);
+      if (t == 0) {
+        wr[si] = V{0, 0, 0, 0};
+        wi[si] = V{0, 0, 0, 0};
+      }
+      tile_mma<R>(acur[si], (16 * t + j < wf) ? (R)1 : (R)0, xr, xi, wr[si], wi[si]);
+      if (t == 0) {  // the block's rows are final; the tile re-enters as the window's last rows
+        if (mine) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) y[b * 16 + T::row_of(lane, r)] = mkc<C, R>(wr[si][r], wi[si][r]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          wr[si][r] = (R)fr[r].x;
+          wi[si][r] = (R)fr[r].y;
+        }
+      } else if (t == 1) {  // X of the next block
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xsh[(par ^ 1) * 256 + T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[si][r], wi[si][r]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int si = 0; si < SPW; ++si)
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) acur[si][ks] = anxt[si][ks];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) fr[r] = frn[r];
+    bm = bmn;
+  }
+}
+
+template <typename R, int SPW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_bwd_mm(
+    Geom g, SolveLayout L, const Entry* ent, const int2* tiles, const FaceTab* ft, const IfCoef* coef,
+    const typename Cplx<R>::T* __restrict__ MB, SolveIO io, typename Cplx<R>::T* __restrict__ ybuf) {
+  typedef typename Cplx<R>::T C;
+  typedef TriMma<R> T;
+  typedef typename T::V V;
+  extern __shared__ unsigned char smem_raw[];
+  const int nblk = L.nblk, wb = L.wb, NT = (wb + 15) >> 4, pad = NT * 16 - wb, ylen = nblk * 16;
+  C* xsh = reinterpret_cast<C*>(smem_raw);  // [2][16 rows][16 right-hand sides]
+  const int2 tl = make_int2(__builtin_amdgcn_readfirstlane(tiles[blockIdx.x].x),
+                            __builtin_amdgcn_readfirstlane(tiles[blockIdx.x].y));
+  const int lane = threadIdx.x & 63, j = lane & 15;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const bool mine = j < tl.y;
+  const int slot = tl.x + (mine ? j : 0);
+  const int s = __builtin_amdgcn_readfirstlane(ent[tl.x].s);
+  const C* M = MB + (size_t)s * L.mb_per_sub;
+  C* y = ybuf + (size_t)slot * ylen;
+  // logical tile u of step i (block b = nblk - 1 - i) holds rows b*16 - (NT - 1 - u)*16 + [0, 16),
+  // window rows 16 u - pad + [0, 16) of k_bwd; it is physical tile (u - i) mod NT
+  auto fresh = [&](int row0, C(&v)[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int l = row0 + T::row_of(lane, r);
+      v[r] = (l >= 0) ? y[l] : czero<C>();
+    }
+  };
+  auto load_a = [&](int b, int u, C(&a)[4]) {
+    const C* Mb = M + (size_t)b * 16 * wb;
+    const int r = max(16 * u + j - pad, 0);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) a[ks] = Mb[tile_index(4 * ks + (lane >> 4), r, wb, 16, L.cgb)];
+  };
+  auto logical = [&](int p, int im) { return p + im < NT ? p + im : p + im - NT; };
+
+  V wr[SPW], wi[SPW];
+  C acur[SPW][4], anxt[SPW][4];
+  C fr[4], frn[4];
+#pragma unroll
+  for (int si = 0; si < SPW; ++si) {
+    const int p = w + 4 * si;
+    if (p >= NT) continue;
+    C v[4];
+    fresh((nblk - NT + p) * 16, v);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      wr[si][r] = (R)v[r].x;
+      wi[si][r] = (R)v[r].y;
+    }
+    load_a(nblk - 1, p, acur[si]);
+  }
+  fresh((nblk - 1 - NT) * 16, fr);
+  {  // X of the last block: logical tile NT - 1 = physical tile NT - 1
+    const int p = NT - 1;
+    if (w == (p & 3)) {
+#pragma unroll
+      for (int si = 0; si < SPW; ++si)
+        if (w + 4 * si == p)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) xsh[T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[si][r], wi[si][r]);
+    }
+  }
+  __syncthreads();
+
+  int im = 0;  // i mod NT
+  for (int i = 0; i < nblk; ++i) {
+    const int b = nblk - 1 - i, par = i & 1;
+    const int bn = max(b - 1, 0), imn = (im + 1 == NT) ? 0 : im + 1;
+#pragma unroll
+    for (int si = 0; si < SPW; ++si) {
+      const int p = w + 4 * si;
+      if (p < NT) load_a(bn, logical(p, imn), anxt[si]);
+    }
+    fresh((b - 1 - NT) * 16, frn);
+    R xr[4], xi[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const C v = xsh[par * 256 + (4 * ks + (lane >> 4)) * 16 + j];
+      xr[ks] = (R)v.x;
+      xi[ks] = (R)v.y;
+    }
+#pragma unroll
+    for (int si = 0; si < SPW; ++si) {
+      const int p = w + 4 * si;
+      if (p >= NT) continue;
+      const int u = logical(p, im);
+      if (u == NT - 1) {
+        wr[si] = V{0, 0, 0, 0};
+        wi[si] = V{0, 0, 0, 0};
+      }
+      tile_mma<R>(acur[si], (16 * u + j >= pad) ? (R)1 : (R)0, xr, xi, wr[si], wi[si]);
+      if (u == NT - 1) {  // the block's unknowns are final; the tile re-enters as the window's top rows
+        if (mine) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) y[b * 16 + T::row_of(lane, r)] = mkc<C, R>(wr[si][r], wi[si][r]);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          wr[si][r] = (R)fr[r].x;
+          wi[si][r] = (R)fr[r].y;
+        }
+      } else if (u == NT - 2) {  // X of the next block
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xsh[(par ^ 1) * 256 + T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[si][r], wi[si][r]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int si = 0; si < SPW; ++si)
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) acur[si][ks] = anxt[si][ks];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) fr[r] = frn[r];
+    im = imn;
+  }
+  // the solutions are final: the outputs of every entry of the tile, as k_bwd writes them
+  const FaceTab F = ft[s];
+  const int cnt = tl.y, nloc = g.nloc;
+  if (io.u || io.x64) {
+    for (int idx = threadIdx.x; idx < cnt * nloc; idx += 256) {
+      const int jj = idx / nloc, l = idx - jj * nloc, sl = tl.x + jj;
+      const Entry ej = ent[sl];
+      if (io.nz && io.nz_skip_out && !io.nz[(size_t)ej.rhs * g.n1 * g.n2 + ej.s]) continue;
+      emit_field(g, ej, io, sl, l, to_d(ybuf[(size_t)sl * ylen + l]));
+    }
+  }
+  if (io.tr_dst) {
+    const int nedge = 2 * g.snx + 2 * (g.sny - 2);
+    for (int idx = threadIdx.x; idx < cnt * nedge; idx += 256) {
+      const int jj = idx / nedge, qq = idx - jj * nedge, sl = tl.x + jj;
+      const Entry ej = ent[sl];
+      if (io.nz && io.nz_skip_out && !io.nz[(size_t)ej.rhs * g.n1 * g.n2 + ej.s]) continue;
+      const double2* gin = ej.src ? io.g_b : io.g_a;
+      if (gin) gin += (size_t)ej.rhs * g.nif;
+      const int l = edge_row(g, qq);
+      emit_traces(g, ej, F, coef, io, gin, l, to_d(ybuf[(size_t)sl * ylen + l]));
+    }
+  }
+}
+
 }  // namespace
 
 // column groups per window row (must match the tiled layout written by the repack)
@@ -464,6 +815,54 @@ template hipError_t launch_bwd<double>(const Geom&, const SolveLayout&, const En
                                        const IfCoef*, const double2*, const SolveIO&, double2*, hipStream_t);
 template hipError_t launch_bwd<float>(const Geom&, const SolveLayout&, const Entry*, int, const FaceTab*,
                                       const IfCoef*, const float2*, const SolveIO&, float2*, hipStream_t);
+
+constexpr int kMmSpw = 5;  // window tiles per wavefront of the MFMA solves: windows of up to 20 tiles
+
+static size_t fwd_mm_lds(const SolveLayout& L, size_t elem) {
+  return 512 * elem + (size_t)((L.nblk + 3) & ~3) * sizeof(int) + (size_t)((L.wf + 15) / 16) * 256 * elem;
+}
+
+bool trisolve_mm_fits(const SolveLayout& L, size_t elem) {
+  return L.nb == 16 && (L.wf + 15) / 16 <= 4 * kMmSpw && (L.wb + 15) / 16 <= 4 * kMmSpw &&
+         fwd_mm_lds(L, elem) <= 64 * 1024;
+}
+
+template <typename R>
+hipError_t launch_fwd_mm(const Geom& g, const SolveLayout& L, const Entry* ent, const int2* tiles, int ntiles,
+                         const FaceTab* ft, const IfCoef* coef, const typename Cplx<R>::T* mf, const int16_t* pf,
+                         const int32_t* pflag, const SolveIO& io, typename Cplx<R>::T* ybuf, hipStream_t st) {
+  typedef typename Cplx<R>::T C;
+  if (ntiles == 0) return hipSuccess;
+  if (!trisolve_mm_fits(L, sizeof(C))) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_fwd_mm<R, kMmSpw>), dim3(ntiles), dim3(256), fwd_mm_lds(L, sizeof(C)), st, g, L, ent, tiles,
+                     ft, coef, mf, pf, pflag, io, ybuf);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_bwd_mm(const Geom& g, const SolveLayout& L, const Entry* ent, const int2* tiles, int ntiles,
+                         const FaceTab* ft, const IfCoef* coef, const typename Cplx<R>::T* mb, const SolveIO& io,
+                         typename Cplx<R>::T* ybuf, hipStream_t st) {
+  typedef typename Cplx<R>::T C;
+  if (ntiles == 0) return hipSuccess;
+  if (!trisolve_mm_fits(L, sizeof(C))) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_bwd_mm<R, kMmSpw>), dim3(ntiles), dim3(256), 512 * sizeof(C), st, g, L, ent, tiles, ft, coef,
+                     mb, io, ybuf);
+  return hipGetLastError();
+}
+
+template hipError_t launch_fwd_mm<double>(const Geom&, const SolveLayout&, const Entry*, const int2*, int,
+                                          const FaceTab*, const IfCoef*, const double2*, const int16_t*,
+                                          const int32_t*, const SolveIO&, double2*, hipStream_t);
+template hipError_t launch_fwd_mm<float>(const Geom&, const SolveLayout&, const Entry*, const int2*, int,
+                                         const FaceTab*, const IfCoef*, const float2*, const int16_t*, const int32_t*,
+                                         const SolveIO&, float2*, hipStream_t);
+template hipError_t launch_bwd_mm<double>(const Geom&, const SolveLayout&, const Entry*, const int2*, int,
+                                          const FaceTab*, const IfCoef*, const double2*, const SolveIO&, double2*,
+                                          hipStream_t);
+template hipError_t launch_bwd_mm<float>(const Geom&, const SolveLayout&, const Entry*, const int2*, int,
+                                         const FaceTab*, const IfCoef*, const float2*, const SolveIO&, float2*,
+                                         hipStream_t);
 
 hipError_t launch_build_rhs(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
                             const SolveIO& io, double2* rhs64, hipStream_t st) {

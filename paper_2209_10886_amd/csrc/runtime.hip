@@ -50,6 +50,8 @@ struct Step {
   double dense_elems = 0;  // dense operator entries read by the step (rows x columns)
   size_t sub_first = 0;    // offset into the schedule's subdomain list (one per subdomain)
   int sub_count = 0;
+  size_t tile_first = 0;   // offset into the schedule's tile list (banded solves on MFMA)
+  int tile_count = 0;
 };
 
 // All launches for a given number of right-hand sides.
@@ -63,6 +65,9 @@ struct Schedule {
   int32_t* subs = nullptr;  // device subdomain lists of the steps (many right-hand sides)
   size_t all_sub_first = 0;
   int all_sub_count = 0;
+  int2* tiles = nullptr;  // {first entry relative to the step's first, count}: runs of one subdomain, <= 16
+  size_t all_tile_first = 0;
+  int all_tile_count = 0;
   std::vector<Step> fwd, bwd;  // preconditioner passes
   // dataflow launches (dense form): task lists per kind, double-buffered completion counters
   struct DfPlan {
@@ -169,6 +174,7 @@ struct hbj_ctx {
   Gmres* gm = nullptr;
   bool use_graphs = false;  // eager launches measured faster once step j+1 is queued ahead
   int orth = HBJ_ORTH_DCGS2;     // Gram-Schmidt variant of the Arnoldi steps
+  int msolve = HBJ_MSOLVE_MFMA;  // banded solves of many right-hand sides per subdomain on MFMA
   int graph_epoch = 0;           // bumped when captured operands change (a new factorisation)
   hipStream_t cap = nullptr;     // capture stream (graphs are replayed on st)
   // profiling
@@ -197,6 +203,7 @@ hbj_ctx::~hbj_ctx() {
     dfree(kv.second->dev);
     dfree(kv.second->eft);
     dfree(kv.second->subs);
+    dfree(kv.second->tiles);
     for (auto& pl : kv.second->df) dfree(pl.dev);
     dfree(kv.second->df_ctr);
   }
@@ -306,6 +313,16 @@ void build_blocks(hbj_ctx* c) {
   }
 }
 
+// runs of at most 16 consecutive entries with one subdomain, as {first - base, count}
+void append_tiles(const std::vector<Entry>& ent, size_t first, int count, std::vector<int2>& tiles) {
+  for (int q = 0; q < count;) {
+    int n = 1;
+    while (q + n < count && n < 16 && ent[first + q + n].s == ent[first + q].s) ++n;
+    tiles.push_back(make_int2(q, n));
+    q += n;
+  }
+}
+
 int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
   auto it = c->sched.find(nrhs);
   if (it != c->sched.end()) {
@@ -379,6 +396,18 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
   HIPCHK(hipMemcpyAsync(S->eft, eft.data(), eft.size() * sizeof(FaceTab), hipMemcpyHostToDevice, c->st));
   HIPCHK(dalloc(&S->subs, subs.size()));
   HIPCHK(hipMemcpyAsync(S->subs, subs.data(), subs.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  std::vector<int2> tiles;
+  S->all_tile_first = 0;
+  append_tiles(ent, S->all_first, S->all_count, tiles);
+  S->all_tile_count = (int)tiles.size();
+  for (auto* v : {&S->fwd, &S->bwd})
+    for (Step& st : *v) {
+      st.tile_first = tiles.size();
+      append_tiles(ent, st.first, st.count, tiles);
+      st.tile_count = (int)(tiles.size() - st.tile_first);
+    }
+  HIPCHK(dalloc(&S->tiles, tiles.size()));
+  HIPCHK(hipMemcpyAsync(S->tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
   *out = S.get();
   c->sched[nrhs] = std::move(S);
@@ -454,8 +483,12 @@ double bwd_bytes(const hbj_ctx* c, size_t elem) { return (double)c->g.nloc * (c-
 // ---------------------------------------------------------------------------
 // batched local solves
 // ---------------------------------------------------------------------------
+// launches with at least this many entries per tile on average run the MFMA solves
+constexpr int kMmMinPerTile = 8;
+
 template <typename R>
-int run_solves(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io_in) {
+int run_solves(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io_in, const int2* tiles = nullptr,
+               int ntiles = 0) {
   typedef typename Cplx<R>::T C;
   if (nent == 0) return HBJ_OK;
   int rc = ensure_ybuf(c, nent, sizeof(C));
@@ -488,13 +521,24 @@ int run_solves(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io_in) {
     mf = c->mf32;
     mb = c->mb32;
   }
+  // many right-hand sides per subdomain: 16 per workgroup on MFMA, the factors read once per tile
+  const bool mm = c->msolve == HBJ_MSOLVE_MFMA && tiles && ntiles > 0 && nent >= kMmMinPerTile * ntiles &&
+                  trisolve_mm_fits(c->L, sizeof(C));
+  const double nread = mm ? (double)ntiles : (double)nent;
   {
-    ProfScope ps(c, HBJ_K_FWD, nent * fwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * c->g.kl);
-    HIPCHK((launch_fwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mf, c->pf, c->pflag, io, (C*)c->ybuf, c->st)));
+    ProfScope ps(c, HBJ_K_FWD, nread * fwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * c->g.kl);
+    if (mm)
+      HIPCHK((launch_fwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mf, c->pf, c->pflag, io, (C*)c->ybuf,
+                               c->st)));
+    else
+      HIPCHK((launch_fwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mf, c->pf, c->pflag, io, (C*)c->ybuf, c->st)));
   }
   {
-    ProfScope ps(c, HBJ_K_BWD, nent * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1));
-    HIPCHK((launch_bwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st)));
+    ProfScope ps(c, HBJ_K_BWD, nread * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1));
+    if (mm)
+      HIPCHK((launch_bwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st)));
+    else
+      HIPCHK((launch_bwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st)));
   }
   if (field) {
     SolveIO tio = io_in;
@@ -878,7 +922,7 @@ int run_lifting(hbj_ctx* c, Schedule* S, const double2* f, double2* b, int nrhs)
   io.tr_dst = b;
   io.tr_sign = 1.0;
   io.tr_reflect = 0;
-  return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+  return run_solves<double>(c, S->dev + S->all_first, S->all_count, io, S->tiles + S->all_tile_first, S->all_tile_count);
 }
 
 // Source part of the reconstruction, u_s = A_s^{-1} f_s (zero where f_s = 0), on the side
@@ -925,7 +969,7 @@ int run_reconstruct(hbj_ctx* c, Schedule* S, const double2* f, const double2* g,
       io.nz = c->nzf;
       io.nz_skip_out = 1;
       io.u = u;
-      int rc = run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+      int rc = run_solves<double>(c, S->dev + S->all_first, S->all_count, io, S->tiles + S->all_tile_first, S->all_tile_count);
       if (rc) return rc;
     }
     const double elems = (double)c->ndom * c->g.nloc * local_if_len(c->g);
@@ -954,7 +998,7 @@ int run_reconstruct(hbj_ctx* c, Schedule* S, const double2* f, const double2* g,
   io.f = f;
   io.g_a = (c->g.nif > 0) ? g : nullptr;
   io.u = u;
-  return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+  return run_solves<double>(c, S->dev + S->all_first, S->all_count, io, S->tiles + S->all_tile_first, S->all_tile_count);
 }
 
 int check_ready(hbj_ctx* c) {
@@ -979,7 +1023,7 @@ int op_fp64(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
   if (c->dense)
     return run_dense(c, S->dev + S->all_first, S->eft + S->all_first, S->all_count, 0xF, io, false, S->all_dense_elems,
                      S->subs + S->all_sub_first, S->all_sub_count, S->nrhs, 0);
-  return run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+  return run_solves<double>(c, S->dev + S->all_first, S->all_count, io, S->tiles + S->all_tile_first, S->all_tile_count);
 }
 
 // sweeps over the precomputed steps; in = pass input, out = pass output (pre-filled with in)
@@ -1005,7 +1049,7 @@ int run_pass(hbj_ctx* c, const Schedule* S, const std::vector<Step>& steps, cons
     io.tr_reflect = 1;
     int rc = c->dense ? run_dense(c, dev + s.first, S->eft + s.first, s.count, mask, io, sizeof(R) == 4, s.dense_elems,
                                   S->subs + s.sub_first, s.sub_count, S->nrhs, si == 0 ? 0 : 1)
-                      : run_solves<R>(c, dev + s.first, s.count, io);
+                      : run_solves<R>(c, dev + s.first, s.count, io, S->tiles + s.tile_first, s.tile_count);
     if (rc) return rc;
   }
   return HBJ_OK;
@@ -1845,15 +1889,24 @@ static int build_dense(hbj_ctx* c) {
     }
   const int chunk = (int)std::min<size_t>(4096, all.size());
   Entry* dev = nullptr;
+  int2* tdev = nullptr;
   HIPCHK(dalloc(&dev, (size_t)chunk));
+  if (dalloc(&tdev, (size_t)chunk) != hipSuccess) {
+    dfree(dev);
+    return fail(HBJ_ENOMEM, "dense operator workspace allocation failed");
+  }
   SolveIO io{};
   io.unit = 1;
   int rc = HBJ_OK;
   for (size_t off = 0; off < all.size() && rc == HBJ_OK; off += chunk) {
     const int n = (int)std::min<size_t>(chunk, all.size() - off);
+    std::vector<int2> tiles;
+    append_tiles(all, off, n, tiles);
     hipError_t he = hipMemcpyAsync(dev, all.data() + off, n * sizeof(Entry), hipMemcpyHostToDevice, c->st);
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(tdev, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, c->st);
     if (he != hipSuccess) { rc = fail(HBJ_EHIP, hipGetErrorString(he)); break; }
-    rc = run_solves<double>(c, dev, n, io);
+    rc = run_solves<double>(c, dev, n, io, tdev, (int)tiles.size());
     if (rc) break;
     he = launch_build_T(g, dev, n, c->ft, c->band, (const double2*)c->ybuf, (size_t)c->L.nblk * c->L.nb, c->T64,
                         c->st);
@@ -1864,6 +1917,7 @@ static int build_dense(hbj_ctx* c) {
   }
   hipError_t he = hipStreamSynchronize(c->st);
   dfree(dev);
+  dfree(tdev);
   if (rc) return rc;
   if (he != hipSuccess) return fail(HBJ_EHIP, hipGetErrorString(he));
   if (c->T32) HIPCHK(launch_cast_c64(c->T64, c->T32, per * c->ndom, c->st));
@@ -1988,7 +2042,7 @@ static int solve_impl(hbj_ctx* c, const double2* f, double2* u, int nrhs, const 
     SolveIO io{};
     io.f = f;
     io.u = u;
-    rc = run_solves<double>(c, S->dev + S->all_first, S->all_count, io);
+    rc = run_solves<double>(c, S->dev + S->all_first, S->all_count, io, S->tiles + S->all_tile_first, S->all_tile_count);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(c->st));
     iters.assign(nrhs, 0);
@@ -2221,6 +2275,14 @@ int hbj_set_orthogonalization(hbj_ctx* c, int32_t mode) {
   if (mode != HBJ_ORTH_CGS2 && mode != HBJ_ORTH_DCGS2) return fail(HBJ_EINVAL, "unknown orthogonalisation");
   if (mode != c->orth) ++c->graph_epoch;  // the captured steps hold the other kernels
   c->orth = mode;
+  return HBJ_OK;
+}
+
+int hbj_set_multi_solve(hbj_ctx* c, int32_t mode) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  if (mode != HBJ_MSOLVE_CHAINS && mode != HBJ_MSOLVE_MFMA) return fail(HBJ_EINVAL, "unknown multi-solve mode");
+  if (mode != c->msolve) ++c->graph_epoch;  // the captured steps hold the other kernels
+  c->msolve = mode;
   return HBJ_OK;
 }
 
