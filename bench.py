@@ -50,6 +50,9 @@ def parse():
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     p.add_argument("--no-banded", action="store_true", help="skip the banded-operator comparison")
     p.add_argument("--graphs", action="store_true", help="replay the GMRES iterations as HIP graphs")
+    p.add_argument("--no-many-rhs", action="store_true",
+                   help="skip the banded solves of many right-hand sides per subdomain (MFMA against one "
+                        "workgroup per solve)")
     p.add_argument("--no-second-order", action="store_true",
                    help="skip the run with the second-order transmission condition")
     p.add_argument("--transmission", type=int, default=1, choices=(1, 2),
@@ -200,6 +203,62 @@ def roofline_of(kernels, workload, mfma=None):
             "share_of_kernel_time": share, "launch_kinds": detail}
 
 
+def factor_seconds(hbj, wl, mt, precision, transmission, multi_solve):
+    """Wall time of hbj_factor (band LU, repack, and the dense operators) with the given kind of
+    multi-right-hand-side solves."""
+    import torch
+
+    ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=mt, precision=precision, precond=hbj.PC_BJ,
+                    operator_form=hbj.OP_DENSE, transmission=transmission, device=mt.device)
+    ctx.set_multi_solve(multi_solve)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.factor()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.close()
+    return dt
+
+
+def many_rhs_solves(hbj, wl, mt, nrhs, precision, names, reps=3):
+    """The banded operator (one local solve per subdomain and right-hand side) on nrhs columns:
+    16 right-hand sides per workgroup on MFMA against one workgroup per solve."""
+    import torch
+
+    ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=mt, precision=precision, precond=hbj.PC_BJ,
+                    operator_form=hbj.OP_BANDED, device=mt.device)
+    ctx.factor()
+    gen = torch.Generator(device=mt.device).manual_seed(5)
+    g = torch.randn(nrhs, ctx.nif, dtype=torch.complex128, device=mt.device, generator=gen)
+    out = {}
+    peak = MFMA_PEAK_TFLOPS["f64" if precision == hbj.FP64 else "f32"]
+    for mode, key in ((hbj.MSOLVE_MFMA, "mfma"), (hbj.MSOLVE_CHAINS, "one_solve_per_workgroup")):
+        ctx.set_multi_solve(mode)
+        w = ctx.apply_operator(g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.apply_operator(g, out=w)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        ctx.reset_kernel_stats()
+        ctx.set_profiling(True)
+        ctx.apply_operator(g, out=w)
+        ctx.set_profiling(False)
+        ks = [ctx.kernel_stats(k) for k in (hbj.K_FWD, hbj.K_BWD)]
+        ms = sum(k["ms"] for k in ks)
+        fl = sum(k["flops"] for k in ks)
+        by = sum(k["bytes"] for k in ks)
+        tf = fl / (ms * 1e-3) / 1e12
+        out[key] = {"ms_per_apply": dt * 1e3, "local_solves_per_s": ctx.ndom * nrhs / dt,
+                    "solve_kernels_ms": ms, "TFLOP/s": tf, "frac_of_mfma_peak": tf / peak,
+                    "factor_GB/s": by / (ms * 1e-3) / 1e9}
+    ctx.close()
+    out["right_hand_sides"] = nrhs
+    out["peak_TFLOP/s"] = peak
+    return out
+
+
 def solve_gbs(kernels, names):
     b = sum(kernels[n]["bytes"] for n in names)
     t = sum(kernels[n]["ms"] for n in names)
@@ -296,6 +355,12 @@ def main():
     }
     if main_run["tuning"]:
         result["autotuned_operator_tiles"] = main_run["tuning"]
+    # the dense operators come from one banded solve per interface position (16 per workgroup on
+    # MFMA by default); the same factorisation with one workgroup per solve, for comparison
+    result["factor_s_one_solve_per_workgroup"] = factor_seconds(hbj, wl, mt, headline_prec, args.transmission,
+                                                                hbj.MSOLVE_CHAINS)
+    log(f"[bench] factor {main_run['factor_s']:.2f} s; with one workgroup per solve "
+        f"{result['factor_s_one_solve_per_workgroup']:.2f} s")
 
     if not args.no_banded:
         log("[bench] FP64, banded local solves inside GMRES")
@@ -331,6 +396,14 @@ def main():
             "factor_s": sr["factor_s"], "rel_diff_vs_robin_field": diff}
         log(f"[bench] second order: {sr['seconds'] / args.steps * 1e3:.2f} ms/solve, iters {sr['stats'].iters}, "
             f"field differs from the Robin run by {diff:.1e}")
+
+    if not args.no_many_rhs and nsrc == 1:
+        for prec, key, nm in ((hbj.FP64, "banded_64rhs_fp64", names64), (hbj.MIXED, "banded_64rhs_mixed", names32)):
+            log(f"[bench] banded operator on 64 right-hand sides ({key}): MFMA against one workgroup per solve")
+            result[key] = many_rhs_solves(hbj, wl, mt, 64, prec, nm)
+            r = result[key]
+            log(f"[bench]   MFMA {r['mfma']['ms_per_apply']:.1f} ms ({r['mfma']['TFLOP/s']:.1f} TFLOP/s), "
+                f"one per workgroup {r['one_solve_per_workgroup']['ms_per_apply']:.1f} ms")
 
     if not args.no_cpu:
         log("[bench] CPU oracle sample")

@@ -486,6 +486,34 @@ double bwd_bytes(const hbj_ctx* c, size_t elem) { return (double)c->g.nloc * (c-
 // launches with at least this many entries per tile on average run the MFMA solves
 constexpr int kMmMinPerTile = 8;
 
+// forward and backward solves of a batch into the solve buffer: 16 right-hand sides of one
+// subdomain per workgroup on MFMA (factors read once per tile) where the batch has many
+// right-hand sides per subdomain, else one workgroup per solve
+template <typename R>
+int launch_solve_pair(hbj_ctx* c, const Entry* ent, int nent, const int2* tiles, int ntiles, const SolveIO& io,
+                      const typename Cplx<R>::T* mf, const typename Cplx<R>::T* mb) {
+  typedef typename Cplx<R>::T C;
+  const bool mm = c->msolve == HBJ_MSOLVE_MFMA && tiles && ntiles > 0 && nent >= kMmMinPerTile * ntiles &&
+                  trisolve_mm_fits(c->L, sizeof(C));
+  const double nread = mm ? (double)ntiles : (double)nent;
+  {
+    ProfScope ps(c, HBJ_K_FWD, nread * fwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * c->g.kl);
+    if (mm)
+      HIPCHK((launch_fwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mf, c->pf, c->pflag, io, (C*)c->ybuf,
+                               c->st)));
+    else
+      HIPCHK((launch_fwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mf, c->pf, c->pflag, io, (C*)c->ybuf, c->st)));
+  }
+  {
+    ProfScope ps(c, HBJ_K_BWD, nread * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1));
+    if (mm)
+      HIPCHK((launch_bwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st)));
+    else
+      HIPCHK((launch_bwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st)));
+  }
+  return HBJ_OK;
+}
+
 template <typename R>
 int run_solves(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io_in, const int2* tiles = nullptr,
                int ntiles = 0) {
@@ -521,25 +549,8 @@ int run_solves(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io_in, con
     mf = c->mf32;
     mb = c->mb32;
   }
-  // many right-hand sides per subdomain: 16 per workgroup on MFMA, the factors read once per tile
-  const bool mm = c->msolve == HBJ_MSOLVE_MFMA && tiles && ntiles > 0 && nent >= kMmMinPerTile * ntiles &&
-                  trisolve_mm_fits(c->L, sizeof(C));
-  const double nread = mm ? (double)ntiles : (double)nent;
-  {
-    ProfScope ps(c, HBJ_K_FWD, nread * fwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * c->g.kl);
-    if (mm)
-      HIPCHK((launch_fwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mf, c->pf, c->pflag, io, (C*)c->ybuf,
-                               c->st)));
-    else
-      HIPCHK((launch_fwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mf, c->pf, c->pflag, io, (C*)c->ybuf, c->st)));
-  }
-  {
-    ProfScope ps(c, HBJ_K_BWD, nread * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1));
-    if (mm)
-      HIPCHK((launch_bwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st)));
-    else
-      HIPCHK((launch_bwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st)));
-  }
+  rc = launch_solve_pair<R>(c, ent, nent, tiles, ntiles, io, mf, mb);
+  if (rc) return rc;
   if (field) {
     SolveIO tio = io_in;
     tio.u = nullptr;
@@ -1189,15 +1200,9 @@ int op_mixed(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
   for (int it = 0; it <= kLocalRefine; ++it) {
     SolveIO lio{};
     lio.rhs64 = c->r64;
-    {
-      ProfScope ps(c, HBJ_K_FWD, nent * fwd_bytes(c, 8), nent * 8.0 * c->g.nloc * c->g.kl);
-      HIPCHK(launch_fwd<float>(c->g, c->L, ent, nent, c->ft, c->coef, c->mf32, c->pf, c->pflag, lio, (float2*)c->ybuf,
-                              c->st));
-    }
-    {
-      ProfScope ps(c, HBJ_K_BWD, nent * bwd_bytes(c, 8), nent * 8.0 * c->g.nloc * (c->g.kv + 1));
-      HIPCHK(launch_bwd<float>(c->g, c->L, ent, nent, c->ft, c->coef, c->mb32, lio, (float2*)c->ybuf, c->st));
-    }
+    rc = launch_solve_pair<float>(c, ent, nent, S->tiles + S->all_tile_first, S->all_tile_count, lio, c->mf32,
+                                  c->mb32);
+    if (rc) return rc;
     c->local_solves += nent;
     HIPCHK(launch_axpy_c64(c->x64, (const float2*)c->ybuf, c->g, c->L, nent, c->st));
     HIPCHK(launch_local_residual(c->g, ent, nent, c->ft, c->band, c->diag, c->rhs64, c->x64, c->r64, c->st));
