@@ -451,19 +451,35 @@ template <> struct TriMma<float> {
   static __device__ inline int row_of(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-// acc += A (16 x 16, this lane's row j and k-steps in a[]) * X (x[] = this lane's B operands)
-template <typename R>
-__device__ inline void tile_mma(const typename Cplx<R>::T (&a)[4], R ok, const R (&xr)[4], const R (&xi)[4],
-                                typename TriMma<R>::V& wr, typename TriMma<R>::V& wi) {
+// acc_si += A_si X for the SPW tiles of a wavefront (a[si][ks]: this lane's multipliers, row lane % 16,
+// column 4 ks + lane / 16, times ok[si], 0 for rows outside the band; x: this lane's X operands),
+// k-steps outermost so that consecutive MFMAs go to independent accumulators
+template <typename R, int SPW>
+__device__ inline void tiles_mma(const typename Cplx<R>::T (&a)[SPW][4], const R (&ok)[SPW], const R (&xr)[4],
+                                 const R (&xi)[4],
+                                 typename TriMma<R>::V (&wr)[SPW], typename TriMma<R>::V (&wi)[SPW]) {
   typedef TriMma<R> T;
+  R nxi[4];
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks) {
-    const R ar = (R)a[ks].x * ok, ai = (R)a[ks].y * ok;
-    wr = T::mma(ar, xr[ks], wr);
-    wi = T::mma(ar, xi[ks], wi);
-    wr = T::mma(-ai, xi[ks], wr);
-    wi = T::mma(ai, xr[ks], wi);
-  }
+  for (int ks = 0; ks < 4; ++ks) nxi[ks] = -xi[ks];
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+    for (int si = 0; si < SPW; ++si) {
+      const R ar = (R)a[si][ks].x * ok[si], ai = (R)a[si][ks].y * ok[si];
+      wr[si] = T::mma(ar, xr[ks], wr[si]);
+      wi[si] = T::mma(ar, xi[ks], wi[si]);
+      wr[si] = T::mma(ai, nxi[ks], wr[si]);
+      wi[si] = T::mma(ai, xr[ks], wi[si]);
+    }
+}
+
+// Workgroups are dealt to the 8 XCDs in turn (workgroup b to XCD b % 8), each XCD with its own L2.
+// Tile index of workgroup b such that XCD x works on one contiguous run of tiles: the tiles of one
+// subdomain (consecutive) then share an L2 and its factors are fetched once per XCD.
+__device__ inline int xcd_tile(int b, int n) {
+  const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + k;
 }
 
 template <typename R, int SPW>
@@ -474,13 +490,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   typedef typename Cplx<R>::T C;
   typedef TriMma<R> T;
   typedef typename T::V V;
+  constexpr int NT = 4 * SPW;  // window tiles; rows past wf have zero multipliers
   extern __shared__ unsigned char smem_raw[];
-  const int nblk = L.nblk, wf = L.wf, NT = (wf + 15) >> 4, ylen = nblk * 16;
+  const int nblk = L.nblk, wf = L.wf, ylen = nblk * 16;
   C* xsh = reinterpret_cast<C*>(smem_raw);                   // [2][16 rows][16 right-hand sides]
   int* ident = reinterpret_cast<int*>(xsh + 512);            // [nblk]
   C* wsh = reinterpret_cast<C*>(ident + ((nblk + 3) & ~3));  // [NT * 16 rows][16]: interchanges
-  const int2 tl = make_int2(__builtin_amdgcn_readfirstlane(tiles[blockIdx.x].x),
-                            __builtin_amdgcn_readfirstlane(tiles[blockIdx.x].y));  // first entry, count (1..16)
+  const int tix = xcd_tile(blockIdx.x, gridDim.x);
+  const int2 tl = make_int2(__builtin_amdgcn_readfirstlane(tiles[tix].x),
+                            __builtin_amdgcn_readfirstlane(tiles[tix].y));  // first entry, count (1..16)
   const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool mine = j < tl.y;  // lanes past the count work on a copy of the first entry, unstored
@@ -492,42 +510,47 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   const RhsCtx rhs(g, e, F, coef, io, slot);
   const C* M = MF + (size_t)s * L.mf_per_sub;
   const int16_t* P = PF + (size_t)s * L.pf_per_sub;
-  C* y = ybuf + (size_t)slot * ylen;
+  C* y = ybuf + (size_t)tl.x * ylen;                   // the tile's first solve buffer (uniform)
+  const unsigned yl = (unsigned)((mine ? j : 0) * ylen);  // this lane's, relative to it
   for (int b = threadIdx.x; b < nblk; b += 256) ident[b] = PFL[(size_t)s * nblk + b];
 
   auto fresh = [&](int row0, C(&v)[4]) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int l = row0 + T::row_of(lane, r);
-      v[r] = (zero || l >= ylen) ? czero<C>() : to_c<C>(rhs(l));
+      v[r] = (zero || row0 >= ylen) ? czero<C>() : to_c<C>(rhs(l));
     }
   };
-  // multipliers of logical tile t of block b: row 16 t + j, columns 4 ks + q (clamped, masked at use)
-  auto load_a = [&](int b, int t, C(&a)[4]) {
-    const C* Mb = M + (size_t)b * 16 * wf;
-    const int r = min(16 * t + j, wf - 1);
+  // multipliers of logical tile t of block b: row 16 t + j, columns 4 ks + q.  In the tiled layout
+  // entry (r, 4 ks + q) lies at (q wf + r) cg + kofs[ks]: a lane part and a uniform part per k-step.
+  const int cg = L.cgf, nc = 16 / cg;
+  int kofs[4];
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) a[ks] = Mb[tile_index(4 * ks + q, r, wf, 16, L.cgf)];
+  for (int ks = 0; ks < 4; ++ks) kofs[ks] = ((4 * ks) % nc) * wf * cg + (4 * ks) / nc;
+  auto load_a = [&](int b, int t, C(&a)[4]) {  // rows past the band: clamped here, masked at use
+    const C* Mb = M + (size_t)b * 16 * wf;
+    const unsigned ob = (unsigned)((q * wf + min(16 * t + j, wf - 1)) * cg) * (unsigned)sizeof(C);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) a[ks] = *reinterpret_cast<const C*>(reinterpret_cast<const char*>(Mb + kofs[ks]) + ob);
   };
-  auto logical = [&](int p, int bm) { return p >= bm ? p - bm : p - bm + NT; };
+  // logical tile of physical tile w + 4 si at block b (b mod NT = bm)
+  auto logical = [&](int si, int bm) { return (w + 4 * si - bm + NT) % NT; };
 
   V wr[SPW], wi[SPW];
-  C acur[SPW][4], anxt[SPW][4];
-  C fr[4], frn[4];
+  C a0[SPW][4], a1[SPW][4];
+  C f0[4], f1[4];
 #pragma unroll
   for (int si = 0; si < SPW; ++si) {
-    const int p = w + 4 * si;
-    if (p >= NT) continue;
     C v[4];
-    fresh(16 * p, v);
+    fresh(16 * (w + 4 * si), v);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       wr[si][r] = (R)v[r].x;
       wi[si][r] = (R)v[r].y;
     }
-    load_a(0, p, acur[si]);
+    load_a(0, w + 4 * si, a0[si]);
   }
-  fresh(NT * 16, fr);
+  fresh(NT * 16, f0);
   if (w == 0) {  // X of block 0: logical tile 0 = physical tile 0 (wavefront 0, slot 0)
 #pragma unroll
     for (int r = 0; r < 4; ++r) xsh[T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[0][r], wi[0][r]);
@@ -535,22 +558,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   __syncthreads();
 
   int bm = 0;  // b mod NT
-  for (int b = 0; b < nblk; ++b) {
+  // one block: the multipliers of this block are in acur (loaded one block earlier), the rows that
+  // enter the window after it in fr; the next block's go to anxt / frn
+  auto block = [&](int b, C(&acur)[SPW][4], C(&anxt)[SPW][4], C(&fr)[4], C(&frn)[4]) {
     const int par = b & 1;
     const int bn = min(b + 1, nblk - 1), bmn = (bm + 1 == NT) ? 0 : bm + 1;
 #pragma unroll
-    for (int si = 0; si < SPW; ++si) {
-      const int p = w + 4 * si;
-      if (p < NT) load_a(bn, logical(p, bmn), anxt[si]);
-    }
+    for (int si = 0; si < SPW; ++si) load_a(bn, logical(si, bmn), anxt[si]);
     fresh((b + 1 + NT) * 16, frn);
     R xr[4], xi[4];
-    if (!__builtin_amdgcn_readfirstlane(ident[b])) {  // row interchanges in this block: gather the window rows through LDS
+    if (!__builtin_amdgcn_readfirstlane(ident[b])) {  // row interchanges: gather the window through LDS
 #pragma unroll
       for (int si = 0; si < SPW; ++si) {
-        const int p = w + 4 * si;
-        if (p >= NT) continue;
-        const int t = logical(p, bm);
+        const int t = logical(si, bm);
 #pragma unroll
         for (int r = 0; r < 4; ++r) wsh[(16 * t + T::row_of(lane, r)) * 16 + j] = mkc<C, R>(wr[si][r], wi[si][r]);
       }
@@ -558,9 +578,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       const int16_t* Pb = P + (size_t)b * wf;
 #pragma unroll
       for (int si = 0; si < SPW; ++si) {
-        const int p = w + 4 * si;
-        if (p >= NT) continue;
-        const int t = logical(p, bm);
+        const int t = logical(si, bm);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * t + T::row_of(lane, r);
@@ -584,20 +602,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         xi[ks] = (R)v.y;
       }
     }
+    // the tile holding the block's own rows starts from zero; every tile then takes M_t X
+    R ok[SPW];
 #pragma unroll
     for (int si = 0; si < SPW; ++si) {
-      const int p = w + 4 * si;
-      if (p >= NT) continue;
-      const int t = logical(p, bm);
-      if (t == 0) {
+      ok[si] = (16 * logical(si, bm) + j < wf) ? (R)1 : (R)0;
+      if (logical(si, bm) == 0) {
         wr[si] = V{0, 0, 0, 0};
         wi[si] = V{0, 0, 0, 0};
       }
-      tile_mma<R>(acur[si], (16 * t + j < wf) ? (R)1 : (R)0, xr, xi, wr[si], wi[si]);
+    }
+    tiles_mma<R, SPW>(acur, ok, xr, xi, wr, wi);
+#pragma unroll
+    for (int si = 0; si < SPW; ++si) {
+      const int t = logical(si, bm);
       if (t == 0) {  // the block's rows are final; the tile re-enters as the window's last rows
         if (mine) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) y[b * 16 + T::row_of(lane, r)] = mkc<C, R>(wr[si][r], wi[si][r]);
+          for (int r = 0; r < 4; ++r) y[yl + (unsigned)(b * 16 + T::row_of(lane, r))] = mkc<C, R>(wr[si][r], wi[si][r]);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -606,18 +628,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         }
       } else if (t == 1) {  // X of the next block
 #pragma unroll
-        for (int r = 0; r < 4; ++r) xsh[(par ^ 1) * 256 + T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[si][r], wi[si][r]);
+        for (int r = 0; r < 4; ++r)
+          xsh[(par ^ 1) * 256 + T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[si][r], wi[si][r]);
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int si = 0; si < SPW; ++si)
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) acur[si][ks] = anxt[si][ks];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) fr[r] = frn[r];
     bm = bmn;
+  };
+  int b = 0;
+  for (; b + 1 < nblk; b += 2) {  // two blocks per trip: the register sets swap roles without copies
+    block(b, a0, a1, f0, f1);
+    block(b + 1, a1, a0, f1, f0);
   }
+  if (b < nblk) block(b, a0, a1, f0, f1);
 }
 
 template <typename R, int SPW>
@@ -627,42 +650,51 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   typedef typename Cplx<R>::T C;
   typedef TriMma<R> T;
   typedef typename T::V V;
+  constexpr int NT = 4 * SPW;  // window tiles; rows above the band have zero multipliers
   extern __shared__ unsigned char smem_raw[];
-  const int nblk = L.nblk, wb = L.wb, NT = (wb + 15) >> 4, pad = NT * 16 - wb, ylen = nblk * 16;
+  const int nblk = L.nblk, wb = L.wb, pad = NT * 16 - wb, ylen = nblk * 16;
   C* xsh = reinterpret_cast<C*>(smem_raw);  // [2][16 rows][16 right-hand sides]
-  const int2 tl = make_int2(__builtin_amdgcn_readfirstlane(tiles[blockIdx.x].x),
-                            __builtin_amdgcn_readfirstlane(tiles[blockIdx.x].y));
+  const int tix = xcd_tile(blockIdx.x, gridDim.x);
+  const int2 tl = make_int2(__builtin_amdgcn_readfirstlane(tiles[tix].x), __builtin_amdgcn_readfirstlane(tiles[tix].y));
   const int lane = threadIdx.x & 63, j = lane & 15;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool mine = j < tl.y;
   const int slot = tl.x + (mine ? j : 0);
   const int s = __builtin_amdgcn_readfirstlane(ent[tl.x].s);
   const C* M = MB + (size_t)s * L.mb_per_sub;
-  C* y = ybuf + (size_t)slot * ylen;
+  C* y = ybuf + (size_t)tl.x * ylen;                   // the tile's first solve buffer (uniform)
+  const unsigned yl = (unsigned)((mine ? j : 0) * ylen);  // this lane's, relative to it
+  const int q = lane >> 4;
   // logical tile u of step i (block b = nblk - 1 - i) holds rows b*16 - (NT - 1 - u)*16 + [0, 16),
   // window rows 16 u - pad + [0, 16) of k_bwd; it is physical tile (u - i) mod NT
-  auto fresh = [&](int row0, C(&v)[4]) {
+  auto fresh = [&](int row0, C(&v)[4]) {  // row0 is a multiple of 16: the tile is in range or above row 0
+    if (row0 >= 0) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int l = row0 + T::row_of(lane, r);
-      v[r] = (l >= 0) ? y[l] : czero<C>();
+      for (int r = 0; r < 4; ++r) v[r] = y[yl + (unsigned)(row0 + T::row_of(lane, r))];
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) v[r] = czero<C>();
     }
   };
-  auto load_a = [&](int b, int u, C(&a)[4]) {
-    const C* Mb = M + (size_t)b * 16 * wb;
-    const int r = max(16 * u + j - pad, 0);
+  // multipliers of logical tile u: window row 16 u + j - pad, columns 4 ks + q (layout as in k_fwd_mm)
+  const int cg = L.cgb, nc = 16 / cg;
+  int kofs[4];
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) a[ks] = Mb[tile_index(4 * ks + (lane >> 4), r, wb, 16, L.cgb)];
+  for (int ks = 0; ks < 4; ++ks) kofs[ks] = ((4 * ks) % nc) * wb * cg + (4 * ks) / nc;
+  auto load_a = [&](int b, int u, C(&a)[4]) {  // rows above the band: clamped here, masked at use
+    const C* Mb = M + (size_t)b * 16 * wb;
+    const unsigned ob = (unsigned)((q * wb + max(16 * u + j - pad, 0)) * cg) * (unsigned)sizeof(C);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) a[ks] = *reinterpret_cast<const C*>(reinterpret_cast<const char*>(Mb + kofs[ks]) + ob);
   };
-  auto logical = [&](int p, int im) { return p + im < NT ? p + im : p + im - NT; };
+  auto logical = [&](int si, int im) { return (w + 4 * si + im) % NT; };
 
   V wr[SPW], wi[SPW];
-  C acur[SPW][4], anxt[SPW][4];
-  C fr[4], frn[4];
+  C a0[SPW][4], a1[SPW][4];
+  C f0[4], f1[4];
 #pragma unroll
   for (int si = 0; si < SPW; ++si) {
     const int p = w + 4 * si;
-    if (p >= NT) continue;
     C v[4];
     fresh((nblk - NT + p) * 16, v);
 #pragma unroll
@@ -670,52 +702,46 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       wr[si][r] = (R)v[r].x;
       wi[si][r] = (R)v[r].y;
     }
-    load_a(nblk - 1, p, acur[si]);
+    load_a(nblk - 1, p, a0[si]);
   }
-  fresh((nblk - 1 - NT) * 16, fr);
-  {  // X of the last block: logical tile NT - 1 = physical tile NT - 1
-    const int p = NT - 1;
-    if (w == (p & 3)) {
+  fresh((nblk - 1 - NT) * 16, f0);
+  if (w == 3) {  // X of the last block: logical tile NT - 1 = physical tile NT - 1 (wavefront 3, last slot)
 #pragma unroll
-      for (int si = 0; si < SPW; ++si)
-        if (w + 4 * si == p)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) xsh[T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[si][r], wi[si][r]);
-    }
+    for (int r = 0; r < 4; ++r) xsh[T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[SPW - 1][r], wi[SPW - 1][r]);
   }
   __syncthreads();
 
   int im = 0;  // i mod NT
-  for (int i = 0; i < nblk; ++i) {
+  auto step = [&](int i, C(&acur)[SPW][4], C(&anxt)[SPW][4], C(&fr)[4], C(&frn)[4]) {
     const int b = nblk - 1 - i, par = i & 1;
     const int bn = max(b - 1, 0), imn = (im + 1 == NT) ? 0 : im + 1;
 #pragma unroll
-    for (int si = 0; si < SPW; ++si) {
-      const int p = w + 4 * si;
-      if (p < NT) load_a(bn, logical(p, imn), anxt[si]);
-    }
+    for (int si = 0; si < SPW; ++si) load_a(bn, logical(si, imn), anxt[si]);
     fresh((b - 1 - NT) * 16, frn);
     R xr[4], xi[4];
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      const C v = xsh[par * 256 + (4 * ks + (lane >> 4)) * 16 + j];
+      const C v = xsh[par * 256 + (4 * ks + q) * 16 + j];
       xr[ks] = (R)v.x;
       xi[ks] = (R)v.y;
     }
+    R ok[SPW];
 #pragma unroll
     for (int si = 0; si < SPW; ++si) {
-      const int p = w + 4 * si;
-      if (p >= NT) continue;
-      const int u = logical(p, im);
-      if (u == NT - 1) {
+      ok[si] = (16 * logical(si, im) + j >= pad) ? (R)1 : (R)0;
+      if (logical(si, im) == NT - 1) {
         wr[si] = V{0, 0, 0, 0};
         wi[si] = V{0, 0, 0, 0};
       }
-      tile_mma<R>(acur[si], (16 * u + j >= pad) ? (R)1 : (R)0, xr, xi, wr[si], wi[si]);
+    }
+    tiles_mma<R, SPW>(acur, ok, xr, xi, wr, wi);
+#pragma unroll
+    for (int si = 0; si < SPW; ++si) {
+      const int u = logical(si, im);
       if (u == NT - 1) {  // the block's unknowns are final; the tile re-enters as the window's top rows
         if (mine) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) y[b * 16 + T::row_of(lane, r)] = mkc<C, R>(wr[si][r], wi[si][r]);
+          for (int r = 0; r < 4; ++r) y[yl + (unsigned)(b * 16 + T::row_of(lane, r))] = mkc<C, R>(wr[si][r], wi[si][r]);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -724,18 +750,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         }
       } else if (u == NT - 2) {  // X of the next block
 #pragma unroll
-        for (int r = 0; r < 4; ++r) xsh[(par ^ 1) * 256 + T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[si][r], wi[si][r]);
+        for (int r = 0; r < 4; ++r)
+          xsh[(par ^ 1) * 256 + T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[si][r], wi[si][r]);
       }
     }
     __syncthreads();
-#pragma unroll
-    for (int si = 0; si < SPW; ++si)
-#pragma unroll
-      for (int ks = 0; ks < 4; ++ks) acur[si][ks] = anxt[si][ks];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) fr[r] = frn[r];
     im = imn;
+  };
+  int i = 0;
+  for (; i + 1 < nblk; i += 2) {
+    step(i, a0, a1, f0, f1);
+    step(i + 1, a1, a0, f1, f0);
   }
+  if (i < nblk) step(i, a0, a1, f0, f1);
   // the solutions are final: the outputs of every entry of the tile, as k_bwd writes them
   const FaceTab F = ft[s];
   const int cnt = tl.y, nloc = g.nloc;
@@ -816,15 +843,17 @@ template hipError_t launch_bwd<double>(const Geom&, const SolveLayout&, const En
 template hipError_t launch_bwd<float>(const Geom&, const SolveLayout&, const Entry*, int, const FaceTab*,
                                       const IfCoef*, const float2*, const SolveIO&, float2*, hipStream_t);
 
-constexpr int kMmSpw = 5;  // window tiles per wavefront of the MFMA solves: windows of up to 20 tiles
+constexpr int kMmSpwMax = 5;  // window tiles per wavefront of the MFMA solves: windows of up to 20 tiles
+
+// tiles per wavefront for a window of `rows` rows (the window is padded to 4 x that many tiles)
+static int mm_spw(int rows) { return ((rows + 15) / 16 + 3) / 4; }
 
 static size_t fwd_mm_lds(const SolveLayout& L, size_t elem) {
-  return 512 * elem + (size_t)((L.nblk + 3) & ~3) * sizeof(int) + (size_t)((L.wf + 15) / 16) * 256 * elem;
+  return 512 * elem + (size_t)((L.nblk + 3) & ~3) * sizeof(int) + (size_t)(4 * mm_spw(L.wf)) * 256 * elem;
 }
 
 bool trisolve_mm_fits(const SolveLayout& L, size_t elem) {
-  return L.nb == 16 && (L.wf + 15) / 16 <= 4 * kMmSpw && (L.wb + 15) / 16 <= 4 * kMmSpw &&
-         fwd_mm_lds(L, elem) <= 64 * 1024;
+  return L.nb == 16 && mm_spw(L.wf) <= kMmSpwMax && mm_spw(L.wb) <= kMmSpwMax && fwd_mm_lds(L, elem) <= 64 * 1024;
 }
 
 template <typename R>
@@ -834,8 +863,18 @@ hipError_t launch_fwd_mm(const Geom& g, const SolveLayout& L, const Entry* ent, 
   typedef typename Cplx<R>::T C;
   if (ntiles == 0) return hipSuccess;
   if (!trisolve_mm_fits(L, sizeof(C))) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_fwd_mm<R, kMmSpw>), dim3(ntiles), dim3(256), fwd_mm_lds(L, sizeof(C)), st, g, L, ent, tiles,
-                     ft, coef, mf, pf, pflag, io, ybuf);
+  const size_t shm = fwd_mm_lds(L, sizeof(C));
+#define HBJ_FWD_MM(S)                                                                                          \
+  hipLaunchKernelGGL((k_fwd_mm<R, S>), dim3(ntiles), dim3(256), shm, st, g, L, ent, tiles, ft, coef, mf, pf, pflag, \
+                     io, ybuf)
+  switch (mm_spw(L.wf)) {
+    case 1: HBJ_FWD_MM(1); break;
+    case 2: HBJ_FWD_MM(2); break;
+    case 3: HBJ_FWD_MM(3); break;
+    case 4: HBJ_FWD_MM(4); break;
+    default: HBJ_FWD_MM(5); break;
+  }
+#undef HBJ_FWD_MM
   return hipGetLastError();
 }
 
@@ -846,8 +885,17 @@ hipError_t launch_bwd_mm(const Geom& g, const SolveLayout& L, const Entry* ent, 
   typedef typename Cplx<R>::T C;
   if (ntiles == 0) return hipSuccess;
   if (!trisolve_mm_fits(L, sizeof(C))) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_bwd_mm<R, kMmSpw>), dim3(ntiles), dim3(256), 512 * sizeof(C), st, g, L, ent, tiles, ft, coef,
-                     mb, io, ybuf);
+  const size_t shm = 512 * sizeof(C);
+#define HBJ_BWD_MM(S)                                                                                           \
+  hipLaunchKernelGGL((k_bwd_mm<R, S>), dim3(ntiles), dim3(256), shm, st, g, L, ent, tiles, ft, coef, mb, io, ybuf)
+  switch (mm_spw(L.wb)) {
+    case 1: HBJ_BWD_MM(1); break;
+    case 2: HBJ_BWD_MM(2); break;
+    case 3: HBJ_BWD_MM(3); break;
+    case 4: HBJ_BWD_MM(4); break;
+    default: HBJ_BWD_MM(5); break;
+  }
+#undef HBJ_BWD_MM
   return hipGetLastError();
 }
 
