@@ -240,16 +240,18 @@ hipError_t launch_bwd(const Geom& g, const SolveLayout& L, const Entry* ent, int
 
 // The same solves for tiles of up to 16 entries of one subdomain (tiles[t] = {first entry, count},
 // entries of a tile consecutive and with the same subdomain), 16 right-hand sides per workgroup on
-// MFMA; results and outputs as launch_fwd / launch_bwd.
+// MFMA; results and outputs as launch_fwd / launch_bwd.  piv: some subdomain has row interchanges.
+// sink: nblk * nb elements that absorb the stores of lanes without a right-hand side.
 bool trisolve_mm_fits(const SolveLayout& L, size_t elem);
 template <typename R>
 hipError_t launch_fwd_mm(const Geom& g, const SolveLayout& L, const Entry* ent, const int2* tiles, int ntiles,
                          const FaceTab* ft, const IfCoef* coef, const typename Cplx<R>::T* mf, const int16_t* pf,
-                         const int32_t* pflag, const SolveIO& io, typename Cplx<R>::T* ybuf, hipStream_t st);
+                         const int32_t* pflag, bool piv, const SolveIO& io, typename Cplx<R>::T* ybuf,
+                         typename Cplx<R>::T* sink, hipStream_t st);
 template <typename R>
 hipError_t launch_bwd_mm(const Geom& g, const SolveLayout& L, const Entry* ent, const int2* tiles, int ntiles,
                          const FaceTab* ft, const IfCoef* coef, const typename Cplx<R>::T* mb, const SolveIO& io,
-                         typename Cplx<R>::T* ybuf, hipStream_t st);
+                         typename Cplx<R>::T* ybuf, typename Cplx<R>::T* sink, hipStream_t st);
 
 // Krylov helpers on [ncol][n] column blocks (complex128)
 hipError_t launch_multidot(const double2* V, size_t vstride, int nvec, const double2* w, int n, int ncol,

@@ -482,110 +482,167 @@ __device__ inline int xcd_tile(int b, int n) {
   return x * q + min(x, r) + k;
 }
 
+// Per-wavefront state of the MFMA band solves: wavefront w holds the logical window tiles
+// w SPW + si (si < SPW) in accumulators, so every tile keeps one role (and one set of load
+// offsets and row masks) for the whole solve; the window slides by moving tiles one slot along,
+// the tile that leaves a wavefront's range passing to the neighbouring wavefront through LDS.
 template <typename R, int SPW>
+struct MmWin {
+  typedef typename TriMma<R>::V V;
+  V wr[SPW], wi[SPW];
+  __device__ inline void zero(int si) {
+    wr[si] = V{0, 0, 0, 0};
+    wi[si] = V{0, 0, 0, 0};
+  }
+  template <typename C>
+  __device__ inline void set(int si, const C (&v)[4]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      wr[si][r] = (R)v[r].x;
+      wi[si][r] = (R)v[r].y;
+    }
+  }
+  // tile si to LDS as [16 rows][16 right-hand sides] (this lane: rows row_of(lane, r), column lane % 16)
+  template <typename C>
+  __device__ inline void put(int si, C* dst, int lane) const {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dst[TriMma<R>::row_of(lane, r) * 16 + (lane & 15)] = mkc<C, R>(wr[si][r], wi[si][r]);
+  }
+  template <typename C>
+  __device__ inline void get(int si, const C* src, int lane) {
+    C v[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[r] = src[TriMma<R>::row_of(lane, r) * 16 + (lane & 15)];
+    set(si, v);
+  }
+};
+
+// Every global load and store of the block loops is issued by every lane on every path (rows out of
+// range are clamped and replaced where they are used; the final rows of a block are stored by all
+// four wavefronts from LDS, lanes without a right-hand side writing to a sink), so the compiler can
+// count the loads in flight exactly and waits only for the previous block's.  PIV: the subdomains may
+// have row interchanges (a per-block flag and permutation; otherwise the flags are not read).
+template <typename R, int SPW, bool PIV>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_fwd_mm(
     Geom g, SolveLayout L, const Entry* ent, const int2* tiles, const FaceTab* ft, const IfCoef* coef,
     const typename Cplx<R>::T* __restrict__ MF, const int16_t* __restrict__ PF, const int32_t* __restrict__ PFL,
-    SolveIO io, typename Cplx<R>::T* __restrict__ ybuf) {
+    SolveIO io, typename Cplx<R>::T* __restrict__ ybuf, typename Cplx<R>::T* __restrict__ sink) {
   typedef typename Cplx<R>::T C;
   typedef TriMma<R> T;
-  typedef typename T::V V;
   constexpr int NT = 4 * SPW;  // window tiles; rows past wf have zero multipliers
   extern __shared__ unsigned char smem_raw[];
   const int nblk = L.nblk, wf = L.wf, ylen = nblk * 16;
-  C* xsh = reinterpret_cast<C*>(smem_raw);                   // [2][16 rows][16 right-hand sides]
-  int* ident = reinterpret_cast<int*>(xsh + 512);            // [nblk]
-  C* wsh = reinterpret_cast<C*>(ident + ((nblk + 3) & ~3));  // [NT * 16 rows][16]: interchanges
+  C* xsh = reinterpret_cast<C*>(smem_raw);                               // [2][16 rows][16]: X of a block
+  int* ident = reinterpret_cast<int*>(xsh + 512);                        // [nblk] (PIV)
+  C* wsh = reinterpret_cast<C*>(ident + (PIV ? ((nblk + 3) & ~3) : 0));  // [NT * 16][16] interchanges, or:
+  C* bsh = wsh;                                                          // [2][3][16][16] tiles passed on
+  C* ysh = wsh + 6 * 256;                                                // [2][16][16] final rows
   const int tix = xcd_tile(blockIdx.x, gridDim.x);
   const int2 tl = make_int2(__builtin_amdgcn_readfirstlane(tiles[tix].x),
                             __builtin_amdgcn_readfirstlane(tiles[tix].y));  // first entry, count (1..16)
   const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool mine = j < tl.y;  // lanes past the count work on a copy of the first entry, unstored
-  const int slot = tl.x + (mine ? j : 0);
-  const Entry e = ent[slot];
   const int s = __builtin_amdgcn_readfirstlane(ent[tl.x].s);
   const FaceTab F = ft[s];
-  const bool zero = !mine || (io.nz && !io.nz[(size_t)e.rhs * g.n1 * g.n2 + e.s]);
-  const RhsCtx rhs(g, e, F, coef, io, slot);
   const C* M = MF + (size_t)s * L.mf_per_sub;
   const int16_t* P = PF + (size_t)s * L.pf_per_sub;
-  C* y = ybuf + (size_t)tl.x * ylen;                   // the tile's first solve buffer (uniform)
+  C* y = ybuf + (size_t)tl.x * ylen;                      // the tile's first solve buffer (uniform)
   const unsigned yl = (unsigned)((mine ? j : 0) * ylen);  // this lane's, relative to it
-  for (int b = threadIdx.x; b < nblk; b += 256) ident[b] = PFL[(size_t)s * nblk + b];
+  C* yout = mine ? ybuf + (size_t)(tl.x + j) * ylen : sink;  // where this lane's final rows go
+  if (PIV)
+    for (int b = threadIdx.x; b < nblk; b += 256) ident[b] = PFL[(size_t)s * nblk + b];
+  {  // the right-hand sides into the solve buffers (the window reads them ahead of the solution)
+    const int jj = threadIdx.x & 15;
+    if (jj < tl.y) {
+      const Entry ej = ent[tl.x + jj];
+      const bool zj = io.nz && !io.nz[(size_t)ej.rhs * g.n1 * g.n2 + ej.s];
+      const RhsCtx rj(g, ej, F, coef, io, tl.x + jj);
+      C* yj = ybuf + (size_t)(tl.x + jj) * ylen;
+      for (int l = threadIdx.x >> 4; l < ylen; l += 16) yj[l] = zj ? czero<C>() : to_c<C>(rj(l));
+    }
+  }
+  __syncthreads();
 
+  // rows row0 + [0, 16) of the right-hand sides (row0 a multiple of 16): always loaded (clamped into
+  // the buffer), so that the number of loads in flight is the same on every path; rows past the end
+  // are replaced by zeros where they enter the window
   auto fresh = [&](int row0, C(&v)[4]) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int l = row0 + T::row_of(lane, r);
-      v[r] = (zero || row0 >= ylen) ? czero<C>() : to_c<C>(rhs(l));
-    }
+    for (int r = 0; r < 4; ++r) v[r] = y[yl + (unsigned)min(row0 + T::row_of(lane, r), ylen - 1)];
   };
-  // multipliers of logical tile t of block b: row 16 t + j, columns 4 ks + q.  In the tiled layout
-  // entry (r, 4 ks + q) lies at (q wf + r) cg + kofs[ks]: a lane part and a uniform part per k-step.
+  // multipliers: entry (row r, column 4 ks + q) of a block lies at (q wf + r) cg + kofs[ks] in the
+  // tiled layout; the row of tile si is 16 (w SPW + si) + j (clamped, masked by ok)
   const int cg = L.cgf, nc = 16 / cg;
   int kofs[4];
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) kofs[ks] = ((4 * ks) % nc) * wf * cg + (4 * ks) / nc;
-  auto load_a = [&](int b, int t, C(&a)[4]) {  // rows past the band: clamped here, masked at use
-    const C* Mb = M + (size_t)b * 16 * wf;
-    const unsigned ob = (unsigned)((q * wf + min(16 * t + j, wf - 1)) * cg) * (unsigned)sizeof(C);
+  unsigned lo[SPW];
+  R ok[SPW];
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) a[ks] = *reinterpret_cast<const C*>(reinterpret_cast<const char*>(Mb + kofs[ks]) + ob);
+  for (int si = 0; si < SPW; ++si) {
+    const int row = 16 * (w * SPW + si) + j;
+    lo[si] = (unsigned)((q * wf + min(row, wf - 1)) * cg) * (unsigned)sizeof(C);
+    ok[si] = row < wf ? (R)1 : (R)0;
+  }
+  auto load_a = [&](int b, C(&a)[SPW][4]) {
+    const C* Mb = M + (size_t)b * 16 * wf;
+#pragma unroll
+    for (int si = 0; si < SPW; ++si)
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        a[si][ks] = *reinterpret_cast<const C*>(reinterpret_cast<const char*>(Mb + kofs[ks]) + lo[si]);
   };
-  // logical tile of physical tile w + 4 si at block b (b mod NT = bm)
-  auto logical = [&](int si, int bm) { return (w + 4 * si - bm + NT) % NT; };
 
-  V wr[SPW], wi[SPW];
+  MmWin<R, SPW> W;
   C a0[SPW][4], a1[SPW][4];
   C f0[4], f1[4];
 #pragma unroll
   for (int si = 0; si < SPW; ++si) {
     C v[4];
-    fresh(16 * (w + 4 * si), v);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      wr[si][r] = (R)v[r].x;
-      wi[si][r] = (R)v[r].y;
-    }
-    load_a(0, w + 4 * si, a0[si]);
+    fresh(16 * (w * SPW + si), v);
+    if (16 * (w * SPW + si) < ylen) W.set(si, v);
+    else W.zero(si);
   }
-  fresh(NT * 16, f0);
-  if (w == 0) {  // X of block 0: logical tile 0 = physical tile 0 (wavefront 0, slot 0)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) xsh[T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[0][r], wi[0][r]);
+  load_a(0, a0);
+  fresh(NT * 16, f0);  // used by wavefront 3
+  if (w == 0) {  // X of block 0 is logical tile 0; that tile then starts from zero
+    W.put(0, xsh, lane);
+    W.zero(0);
   }
   __syncthreads();
 
-  int bm = 0;  // b mod NT
-  // one block: the multipliers of this block are in acur (loaded one block earlier), the rows that
-  // enter the window after it in fr; the next block's go to anxt / frn
   auto block = [&](int b, C(&acur)[SPW][4], C(&anxt)[SPW][4], C(&fr)[4], C(&frn)[4]) {
     const int par = b & 1;
-    const int bn = min(b + 1, nblk - 1), bmn = (bm + 1 == NT) ? 0 : bm + 1;
-#pragma unroll
-    for (int si = 0; si < SPW; ++si) load_a(bn, logical(si, bmn), anxt[si]);
-    fresh((b + 1 + NT) * 16, frn);
+    load_a(min(b + 1, nblk - 1), anxt);
+    fresh((b + 1 + NT) * 16, frn);  // used by wavefront 3; loaded by all so that the load count is static
     R xr[4], xi[4];
-    if (!__builtin_amdgcn_readfirstlane(ident[b])) {  // row interchanges: gather the window through LDS
+    if (PIV && !__builtin_amdgcn_readfirstlane(ident[b])) {  // row interchanges: gather the window through LDS
+      __syncthreads();  // the scratch also holds the tiles passed on at the end of the last block
 #pragma unroll
       for (int si = 0; si < SPW; ++si) {
-        const int t = logical(si, bm);
+        C* dst = wsh + (w * SPW + si) * 256;
+        if (w == 0 && si == 0) {  // logical tile 0 is X (its accumulator was cleared)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) wsh[(16 * t + T::row_of(lane, r)) * 16 + j] = mkc<C, R>(wr[si][r], wi[si][r]);
+          for (int r = 0; r < 4; ++r) {
+            const int o = T::row_of(lane, r) * 16 + j;
+            dst[o] = xsh[par * 256 + o];
+          }
+        } else {
+          W.put(si, dst, lane);
+        }
       }
       __syncthreads();
       const int16_t* Pb = P + (size_t)b * wf;
 #pragma unroll
       for (int si = 0; si < SPW; ++si) {
-        const int t = logical(si, bm);
+        C v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int row = 16 * t + T::row_of(lane, r);
-          const C v = wsh[(row < wf ? (int)Pb[row] : row) * 16 + j];
-          wr[si][r] = (R)v.x;
-          wi[si][r] = (R)v.y;
+          const int row = 16 * (w * SPW + si) + T::row_of(lane, r);
+          v[r] = wsh[(row < wf ? (int)Pb[row] : row) * 16 + j];
         }
+        W.set(si, v);
       }
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
@@ -593,6 +650,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         xr[ks] = (R)v.x;
         xi[ks] = (R)v.y;
       }
+      if (w == 0) W.zero(0);
       __syncthreads();
     } else {
 #pragma unroll
@@ -602,38 +660,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
         xi[ks] = (R)v.y;
       }
     }
-    // the tile holding the block's own rows starts from zero; every tile then takes M_t X
-    R ok[SPW];
-#pragma unroll
-    for (int si = 0; si < SPW; ++si) {
-      ok[si] = (16 * logical(si, bm) + j < wf) ? (R)1 : (R)0;
-      if (logical(si, bm) == 0) {
-        wr[si] = V{0, 0, 0, 0};
-        wi[si] = V{0, 0, 0, 0};
-      }
+    tiles_mma<R, SPW>(acur, ok, xr, xi, W.wr, W.wi);
+    // logical tile 0 holds the block's final rows; tile 1 is the next block's X; the window moves
+    // down one tile: every tile goes one slot lower, slot 0 of wavefronts 1-3 to the wavefront below
+    if (w == 0) W.put(0, ysh + par * 256, lane);
+    else W.put(0, bsh + (par * 3 + w - 1) * 256, lane);
+    if (SPW >= 2) {
+      if (w == 0) W.put(1, xsh + (par ^ 1) * 256, lane);
+    } else {
+      if (w == 1) W.put(0, xsh + (par ^ 1) * 256, lane);
     }
-    tiles_mma<R, SPW>(acur, ok, xr, xi, wr, wi);
 #pragma unroll
-    for (int si = 0; si < SPW; ++si) {
-      const int t = logical(si, bm);
-      if (t == 0) {  // the block's rows are final; the tile re-enters as the window's last rows
-        if (mine) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) y[yl + (unsigned)(b * 16 + T::row_of(lane, r))] = mkc<C, R>(wr[si][r], wi[si][r]);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          wr[si][r] = (R)fr[r].x;
-          wi[si][r] = (R)fr[r].y;
-        }
-      } else if (t == 1) {  // X of the next block
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          xsh[(par ^ 1) * 256 + T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[si][r], wi[si][r]);
-      }
+    for (int si = 0; si + 1 < SPW; ++si) {
+      W.wr[si] = W.wr[si + 1];
+      W.wi[si] = W.wi[si + 1];
     }
+    if (SPW >= 2 && w == 0) W.zero(0);  // the next block's X: its tile starts from zero
     __syncthreads();
-    bm = bmn;
+    yout[b * 16 + 4 * w + q] = ysh[par * 256 + (4 * w + q) * 16 + j];  // rows 4 w + [0, 4) of the final rows
+    if (w == 3) {  // rows entering the window
+      if ((b + NT) * 16 < ylen) W.set(SPW - 1, fr);
+      else W.zero(SPW - 1);
+    } else if (SPW == 1 && w == 0) {
+      W.zero(0);
+    } else {
+      W.get(SPW - 1, bsh + (par * 3 + w) * 256, lane);
+    }
   };
   int b = 0;
   for (; b + 1 < nblk; b += 2) {  // two blocks per trip: the register sets swap roles without copies
@@ -646,78 +698,77 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 template <typename R, int SPW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_bwd_mm(
     Geom g, SolveLayout L, const Entry* ent, const int2* tiles, const FaceTab* ft, const IfCoef* coef,
-    const typename Cplx<R>::T* __restrict__ MB, SolveIO io, typename Cplx<R>::T* __restrict__ ybuf) {
+    const typename Cplx<R>::T* __restrict__ MB, SolveIO io, typename Cplx<R>::T* __restrict__ ybuf,
+    typename Cplx<R>::T* __restrict__ sink) {
   typedef typename Cplx<R>::T C;
   typedef TriMma<R> T;
-  typedef typename T::V V;
   constexpr int NT = 4 * SPW;  // window tiles; rows above the band have zero multipliers
   extern __shared__ unsigned char smem_raw[];
   const int nblk = L.nblk, wb = L.wb, pad = NT * 16 - wb, ylen = nblk * 16;
-  C* xsh = reinterpret_cast<C*>(smem_raw);  // [2][16 rows][16 right-hand sides]
+  C* xsh = reinterpret_cast<C*>(smem_raw);  // [2][16 rows][16]: X of a block
+  C* bsh = xsh + 512;                       // [2][3][16][16]: tiles passed on
+  C* ysh = bsh + 6 * 256;                   // [2][16][16]: final rows
   const int tix = xcd_tile(blockIdx.x, gridDim.x);
   const int2 tl = make_int2(__builtin_amdgcn_readfirstlane(tiles[tix].x), __builtin_amdgcn_readfirstlane(tiles[tix].y));
-  const int lane = threadIdx.x & 63, j = lane & 15;
+  const int lane = threadIdx.x & 63, j = lane & 15, q = lane >> 4;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const bool mine = j < tl.y;
-  const int slot = tl.x + (mine ? j : 0);
   const int s = __builtin_amdgcn_readfirstlane(ent[tl.x].s);
   const C* M = MB + (size_t)s * L.mb_per_sub;
-  C* y = ybuf + (size_t)tl.x * ylen;                   // the tile's first solve buffer (uniform)
+  C* y = ybuf + (size_t)tl.x * ylen;                      // the tile's first solve buffer (uniform)
   const unsigned yl = (unsigned)((mine ? j : 0) * ylen);  // this lane's, relative to it
-  const int q = lane >> 4;
-  // logical tile u of step i (block b = nblk - 1 - i) holds rows b*16 - (NT - 1 - u)*16 + [0, 16),
-  // window rows 16 u - pad + [0, 16) of k_bwd; it is physical tile (u - i) mod NT
-  auto fresh = [&](int row0, C(&v)[4]) {  // row0 is a multiple of 16: the tile is in range or above row 0
-    if (row0 >= 0) {
+  C* yout = mine ? ybuf + (size_t)(tl.x + j) * ylen : sink;  // where this lane's final rows go
+  // logical tile u of the step for block b holds rows b*16 - (NT - 1 - u)*16 + [0, 16), window
+  // rows 16 u - pad + [0, 16) of k_bwd
+  // rows row0 + [0, 16) of y (row0 a multiple of 16): always loaded (clamped to row 0 above the
+  // matrix), rows above the matrix replaced by zeros where they enter the window
+  auto fresh = [&](int row0, C(&v)[4]) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = y[yl + (unsigned)(row0 + T::row_of(lane, r))];
-    } else {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) v[r] = czero<C>();
-    }
+    for (int r = 0; r < 4; ++r) v[r] = y[yl + (unsigned)max(row0 + T::row_of(lane, r), 0)];
   };
-  // multipliers of logical tile u: window row 16 u + j - pad, columns 4 ks + q (layout as in k_fwd_mm)
   const int cg = L.cgb, nc = 16 / cg;
   int kofs[4];
 #pragma unroll
   for (int ks = 0; ks < 4; ++ks) kofs[ks] = ((4 * ks) % nc) * wb * cg + (4 * ks) / nc;
-  auto load_a = [&](int b, int u, C(&a)[4]) {  // rows above the band: clamped here, masked at use
-    const C* Mb = M + (size_t)b * 16 * wb;
-    const unsigned ob = (unsigned)((q * wb + max(16 * u + j - pad, 0)) * cg) * (unsigned)sizeof(C);
+  unsigned lo[SPW];
+  R ok[SPW];
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) a[ks] = *reinterpret_cast<const C*>(reinterpret_cast<const char*>(Mb + kofs[ks]) + ob);
+  for (int si = 0; si < SPW; ++si) {
+    const int row = 16 * (w * SPW + si) + j - pad;
+    lo[si] = (unsigned)((q * wb + max(row, 0)) * cg) * (unsigned)sizeof(C);
+    ok[si] = row >= 0 ? (R)1 : (R)0;
+  }
+  auto load_a = [&](int b, C(&a)[SPW][4]) {
+    const C* Mb = M + (size_t)b * 16 * wb;
+#pragma unroll
+    for (int si = 0; si < SPW; ++si)
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+        a[si][ks] = *reinterpret_cast<const C*>(reinterpret_cast<const char*>(Mb + kofs[ks]) + lo[si]);
   };
-  auto logical = [&](int si, int im) { return (w + 4 * si + im) % NT; };
 
-  V wr[SPW], wi[SPW];
+  MmWin<R, SPW> W;
   C a0[SPW][4], a1[SPW][4];
   C f0[4], f1[4];
 #pragma unroll
   for (int si = 0; si < SPW; ++si) {
-    const int p = w + 4 * si;
     C v[4];
-    fresh((nblk - NT + p) * 16, v);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      wr[si][r] = (R)v[r].x;
-      wi[si][r] = (R)v[r].y;
-    }
-    load_a(nblk - 1, p, a0[si]);
+    fresh((nblk - NT + w * SPW + si) * 16, v);
+    if (nblk - NT + w * SPW + si >= 0) W.set(si, v);
+    else W.zero(si);
   }
-  fresh((nblk - 1 - NT) * 16, f0);
-  if (w == 3) {  // X of the last block: logical tile NT - 1 = physical tile NT - 1 (wavefront 3, last slot)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) xsh[T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[SPW - 1][r], wi[SPW - 1][r]);
+  load_a(nblk - 1, a0);
+  fresh((nblk - 1 - NT) * 16, f0);  // used by wavefront 0
+  if (w == 3) {  // X of the last block is logical tile NT - 1; that tile then starts from zero
+    W.put(SPW - 1, xsh, lane);
+    W.zero(SPW - 1);
   }
   __syncthreads();
 
-  int im = 0;  // i mod NT
   auto step = [&](int i, C(&acur)[SPW][4], C(&anxt)[SPW][4], C(&fr)[4], C(&frn)[4]) {
     const int b = nblk - 1 - i, par = i & 1;
-    const int bn = max(b - 1, 0), imn = (im + 1 == NT) ? 0 : im + 1;
-#pragma unroll
-    for (int si = 0; si < SPW; ++si) load_a(bn, logical(si, imn), anxt[si]);
-    fresh((b - 1 - NT) * 16, frn);
+    load_a(max(b - 1, 0), anxt);
+    fresh((b - 1 - NT) * 16, frn);  // used by wavefront 0; loaded by all so that the load count is static
     R xr[4], xi[4];
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
@@ -725,37 +776,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       xr[ks] = (R)v.x;
       xi[ks] = (R)v.y;
     }
-    R ok[SPW];
-#pragma unroll
-    for (int si = 0; si < SPW; ++si) {
-      ok[si] = (16 * logical(si, im) + j >= pad) ? (R)1 : (R)0;
-      if (logical(si, im) == NT - 1) {
-        wr[si] = V{0, 0, 0, 0};
-        wi[si] = V{0, 0, 0, 0};
-      }
+    tiles_mma<R, SPW>(acur, ok, xr, xi, W.wr, W.wi);
+    // logical tile NT - 1 holds the block's unknowns; tile NT - 2 is the next block's X; the window
+    // moves up one tile: every tile goes one slot higher, the last slot of wavefronts 0-2 to the next
+    if (w == 3) W.put(SPW - 1, ysh + par * 256, lane);
+    else W.put(SPW - 1, bsh + (par * 3 + w) * 256, lane);
+    if (SPW >= 2) {
+      if (w == 3) W.put(SPW - 2, xsh + (par ^ 1) * 256, lane);
+    } else {
+      if (w == 2) W.put(0, xsh + (par ^ 1) * 256, lane);
     }
-    tiles_mma<R, SPW>(acur, ok, xr, xi, wr, wi);
 #pragma unroll
-    for (int si = 0; si < SPW; ++si) {
-      const int u = logical(si, im);
-      if (u == NT - 1) {  // the block's unknowns are final; the tile re-enters as the window's top rows
-        if (mine) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) y[yl + (unsigned)(b * 16 + T::row_of(lane, r))] = mkc<C, R>(wr[si][r], wi[si][r]);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          wr[si][r] = (R)fr[r].x;
-          wi[si][r] = (R)fr[r].y;
-        }
-      } else if (u == NT - 2) {  // X of the next block
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          xsh[(par ^ 1) * 256 + T::row_of(lane, r) * 16 + j] = mkc<C, R>(wr[si][r], wi[si][r]);
-      }
+    for (int si = SPW - 1; si > 0; --si) {
+      W.wr[si] = W.wr[si - 1];
+      W.wi[si] = W.wi[si - 1];
     }
+    if (SPW >= 2 && w == 3) W.zero(SPW - 1);  // the next block's X: its tile starts from zero
     __syncthreads();
-    im = imn;
+    yout[b * 16 + 4 * w + q] = ysh[par * 256 + (4 * w + q) * 16 + j];  // rows 4 w + [0, 4) of the unknowns
+    if (w == 0) {  // rows entering the window
+      if (b - NT >= 0) W.set(0, fr);
+      else W.zero(0);
+    } else if (SPW == 1 && w == 3) {
+      W.zero(0);
+    } else {
+      W.get(0, bsh + (par * 3 + w - 1) * 256, lane);
+    }
   };
   int i = 0;
   for (; i + 1 < nblk; i += 2) {
@@ -763,6 +809,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     step(i + 1, a1, a0, f1, f0);
   }
   if (i < nblk) step(i, a0, a1, f0, f1);
+  __syncthreads();
   // the solutions are final: the outputs of every entry of the tile, as k_bwd writes them
   const FaceTab F = ft[s];
   const int cnt = tl.y, nloc = g.nloc;
@@ -848,8 +895,10 @@ constexpr int kMmSpwMax = 5;  // window tiles per wavefront of the MFMA solves: 
 // tiles per wavefront for a window of `rows` rows (the window is padded to 4 x that many tiles)
 static int mm_spw(int rows) { return ((rows + 15) / 16 + 3) / 4; }
 
-static size_t fwd_mm_lds(const SolveLayout& L, size_t elem) {
-  return 512 * elem + (size_t)((L.nblk + 3) & ~3) * sizeof(int) + (size_t)(4 * mm_spw(L.wf)) * 256 * elem;
+// X, flags, interchange scratch / tiles passed on and final rows
+static size_t fwd_mm_lds(const SolveLayout& L, size_t elem, bool piv = true) {
+  return 512 * elem + (piv ? (size_t)((L.nblk + 3) & ~3) * sizeof(int) : 0) +
+         (size_t)std::max(piv ? 4 * mm_spw(L.wf) : 0, 8) * 256 * elem;
 }
 
 bool trisolve_mm_fits(const SolveLayout& L, size_t elem) {
@@ -859,21 +908,25 @@ bool trisolve_mm_fits(const SolveLayout& L, size_t elem) {
 template <typename R>
 hipError_t launch_fwd_mm(const Geom& g, const SolveLayout& L, const Entry* ent, const int2* tiles, int ntiles,
                          const FaceTab* ft, const IfCoef* coef, const typename Cplx<R>::T* mf, const int16_t* pf,
-                         const int32_t* pflag, const SolveIO& io, typename Cplx<R>::T* ybuf, hipStream_t st) {
+                         const int32_t* pflag, bool piv, const SolveIO& io, typename Cplx<R>::T* ybuf,
+                         typename Cplx<R>::T* sink, hipStream_t st) {
   typedef typename Cplx<R>::T C;
   if (ntiles == 0) return hipSuccess;
   if (!trisolve_mm_fits(L, sizeof(C))) return hipErrorInvalidValue;
-  const size_t shm = fwd_mm_lds(L, sizeof(C));
-#define HBJ_FWD_MM(S)                                                                                          \
-  hipLaunchKernelGGL((k_fwd_mm<R, S>), dim3(ntiles), dim3(256), shm, st, g, L, ent, tiles, ft, coef, mf, pf, pflag, \
-                     io, ybuf)
+  const size_t shm = fwd_mm_lds(L, sizeof(C), piv);
+#define HBJ_FWD_MM(S, P)                                                                                      \
+  hipLaunchKernelGGL((k_fwd_mm<R, S, P>), dim3(ntiles), dim3(256), shm, st, g, L, ent, tiles, ft, coef, mf, pf, \
+                     pflag, io, ybuf, sink)
+#define HBJ_FWD_MM2(S) \
+  if (piv) HBJ_FWD_MM(S, true); else HBJ_FWD_MM(S, false)
   switch (mm_spw(L.wf)) {
-    case 1: HBJ_FWD_MM(1); break;
-    case 2: HBJ_FWD_MM(2); break;
-    case 3: HBJ_FWD_MM(3); break;
-    case 4: HBJ_FWD_MM(4); break;
-    default: HBJ_FWD_MM(5); break;
+    case 1: HBJ_FWD_MM2(1); break;
+    case 2: HBJ_FWD_MM2(2); break;
+    case 3: HBJ_FWD_MM2(3); break;
+    case 4: HBJ_FWD_MM2(4); break;
+    default: HBJ_FWD_MM2(5); break;
   }
+#undef HBJ_FWD_MM2
 #undef HBJ_FWD_MM
   return hipGetLastError();
 }
@@ -881,13 +934,14 @@ hipError_t launch_fwd_mm(const Geom& g, const SolveLayout& L, const Entry* ent, 
 template <typename R>
 hipError_t launch_bwd_mm(const Geom& g, const SolveLayout& L, const Entry* ent, const int2* tiles, int ntiles,
                          const FaceTab* ft, const IfCoef* coef, const typename Cplx<R>::T* mb, const SolveIO& io,
-                         typename Cplx<R>::T* ybuf, hipStream_t st) {
+                         typename Cplx<R>::T* ybuf, typename Cplx<R>::T* sink, hipStream_t st) {
   typedef typename Cplx<R>::T C;
   if (ntiles == 0) return hipSuccess;
   if (!trisolve_mm_fits(L, sizeof(C))) return hipErrorInvalidValue;
-  const size_t shm = 512 * sizeof(C);
+  const size_t shm = (512 + 8 * 256) * sizeof(C);  // X, tiles passed on, final rows
 #define HBJ_BWD_MM(S)                                                                                           \
-  hipLaunchKernelGGL((k_bwd_mm<R, S>), dim3(ntiles), dim3(256), shm, st, g, L, ent, tiles, ft, coef, mb, io, ybuf)
+  hipLaunchKernelGGL((k_bwd_mm<R, S>), dim3(ntiles), dim3(256), shm, st, g, L, ent, tiles, ft, coef, mb, io, ybuf, \
+                     sink)
   switch (mm_spw(L.wb)) {
     case 1: HBJ_BWD_MM(1); break;
     case 2: HBJ_BWD_MM(2); break;
@@ -901,16 +955,16 @@ hipError_t launch_bwd_mm(const Geom& g, const SolveLayout& L, const Entry* ent, 
 
 template hipError_t launch_fwd_mm<double>(const Geom&, const SolveLayout&, const Entry*, const int2*, int,
                                           const FaceTab*, const IfCoef*, const double2*, const int16_t*,
-                                          const int32_t*, const SolveIO&, double2*, hipStream_t);
+                                          const int32_t*, bool, const SolveIO&, double2*, double2*, hipStream_t);
 template hipError_t launch_fwd_mm<float>(const Geom&, const SolveLayout&, const Entry*, const int2*, int,
                                          const FaceTab*, const IfCoef*, const float2*, const int16_t*, const int32_t*,
-                                         const SolveIO&, float2*, hipStream_t);
+                                         bool, const SolveIO&, float2*, float2*, hipStream_t);
 template hipError_t launch_bwd_mm<double>(const Geom&, const SolveLayout&, const Entry*, const int2*, int,
                                           const FaceTab*, const IfCoef*, const double2*, const SolveIO&, double2*,
-                                          hipStream_t);
+                                          double2*, hipStream_t);
 template hipError_t launch_bwd_mm<float>(const Geom&, const SolveLayout&, const Entry*, const int2*, int,
                                          const FaceTab*, const IfCoef*, const float2*, const SolveIO&, float2*,
-                                         hipStream_t);
+                                         float2*, hipStream_t);
 
 hipError_t launch_build_rhs(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
                             const SolveIO& io, double2* rhs64, hipStream_t st) {

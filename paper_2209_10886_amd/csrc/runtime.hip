@@ -174,6 +174,7 @@ struct hbj_ctx {
   Gmres* gm = nullptr;
   bool use_graphs = false;  // eager launches measured faster once step j+1 is queued ahead
   int orth = HBJ_ORTH_DCGS2;     // Gram-Schmidt variant of the Arnoldi steps
+  bool interchanges = true;      // some subdomain factorisation has row interchanges (set by hbj_factor)
   int msolve = HBJ_MSOLVE_MFMA;  // banded solves of many right-hand sides per subdomain on MFMA
   int graph_epoch = 0;           // bumped when captured operands change (a new factorisation)
   hipStream_t cap = nullptr;     // capture stream (graphs are replayed on st)
@@ -415,7 +416,7 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
 }
 
 int ensure_ybuf(hbj_ctx* c, size_t entries, size_t elem_bytes) {
-  const size_t need = entries * (size_t)c->L.nblk * c->L.nb * elem_bytes;
+  const size_t need = (entries + 1) * (size_t)c->L.nblk * c->L.nb * elem_bytes;  // one spare entry (MFMA solves)
   if (need <= c->ybuf_bytes) return HBJ_OK;
   dfree(c->ybuf);
   c->ybuf = nullptr;
@@ -496,18 +497,19 @@ int launch_solve_pair(hbj_ctx* c, const Entry* ent, int nent, const int2* tiles,
   const bool mm = c->msolve == HBJ_MSOLVE_MFMA && tiles && ntiles > 0 && nent >= kMmMinPerTile * ntiles &&
                   trisolve_mm_fits(c->L, sizeof(C));
   const double nread = mm ? (double)ntiles : (double)nent;
+  C* sink = (C*)c->ybuf + (size_t)nent * c->L.nblk * c->L.nb;  // the solve buffer holds one spare entry
   {
     ProfScope ps(c, HBJ_K_FWD, nread * fwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * c->g.kl);
     if (mm)
-      HIPCHK((launch_fwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mf, c->pf, c->pflag, io, (C*)c->ybuf,
-                               c->st)));
+      HIPCHK((launch_fwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mf, c->pf, c->pflag, c->interchanges,
+                               io, (C*)c->ybuf, sink, c->st)));
     else
       HIPCHK((launch_fwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mf, c->pf, c->pflag, io, (C*)c->ybuf, c->st)));
   }
   {
     ProfScope ps(c, HBJ_K_BWD, nread * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1));
     if (mm)
-      HIPCHK((launch_bwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st)));
+      HIPCHK((launch_bwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mb, io, (C*)c->ybuf, sink, c->st)));
     else
       HIPCHK((launch_bwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st)));
   }
@@ -1962,6 +1964,12 @@ int hbj_factor(hbj_ctx* c) {
                                       std::to_string(info[s] - 1));
     }
   HIPCHK(launch_repack(g, L, c->ab, c->ipiv, c->mf64, c->pf, c->pflag, c->mb64, c->ndom, c->st));
+  {  // blocks with row interchanges anywhere (the MFMA solves skip the permutation step without them)
+    std::vector<int32_t> fl((size_t)L.nblk * c->ndom);
+    HIPCHK(hipMemcpyAsync(fl.data(), c->pflag, fl.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    c->interchanges = std::find(fl.begin(), fl.end(), 0) != fl.end();
+  }
   if (c->P.precision == HBJ_MIXED) {
     HIPCHK(launch_cast_c64(c->mf64, c->mf32, L.mf_per_sub * c->ndom, c->st));
     HIPCHK(launch_cast_c64(c->mb64, c->mb32, L.mb_per_sub * c->ndom, c->st));
