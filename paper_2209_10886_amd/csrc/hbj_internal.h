@@ -222,7 +222,10 @@ hipError_t launch_local_diag(const Geom& g, const double* m, const FaceTab* ft, 
                              double2* diag, hipStream_t st);
 hipError_t launch_band_assemble(const Geom& g, const double2* diag, const FaceTab* ft, const IfBand* band, double2* ab,
                                 int nsub, hipStream_t st);
-hipError_t launch_band_lu(const Geom& g, double2* ab, int32_t* ipiv, int32_t* info, int nsub, hipStream_t st);
+// blocked: panels of 16 columns (the same factors; falls back to the column-by-column kernel when the
+// panel does not fit in LDS)
+hipError_t launch_band_lu(const Geom& g, double2* ab, int32_t* ipiv, int32_t* info, int nsub, hipStream_t st,
+                          bool blocked = true);
 hipError_t launch_repack(const Geom& g, const SolveLayout& L, const double2* ab, const int32_t* ipiv,
                          double2* mf, int16_t* pf, int32_t* pflag, double2* mb, int nsub, hipStream_t st);
 hipError_t launch_cast_c64(const double2* src, float2* dst, size_t n, hipStream_t st);
