@@ -326,13 +326,15 @@ hipError_t launch_recon_mm(const Geom& g, const IfCoef* coef, const FaceTab* ft,
 hipError_t launch_recon_dense(const Geom& g, const FaceTab* ft, const IfCoef* coef, const double2* W,
                               const double2* gin, const int32_t* nz, int nrhs, double2* u, hipStream_t st);
 
-// many right-hand sides: gather the incoming data G[j][col][r] of subdomains subs[j], then
-// OUT = T_s[masked rows, :] G_s on MFMA (complex128 operators on f64 MFMA, complex64 on f32)
+// many right-hand sides: gather the incoming data G[j][col][r] of subdomains subs[j] (in the element
+// type of the operators), then OUT = T_s[masked rows, :] G_s on MFMA (complex128 operators on f64
+// MFMA, complex64 on f32)
+template <typename GT>
 hipError_t launch_gather_incoming(const Geom& g, const int32_t* subs, int nsub, const FaceTab* ft, const double2* gin,
-                                  int nrhs, int rpad, double2* G, hipStream_t st);
+                                  int nrhs, int rpad, GT* G, hipStream_t st);
 template <typename C>
 hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int mask, const FaceTab* ft, const C* T,
-                             const double2* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st, int variant);
+                             const C* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st, int variant);
 constexpr int kMmVariants = 3;  // k-steps per batch of loads: 2, 4, 8
 
 // gradient / misc

@@ -16,9 +16,11 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 
 // G[j][col][r] = incoming datum of subdomain subs[j] at local interface position col, column r
 // With coef, every datum is scaled by inj of its position: the incoming data in the form the
-// lifting matrices W_s take for the reconstruction (x_col = W_s[.][col] inj_col).
+// lifting matrices W_s take for the reconstruction (x_col = W_s[.][col] inj_col).  GT: complex128,
+// or complex64 for the products on f32 MFMA (which round every operand to float anyway).
+template <typename GT>
 __global__ void k_gather_incoming(Geom g, const int32_t* subs, const FaceTab* ft, const double2* gin, int nrhs,
-                                  int rpad, double2* G, const IfCoef* coef) {
+                                  int rpad, GT* G, const IfCoef* coef) {
   const int j = blockIdx.y;
   const int s = subs ? subs[j] : j;
   const FaceTab F = ft[s];
@@ -34,7 +36,7 @@ __global__ void k_gather_incoming(Geom g, const int32_t* subs, const FaceTab* ft
       v = gin[(size_t)r * g.nif + io + ee];
       if (coef) v = cmul(coef[io + ee].inj, v);
     }
-    G[(size_t)j * n + t] = v;
+    G[(size_t)j * n + t] = to_c<GT>(v);
   }
 }
 
@@ -70,7 +72,7 @@ constexpr int KW = 4;  // wavefronts splitting the k range of one tile
 // eight independent accumulators; KB is the tile depth chosen by the autotuner.
 template <typename C, typename M, int KB>
 __global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_scatter_mm(Geom g, const int32_t* subs, int mask, const FaceTab* ft,
-                                                        const C* __restrict__ T, const double2* __restrict__ G,
+                                                        const C* __restrict__ T, const C* __restrict__ G,
                                                         int nrhs, int rpad, SolveIO io) {
   typedef MfmaAcc<M> A;
   typedef typename A::T V4;
@@ -86,7 +88,7 @@ __global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2)))
   const C* Ts = T + (size_t)s * t_per_sub(g) + t_index(L, mrow < 0 ? 0 : mrow, 0);
   // right-hand-side columns of this lane's B operands, clamped into the padded width (with fewer
   // than 64 right-hand sides the upper blocks of the tile do not exist; their results are dropped)
-  const double2* Gs = G + (size_t)j * L * rpad;
+  const C* Gs = G + (size_t)j * L * rpad;
   int jr[TB];
 #pragma unroll
   for (int t = 0; t < TB; ++t) jr[t] = min(rb0 + 16 * t + i, rpad - 1);
@@ -104,7 +106,7 @@ __global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2)))
     // this wavefront's k-steps: c0 + 4 (w + KW q), KB of them per batch
     for (int c = c0 + 4 * w; c < c1; c += 4 * KW * KB) {
       C tv[KB];
-      double2 gv[KB][TB];
+      C gv[KB][TB];
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
         const int col = c + 4 * KW * b + k;
@@ -241,7 +243,7 @@ hipError_t launch_recon_mm(const Geom& g, const IfCoef* coef, const FaceTab* ft,
   const int ndom = g.n1 * g.n2;
   const size_t n = (size_t)local_if_len(g) * rpad;
   const int bx = (int)std::min<size_t>(64, (n + 255) / 256);
-  hipLaunchKernelGGL(k_gather_incoming, dim3(bx, ndom), dim3(256), 0, st, g, (const int32_t*)nullptr, ft, gin, nrhs,
+  hipLaunchKernelGGL(k_gather_incoming<double2>, dim3(bx, ndom), dim3(256), 0, st, g, (const int32_t*)nullptr, ft, gin, nrhs,
                      rpad, Gbuf, coef);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -250,19 +252,24 @@ hipError_t launch_recon_mm(const Geom& g, const IfCoef* coef, const FaceTab* ft,
   return hipGetLastError();
 }
 
+template <typename GT>
 hipError_t launch_gather_incoming(const Geom& g, const int32_t* subs, int nsub, const FaceTab* ft, const double2* gin,
-                                  int nrhs, int rpad, double2* G, hipStream_t st) {
+                                  int nrhs, int rpad, GT* G, hipStream_t st) {
   if (nsub == 0) return hipSuccess;
   const size_t n = (size_t)local_if_len(g) * rpad;
   const int bx = (int)std::min<size_t>(64, (n + 255) / 256);
-  hipLaunchKernelGGL(k_gather_incoming, dim3(bx, nsub), dim3(256), 0, st, g, subs, ft, gin, nrhs, rpad, G,
+  hipLaunchKernelGGL(k_gather_incoming<GT>, dim3(bx, nsub), dim3(256), 0, st, g, subs, ft, gin, nrhs, rpad, G,
                      (const IfCoef*)nullptr);
   return hipGetLastError();
 }
+template hipError_t launch_gather_incoming<double2>(const Geom&, const int32_t*, int, const FaceTab*, const double2*,
+                                                    int, int, double2*, hipStream_t);
+template hipError_t launch_gather_incoming<float2>(const Geom&, const int32_t*, int, const FaceTab*, const double2*,
+                                                   int, int, float2*, hipStream_t);
 
 template <typename C>
 hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int mask, const FaceTab* ft, const C* T,
-                             const double2* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st, int variant) {
+                             const C* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st, int variant) {
   if (nsub == 0) return hipSuccess;
   int rows = 0;
   for (int f = 0; f < 4; ++f)
@@ -288,4 +295,4 @@ hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int m
 template hipError_t launch_scatter_mm<double2>(const Geom&, const int32_t*, int, int, const FaceTab*, const double2*,
                                                const double2*, int, int, const SolveIO&, hipStream_t, int);
 template hipError_t launch_scatter_mm<float2>(const Geom&, const int32_t*, int, int, const FaceTab*, const float2*,
-                                              const double2*, int, int, const SolveIO&, hipStream_t, int);
+                                              const float2*, int, int, const SolveIO&, hipStream_t, int);

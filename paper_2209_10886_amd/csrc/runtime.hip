@@ -600,10 +600,16 @@ int run_dense(hbj_ctx* c, const Entry* ent, const FaceTab* eft, int nent, int ma
     }
     // per subdomain the operator is read once for all right-hand sides
     const double tbytes = elems / nrhs * (c64 ? 8.0 : 16.0);
-    HIPCHK(launch_gather_incoming(c->g, subs, nsub, c->ft, src ? io.g_b : io.g_a, nrhs, rpad, c->Gbuf, c->st));
+    // the complex64 products round every operand to float: their incoming data are gathered in complex64
+    if (c64)
+      HIPCHK(launch_gather_incoming(c->g, subs, nsub, c->ft, src ? io.g_b : io.g_a, nrhs, rpad, (float2*)c->Gbuf,
+                                    c->st));
+    else
+      HIPCHK(launch_gather_incoming(c->g, subs, nsub, c->ft, src ? io.g_b : io.g_a, nrhs, rpad, c->Gbuf, c->st));
     const int slot = (c64 ? 2 : 0) + (mask == 0xF ? 1 : 0);
     auto launch = [&](int v, const SolveIO& lio) -> hipError_t {
-      return c64 ? launch_scatter_mm<float2>(c->g, subs, nsub, mask, c->ft, c->T32, c->Gbuf, nrhs, rpad, lio, c->st, v)
+      return c64 ? launch_scatter_mm<float2>(c->g, subs, nsub, mask, c->ft, c->T32, (const float2*)c->Gbuf, nrhs,
+                                             rpad, lio, c->st, v)
                  : launch_scatter_mm<double2>(c->g, subs, nsub, mask, c->ft, c->T64, c->Gbuf, nrhs, rpad, lio, c->st,
                                               v);
     };
