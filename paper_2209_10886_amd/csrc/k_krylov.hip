@@ -10,6 +10,26 @@ namespace {
 
 constexpr int RT = 256;  // threads per reduction workgroup
 
+// Sum over the 64 lanes of a wavefront with DPP moves only (no LDS traffic): a running sum inside
+// each row of 16 lanes (row_shr 1, 2, 4, 8), then rows 1 and 3 add the last lane of the row before
+// (row_bcast:15) and rows 2 and 3 the last lane of row 1 (row_bcast:31).  Lane 63 ends with the sum.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffll), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+  return v + __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ inline double wave_sum_last(double v) {
+  v = dpp_add<0x111, 0xF>(v);  // row_shr:1
+  v = dpp_add<0x112, 0xF>(v);  // row_shr:2
+  v = dpp_add<0x114, 0xF>(v);  // row_shr:4
+  v = dpp_add<0x118, 0xF>(v);  // row_shr:8
+  v = dpp_add<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  v = dpp_add<0x143, 0xC>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
 __device__ inline double2 shfl_down2(double2 v, int off) {
   v.x = __shfl_down(v.x, off);
   v.y = __shfl_down(v.y, off);
@@ -267,16 +287,15 @@ __global__ __launch_bounds__(RT2) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   }
   vals[2 * VG2] = mk(sxx, sww);
   vals[2 * VG2 + 1] = sxw;
+  // wavefront sums with DPP moves (lane 63 holds them)
 #pragma unroll
   for (int v = 0; v < NS; ++v) {
-    double2 a = vals[v];
-    for (int off = 32; off > 0; off >>= 1) {
-      const double2 o = shfl_down2(a, off);
-      a.x += o.x;
-      a.y += o.y;
-    }
-    if (lane == 0) sh[wid][v] = a;
+    vals[v].x = wave_sum_last(vals[v].x);
+    vals[v].y = wave_sum_last(vals[v].y);
   }
+  if (lane == 63)
+#pragma unroll
+    for (int v = 0; v < NS; ++v) sh[wid][v] = vals[v];
   __syncthreads();
   const int np = 2 * nv + 3;
   double2* pc = partial + (size_t)col * np * nchunk + chunk;
