@@ -369,7 +369,7 @@ __global__ __launch_bounds__(RT) void k_dcgs_update(const double2* V, size_t vst
     cb[i] = i < nv ? sp[nv + i] : mk(0.0, 0.0);
   }
   if (threadIdx.x < 64) {
-    // |a|^2 and a^H b over wavefront 0: strided per-lane sums, then a shuffle tree (fixed order)
+    // |a|^2 and a^H b over wavefront 0: strided per-lane sums, then a DPP sum (fixed order)
     double na = 0.0;
     double2 ab = mk(0.0, 0.0);
     for (int i = threadIdx.x; i < nv; i += 64) {
@@ -377,12 +377,10 @@ __global__ __launch_bounds__(RT) void k_dcgs_update(const double2* V, size_t vst
       na += a.x * a.x + a.y * a.y;
       cfma_conj(ab, a, sp[nv + i]);
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      na += __shfl_down(na, off);
-      ab.x += __shfl_down(ab.x, off);
-      ab.y += __shfl_down(ab.y, off);
-    }
-    if (threadIdx.x == 0) {
+    na = wave_sum_last(na);  // DPP sums: lane 63 holds them
+    ab.x = wave_sum_last(ab.x);
+    ab.y = wave_sum_last(ab.y);
+    if (threadIdx.x == 63) {
       const double xx = sp[2 * nv].x, ww = sp[2 * nv + 2].x;
       const double2 xw = sp[2 * nv + 1];
       const double nu2 = xx - na;
