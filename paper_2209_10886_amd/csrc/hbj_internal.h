@@ -172,6 +172,16 @@ __host__ __device__ inline size_t t_per_sub(const Geom& g) { return (size_t)t_ro
 __host__ __device__ inline size_t t_index(int L, int row, int col) {
   return ((size_t)(row / kTR) * L + col) * kTR + (row % kTR);
 }
+// Tables of a small stepped launch of the dense operators, passed by value: a workgroup then has
+// its entry, face table and row block with its kernel arguments, and its operator loads need no
+// dependent table load first.
+constexpr int kStepArgMax = 16;   // entries
+constexpr int kStepArgRb = 128;   // row blocks (local interface length <= 1024)
+struct StepArgs {
+  Entry e[kStepArgMax];
+  FaceTab f[kStepArgMax];  // face table of entry i's subdomain
+  int32_t rb[kStepArgRb];  // the launch's row blocks
+};
 __host__ __device__ inline int pick4(const int32_t (&a)[4], int f) {
   return f == 0 ? a[0] : f == 1 ? a[1] : f == 2 ? a[2] : a[3];
 }
@@ -300,7 +310,7 @@ hipError_t launch_build_T(const Geom& g, const Entry* ent, int nent, const FaceT
 template <typename C>
 hipError_t launch_scatter_apply(const Geom& g, const Entry* ent, int nent, int mask, const int32_t* rblist, int nrb,
                                 const FaceTab* eft, const C* T, const SolveIO& io, hipStream_t st,
-                                hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr);
+                                hipEvent_t t0 = nullptr, hipEvent_t t1 = nullptr, const StepArgs* sa = nullptr);
 // dataflow sweep launch: ctr = [ticket, counters...] (zero at entry), ctr_next is zeroed for the
 // next launch; err receives 1 if a dependency wait exceeded spin_limit polls; the waits of
 // task stall_task (-1: none) need one completion more than exists (error-path tests)

@@ -10,6 +10,8 @@
 // spread over many workgroups, instead of one workgroup walking the whole band.
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "hbj_internal.h"
 
 namespace {
@@ -57,14 +59,27 @@ constexpr int LMAX = 1024;   // local interface length limit (sub_nx, sub_ny <= 
 // ALIGNED: every face starts at a multiple of CG, so the CG columns of load k (grp + CG k over the
 // workgroup) lie on one face; whether they are needed is then the same in every lane and is
 // decided on the scalar unit (loads of faces without data read the block's first columns again).
-template <typename C, int KMAX, bool ALIGNED>
+// KARG: the entry, face table and row block come from the by-value tables sa (small launches),
+// read with the kernel arguments, so the operator and data loads follow without another round.
+struct NoStepArgs {};
+template <typename C, int KMAX, bool ALIGNED, bool KARG>
 __global__ __launch_bounds__(kTR * CG) void k_scatter_apply(Geom g, const Entry* ent, const int32_t* rblist,
-                                                            const FaceTab* eft, const C* __restrict__ T, SolveIO io) {
+                                                            const FaceTab* eft, const C* __restrict__ T, SolveIO io,
+                                                            std::conditional_t<KARG, StepArgs, NoStepArgs> sa) {
   constexpr int NT = kTR * CG;
   constexpr int GLP = LMAX / NT;  // incoming data per thread
-  const Entry e = ent[blockIdx.y];
-  const FaceTab F = eft[blockIdx.y];
-  const int rb = rblist[blockIdx.x];
+  Entry e;
+  FaceTab F;
+  int rb;
+  if constexpr (KARG) {
+    e = sa.e[blockIdx.y];
+    F = sa.f[blockIdx.y];
+    rb = sa.rb[blockIdx.x];
+  } else {
+    e = ent[blockIdx.y];
+    F = eft[blockIdx.y];
+    rb = rblist[blockIdx.x];
+  }
   // every table value and kernel argument the workgroup needs is taken into registers here, before
   // the idle-block test below: their scalar loads then go out together instead of one round after
   // the other (the empty statements only name the registers)
@@ -212,33 +227,39 @@ hipError_t launch_build_T(const Geom& g, const Entry* ent, int nent, const FaceT
 template <typename C>
 hipError_t launch_scatter_apply(const Geom& g, const Entry* ent, int nent, int mask, const int32_t* rblist, int nrb,
                                 const FaceTab* eft, const C* T, const SolveIO& io, hipStream_t st, hipEvent_t t0,
-                                hipEvent_t t1) {
+                                hipEvent_t t1, const StepArgs* sa) {
   (void)mask;  // carried by every entry
   if (nent == 0 || nrb == 0) return hipSuccess;
   const int L = local_if_len(g);
   if (L > LMAX) return hipErrorInvalidValue;
+  if (sa && (nent > kStepArgMax || nrb > kStepArgRb)) return hipErrorInvalidValue;
   const dim3 grid(nrb, nent);
   const bool aligned = g.snx % CG == 0 && g.sny % CG == 0;
-  auto go = [&](auto kern) {
+  auto go = [&](auto kern, auto tab) {
     // with events, the start and stop times are those of the dispatch itself
     if (t0 || t1)
-      hipExtLaunchKernelGGL(kern, grid, dim3(kTR * CG), 0, st, t0, t1, 0, g, ent, rblist, eft, T, io);
+      hipExtLaunchKernelGGL(kern, grid, dim3(kTR * CG), 0, st, t0, t1, 0, g, ent, rblist, eft, T, io, tab);
     else
-      hipLaunchKernelGGL(kern, grid, dim3(kTR * CG), 0, st, g, ent, rblist, eft, T, io);
+      hipLaunchKernelGGL(kern, grid, dim3(kTR * CG), 0, st, g, ent, rblist, eft, T, io, tab);
   };
-  if (L <= 16 * CG) {
-    if (aligned) go(k_scatter_apply<C, 16, true>);
-    else go(k_scatter_apply<C, 16, false>);
-  } else {
-    if (aligned) go(k_scatter_apply<C, LMAX / CG, true>);
-    else go(k_scatter_apply<C, LMAX / CG, false>);
-  }
+  auto pick = [&](auto km) {
+    constexpr int K = decltype(km)::value;
+    if (sa) {
+      if (aligned) go(k_scatter_apply<C, K, true, true>, *sa);
+      else go(k_scatter_apply<C, K, false, true>, *sa);
+    } else {
+      if (aligned) go(k_scatter_apply<C, K, true, false>, NoStepArgs{});
+      else go(k_scatter_apply<C, K, false, false>, NoStepArgs{});
+    }
+  };
+  if (L <= 16 * CG) pick(std::integral_constant<int, 16>{});
+  else pick(std::integral_constant<int, LMAX / CG>{});
   return hipGetLastError();
 }
 
 template hipError_t launch_scatter_apply<double2>(const Geom&, const Entry*, int, int, const int32_t*, int,
                                                   const FaceTab*, const double2*, const SolveIO&, hipStream_t,
-                                                  hipEvent_t, hipEvent_t);
+                                                  hipEvent_t, hipEvent_t, const StepArgs*);
 template hipError_t launch_scatter_apply<float2>(const Geom&, const Entry*, int, int, const int32_t*, int,
                                                  const FaceTab*, const float2*, const SolveIO&, hipStream_t, hipEvent_t,
-                                                 hipEvent_t);
+                                                 hipEvent_t, const StepArgs*);

@@ -52,6 +52,7 @@ struct Step {
   int sub_count = 0;
   size_t tile_first = 0;   // offset into the schedule's tile list (banded solves on MFMA)
   int tile_count = 0;
+  int sarg = -1;           // the step's tables by value (dense operators), index into Schedule::sargs
 };
 
 // All launches for a given number of right-hand sides.
@@ -69,6 +70,7 @@ struct Schedule {
   size_t all_tile_first = 0;
   int all_tile_count = 0;
   std::vector<Step> fwd, bwd;  // preconditioner passes
+  std::vector<StepArgs> sargs;
   // dataflow launches (dense form): task lists per kind, double-buffered completion counters
   struct DfPlan {
     bool built = false;
@@ -141,6 +143,7 @@ struct hbj_ctx {
   float2* T32 = nullptr;
   int32_t* rbl = nullptr;  // stepped launches: row blocks of the forward, backward and full masks
   int rbl_off[3] = {0, 0, 0}, rbl_n[3] = {0, 0, 0};
+  std::vector<int32_t> rbl_host;
   int32_t* df_err = nullptr;  // dataflow dependency-wait error flag
   int df_grid = 0;            // persistent workgroups per dataflow launch
   int df_spin = kDfSpinDefault;
@@ -407,6 +410,23 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
       append_tiles(ent, st.first, st.count, tiles);
       st.tile_count = (int)(tiles.size() - st.tile_first);
     }
+  // small sweep steps of the dense operators take their tables by value (li: row-block list)
+  auto by_value = [&](Step& st, int li) {
+    const int nrb = c->rbl_n[li];
+    if (st.count == 0 || st.count > kStepArgMax || nrb > kStepArgRb) return;
+    StepArgs a{};
+    for (int q = 0; q < st.count; ++q) {
+      a.e[q] = ent[st.first + q];
+      a.f[q] = eft[st.first + q];
+    }
+    for (int q = 0; q < nrb; ++q) a.rb[q] = c->rbl_host[c->rbl_off[li] + q];
+    st.sarg = (int)S->sargs.size();
+    S->sargs.push_back(a);
+  };
+  if (!c->rbl_host.empty()) {
+    for (Step& st : S->fwd) by_value(st, 0);
+    for (Step& st : S->bwd) by_value(st, 1);
+  }
   HIPCHK(dalloc(&S->tiles, tiles.size()));
   HIPCHK(hipMemcpyAsync(S->tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
@@ -586,7 +606,7 @@ constexpr int kMatrixRhs = 4;  // from this many right-hand sides on, the operat
 
 int run_dense(hbj_ctx* c, const Entry* ent, const FaceTab* eft, int nent, int mask, const SolveIO& io, bool c64,
               double elems,
-              const int32_t* subs = nullptr, int nsub = 0, int nrhs = 1, int src = 0) {
+              const int32_t* subs = nullptr, int nsub = 0, int nrhs = 1, int src = 0, const StepArgs* sa = nullptr) {
   if (nent == 0) return HBJ_OK;
   if (subs && nrhs >= kMatrixRhs) {
     const int rpad = (nrhs + 15) / 16 * 16;
@@ -651,9 +671,9 @@ int run_dense(hbj_ctx* c, const Entry* ent, const FaceTab* eft, int nent, int ma
   // profiling: the dispatch's own start and stop times (no event packets around the launch)
   hipEvent_t t0 = c->prof ? c->ev0 : nullptr, t1 = c->prof ? c->ev1 : nullptr;
   if (c64)
-    HIPCHK(launch_scatter_apply<float2>(c->g, ent, nent, mask, rbl, c->rbl_n[li], eft, c->T32, io, c->st, t0, t1));
+    HIPCHK(launch_scatter_apply<float2>(c->g, ent, nent, mask, rbl, c->rbl_n[li], eft, c->T32, io, c->st, t0, t1, sa));
   else
-    HIPCHK(launch_scatter_apply<double2>(c->g, ent, nent, mask, rbl, c->rbl_n[li], eft, c->T64, io, c->st, t0, t1));
+    HIPCHK(launch_scatter_apply<double2>(c->g, ent, nent, mask, rbl, c->rbl_n[li], eft, c->T64, io, c->st, t0, t1, sa));
   if (c->prof) {
     HIPCHK(hipEventSynchronize(c->ev1));
     float ms = 0.f;
@@ -1067,7 +1087,8 @@ int run_pass(hbj_ctx* c, const Schedule* S, const std::vector<Step>& steps, cons
     io.tr_sign = 1.0;
     io.tr_reflect = 1;
     int rc = c->dense ? run_dense(c, dev + s.first, S->eft + s.first, s.count, mask, io, sizeof(R) == 4, s.dense_elems,
-                                  S->subs + s.sub_first, s.sub_count, S->nrhs, si == 0 ? 0 : 1)
+                                  S->subs + s.sub_first, s.sub_count, S->nrhs, si == 0 ? 0 : 1,
+                                  s.sarg >= 0 ? &S->sargs[s.sarg] : nullptr)
                       : run_solves<R>(c, dev + s.first, s.count, io, S->tiles + s.tile_first, s.tile_count);
     if (rc) return rc;
   }
@@ -1845,6 +1866,7 @@ int hbj_setup(const hbj_problem* prob, const double* c_dev, void* stream, hbj_ct
       }
       c->rbl_n[i] = (int)rbl.size() - c->rbl_off[i];
     }
+    c->rbl_host = rbl;
     if (dalloc(&c->rbl, rbl.size()) || dalloc(&c->df_err, 1)) return fail(HBJ_ENOMEM, "setup allocation failed");
     HIPCHK(hipMemcpyAsync(c->rbl, rbl.data(), rbl.size() * 4, hipMemcpyHostToDevice, c->st));
     HIPCHK(launch_fill_zero(c->df_err, sizeof(int32_t), c->st));

@@ -6,7 +6,8 @@
         per kernel: dispatches and the mean of every collected counter per dispatch
     python -m paper_2209_10886_amd.profsum traffic --fetch DIR --write DIR --calib-fetch DIR --calib-write DIR
                                            --kernel SUBSTRING --name NAME --source FILE [--out JSON]
-        HBM bytes per launch of one kernel: FETCH_SIZE and WRITE_SIZE (KiB per dispatch, two separate
+        HBM bytes per launch of one kernel (pooled over every instantiation whose name contains
+        SUBSTRING): FETCH_SIZE and WRITE_SIZE (KiB per dispatch, two separate
         counter runs) scaled by what the same counters read for the plain 1 GiB copy of the streaming
         probe (1 GiB read + 1 GiB written); the entry is keyed by NAME and stamped with the hash of FILE
         so that a later change of the kernel's source invalidates it.
@@ -113,9 +114,19 @@ def _pick(means, sub, counter):
     return hits[0][1][counter], hits[0][1]["_dispatches"]
 
 
+def _pool(means, sub, counter):
+    """Dispatch-weighted mean of a counter over every kernel whose name contains sub (the
+    instantiations of one kernel template)."""
+    hits = [v for k, v in means.items() if sub in k and counter in v]
+    if not hits:
+        raise SystemExit(f"kernel '{sub}' with {counter}: no match")
+    n = sum(v["_dispatches"] for v in hits)
+    return sum(v[counter] * v["_dispatches"] for v in hits) / n, n
+
+
 def traffic(a):
-    fetch, nd = _pick(counter_means(a.fetch), a.kernel, "FETCH_SIZE")
-    write, _ = _pick(counter_means(a.write), a.kernel, "WRITE_SIZE")
+    fetch, nd = _pool(counter_means(a.fetch), a.kernel, "FETCH_SIZE")
+    write, _ = _pool(counter_means(a.write), a.kernel, "WRITE_SIZE")
     cf, _ = _pick(counter_means(a.calib_fetch), "k_plain_copy", "FETCH_SIZE")
     cw, _ = _pick(counter_means(a.calib_write), "k_plain_copy", "WRITE_SIZE")
     # bytes per KiB of counter reading, from the copy of known size
