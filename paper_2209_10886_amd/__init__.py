@@ -88,6 +88,7 @@ _SIGS = {
     "hbj_reset_kernel_stats": (_I, [_P]),
     "hbj_set_sweep_wait": (_I, [_P, _I32, _I32]),
     "hbj_get_tuning": (_I, [_P, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)]),
+    "hbj_set_tuning": (_I, [_P, ctypes.POINTER(_I32)]),
     "hbj_set_graphs": (_I, [_P, _I32]),
     "hbj_set_orthogonalization": (_I, [_P, _I32]),
     "hbj_set_multi_solve": (_I, [_P, _I32]),
@@ -299,15 +300,26 @@ class Context:
         _check(_lib.hbj_set_multi_solve(self._h, int(mode)))
 
     def tuning(self):
-        """Autotuned tile depths of the many-RHS operator kernel and their measured us per launch."""
+        """Autotuned variants of the many-RHS operator kernel (tile depth, and whether the incoming
+        data are gathered into tiles first or read from the interface vector) with the measured us
+        per launch of every variant."""
+        nv = 6
         v = (_I32 * 4)()
-        us = (ctypes.c_float * 12)()
+        us = (ctypes.c_float * (4 * nv))()
         _check(_lib.hbj_get_tuning(self._h, v, us))
         kinds = ("c128 steps", "c128 operator", "c64 steps", "c64 operator")
         depths = (2, 4, 8)
-        return {k: {"k_steps_per_batch": depths[v[i]] if v[i] >= 0 else None,
-                    "us": {d: round(us[i * 3 + j], 2) for j, d in enumerate(depths)} if v[i] >= 0 else None}
+        label = [f"{'gathered' if j < 3 else 'direct'}/{depths[j % 3]}" for j in range(nv)]
+        return {k: {"k_steps_per_batch": depths[v[i] % 3] if v[i] >= 0 else None,
+                    "incoming": ("gathered" if v[i] < 3 else "direct") if v[i] >= 0 else None,
+                    "us": {label[j]: round(us[i * nv + j], 2) for j in range(nv)} if v[i] >= 0 else None}
                 for i, k in enumerate(kinds)}
+
+    def set_tuning(self, variants):
+        """Fix the many-RHS operator kernel's variant per kind (c128 steps, c128 operator, c64 steps,
+        c64 operator): 0-5, or -1 to let the autotuner choose."""
+        v = (_I32 * 4)(*[int(x) for x in variants])
+        _check(_lib.hbj_set_tuning(self._h, v))
 
     def set_sweep_wait(self, max_polls=0, stall_task=-1):
         """Bounds of the dataflow sweeps' dependency waits (error-path tests)."""

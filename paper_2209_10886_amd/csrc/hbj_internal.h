@@ -337,15 +337,17 @@ hipError_t launch_recon_dense(const Geom& g, const FaceTab* ft, const IfCoef* co
                               const double2* gin, const int32_t* nz, int nrhs, double2* u, hipStream_t st);
 
 // many right-hand sides: gather the incoming data G[j][col][r] of subdomains subs[j] (in the element
-// type of the operators), then OUT = T_s[masked rows, :] G_s on MFMA (complex128 operators on f64
-// MFMA, complex64 on f32)
+// type GT); OUT = T_s[masked rows, :] G_s on MFMA (complex128 operators on f64 MFMA, complex64 on
+// f32), with G_s from the gathered tiles G (variants 0-2: k-steps per batch 2, 4, 8) or straight
+// from the interface vector gin [nrhs][nif] (variants 3-5)
 template <typename GT>
 hipError_t launch_gather_incoming(const Geom& g, const int32_t* subs, int nsub, const FaceTab* ft, const double2* gin,
                                   int nrhs, int rpad, GT* G, hipStream_t st);
 template <typename C>
 hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int mask, const FaceTab* ft, const C* T,
-                             const C* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st, int variant);
-constexpr int kMmVariants = 3;  // k-steps per batch of loads: 2, 4, 8
+                             const double2* gin, const C* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st,
+                             int variant);
+constexpr int kMmVariants = 6;  // k-steps per batch of loads 2, 4, 8; gathered (0-2) or direct (3-5)
 
 // gradient / misc
 hipError_t launch_gather_receivers(const double2* u, const int32_t* rec, int nrec, int npts, const double2* d,

@@ -7,6 +7,8 @@
 //   A[i][k] at lane i + 16 k, B[k][j] at lane j + 16 k;
 //   f64: D[i][j] in lane j + 16 (i % 4), register i / 4;
 //   f32: D[i][j] in lane j + 16 (i / 4), register i % 4.
+#include <type_traits>
+
 #include "hbj_internal.h"
 
 namespace {
@@ -69,11 +71,17 @@ constexpr int KW = 4;  // wavefronts splitting the k range of one tile
 // workgroup; wavefront w takes every KW-th group of 4 columns of each existing face, and the four
 // partial tiles are summed in LDS.  Each wavefront issues the loads of KB k-steps (column indices
 // clamped into the face, out-of-range steps zeroed after the load) before their MFMAs, which go to
-// eight independent accumulators; KB is the tile depth chosen by the autotuner.
-template <typename C, typename M, int KB>
+// eight independent accumulators.  The B operands (lane (j, k) of a k-step: right-hand side j at
+// the step's position k) come either from the gathered tiles G ([nsub][L][rpad], element type C:
+// right-hand sides contiguous) or, DIRECT, straight from the interface vector gin ([R][nif],
+// complex128: positions contiguous), where the products on f32 MFMA round them to float at use.
+// KB and the source of B are chosen by the autotuner.
+template <typename C, typename M, int KB, bool DIRECT>
 __global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_scatter_mm(Geom g, const int32_t* subs, int mask, const FaceTab* ft,
-                                                        const C* __restrict__ T, const C* __restrict__ G,
+                                                        const C* __restrict__ T,
+                                                        const std::conditional_t<DIRECT, double2, C>* __restrict__ B,
                                                         int nrhs, int rpad, SolveIO io) {
+  typedef std::conditional_t<DIRECT, double2, C> BT;
   typedef MfmaAcc<M> A;
   typedef typename A::T V4;
   const int j = blockIdx.y;
@@ -86,12 +94,15 @@ __global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2)))
   const M amask = mrow >= 0 ? (M)1 : (M)0;
   const int rb0 = blockIdx.z * 16 * TB;
   const C* Ts = T + (size_t)s * t_per_sub(g) + t_index(L, mrow < 0 ? 0 : mrow, 0);
-  // right-hand-side columns of this lane's B operands, clamped into the padded width (with fewer
-  // than 64 right-hand sides the upper blocks of the tile do not exist; their results are dropped)
-  const C* Gs = G + (size_t)j * L * rpad;
-  int jr[TB];
+  // right-hand sides of this lane's B operands, clamped to the last one (columns past nrhs only
+  // feed output columns that are dropped); B element (rhs, col) at bface[jr + col * cs]
+  const long cs = DIRECT ? 1 : rpad;
+  long jr[TB];
 #pragma unroll
-  for (int t = 0; t < TB; ++t) jr[t] = min(rb0 + 16 * t + i, rpad - 1);
+  for (int t = 0; t < TB; ++t) {
+    const long r = min(rb0 + 16 * t + i, nrhs - 1);
+    jr[t] = DIRECT ? r * g.nif : (long)j * L * rpad + r;
+  }
   V4 cr[TB], ci[TB];
 #pragma unroll
   for (int t = 0; t < TB; ++t) {
@@ -103,17 +114,18 @@ __global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2)))
   for (int f = 0; f < 4; ++f) {
     if (!present[f]) continue;
     const int c0 = face_off(g, f), c1 = c0 + face_len(g, f);
+    const long fo = DIRECT ? (long)pick4(F.in_off, f) - c0 : 0;  // gin[rhs * nif + fo + col]
     // this wavefront's k-steps: c0 + 4 (w + KW q), KB of them per batch
     for (int c = c0 + 4 * w; c < c1; c += 4 * KW * KB) {
       C tv[KB];
-      C gv[KB][TB];
+      BT gv[KB][TB];
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
         const int col = c + 4 * KW * b + k;
         const int cc = col < c1 ? col : c1 - 1;
         tv[b] = Ts[(size_t)cc * kTR];
 #pragma unroll
-        for (int t = 0; t < TB; ++t) gv[b][t] = Gs[(size_t)cc * rpad + jr[t]];
+        for (int t = 0; t < TB; ++t) gv[b][t] = B[jr[t] + fo + (long)cc * cs];
       }
       __builtin_amdgcn_sched_barrier(0);  // keep the whole batch of loads ahead of the MFMAs
 #pragma unroll
@@ -269,30 +281,33 @@ template hipError_t launch_gather_incoming<float2>(const Geom&, const int32_t*, 
 
 template <typename C>
 hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int mask, const FaceTab* ft, const C* T,
-                             const C* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st, int variant) {
-  if (nsub == 0) return hipSuccess;
+                             const double2* gin, const C* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st,
+                             int variant) {
+  if (nsub == 0 || nrhs < 1) return hipSuccess;
   int rows = 0;
   for (int f = 0; f < 4; ++f)
     if ((mask >> f) & 1) rows += face_len(g, f);
   static_assert(KW == TB, "one right-hand-side block per wavefront in the epilogue");
   const dim3 grid((rows + 15) / 16, nsub, (nrhs + 16 * TB - 1) / (16 * TB));
   typedef typename std::conditional<sizeof(C) == 16, double, float>::type M;
+  auto go = [&](auto kern, auto src) {
+    hipLaunchKernelGGL(kern, grid, dim3(64 * KW), 0, st, g, subs, mask, ft, T, src, nrhs, rpad, io);
+  };
   switch (variant) {
-    case 0:
-      hipLaunchKernelGGL((k_scatter_mm<C, M, 2>), grid, dim3(64 * KW), 0, st, g, subs, mask, ft, T, G, nrhs, rpad, io);
-      break;
-    case 1:
-      hipLaunchKernelGGL((k_scatter_mm<C, M, 4>), grid, dim3(64 * KW), 0, st, g, subs, mask, ft, T, G, nrhs, rpad, io);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_scatter_mm<C, M, 8>), grid, dim3(64 * KW), 0, st, g, subs, mask, ft, T, G, nrhs, rpad, io);
-      break;
+    case 0: go(k_scatter_mm<C, M, 2, false>, G); break;
+    case 1: go(k_scatter_mm<C, M, 4, false>, G); break;
+    case 2: go(k_scatter_mm<C, M, 8, false>, G); break;
+    case 3: go(k_scatter_mm<C, M, 2, true>, gin); break;
+    case 4: go(k_scatter_mm<C, M, 4, true>, gin); break;
+    case 5: go(k_scatter_mm<C, M, 8, true>, gin); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template hipError_t launch_scatter_mm<double2>(const Geom&, const int32_t*, int, int, const FaceTab*, const double2*,
-                                               const double2*, int, int, const SolveIO&, hipStream_t, int);
+                                               const double2*, const double2*, int, int, const SolveIO&, hipStream_t,
+                                               int);
 template hipError_t launch_scatter_mm<float2>(const Geom&, const int32_t*, int, int, const FaceTab*, const float2*,
-                                              const float2*, int, int, const SolveIO&, hipStream_t, int);
+                                              const double2*, const float2*, int, int, const SolveIO&, hipStream_t,
+                                              int);

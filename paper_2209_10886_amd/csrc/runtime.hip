@@ -620,21 +620,27 @@ int run_dense(hbj_ctx* c, const Entry* ent, const FaceTab* eft, int nent, int ma
     }
     // per subdomain the operator is read once for all right-hand sides
     const double tbytes = elems / nrhs * (c64 ? 8.0 : 16.0);
-    // the complex64 products round every operand to float: their incoming data are gathered in complex64
-    if (c64)
-      HIPCHK(launch_gather_incoming(c->g, subs, nsub, c->ft, src ? io.g_b : io.g_a, nrhs, rpad, (float2*)c->Gbuf,
-                                    c->st));
-    else
-      HIPCHK(launch_gather_incoming(c->g, subs, nsub, c->ft, src ? io.g_b : io.g_a, nrhs, rpad, c->Gbuf, c->st));
+    const double2* gin = src ? io.g_b : io.g_a;
     const int slot = (c64 ? 2 : 0) + (mask == 0xF ? 1 : 0);
+    // variants 0-2 gather the incoming data into tiles first (in complex64 for the complex64
+    // products, which round every operand to float anyway); 3-5 read them from gin directly
     auto launch = [&](int v, const SolveIO& lio) -> hipError_t {
-      return c64 ? launch_scatter_mm<float2>(c->g, subs, nsub, mask, c->ft, c->T32, (const float2*)c->Gbuf, nrhs,
-                                             rpad, lio, c->st, v)
-                 : launch_scatter_mm<double2>(c->g, subs, nsub, mask, c->ft, c->T64, c->Gbuf, nrhs, rpad, lio, c->st,
-                                              v);
+      if (v < 3) {
+        const hipError_t e =
+            c64 ? launch_gather_incoming(c->g, subs, nsub, c->ft, gin, nrhs, rpad, (float2*)c->Gbuf, c->st)
+                : launch_gather_incoming(c->g, subs, nsub, c->ft, gin, nrhs, rpad, c->Gbuf, c->st);
+        if (e != hipSuccess) return e;
+      }
+      return c64 ? launch_scatter_mm<float2>(c->g, subs, nsub, mask, c->ft, c->T32, gin, (const float2*)c->Gbuf,
+                                             nrhs, rpad, lio, c->st, v)
+                 : launch_scatter_mm<double2>(c->g, subs, nsub, mask, c->ft, c->T64, gin, c->Gbuf, nrhs, rpad, lio,
+                                              c->st, v);
     };
     if (c->mm_variant[slot] < 0) {
-      // autotuner: time every tile depth on this very launch, writing into scratch, keep the fastest
+      // autotuner: time every variant on this very launch, writing into scratch, keep the fastest
+      // (after the device is idle: the source part of a reconstruction may still run on the second
+      // stream, and the variants timed beside it would look slower)
+      HIPCHK(hipDeviceSynchronize());
       double2* scratch = nullptr;
       if (dalloc(&scratch, (size_t)nrhs * c->g.nif)) return fail(HBJ_ENOMEM, "tuning workspace allocation failed");
       SolveIO tio = io;
@@ -2333,6 +2339,17 @@ int hbj_get_tuning(const hbj_ctx* c, int32_t* variants, float* us) {
     variants[i] = c->mm_variant[i];
     if (us)
       for (int v = 0; v < kMmVariants; ++v) us[i * kMmVariants + v] = c->mm_us[i][v];
+  }
+  return HBJ_OK;
+}
+
+int hbj_set_tuning(hbj_ctx* c, const int32_t* variants) {
+  if (!c || !variants) return fail(HBJ_EINVAL, "bad arguments");
+  for (int i = 0; i < 4; ++i)
+    if (variants[i] < -1 || variants[i] >= kMmVariants) return fail(HBJ_EINVAL, "tuning variant out of range");
+  for (int i = 0; i < 4; ++i) {
+    c->mm_variant[i] = variants[i];
+    for (int v = 0; v < kMmVariants; ++v) c->mm_us[i][v] = 0.f;
   }
   return HBJ_OK;
 }

@@ -282,6 +282,41 @@ def test_dense_operators_many_rhs(ctxs, name, kw):
     assert all(v > 0 for v in tun[used]["us"].values())
 
 
+@pytest.mark.parametrize("variant,nr", [(v, 20) for v in range(6)] + [(1, 70), (4, 70)])
+@pytest.mark.parametrize("kw", [{}, dict(precision=1)])
+def test_operator_kernel_variants(ctxs, kw, variant, nr):
+    """Every variant of the many-RHS operator kernel (tile depth 2/4/8, incoming data gathered into
+    tiles or read from the interface vector), forced, against the oracle; 70 columns span two
+    64-column tiles."""
+    from oracle import sweep
+
+    wl, m, g, dd, ctx = ctxs("ragged", operator_form=1, **kw)
+    gv = W.random_interface_vector(ctx.nif, seed=11, nrhs=nr)
+    say(f"[operator kernel variant] {variant} nrhs={nr} {kw}")
+    ctx.set_tuning([variant] * 4)
+    try:
+        w = _to_np(ctx.apply_operator(torch.as_tensor(gv, device="cuda")))
+        z = _to_np(ctx.apply_preconditioner(torch.as_tensor(gv, device="cuda")))
+        tun = ctx.tuning()
+    finally:
+        ctx.set_tuning([-1] * 4)
+    tol_pc = 1e-11 if not kw else 1e-5
+    for k in range(nr):
+        assert rel(w[k], dd.apply_operator(gv[k])) < 1e-12
+        assert rel(z[k], sweep.apply_bj(dd, gv[k])) < tol_pc
+    used = ("c64" if kw else "c128") + " steps"
+    assert tun[used]["k_steps_per_batch"] == (2, 4, 8)[variant % 3]
+    assert tun[used]["incoming"] == ("gathered" if variant < 3 else "direct")
+
+
+def test_set_tuning_rejects_bad_variants(hbj, ctxs):
+    wl, m, g, dd, ctx = ctxs("ragged", operator_form=1)
+    with pytest.raises(hbj.HbjError):
+        ctx.set_tuning([0, 0, 6, 0])
+    with pytest.raises(hbj.HbjError):
+        ctx.set_tuning([-2, 0, 0, 0])
+
+
 def test_dense_solve_many_rhs(ctxs):
     from oracle import solver
 
