@@ -646,22 +646,25 @@ int run_dense(hbj_ctx* c, const Entry* ent, const FaceTab* eft, int nent, int ma
       SolveIO tio = io;
       tio.tr_dst = scratch;
       tio.tr_base = nullptr;
-      int best = 0;
-      float best_ms = 1e30f;
+      // the variants take turns (three rounds after a warm-up round), so that each one is timed after
+      // another has streamed its data, as in a solve, rather than on caches it has just filled itself
       hipError_t he = hipSuccess;
-      for (int v = 0; v < kMmVariants && he == hipSuccess; ++v) {
-        he = launch(v, tio);  // warm-up
-        if (he == hipSuccess) he = hipEventRecord(c->ev0, c->st);
-        for (int rep = 0; rep < 3 && he == hipSuccess; ++rep) he = launch(v, tio);
-        if (he == hipSuccess) he = hipEventRecord(c->ev1, c->st);
-        if (he == hipSuccess) he = hipEventSynchronize(c->ev1);
-        float ms = 0.f;
-        if (he == hipSuccess) he = hipEventElapsedTime(&ms, c->ev0, c->ev1);
-        c->mm_us[slot][v] = ms / 3.0f * 1e3f;
-        if (he == hipSuccess && ms < best_ms) {
-          best_ms = ms;
-          best = v;
+      float tot[kMmVariants] = {};
+      for (int v = 0; v < kMmVariants && he == hipSuccess; ++v) he = launch(v, tio);
+      for (int rep = 0; rep < 3 && he == hipSuccess; ++rep)
+        for (int v = 0; v < kMmVariants && he == hipSuccess; ++v) {
+          he = hipEventRecord(c->ev0, c->st);
+          if (he == hipSuccess) he = launch(v, tio);
+          if (he == hipSuccess) he = hipEventRecord(c->ev1, c->st);
+          if (he == hipSuccess) he = hipEventSynchronize(c->ev1);
+          float ms = 0.f;
+          if (he == hipSuccess) he = hipEventElapsedTime(&ms, c->ev0, c->ev1);
+          tot[v] += ms;
         }
+      int best = 0;
+      for (int v = 0; v < kMmVariants; ++v) {
+        c->mm_us[slot][v] = tot[v] / 3.0f * 1e3f;
+        if (tot[v] < tot[best]) best = v;
       }
       (void)hipStreamSynchronize(c->st);
       dfree(scratch);
