@@ -327,16 +327,25 @@ __global__ __launch_bounds__(576) void k_bwd(Geom g, SolveLayout L, const Entry*
   }
 }
 
-// nz[rhs][s] = 1 if the source restricted to subdomain s is not identically zero
-__global__ void k_source_flags(Geom g, const double2* f, int32_t* nz) {
+// nz[rhs][s] = 1 if the source restricted to subdomain s is not identically zero.  Each thread
+// issues the loads of kFlagU positions (clamped into the subdomain: a repeated position does not
+// change the result) before it tests any, so a 128^2 subdomain costs one round of loads.
+constexpr int kFlagThreads = 1024, kFlagU = 16;
+__global__ __launch_bounds__(kFlagThreads) void k_source_flags(Geom g, const double2* f, int32_t* nz) {
   const int s = blockIdx.x, rhs = blockIdx.y;
   const int x0 = (s % g.n1) * g.snx, y0 = (s / g.n1) * g.sny;
   const double2* fr = f + (size_t)rhs * g.nx * g.ny;
   int any = 0;
-  for (int l = threadIdx.x; l < g.nloc && !any; l += blockDim.x) {
-    const int ly = l / g.snx, lx = l - ly * g.snx;
-    const double2 v = fr[(size_t)(y0 + ly) * g.nx + x0 + lx];
-    any = (v.x != 0.0 || v.y != 0.0);
+  for (int l0 = 0; l0 < g.nloc; l0 += kFlagU * kFlagThreads) {
+    double2 v[kFlagU];
+#pragma unroll
+    for (int u = 0; u < kFlagU; ++u) {
+      const int l = min(l0 + (int)threadIdx.x + u * kFlagThreads, g.nloc - 1);
+      const int ly = l / g.snx, lx = l - ly * g.snx;
+      v[u] = fr[(size_t)(y0 + ly) * g.nx + x0 + lx];
+    }
+#pragma unroll
+    for (int u = 0; u < kFlagU; ++u) any |= (v[u].x != 0.0) | (v[u].y != 0.0);
   }
   any = __syncthreads_or(any);
   if (threadIdx.x == 0) nz[(size_t)rhs * g.n1 * g.n2 + s] = any;
@@ -989,6 +998,6 @@ hipError_t launch_axpy_c64(double2* x64, const float2* dx, const Geom& g, const 
 }
 
 hipError_t launch_source_flags(const Geom& g, const double2* f, int nrhs, int32_t* nz, hipStream_t st) {
-  hipLaunchKernelGGL(k_source_flags, dim3(g.n1 * g.n2, nrhs), dim3(256), 0, st, g, f, nz);
+  hipLaunchKernelGGL(k_source_flags, dim3(g.n1 * g.n2, nrhs), dim3(kFlagThreads), 0, st, g, f, nz);
   return hipGetLastError();
 }
