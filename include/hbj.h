@@ -334,20 +334,21 @@ int hbj_set_multi_solve(hbj_ctx* ctx, int32_t mode);
  * kind the library times every variant on that launch's own data, writing into
  * scratch, and keeps the fastest.  Variant v: tile depth (k-steps per batch of
  * loads) 2, 4, 8 for v % 3 = 0, 1, 2; incoming data gathered into tiles by a
- * separate launch first (v < 3, its time included) or read straight from the
- * interface vector (v >= 3).
+ * separate launch first ((v % 6) < 3, its time included) or read straight from
+ * the interface vector ((v % 6) >= 3); the 64 right-hand sides of a tile taken by
+ * one group of four wavefronts (v < 6) or split over two groups (v >= 6).
  *   variants  HOST [4]: complex128 sweep steps, complex128 operator, complex64
  *             sweep steps, complex64 operator; -1 = not tuned yet.
- *   us        HOST [4][6] or NULL: the measured microseconds per launch.
+ *   us        HOST [4][12] or NULL: the measured microseconds per launch.
  */
 int hbj_get_tuning(const hbj_ctx* ctx, int32_t* variants, float* us);
 
 /*
  * hbj_set_tuning - fix the variants of the many-right-hand-side operator kernel
  * instead of timing them (reproducible timings, tests of every variant).
- *   variants  HOST [4], same order as hbj_get_tuning; each in 0..5, or -1 to let
+ *   variants  HOST [4], same order as hbj_get_tuning; each in 0..11, or -1 to let
  *             the autotuner choose on the next launch of that kind.
- * Returns HBJ_EINVAL for a value outside -1..5 (nothing is changed then).
+ * Returns HBJ_EINVAL for a value outside -1..11 (nothing is changed then).
  */
 int hbj_set_tuning(hbj_ctx* ctx, const int32_t* variants);
 

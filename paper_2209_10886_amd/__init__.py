@@ -300,24 +300,26 @@ class Context:
         _check(_lib.hbj_set_multi_solve(self._h, int(mode)))
 
     def tuning(self):
-        """Autotuned variants of the many-RHS operator kernel (tile depth, and whether the incoming
-        data are gathered into tiles first or read from the interface vector) with the measured us
-        per launch of every variant."""
-        nv = 6
+        """Autotuned variants of the many-RHS operator kernel (tile depth, whether the incoming data
+        are gathered into tiles first or read from the interface vector, wavefront groups sharing the
+        right-hand sides) with the measured us per launch of every variant."""
+        nv = 12
         v = (_I32 * 4)()
         us = (ctypes.c_float * (4 * nv))()
         _check(_lib.hbj_get_tuning(self._h, v, us))
         kinds = ("c128 steps", "c128 operator", "c64 steps", "c64 operator")
         depths = (2, 4, 8)
-        label = [f"{'gathered' if j < 3 else 'direct'}/{depths[j % 3]}" for j in range(nv)]
+        groups = (1, 2)
+        label = [f"{'gathered' if j % 6 < 3 else 'direct'}/{depths[j % 3]}/{groups[j // 6]}" for j in range(nv)]
         return {k: {"k_steps_per_batch": depths[v[i] % 3] if v[i] >= 0 else None,
-                    "incoming": ("gathered" if v[i] < 3 else "direct") if v[i] >= 0 else None,
+                    "incoming": ("gathered" if v[i] % 6 < 3 else "direct") if v[i] >= 0 else None,
+                    "wave_groups": groups[v[i] // 6] if v[i] >= 0 else None,
                     "us": {label[j]: round(us[i * nv + j], 2) for j in range(nv)} if v[i] >= 0 else None}
                 for i, k in enumerate(kinds)}
 
     def set_tuning(self, variants):
         """Fix the many-RHS operator kernel's variant per kind (c128 steps, c128 operator, c64 steps,
-        c64 operator): 0-5, or -1 to let the autotuner choose."""
+        c64 operator): 0-11, or -1 to let the autotuner choose."""
         v = (_I32 * 4)(*[int(x) for x in variants])
         _check(_lib.hbj_set_tuning(self._h, v))
 

@@ -339,7 +339,8 @@ hipError_t launch_recon_dense(const Geom& g, const FaceTab* ft, const IfCoef* co
 // many right-hand sides: gather the incoming data G[j][col][r] of subdomains subs[j] (in the element
 // type GT); OUT = T_s[masked rows, :] G_s on MFMA (complex128 operators on f64 MFMA, complex64 on
 // f32), with G_s from the gathered tiles G (variants 0-2: k-steps per batch 2, 4, 8) or straight
-// from the interface vector gin [nrhs][nif] (variants 3-5)
+// from the interface vector gin [nrhs][nif] (variants 3-5); variants 6-11 as 0-5 with the
+// right-hand sides split over two groups of wavefronts
 template <typename GT>
 hipError_t launch_gather_incoming(const Geom& g, const int32_t* subs, int nsub, const FaceTab* ft, const double2* gin,
                                   int nrhs, int rpad, GT* G, hipStream_t st);
@@ -347,7 +348,7 @@ template <typename C>
 hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int mask, const FaceTab* ft, const C* T,
                              const double2* gin, const C* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st,
                              int variant);
-constexpr int kMmVariants = 6;  // k-steps per batch of loads 2, 4, 8; gathered (0-2) or direct (3-5)
+constexpr int kMmVariants = 12;  // k-steps per batch 2, 4, 8; gathered or direct; one or two wave groups
 
 // gradient / misc
 hipError_t launch_gather_receivers(const double2* u, const int32_t* rec, int nrec, int npts, const double2* d,

@@ -75,37 +75,41 @@ constexpr int KW = 4;  // wavefronts splitting the k range of one tile
 // the step's position k) come either from the gathered tiles G ([nsub][L][rpad], element type C:
 // right-hand sides contiguous) or, DIRECT, straight from the interface vector gin ([R][nif],
 // complex128: positions contiguous), where the products on f32 MFMA round them to float at use.
-// KB and the source of B are chosen by the autotuner.
-template <typename C, typename M, int KB, bool DIRECT>
-__global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_scatter_mm(Geom g, const int32_t* subs, int mask, const FaceTab* ft,
+// With NS = 2 the workgroup has two groups of KW wavefronts, each taking half of the right-hand-side
+// blocks (two wavefronts per SIMD, so one's MFMAs overlap the other's loads; the A operands are
+// loaded by both groups).  KB, NS and the source of B are chosen by the autotuner.
+template <typename C, typename M, int KB, bool DIRECT, int NS>
+__global__ __launch_bounds__(64 * KW * NS) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_scatter_mm(Geom g, const int32_t* subs, int mask, const FaceTab* ft,
                                                         const C* __restrict__ T,
                                                         const std::conditional_t<DIRECT, double2, C>* __restrict__ B,
                                                         int nrhs, int rpad, SolveIO io) {
   typedef std::conditional_t<DIRECT, double2, C> BT;
   typedef MfmaAcc<M> A;
   typedef typename A::T V4;
+  constexpr int TW = TB / NS;  // right-hand-side blocks per wavefront
   const int j = blockIdx.y;
   const int s = subs[j];
   const FaceTab F = ft[s];
   const int L = local_if_len(g);
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, w = (threadIdx.x >> 6) % KW, grp = (threadIdx.x >> 6) / KW;
   const int i = lane & 15, k = lane >> 4;
   const int mrow = masked_row_mm(g, mask, blockIdx.x * 16 + i);  // this lane's A row
   const M amask = mrow >= 0 ? (M)1 : (M)0;
-  const int rb0 = blockIdx.z * 16 * TB;
+  const int rb0 = blockIdx.z * 16 * TB;  // first right-hand side of the workgroup's tile
+  const int tb0 = grp * TW;               // first right-hand-side block of this wavefront
   const C* Ts = T + (size_t)s * t_per_sub(g) + t_index(L, mrow < 0 ? 0 : mrow, 0);
   // right-hand sides of this lane's B operands, clamped to the last one (columns past nrhs only
   // feed output columns that are dropped); B element (rhs, col) at bface[jr + col * cs]
   const long cs = DIRECT ? 1 : rpad;
-  long jr[TB];
+  long jr[TW];
 #pragma unroll
-  for (int t = 0; t < TB; ++t) {
-    const long r = min(rb0 + 16 * t + i, nrhs - 1);
+  for (int t = 0; t < TW; ++t) {
+    const long r = min(rb0 + 16 * (tb0 + t) + i, nrhs - 1);
     jr[t] = DIRECT ? r * g.nif : (long)j * L * rpad + r;
   }
-  V4 cr[TB], ci[TB];
+  V4 cr[TW], ci[TW];
 #pragma unroll
-  for (int t = 0; t < TB; ++t) {
+  for (int t = 0; t < TW; ++t) {
     cr[t] = V4{0, 0, 0, 0};
     ci[t] = V4{0, 0, 0, 0};
   }
@@ -118,14 +122,14 @@ __global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2)))
     // this wavefront's k-steps: c0 + 4 (w + KW q), KB of them per batch
     for (int c = c0 + 4 * w; c < c1; c += 4 * KW * KB) {
       C tv[KB];
-      BT gv[KB][TB];
+      BT gv[KB][TW];
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
         const int col = c + 4 * KW * b + k;
         const int cc = col < c1 ? col : c1 - 1;
         tv[b] = Ts[(size_t)cc * kTR];
 #pragma unroll
-        for (int t = 0; t < TB; ++t) gv[b][t] = B[jr[t] + fo + (long)cc * cs];
+        for (int t = 0; t < TW; ++t) gv[b][t] = B[jr[t] + fo + (long)cc * cs];
       }
       __builtin_amdgcn_sched_barrier(0);  // keep the whole batch of loads ahead of the MFMAs
 #pragma unroll
@@ -133,7 +137,7 @@ __global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2)))
         const M ok = (c + 4 * KW * b + k < c1) ? amask : (M)0;
         const M ar = (M)tv[b].x * ok, ai = (M)tv[b].y * ok;
 #pragma unroll
-        for (int t = 0; t < TB; ++t) {
+        for (int t = 0; t < TW; ++t) {
           const M br = (M)gv[b][t].x, bi = (M)gv[b][t].y;
           cr[t] = A::mma(ar, br, cr[t]);
           ci[t] = A::mma(ar, bi, ci[t]);
@@ -143,16 +147,17 @@ __global__ __launch_bounds__(64 * KW) __attribute__((amdgpu_waves_per_eu(1, 2)))
       }
     }
   }
-  // sum the KW partial tiles: wavefront w finishes right-hand-side block t = w
+  // sum the KW partial tiles: the wavefronts of group 0 finish right-hand-side block t = w
   __shared__ M red[KW][TB][2][4][64];
 #pragma unroll
-  for (int t = 0; t < TB; ++t)
+  for (int t = 0; t < TW; ++t)
 #pragma unroll
     for (int reg = 0; reg < 4; ++reg) {
-      red[w][t][0][reg][lane] = cr[t][reg];
-      red[w][t][1][reg][lane] = ci[t][reg];
+      red[w][tb0 + t][0][reg][lane] = cr[t][reg];
+      red[w][tb0 + t][1][reg][lane] = ci[t][reg];
     }
   __syncthreads();
+  if (grp != 0) return;
   const int t = w;  // KW == TB
 #pragma unroll
   for (int reg = 0; reg < 4; ++reg) {
@@ -290,16 +295,22 @@ hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int m
   static_assert(KW == TB, "one right-hand-side block per wavefront in the epilogue");
   const dim3 grid((rows + 15) / 16, nsub, (nrhs + 16 * TB - 1) / (16 * TB));
   typedef typename std::conditional<sizeof(C) == 16, double, float>::type M;
-  auto go = [&](auto kern, auto src) {
-    hipLaunchKernelGGL(kern, grid, dim3(64 * KW), 0, st, g, subs, mask, ft, T, src, nrhs, rpad, io);
+  auto go = [&](auto kern, auto src, int ns) {
+    hipLaunchKernelGGL(kern, grid, dim3(64 * KW * ns), 0, st, g, subs, mask, ft, T, src, nrhs, rpad, io);
   };
   switch (variant) {
-    case 0: go(k_scatter_mm<C, M, 2, false>, G); break;
-    case 1: go(k_scatter_mm<C, M, 4, false>, G); break;
-    case 2: go(k_scatter_mm<C, M, 8, false>, G); break;
-    case 3: go(k_scatter_mm<C, M, 2, true>, gin); break;
-    case 4: go(k_scatter_mm<C, M, 4, true>, gin); break;
-    case 5: go(k_scatter_mm<C, M, 8, true>, gin); break;
+    case 0: go(k_scatter_mm<C, M, 2, false, 1>, G, 1); break;
+    case 1: go(k_scatter_mm<C, M, 4, false, 1>, G, 1); break;
+    case 2: go(k_scatter_mm<C, M, 8, false, 1>, G, 1); break;
+    case 3: go(k_scatter_mm<C, M, 2, true, 1>, gin, 1); break;
+    case 4: go(k_scatter_mm<C, M, 4, true, 1>, gin, 1); break;
+    case 5: go(k_scatter_mm<C, M, 8, true, 1>, gin, 1); break;
+    case 6: go(k_scatter_mm<C, M, 2, false, 2>, G, 2); break;
+    case 7: go(k_scatter_mm<C, M, 4, false, 2>, G, 2); break;
+    case 8: go(k_scatter_mm<C, M, 8, false, 2>, G, 2); break;
+    case 9: go(k_scatter_mm<C, M, 2, true, 2>, gin, 2); break;
+    case 10: go(k_scatter_mm<C, M, 4, true, 2>, gin, 2); break;
+    case 11: go(k_scatter_mm<C, M, 8, true, 2>, gin, 2); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

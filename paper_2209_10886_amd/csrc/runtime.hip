@@ -622,10 +622,11 @@ int run_dense(hbj_ctx* c, const Entry* ent, const FaceTab* eft, int nent, int ma
     const double tbytes = elems / nrhs * (c64 ? 8.0 : 16.0);
     const double2* gin = src ? io.g_b : io.g_a;
     const int slot = (c64 ? 2 : 0) + (mask == 0xF ? 1 : 0);
-    // variants 0-2 gather the incoming data into tiles first (in complex64 for the complex64
-    // products, which round every operand to float anyway); 3-5 read them from gin directly
+    // variants 0-2 and 6-8 gather the incoming data into tiles first (in complex64 for the
+    // complex64 products, which round every operand to float anyway); the others read them from
+    // gin directly
     auto launch = [&](int v, const SolveIO& lio) -> hipError_t {
-      if (v < 3) {
+      if (v % 6 < 3) {
         const hipError_t e =
             c64 ? launch_gather_incoming(c->g, subs, nsub, c->ft, gin, nrhs, rpad, (float2*)c->Gbuf, c->st)
                 : launch_gather_incoming(c->g, subs, nsub, c->ft, gin, nrhs, rpad, c->Gbuf, c->st);
