@@ -122,7 +122,10 @@ typedef struct {
   double  tol;           /* stop at ||b - (I-S) g|| <= tol ||b|| (Sec. 7: 1e-6)     */
   int32_t restart;       /* GMRES restart length (50)                               */
   int32_t maxit;         /* total iteration cap                                     */
-  int32_t flexible;      /* 1 = FGMRES (forced on for HBJ_MIXED)                    */
+  int32_t flexible;      /* ignored: the preconditioned directions are always kept
+                            (FGMRES storage; with a fixed preconditioner the same
+                            iterates as GMRES, and the solution update needs no
+                            further preconditioner application)                  */
 } hbj_solve_opts;
 
 typedef struct {

@@ -2081,7 +2081,10 @@ static int solve_impl(hbj_ctx* c, const double2* f, double2* u, int nrhs, const 
   hbj_solve_opts o{1e-6, 50, 1000, 0};
   if (opts) o = *opts;
   if (!(o.tol > 0.0) || o.restart < 1 || o.maxit < 0) return fail(HBJ_EINVAL, "bad solve options");
-  if (c->P.precision == HBJ_MIXED) o.flexible = 1;
+  // The preconditioned search directions are always kept (FGMRES storage): with a fixed
+  // preconditioner the iterates are those of right-preconditioned GMRES, and the solution update
+  // is then one pass over them instead of one more preconditioner application.
+  o.flexible = 1;
   Schedule* S;
   int rc = build_schedule(c, nrhs, &S);
   if (rc) return rc;
