@@ -1,24 +1,29 @@
 """Benchmark: Helmholtz solves/s of the block-Jacobi sweeping preconditioner in GMRES.
 
-Workload (default): 1024 x 1024 interior grid (h = 1/1025), 8 x 8 checkerboard of
-128 x 128 subdomains, 10 points per wavelength (k = 2 pi / (10 h)), smooth seeded
-random medium c in [0.8, 1.2], one Gaussian source at (0.5, 0.1); GMRES(50) to
-relative residual 1e-6 with the block-Jacobi preconditioner, complex128.
+Workload of the headline (default): 1024 x 1024 interior grid (h = 1/1025), 8 x 8 checkerboard
+of 128 x 128 subdomains, 10 points per wavelength (k = 2 pi / (10 h)), smooth seeded random
+medium c in [0.8, 1.2], one Gaussian source at (0.5, 0.1); GMRES(50) to relative residual 1e-6
+with the block-Jacobi preconditioner, complex128.
 
-A step is one solve(): lifting, GMRES on (I - S) g = b and reconstruction, with
-every input already resident in HBM.  Setup and the factorisation are done once
-before the timed region (reported separately).
+A step is one solve(): lifting, GMRES on (I - S) g = b and reconstruction, with every input
+already resident in HBM.  Setup and the factorisation are done once before the timed region
+(reported separately).
 
 Prints one JSON line.  Besides the contract fields it carries
-  roofline      the dominant kernel's algorithmic bytes per launch over its mean
-                launch time (HIP events on the solver stream, profiled solve after
-                the timed region), against 8 TB/s; for many right-hand sides, where
-                the operators are matrix-core products, their flops per launch
-                against the FP32 / FP64 matrix peak;
-  cpu_baseline  the CPU oracle (numpy/scipy, one core) timed on a bounded sample:
-                lifting + a few GMRES iterations + reconstruction, scaled to one
-                full solve with the GPU's iteration count;
-  mixed         the same problem with complex64 factors (FGMRES, refined operator).
+  roofline      the dominant kernel's algorithmic bytes per launch over its mean launch time
+                (HIP events on the solver stream, from a profiled solve right after the timed
+                region), against 8 TB/s; traffic = HBM bytes per launch from the committed
+                rocprofv3 counter summary (profiles/traffic.json), when it was taken from the
+                current source of the kernel;
+  cpu_baseline  the CPU oracle (numpy/scipy, one process) timed on a bounded sample: lifting +
+                a few GMRES iterations + reconstruction, scaled to one full solve with the GPU's
+                iteration count; cpu_baseline_row_owners: the same oracle with one process per
+                row of subdomains (the paper's rank layout, Sec. 7);
+  legs          the other workloads, each on the GPU: the FP64 solve to 1e-8, the banded local
+                solves (subdomain-solve GB/s, FP64 and complex64), mixed precision (complex64
+                factors, FGMRES) to 1e-6 and 1e-8 with the error against the FP64 field, the
+                second-order transmission, banded solves of 64 right-hand sides, the 2048^2
+                64-source block solve (MFMA), and the 512^2 adjoint gradient.
 """
 from __future__ import annotations
 
@@ -33,6 +38,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# dense matrix-core peaks of MI355X (TFLOP/s) for the contractions of the many-right-hand-side form
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 
 
 def log(*a):
@@ -46,7 +53,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="fp64_1024_8x8_grf")
     p.add_argument("--tol", type=float, default=1e-6)
-    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
     p.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     p.add_argument("--no-banded", action="store_true", help="skip the banded-operator comparison")
     p.add_argument("--graphs", action="store_true", help="replay the GMRES iterations as HIP graphs")
@@ -57,9 +64,11 @@ def parse():
                    help="skip the run of the same solve to relative residual 1e-8")
     p.add_argument("--no-second-order", action="store_true",
                    help="skip the run with the second-order transmission condition")
+    p.add_argument("--no-multi", action="store_true", help="skip the 2048^2 64-source leg")
+    p.add_argument("--no-gradient", action="store_true", help="skip the 512^2 adjoint-gradient leg")
     p.add_argument("--transmission", type=int, default=1, choices=(1, 2),
                    help="transmission condition of the main run (1: Robin, as the workloads specify; 2: second order)")
-    p.add_argument("--cpu-seconds", type=float, default=20.0, help="target CPU time of the oracle sample")
+    p.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of each oracle sample")
     return p.parse_args()
 
 
@@ -83,25 +92,89 @@ def traffic_from_profiles(kernel_symbol, workload):
         return None
 
 
-def cpu_baseline(wl, m, f, iters_gpu, target_s):
-    """Time the oracle on a bounded sample and scale to one solve (single core)."""
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
-    import numpy as np
+# ---------------------------------------------------------------------------
+# CPU oracle baselines (run before the GPU is touched: the row-owner processes are forked)
+# ---------------------------------------------------------------------------
 
-    from oracle import sweep
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def usable_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def _owner_main(conn, grid_args, n1, n2):
+    """Row-owner process: keeps the factors of the subdomains it is sent (one row of the
+    checkerboard) and runs the oracle's per-subdomain methods on request."""
     from oracle.dd import Decomposition
     from oracle.fd import Grid
 
-    t0 = time.perf_counter()
-    dd = Decomposition(Grid(wl.nx, wl.ny, wl.h, wl.k, m), wl.n1, wl.n2)
-    for s in dd.sub.values():
-        _ = s.lu  # sparse LU of every subdomain (setup, not timed)
-    t_factor = time.perf_counter() - t0
+    dd = Decomposition(Grid(*grid_args), n1, n2)
+    while True:
+        msg = conn.recv()
+        if msg is None:
+            break
+        kind, keys, data = msg
+        conn.send(dd._map(kind, keys, data))
+
+
+class RowOwners:
+    """One process per row of subdomains (row i2 -> process (i2 - 1) mod nproc), as the paper
+    assigns rows to MPI ranks (Sec. 7); a mapper for oracle.dd.Decomposition."""
+
+    def __init__(self, grid_args, n1, n2, nproc):
+        import multiprocessing as mp
+
+        ctx = mp.get_context("fork")
+        self.nproc = nproc
+        self.conns, self.procs = [], []
+        for _ in range(nproc):
+            a, b = ctx.Pipe()
+            p = ctx.Process(target=_owner_main, args=(b, grid_args, n1, n2), daemon=True)
+            p.start()
+            self.conns.append(a)
+            self.procs.append(p)
+
+    def __call__(self, kind, keys, data):
+        by = {}
+        for idx, i in enumerate(keys):
+            by.setdefault((i[1] - 1) % self.nproc, []).append((idx, i))
+        for o, lst in by.items():
+            self.conns[o].send((kind, [i for _, i in lst], data))
+        out = [None] * len(keys)
+        for o, lst in by.items():
+            for (idx, _), r in zip(lst, self.conns[o].recv()):
+                out[idx] = r
+        return out
+
+    def close(self):
+        for c in self.conns:
+            c.send(None)
+        for p in self.procs:
+            p.join(timeout=10)
+
+
+def time_oracle(dd, f, target_s):
+    """Lifting + reconstruction once, then preconditioned GMRES iterations (one block-Jacobi
+    application and one operator application each) until about target_s seconds."""
+    import numpy as np
+
+    from oracle import sweep
+
     t1 = time.perf_counter()
     b = dd.lifting(f)
     u = dd.reconstruct(f, b)  # same cost as the reconstruction of a solve
     t_lr = time.perf_counter() - t1
-    # GMRES iterations: one preconditioner application + one operator application each
     v = b / np.linalg.norm(b)
     n_it = 0
     t2 = time.perf_counter()
@@ -113,22 +186,68 @@ def cpu_baseline(wl, m, f, iters_gpu, target_s):
         el = time.perf_counter() - t2
         if el * (n_it + 1) / n_it > target_s or n_it >= 50:
             break
-    t_it = (time.perf_counter() - t2) / n_it
-    per_solve = t_lr + iters_gpu * t_it
     del u
+    return t_lr, (time.perf_counter() - t2) / n_it, n_it
+
+
+def cpu_baselines(wl, m, f, target_s):
+    """Per-iteration and lifting+reconstruction costs of the oracle: one process, and one process
+    per row of subdomains.  Returns the raw timings; the solves/s figures use the GPU's
+    iteration count once it is known."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    from oracle.dd import Decomposition
+    from oracle.fd import Grid
+
+    grid_args = (wl.nx, wl.ny, wl.h, wl.k, m)
+    t0 = time.perf_counter()
+    dd = Decomposition(Grid(*grid_args), wl.n1, wl.n2)
+    for s in dd.sub.values():
+        _ = s.lu  # sparse LU of every subdomain (setup, not timed)
+    t_factor = time.perf_counter() - t0
+    log(f"[bench] CPU oracle, one process: factorisation {t_factor:.1f} s")
+    t_lr, t_it, n_it = time_oracle(dd, f, target_s)
+    out = {"single": {"t_lr": t_lr, "t_it": t_it, "n_it": n_it, "t_factor": t_factor, "cores": 1}}
+    del dd
+    nproc = min(wl.n2, usable_cores())
+    if nproc > 1:
+        log(f"[bench] CPU oracle, {nproc} row-owner processes")
+        pool = RowOwners(grid_args, wl.n1, wl.n2, nproc)
+        try:
+            dd = Decomposition(Grid(*grid_args), wl.n1, wl.n2)
+            dd.mapper = pool
+            t0 = time.perf_counter()
+            dd.lifting(f)  # factors every subdomain in its owner (setup, not timed)
+            t_factor = time.perf_counter() - t0
+            t_lr, t_it, n_it = time_oracle(dd, f, target_s)
+            out["rows"] = {"t_lr": t_lr, "t_it": t_it, "n_it": n_it, "t_factor": t_factor, "cores": nproc}
+        finally:
+            pool.close()
+    return out
+
+
+def cpu_entry(wl, timing, iters_gpu, kind_note):
+    per_solve = timing["t_lr"] + iters_gpu * timing["t_it"]
     return {
         "value": 1.0 / per_solve,
         "unit": "solves/s",
-        "cores": 1,
+        "cores": timing["cores"],
         "kind": "oracle",
-        "sample": (f"{wl.nx}^2 grid, {wl.n1}x{wl.n2} subdomains: lifting + reconstruction ({t_lr:.2f} s) and "
-                   f"{n_it} preconditioned GMRES iterations ({t_it:.2f} s each, scipy SuperLU local solves); "
-                   f"scaled to {iters_gpu} iterations; subdomain factorisation ({t_factor:.1f} s) excluded as on the GPU"),
+        "cpu_model": cpu_model(),
+        "host_cpu_count": os.cpu_count(),
+        "host_usable_cores": usable_cores(),
+        "sample": (f"{wl.nx}^2 grid, {wl.n1}x{wl.n2} subdomains, {kind_note}: lifting + reconstruction "
+                   f"({timing['t_lr']:.2f} s) and {timing['n_it']} preconditioned GMRES iterations "
+                   f"({timing['t_it']:.3f} s each, scipy SuperLU local solves); scaled to {iters_gpu} iterations; "
+                   f"subdomain factorisation ({timing['t_factor']:.1f} s) excluded as on the GPU"),
     }
 
 
+# ---------------------------------------------------------------------------
+# GPU legs
+# ---------------------------------------------------------------------------
+
 def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, profile_names, graphs=False,
-             transmission=1):
+             transmission=1, keep=False):
     """Setup + factor (untimed), warmup solves, timed solves, one profiled solve."""
     import torch
 
@@ -155,8 +274,12 @@ def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, p
     ctx.set_profiling(False)
     stats = {name: ctx.kernel_stats(kc) for kc, name in profile_names.items()}
     tuning = {k: v for k, v in ctx.tuning().items() if v["k_steps_per_batch"] is not None}
-    ctx.close()
-    return {"seconds": dt, "steps": steps, "factor_s": t_factor, "stats": st, "kernels": stats, "tuning": tuning}
+    res = {"seconds": dt, "steps": steps, "factor_s": t_factor, "stats": st, "kernels": stats, "tuning": tuning}
+    if keep:
+        res["ctx"] = ctx
+    else:
+        ctx.close()
+    return res
 
 
 def merge_kernels(kernels):
@@ -171,16 +294,12 @@ def merge_kernels(kernels):
     return out
 
 
-# dense matrix-core peaks of MI355X (TFLOP/s) for the contractions of the many-right-hand-side form
-MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
-
-
 def roofline_of(kernels, workload, mfma=None):
     """Roofline of the kernel with the most time. mfma maps kernel symbols that are dense
     contractions (the operator products for many right-hand sides) to their precision: those are
     priced in TFLOP/s against the matrix-core peak, every other kernel in GB/s against HBM."""
     mfma = mfma or {}
-    merged = merge_kernels(kernels)
+    merged = merge_kernels({k: v for k, v in kernels.items() if v["launches"] > 0})
     name, ks = max(merged.items(), key=lambda kv: kv[1]["ms"])
     avg_ms = ks["ms"] / ks["launches"]
     bpl = ks["bytes"] / ks["launches"]
@@ -199,8 +318,12 @@ def roofline_of(kernels, workload, mfma=None):
                 "avg_launch_ms": avg_ms, "launches": ks["launches"], "share_of_kernel_time": share,
                 "launch_kinds": detail}
     achieved = bpl / (avg_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles(name, workload)
     return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(name, workload),
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_source": ("profiles/traffic.json: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE of this kernel on "
+                               "this workload, scaled by a copy of known size; taken from the current kernel source")
+            if traffic is not None else None,
             "bytes_per_launch": bpl, "avg_launch_ms": avg_ms, "launches": ks["launches"],
             "share_of_kernel_time": share, "launch_kinds": detail}
 
@@ -222,7 +345,7 @@ def factor_seconds(hbj, wl, mt, precision, transmission, multi_solve):
     return dt
 
 
-def many_rhs_solves(hbj, wl, mt, nrhs, precision, names, reps=3):
+def many_rhs_solves(hbj, wl, mt, nrhs, precision, reps=3):
     """The banded operator (one local solve per subdomain and right-hand side) on nrhs columns:
     16 right-hand sides per workgroup on MFMA against one workgroup per solve."""
     import torch
@@ -267,33 +390,13 @@ def solve_gbs(kernels, names):
     return b / (t * 1e-3) / 1e9 if t > 0 else None
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form of the sweep is a "
-              "design, not a measured configuration", file=sys.stderr)
-        sys.exit(2)
+def relerr(a, b):
     import torch
 
-    import paper_2209_10886_amd as hbj
-    import workload as W
+    return float((torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)).item())
 
-    wl = W.WORKLOADS[args.workload]
-    dev = torch.device("cuda:0")
-    log(f"[bench] workload {wl.name}: generating medium and sources")
-    m = W.slowness2(wl)
-    f_all = W.sources(wl)
-    nsrc = f_all.shape[0]
-    f = f_all[0] if nsrc == 1 else f_all
-    mt = torch.as_tensor(m, device=dev)
-    ft = torch.as_tensor(f, device=dev)
-    u = torch.empty_like(ft)
-    # the multi-source and mixed workloads store the factors in complex64
-    headline_prec = hbj.MIXED if wl.name.startswith(("mixed", "multi")) else hbj.FP64
-    if nsrc > 1:
-        args.no_banded = True
-        args.no_cpu = args.no_cpu or nsrc > 1
-        args.no_mixed = True
+
+def kernel_names(hbj, many):
     names64 = {hbj.K_FWD: "k_fwd<double,16,4,5>", hbj.K_BWD: "k_bwd<double,16,2,3>",
                hbj.K_SCATTER: "k_scatter_apply<double2,16> (sweep steps)",
                hbj.K_OPERATOR: "k_scatter_apply<double2,16> (operator)",
@@ -305,20 +408,139 @@ def main():
                hbj.K_SWEEP: "k_sweep_df", hbj.K_LIFT: "k_lift_partial+k_recon_dense",
                hbj.K_KRYLOV: "krylov (Gram-Schmidt kernels of one iteration)"}
     mfma = {}
-    if nsrc >= 4:
+    if many:
         # from 4 right-hand sides on the operators run as matrix-core products (k_scatter_mm)
+        names32[hbj.K_SCATTER] = "k_scatter_mm<float2,float> (sweep steps)"
+        names64[hbj.K_SCATTER] = "k_scatter_mm<double2,double> (sweep steps)"
         for nm_ in (names64, names32):
-            nm_[hbj.K_SCATTER] = ("k_scatter_mm<float2,float> (sweep steps)" if nm_ is names32
-                                  else "k_scatter_mm<double2,double> (sweep steps)")
             nm_[hbj.K_OPERATOR] = "k_scatter_mm<double2,double> (operator)"
             nm_[hbj.K_LIFT] = "k_lift_partial+k_recon_mm"
         mfma = {"k_scatter_mm<float2,float>": "f32", "k_scatter_mm<double2,double>": "f64"}
+    return names64, names32, mfma
+
+
+def multi_source_leg(hbj, steps=2, warmup=1):
+    """2048^2, 16 x 16 of 128^2, 64 sources: complex64 factors, MFMA operator products, lockstep
+    FGMRES to 1e-6 (one block solve of 64 right-hand sides per step)."""
+    import torch
+
+    import workload as W
+
+    wl = W.MULTI_2048
+    dev = torch.device("cuda:0")
+    log(f"[bench] {wl.name}: 64-source block solve")
+    mt = torch.as_tensor(W.slowness2(wl), device=dev)
+    ft = torch.as_tensor(W.sources(wl), device=dev)
+    u = torch.empty_like(ft)
+    names64, names32, mfma = kernel_names(hbj, True)
+    r = run_form(hbj, wl, mt, ft, u, hbj.MIXED, hbj.OP_DENSE, steps, warmup, 1e-6, names32, keep=True)
+    ctx = r.pop("ctx")
+    vr = ctx.volume_residual(ft, u)
+    ctx.close()
+    st = r["stats"]
+    kr = r["kernels"][names32[hbj.K_KRYLOV]]
+    mm = r["kernels"][names32[hbj.K_SCATTER]]
+    out = {
+        "workload": wl.name, "sources": 64, "tol": 1e-6,
+        "solves_per_s": steps * 64 / r["seconds"], "ms_per_block_solve": r["seconds"] / steps * 1e3,
+        "iters": st.iters, "converged": st.converged, "relres": st.relres, "factor_s": r["factor_s"],
+        "volume_residual_max": max(vr),
+        "roofline": roofline_of(r["kernels"], wl.name, mfma),
+        "step_products_f32": {"avg_launch_ms": mm["ms"] / max(1, mm["launches"]),
+                              "TFLOP/s": mm["flops"] / max(1e-12, mm["ms"] * 1e-3) / 1e12,
+                              "frac_of_f32_mfma_peak": mm["flops"] / max(1e-12, mm["ms"] * 1e-3) / 1e12
+                              / MFMA_PEAK_TFLOPS["f32"]},
+        "gram_schmidt": {"ms_per_iteration": kr["ms"] / max(1, st.iters),
+                         "GB/s": kr["bytes"] / max(1e-12, kr["ms"] * 1e-3) / 1e9,
+                         "frac_of_hbm_peak": kr["bytes"] / max(1e-12, kr["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "autotuned_operator_tiles": r["tuning"],
+    }
+    log(f"[bench]   {out['ms_per_block_solve']:.1f} ms per block solve ({out['solves_per_s']:.1f} solves/s), "
+        f"iters {st.iters}, step products {out['step_products_f32']['TFLOP/s']:.1f} TFLOP/s, "
+        f"Gram-Schmidt {out['gram_schmidt']['GB/s']:.0f} GB/s")
+    del ft, u, mt
+    torch.cuda.empty_cache()
+    return out
+
+
+def gradient_leg(hbj, reps=2):
+    """512^2, 8 x 8 of 64^2, 16 sources: loss and dL/dm by forward + adjoint solves at tol 1e-12.
+    The synthetic data d = P u(m_true) come from a GPU solve at tol 1e-12 with the true model."""
+    import torch
+
+    import workload as W
+
+    wl = W.GRAD_512
+    dev = torch.device("cuda:0")
+    log(f"[bench] {wl.name}: adjoint gradient, 16 sources")
+    m_true = W.slowness2(wl)
+    m0 = W.smoothed_model(m_true, 20.0)
+    ft = torch.as_tensor(W.sources(wl), device=dev)
+    rec = torch.as_tensor(W.receiver_row(wl), device=dev)
+    ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=torch.as_tensor(m_true, device=dev), precond=hbj.PC_BJ,
+                    operator_form=hbj.OP_DENSE, device=dev)
+    ctx.factor()
+    ut, _ = ctx.solve(ft, tol=1e-12, maxit=3000)
+    d = ut.reshape(16, -1)[:, rec.long()].contiguous()
+    ctx.set_slowness2(torch.as_tensor(m0, device=dev))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.factor()
+    torch.cuda.synchronize()
+    t_factor = time.perf_counter() - t0
+    loss, grad = ctx.gradient(ft, rec, d, tol=1e-12, maxit=3000)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        loss, grad = ctx.gradient(ft, rec, d, tol=1e-12, maxit=3000)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ctx.close()
+    out = {"workload": wl.name, "sources": 16, "receivers": int(rec.numel()), "tol": 1e-12,
+           "gradient_s": dt, "solves_per_s": 32 / dt, "factor_s": t_factor, "loss": loss,
+           "grad_norm": float(torch.linalg.vector_norm(grad).item())}
+    log(f"[bench]   gradient {dt * 1e3:.1f} ms (32 solves at tol 1e-12), loss {loss:.6e}")
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form of the sweep is a "
+              "design, not a measured configuration", file=sys.stderr)
+        sys.exit(2)
+    import workload as W
+
+    wl = W.WORKLOADS[args.workload]
+    log(f"[bench] workload {wl.name}: generating medium and sources")
+    m = W.slowness2(wl)
+    f_all = W.sources(wl)
+    nsrc = f_all.shape[0]
+    f = f_all[0] if nsrc == 1 else f_all
+    cpu = None
+    if not args.no_cpu and nsrc == 1:
+        cpu = cpu_baselines(wl, m, f, args.cpu_seconds)
+
+    import torch
+
+    import paper_2209_10886_amd as hbj
+
+    dev = torch.device("cuda:0")
+    mt = torch.as_tensor(m, device=dev)
+    ft = torch.as_tensor(f, device=dev)
+    u = torch.empty_like(ft)
+    # the multi-source and mixed workloads store the factors in complex64
+    headline_prec = hbj.MIXED if wl.name.startswith(("mixed", "multi")) else hbj.FP64
+    if nsrc > 1:
+        args.no_banded = args.no_mixed = args.no_multi = True
+    names64, names32, mfma = kernel_names(hbj, nsrc >= 4)
+    names_main = names64 if headline_prec == hbj.FP64 else names32
 
     log(f"[bench] {'FP64' if headline_prec == hbj.FP64 else 'mixed'}, dense scattering operators (headline), "
         f"{nsrc} right-hand side(s)")
     main_run = run_form(hbj, wl, mt, ft, u, headline_prec, hbj.OP_DENSE, args.steps, args.warmup, args.tol,
-                        names64 if headline_prec == hbj.FP64 else names32, graphs=args.graphs,
-                        transmission=args.transmission)
+                        names_main, graphs=args.graphs, transmission=args.transmission, keep=True)
+    ctx_main = main_run.pop("ctx")
     u_main = u.clone()
     st = main_run["stats"]
     ms_per_step = main_run["seconds"] / max(args.steps, 1) * 1e3
@@ -326,6 +548,13 @@ def main():
         f"factor {main_run['factor_s']:.2f} s")
     roof = roofline_of(main_run["kernels"], wl.name, mfma)
     log(f"[bench] dominant {roof['kernel']}: {roof['avg_launch_ms']:.4f} ms avg, {roof['achieved']:.1f} {roof['unit']}")
+    # accuracy of the timed solve: volume residual of the field, and its error against the same
+    # solver run to tol 1e-12 (which the parity tests hold within 1e-8 of the direct solution)
+    vres = ctx_main.volume_residual(ft, u_main)
+    u_ref = None
+    if nsrc == 1:
+        u_ref, st_ref = ctx_main.solve(ft, tol=1e-12, maxit=3000)
+    ctx_main.close()
 
     result = {
         "metric": "Helmholtz solves/s at rel-res 1e-6; subdomain-solve HBM GB/s (FP64 vs mixed)",
@@ -343,18 +572,21 @@ def main():
         "config": {"workload": wl.name, "grid": [wl.nx, wl.ny], "decomposition": [wl.n1, wl.n2],
                    "subdomain": [wl.sub_nx, wl.sub_ny], "points_per_wavelength": wl.ppw, "k": wl.k,
                    "medium": wl.medium, "sources": nsrc, "tol": args.tol,
-                   "krylov": "GMRES(50), right-preconditioned, delayed reorthogonalisation", "preconditioner": "block Jacobi, width N1",
+                   "krylov": "FGMRES(50), right-preconditioned, delayed reorthogonalisation",
+                   "preconditioner": "block Jacobi, width N1",
                    "operator_form": "dense local scattering operators (formed at factor time)",
                    "transmission": "Robin (first order)" if args.transmission == 1 else
                    "second order on interface faces"},
         "iters": st.iters,
         "relres": st.relres,
+        "volume_residual": max(vres),
         "steps_per_pc": st.steps_per_pc,
         "factor_s": main_run["factor_s"],
-        "subdomain_solve_gbs": solve_gbs(main_run["kernels"], [names64[hbj.K_FWD], names64[hbj.K_BWD]])
-        if headline_prec == hbj.FP64 else None,
         "roofline": roof,
     }
+    if u_ref is not None:
+        result["err_vs_tol1e-12_field"] = relerr(u_main, u_ref)
+        result["reference_solve_tol1e-12"] = {"iters": st_ref.iters, "relres": st_ref.relres}
     if main_run["tuning"]:
         result["autotuned_operator_tiles"] = main_run["tuning"]
     # the dense operators come from one banded solve per interface position (16 per workgroup on
@@ -367,12 +599,13 @@ def main():
     if not args.no_tight and nsrc == 1 and args.tol > 1e-8:
         # the FP64 workload is also specified to relative residual 1e-8: the same solve to that tolerance
         log("[bench] same solve to relative residual 1e-8")
-        tr = run_form(hbj, wl, mt, ft, u, headline_prec, hbj.OP_DENSE, args.steps, 1, 1e-8,
-                      names64 if headline_prec == hbj.FP64 else names32, graphs=args.graphs,
-                      transmission=args.transmission)
+        tr = run_form(hbj, wl, mt, ft, u, headline_prec, hbj.OP_DENSE, args.steps, 1, 1e-8, names_main,
+                      graphs=args.graphs, transmission=args.transmission)
         result["tol_1e-8"] = {"solves_per_s": args.steps / tr["seconds"], "iters": tr["stats"].iters,
                               "relres": tr["stats"].relres,
                               "ms_per_solve": tr["seconds"] / max(args.steps, 1) * 1e3}
+        if u_ref is not None:
+            result["tol_1e-8"]["err_vs_tol1e-12_field"] = relerr(u, u_ref)
         log(f"[bench] to 1e-8: {result['tol_1e-8']['ms_per_solve']:.2f} ms/solve, iters {tr['stats'].iters}")
 
     if not args.no_banded:
@@ -382,28 +615,43 @@ def main():
             "solves_per_s": 1.0 / br["seconds"], "iters": br["stats"].iters, "relres": br["stats"].relres,
             "subdomain_solve_gbs": solve_gbs(br["kernels"], [names64[hbj.K_FWD], names64[hbj.K_BWD]]),
             "roofline": roofline_of(br["kernels"], wl.name + "/banded")}
+        result["banded_fp64"]["subdomain_solve_frac_of_hbm_peak"] = \
+            result["banded_fp64"]["subdomain_solve_gbs"] / HBM_PEAK_GBS
 
     if not args.no_mixed:
         log("[bench] mixed precision (complex64 factors and preconditioner operators)")
-        mr = run_form(hbj, wl, mt, ft, u, hbj.MIXED, hbj.OP_DENSE, args.steps, 1, args.tol, names32,
-                      graphs=args.graphs)
-        result["mixed"] = {"solves_per_s": args.steps / mr["seconds"], "iters": mr["stats"].iters,
-                           "relres": mr["stats"].relres, "factor_s": mr["factor_s"],
-                           "roofline": roofline_of(mr["kernels"], wl.name + "/mixed")}
+        mixed = {}
+        for tol in (args.tol, 1e-8):
+            mr = run_form(hbj, wl, mt, ft, u, hbj.MIXED, hbj.OP_DENSE, args.steps, 1, tol, names32,
+                          graphs=args.graphs)
+            leg = {"solves_per_s": args.steps / mr["seconds"], "iters": mr["stats"].iters,
+                   "relres": mr["stats"].relres, "factor_s": mr["factor_s"]}
+            if u_ref is not None:
+                leg["err_vs_fp64_field"] = relerr(u, u_ref)
+            if tol == args.tol:
+                leg["roofline"] = roofline_of(mr["kernels"], wl.name + "/mixed")
+            mixed[f"tol_{tol:g}"] = leg
+            log(f"[bench] mixed to {tol:g}: {mr['seconds'] / args.steps * 1e3:.2f} ms/solve, iters "
+                f"{mr['stats'].iters}, error vs FP64 field {leg.get('err_vs_fp64_field', float('nan')):.2e}")
+        result["mixed"] = mixed
         if not args.no_banded:
             mb = run_form(hbj, wl, mt, ft, u, hbj.MIXED, hbj.OP_BANDED, 1, 0, args.tol, names32)
             result["banded_mixed"] = {
                 "solves_per_s": 1.0 / mb["seconds"], "iters": mb["stats"].iters,
+                "local_ir_max": mb["stats"].local_ir_max, "local_ir_resid": mb["stats"].local_ir_resid,
                 "subdomain_solve_gbs": solve_gbs(mb["kernels"], [names32[hbj.K_FWD], names32[hbj.K_BWD]])}
+            result["banded_mixed"]["subdomain_solve_frac_of_hbm_peak"] = \
+                result["banded_mixed"]["subdomain_solve_gbs"] / HBM_PEAK_GBS
+            if u_ref is not None:
+                result["banded_mixed"]["err_vs_fp64_field"] = relerr(u, u_ref)
 
     if not args.no_second_order and nsrc == 1 and args.transmission == 1:
         # the workload fixes the Robin transmission condition; the second-order one (interface faces
         # only, same field) is measured beside it
         log("[bench] second-order transmission condition (dense form, same precision)")
-        u1 = u_main
-        sr = run_form(hbj, wl, mt, ft, u, headline_prec, hbj.OP_DENSE, args.steps, 1, args.tol,
-                      names64 if headline_prec == hbj.FP64 else names32, graphs=args.graphs, transmission=2)
-        diff = float((torch.linalg.vector_norm(u - u1) / torch.linalg.vector_norm(u1)).item())
+        sr = run_form(hbj, wl, mt, ft, u, headline_prec, hbj.OP_DENSE, args.steps, 1, args.tol, names_main,
+                      graphs=args.graphs, transmission=2)
+        diff = relerr(u, u_main)
         result["second_order_transmission"] = {
             "solves_per_s": args.steps / sr["seconds"], "iters": sr["stats"].iters, "relres": sr["stats"].relres,
             "factor_s": sr["factor_s"], "rel_diff_vs_robin_field": diff}
@@ -411,16 +659,25 @@ def main():
             f"field differs from the Robin run by {diff:.1e}")
 
     if not args.no_many_rhs and nsrc == 1:
-        for prec, key, nm in ((hbj.FP64, "banded_64rhs_fp64", names64), (hbj.MIXED, "banded_64rhs_mixed", names32)):
+        for prec, key in ((hbj.FP64, "banded_64rhs_fp64"), (hbj.MIXED, "banded_64rhs_mixed")):
             log(f"[bench] banded operator on 64 right-hand sides ({key}): MFMA against one workgroup per solve")
-            result[key] = many_rhs_solves(hbj, wl, mt, 64, prec, nm)
+            result[key] = many_rhs_solves(hbj, wl, mt, 64, prec)
             r = result[key]
             log(f"[bench]   MFMA {r['mfma']['ms_per_apply']:.1f} ms ({r['mfma']['TFLOP/s']:.1f} TFLOP/s), "
                 f"one per workgroup {r['one_solve_per_workgroup']['ms_per_apply']:.1f} ms")
 
-    if not args.no_cpu:
-        log("[bench] CPU oracle sample")
-        result["cpu_baseline"] = cpu_baseline(wl, m, f, st.iters, args.cpu_seconds)
+    del mt, ft, u, u_main, u_ref
+    torch.cuda.empty_cache()
+    if not args.no_multi:
+        result["multi_source_2048"] = multi_source_leg(hbj)
+    if not args.no_gradient and nsrc == 1:
+        result["gradient_512"] = gradient_leg(hbj)
+
+    if cpu is not None:
+        result["cpu_baseline"] = cpu_entry(wl, cpu["single"], st.iters, "one process")
+        if "rows" in cpu:
+            result["cpu_baseline_row_owners"] = cpu_entry(
+                wl, cpu["rows"], st.iters, f"{cpu['rows']['cores']} row-owner processes (the paper's rank layout)")
     print(json.dumps(result), flush=True)
 
 

@@ -122,16 +122,23 @@ typedef struct {
   double  tol;           /* stop at ||b - (I-S) g|| <= tol ||b|| (Sec. 7: 1e-6)     */
   int32_t restart;       /* GMRES restart length (50)                               */
   int32_t maxit;         /* total iteration cap                                     */
-  int32_t flexible;      /* ignored: the preconditioned directions are always kept
-                            (FGMRES storage; with a fixed preconditioner the same
-                            iterates as GMRES, and the solution update needs no
-                            further preconditioner application)                  */
+  int32_t flexible;      /* 1: flexible GMRES, the preconditioned search directions
+                            z_j = P^{-1} v_j are kept and the solution update is
+                            x += Z y (the mixed-precision form, whose complex64
+                            preconditioner is applied inside an FP64 FGMRES);
+                            0: GMRES, only the Krylov basis is kept and x +=
+                            P^{-1} (V y), one more preconditioner application per
+                            restart cycle.  With a fixed preconditioner both give
+                            the same iterates (up to rounding); 1 moves less data.
+                            Default (opts = NULL): 1.  Other values: HBJ_EINVAL  */
 } hbj_solve_opts;
 
 typedef struct {
   int32_t iters;         /* GMRES iterations (max over right-hand sides)            */
   int32_t steps_per_pc;  /* sequential sweep steps per preconditioner application  */
-  int32_t local_ir_max;  /* HBJ_MIXED: max refinement steps of a local solve        */
+  int32_t local_ir_max;  /* HBJ_MIXED with banded operators: most complex64 solves
+                            spent on one refined local solve of the operator (1 +
+                            refinement steps); 0 otherwise                        */
   int32_t converged;     /* number of right-hand sides that reached tol             */
   double  relres;        /* max over right-hand sides of the final true residual    */
   double  seconds;       /* wall time of the call                                   */
@@ -140,6 +147,12 @@ typedef struct {
                             estimates relative to ||b|| of right-hand side 0,
                             entry 0 = 1.0                                          */
   int32_t res_hist_len;  /* capacity of res_hist on input, entries written on output */
+  double  local_ir_resid;/* HBJ_MIXED with banded operators: largest relative residual
+                            ||rhs - A_s x|| / ||rhs|| (FP64) left by a refined local
+                            solve; refinement stops at 1e-14 or when a step no longer
+                            halves it (at most 8 solves).  A value far above
+                            eps64 cond(A_s) flags a local problem too ill-conditioned
+                            for complex64 factors; 0 otherwise                   */
 } hbj_solve_stats;
 
 typedef struct {         /* per kernel class, accumulated while profiling is on     */
@@ -223,13 +236,20 @@ int hbj_lifting(hbj_ctx* ctx, const hbj_c128* f, hbj_c128* b, int32_t nrhs);
 int hbj_reconstruct(hbj_ctx* ctx, const hbj_c128* f, const hbj_c128* g, hbj_c128* u, int32_t nrhs);
 
 /*
- * hbj_solve - u = A^{-1} f for nrhs sources: lifting, (F)GMRES on (I - S) g = b
- * with the preconditioner, reconstruction.  The right-hand sides iterate in
- * lockstep, each with its own Krylov recurrence.  Synchronises with the host
- * once per iteration and returns after completion.
+ * hbj_solve - u = A^{-1} f for nrhs sources by the interface problem of the
+ * decomposition: the lifting b (Sec. 4, eq. (3)), the interface system
+ * (I - S) g = b (Sec. 4, eq. (5)) solved by right-preconditioned GMRES with restarts
+ * to ||b - (I - S) g|| <= tol ||b|| (Sec. 7 solves it with GMRES to 1e-6), the
+ * preconditioner of the context (Sec. 5, eq. (7), or Sec. 6), and the reconstruction
+ * u_i = A_i^{-1}(f_i + B_i g) (Sec. 4).  The right-hand sides iterate in lockstep,
+ * each with its own Krylov recurrence (a column stops once it meets tol).
+ * Synchronises with the host once per iteration and returns after completion.
  *   f, u   device [nrhs][ny][nx] (may not alias); opts host (NULL = defaults
- *          tol 1e-6, restart 50, maxit 1000); stats host or NULL.
- * Returns HBJ_NOT_CONVERGED (u = last iterate) when maxit is reached.
+ *          tol 1e-6, restart 50, maxit 1000, flexible 1); stats host or NULL.
+ * Errors: HBJ_ESTATE before hbj_factor; HBJ_EINVAL for nrhs < 1, tol <= 0,
+ * restart < 1, maxit < 0 or flexible not 0 / 1; HBJ_ENOMEM (the Krylov workspace,
+ * kept for later calls with the same sizes).  Returns HBJ_NOT_CONVERGED (u = last
+ * iterate, stats filled) when maxit is reached.
  */
 int hbj_solve(hbj_ctx* ctx, const hbj_c128* f, hbj_c128* u, int32_t nrhs,
               const hbj_solve_opts* opts, hbj_solve_stats* stats);
@@ -249,6 +269,19 @@ int hbj_solve(hbj_ctx* ctx, const hbj_c128* f, hbj_c128* u, int32_t nrhs,
 int hbj_gradient(hbj_ctx* ctx, const hbj_c128* f, int32_t nsrc, const int32_t* rec_idx, int32_t nrec,
                  const hbj_c128* d, double* grad_m, double* loss, hbj_c128* u_out,
                  const hbj_solve_opts* opts, hbj_solve_stats* stats);
+
+/*
+ * hbj_volume_residual - relative residual of the global discrete problem (Sec. 3, eq. (1)):
+ * relres[k] = ||f_k - A u_k|| / ||f_k|| (||A u_k|| when f_k = 0), A the 5-point operator on the
+ * whole grid with the absorbing condition on the outer faces.  It does not involve the
+ * decomposition, so it measures how well a field from hbj_solve solves the original problem.
+ * Needs hbj_setup only (not hbj_factor).  Synchronises with the host.
+ *   f, u    device [nrhs][ny][nx] hbj_c128
+ *   relres  HOST [nrhs]
+ * Errors: HBJ_EINVAL (null pointers, nrhs < 1), HBJ_ENOMEM (its small reduction workspace, kept
+ * for later calls), HBJ_EHIP.
+ */
+int hbj_volume_residual(hbj_ctx* ctx, const hbj_c128* f, const hbj_c128* u, int32_t nrhs, double* relres);
 
 /*
  * hbj_local_solve - x_e = A_{s_e}^{-1} rhs_e for a batch of subdomains (the unit

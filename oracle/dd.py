@@ -177,6 +177,19 @@ class Decomposition:
         self.layout = Layout(n1, n2, self.snx, self.sny)
         self.nif = self.layout.nif
         self.sub = {i: Subdomain(self, i) for i in subdomains(n1, n2)}
+        # Where independent local problems are solved: None = one after the other in this process;
+        # otherwise a callable (kind, keys, data) -> [result per key] that runs the same methods
+        # (scatter_subdomain, lift_subdomain, reconstruct_subdomain) elsewhere, e.g. in processes
+        # that each own a row of subdomains as the paper's MPI ranks do (Sec. 7).  The arithmetic
+        # is the same either way.
+        self.mapper = None
+
+    def _map(self, kind, keys, data):
+        if self.mapper is not None:
+            return self.mapper(kind, keys, data)
+        fn = {"scatter": self.scatter_subdomain, "lift": self.lift_subdomain,
+              "reconstruct": self.reconstruct_subdomain}[kind]
+        return [fn(i, *data) for i in keys]
 
     # -- local solves and traces (Sec. 4) ---------------------------------
     def local_rhs(self, i, g, f_loc=None):
@@ -224,12 +237,26 @@ class Decomposition:
         {j: sum_k S_{m(j,i), m(i,k)} g_{m(i,k)}} over all k in D_i (Sec. 4)."""
         return self.outgoing(i, self.local_solve(i, g), g)
 
+    def scatter_many(self, keys, g):
+        """scatter_subdomain for every subdomain in keys (independent local problems)."""
+        return self._map("scatter", list(keys), (g,))
+
+    def lift_subdomain(self, i, f):
+        """Outgoing traces of the lifting w_i of the source f ([ny, nx]) of subdomain i (eq. (3))."""
+        w = self.local_solve(i, None, self.sub[i].restrict(f))
+        return self.outgoing(i, w, None)
+
+    def reconstruct_subdomain(self, i, f, g):
+        """u_i = A_i^{-1}(f_i + B_i g) of subdomain i, in local order."""
+        return self.local_solve(i, g, self.sub[i].restrict(f))
+
     # -- global interface operators ----------------------------------------
     def apply_S(self, g):
         """S g: every block m(j,i) receives the scattered data of its sender i (Sec. 4)."""
         out = np.zeros(self.nif, dtype=np.complex128)
-        for i in self.sub:
-            for j, v in self.scatter_subdomain(i, g).items():
+        keys = list(self.sub)
+        for i, sc in zip(keys, self.scatter_many(keys, g)):
+            for j, v in sc.items():
                 out[self.layout.block(j, i)] = v
         return out
 
@@ -240,17 +267,18 @@ class Decomposition:
     def lifting(self, f):
         """b_{m(j,i)} = (-d_{n_ij} - T) w_i with w_i the lifting of the source (Sec. 4, eq. (3))."""
         b = np.zeros(self.nif, dtype=np.complex128)
-        for i, s in self.sub.items():
-            w = self.local_solve(i, None, s.restrict(f))
-            for j, v in self.outgoing(i, w, None).items():
+        keys = list(self.sub)
+        for i, out in zip(keys, self._map("lift", keys, (f,))):
+            for j, v in out.items():
                 b[self.layout.block(j, i)] = v
         return b
 
     def reconstruct(self, f, g):
         """u_i = A_i^{-1}(f_i + B_i g) on every subdomain, assembled into a global [ny, nx] field."""
         u = np.zeros((self.grid.ny, self.grid.nx), dtype=np.complex128)
-        for i, s in self.sub.items():
-            ui = self.local_solve(i, g, s.restrict(f))
+        keys = list(self.sub)
+        for i, ui in zip(keys, self._map("reconstruct", keys, (f, g))):
+            s = self.sub[i]
             u[s.y0:s.y0 + s.sny, s.x0:s.x0 + s.snx] = ui.reshape(s.sny, s.snx)
         return u
 
@@ -281,9 +309,6 @@ class Decomposition:
             e[c] = 1
             S[:, c] = self.apply_S(e)
         return S
-
-    def group_antidiagonals(self):
-        return list(range(2, self.layout.n_g + 2))
 
     def subdomains_on(self, a):
         return [i for i in self.sub if norm1(i) == a]

@@ -14,10 +14,6 @@ from .fd import Grid, direct_solve
 from .krylov import gmres
 
 
-def make_grid(nx, ny, h, k, m):
-    return Grid(nx, ny, h, k, m)
-
-
 class DDResult:
     def __init__(self, u, g, gm):
         self.u, self.g, self.gmres = u, g, gm
@@ -50,7 +46,20 @@ def direct(grid: Grid, f):
 
 
 def volume_residual(grid: Grid, u, f):
-    """||f - A u|| / ||f|| on the global grid."""
+    """||f - A u|| / ||f|| on the global grid (the residual of eq. (1) discretised, Sec. 3),
+    per right-hand side: u and f are [ny, nx] (returns a float) or [nrhs, ny, nx] (returns an
+    array of nrhs floats).
+
+    Pins (tests/test_oracle_fd.py): zero to round-off for the direct solution; a known value
+    for a single perturbed entry of f; A u against a node-by-node evaluation of the 5-point
+    stencil with the absorbing ghost values."""
     A = grid.matrix()
-    r = f.ravel() - A @ u.ravel()
-    return np.linalg.norm(r) / np.linalg.norm(f.ravel())
+    u = np.asarray(u, dtype=np.complex128)
+    f = np.asarray(f, dtype=np.complex128)
+    if u.ndim == 2:
+        r = f.ravel() - A @ u.ravel()
+        return float(np.linalg.norm(r) / np.linalg.norm(f.ravel()))
+    U = u.reshape(u.shape[0], -1).T
+    F = f.reshape(f.shape[0], -1).T
+    R = F - A @ U
+    return np.linalg.norm(R, axis=0) / np.linalg.norm(F, axis=0)

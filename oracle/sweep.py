@@ -45,15 +45,17 @@ class SweepStats:
         self.local_solves = 0
 
 
-def _sweep_step(dd, src, dst, antidiag, direction, stats):
-    """Solve every subdomain on ``antidiag`` with incoming data from ``src`` and add its
-    outgoing traces into ``dst`` toward anti-diagonal antidiag + direction."""
+def _sweep_step(dd, src, dst, antidiags, direction, stats):
+    """One lockstep step: solve every subdomain on the anti-diagonals ``antidiags`` (one per
+    interval) with incoming data from ``src`` and add its outgoing traces into ``dst`` toward
+    anti-diagonal a + direction.  The subdomains of a step read only their own groups, which no
+    subdomain of the same step writes, so they are independent local problems."""
     lay = dd.layout
-    for i in dd.subdomains_on(antidiag):
+    keys = [i for a in antidiags for i in dd.subdomains_on(a)]
+    for i, out in zip(keys, dd.scatter_many(keys, src)):
         stats.local_solves += 1
-        out = dd.scatter_subdomain(i, src)
         for j, v in out.items():
-            if j[0] + j[1] == antidiag + direction:
+            if j[0] + j[1] == i[0] + i[1] + direction:
                 dst[lay.block(j, i)] += v
 
 
@@ -69,11 +71,8 @@ def forward_pass(dd, r, blocks, combine="restricted", stats=None):
     extra = np.zeros_like(r)
     nsteps = max(e - s for s, e in blocks)
     for t in range(1, nsteps + 1):
-        for (s, e) in blocks:
-            if s + t > e:
-                continue
-            src = r if t == 1 else y
-            _sweep_step(dd, src, y, s + t - 1, +1, stats)
+        src = r if t == 1 else y
+        _sweep_step(dd, src, y, [s + t - 1 for (s, e) in blocks if s + t <= e], +1, stats)
         stats.steps += 1
     if combine == "additive":
         for b, (s, e) in enumerate(blocks):
@@ -92,11 +91,8 @@ def backward_pass(dd, r, blocks, combine="restricted", stats=None):
     extra = np.zeros_like(r)
     nsteps = max(e - s for s, e in blocks)
     for t in range(1, nsteps + 1):
-        for (s, e) in blocks:
-            if e - t < s:
-                continue
-            src = r if t == 1 else z
-            _sweep_step(dd, src, z, e - t + 1, -1, stats)
+        src = r if t == 1 else z
+        _sweep_step(dd, src, z, [e - t + 1 for (s, e) in blocks if e - t >= s], -1, stats)
         stats.steps += 1
     if combine == "additive":
         for b, (s, e) in enumerate(blocks):

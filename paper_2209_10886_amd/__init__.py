@@ -55,7 +55,7 @@ class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("steps_per_pc", ctypes.c_int32), ("local_ir_max", ctypes.c_int32),
                 ("converged", ctypes.c_int32), ("relres", ctypes.c_double), ("seconds", ctypes.c_double),
                 ("local_solves", ctypes.c_int64), ("res_hist", ctypes.POINTER(ctypes.c_double)),
-                ("res_hist_len", ctypes.c_int32)]
+                ("res_hist_len", ctypes.c_int32), ("local_ir_resid", ctypes.c_double)]
 
 
 class KernelStat(ctypes.Structure):
@@ -78,6 +78,7 @@ _SIGS = {
     "hbj_solve": (_I, [_P, _P, _P, _I32, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)]),
     "hbj_gradient": (_I, [_P, _P, _I32, _P, _I32, _P, _P, ctypes.POINTER(ctypes.c_double), _P,
                           ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)]),
+    "hbj_volume_residual": (_I, [_P, _P, _P, _I32, ctypes.POINTER(ctypes.c_double)]),
     "hbj_local_solve": (_I, [_P, _I32, ctypes.POINTER(_I32), _P, _P, _I32]),
     "hbj_band_factors": (_I, [_P, _I32, _P, _P]),
     "hbj_interface_len": (_I32, [_P]),
@@ -137,11 +138,12 @@ class Stats:
     local_solves: int
     history: list
     code: int
+    local_ir_resid: float = 0.0
 
 
 def _stats(st: SolveStats, hist, code) -> Stats:
     return Stats(st.iters, st.steps_per_pc, st.local_ir_max, st.converged, st.relres, st.seconds, st.local_solves,
-                 list(hist[: st.res_hist_len]), code)
+                 list(hist[: st.res_hist_len]), code, st.local_ir_resid)
 
 
 class Context:
@@ -227,7 +229,7 @@ class Context:
         _check(_lib.hbj_reconstruct(self._h, _dev(f, torch.complex128, "f"), gp, _dev(out, torch.complex128, "u"), n))
         return out
 
-    def solve(self, f, tol=1e-6, restart=50, maxit=1000, flexible=False, out=None, hist_len=4096, check=True):
+    def solve(self, f, tol=1e-6, restart=50, maxit=1000, flexible=True, out=None, hist_len=4096, check=True):
         n = self._nrhs(f, 2)
         out = torch.empty_like(f) if out is None else out
         opts = SolveOpts(tol, restart, maxit, 1 if flexible else 0)
@@ -240,7 +242,7 @@ class Context:
         _check(code, allow=() if check else (NOT_CONVERGED,))
         return out, _stats(st, hist, code)
 
-    def gradient(self, f, rec_idx, d, tol=1e-10, restart=50, maxit=2000, flexible=False, return_u=False):
+    def gradient(self, f, rec_idx, d, tol=1e-10, restart=50, maxit=2000, flexible=True, return_u=False):
         """(loss, dL/dm [ny, nx] float64[, u]) by forward + adjoint solves."""
         n = self._nrhs(f, 2)
         grad = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
@@ -253,6 +255,16 @@ class Context:
                                  ctypes.byref(loss), _dev(u, torch.complex128, "u") if u is not None else _P(0),
                                  ctypes.byref(opts), ctypes.byref(st)))
         return (loss.value, grad, u) if return_u else (loss.value, grad)
+
+    def volume_residual(self, f, u):
+        """||f - A u|| / ||f|| of the global discrete problem per right-hand side (list of floats)."""
+        n = self._nrhs(f, 2)
+        if u.shape != f.shape:
+            raise ValueError("f and u must have the same shape")
+        out = (ctypes.c_double * n)()
+        _check(_lib.hbj_volume_residual(self._h, _dev(f, torch.complex128, "f"), _dev(u, torch.complex128, "u"), n,
+                                        out))
+        return [float(x) for x in out]
 
     def local_solve(self, subs, rhs, precision=FP64, out=None):
         subs = [int(s) for s in subs]

@@ -56,13 +56,6 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
-    # diagnostic program: streaming-read ceiling and the copy kernel that calibrates counters
-    probe = os.path.join(HERE, "probe_stream")
-    cmd = [hipcc(), *FLAGS, os.path.join(CSRC, "probe_stream.hip"), "-o", probe + ".tmp"]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError(f"probe build failed: {' '.join(cmd)}\n{r.stderr}")
-    os.replace(probe + ".tmp", probe)
     if verbose:
         print(f"built {LIB}", file=sys.stderr)
     return LIB

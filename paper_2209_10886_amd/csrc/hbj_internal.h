@@ -357,6 +357,13 @@ hipError_t launch_spread_adjoint(const double2* resid, const int32_t* rec, int n
                                  int nsrc, hipStream_t st);
 hipError_t launch_grad_accumulate(const Geom& g, const double* m, const double2* u, const double2* mu, int nsrc,
                                   double* grad, hipStream_t st);
+// global residual sums of r = f - A u (|r|^2 and |f|^2 per right-hand side into sums[2 nrhs]);
+// part holds volume_residual_blocks(g) * 2 doubles per right-hand side
+int volume_residual_blocks(const Geom& g);
+hipError_t launch_volume_residual(const Geom& g, const double* m, const double2* f, const double2* u, int nrhs,
+                                  double* part, double* sums, hipStream_t st);
+// ratio[e] = ||r_e|| / ||b_e|| over the nloc entries of each of nent local vectors
+hipError_t launch_entry_ratio(const double2* r, const double2* b, int nloc, int nent, double* ratio, hipStream_t st);
 hipError_t launch_local_residual(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfBand* band,
                                  const double2* diag, const double2* rhs64, const double2* x64, double2* r64,
                                  hipStream_t st);

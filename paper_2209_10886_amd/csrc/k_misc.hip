@@ -1,4 +1,6 @@
 // Receiver sampling, adjoint sources, gradient accumulation and the FP64 local residual.
+#include <algorithm>
+
 #include "hbj_internal.h"
 
 namespace {
@@ -86,9 +88,134 @@ __global__ void k_local_residual(Geom g, const Entry* ent, const FaceTab* ft, co
   r64[(size_t)slot * g.nloc + l] = mk(b.x - ax.x, b.y - ax.y);
 }
 
+// Residual of the global discrete problem (Sec. 3, eq. (1)): r = f - A u with A the 5-point
+// operator on the whole grid, whose outer faces carry the absorbing condition (ghost value
+// rho_b u_p, rho_b = beta+/beta- with alpha_b = k sqrt(m_p)).  Workgroup (b, rhs) sums |r|^2 and
+// |f|^2 over its share of the nodes (grid-stride) and writes the two sums to
+// part[(rhs * nblk + b) * 2 + {0, 1}].
+constexpr int kVrThreads = 256;
+__global__ void __launch_bounds__(kVrThreads) k_volume_residual(Geom g, const double* m, const double2* f,
+                                                                const double2* u, int nblk, double* part) {
+  const int rhs = blockIdx.y;
+  const int npts = g.nx * g.ny;
+  const double2* ur = u + (size_t)rhs * npts;
+  const double2* fr = f + (size_t)rhs * npts;
+  const double ih2 = 1.0 / (g.h * g.h);
+  double rr = 0.0, ff = 0.0;
+  for (int t = blockIdx.x * kVrThreads + threadIdx.x; t < npts; t += nblk * kVrThreads) {
+    const int iy = t / g.nx, ix = t - iy * g.nx;
+    const double2 up = ur[t];
+    const int nout = (ix == 0) + (ix == g.nx - 1) + (iy == 0) + (iy == g.ny - 1);
+    double2 nb = mk(0.0, 0.0);
+    if (ix > 0) nb = cadd(nb, ur[t - 1]);
+    if (ix < g.nx - 1) nb = cadd(nb, ur[t + 1]);
+    if (iy > 0) nb = cadd(nb, ur[t - g.nx]);
+    if (iy < g.ny - 1) nb = cadd(nb, ur[t + g.nx]);
+    double2 d = mk(4.0 * ih2 - g.k * g.k * m[t], 0.0);
+    if (nout) {
+      const double alpha = g.k * sqrt(m[t]);
+      const double2 rho = cdiv(mk(1.0 / g.h, 0.5 * alpha), mk(1.0 / g.h, -0.5 * alpha));
+      d.x -= nout * rho.x * ih2;
+      d.y -= nout * rho.y * ih2;
+    }
+    double2 au = cmul(d, up);
+    au.x -= ih2 * nb.x;
+    au.y -= ih2 * nb.y;
+    const double2 fv = fr[t];
+    const double rx = fv.x - au.x, ry = fv.y - au.y;
+    rr += rx * rx + ry * ry;
+    ff += fv.x * fv.x + fv.y * fv.y;
+  }
+  __shared__ double sr[kVrThreads], sf[kVrThreads];
+  sr[threadIdx.x] = rr;
+  sf[threadIdx.x] = ff;
+  __syncthreads();
+  for (int w = kVrThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sr[threadIdx.x] += sr[threadIdx.x + w];
+      sf[threadIdx.x] += sf[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[((size_t)rhs * nblk + blockIdx.x) * 2 + 0] = sr[0];
+    part[((size_t)rhs * nblk + blockIdx.x) * 2 + 1] = sf[0];
+  }
+}
+
+// out[rhs * 2 + {0, 1}] = sums of the nblk partial pairs of rhs (one workgroup per rhs)
+__global__ void __launch_bounds__(kVrThreads) k_volume_residual_sum(const double* part, int nblk, double* out) {
+  const int rhs = blockIdx.x;
+  double rr = 0.0, ff = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kVrThreads) {
+    rr += part[((size_t)rhs * nblk + b) * 2 + 0];
+    ff += part[((size_t)rhs * nblk + b) * 2 + 1];
+  }
+  __shared__ double sr[kVrThreads], sf[kVrThreads];
+  sr[threadIdx.x] = rr;
+  sf[threadIdx.x] = ff;
+  __syncthreads();
+  for (int w = kVrThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sr[threadIdx.x] += sr[threadIdx.x + w];
+      sf[threadIdx.x] += sf[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[rhs * 2 + 0] = sr[0];
+    out[rhs * 2 + 1] = sf[0];
+  }
+}
+
+// ratio[e] = ||r_e|| / ||b_e|| for the local vectors of entry e (0 when b_e = 0): the relative
+// residual of each refined local solve (one workgroup per entry)
+__global__ void __launch_bounds__(kVrThreads) k_entry_ratio(const double2* r, const double2* b, int nloc,
+                                                            double* ratio) {
+  const size_t base = (size_t)blockIdx.x * nloc;
+  double rr = 0.0, bb = 0.0;
+  for (int l = threadIdx.x; l < nloc; l += kVrThreads) {
+    const double2 rv = r[base + l], bv = b[base + l];
+    rr += rv.x * rv.x + rv.y * rv.y;
+    bb += bv.x * bv.x + bv.y * bv.y;
+  }
+  __shared__ double sr[kVrThreads], sb[kVrThreads];
+  sr[threadIdx.x] = rr;
+  sb[threadIdx.x] = bb;
+  __syncthreads();
+  for (int w = kVrThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sr[threadIdx.x] += sr[threadIdx.x + w];
+      sb[threadIdx.x] += sb[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ratio[blockIdx.x] = sb[0] > 0.0 ? sqrt(sr[0] / sb[0]) : 0.0;
+}
+
 inline dim3 grid1(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 }  // namespace
+
+hipError_t launch_entry_ratio(const double2* r, const double2* b, int nloc, int nent, double* ratio, hipStream_t st) {
+  if (nent <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_entry_ratio, dim3(nent), dim3(kVrThreads), 0, st, r, b, nloc, ratio);
+  return hipGetLastError();
+}
+
+int volume_residual_blocks(const Geom& g) {
+  const int npts = g.nx * g.ny;
+  return std::max(1, std::min(1024, (npts + kVrThreads - 1) / kVrThreads));
+}
+
+hipError_t launch_volume_residual(const Geom& g, const double* m, const double2* f, const double2* u, int nrhs,
+                                  double* part, double* sums, hipStream_t st) {
+  if (nrhs <= 0) return hipSuccess;
+  const int nblk = volume_residual_blocks(g);
+  hipLaunchKernelGGL(k_volume_residual, dim3(nblk, nrhs), dim3(kVrThreads), 0, st, g, m, f, u, nblk, part);
+  hipLaunchKernelGGL(k_volume_residual_sum, dim3(nrhs), dim3(kVrThreads), 0, st, part, nblk, sums);
+  return hipGetLastError();
+}
 
 hipError_t launch_gather_receivers(const double2* u, const int32_t* rec, int nrec, int npts, const double2* d,
                                    double2* resid, int nsrc, hipStream_t st) {

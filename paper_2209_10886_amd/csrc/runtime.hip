@@ -186,7 +186,15 @@ struct hbj_ctx {
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   hbj_kernel_stat ks[HBJ_K_NCLASS]{};
   int64_t local_solves = 0;
-  int last_ir = 0;
+  int last_ir = 0;             // solves of the last refined local solve batch (mixed banded operator)
+  double last_ir_resid = 0.0;  // its largest final relative local residual
+  int ir_max = 0;              // the same, maximised over the current solve
+  double ir_resid_max = 0.0;
+  double* ir_ratio = nullptr;  // per-entry relative residuals of the refinement
+  size_t ir_ratio_cap = 0;
+  // volume residual: per-workgroup partial sums and the per-right-hand-side totals
+  double* vr_part = nullptr;
+  size_t vr_cap = 0;  // right-hand sides the buffer holds
 
   ~hbj_ctx();
 };
@@ -213,6 +221,8 @@ hbj_ctx::~hbj_ctx() {
   }
   dfree(rbl);
   dfree(df_err);
+  dfree(vr_part);
+  dfree(ir_ratio);
   for (void* p : {(void*)ft, (void*)coef, (void*)band, (void*)pos_tab, (void*)m, (void*)diag, (void*)ranges_f, (void*)ranges_b,
                   (void*)ab, (void*)ipiv, (void*)info, (void*)mf64, (void*)mb64, (void*)pf, (void*)pflag, (void*)mf32, (void*)mb32, (void*)T64, (void*)T32, (void*)Wl, (void*)lpart,
                   ybuf, (void*)nzf, (void*)Gbuf, (void*)rhs64, (void*)x64, (void*)xtr, (void*)r64, (void*)pc_y, (void*)pc_t})
@@ -1221,7 +1231,12 @@ hipError_t launch_build_rhs(const Geom& g, const Entry* ent, int nent, const Fac
 hipError_t launch_axpy_c64(double2* x64, const float2* dx, const Geom& g, const SolveLayout& L, int nent,
                            hipStream_t st);
 
-static const int kLocalRefine = 3;
+// Refinement of the operator's complex64 local solves: at most kLocalSolvesMax solves per local
+// problem; a step counts as progress when the largest relative local residual ||r|| / ||rhs||
+// falls below half of the previous one, and refinement stops once it is below kLocalResidTarget
+// (FP64 level) or stops making progress (its floor, about eps64 cond(A_s), is then reached).
+static const int kLocalSolvesMax = 8;
+static const double kLocalResidTarget = 1e-14;
 
 int op_mixed(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
   if (c->dense) return op_fp64(c, S, g, out);  // the complex128 dense operator is exact already
@@ -1231,22 +1246,42 @@ int op_mixed(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
   if (rc) return rc;
   rc = ensure_ybuf(c, nent, sizeof(float2));
   if (rc) return rc;
+  if ((size_t)nent > c->ir_ratio_cap) {
+    dfree(c->ir_ratio);
+    c->ir_ratio = nullptr;
+    c->ir_ratio_cap = 0;
+    if (dalloc(&c->ir_ratio, (size_t)nent)) return fail(HBJ_ENOMEM, "refinement workspace allocation failed");
+    c->ir_ratio_cap = nent;
+  }
   SolveIO io{};
   io.g_a = g;
   HIPCHK(launch_build_rhs(c->g, ent, nent, c->ft, c->coef, io, c->rhs64, c->st));
   HIPCHK(launch_fill_zero(c->x64, (size_t)nent * c->g.nloc * sizeof(double2), c->st));
   HIPCHK(launch_copy(c->r64, c->rhs64, (size_t)nent * c->g.nloc, c->st));
-  for (int it = 0; it <= kLocalRefine; ++it) {
+  std::vector<double> ratio(nent);
+  double prev = 1.0;
+  int nsolves = 0;
+  for (int it = 0; it < kLocalSolvesMax; ++it) {
     SolveIO lio{};
     lio.rhs64 = c->r64;
     rc = launch_solve_pair<float>(c, ent, nent, S->tiles + S->all_tile_first, S->all_tile_count, lio, c->mf32,
                                   c->mb32);
     if (rc) return rc;
     c->local_solves += nent;
+    ++nsolves;
     HIPCHK(launch_axpy_c64(c->x64, (const float2*)c->ybuf, c->g, c->L, nent, c->st));
     HIPCHK(launch_local_residual(c->g, ent, nent, c->ft, c->band, c->diag, c->rhs64, c->x64, c->r64, c->st));
+    HIPCHK(launch_entry_ratio(c->r64, c->rhs64, c->g.nloc, nent, c->ir_ratio, c->st));
+    HIPCHK(hipMemcpyAsync(ratio.data(), c->ir_ratio, nent * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    const double worst = *std::max_element(ratio.begin(), ratio.end());
+    c->last_ir_resid = worst;
+    if (worst <= kLocalResidTarget || worst > 0.5 * prev) break;
+    prev = worst;
   }
-  c->last_ir = kLocalRefine + 1;
+  c->last_ir = nsolves;
+  c->ir_max = std::max(c->ir_max, nsolves);
+  c->ir_resid_max = std::max(c->ir_resid_max, c->last_ir_resid);
   SolveIO tio{};
   tio.g_a = g;
   tio.tr_dst = out;
@@ -1648,7 +1683,15 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
           any_active |= active[k];
         }
         if (j >= 1) ++total;
-        if (j == kmax || stop_next || !any_active) break;
+        if (j == kmax || !any_active) break;
+        if (stop_next) {
+          // The provisional column j - 1 met the tolerance but the completed one did not (the
+          // delayed correction raised its subdiagonal): the cycle goes on.  Step j + 1 was not
+          // queued ahead, so it is launched now.
+          stop_next = false;
+          rc = launch_dstep(j + 1);
+          if (rc) return rc;
+        }
         // provisional column j
         bool all_done = true;
         for (int k = 0; k < ncol && all_done; ++k) {
@@ -2078,17 +2121,20 @@ int hbj_reconstruct(hbj_ctx* c, const hbj_c128* f, const hbj_c128* g, hbj_c128* 
 static int solve_impl(hbj_ctx* c, const double2* f, double2* u, int nrhs, const hbj_solve_opts* opts,
                       hbj_solve_stats* stats) {
   auto t0 = std::chrono::steady_clock::now();
-  hbj_solve_opts o{1e-6, 50, 1000, 0};
+  hbj_solve_opts o{1e-6, 50, 1000, 1};
   if (opts) o = *opts;
-  if (!(o.tol > 0.0) || o.restart < 1 || o.maxit < 0) return fail(HBJ_EINVAL, "bad solve options");
-  // The preconditioned search directions are always kept (FGMRES storage): with a fixed
+  if (!(o.tol > 0.0) || o.restart < 1 || o.maxit < 0 || (o.flexible != 0 && o.flexible != 1))
+    return fail(HBJ_EINVAL, "bad solve options");
+  // flexible = 1 keeps the preconditioned search directions (FGMRES storage): with a fixed
   // preconditioner the iterates are those of right-preconditioned GMRES, and the solution update
-  // is then one pass over them instead of one more preconditioner application.
-  o.flexible = 1;
+  // is one pass over them.  flexible = 0 stores only the Krylov basis and applies the
+  // preconditioner once more to the combination of basis vectors at the end of each cycle.
   Schedule* S;
   int rc = build_schedule(c, nrhs, &S);
   if (rc) return rc;
   const int64_t ls0 = c->local_solves;
+  c->ir_max = 0;
+  c->ir_resid_max = 0.0;
   std::vector<int> iters;
   std::vector<double> relres, hist;
   std::vector<char> conv;
@@ -2149,7 +2195,8 @@ static int solve_impl(hbj_ctx* c, const double2* f, double2* u, int nrhs, const 
   if (stats) {
     stats->iters = itmax;
     stats->steps_per_pc = hbj_steps_per_preconditioner(c);
-    stats->local_ir_max = (c->P.precision == HBJ_MIXED) ? c->last_ir : 0;
+    stats->local_ir_max = (c->P.precision == HBJ_MIXED) ? c->ir_max : 0;
+    stats->local_ir_resid = (c->P.precision == HBJ_MIXED) ? c->ir_resid_max : 0.0;
     stats->converged = nconv;
     stats->relres = rmax;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -2239,6 +2286,27 @@ int hbj_gradient(hbj_ctx* c, const hbj_c128* f, int32_t nsrc, const int32_t* rec
     stats->converged = std::min(s1.converged, s2.converged);
   }
   return (rc_fwd == HBJ_OK && rc == HBJ_OK) ? HBJ_OK : HBJ_NOT_CONVERGED;
+}
+
+int hbj_volume_residual(hbj_ctx* c, const hbj_c128* f, const hbj_c128* u, int32_t nrhs, double* relres) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  if (nrhs < 1 || !f || !u || !relres) return fail(HBJ_EINVAL, "bad arguments");
+  const int nblk = volume_residual_blocks(c->g);
+  if ((size_t)nrhs > c->vr_cap) {
+    dfree(c->vr_part);
+    c->vr_part = nullptr;
+    c->vr_cap = 0;
+    // partial pairs of every workgroup, then the nrhs totals
+    if (dalloc(&c->vr_part, (size_t)nrhs * (2 * nblk + 2))) return fail(HBJ_ENOMEM, "residual workspace allocation failed");
+    c->vr_cap = nrhs;
+  }
+  double* sums = c->vr_part + (size_t)nrhs * 2 * nblk;
+  HIPCHK(launch_volume_residual(c->g, c->m, (const double2*)f, (const double2*)u, nrhs, c->vr_part, sums, c->st));
+  std::vector<double> h(2 * (size_t)nrhs);
+  HIPCHK(hipMemcpyAsync(h.data(), sums, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  for (int k = 0; k < nrhs; ++k) relres[k] = h[2 * k + 1] > 0 ? std::sqrt(h[2 * k] / h[2 * k + 1]) : std::sqrt(h[2 * k]);
+  return HBJ_OK;
 }
 
 int hbj_local_solve(hbj_ctx* c, int32_t nbatch, const int32_t* sub_host, const hbj_c128* rhs, hbj_c128* x,

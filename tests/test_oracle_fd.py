@@ -120,3 +120,47 @@ def test_dA_dm_matches_finite_difference():
     fd = (gp.matrix().diagonal() - gm.matrix().diagonal()) / (2 * eps)
     an = g.dA_dm_diag().ravel()
     assert np.max(np.abs(fd - an) / np.abs(an)) < 1e-7
+
+
+def _stencil_by_node(nx, ny, h, k, m, u):
+    """A u evaluated node by node from the definition (Sec. 3, eq. (1) with the face template):
+    (4 u_p - sum of the in-grid neighbours)/h^2 - k^2 m_p u_p, where an outer face contributes the
+    ghost value u_q = (beta+/beta-) u_p of the absorbing condition (data 0, alpha = k sqrt(m_p))."""
+    out = np.zeros((ny, nx), dtype=np.complex128)
+    for iy in range(ny):
+        for ix in range(nx):
+            up = u[iy, ix]
+            alpha = k * np.sqrt(m[iy, ix])
+            ghost = (1.0 / h + 0.5j * alpha) / (1.0 / h - 0.5j * alpha) * up
+            s = 0.0j
+            for jy, jx in ((iy, ix - 1), (iy, ix + 1), (iy - 1, ix), (iy + 1, ix)):
+                s += u[jy, jx] if (0 <= jx < nx and 0 <= jy < ny) else ghost
+            out[iy, ix] = (4.0 * up - s) / h**2 - k * k * m[iy, ix] * up
+    return out
+
+
+def test_volume_residual_pins():
+    """oracle.solver.volume_residual: A u against the node-by-node stencil; exactly zero residual
+    for f = A u and |delta| / ||f'|| after one entry of f is perturbed by delta; round-off for the
+    direct solution; one value per right-hand side for a batch."""
+    from oracle.solver import direct, volume_residual
+
+    rng = np.random.default_rng(11)
+    nx, ny = 9, 7
+    h = 1.0 / (nx + 1)
+    m = 1.0 + 0.2 * rng.random((ny, nx))
+    g = Grid(nx, ny, h, 25.0, m)
+    u = rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
+    Au = _stencil_by_node(nx, ny, h, 25.0, m, u)
+    assert np.max(np.abs((g.matrix() @ u.ravel()).reshape(ny, nx) - Au)) <= 1e-12 * np.max(np.abs(Au))
+    assert volume_residual(g, u, Au) <= 1e-15
+    delta = 0.37 - 0.21j
+    fp = Au.copy()
+    fp[3, 4] += delta
+    assert abs(volume_residual(g, u, fp) - abs(delta) / np.linalg.norm(fp)) <= 1e-14
+    f = rng.standard_normal((2, ny, nx)) + 0j
+    ud = direct(g, f)
+    r = volume_residual(g, ud, f)
+    assert r.shape == (2,) and np.all(r < 1e-13)
+    r2 = volume_residual(g, np.stack([u, u]), np.stack([Au, fp]))
+    assert r2[0] <= 1e-15 and abs(r2[1] - abs(delta) / np.linalg.norm(fp)) <= 1e-14

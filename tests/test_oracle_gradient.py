@@ -63,3 +63,34 @@ def test_dot_product_identity():
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
     # complex symmetry: A^H v = conj(A conj(v))
     assert np.allclose(A.conj().T @ v, np.conj(A @ np.conj(v)), rtol=1e-14, atol=0)
+
+
+def test_stored_finite_differences_reproduce():
+    """tests/golden/grad_512_fd.json (written by tests/golden/make_grad_fd.py from the oracle) holds
+    the oracle's misfit at m0 +- eps dm_j for the 512^2 gradient workload; the loss at m0 and
+    direction 0 are recomputed here."""
+    import importlib.util
+    import json
+    import os
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    gold = json.load(open(os.path.join(here, "golden", "grad_512_fd.json")))
+    spec = importlib.util.spec_from_file_location("make_grad_fd", os.path.join(here, "golden", "make_grad_fd.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    import workload as W
+    from oracle import gradient, solver
+    from oracle.fd import Grid
+
+    wl, m_true, m0, f, rec = mod.problem()
+    assert gold["eps"] == mod.EPS and len(gold["directions"]) == mod.NDIR
+    u = solver.direct(Grid(wl.nx, wl.ny, wl.h, wl.k, m_true), f)
+    d = np.ascontiguousarray(u.reshape(f.shape[0], -1)[:, rec])
+    L0 = gradient.misfit(Grid(wl.nx, wl.ny, wl.h, wl.k, m0), f, rec, d)
+    assert abs(L0 - gold["loss_m0"]) <= 1e-11 * L0
+    dm = W.gradient_direction(m0.shape, 0)
+    Lp = gradient.misfit(Grid(wl.nx, wl.ny, wl.h, wl.k, m0 + mod.EPS * dm), f, rec, d)
+    e0 = gold["directions"][0]
+    assert abs(Lp - e0["loss_plus"]) <= 1e-11 * Lp
+    for e in gold["directions"]:
+        assert abs(e["fd"] - (e["loss_plus"] - e["loss_minus"]) / (2 * gold["eps"])) <= 1e-12 * abs(e["fd"])

@@ -157,6 +157,13 @@ def receiver_row(w: Workload, y_rec: float = 0.95) -> np.ndarray:
     return (iy * w.nx + np.arange(w.nx)).astype(np.int32)
 
 
+def gradient_direction(shape, j: int) -> np.ndarray:
+    """Seeded perturbation direction j of a model m for finite-difference checks of dL/dm:
+    ``default_rng(100 + j)`` normal draws scaled to max-norm 1 (float64)."""
+    d = np.random.default_rng(100 + j).standard_normal(shape)
+    return d / np.abs(d).max()
+
+
 def random_interface_vector(nif: int, seed: int, nrhs: int | None = None) -> np.ndarray:
     """Seeded complex128 test vector for operator-level parity checks."""
     rng = np.random.default_rng(seed)
