@@ -115,10 +115,16 @@ def usable_cores():
 
 def _owner_main(conn, grid_args, n1, n2):
     """Row-owner process: keeps the factors of the subdomains it is sent (one row of the
-    checkerboard) and runs the oracle's per-subdomain methods on request."""
+    checkerboard) and runs the oracle's per-subdomain methods on request, on one core."""
+    from threadpoolctl import threadpool_limits
+
     from oracle.dd import Decomposition
     from oracle.fd import Grid
 
+    # after the oracle's imports: numpy and scipy each load their own BLAS, and a limit set
+    # before scipy is loaded leaves scipy's thread pool at the machine's width (eight such
+    # processes would then oversubscribe every core)
+    threadpool_limits(1)
     dd = Decomposition(Grid(*grid_args), n1, n2)
     while True:
         msg = conn.recv()
@@ -130,13 +136,15 @@ def _owner_main(conn, grid_args, n1, n2):
 
 class RowOwners:
     """One process per row of subdomains (row i2 -> process (i2 - 1) mod nproc), as the paper
-    assigns rows to MPI ranks (Sec. 7); a mapper for oracle.dd.Decomposition."""
+    assigns rows to MPI ranks (Sec. 7); a mapper for oracle.dd.Decomposition.  The processes are
+    started fresh (spawn: no BLAS thread pool inherited from this process) and every reply is
+    awaited for at most `timeout` seconds."""
 
-    def __init__(self, grid_args, n1, n2, nproc):
+    def __init__(self, grid_args, n1, n2, nproc, timeout=120.0):
         import multiprocessing as mp
 
-        ctx = mp.get_context("fork")
-        self.nproc = nproc
+        ctx = mp.get_context("spawn")
+        self.nproc, self.timeout = nproc, timeout
         self.conns, self.procs = [], []
         for _ in range(nproc):
             a, b = ctx.Pipe()
@@ -153,15 +161,23 @@ class RowOwners:
             self.conns[o].send((kind, [i for _, i in lst], data))
         out = [None] * len(keys)
         for o, lst in by.items():
+            if not self.conns[o].poll(self.timeout):
+                raise TimeoutError(f"row-owner process {o} gave no reply within {self.timeout:.0f} s")
             for (idx, _), r in zip(lst, self.conns[o].recv()):
                 out[idx] = r
         return out
 
     def close(self):
         for c in self.conns:
-            c.send(None)
+            try:
+                c.send(None)
+            except (BrokenPipeError, OSError):
+                pass
         for p in self.procs:
             p.join(timeout=10)
+            if p.is_alive():
+                p.terminate()
+                p.join(timeout=5)
 
 
 def time_oracle(dd, f, target_s):
@@ -175,6 +191,7 @@ def time_oracle(dd, f, target_s):
     b = dd.lifting(f)
     u = dd.reconstruct(f, b)  # same cost as the reconstruction of a solve
     t_lr = time.perf_counter() - t1
+    log(f"[bench]   oracle lifting + reconstruction {t_lr:.2f} s")
     v = b / np.linalg.norm(b)
     n_it = 0
     t2 = time.perf_counter()
@@ -184,6 +201,7 @@ def time_oracle(dd, f, target_s):
         v = w / np.linalg.norm(w)
         n_it += 1
         el = time.perf_counter() - t2
+        log(f"[bench]   oracle iteration {n_it}: {el / n_it:.2f} s each")
         if el * (n_it + 1) / n_it > target_s or n_it >= 50:
             break
     del u
@@ -191,37 +209,47 @@ def time_oracle(dd, f, target_s):
 
 
 def cpu_baselines(wl, m, f, target_s):
-    """Per-iteration and lifting+reconstruction costs of the oracle: one process, and one process
-    per row of subdomains.  Returns the raw timings; the solves/s figures use the GPU's
-    iteration count once it is known."""
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    """Per-iteration and lifting+reconstruction costs of the oracle: one process on one core, and
+    one process per row of subdomains.  Returns the raw timings; the solves/s figures use the GPU's
+    iteration count once it is known.  The row-owner variant is dropped (with a note) if its
+    processes fail or stall."""
+    from threadpoolctl import threadpool_limits
+
     from oracle.dd import Decomposition
     from oracle.fd import Grid
 
     grid_args = (wl.nx, wl.ny, wl.h, wl.k, m)
-    t0 = time.perf_counter()
-    dd = Decomposition(Grid(*grid_args), wl.n1, wl.n2)
-    for s in dd.sub.values():
-        _ = s.lu  # sparse LU of every subdomain (setup, not timed)
-    t_factor = time.perf_counter() - t0
-    log(f"[bench] CPU oracle, one process: factorisation {t_factor:.1f} s")
-    t_lr, t_it, n_it = time_oracle(dd, f, target_s)
-    out = {"single": {"t_lr": t_lr, "t_it": t_it, "n_it": n_it, "t_factor": t_factor, "cores": 1}}
-    del dd
+    out = {}
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        dd = Decomposition(Grid(*grid_args), wl.n1, wl.n2)
+        for s in dd.sub.values():
+            _ = s.lu  # sparse LU of every subdomain (setup, not timed)
+        t_factor = time.perf_counter() - t0
+        log(f"[bench] CPU oracle, one process: factorisation {t_factor:.1f} s")
+        t_lr, t_it, n_it = time_oracle(dd, f, target_s)
+        out["single"] = {"t_lr": t_lr, "t_it": t_it, "n_it": n_it, "t_factor": t_factor, "cores": 1}
+        del dd
     nproc = min(wl.n2, usable_cores())
     if nproc > 1:
         log(f"[bench] CPU oracle, {nproc} row-owner processes")
-        pool = RowOwners(grid_args, wl.n1, wl.n2, nproc)
+        pool = None
         try:
+            pool = RowOwners(grid_args, wl.n1, wl.n2, nproc)
             dd = Decomposition(Grid(*grid_args), wl.n1, wl.n2)
             dd.mapper = pool
             t0 = time.perf_counter()
             dd.lifting(f)  # factors every subdomain in its owner (setup, not timed)
             t_factor = time.perf_counter() - t0
+            log(f"[bench]   row owners: factorisation and first lifting {t_factor:.1f} s")
             t_lr, t_it, n_it = time_oracle(dd, f, target_s)
             out["rows"] = {"t_lr": t_lr, "t_it": t_it, "n_it": n_it, "t_factor": t_factor, "cores": nproc}
+        except Exception as exc:  # a failed baseline must not take the GPU measurement with it
+            log(f"[bench]   row-owner baseline dropped: {exc!r}")
+            out["rows_error"] = repr(exc)
         finally:
-            pool.close()
+            if pool is not None:
+                pool.close()
     return out
 
 
@@ -678,6 +706,8 @@ def main():
         if "rows" in cpu:
             result["cpu_baseline_row_owners"] = cpu_entry(
                 wl, cpu["rows"], st.iters, f"{cpu['rows']['cores']} row-owner processes (the paper's rank layout)")
+        elif "rows_error" in cpu:
+            result["cpu_baseline_row_owners"] = {"value": None, "error": cpu["rows_error"]}
     print(json.dumps(result), flush=True)
 
 

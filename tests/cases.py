@@ -64,6 +64,20 @@ def sub_index(wl, i):
     return (i[1] - 1) * wl.n1 + (i[0] - 1)
 
 
+def residual_rounding_bound(grid, u, f):
+    """Bound on the difference between two evaluations of ||f - A u|| / ||f|| that sum in
+    different orders: each entry of f - A u carries a rounding error of at most about
+    gamma (|f_p| + sum_q |A_pq| |u_q|) with gamma = 8 eps for the five stencil terms and the
+    subtraction (Higham, Accuracy and Stability of Numerical Algorithms, Sec. 3.1), so the two
+    relative residuals differ by at most 2 gamma || |f| + |A| |u| || / ||f||.  A residual near
+    round-off (a converged solve) can differ by much more than its own relative precision."""
+    A = abs(grid.matrix())
+    u = np.asarray(u).ravel()
+    f = np.asarray(f).ravel()
+    gamma = 8 * np.finfo(np.float64).eps
+    return 2 * gamma * np.linalg.norm(np.abs(f) + A @ np.abs(u)) / np.linalg.norm(f)
+
+
 def rel(a, b):
     a = np.asarray(a)
     b = np.asarray(b)

@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import workload as W
-from cases import rel, say
+from cases import rel, residual_rounding_bound, say
 
 pytestmark = pytest.mark.gpu
 
@@ -91,9 +91,12 @@ def test_fullsize_solve_matches_direct_solution(full, hbj):
     e = rel(_np(u), ud)
     vr_o = solver.volume_residual(dd.grid, _np(u), f)
     vr_g = ctx.volume_residual(ft, u)[0]
-    say(f"  error vs direct solution {e:.2e}; volume residual oracle {vr_o:.2e} library {vr_g:.2e}")
+    bound = residual_rounding_bound(dd.grid, _np(u), f)
+    say(f"  error vs direct solution {e:.2e}; volume residual oracle {vr_o:.2e} library {vr_g:.2e} "
+        f"(rounding bound of their difference {bound:.1e})")
     assert e < 1e-8
-    assert abs(vr_g - vr_o) <= 1e-6 * vr_o
+    # both sum f - A u in their own order; at a converged field the residual is near round-off
+    assert abs(vr_g - vr_o) <= bound
     del ud
     say("[fullsize] FP64 solve, tol 1e-6, against the oracle's DD-GMRES")
     _, st6 = ctx.solve(ft, tol=1e-6)

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import workload as W
-from cases import CASES, gpu_context, oracle_problem, rel, say
+from cases import CASES, gpu_context, oracle_problem, rel, residual_rounding_bound, say
 
 pytestmark = pytest.mark.gpu
 
@@ -62,7 +62,7 @@ def test_volume_residual_of_solves_and_bad_arguments(hbj):
         r = ctx.volume_residual(ft, u)[0]
         ro = solver.volume_residual(g, _np(u), f)
         say(f"  tol {tol:g}: iters {st.iters}, volume residual gpu {r:.3e} oracle {ro:.3e}")
-        assert abs(r - ro) <= 1e-12 * max(ro, 1e-300) + 1e-15
+        assert abs(r - ro) <= residual_rounding_bound(g, _np(u), f)
         if prev is not None:
             assert r < prev
         prev = r
