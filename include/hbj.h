@@ -284,6 +284,25 @@ int hbj_gradient(hbj_ctx* ctx, const hbj_c128* f, int32_t nsrc, const int32_t* r
 int hbj_volume_residual(hbj_ctx* ctx, const hbj_c128* f, const hbj_c128* u, int32_t nrhs, double* relres);
 
 /*
+ * hbj_volume_residual_noalloc - the same relative residual as hbj_volume_residual, for callers
+ * that cannot allocate memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  It calls no allocating routine: the per-workgroup partial sums go to a
+ * static scratch array of the library (1 MiB per device, holding up to HBJ_VR_NOALLOC_MAX_RHS
+ * right-hand sides; each device holds it until the process ends), and the result stays on the
+ * device.  Asynchronous: enqueued on the context's stream, no host synchronisation.
+ *   f, u    device [nrhs][ny][nx] hbj_c128
+ *   relres  DEVICE [nrhs] float64, written in stream order
+ * Every call on one device shares that device's scratch array, which keeps the last call's
+ * partial sums (each call writes every partial it reads, so nothing needs clearing): calls that
+ * overlap on one device (two streams, two contexts, two host threads) race and give undefined
+ * results.  Errors: HBJ_EINVAL (null pointers, nrhs < 1 or nrhs > HBJ_VR_NOALLOC_MAX_RHS; nothing
+ * is enqueued), HBJ_ESTATE (the scratch address of the context's device is resolved by
+ * hbj_setup; a failure there is reported by hbj_setup), HBJ_EHIP.
+ */
+#define HBJ_VR_NOALLOC_MAX_RHS 64
+int hbj_volume_residual_noalloc(hbj_ctx* ctx, const hbj_c128* f, const hbj_c128* u, int32_t nrhs, double* relres);
+
+/*
  * hbj_local_solve - x_e = A_{s_e}^{-1} rhs_e for a batch of subdomains (the unit
  * of work of every operator above), using the factored band.
  *   sub_host  HOST [nbatch] int32 subdomain indices s = (i2-1) n1 + (i1-1)

@@ -35,6 +35,7 @@ SWEEP_STEPPED, SWEEP_DATAFLOW = 0, 1
 ORTH_CGS2, ORTH_DCGS2 = 0, 1  # Gram-Schmidt variant of the Arnoldi steps
 MSOLVE_CHAINS, MSOLVE_MFMA = 0, 1  # banded solves of many right-hand sides per subdomain
 OK, EINVAL, ESTATE, EHIP, ENOMEM, EWAIT, ZERO_PIVOT, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, 1, 2
+VR_NOALLOC_MAX_RHS = 64  # right-hand sides the allocation-free residual's static scratch holds
 K_FWD, K_BWD, K_FACTOR, K_KRYLOV, K_SCATTER, K_SWEEP, K_LIFT, K_OPERATOR = 0, 1, 2, 3, 4, 5, 6, 7
 
 
@@ -79,6 +80,7 @@ _SIGS = {
     "hbj_gradient": (_I, [_P, _P, _I32, _P, _I32, _P, _P, ctypes.POINTER(ctypes.c_double), _P,
                           ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats)]),
     "hbj_volume_residual": (_I, [_P, _P, _P, _I32, ctypes.POINTER(ctypes.c_double)]),
+    "hbj_volume_residual_noalloc": (_I, [_P, _P, _P, _I32, _P]),
     "hbj_local_solve": (_I, [_P, _I32, ctypes.POINTER(_I32), _P, _P, _I32]),
     "hbj_band_factors": (_I, [_P, _I32, _P, _P]),
     "hbj_interface_len": (_I32, [_P]),
@@ -265,6 +267,18 @@ class Context:
         _check(_lib.hbj_volume_residual(self._h, _dev(f, torch.complex128, "f"), _dev(u, torch.complex128, "u"), n,
                                         out))
         return [float(x) for x in out]
+
+    def volume_residual_noalloc(self, f, u, out):
+        """The same residuals into the caller's device tensor out [nrhs] float64, through the
+        library's static scratch (no allocation, no host synchronisation)."""
+        n = self._nrhs(f, 2)
+        if u.shape != f.shape:
+            raise ValueError("f and u must have the same shape")
+        if out.numel() < n:
+            raise ValueError("out holds fewer than nrhs entries")
+        _check(_lib.hbj_volume_residual_noalloc(self._h, _dev(f, torch.complex128, "f"), _dev(u, torch.complex128, "u"),
+                                                n, _dev(out, torch.float64, "relres")))
+        return out
 
     def local_solve(self, subs, rhs, precision=FP64, out=None):
         subs = [int(s) for s in subs]

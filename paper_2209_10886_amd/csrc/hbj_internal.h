@@ -362,6 +362,13 @@ hipError_t launch_grad_accumulate(const Geom& g, const double* m, const double2*
 int volume_residual_blocks(const Geom& g);
 hipError_t launch_volume_residual(const Geom& g, const double* m, const double2* f, const double2* u, int nrhs,
                                   double* part, double* sums, hipStream_t st);
+// the allocation-free variant: partial pairs in the library's static per-device scratch (its
+// address resolved once per device, with that device current, by volume_residual_scratch_init),
+// relres[nrhs] left on the device; hipErrorInvalidValue for nrhs outside 1..HBJ_VR_NOALLOC_MAX_RHS,
+// hipErrorNotInitialized when the scratch address of dev was never resolved
+hipError_t volume_residual_scratch_init(int dev);
+hipError_t launch_volume_residual_noalloc(int dev, const Geom& g, const double* m, const double2* f,
+                                          const double2* u, int nrhs, double* relres, hipStream_t st);
 // ratio[e] = ||r_e|| / ||b_e|| over the nloc entries of each of nent local vectors
 hipError_t launch_entry_ratio(const double2* r, const double2* b, int nloc, int nent, double* ratio, hipStream_t st);
 hipError_t launch_local_residual(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfBand* band,

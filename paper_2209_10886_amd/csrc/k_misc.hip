@@ -1,5 +1,7 @@
 // Receiver sampling, adjoint sources, gradient accumulation and the FP64 local residual.
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "hbj_internal.h"
 
@@ -94,6 +96,7 @@ __global__ void k_local_residual(Geom g, const Entry* ent, const FaceTab* ft, co
 // |f|^2 over its share of the nodes (grid-stride) and writes the two sums to
 // part[(rhs * nblk + b) * 2 + {0, 1}].
 constexpr int kVrThreads = 256;
+constexpr int kVrMaxBlocks = 1024;  // workgroups per right-hand side of k_volume_residual
 __global__ void __launch_bounds__(kVrThreads) k_volume_residual(Geom g, const double* m, const double2* f,
                                                                 const double2* u, int nblk, double* part) {
   const int rhs = blockIdx.y;
@@ -143,8 +146,9 @@ __global__ void __launch_bounds__(kVrThreads) k_volume_residual(Geom g, const do
   }
 }
 
-// out[rhs * 2 + {0, 1}] = sums of the nblk partial pairs of rhs (one workgroup per rhs)
-__global__ void __launch_bounds__(kVrThreads) k_volume_residual_sum(const double* part, int nblk, double* out) {
+// Sums of the nblk partial pairs of right-hand side rhs = blockIdx.x (one workgroup per rhs); the
+// result is valid in thread 0.
+__device__ inline void sum_partial_pairs(const double* part, int nblk, double* rr_out, double* ff_out) {
   const int rhs = blockIdx.x;
   double rr = 0.0, ff = 0.0;
   for (int b = threadIdx.x; b < nblk; b += kVrThreads) {
@@ -162,11 +166,37 @@ __global__ void __launch_bounds__(kVrThreads) k_volume_residual_sum(const double
     }
     __syncthreads();
   }
+  *rr_out = sr[0];
+  *ff_out = sf[0];
+}
+
+// out[rhs * 2 + {0, 1}] = sums of the nblk partial pairs of rhs (one workgroup per rhs)
+__global__ void __launch_bounds__(kVrThreads) k_volume_residual_sum(const double* part, int nblk, double* out) {
+  double rr, ff;
+  sum_partial_pairs(part, nblk, &rr, &ff);
   if (threadIdx.x == 0) {
-    out[rhs * 2 + 0] = sr[0];
-    out[rhs * 2 + 1] = sf[0];
+    out[blockIdx.x * 2 + 0] = rr;
+    out[blockIdx.x * 2 + 1] = ff;
   }
 }
+
+// relres[rhs] = sqrt(|r|^2 / |f|^2) from the partial pairs of rhs (sqrt(|r|^2) when f = 0), left on
+// the device: the second stage of the allocation-free variant
+__global__ void __launch_bounds__(kVrThreads) k_volume_residual_ratio(const double* part, int nblk,
+                                                                     double* relres) {
+  double rr, ff;
+  sum_partial_pairs(part, nblk, &rr, &ff);
+  if (threadIdx.x == 0) relres[blockIdx.x] = ff > 0.0 ? sqrt(rr / ff) : sqrt(rr);
+}
+
+// Scratch of the allocation-free volume residual: the partial pairs of every workgroup for at
+// most HBJ_VR_NOALLOC_MAX_RHS right-hand sides (1 MiB).  Each device holds its own copy until the
+// process ends.  Host code never passes this name to a kernel: it uses the device address that
+// hipGetSymbolAddress returned for the device (volume_residual_scratch_init).
+static __device__ __align__(256) double scratch[(size_t)HBJ_VR_NOALLOC_MAX_RHS * kVrMaxBlocks * 2];
+
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;  // device ordinal -> address of that device's scratch
 
 // ratio[e] = ||r_e|| / ||b_e|| for the local vectors of entry e (0 when b_e = 0): the relative
 // residual of each refined local solve (one workgroup per entry)
@@ -205,7 +235,7 @@ hipError_t launch_entry_ratio(const double2* r, const double2* b, int nloc, int 
 
 int volume_residual_blocks(const Geom& g) {
   const int npts = g.nx * g.ny;
-  return std::max(1, std::min(1024, (npts + kVrThreads - 1) / kVrThreads));
+  return std::max(1, std::min(kVrMaxBlocks, (npts + kVrThreads - 1) / kVrThreads));
 }
 
 hipError_t launch_volume_residual(const Geom& g, const double* m, const double2* f, const double2* u, int nrhs,
@@ -214,6 +244,32 @@ hipError_t launch_volume_residual(const Geom& g, const double* m, const double2*
   const int nblk = volume_residual_blocks(g);
   hipLaunchKernelGGL(k_volume_residual, dim3(nblk, nrhs), dim3(kVrThreads), 0, st, g, m, f, u, nblk, part);
   hipLaunchKernelGGL(k_volume_residual_sum, dim3(nrhs), dim3(kVrThreads), 0, st, part, nblk, sums);
+  return hipGetLastError();
+}
+
+hipError_t volume_residual_scratch_init(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr.count(dev)) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = static_cast<double*>(p);
+  return hipSuccess;
+}
+
+hipError_t launch_volume_residual_noalloc(int dev, const Geom& g, const double* m, const double2* f,
+                                          const double2* u, int nrhs, double* relres, hipStream_t st) {
+  if (nrhs <= 0 || nrhs > HBJ_VR_NOALLOC_MAX_RHS) return hipErrorInvalidValue;
+  double* part = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) part = it->second;
+  }
+  if (!part) return hipErrorNotInitialized;
+  const int nblk = volume_residual_blocks(g);
+  hipLaunchKernelGGL(k_volume_residual, dim3(nblk, nrhs), dim3(kVrThreads), 0, st, g, m, f, u, nblk, part);
+  hipLaunchKernelGGL(k_volume_residual_ratio, dim3(nrhs), dim3(kVrThreads), 0, st, part, nblk, relres);
   return hipGetLastError();
 }
 

@@ -195,6 +195,7 @@ struct hbj_ctx {
   // volume residual: per-workgroup partial sums and the per-right-hand-side totals
   double* vr_part = nullptr;
   size_t vr_cap = 0;  // right-hand sides the buffer holds
+  int dev = 0;        // device current at hbj_setup (the allocation-free residual's scratch)
 
   ~hbj_ctx();
 };
@@ -1834,6 +1835,8 @@ int hbj_setup(const hbj_problem* prob, const double* c_dev, void* stream, hbj_ct
   std::unique_ptr<hbj_ctx> c(new hbj_ctx());
   c->P = P;
   c->st = (hipStream_t)stream;
+  HIPCHK(hipGetDevice(&c->dev));
+  HIPCHK(volume_residual_scratch_init(c->dev));
   Geom& g = c->g;
   g.nx = P.nx;
   g.ny = P.ny;
@@ -2306,6 +2309,19 @@ int hbj_volume_residual(hbj_ctx* c, const hbj_c128* f, const hbj_c128* u, int32_
   HIPCHK(hipMemcpyAsync(h.data(), sums, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
   for (int k = 0; k < nrhs; ++k) relres[k] = h[2 * k + 1] > 0 ? std::sqrt(h[2 * k] / h[2 * k + 1]) : std::sqrt(h[2 * k]);
+  return HBJ_OK;
+}
+
+int hbj_volume_residual_noalloc(hbj_ctx* c, const hbj_c128* f, const hbj_c128* u, int32_t nrhs, double* relres) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  if (!f || !u || !relres) return fail(HBJ_EINVAL, "null argument");
+  if (nrhs < 1 || nrhs > HBJ_VR_NOALLOC_MAX_RHS)
+    return fail(HBJ_EINVAL, "nrhs must be between 1 and HBJ_VR_NOALLOC_MAX_RHS (" +
+                                std::to_string(HBJ_VR_NOALLOC_MAX_RHS) + ") for the allocation-free residual");
+  const hipError_t e = launch_volume_residual_noalloc(c->dev, c->g, c->m, (const double2*)f, (const double2*)u, nrhs,
+                                                      relres, c->st);
+  if (e == hipErrorNotInitialized) return fail(HBJ_ESTATE, "scratch of the context's device not resolved");
+  if (e != hipSuccess) return fail(HBJ_EHIP, std::string("volume residual launch: ") + hipGetErrorString(e));
   return HBJ_OK;
 }
 
