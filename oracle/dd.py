@@ -40,11 +40,20 @@ Sigma = M B-^{-1} M - B- (R = diag(rho), Sigma = diag(sigma) when C = 0).  The o
 faces keep the first-order absorbing condition, so the global problem, and with it the
 solution, do not depend on the transmission order; only the convergence does.
 
+Pade transmission (transmission=3, the paper's own condition, Sec. 7): on interface faces the
+impedance alpha of the face template becomes the dense symmetric matrix X of oracle.habc (the
+rotated Pade approximation of the one-way operator with N_pade auxiliary fields eliminated), so
+the ghost values are u_q = Q (g + beta+ u_p) with Q = (I/h - (i/2) X)^{-1}: the face nodes' rows
+gain the dense block -rho / h^2, the incoming data enter as (Q / h^2) g, and the data sent across
+are -rho g - sigma u_p, all n x n matrices along the face (oracle.habc.face_maps).  The local
+matrix stays complex symmetric; it is no longer banded along the vertical faces.
+
 Pins (tests/test_oracle_dd.py): the reconstructed u equals the global direct
 solve to round-off on every decomposition (1 x 1 included); the traces of the
 global solution satisfy (I - S) g = b exactly; the dense S has the group
 structure of Sec. 5; GMRES agrees with a dense solve of (I - S) g = b; for the
-second-order transmission the same identities and A = A^T.
+second-order transmission the same identities and A = A^T (tests/test_oracle_habc.py
+for the Pade transmission).
 """
 from __future__ import annotations
 
@@ -52,6 +61,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+from . import habc
 from .fd import Grid, robin_coeffs
 from .layout import Layout, neighbours, norm1, subdomains
 
@@ -105,6 +115,12 @@ class Subdomain:
                 self.alpha[f] = g.k * np.sqrt(mp)
         # second-order transmission: zeroth-order impedance alpha a on interface faces
         a0, b0 = (dd.tcoef if dd.transmission == 2 else (1.0, 0.0))
+        # Pade transmission: the dense face maps of every interface face
+        self.pade = {}
+        if dd.transmission == 3:
+            npade, phi = dd.tcoef
+            for f in self.nbr:
+                self.pade[f] = habc.face_maps(np.real(self.alpha[f]), g.h, npade, phi)
         self.coef = {f: robin_coeffs(self.alpha[f] * (a0 if f in self.nbr else 1.0), g.h) for f in FACES}
         # tangential operator C of every interface face (zero for first-order transmission)
         self.tang = {}
@@ -130,10 +146,18 @@ class Subdomain:
         n = snx * sny
         diag = (4.0 / h**2 - k * k * self.m_loc.ravel()).astype(np.complex128)
         for f in FACES:
+            if f in self.pade:
+                continue
             rho = self.coef[f][2]
             np.add.at(diag, self.edge[f], -rho / h**2)
         idx = np.arange(n).reshape(sny, snx)
         rows, cols, vals = [np.arange(n)], [np.arange(n)], [diag]
+        # Pade transmission: the dense block -rho / h^2 on the nodes of each interface face
+        for f, P in self.pade.items():
+            e = self.edge[f]
+            rows.append(np.repeat(e, e.size))
+            cols.append(np.tile(e, e.size))
+            vals.append((-P["rho"] / h**2).ravel())
         off = -1.0 / h**2
         for a, b in ((idx[:, :-1].ravel(), idx[:, 1:].ravel()), (idx[:-1, :].ravel(), idx[1:, :].ravel())):
             rows += [a, b]
@@ -167,12 +191,15 @@ class Decomposition:
     def __init__(self, grid: Grid, n1: int, n2: int, transmission: int = 1, tcoef=None):
         if grid.nx % n1 or grid.ny % n2:
             raise ValueError("grid size must be divisible by the decomposition")
-        if transmission not in (1, 2):
-            raise ValueError("transmission order must be 1 or 2")
+        if transmission not in (1, 2, 3):
+            raise ValueError("transmission must be 1 (Robin), 2 (second order) or 3 (Pade)")
         self.grid, self.n1, self.n2 = grid, n1, n2
         self.transmission = transmission
-        # (a, b) of the second-order condition d_n u - i alpha a u - (i b / alpha) d_tt u = g
-        self.tcoef = tcoef if tcoef is not None else SECOND_ORDER
+        # (a, b) of the second-order condition d_n u - i alpha a u - (i b / alpha) d_tt u = g;
+        # (N_pade, phi) of the Pade condition
+        if tcoef is None:
+            tcoef = habc.PADE_DEFAULT if transmission == 3 else SECOND_ORDER
+        self.tcoef = tcoef
         self.snx, self.sny = grid.nx // n1, grid.ny // n2
         self.layout = Layout(n1, n2, self.snx, self.sny)
         self.nif = self.layout.nif
@@ -198,8 +225,11 @@ class Decomposition:
         r = np.zeros(s.snx * s.sny, dtype=np.complex128) if f_loc is None else np.array(f_loc, dtype=np.complex128)
         if g is not None:
             for f, j in s.nbr.items():
-                inj = s.coef[f][4]
-                r[s.edge[f]] += inj * g[self.layout.block(i, j)]
+                if f in s.pade:
+                    r[s.edge[f]] += s.pade[f]["inj"] @ g[self.layout.block(i, j)]
+                else:
+                    inj = s.coef[f][4]
+                    r[s.edge[f]] += inj * g[self.layout.block(i, j)]
         return r
 
     def local_solve(self, i, g, f_loc=None):
@@ -209,6 +239,8 @@ class Decomposition:
     def face_maps(self, i, f):
         """R and Sigma of face f of subdomain i (out = -R g - Sigma u_line along the face)."""
         s = self.sub[i]
+        if f in s.pade:
+            return s.pade[f]["rho"], s.pade[f]["sigma"]
         bm, bp = s.coef[f][0], s.coef[f][1]
         M = np.diag(bp) + bm[:, None] * s.tang[f]
         R = M / bm[None, :]
@@ -224,7 +256,10 @@ class Decomposition:
         out = {}
         for f, j in s.nbr.items():
             gin = np.zeros(s.edge[f].size, np.complex128) if g is None else g[self.layout.block(i, j)]
-            if not s.tang[f].any():
+            if f in s.pade:
+                P = s.pade[f]
+                out[j] = -P["rho"] @ gin - P["sigma"] @ u_loc[s.edge[f]]
+            elif not s.tang[f].any():
                 _, _, rho, sigma, _ = s.coef[f]
                 out[j] = -rho * gin - sigma * u_loc[s.edge[f]]
             else:
@@ -295,6 +330,9 @@ class Decomposition:
                 fq = {"W": "E", "E": "W", "S": "N", "N": "S"}[f]
                 up = uloc[s.edge[f]]
                 uq = t.restrict(u)[t.edge[fq]]
+                if f in s.pade:  # (u_q - u_p)/h - (i/2) X (u_p + u_q) = bm u_q - bp u_p with matrices
+                    g[self.layout.block(i, j)] = s.pade[f]["bm"] @ uq - s.pade[f]["bp"] @ up
+                    continue
                 bm, bp = s.coef[f][0], s.coef[f][1]  # (u_q - u_p)/h - i alpha a (u_p + u_q)/2 = bm u_q - bp u_p
                 g[self.layout.block(i, j)] = bm * uq - bp * up - bm * (s.tang[f] @ up)
         return g
