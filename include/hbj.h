@@ -115,7 +115,17 @@ typedef struct {
                             that damp the grid-scale modes).  The outer faces keep
                             the absorbing condition, so the solution does not
                             depend on it.  Any operator form; in the banded form the
-                            traces follow the solves in a second kernel            */
+                            traces follow the solves in a second kernel;
+                            3 = the Pade condition of the paper's experiments (Sec. 7:
+                            8 auxiliary fields, branch rotation pi/3): the impedance
+                            becomes the dense symmetric face matrix K^1/2 R(D) K^1/2,
+                            R the rotated Pade approximation of sqrt(1 + D), D the
+                            tangential second difference of the face (Neumann face
+                            ends), K the interface wavenumbers.  Dense operator form
+                            only (HBJ_EINVAL otherwise): the band factors keep the
+                            Robin closure and the operators, lifting and
+                            reconstruction are corrected on the edge nodes by a
+                            Woodbury identity; hbj_local_solve is not available   */
 } hbj_problem;
 
 typedef struct {

@@ -358,7 +358,8 @@ def setup(nx, ny, k, n1, n2, c=None, m=None, h=0.0, precision=FP64, precond=PC_B
           bj_combine=BJ_RESTRICTED, bj_compose=BJ_PRODUCT, operator_form=OP_BANDED, sweep_exec=SWEEP_STEPPED,
           transmission=1, device="cuda", stream=None) -> Context:
     """hbj_setup with a wave speed c (or squared slowness m) given as a [ny, nx] float64 tensor.
-    transmission: 1 (Robin) or 2 (second-order condition on interface faces), in either operator form."""
+    transmission: 1 (Robin) or 2 (second-order condition on interface faces), in either operator form;
+    3 (the Pade condition with 8 auxiliary fields and branch rotation pi/3) in the dense form."""
     prob = Problem(nx, ny, h, k, n1, n2, precision, precond, bj_width, bj_combine, bj_compose, operator_form,
                    sweep_exec, transmission)
     if c is None and m is None:

@@ -325,6 +325,9 @@ int sweep_df_occupancy(int L, bool c64);
 hipError_t launch_build_W(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfCoef* coef,
                           const double2* ybuf, size_t ystride, double2* W, hipStream_t st);
 int lift_chunks(const Geom& g, int pchunk);
+// the first pass of launch_lift_dense alone: part[(r, s, chunk)][row] = sum over the chunk's nodes of W f
+hipError_t launch_lift_partials(const Geom& g, const double2* W, const double2* f, const int32_t* nz, int nrhs,
+                                int pchunk, double2* part, hipStream_t st);
 hipError_t launch_lift_dense(const Geom& g, const FaceTab* ft, const IfBand* band, const double2* W, const double2* f,
                              const int32_t* nz, int nrhs, int pchunk, double2* part, double2* b, hipStream_t st);
 // many right-hand sides: the same transmission part as one complex matrix product per
@@ -369,6 +372,20 @@ hipError_t launch_volume_residual(const Geom& g, const double* m, const double2*
 hipError_t volume_residual_scratch_init(int dev);
 hipError_t launch_volume_residual_noalloc(int dev, const Geom& g, const double* m, const double2* f,
                                           const double2* u, int nrhs, double* relres, hipStream_t st);
+// Pade transmission, dense form: face blocks (rho, Sigma, J, C per interface face, pade_fb_per_sub
+// entries per subdomain) on the host; on the device G^-1 and the operators T, the lifting and the
+// reconstruction data (see k_pade.hip)
+size_t pade_fb_per_sub(const Geom& g);
+int pade_face_blocks(const Geom& g, const FaceTab* ft_host, const double* m_host, const IfCoef* coef_host,
+                     int npade, double phi, double2* rho, double2* sigma, double2* inj, double2* corr);
+hipError_t launch_pade_T(const Geom& g, const FaceTab* ft, const double2* W, const double2* fbP, const double2* fbS,
+                         const double2* fbJ, const double2* fbC, double2* Ginv, double2* work, int32_t* piv,
+                         int32_t* info, double2* T, hipStream_t st);
+hipError_t launch_pade_lift(const Geom& g, const FaceTab* ft, const double2* fbS, const double2* Ginv,
+                            const int32_t* nz, const double2* part, int nchunk, int nrhs, double2* b, hipStream_t st);
+hipError_t launch_pade_recon_prep(const Geom& g, const FaceTab* ft, const IfCoef* coef, const double2* fbJ,
+                                  const double2* fbC, const double2* Ginv, const double2* gin, const int32_t* nz,
+                                  const double2* u, int nrhs, double2* gt, hipStream_t st);
 // ratio[e] = ||r_e|| / ||b_e|| over the nloc entries of each of nent local vectors
 hipError_t launch_entry_ratio(const double2* r, const double2* b, int nloc, int nent, double* ratio, hipStream_t st);
 hipError_t launch_local_residual(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfBand* band,

@@ -274,8 +274,8 @@ hipError_t launch_build_W(const Geom& g, const Entry* ent, int nent, const FaceT
 
 int lift_chunks(const Geom& g, int pchunk) { return (g.nloc + pchunk - 1) / pchunk; }
 
-hipError_t launch_lift_dense(const Geom& g, const FaceTab* ft, const IfBand* band, const double2* W, const double2* f,
-                             const int32_t* nz, int nrhs, int pchunk, double2* part, double2* b, hipStream_t st) {
+hipError_t launch_lift_partials(const Geom& g, const double2* W, const double2* f, const int32_t* nz, int nrhs,
+                                int pchunk, double2* part, hipStream_t st) {
   const int L = local_if_len(g);
   if (pchunk > 1024 || L > 1024) return hipErrorInvalidValue;
   const int nchunk = lift_chunks(g, pchunk);
@@ -284,7 +284,14 @@ hipError_t launch_lift_dense(const Geom& g, const FaceTab* ft, const IfBand* ban
   else if (L <= 2 * RT)
     hipLaunchKernelGGL((k_lift_partial<2>), grid, dim3(RT), 0, st, g, W, f, nz, pchunk, nchunk, part);
   else hipLaunchKernelGGL((k_lift_partial<4>), grid, dim3(RT), 0, st, g, W, f, nz, pchunk, nchunk, part);
-  hipError_t e = hipGetLastError();
+  return hipGetLastError();
+}
+
+hipError_t launch_lift_dense(const Geom& g, const FaceTab* ft, const IfBand* band, const double2* W, const double2* f,
+                             const int32_t* nz, int nrhs, int pchunk, double2* part, double2* b, hipStream_t st) {
+  const int L = local_if_len(g);
+  const int nchunk = lift_chunks(g, pchunk);
+  hipError_t e = launch_lift_partials(g, W, f, nz, nrhs, pchunk, part, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_lift_reduce, dim3((L + 31) / 32, g.n1 * g.n2, nrhs), dim3(RT), 0, st, g, ft, band, nz, part,
                      nchunk, b);

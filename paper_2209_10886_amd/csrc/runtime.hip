@@ -196,6 +196,15 @@ struct hbj_ctx {
   double* vr_part = nullptr;
   size_t vr_cap = 0;  // right-hand sides the buffer holds
   int dev = 0;        // device current at hbj_setup (the allocation-free residual's scratch)
+  // Pade transmission (dense form): face blocks rho, Sigma, J and the correction C of every
+  // subdomain, G^-1 = (I + C M)^-1 per subdomain, and the reconstruction data workspace
+  double2* pade_P = nullptr;
+  double2* pade_S = nullptr;
+  double2* pade_J = nullptr;
+  double2* pade_C = nullptr;
+  double2* Ginv = nullptr;
+  double2* pade_gt = nullptr;
+  size_t pade_gt_cap = 0;
 
   ~hbj_ctx();
 };
@@ -224,6 +233,7 @@ hbj_ctx::~hbj_ctx() {
   dfree(df_err);
   dfree(vr_part);
   dfree(ir_ratio);
+  for (void* p : {(void*)pade_P, (void*)pade_S, (void*)pade_J, (void*)pade_C, (void*)Ginv, (void*)pade_gt}) dfree(p);
   for (void* p : {(void*)ft, (void*)coef, (void*)band, (void*)pos_tab, (void*)m, (void*)diag, (void*)ranges_f, (void*)ranges_b,
                   (void*)ab, (void*)ipiv, (void*)info, (void*)mf64, (void*)mb64, (void*)pf, (void*)pflag, (void*)mf32, (void*)mb32, (void*)T64, (void*)T32, (void*)Wl, (void*)lpart,
                   ybuf, (void*)nzf, (void*)Gbuf, (void*)rhs64, (void*)x64, (void*)xtr, (void*)r64, (void*)pc_y, (void*)pc_t})
@@ -935,11 +945,14 @@ int df_check(hbj_ctx* c) {
 
 // The lifting matrices serve few right-hand sides (one matrix-vector product each); many
 // right-hand sides keep the batched banded solves, which read each factor once per launch.
-bool dense_lift(const hbj_ctx* c, int nrhs) { return c->Wl && nrhs < kMatrixRhs; }
+bool is_pade(const hbj_ctx* c) { return c->P.transmission == 3; }
+
+bool dense_lift(const hbj_ctx* c, int nrhs) { return c->Wl && (nrhs < kMatrixRhs || is_pade(c)); }
 
 // lifting b = traces of A^{-1} f: subdomains whose source restriction is identically zero
 // contribute exactly zero and skip their solves
 int run_lifting(hbj_ctx* c, Schedule* S, const double2* f, double2* b, int nrhs) {
+  if (is_pade(c) && !c->Wl) return fail(HBJ_ESTATE, "the Pade transmission needs the dense lifting matrices");
   const size_t need = (size_t)nrhs * c->ndom;
   if (need > c->nzf_cap) {
     dfree(c->nzf);
@@ -970,6 +983,14 @@ int run_lifting(hbj_ctx* c, Schedule* S, const double2* f, double2* b, int nrhs)
       double pairs = 0;
       for (size_t q = (size_t)r0 * c->ndom; q < (size_t)(r0 + nb) * c->ndom; ++q) pairs += nzh[q] != 0;
       ProfScope ps(c, HBJ_K_LIFT, pairs * (double)c->g.nloc * L * 16.0, pairs * 8.0 * c->g.nloc * L);
+      if (is_pade(c)) {
+        // y = W^T f per chunk, then b = -Sigma G^-T y along each face
+        HIPCHK(launch_lift_partials(c->g, c->Wl, f + (size_t)r0 * c->g.nx * c->g.ny, c->nzf + (size_t)r0 * c->ndom,
+                                    nb, kLiftChunk, c->lpart, c->st));
+        HIPCHK(launch_pade_lift(c->g, c->ft, c->pade_S, c->Ginv, c->nzf + (size_t)r0 * c->ndom, c->lpart, nchunk, nb,
+                                b + (size_t)r0 * c->g.nif, c->st));
+        continue;
+      }
       HIPCHK(launch_lift_dense(c->g, c->ft, c->band, c->Wl, f + (size_t)r0 * c->g.nx * c->g.ny,
                                c->nzf + (size_t)r0 * c->ndom,
                                nb, kLiftChunk, c->lpart, b + (size_t)r0 * c->g.nif, c->st));
@@ -1011,6 +1032,7 @@ int fork_source_part(hbj_ctx* c, Schedule* S, const double2* f, double2* u) {
 // the lifting matrices per subdomain; banded form: one local solve per subdomain.
 int run_reconstruct(hbj_ctx* c, Schedule* S, const double2* f, const double2* g, double2* u, int nrhs,
                     bool source_done) {
+  if (is_pade(c) && !c->Wl) return fail(HBJ_ESTATE, "the Pade transmission needs the dense lifting matrices");
   if (c->Wl && c->g.nif > 0 && g) {
     if (source_done) {
       HIPCHK(hipStreamWaitEvent(c->st, c->ev_join, 0));
@@ -1031,6 +1053,21 @@ int run_reconstruct(hbj_ctx* c, Schedule* S, const double2* f, const double2* g,
       io.u = u;
       int rc = run_solves<double>(c, S->dev + S->all_first, S->all_count, io, S->tiles + S->all_tile_first, S->all_tile_count);
       if (rc) return rc;
+    }
+    if (is_pade(c)) {
+      // u holds v = A_b^-1 f (the band factors keep the Robin closure): the transmission part
+      // becomes Y G^-1 (J g - C U^T v), handed to the products below as incoming data gt
+      const size_t need = (size_t)nrhs * c->g.nif;
+      if (need > c->pade_gt_cap) {
+        dfree(c->pade_gt);
+        c->pade_gt = nullptr;
+        c->pade_gt_cap = 0;
+        if (dalloc(&c->pade_gt, need)) return fail(HBJ_ENOMEM, "reconstruction workspace allocation failed");
+        c->pade_gt_cap = need;
+      }
+      HIPCHK(launch_pade_recon_prep(c->g, c->ft, c->coef, c->pade_J, c->pade_C, c->Ginv, g, c->nzf, u, nrhs,
+                                    c->pade_gt, c->st));
+      g = c->pade_gt;
     }
     const double elems = (double)c->ndom * c->g.nloc * local_if_len(c->g);
     if (nrhs < kMatrixRhs) {
@@ -1798,6 +1835,12 @@ const char* hbj_strerror(int code) {
 static const double2 kTransA = {1.0, 0.2};
 static const double2 kTransB = {0.15 * 0.70710678118654752, -0.15 * 0.70710678118654752};
 
+// Pade transmission (paper Sec. 7): N_pade auxiliary fields, branch-cut rotation phi
+static const int kPadeTerms = 8;
+static const double kPadePhi = 1.04719755119659774615;  // pi / 3
+
+// order of the band's transmission closure: the Pade form factors the Robin-closed matrices
+// and corrects them in the dense operators
 static int transmission_order(const hbj_ctx* c) { return c->P.transmission == 2 ? 2 : 1; }
 
 static int assemble_medium(hbj_ctx* c) {
@@ -1828,7 +1871,9 @@ int hbj_setup(const hbj_problem* prob, const double* c_dev, void* stream, hbj_ct
     return fail(HBJ_EINVAL, "bad operator form");
   if (P.sweep_exec != HBJ_SWEEP_DATAFLOW && P.sweep_exec != HBJ_SWEEP_STEPPED)
     return fail(HBJ_EINVAL, "bad sweep execution option");
-  if (P.transmission < 0 || P.transmission > 2) return fail(HBJ_EINVAL, "transmission order must be 0, 1 or 2");
+  if (P.transmission < 0 || P.transmission > 3) return fail(HBJ_EINVAL, "transmission must be 0, 1, 2 or 3");
+  if (P.transmission == 3 && P.operator_form != HBJ_OP_DENSE)
+    return fail(HBJ_EINVAL, "the Pade transmission needs the dense operator form");
   if (P.operator_form == HBJ_OP_DENSE && 2 * (P.nx / P.n1 + P.ny / P.n2) > 1024)
     return fail(HBJ_EINVAL, "dense operators need 2 (sub_nx + sub_ny) <= 1024");
   if ((size_t)P.nx * P.ny > (size_t)1 << 31) return fail(HBJ_EINVAL, "grid too large");
@@ -1957,6 +2002,60 @@ int hbj_set_slowness2(hbj_ctx* c, const double* m_dev) {
 
 // Dense scattering operators: one unit-datum local solve per (subdomain, interface
 // position), in chunks, then T_s[row][col] = -sigma x_row - rho delta_{row,col} (row blocks).
+// The Pade form's dense operators (after the unit-datum solves with the Robin-closed factors have
+// filled W = A_b^-1 U): face blocks on the host, then G^-1 = (I + C U^T W)^-1 and
+// T = -P - Sigma U^T W G^-1 J on the device.
+static int build_pade(hbj_ctx* c) {
+  const Geom& g = c->g;
+  if (!c->Wl) return fail(HBJ_ENOMEM, "the Pade transmission needs the dense lifting matrices (device memory)");
+  const int L = local_if_len(g);
+  const size_t fbs = pade_fb_per_sub(g), nfb = fbs * c->ndom;
+  std::vector<double> mh((size_t)g.nx * g.ny);
+  std::vector<IfCoef> ch((size_t)std::max(g.nif, 1));
+  HIPCHK(hipMemcpyAsync(mh.data(), c->m, mh.size() * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipMemcpyAsync(ch.data(), c->coef, (size_t)g.nif * sizeof(IfCoef), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  std::vector<double2> hP(nfb), hS(nfb), hJ(nfb), hC(nfb);
+  if (pade_face_blocks(g, c->ft_host.data(), mh.data(), ch.data(), kPadeTerms, kPadePhi, hP.data(), hS.data(),
+                       hJ.data(), hC.data()))
+    return fail(HBJ_ZERO_PIVOT, "singular face matrix I/h - (i/2) X of the Pade transmission");
+  const size_t nG = (size_t)c->ndom * L * L;
+  if (!c->pade_P) {
+    if (dalloc(&c->pade_P, nfb) || dalloc(&c->pade_S, nfb) || dalloc(&c->pade_J, nfb) || dalloc(&c->pade_C, nfb) ||
+        dalloc(&c->Ginv, nG))
+      return fail(HBJ_ENOMEM, "Pade operator allocation failed");
+  }
+  HIPCHK(hipMemcpyAsync(c->pade_P, hP.data(), nfb * sizeof(double2), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipMemcpyAsync(c->pade_S, hS.data(), nfb * sizeof(double2), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipMemcpyAsync(c->pade_J, hJ.data(), nfb * sizeof(double2), hipMemcpyHostToDevice, c->st));
+  HIPCHK(hipMemcpyAsync(c->pade_C, hC.data(), nfb * sizeof(double2), hipMemcpyHostToDevice, c->st));
+  double2* work = nullptr;
+  int32_t* piv = nullptr;
+  int32_t* info = nullptr;
+  if (dalloc(&work, 2 * nG) || dalloc(&piv, (size_t)c->ndom * L) || dalloc(&info, (size_t)c->ndom)) {
+    dfree(work);
+    dfree(piv);
+    return fail(HBJ_ENOMEM, "Pade workspace allocation failed");
+  }
+  hipError_t he = launch_pade_T(g, c->ft, c->Wl, c->pade_P, c->pade_S, c->pade_J, c->pade_C, c->Ginv, work, piv, info,
+                                c->T64, c->st);
+  std::vector<int32_t> ih(c->ndom);
+  if (he == hipSuccess) he = hipMemcpyAsync(ih.data(), info, c->ndom * sizeof(int32_t), hipMemcpyDeviceToHost, c->st);
+  if (he == hipSuccess) he = hipStreamSynchronize(c->st);
+  dfree(work);
+  dfree(piv);
+  dfree(info);
+  if (he != hipSuccess) return fail(HBJ_EHIP, std::string("Pade operators: ") + hipGetErrorString(he));
+  for (int s = 0; s < c->ndom; ++s)
+    if (ih[s]) {
+      c->zero_sub = s;
+      c->zero_row = ih[s] - 1;
+      return fail(HBJ_ZERO_PIVOT, "singular Woodbury matrix I + C M of the Pade form in subdomain " +
+                                      std::to_string(s));
+    }
+  return HBJ_OK;
+}
+
 static int build_dense(hbj_ctx* c) {
   const Geom& g = c->g;
   const int L = local_if_len(g);
@@ -2011,6 +2110,10 @@ static int build_dense(hbj_ctx* c) {
   dfree(tdev);
   if (rc) return rc;
   if (he != hipSuccess) return fail(HBJ_EHIP, hipGetErrorString(he));
+  if (is_pade(c)) {
+    rc = build_pade(c);
+    if (rc) return rc;
+  }
   if (c->T32) HIPCHK(launch_cast_c64(c->T64, c->T32, per * c->ndom, c->st));
   return HBJ_OK;
 }
@@ -2331,6 +2434,8 @@ int hbj_local_solve(hbj_ctx* c, int32_t nbatch, const int32_t* sub_host, const h
   if (rc) return rc;
   if (nbatch < 1 || !sub_host || !rhs || !x) return fail(HBJ_EINVAL, "bad arguments");
   if (precision == HBJ_MIXED && !c->mf32) return fail(HBJ_EINVAL, "context has no complex64 factors");
+  if (is_pade(c))
+    return fail(HBJ_EINVAL, "the Pade form factors the Robin-closed local matrices; its local solves are not exposed");
   std::vector<Entry> ent(nbatch);
   for (int i = 0; i < nbatch; ++i) {
     if (sub_host[i] < 0 || sub_host[i] >= c->ndom) return fail(HBJ_EINVAL, "subdomain index out of range");
