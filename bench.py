@@ -66,9 +66,13 @@ def parse():
                    help="skip the run with the second-order transmission condition")
     p.add_argument("--no-multi", action="store_true", help="skip the 2048^2 64-source leg")
     p.add_argument("--no-gradient", action="store_true", help="skip the 512^2 adjoint-gradient leg")
-    p.add_argument("--transmission", type=int, default=1, choices=(1, 2),
-                   help="transmission condition of the main run (1: Robin, as the workloads specify; 2: second order)")
+    p.add_argument("--transmission", type=int, default=1, choices=(1, 2, 3),
+                   help="transmission condition of the main run (1: Robin, as the workloads specify; 2: second order; "
+                        "3: the paper's Pade condition)")
+    p.add_argument("--no-pade", action="store_true", help="skip the run with the paper's Pade transmission")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of each oracle sample")
+    p.add_argument("--only", choices=("banded", "multi", "gradient"),
+                   help="run one leg alone and print its figures (for profiling runs; no headline line)")
     return p.parse_args()
 
 
@@ -531,12 +535,66 @@ def gradient_leg(hbj, reps=2):
     return out
 
 
+def banded_legs(hbj, wl, mt, ft, u, tol, names64, names32, u_ref, mixed=True):
+    """GMRES with a banded local solve per application of every operator (one workgroup per
+    subdomain solve): FP64, and complex64 factors with FP64-refined operator solves."""
+    out = {}
+    log("[bench] FP64, banded local solves inside GMRES")
+    br = run_form(hbj, wl, mt, ft, u, hbj.FP64, hbj.OP_BANDED, 1, 0, tol, names64)
+    out["banded_fp64"] = {
+        "solves_per_s": 1.0 / br["seconds"], "iters": br["stats"].iters, "relres": br["stats"].relres,
+        "subdomain_solve_gbs": solve_gbs(br["kernels"], [names64[hbj.K_FWD], names64[hbj.K_BWD]]),
+        "roofline": roofline_of(br["kernels"], wl.name + "/banded")}
+    out["banded_fp64"]["subdomain_solve_frac_of_hbm_peak"] = out["banded_fp64"]["subdomain_solve_gbs"] / HBM_PEAK_GBS
+    log(f"[bench]   {br['seconds'] * 1e3:.1f} ms per solve, subdomain solves "
+        f"{out['banded_fp64']['subdomain_solve_gbs']:.0f} GB/s")
+    if mixed:
+        mb = run_form(hbj, wl, mt, ft, u, hbj.MIXED, hbj.OP_BANDED, 1, 0, tol, names32)
+        out["banded_mixed"] = {
+            "solves_per_s": 1.0 / mb["seconds"], "iters": mb["stats"].iters,
+            "local_ir_max": mb["stats"].local_ir_max, "local_ir_resid": mb["stats"].local_ir_resid,
+            "subdomain_solve_gbs": solve_gbs(mb["kernels"], [names32[hbj.K_FWD], names32[hbj.K_BWD]])}
+        out["banded_mixed"]["subdomain_solve_frac_of_hbm_peak"] = \
+            out["banded_mixed"]["subdomain_solve_gbs"] / HBM_PEAK_GBS
+        if u_ref is not None:
+            out["banded_mixed"]["err_vs_fp64_field"] = relerr(u, u_ref)
+        log(f"[bench]   mixed: {mb['seconds'] * 1e3:.1f} ms per solve, subdomain solves "
+            f"{out['banded_mixed']['subdomain_solve_gbs']:.0f} GB/s")
+    return out
+
+
+def only_leg(args):
+    """One leg alone (profiling runs): its figures as one JSON line."""
+    import torch
+
+    import paper_2209_10886_amd as hbj
+    import workload as W
+
+    if args.only == "multi":
+        print(json.dumps({"leg": "multi_source_2048", **multi_source_leg(hbj)}), flush=True)
+        return
+    if args.only == "gradient":
+        print(json.dumps({"leg": "gradient_512", **gradient_leg(hbj)}), flush=True)
+        return
+    wl = W.WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    mt = torch.as_tensor(W.slowness2(wl), device=dev)
+    ft = torch.as_tensor(W.sources(wl)[0], device=dev)
+    u = torch.empty_like(ft)
+    names64, names32, _ = kernel_names(hbj, False)
+    out = banded_legs(hbj, wl, mt, ft, u, args.tol, names64, names32, None, mixed=not args.no_mixed)
+    print(json.dumps({"leg": "banded", "workload": wl.name, **out}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form of the sweep is a "
               "design, not a measured configuration", file=sys.stderr)
         sys.exit(2)
+    if args.only:
+        only_leg(args)
+        return
     import workload as W
 
     wl = W.WORKLOADS[args.workload]
@@ -603,8 +661,8 @@ def main():
                    "krylov": "FGMRES(50), right-preconditioned, delayed reorthogonalisation",
                    "preconditioner": "block Jacobi, width N1",
                    "operator_form": "dense local scattering operators (formed at factor time)",
-                   "transmission": "Robin (first order)" if args.transmission == 1 else
-                   "second order on interface faces"},
+                   "transmission": {1: "Robin (first order)", 2: "second order on interface faces",
+                                    3: "Pade (8 auxiliary fields, rotation pi/3) on interface faces"}[args.transmission]},
         "iters": st.iters,
         "relres": st.relres,
         "volume_residual": max(vres),
@@ -637,14 +695,8 @@ def main():
         log(f"[bench] to 1e-8: {result['tol_1e-8']['ms_per_solve']:.2f} ms/solve, iters {tr['stats'].iters}")
 
     if not args.no_banded:
-        log("[bench] FP64, banded local solves inside GMRES")
-        br = run_form(hbj, wl, mt, ft, u, hbj.FP64, hbj.OP_BANDED, 1, 0, args.tol, names64)
-        result["banded_fp64"] = {
-            "solves_per_s": 1.0 / br["seconds"], "iters": br["stats"].iters, "relres": br["stats"].relres,
-            "subdomain_solve_gbs": solve_gbs(br["kernels"], [names64[hbj.K_FWD], names64[hbj.K_BWD]]),
-            "roofline": roofline_of(br["kernels"], wl.name + "/banded")}
-        result["banded_fp64"]["subdomain_solve_frac_of_hbm_peak"] = \
-            result["banded_fp64"]["subdomain_solve_gbs"] / HBM_PEAK_GBS
+        result.update(banded_legs(hbj, wl, mt, ft, u, args.tol, names64, names32, u_ref,
+                                  mixed=not args.no_mixed))
 
     if not args.no_mixed:
         log("[bench] mixed precision (complex64 factors and preconditioner operators)")
@@ -662,16 +714,6 @@ def main():
             log(f"[bench] mixed to {tol:g}: {mr['seconds'] / args.steps * 1e3:.2f} ms/solve, iters "
                 f"{mr['stats'].iters}, error vs FP64 field {leg.get('err_vs_fp64_field', float('nan')):.2e}")
         result["mixed"] = mixed
-        if not args.no_banded:
-            mb = run_form(hbj, wl, mt, ft, u, hbj.MIXED, hbj.OP_BANDED, 1, 0, args.tol, names32)
-            result["banded_mixed"] = {
-                "solves_per_s": 1.0 / mb["seconds"], "iters": mb["stats"].iters,
-                "local_ir_max": mb["stats"].local_ir_max, "local_ir_resid": mb["stats"].local_ir_resid,
-                "subdomain_solve_gbs": solve_gbs(mb["kernels"], [names32[hbj.K_FWD], names32[hbj.K_BWD]])}
-            result["banded_mixed"]["subdomain_solve_frac_of_hbm_peak"] = \
-                result["banded_mixed"]["subdomain_solve_gbs"] / HBM_PEAK_GBS
-            if u_ref is not None:
-                result["banded_mixed"]["err_vs_fp64_field"] = relerr(u, u_ref)
 
     if not args.no_second_order and nsrc == 1 and args.transmission == 1:
         # the workload fixes the Robin transmission condition; the second-order one (interface faces
@@ -685,6 +727,18 @@ def main():
             "factor_s": sr["factor_s"], "rel_diff_vs_robin_field": diff}
         log(f"[bench] second order: {sr['seconds'] / args.steps * 1e3:.2f} ms/solve, iters {sr['stats'].iters}, "
             f"field differs from the Robin run by {diff:.1e}")
+
+    if not args.no_pade and nsrc == 1 and args.transmission == 1:
+        # the paper's own transmission condition (Sec. 7), same field
+        log("[bench] Pade transmission condition (dense form, same precision)")
+        pr = run_form(hbj, wl, mt, ft, u, headline_prec, hbj.OP_DENSE, args.steps, 1, args.tol, names_main,
+                      graphs=args.graphs, transmission=3)
+        diff = relerr(u, u_main)
+        result["pade_transmission"] = {
+            "solves_per_s": args.steps / pr["seconds"], "iters": pr["stats"].iters, "relres": pr["stats"].relres,
+            "factor_s": pr["factor_s"], "rel_diff_vs_robin_field": diff, "n_pade": 8, "phi": "pi/3"}
+        log(f"[bench] Pade: {pr['seconds'] / args.steps * 1e3:.2f} ms/solve, iters {pr['stats'].iters}, "
+            f"factor {pr['factor_s']:.2f} s, field differs from the Robin run by {diff:.1e}")
 
     if not args.no_many_rhs and nsrc == 1:
         for prec, key in ((hbj.FP64, "banded_64rhs_fp64"), (hbj.MIXED, "banded_64rhs_mixed")):

@@ -11,6 +11,7 @@ field used by the 1024^2 workload, 10 points per wavelength, one Gaussian source
 reconstruction) with the dense scattering operators, after one warmup solve.
 
     python -m paper_2209_10886_amd.table1 [--sub 128] [--out profiles/table1_sp_vs_bsp.md]
+        (both the Robin condition and the paper's Pade condition; residual histories on 5 x 10)
     python -m paper_2209_10886_amd.table1 --ablation fp64_1024_8x8_grf --out profiles/ablation_readings_1024_8x8.md
 """
 from __future__ import annotations
@@ -23,7 +24,10 @@ import sys
 import time
 
 
-def run(sub=128, layouts=((5, 5), (5, 10), (5, 15), (5, 20)), tol=1e-6, ppw=10.0, reps=2):
+TRANSMISSIONS = ((1, "Robin"), (3, "Pade"))
+
+
+def run(sub=128, layouts=((5, 5), (5, 10), (5, 15), (5, 20)), tol=1e-6, ppw=10.0, reps=2, transmissions=TRANSMISSIONS):
     import torch
 
     import paper_2209_10886_amd as hbj
@@ -35,20 +39,22 @@ def run(sub=128, layouts=((5, 5), (5, 10), (5, 15), (5, 20)), tol=1e-6, ppw=10.0
         wl = W.Workload(f"strip_{n1}x{n2}", nx, ny, n1, n2, ppw, "random_smooth", 0, ((0.5, 0.1 * (ny + 1) / (nx + 1)),))
         m = torch.as_tensor(W.slowness2(wl), device="cuda")
         f = torch.as_tensor(W.sources(wl)[0], device="cuda")
-        for name, pc in (("SP", hbj.PC_SGS), ("BSP", hbj.PC_BJ)):
-            ctx = hbj.setup(nx, ny, wl.k, n1, n2, m=m, precond=pc, operator_form=hbj.OP_DENSE)
-            ctx.factor()
-            u, st = ctx.solve(f, tol=tol, maxit=2000)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(reps):
-                u, st = ctx.solve(f, tol=tol, maxit=2000, out=u)
-            torch.cuda.synchronize()
-            dt = (time.perf_counter() - t0) / reps
-            rows.append({"layout": f"{n1}x{n2}", "grid": [nx, ny], "preconditioner": name, "ni": st.iters,
-                         "ns": st.steps_per_pc, "t_ms": dt * 1e3, "relres": st.relres})
-            print(json.dumps(rows[-1]), flush=True)
-            ctx.close()
+        for tr, tname in transmissions:
+            for name, pc in (("SP", hbj.PC_SGS), ("BSP", hbj.PC_BJ)):
+                ctx = hbj.setup(nx, ny, wl.k, n1, n2, m=m, precond=pc, operator_form=hbj.OP_DENSE, transmission=tr)
+                ctx.factor()
+                u, st = ctx.solve(f, tol=tol, maxit=2000)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(reps):
+                    u, st = ctx.solve(f, tol=tol, maxit=2000, out=u)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / reps
+                rows.append({"layout": f"{n1}x{n2}", "grid": [nx, ny], "transmission": tname, "preconditioner": name,
+                             "ni": st.iters, "ns": st.steps_per_pc, "t_ms": dt * 1e3, "relres": st.relres,
+                             "history": [float(x) for x in st.history]})
+                print(json.dumps({k: v for k, v in rows[-1].items() if k != "history"}), flush=True)
+                ctx.close()
     return rows
 
 
@@ -108,24 +114,43 @@ def markdown(rows, sub):
            f"Subdomains of {sub}^2 grid points, 10 points per wavelength, seeded smooth random medium, one Gaussian",
            "source; GMRES(50) to relative residual 1e-6; dense scattering operators; MI355X wall time per solve.",
            "ns is the number of sequential sweep steps per preconditioner application (paper: SP 16/26/36/46,",
-           "BSP 10). Iteration counts differ from the paper's (first-order Robin transmission on finite",
-           "differences instead of the Pade high-order condition on P7 elements).", "",
-           "| N1 x N2 | SP ni | SP ns | SP t (ms) | BSP ni | BSP ns | BSP t (ms) |", "|---|---|---|---|---|---|---|"]
-    by = {}
-    for r in rows:
-        by.setdefault(r["layout"], {})[r["preconditioner"]] = r
-    ratios = []
-    for lay, d in by.items():
-        sp, bsp = d["SP"], d["BSP"]
-        out.append(f"| {lay} | {sp['ni']} | {sp['ns']} | {sp['t_ms']:.2f} | {bsp['ni']} | {bsp['ns']} | "
-                   f"{bsp['t_ms']:.2f} |")
-        ratios.append(sp["t_ms"] / bsp["t_ms"])
-    out += ["", "Command (MI355X, repository root): `python -u -m paper_2209_10886_amd.table1 --out "
-            "profiles/table1_sp_vs_bsp.md`.", "",
-            "SP/BSP time ratios: " + ", ".join(f"{x:.2f}" for x in ratios) + " for the layouts above. The paper's MPI "
-            "timings on one multi-core CPU give 1.28, 1.48, 1.77, 2.08. On the GPU one sweep step is a single launch of "
-            "a few microseconds, so the step count weighs less than when a step means MPI exchanges between row ranks. "
-            "The growth with N2 is the same: SP needs 2(N1 + N2 - 2) steps, BSP 2 N1."]
+           "BSP 10). Two transmission conditions: the first-order Robin condition of the workloads, and the",
+           "paper's Pade condition (8 auxiliary fields, branch rotation pi/3) on finite differences. The outer",
+           "boundary keeps the first-order absorbing condition in both.", ""]
+    ratios = {}
+    for tname in dict.fromkeys(r["transmission"] for r in rows):
+        out += [f"## {tname} transmission", "",
+                "| N1 x N2 | SP ni | SP ns | SP t (ms) | BSP ni | BSP ns | BSP t (ms) |", "|---|---|---|---|---|---|---|"]
+        by = {}
+        for r in rows:
+            if r["transmission"] == tname:
+                by.setdefault(r["layout"], {})[r["preconditioner"]] = r
+        for lay, d in by.items():
+            sp, bsp = d["SP"], d["BSP"]
+            out.append(f"| {lay} | {sp['ni']} | {sp['ns']} | {sp['t_ms']:.2f} | {bsp['ni']} | {bsp['ns']} | "
+                       f"{bsp['t_ms']:.2f} |")
+            ratios.setdefault(tname, []).append(sp["t_ms"] / bsp["t_ms"])
+        out.append("")
+    out += ["Command (MI355X, repository root): `python -u -m paper_2209_10886_amd.table1 --out "
+            "profiles/table1_sp_vs_bsp.md`.", ""]
+    for tname, rs in ratios.items():
+        out.append(f"SP/BSP time ratios ({tname}): " + ", ".join(f"{x:.2f}" for x in rs) + ".")
+    out += ["", "The paper's MPI timings on one multi-core CPU give 1.28, 1.48, 1.77, 2.08. On the GPU one sweep "
+            "step is a single launch of a few microseconds, so the step count weighs less than when a step means MPI "
+            "exchanges between row ranks. The growth with N2 is the same: SP needs 2(N1 + N2 - 2) steps, BSP 2 N1.", ""]
+    hist = [r for r in rows if r["layout"] == "5x10"]
+    if hist:
+        out += ["## Residual histories on 5 x 10 (relative GMRES residual estimate per iteration)", "",
+                "The paper (Sec. 7, Fig. 3) shows a sudden drop after about as many iterations as there are partial "
+                "sweeps with its high-order condition on P7 elements and a Pade outer boundary; on this finite-"
+                "difference problem with a first-order outer boundary the residual falls steadily (parity unpinned, "
+                "qualitative).", "",
+                "| iteration | " + " | ".join(f"{r['transmission']} {r['preconditioner']}" for r in hist) + " |",
+                "|---" * (len(hist) + 1) + "|"]
+        nmax = max(len(r["history"]) for r in hist)
+        for it in range(nmax):
+            cells = [f"{r['history'][it]:.2e}" if it < len(r["history"]) else "" for r in hist]
+            out.append(f"| {it} | " + " | ".join(cells) + " |")
     return "\n".join(out) + "\n"
 
 

@@ -73,8 +73,18 @@ def test_fullsize_preconditioner(full):
     assert rel(z, sweep.apply_bj(dd, r)) < 1e-11
 
 
+@pytest.fixture(scope="module")
+def direct_full(full):
+    """The oracle's global direct solution u = A^{-1} f of the 1024^2 workload (SuperLU)."""
+    from oracle import solver
+
+    wl, m, dd, ctx = full
+    say(f"[fullsize] oracle global direct solve (SuperLU, {wl.nx}^2)")
+    return solver.direct(dd.grid, W.sources(wl)[0])
+
+
 @pytest.mark.timeout(900)
-def test_fullsize_solve_matches_direct_solution(full, hbj):
+def test_fullsize_solve_matches_direct_solution(full, direct_full, hbj):
     """FP64 solve at tol 1e-12 against the oracle's global direct solution (relative error 1e-8);
     the iteration count at tol 1e-6 against the oracle's DD-GMRES (within one); the volume
     residual of the GPU field from the oracle and from the library."""
@@ -86,8 +96,8 @@ def test_fullsize_solve_matches_direct_solution(full, hbj):
     say("[fullsize] FP64 solve, tol 1e-12")
     u, st = ctx.solve(ft, tol=1e-12, maxit=2000)
     assert st.relres <= 1e-12
-    say(f"  iters {st.iters}, relres {st.relres:.2e}; oracle global direct solve (SuperLU, {wl.nx}^2)")
-    ud = solver.direct(dd.grid, f)
+    say(f"  iters {st.iters}, relres {st.relres:.2e}")
+    ud = direct_full
     e = rel(_np(u), ud)
     vr_o = solver.volume_residual(dd.grid, _np(u), f)
     vr_g = ctx.volume_residual(ft, u)[0]
@@ -97,7 +107,6 @@ def test_fullsize_solve_matches_direct_solution(full, hbj):
     assert e < 1e-8
     # both sum f - A u in their own order; at a converged field the residual is near round-off
     assert abs(vr_g - vr_o) <= bound
-    del ud
     say("[fullsize] FP64 solve, tol 1e-6, against the oracle's DD-GMRES")
     _, st6 = ctx.solve(ft, tol=1e-6)
     ref = solver.dd_solve(dd, f, precond="bj", tol=1e-6)
@@ -253,3 +262,32 @@ def test_fullsize_second_order(full2):
     res = np.linalg.norm(dd.apply_operator(gs) - b) / np.linalg.norm(b)
     say(f"  iters {st.iters}, relres {st.relres:.2e}, oracle interface residual of the traces {res:.2e}")
     assert res < 5e-8
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_pade(full, direct_full, hbj):
+    """The Pade transmission at 1024^2, 8 x 8 in the bench's configuration: the operator on sampled
+    subdomains against the oracle's transmission=3 decomposition, and the solve at tol 1e-12
+    against the global direct solution; iterations at tol 1e-6 beside the Robin condition's."""
+    from oracle.dd import Decomposition
+
+    wl, m, dd, _ = full
+    say("[fullsize pade] oracle decomposition with the Pade transmission")
+    ddp = Decomposition(dd.grid, wl.n1, wl.n2, transmission=3)
+    ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=torch.as_tensor(m, device="cuda"), precond=hbj.PC_BJ,
+                    operator_form=hbj.OP_DENSE, transmission=3)
+    ctx.factor()
+    gv = W.random_interface_vector(ctx.nif, seed=46)
+    w = _np(ctx.apply_operator(torch.as_tensor(gv, device="cuda")))
+    for s in (0, 27, 63):  # a corner, an interior and the opposite corner subdomain
+        key = list(ddp.sub)[s]
+        for j, v in ddp.scatter_subdomain(key, gv).items():
+            blk = ddp.layout.block(j, key)
+            assert rel(w[blk], gv[blk] - v) < 1e-12
+    ft = torch.as_tensor(W.sources(wl)[0], device="cuda")
+    u, st = ctx.solve(ft, tol=1e-12, maxit=3000)
+    e = rel(_np(u), direct_full)
+    _, st6 = ctx.solve(ft, tol=1e-6)
+    say(f"  tol 1e-12: iters {st.iters}, error vs direct {e:.1e}; tol 1e-6: iters {st6.iters}")
+    assert st.relres <= 1e-12 and e < 1e-8
+    ctx.close()
