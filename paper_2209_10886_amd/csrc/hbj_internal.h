@@ -385,7 +385,7 @@ hipError_t launch_pade_lift(const Geom& g, const FaceTab* ft, const double2* fbS
                             const int32_t* nz, const double2* part, int nchunk, int nrhs, double2* b, hipStream_t st);
 hipError_t launch_pade_recon_prep(const Geom& g, const FaceTab* ft, const IfCoef* coef, const double2* fbJ,
                                   const double2* fbC, const double2* Ginv, const double2* gin, const int32_t* nz,
-                                  const double2* u, int nrhs, double2* gt, hipStream_t st);
+                                  const double2* u, int nrhs, double2* qbuf, double2* gt, hipStream_t st);
 // ratio[e] = ||r_e|| / ||b_e|| over the nloc entries of each of nent local vectors
 hipError_t launch_entry_ratio(const double2* r, const double2* b, int nloc, int nent, double* ratio, hipStream_t st);
 hipError_t launch_local_residual(const Geom& g, const Entry* ent, int nent, const FaceTab* ft, const IfBand* band,

@@ -396,33 +396,48 @@ __global__ __launch_bounds__(kPT) void k_pade_T(Geom g, const FaceTab* ft, const
   }
 }
 
-// Lifting of the Pade form, one workgroup per (subdomain, right-hand side): y = the sum of the
-// chunk partials of W^T f (chunk order), y' = G^-T y, b at the outgoing positions of every face
-// with a neighbour = -Sigma_f y'_f (0 for subdomains without a source).
+// Lifting of the Pade form, one workgroup per subdomain and group of up to PRB right-hand sides (G^-1
+// is read once per group): y = the sum of the chunk partials of W^T f (chunk order), y' = G^-T y,
+// b at the outgoing positions of every face with a neighbour = -Sigma_f y'_f (0 for right-hand sides
+// without a source in the subdomain).
+constexpr int PRB = 4;
 __global__ __launch_bounds__(1024) void k_pade_lift(Geom g, const FaceTab* ft, const double2* __restrict__ fbS,
                                                     const double2* __restrict__ Ginv, const int32_t* nz,
-                                                    const double2* part, int nchunk, double2* b) {
-  const int s = blockIdx.x, r = blockIdx.y;
+                                                    const double2* part, int nchunk, int nrhs, double2* b) {
+  const int s = blockIdx.x, r0 = blockIdx.y * PRB;
   const int ndom = g.n1 * g.n2;
   const int L = local_if_len(g);
-  const bool has = nz[(size_t)r * ndom + s] != 0;
+  const int nr = min(PRB, nrhs - r0);
   const FaceTab F = ft[s];
-  __shared__ double2 y[1024], yp[1024];
-  for (int q = threadIdx.x; q < L; q += blockDim.x) {
-    double2 acc = mk(0.0, 0.0);
-    if (has) {
-      const double2* ps = part + (size_t)(r * ndom + s) * nchunk * L + q;
-      for (int c = 0; c < nchunk; ++c) acc = cadd(acc, ps[(size_t)c * L]);
+  __shared__ double2 y[PRB][1024], yp[PRB][1024];
+  bool any = false;
+  for (int k = 0; k < nr; ++k) any |= nz[(size_t)(r0 + k) * ndom + s] != 0;
+  for (int k = 0; k < nr; ++k) {
+    const bool has = nz[(size_t)(r0 + k) * ndom + s] != 0;
+    for (int q = threadIdx.x; q < L; q += blockDim.x) {
+      double2 acc = mk(0.0, 0.0);
+      if (has) {
+        const double2* ps = part + (size_t)((r0 + k) * ndom + s) * nchunk * L + q;
+        for (int c = 0; c < nchunk; ++c) acc = cadd(acc, ps[(size_t)c * L]);
+      }
+      y[k][q] = acc;
     }
-    y[q] = acc;
   }
   __syncthreads();
   const double2* Gs = Ginv + (size_t)s * L * L;
   for (int c = threadIdx.x; c < L; c += blockDim.x) {
-    double2 acc = mk(0.0, 0.0);
-    if (has)
-      for (int q = 0; q < L; ++q) cfma(acc, Gs[(size_t)q * L + c], y[q]);
-    yp[c] = acc;
+    double2 acc[PRB];
+#pragma unroll
+    for (int k = 0; k < PRB; ++k) acc[k] = mk(0.0, 0.0);
+    if (any)
+      for (int q = 0; q < L; ++q) {
+        const double2 gv = Gs[(size_t)q * L + c];
+#pragma unroll
+        for (int k = 0; k < PRB; ++k)
+          if (k < nr) cfma(acc[k], gv, y[k][q]);
+      }
+#pragma unroll
+    for (int k = 0; k < PRB; ++k) yp[k][c] = acc[k];
   }
   __syncthreads();
   const size_t fbs = 2 * (size_t)g.sny * g.sny + 2 * (size_t)g.snx * g.snx;
@@ -433,28 +448,36 @@ __global__ __launch_bounds__(1024) void k_pade_lift(Geom g, const FaceTab* ft, c
     if (oo < 0) continue;
     const int len = face_len(g, f), off = face_off(g, f);
     const double2* sr = fbS + (size_t)s * fbs + face_off2(g, f) + (size_t)e * len;
-    double2 acc = mk(0.0, 0.0);
-    for (int q = 0; q < len; ++q) cfma(acc, sr[q], yp[off + q]);
-    b[(size_t)r * g.nif + oo + e] = mk(-acc.x, -acc.y);
+    double2 acc[PRB];
+#pragma unroll
+    for (int k = 0; k < PRB; ++k) acc[k] = mk(0.0, 0.0);
+    for (int q = 0; q < len; ++q) {
+      const double2 sv = sr[q];
+#pragma unroll
+      for (int k = 0; k < PRB; ++k)
+        if (k < nr) cfma(acc[k], sv, yp[k][off + q]);
+    }
+    for (int k = 0; k < nr; ++k) b[(size_t)(r0 + k) * g.nif + oo + e] = mk(-acc[k].x, -acc[k].y);
   }
 }
 
-// Reconstruction data of the Pade form, one workgroup per (subdomain, right-hand side):
-// q = J g - C U^T v on the faces with a neighbour (v = the source part already in u, for
-// subdomains with a source), t = G^-1 q, and gt = t / inj at the subdomain's incoming positions,
-// so that the reconstruction products u += W (inj gt) add Y G^-1 q.
-__global__ __launch_bounds__(512) void k_pade_recon_prep(Geom g, const FaceTab* ft, const IfCoef* coef,
-                                                         const double2* __restrict__ fbJ,
-                                                         const double2* __restrict__ fbC,
-                                                         const double2* __restrict__ Ginv, const double2* gin,
-                                                         const int32_t* nz, const double2* u, double2* gt) {
+// Reconstruction data of the Pade form, in two passes.  Pass 1, one workgroup per (subdomain,
+// right-hand side): q = J g - C U^T v on the faces with a neighbour (v = the source part already in
+// u, for subdomains with a source; 0 on outer faces), a wavefront per entry of q reading its rows of
+// J and C along the face.  Pass 2, one workgroup per (subdomain, group of up to PRB right-hand
+// sides, chunk of kRecRows rows of G^-1): t = G^-1 q for the chunk's rows, a wavefront per row of
+// G^-1 (read once per group), and gt = t / inj at the subdomain's incoming positions, so that the
+// reconstruction products u += W (inj gt) add Y G^-1 q.
+__global__ __launch_bounds__(512) void k_pade_recon_q(Geom g, const FaceTab* ft, const double2* __restrict__ fbJ,
+                                                      const double2* __restrict__ fbC, const double2* gin,
+                                                      const int32_t* nz, const double2* u, double2* qbuf) {
   const int s = blockIdx.x, r = blockIdx.y;
   const int ndom = g.n1 * g.n2;
   const int L = local_if_len(g);
   const bool has = nz[(size_t)r * ndom + s] != 0;
   const FaceTab F = ft[s];
   const int x0 = (s % g.n1) * g.snx, y0 = (s / g.n1) * g.sny;
-  __shared__ double2 gl[1024], vl[1024], q[1024];
+  __shared__ double2 gl[1024], vl[1024];
   for (int c = threadIdx.x; c < L; c += blockDim.x) {
     int f, e;
     local_if_face(g, c, &f, &e);
@@ -470,7 +493,9 @@ __global__ __launch_bounds__(512) void k_pade_recon_prep(Geom g, const FaceTab* 
   }
   __syncthreads();
   const size_t fbs = 2 * (size_t)g.sny * g.sny + 2 * (size_t)g.snx * g.snx;
-  for (int c = threadIdx.x; c < L; c += blockDim.x) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  double2* qs = qbuf + ((size_t)r * ndom + s) * L;
+  for (int c = wv; c < L; c += nw) {
     int f, e;
     local_if_face(g, c, &f, &e);
     double2 acc = mk(0.0, 0.0);
@@ -478,31 +503,61 @@ __global__ __launch_bounds__(512) void k_pade_recon_prep(Geom g, const FaceTab* 
       const int len = face_len(g, f), off = face_off(g, f);
       const double2* jr = fbJ + (size_t)s * fbs + face_off2(g, f) + (size_t)e * len;
       const double2* cr = fbC + (size_t)s * fbs + face_off2(g, f) + (size_t)e * len;
-      for (int k = 0; k < len; ++k) {
-        cfma(acc, jr[k], gl[off + k]);
-        const double2 cv = cr[k];
-        cfma(acc, mk(-cv.x, -cv.y), vl[off + k]);
+      for (int m = lane; m < len; m += 64) {
+        cfma(acc, jr[m], gl[off + m]);
+        const double2 cv = cr[m];
+        cfma(acc, mk(-cv.x, -cv.y), vl[off + m]);
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        acc.x += __shfl_xor(acc.x, o);
+        acc.y += __shfl_xor(acc.y, o);
       }
     }
-    q[c] = acc;
+    if (lane == 0) qs[c] = acc;
   }
+}
+
+constexpr int kRecRows = 64;
+__global__ __launch_bounds__(512) void k_pade_recon_t(Geom g, const FaceTab* ft, const IfCoef* coef,
+                                                      const double2* __restrict__ Ginv, const double2* qbuf, int nrhs,
+                                                      double2* gt) {
+  const int s = blockIdx.x, r0 = blockIdx.y * PRB, row0 = blockIdx.z * kRecRows;
+  const int ndom = g.n1 * g.n2;
+  const int L = local_if_len(g);
+  const int nr = min(PRB, nrhs - r0);
+  const FaceTab F = ft[s];
+  __shared__ double2 q[PRB][1024];
+  for (int k = 0; k < nr; ++k)
+    for (int c = threadIdx.x; c < L; c += blockDim.x) q[k][c] = qbuf[((size_t)(r0 + k) * ndom + s) * L + c];
   __syncthreads();
-  // t = G^-1 q: a wavefront per row, 64 lanes along the row
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const double2* Gs = Ginv + (size_t)s * L * L;
-  for (int row = wv; row < L; row += nw) {
-    double2 acc = mk(0.0, 0.0);
-    for (int c = lane; c < L; c += 64) cfma(acc, Gs[(size_t)row * L + c], q[c]);
+  const int row1 = min(L, row0 + kRecRows);
+  for (int row = row0 + wv; row < row1; row += nw) {
+    double2 acc[PRB];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      acc.x += __shfl_xor(acc.x, off);
-      acc.y += __shfl_xor(acc.y, off);
+    for (int k = 0; k < PRB; ++k) acc[k] = mk(0.0, 0.0);
+    for (int c = lane; c < L; c += 64) {
+      const double2 gv = Gs[(size_t)row * L + c];
+#pragma unroll
+      for (int k = 0; k < PRB; ++k)
+        if (k < nr) cfma(acc[k], gv, q[k][c]);
     }
+#pragma unroll
+    for (int k = 0; k < PRB; ++k)
+      if (k < nr)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+          acc[k].x += __shfl_xor(acc[k].x, off);
+          acc[k].y += __shfl_xor(acc[k].y, off);
+        }
     if (lane == 0) {
       int f, e;
       local_if_face(g, row, &f, &e);
       const int io = pick4(F.in_off, f);
-      if (io >= 0) gt[(size_t)r * g.nif + io + e] = cdiv(acc, coef[io + e].inj);
+      if (io >= 0)
+        for (int k = 0; k < nr; ++k) gt[(size_t)(r0 + k) * g.nif + io + e] = cdiv(acc[k], coef[io + e].inj);
     }
   }
 }
@@ -585,16 +640,18 @@ hipError_t launch_pade_lift(const Geom& g, const FaceTab* ft, const double2* fbS
   const int L = local_if_len(g);
   if (L > 1024) return hipErrorInvalidValue;
   const int nt = std::min(1024, (L + 63) / 64 * 64);
-  hipLaunchKernelGGL(k_pade_lift, dim3(g.n1 * g.n2, nrhs), dim3(nt), 0, st, g, ft, fbS, Ginv, nz, part, nchunk, b);
+  hipLaunchKernelGGL(k_pade_lift, dim3(g.n1 * g.n2, (nrhs + PRB - 1) / PRB), dim3(nt), 0, st, g, ft, fbS, Ginv, nz, part,
+                     nchunk, nrhs, b);
   return hipGetLastError();
 }
 
 hipError_t launch_pade_recon_prep(const Geom& g, const FaceTab* ft, const IfCoef* coef, const double2* fbJ,
                                   const double2* fbC, const double2* Ginv, const double2* gin, const int32_t* nz,
-                                  const double2* u, int nrhs, double2* gt, hipStream_t st) {
+                                  const double2* u, int nrhs, double2* qbuf, double2* gt, hipStream_t st) {
   const int L = local_if_len(g);
   if (L > 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pade_recon_prep, dim3(g.n1 * g.n2, nrhs), dim3(512), 0, st, g, ft, coef, fbJ, fbC, Ginv, gin,
-                     nz, u, gt);
+  hipLaunchKernelGGL(k_pade_recon_q, dim3(g.n1 * g.n2, nrhs), dim3(512), 0, st, g, ft, fbJ, fbC, gin, nz, u, qbuf);
+  const dim3 grid(g.n1 * g.n2, (nrhs + PRB - 1) / PRB, (L + kRecRows - 1) / kRecRows);
+  hipLaunchKernelGGL(k_pade_recon_t, grid, dim3(512), 0, st, g, ft, coef, Ginv, qbuf, nrhs, gt);
   return hipGetLastError();
 }

@@ -1057,7 +1057,9 @@ int run_reconstruct(hbj_ctx* c, Schedule* S, const double2* f, const double2* g,
     if (is_pade(c)) {
       // u holds v = A_b^-1 f (the band factors keep the Robin closure): the transmission part
       // becomes Y G^-1 (J g - C U^T v), handed to the products below as incoming data gt
-      const size_t need = (size_t)nrhs * c->g.nif;
+      // workspace: gt [nrhs][nif], then q [nrhs][ndom][L]
+      const size_t nq = (size_t)nrhs * c->ndom * local_if_len(c->g);
+      const size_t need = (size_t)nrhs * c->g.nif + nq;
       if (need > c->pade_gt_cap) {
         dfree(c->pade_gt);
         c->pade_gt = nullptr;
@@ -1066,7 +1068,7 @@ int run_reconstruct(hbj_ctx* c, Schedule* S, const double2* f, const double2* g,
         c->pade_gt_cap = need;
       }
       HIPCHK(launch_pade_recon_prep(c->g, c->ft, c->coef, c->pade_J, c->pade_C, c->Ginv, g, c->nzf, u, nrhs,
-                                    c->pade_gt, c->st));
+                                    c->pade_gt + (size_t)nrhs * c->g.nif, c->pade_gt, c->st));
       g = c->pade_gt;
     }
     const double elems = (double)c->ndom * c->g.nloc * local_if_len(c->g);
