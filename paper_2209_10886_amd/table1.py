@@ -58,9 +58,10 @@ def run(sub=128, layouts=((5, 5), (5, 10), (5, 15), (5, 20)), tol=1e-6, ppw=10.0
     return rows
 
 
-def ablation(wl_name="fp64_1024_8x8_grf", tol=1e-6, reps=3):
+def ablation(wl_name="fp64_1024_8x8_grf", tol=1e-6, reps=3, transmissions=TRANSMISSIONS):
     """Readings of Sec. 6 that the paper leaves open, on one workload: interval width (number of
-    partial sweeps), the combination at shared groups, the composition of the two passes."""
+    partial sweeps), the combination at shared groups, the composition of the two passes; with the
+    Robin and with the Pade transmission condition."""
     import torch
 
     import paper_2209_10886_amd as hbj
@@ -80,20 +81,21 @@ def ablation(wl_name="fp64_1024_8x8_grf", tol=1e-6, reps=3):
                   dict(precond=hbj.PC_BJ, bj_combine=hbj.BJ_ADDITIVE, bj_compose=hbj.BJ_RESIDUAL)),
                  ("none", dict(precond=hbj.PC_NONE))]
     rows = []
-    for name, kw in variants:
-        ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=m, operator_form=hbj.OP_DENSE, **kw)
-        ctx.factor()
-        u, st = ctx.solve(f, tol=tol, maxit=3000)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            u, st = ctx.solve(f, tol=tol, maxit=3000, out=u)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
-        rows.append({"variant": name, "ni": st.iters, "ns": st.steps_per_pc, "t_ms": dt * 1e3,
-                     "relres": st.relres, "converged": st.converged})
-        print(json.dumps(rows[-1]), flush=True)
-        ctx.close()
+    for tr, tname in transmissions:
+        for name, kw in variants:
+            ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=m, operator_form=hbj.OP_DENSE, transmission=tr, **kw)
+            ctx.factor()
+            u, st = ctx.solve(f, tol=tol, maxit=3000)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                u, st = ctx.solve(f, tol=tol, maxit=3000, out=u)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            rows.append({"transmission": tname, "variant": name, "ni": st.iters, "ns": st.steps_per_pc,
+                         "t_ms": dt * 1e3, "relres": st.relres, "converged": st.converged})
+            print(json.dumps(rows[-1]), flush=True)
+            ctx.close()
     return wl, rows
 
 
@@ -101,11 +103,18 @@ def ablation_markdown(wl, rows, tol=1e-6):
     out = [f"# Readings of Sec. 6: interval width, shared-group combination, composition ({wl.name})", "",
            f"{wl.nx}^2 grid, {wl.n1} x {wl.n2} subdomains, one Gaussian source, GMRES(50) to relative residual "
            f"{tol:g}, dense scattering operators, MI355X wall time per solve. ns = sequential sweep steps per "
-           "preconditioner application.", "",
-           "| variant | ni | ns | ni x ns | t (ms) |", "|---|---|---|---|---|"]
-    for r in rows:
-        conv = "" if r["converged"] else " (not converged)"
-        out.append(f"| {r['variant']} | {r['ni']}{conv} | {r['ns']} | {r['ni'] * r['ns']} | {r['t_ms']:.2f} |")
+           "preconditioner application. Two transmission conditions: the Robin condition of the workload and "
+           "the paper's Pade condition.", ""]
+    for tname in dict.fromkeys(r["transmission"] for r in rows):
+        out += [f"## {tname} transmission", "", "| variant | ni | ns | ni x ns | t (ms) |", "|---|---|---|---|---|"]
+        for r in rows:
+            if r["transmission"] != tname:
+                continue
+            conv = "" if r["converged"] else " (not converged)"
+            out.append(f"| {r['variant']} | {r['ni']}{conv} | {r['ns']} | {r['ni'] * r['ns']} | {r['t_ms']:.2f} |")
+        out.append("")
+    out.append("Command (MI355X, repository root): `python -u -m paper_2209_10886_amd.table1 --ablation "
+               f"{wl.name} --out profiles/ablation_readings_1024_8x8.md`.")
     return "\n".join(out) + "\n"
 
 
