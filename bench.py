@@ -287,11 +287,19 @@ def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, p
                     operator_form=operator_form, transmission=transmission, device=mt.device)
     ctx.set_graphs(graphs)
     torch.cuda.synchronize()
+    # the first factorisation also runs the autotuner of the banded solve batches when the tuning
+    # cache has no entry for them yet; the second one is the steady-state figure
+    t0 = time.perf_counter()
+    ctx.factor()
+    torch.cuda.synchronize()
+    t_factor_first = time.perf_counter() - t0
     t0 = time.perf_counter()
     ctx.factor()
     torch.cuda.synchronize()
     t_factor = time.perf_counter() - t0
     st = None
+    if warmup == 0:
+        ctx.solve(ft, tol=tol, maxit=2, out=u, check=False)  # untimed: the autotuner sees every batch class
     for _ in range(warmup):
         _, st = ctx.solve(ft, tol=tol, out=u)
     torch.cuda.synchronize()
@@ -306,7 +314,8 @@ def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, p
     ctx.set_profiling(False)
     stats = {name: ctx.kernel_stats(kc) for kc, name in profile_names.items()}
     tuning = {k: v for k, v in ctx.tuning().items() if v["k_steps_per_batch"] is not None}
-    res = {"seconds": dt, "steps": steps, "factor_s": t_factor, "stats": st, "kernels": stats, "tuning": tuning}
+    res = {"seconds": dt, "steps": steps, "factor_s": t_factor, "factor_first_s": t_factor_first, "stats": st,
+           "kernels": stats, "tuning": tuning, "solve_tuning": ctx.solve_tuning()}
     if keep:
         res["ctx"] = ctx
     else:
@@ -368,6 +377,7 @@ def factor_seconds(hbj, wl, mt, precision, transmission, multi_solve):
     ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=mt, precision=precision, precond=hbj.PC_BJ,
                     operator_form=hbj.OP_DENSE, transmission=transmission, device=mt.device)
     ctx.set_multi_solve(multi_solve)
+    ctx.factor()  # the autotuner's first look at these batches (untimed)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.factor()
@@ -391,6 +401,8 @@ def many_rhs_solves(hbj, wl, mt, nrhs, precision, reps=3):
     peak = MFMA_PEAK_TFLOPS["f64" if precision == hbj.FP64 else "f32"]
     for mode, key in ((hbj.MSOLVE_MFMA, "mfma"), (hbj.MSOLVE_CHAINS, "one_solve_per_workgroup")):
         ctx.set_multi_solve(mode)
+        # every batch on MFMA tiles, or one workgroup per solve at the autotuned prefetch depth
+        ctx.set_solve_tuning(hbj.SOLVE_SHAPE_MFMA if mode == hbj.MSOLVE_MFMA else -1)
         w = ctx.apply_operator(g)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -429,12 +441,14 @@ def relerr(a, b):
 
 
 def kernel_names(hbj, many):
-    names64 = {hbj.K_FWD: "k_fwd<double,16,4,5>", hbj.K_BWD: "k_bwd<double,16,2,3>",
+    # the one-workgroup-per-solve kernels run at the autotuned prefetch depth D (the legs report the
+    # choices under "solve_tuning")
+    names64 = {hbj.K_FWD: "k_fwd<double,16,4,D>", hbj.K_BWD: "k_bwd<double,16,2,D>",
                hbj.K_SCATTER: "k_scatter_apply<double2,16> (sweep steps)",
                hbj.K_OPERATOR: "k_scatter_apply<double2,16> (operator)",
                hbj.K_SWEEP: "k_sweep_df<double2,16>", hbj.K_LIFT: "k_lift_partial+k_recon_dense",
                hbj.K_KRYLOV: "krylov (Gram-Schmidt kernels of one iteration)"}
-    names32 = {hbj.K_FWD: "k_fwd<float,16,4,8>", hbj.K_BWD: "k_bwd<float,16,2,4>",
+    names32 = {hbj.K_FWD: "k_fwd<float,16,4,D>", hbj.K_BWD: "k_bwd<float,16,2,D>",
                hbj.K_SCATTER: "k_scatter_apply<float2,16> (sweep steps)",
                hbj.K_OPERATOR: "k_scatter_apply<double2,16> (operator)",
                hbj.K_SWEEP: "k_sweep_df", hbj.K_LIFT: "k_lift_partial+k_recon_dense",
@@ -556,7 +570,7 @@ def banded_legs(hbj, wl, mt, ft, u, tol, names64, names32, u_ref, mixed=True):
     out["banded_fp64"] = {
         "solves_per_s": 1.0 / br["seconds"], "iters": br["stats"].iters, "relres": br["stats"].relres,
         "subdomain_solve_gbs": solve_gbs(br["kernels"], [names64[hbj.K_FWD], names64[hbj.K_BWD]]),
-        "roofline": roofline_of(br["kernels"], wl.name + "/banded")}
+        "roofline": roofline_of(br["kernels"], wl.name + "/banded"), "solve_tuning": br["solve_tuning"]}
     out["banded_fp64"]["subdomain_solve_frac_of_hbm_peak"] = out["banded_fp64"]["subdomain_solve_gbs"] / HBM_PEAK_GBS
     log(f"[bench]   {br['seconds'] * 1e3:.1f} ms per solve, subdomain solves "
         f"{out['banded_fp64']['subdomain_solve_gbs']:.0f} GB/s")
@@ -565,7 +579,8 @@ def banded_legs(hbj, wl, mt, ft, u, tol, names64, names32, u_ref, mixed=True):
         out["banded_mixed"] = {
             "solves_per_s": 1.0 / mb["seconds"], "iters": mb["stats"].iters,
             "local_ir_max": mb["stats"].local_ir_max, "local_ir_resid": mb["stats"].local_ir_resid,
-            "subdomain_solve_gbs": solve_gbs(mb["kernels"], [names32[hbj.K_FWD], names32[hbj.K_BWD]])}
+            "subdomain_solve_gbs": solve_gbs(mb["kernels"], [names32[hbj.K_FWD], names32[hbj.K_BWD]]),
+            "solve_tuning": mb["solve_tuning"]}
         out["banded_mixed"]["subdomain_solve_frac_of_hbm_peak"] = \
             out["banded_mixed"]["subdomain_solve_gbs"] / HBM_PEAK_GBS
         if u_ref is not None:
@@ -687,6 +702,10 @@ def main():
         result["reference_solve_tol1e-12"] = {"iters": st_ref.iters, "relres": st_ref.relres}
     if main_run["tuning"]:
         result["autotuned_operator_tiles"] = main_run["tuning"]
+    # launch shapes of the banded solve batches (at factor time: the unit-datum solves that form the
+    # dense operators), chosen by the autotuner or read from its cache file
+    result["solve_tuning"] = main_run["solve_tuning"]
+    result["factor_first_s"] = main_run["factor_first_s"]
     # the dense operators come from one banded solve per interface position (16 per workgroup on
     # MFMA by default); the same factorisation with one workgroup per solve, for comparison
     result["factor_s_one_solve_per_workgroup"] = factor_seconds(hbj, wl, mt, headline_prec, args.transmission,

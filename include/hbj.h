@@ -56,6 +56,7 @@ enum {
   HBJ_ENOMEM = -4,         /* device allocation failed                         */
   HBJ_EWAIT = -5,          /* a dataflow sweep's dependency wait exceeded its
                               poll limit; the outputs of the call are invalid  */
+  HBJ_EIO = -6,            /* the tuning cache file could not be written       */
   HBJ_ZERO_PIVOT = 1,      /* exactly singular local matrix (see hbj_factor)   */
   HBJ_NOT_CONVERGED = 2    /* GMRES hit maxit; outputs hold the last iterate   */
 };
@@ -407,6 +408,70 @@ int hbj_set_multi_solve(hbj_ctx* ctx, int32_t mode);
  *   us        HOST [4][12] or NULL: the measured microseconds per launch.
  */
 int hbj_get_tuning(const hbj_ctx* ctx, int32_t* variants, float* us);
+
+/*
+ * Autotuned launch shapes of the banded local solves (Sec. 4: every application of the
+ * operator, of the preconditioner, the lifting and the reconstruction in the banded form, and
+ * the formation of the dense operators at hbj_factor, is a batch of local solves
+ * u = A_s^{-1} rhs).  A batch runs in one of four launch shapes:
+ *   0, 1, 2  one workgroup per (subdomain, right-hand side) with register prefetch depths
+ *            (column blocks of the factors in flight per lane) forward/backward of 5/3, 3/2
+ *            and 6/3 for complex128 factors, 8/4, 4/3 and 10/6 for complex64;
+ *   3        16 right-hand sides of one subdomain per workgroup on MFMA (only for batches
+ *            with many right-hand sides per subdomain and HBJ_MSOLVE_MFMA).
+ * All give the same solutions up to rounding (shapes 0-2 bit for bit).  On the first batch of
+ * each class - precision, subdomain size and band, number of solves (by powers of two) and
+ * right-hand sides per subdomain (1, 2-3, 4-7, 8-15, 16) - the library times every candidate
+ * on that batch's own data (writing only its solve workspace; a candidate at more than twice
+ * the best time after the first round drops out), keeps the fastest, and records it in the
+ * tuning cache file, so later contexts and processes reuse it without timing.  Without timing
+ * (environment HBJ_TUNE=0, or inside a graph capture) a batch takes shape 3 where it averages at
+ * least 8 right-hand sides per 16-wide tile, else shape 0.
+ */
+
+/*
+ * hbj_set_solve_tuning - fix the launch shape of every banded solve batch of this context
+ * (tests of every shape, reproducible timings): 0..3 as above (3 falls back to 0 where the MFMA
+ * solves do not apply), or -1 to choose by timing (default).  Returns HBJ_EINVAL for any other
+ * value.
+ */
+int hbj_set_solve_tuning(hbj_ctx* ctx, int32_t shape);
+
+/*
+ * hbj_get_solve_tuning - the choices made so far by this context, one per batch class.
+ *   n        HOST in: capacity of the arrays; out: number of classes (may exceed the capacity:
+ *            only the first min(capacity, number) are written).
+ *   keys     HOST [capacity][96] or NULL: each class's cache key, NUL-terminated.
+ *   shapes   HOST [capacity] or NULL: the chosen shape.
+ *   us       HOST [capacity][4] or NULL: microseconds per candidate (0: not timed; the choice
+ *            came from the cache file or was fixed).
+ */
+int hbj_get_solve_tuning(const hbj_ctx* ctx, int32_t* n, char* keys, int32_t* shapes, float* us);
+
+/*
+ * The tuning cache file (host code; no GPU is needed for these calls).  One JSON object,
+ *   {"version": 1, "entries": {"<key>": {"variant": v, "us": [t0, ...]}, ...}},
+ * read once per process and rewritten (merged with the file, then an atomic rename) after each
+ * new decision.  Location: hbj_tune_cache_set_path, else the environment variable
+ * HBJ_TUNE_CACHE ("" or "off": no file), else $XDG_CACHE_HOME/hbj/tune.json, else
+ * $HOME/.cache/hbj/tune.json.  A file that does not parse counts as empty.
+ *
+ * hbj_tune_cache_path       the file in use ("" = none); the string stays valid until the next
+ *                           call from the same thread.
+ * hbj_tune_cache_set_path   use `path` from now on (NULL: the default rule above; "": no file)
+ *                           and (re)read it.
+ * hbj_tune_cache_lookup     1 and *variant set if `key` is cached, else 0; HBJ_EINVAL for NULL.
+ * hbj_tune_cache_store      record key -> (variant, us[0..n-1]) and rewrite the file; keys are
+ *                           1-200 characters of [A-Za-z0-9_.:|-], 0 <= n <= 64.  HBJ_EINVAL for
+ *                           a bad key or size, HBJ_EIO if the file could not be written (the
+ *                           entry is kept in memory).
+ * hbj_tune_cache_size       number of entries in memory.
+ */
+const char* hbj_tune_cache_path(void);
+int hbj_tune_cache_set_path(const char* path);
+int hbj_tune_cache_lookup(const char* key, int32_t* variant);
+int hbj_tune_cache_store(const char* key, int32_t variant, const float* us, int32_t n);
+int32_t hbj_tune_cache_size(void);
 
 /*
  * hbj_set_tuning - fix the variants of the many-right-hand-side operator kernel

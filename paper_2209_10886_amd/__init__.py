@@ -34,7 +34,12 @@ OP_BANDED, OP_DENSE = 0, 1
 SWEEP_STEPPED, SWEEP_DATAFLOW = 0, 1
 ORTH_CGS2, ORTH_DCGS2 = 0, 1  # Gram-Schmidt variant of the Arnoldi steps
 MSOLVE_CHAINS, MSOLVE_MFMA = 0, 1  # banded solves of many right-hand sides per subdomain
-OK, EINVAL, ESTATE, EHIP, ENOMEM, EWAIT, ZERO_PIVOT, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, 1, 2
+OK, EINVAL, ESTATE, EHIP, ENOMEM, EWAIT, EIO, ZERO_PIVOT, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, -6, 1, 2
+# launch shapes of the banded solve batches (hbj_set_solve_tuning): one workgroup per solve at three
+# register prefetch depths, or 16 right-hand sides per workgroup on MFMA
+SOLVE_SHAPES = ("workgroup per solve, depth 0", "workgroup per solve, depth 1", "workgroup per solve, depth 2",
+                "MFMA tiles of 16 right-hand sides")
+SOLVE_SHAPE_MFMA = 3
 VR_NOALLOC_MAX_RHS = 64  # right-hand sides the allocation-free residual's static scratch holds
 K_FWD, K_BWD, K_FACTOR, K_KRYLOV, K_SCATTER, K_SWEEP, K_LIFT, K_OPERATOR = 0, 1, 2, 3, 4, 5, 6, 7
 
@@ -92,6 +97,14 @@ _SIGS = {
     "hbj_set_sweep_wait": (_I, [_P, _I32, _I32]),
     "hbj_get_tuning": (_I, [_P, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)]),
     "hbj_set_tuning": (_I, [_P, ctypes.POINTER(_I32)]),
+    "hbj_set_solve_tuning": (_I, [_P, _I32]),
+    "hbj_get_solve_tuning": (_I, [_P, ctypes.POINTER(_I32), ctypes.c_char_p, ctypes.POINTER(_I32),
+                                  ctypes.POINTER(ctypes.c_float)]),
+    "hbj_tune_cache_path": (ctypes.c_char_p, []),
+    "hbj_tune_cache_set_path": (_I, [ctypes.c_char_p]),
+    "hbj_tune_cache_lookup": (_I, [ctypes.c_char_p, ctypes.POINTER(_I32)]),
+    "hbj_tune_cache_store": (_I, [ctypes.c_char_p, _I32, ctypes.POINTER(ctypes.c_float), _I32]),
+    "hbj_tune_cache_size": (_I32, []),
     "hbj_set_graphs": (_I, [_P, _I32]),
     "hbj_set_orthogonalization": (_I, [_P, _I32]),
     "hbj_set_multi_solve": (_I, [_P, _I32]),
@@ -349,9 +362,64 @@ class Context:
         v = (_I32 * 4)(*[int(x) for x in variants])
         _check(_lib.hbj_set_tuning(self._h, v))
 
+    def set_solve_tuning(self, shape):
+        """Fix the launch shape of every banded solve batch (0-2: one workgroup per solve at the three
+        prefetch depths, 3: MFMA tiles where they apply), or -1 to choose per batch class by timing."""
+        _check(_lib.hbj_set_solve_tuning(self._h, int(shape)))
+
+    def solve_tuning(self):
+        """The launch shapes chosen so far, per batch class: {key: {"shape": s, "us": [per shape]}}
+        (us 0: not timed here, the choice came from the tuning cache file or was fixed)."""
+        n = _I32(0)
+        _check(_lib.hbj_get_solve_tuning(self._h, ctypes.byref(n), None, None, None))
+        cap = n.value
+        if cap == 0:
+            return {}
+        keys = ctypes.create_string_buffer(96 * cap)
+        shapes = (_I32 * cap)()
+        us = (ctypes.c_float * (4 * cap))()
+        n = _I32(cap)
+        _check(_lib.hbj_get_solve_tuning(self._h, ctypes.byref(n), keys, shapes, us))
+        out = {}
+        for i in range(min(cap, n.value)):
+            key = keys.raw[96 * i:96 * (i + 1)].split(b"\0", 1)[0].decode()
+            out[key] = {"shape": int(shapes[i]), "us": [round(us[4 * i + j], 2) for j in range(4)]}
+        return out
+
     def set_sweep_wait(self, max_polls=0, stall_task=-1):
         """Bounds of the dataflow sweeps' dependency waits (error-path tests)."""
         _check(_lib.hbj_set_sweep_wait(self._h, max_polls, stall_task))
+
+
+def tune_cache_path():
+    """The tuning cache file in use ("" = none)."""
+    return _lib.hbj_tune_cache_path().decode()
+
+
+def set_tune_cache_path(path):
+    """Use `path` as the tuning cache file (None: the default rule, "": no file) and read it."""
+    _check(_lib.hbj_tune_cache_set_path(None if path is None else str(path).encode()))
+
+
+def tune_cache_lookup(key):
+    """The cached variant for `key`, or None."""
+    v = _I32(0)
+    r = _lib.hbj_tune_cache_lookup(key.encode(), ctypes.byref(v))
+    if r < 0:
+        raise HbjError(r, f"tuning cache lookup {key!r}")
+    return int(v.value) if r == 1 else None
+
+
+def tune_cache_store(key, variant, us=()):
+    """Record key -> (variant, us) in the tuning cache and rewrite its file."""
+    arr = (ctypes.c_float * max(1, len(us)))(*[float(x) for x in us])
+    r = _lib.hbj_tune_cache_store(key.encode(), int(variant), arr, len(us))
+    if r != OK:
+        raise HbjError(r, f"tuning cache entry {key!r}")
+
+
+def tune_cache_size():
+    return int(_lib.hbj_tune_cache_size())
 
 
 def setup(nx, ny, k, n1, n2, c=None, m=None, h=0.0, precision=FP64, precond=PC_BJ, bj_width=0,

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/hbj.h"
 
 // ---------------------------------------------------------------------------
@@ -241,15 +243,23 @@ hipError_t launch_repack(const Geom& g, const SolveLayout& L, const double2* ab,
 hipError_t launch_cast_c64(const double2* src, float2* dst, size_t n, hipStream_t st);
 
 void solve_column_groups(int wf, int wb, int* cgf, int* cgb);
+// Process-wide cache of autotuned choices, persisted as a JSON file (tune_cache.cpp).
+bool tune_cache_get(const std::string& key, int* variant);
+bool tune_cache_put(const std::string& key, int variant, const float* us, int n);
+
+// One workgroup per (subdomain, right-hand side).  dv selects the register prefetch depth
+// (0: default; 1, 2: the alternatives the autotuner times); every depth gives the same result.
+constexpr int kSolveDepthVariants = 3;
+int solve_depth(bool fwd, size_t real_bytes, int dv);
 template <typename R>
 hipError_t launch_fwd(const Geom& g, const SolveLayout& L, const Entry* ent, int nent, const FaceTab* ft,
                       const IfCoef* coef, const typename Cplx<R>::T* mf, const int16_t* pf, const int32_t* pflag,
                       const SolveIO& io,
-                      typename Cplx<R>::T* ybuf, hipStream_t st);
+                      typename Cplx<R>::T* ybuf, hipStream_t st, int dv = 0);
 template <typename R>
 hipError_t launch_bwd(const Geom& g, const SolveLayout& L, const Entry* ent, int nent, const FaceTab* ft,
                       const IfCoef* coef, const typename Cplx<R>::T* mb, const SolveIO& io,
-                      typename Cplx<R>::T* ybuf, hipStream_t st);
+                      typename Cplx<R>::T* ybuf, hipStream_t st, int dv = 0);
 
 // The same solves for tiles of up to 16 entries of one subdomain (tiles[t] = {first entry, count},
 // entries of a tile consecutive and with the same subdomain), 16 right-hand sides per workgroup on

@@ -425,16 +425,22 @@ __global__ __launch_bounds__(1024) void k_pade_lift(Geom g, const FaceTab* ft, c
   }
   __syncthreads();
   const double2* Gs = Ginv + (size_t)s * L * L;
+  constexpr int QU = 8;  // rows of G^-1 whose loads are in flight together
   for (int c = threadIdx.x; c < L; c += blockDim.x) {
     double2 acc[PRB];
 #pragma unroll
     for (int k = 0; k < PRB; ++k) acc[k] = mk(0.0, 0.0);
     if (any)
-      for (int q = 0; q < L; ++q) {
-        const double2 gv = Gs[(size_t)q * L + c];
+      for (int q0 = 0; q0 < L; q0 += QU) {
+        double2 gv[QU];
 #pragma unroll
-        for (int k = 0; k < PRB; ++k)
-          if (k < nr) cfma(acc[k], gv, y[k][q]);
+        for (int u = 0; u < QU; ++u) gv[u] = Gs[(size_t)min(q0 + u, L - 1) * L + c];
+#pragma unroll
+        for (int u = 0; u < QU; ++u)
+          if (q0 + u < L)
+#pragma unroll
+            for (int k = 0; k < PRB; ++k)
+              if (k < nr) cfma(acc[k], gv[u], y[k][q0 + u]);
       }
 #pragma unroll
     for (int k = 0; k < PRB; ++k) yp[k][c] = acc[k];

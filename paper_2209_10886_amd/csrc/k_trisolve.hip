@@ -852,52 +852,88 @@ void solve_column_groups(int wf, int wb, int* cgf, int* cgb) {
   *cgb = (wb * 2 <= 576) ? 2 : 1;
 }
 
+// Register prefetch depth (column blocks in flight per lane) of the one-workgroup-per-solve
+// kernels, per precision and depth variant; variant 0 is the default, the autotuner times the
+// others.  Every depth keeps the kernels within the registers of three wavefronts per SIMD (the
+// 576-thread workgroup) without spills: the complex128 backward kernel has no third depth (at 4
+// it spills), so its variant 2 repeats the default.
+constexpr int kFwdDepth[2][kSolveDepthVariants] = {{5, 3, 6}, {8, 4, 10}};  // [double, float]
+constexpr int kBwdDepth[2][kSolveDepthVariants] = {{3, 2, 3}, {4, 3, 6}};
+
+int solve_depth(bool fwd, size_t real_bytes, int dv) {
+  if (dv < 0 || dv >= kSolveDepthVariants) dv = 0;
+  return (fwd ? kFwdDepth : kBwdDepth)[real_bytes == 8 ? 0 : 1][dv];
+}
+
 template <typename R>
 hipError_t launch_fwd(const Geom& g, const SolveLayout& L, const Entry* ent, int nent, const FaceTab* ft,
                       const IfCoef* coef, const typename Cplx<R>::T* mf, const int16_t* pf, const int32_t* pflag,
-                      const SolveIO& io, typename Cplx<R>::T* ybuf, hipStream_t st) {
+                      const SolveIO& io, typename Cplx<R>::T* ybuf, hipStream_t st, int dv) {
   typedef typename Cplx<R>::T C;
   if (nent == 0) return hipSuccess;
   if (L.nb != 16 || L.wf > 576) return hipErrorInvalidValue;
   const size_t shm = 2 * (size_t)L.wf * sizeof(C) + (size_t)L.nblk * sizeof(int);
   const int rows = L.wf * L.cgf;
   const dim3 blk(((rows + 63) / 64) * 64);
-  if (L.cgf == 4)
-    hipLaunchKernelGGL((k_fwd<R, 16, 4, (sizeof(R) == 8 ? 5 : 8)>), dim3(nent), blk, shm, st, g, L, ent, ft, coef, mf,
-                       pf, pflag, io, ybuf);
-  else
-    hipLaunchKernelGGL((k_fwd<R, 16, 1, 1>), dim3(nent), blk, shm, st, g, L, ent, ft, coef, mf, pf, pflag, io, ybuf);
+#define HBJ_FWD(CG, D) \
+  hipLaunchKernelGGL((k_fwd<R, 16, CG, D>), dim3(nent), blk, shm, st, g, L, ent, ft, coef, mf, pf, pflag, io, ybuf)
+  if (L.cgf == 4) {
+    const int d = solve_depth(true, sizeof(R), dv);
+    if constexpr (sizeof(R) == 8) {
+      if (d == 3) HBJ_FWD(4, 3);
+      else if (d == 6) HBJ_FWD(4, 6);
+      else HBJ_FWD(4, 5);
+    } else {
+      if (d == 4) HBJ_FWD(4, 4);
+      else if (d == 10) HBJ_FWD(4, 10);
+      else HBJ_FWD(4, 8);
+    }
+  } else {
+    HBJ_FWD(1, 1);
+  }
+#undef HBJ_FWD
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_bwd(const Geom& g, const SolveLayout& L, const Entry* ent, int nent, const FaceTab* ft,
                       const IfCoef* coef, const typename Cplx<R>::T* mb, const SolveIO& io,
-                      typename Cplx<R>::T* ybuf, hipStream_t st) {
+                      typename Cplx<R>::T* ybuf, hipStream_t st, int dv) {
   typedef typename Cplx<R>::T C;
   if (nent == 0) return hipSuccess;
   if (L.nb != 16 || L.wb > 576) return hipErrorInvalidValue;
   const size_t shm = 2 * (size_t)L.wb * sizeof(C);
   const int rows = L.wb * L.cgb;
   const dim3 blk(((rows + 63) / 64) * 64);
-  if (L.cgb == 2)
-    hipLaunchKernelGGL((k_bwd<R, 16, 2, (sizeof(R) == 8 ? 3 : 4)>), dim3(nent), blk, shm, st, g, L, ent, ft, coef, mb,
-                       io, ybuf);
-  else
-    hipLaunchKernelGGL((k_bwd<R, 16, 1, 1>), dim3(nent), blk, shm, st, g, L, ent, ft, coef, mb, io, ybuf);
+#define HBJ_BWD(CG, D) \
+  hipLaunchKernelGGL((k_bwd<R, 16, CG, D>), dim3(nent), blk, shm, st, g, L, ent, ft, coef, mb, io, ybuf)
+  if (L.cgb == 2) {
+    const int d = solve_depth(false, sizeof(R), dv);
+    if constexpr (sizeof(R) == 8) {
+      if (d == 2) HBJ_BWD(2, 2);
+      else HBJ_BWD(2, 3);
+    } else {
+      if (d == 3) HBJ_BWD(2, 3);
+      else if (d == 6) HBJ_BWD(2, 6);
+      else HBJ_BWD(2, 4);
+    }
+  } else {
+    HBJ_BWD(1, 1);
+  }
+#undef HBJ_BWD
   return hipGetLastError();
 }
 
 template hipError_t launch_fwd<double>(const Geom&, const SolveLayout&, const Entry*, int, const FaceTab*,
                                        const IfCoef*, const double2*, const int16_t*, const int32_t*, const SolveIO&,
-                                       double2*, hipStream_t);
+                                       double2*, hipStream_t, int);
 template hipError_t launch_fwd<float>(const Geom&, const SolveLayout&, const Entry*, int, const FaceTab*,
                                       const IfCoef*, const float2*, const int16_t*, const int32_t*, const SolveIO&,
-                                      float2*, hipStream_t);
+                                      float2*, hipStream_t, int);
 template hipError_t launch_bwd<double>(const Geom&, const SolveLayout&, const Entry*, int, const FaceTab*,
-                                       const IfCoef*, const double2*, const SolveIO&, double2*, hipStream_t);
+                                       const IfCoef*, const double2*, const SolveIO&, double2*, hipStream_t, int);
 template hipError_t launch_bwd<float>(const Geom&, const SolveLayout&, const Entry*, int, const FaceTab*,
-                                      const IfCoef*, const float2*, const SolveIO&, float2*, hipStream_t);
+                                      const IfCoef*, const float2*, const SolveIO&, float2*, hipStream_t, int);
 
 constexpr int kMmSpwMax = 5;  // window tiles per wavefront of the MFMA solves: windows of up to 20 tiles
 

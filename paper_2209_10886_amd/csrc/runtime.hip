@@ -15,6 +15,9 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cctype>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -43,6 +46,11 @@ typedef std::complex<double> zc;
 // faces written by a forward sweep step (toward +x, +y) and by a backward step (toward -x, -y)
 constexpr int kMaskFwd = (1 << FACE_E) | (1 << FACE_N);
 constexpr int kMaskBwd = (1 << FACE_W) | (1 << FACE_S);
+
+// launch shapes of a batch of banded local solves: one workgroup per solve at the prefetch depth
+// variants of the solve kernels, then 16 right-hand sides of one subdomain per workgroup on MFMA
+constexpr int kShapeMfma = kSolveDepthVariants;
+constexpr int kSolveShapes = kSolveDepthVariants + 1;
 
 struct Step {
   size_t first;  // offset into the schedule's device entry array
@@ -168,6 +176,14 @@ struct hbj_ctx {
   // [complex128 steps, complex128 operator, complex64 steps, complex64 operator]; -1 = not tuned
   int mm_variant[4] = {-1, -1, -1, -1};
   float mm_us[4][kMmVariants] = {};
+  // autotuned launch shapes of the banded solve batches, per batch class (its cache key)
+  struct SolveChoice {
+    int shape = 0;
+    float us[kSolveShapes] = {};
+  };
+  std::map<std::string, SolveChoice> solve_choice;
+  int solve_shape_fixed = -1;  // hbj_set_solve_tuning: -1 = by timing
+  std::string arch;            // device architecture name (cache keys)
   int32_t* nzf = nullptr;   // per (rhs, subdomain) nonzero-source flags for the lifting
   size_t nzf_cap = 0;
   double2* pc_y = nullptr;  // preconditioner pass buffers [nrhs][nif]
@@ -501,11 +517,12 @@ struct ProfScope {
   hbj_ctx* c;
   int kclass;
   double bytes, flops;
-  ProfScope(hbj_ctx* c_, int k, double b, double f) : c(c_), kclass(k), bytes(b), flops(f) {
-    if (c->prof) (void)hipEventRecord(c->ev0, c->st);
+  bool on;  // false: a launch of the autotuner, not counted (the events are the autotuner's)
+  ProfScope(hbj_ctx* c_, int k, double b, double f, bool on_ = true) : c(c_), kclass(k), bytes(b), flops(f), on(on_) {
+    if (c->prof && on) (void)hipEventRecord(c->ev0, c->st);
   }
   ~ProfScope() {
-    if (!c->prof) return;
+    if (!c->prof || !on) return;
     (void)hipEventRecord(c->ev1, c->st);
     (void)hipEventSynchronize(c->ev1);
     float ms = 0.f;
@@ -525,35 +542,139 @@ double bwd_bytes(const hbj_ctx* c, size_t elem) { return (double)c->g.nloc * (c-
 // ---------------------------------------------------------------------------
 // batched local solves
 // ---------------------------------------------------------------------------
-// launches with at least this many entries per tile on average run the MFMA solves
+// without timing, batches with at least this many entries per tile on average run the MFMA solves
 constexpr int kMmMinPerTile = 8;
 
-// forward and backward solves of a batch into the solve buffer: 16 right-hand sides of one
-// subdomain per workgroup on MFMA (factors read once per tile) where the batch has many
-// right-hand sides per subdomain, else one workgroup per solve
+// the forward and backward solves of a batch in launch shape `shape` into the solve buffer
+template <typename R>
+hipError_t solve_pair_shape(hbj_ctx* c, int shape, const Entry* ent, int nent, const int2* tiles, int ntiles,
+                            const SolveIO& io, const typename Cplx<R>::T* mf, const typename Cplx<R>::T* mb,
+                            bool prof) {
+  typedef typename Cplx<R>::T C;
+  const bool mm = shape == kShapeMfma;
+  const double nread = mm ? (double)ntiles : (double)nent;
+  C* sink = (C*)c->ybuf + (size_t)nent * c->L.nblk * c->L.nb;  // the solve buffer holds one spare entry
+  hipError_t e;
+  {
+    ProfScope ps(c, HBJ_K_FWD, nread * fwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * c->g.kl, prof);
+    e = mm ? launch_fwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mf, c->pf, c->pflag, c->interchanges,
+                              io, (C*)c->ybuf, sink, c->st)
+           : launch_fwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mf, c->pf, c->pflag, io, (C*)c->ybuf, c->st, shape);
+  }
+  if (e != hipSuccess) return e;
+  {
+    ProfScope ps(c, HBJ_K_BWD, nread * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1), prof);
+    e = mm ? launch_bwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mb, io, (C*)c->ybuf, sink, c->st)
+           : launch_bwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st, shape);
+  }
+  return e;
+}
+
+// average right-hand sides per 16-wide tile of a batch (rounded up)
+int per_tile(int nent, int ntiles) { return ntiles > 0 ? (nent + ntiles - 1) / ntiles : 0; }
+
+// cache key of a batch class: device, precision, subdomain and band, interchanges, number of
+// solves (next power of two) and average right-hand sides per subdomain tile (1, 2, 4, 8, 16)
+std::string solve_class_key(const hbj_ctx* c, size_t elem, int nent, int ntiles, bool mm_ok) {
+  int n2 = 1;
+  while (n2 < nent) n2 *= 2;
+  const int per = mm_ok ? per_tile(nent, ntiles) : 1;
+  const int pb = per >= 16 ? 16 : per >= 8 ? 8 : per >= 4 ? 4 : per >= 2 ? 2 : 1;
+  char buf[160];
+  std::snprintf(buf, sizeof buf, "solve|%s|%s|%dx%d|kl%d|ku%d|p%d|n%d|r%d|%s", c->arch.c_str(),
+                elem == 16 ? "c128" : "c64", c->g.snx, c->g.sny, c->g.kl, c->g.ku, c->interchanges ? 1 : 0, n2, pb,
+                mm_ok ? "mm" : "wg");
+  return std::string(buf);
+}
+
+bool tuning_enabled(const hbj_ctx* c) {
+  const char* env = std::getenv("HBJ_TUNE");
+  if (env && std::strcmp(env, "0") == 0) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(c->st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+  return true;
+}
+
+// autotuner of the banded solve batches: every candidate shape runs on this batch's own data
+// with the outputs switched off (only the solve buffer is written), once to warm up and to drop
+// candidates at more than twice the best time, then three rounds in turns; the fastest wins
+template <typename R>
+int time_solve_shapes(hbj_ctx* c, const Entry* ent, int nent, const int2* tiles, int ntiles, const SolveIO& io,
+                      const typename Cplx<R>::T* mf, const typename Cplx<R>::T* mb, bool mm_ok,
+                      hbj_ctx::SolveChoice& ch) {
+  HIPCHK(hipDeviceSynchronize());  // the side stream may still run a reconstruction's source part
+  SolveIO tio = io;
+  tio.u = nullptr;
+  tio.x64 = nullptr;
+  tio.tr_dst = nullptr;
+  bool alive[kSolveShapes];
+  float first[kSolveShapes] = {}, tot[kSolveShapes] = {};
+  for (int v = 0; v < kSolveShapes; ++v) alive[v] = (v != kShapeMfma) || mm_ok;
+  auto timed = [&](int v, float* ms) -> hipError_t {
+    hipError_t e = hipEventRecord(c->ev0, c->st);
+    if (e == hipSuccess) e = solve_pair_shape<R>(c, v, ent, nent, tiles, ntiles, tio, mf, mb, false);
+    if (e == hipSuccess) e = hipEventRecord(c->ev1, c->st);
+    if (e == hipSuccess) e = hipEventSynchronize(c->ev1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, c->ev0, c->ev1);
+    return e;
+  };
+  float best = 1e30f;
+  for (int v = 0; v < kSolveShapes; ++v) {
+    if (!alive[v]) continue;
+    HIPCHK(timed(v, &first[v]));
+    best = std::min(best, first[v]);
+  }
+  for (int v = 0; v < kSolveShapes; ++v)
+    if (alive[v] && first[v] > 2.0f * best) alive[v] = false;
+  for (int rep = 0; rep < 3; ++rep)
+    for (int v = 0; v < kSolveShapes; ++v) {
+      if (!alive[v]) continue;
+      float ms = 0.f;
+      HIPCHK(timed(v, &ms));
+      tot[v] += ms;
+    }
+  int pick = -1;
+  for (int v = 0; v < kSolveShapes; ++v) {
+    ch.us[v] = alive[v] ? tot[v] / 3.0f * 1e3f : first[v] * 1e3f;
+    if (alive[v] && (pick < 0 || tot[v] < tot[pick])) pick = v;
+  }
+  ch.shape = pick < 0 ? 0 : pick;
+  return HBJ_OK;
+}
+
+// forward and backward solves of a batch into the solve buffer, in the launch shape chosen for
+// the batch's class: fixed by hbj_set_solve_tuning, chosen earlier in this process, read from
+// the tuning cache file, or timed now
 template <typename R>
 int launch_solve_pair(hbj_ctx* c, const Entry* ent, int nent, const int2* tiles, int ntiles, const SolveIO& io,
                       const typename Cplx<R>::T* mf, const typename Cplx<R>::T* mb) {
   typedef typename Cplx<R>::T C;
-  const bool mm = c->msolve == HBJ_MSOLVE_MFMA && tiles && ntiles > 0 && nent >= kMmMinPerTile * ntiles &&
-                  trisolve_mm_fits(c->L, sizeof(C));
-  const double nread = mm ? (double)ntiles : (double)nent;
-  C* sink = (C*)c->ybuf + (size_t)nent * c->L.nblk * c->L.nb;  // the solve buffer holds one spare entry
-  {
-    ProfScope ps(c, HBJ_K_FWD, nread * fwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * c->g.kl);
-    if (mm)
-      HIPCHK((launch_fwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mf, c->pf, c->pflag, c->interchanges,
-                               io, (C*)c->ybuf, sink, c->st)));
-    else
-      HIPCHK((launch_fwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mf, c->pf, c->pflag, io, (C*)c->ybuf, c->st)));
+  const bool mm_ok = c->msolve == HBJ_MSOLVE_MFMA && tiles && ntiles > 0 && trisolve_mm_fits(c->L, sizeof(C));
+  int shape;
+  if (c->solve_shape_fixed >= 0) {
+    shape = (c->solve_shape_fixed == kShapeMfma && !mm_ok) ? 0 : c->solve_shape_fixed;
+  } else {
+    const std::string key = solve_class_key(c, sizeof(C), nent, ntiles, mm_ok);
+    auto it = c->solve_choice.find(key);
+    if (it != c->solve_choice.end()) {
+      shape = it->second.shape;
+    } else {
+      hbj_ctx::SolveChoice ch;
+      int v = -1;
+      if (tune_cache_get(key, &v) && v >= 0 && v < kSolveShapes && (v != kShapeMfma || mm_ok)) {
+        ch.shape = v;
+      } else if (tuning_enabled(c)) {
+        int rc = time_solve_shapes<R>(c, ent, nent, tiles, ntiles, io, mf, mb, mm_ok, ch);
+        if (rc) return rc;
+        tune_cache_put(key, ch.shape, ch.us, kSolveShapes);  // a file that cannot be written only loses the cache
+      } else {
+        ch.shape = (mm_ok && per_tile(nent, ntiles) >= kMmMinPerTile) ? kShapeMfma : 0;
+      }
+      c->solve_choice[key] = ch;
+      shape = ch.shape;
+    }
   }
-  {
-    ProfScope ps(c, HBJ_K_BWD, nread * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1));
-    if (mm)
-      HIPCHK((launch_bwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mb, io, (C*)c->ybuf, sink, c->st)));
-    else
-      HIPCHK((launch_bwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st)));
-  }
+  HIPCHK(solve_pair_shape<R>(c, shape, ent, nent, tiles, ntiles, io, mf, mb, true));
   return HBJ_OK;
 }
 
@@ -1823,6 +1944,7 @@ const char* hbj_strerror(int code) {
     case HBJ_ESTATE: return "call out of order";
     case HBJ_EHIP: return "HIP runtime error";
     case HBJ_EWAIT: return "dataflow dependency wait exceeded its limit";
+    case HBJ_EIO: return "tuning cache file could not be written";
     case HBJ_ENOMEM: return "out of device memory";
     case HBJ_ZERO_PIVOT: return "exactly singular local matrix";
     case HBJ_NOT_CONVERGED: return "GMRES did not converge";
@@ -1884,6 +2006,14 @@ int hbj_setup(const hbj_problem* prob, const double* c_dev, void* stream, hbj_ct
   c->st = (hipStream_t)stream;
   HIPCHK(hipGetDevice(&c->dev));
   HIPCHK(volume_residual_scratch_init(c->dev));
+  {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, c->dev));
+    c->arch = prop.gcnArchName;
+    c->arch = c->arch.substr(0, c->arch.find(':'));  // gfx950 from gfx950:sramecc+:xnack-
+    for (char& ch : c->arch)
+      if (!std::isalnum((unsigned char)ch)) ch = '_';
+  }
   Geom& g = c->g;
   g.nx = P.nx;
   g.ny = P.ny;
@@ -2528,6 +2658,33 @@ int hbj_set_multi_solve(hbj_ctx* c, int32_t mode) {
   if (mode != HBJ_MSOLVE_CHAINS && mode != HBJ_MSOLVE_MFMA) return fail(HBJ_EINVAL, "unknown multi-solve mode");
   if (mode != c->msolve) ++c->graph_epoch;  // the captured steps hold the other kernels
   c->msolve = mode;
+  return HBJ_OK;
+}
+
+int hbj_set_solve_tuning(hbj_ctx* c, int32_t shape) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  if (shape < -1 || shape >= kSolveShapes) return fail(HBJ_EINVAL, "solve launch shape out of range");
+  c->solve_shape_fixed = shape;
+  return HBJ_OK;
+}
+
+int hbj_get_solve_tuning(const hbj_ctx* c, int32_t* n, char* keys, int32_t* shapes, float* us) {
+  if (!c || !n || *n < 0) return fail(HBJ_EINVAL, "bad arguments");
+  const int cap = *n;
+  int i = 0;
+  for (const auto& kv : c->solve_choice) {
+    if (i < cap) {
+      if (keys) {
+        std::strncpy(keys + (size_t)i * 96, kv.first.c_str(), 95);
+        keys[(size_t)i * 96 + 95] = 0;
+      }
+      if (shapes) shapes[i] = kv.second.shape;
+      if (us)
+        for (int v = 0; v < kSolveShapes; ++v) us[(size_t)i * kSolveShapes + v] = kv.second.us[v];
+    }
+    ++i;
+  }
+  *n = i;
   return HBJ_OK;
 }
 

@@ -53,12 +53,25 @@ def banded(hbj):
         v[4].close()
 
 
+# Bound on the relative error against the oracle of the banded solves of a case (both launch shapes).
+# 1e-12 everywhere except the pivoting case: about 3 points per wavelength, so its local matrices are
+# the worst conditioned and the rounding of the elimination grows accordingly.
+CASE_TOL = {"pivot": 1e-10}
+
+
+def _tol(name):
+    return CASE_TOL.get(name, 1e-12)
+
+
 def _both_modes(hbj, ctx, fn):
+    """fn() with every batch on the MFMA tiles, then with one workgroup per solve (depths as tuned)."""
     out = {}
     for mode in (hbj.MSOLVE_MFMA, hbj.MSOLVE_CHAINS):
         ctx.set_multi_solve(mode)
+        ctx.set_solve_tuning(hbj.SOLVE_SHAPE_MFMA if mode == hbj.MSOLVE_MFMA else -1)
         out[mode] = fn()
     ctx.set_multi_solve(hbj.MSOLVE_MFMA)
+    ctx.set_solve_tuning(-1)
     return out[hbj.MSOLVE_MFMA], out[hbj.MSOLVE_CHAINS]
 
 
@@ -83,11 +96,9 @@ def test_many_rhs_operator_lifting_reconstruction(hbj, banded, name):
         ea = max(rel(a[k], r[k]) for k in range(NRHS))
         ec = max(rel(c[k], r[k]) for k in range(NRHS))
         say(f"  {what}: MFMA {ea:.1e}, one workgroup per solve {ec:.1e} vs oracle; between them {rel(a, c):.1e}")
-        # 1e-12, or the error of the one-solve-per-workgroup kernels on the same data where the
-        # local problems are worse conditioned (the pivoting case, about 3 points per wavelength)
-        tol = max(1e-12, 2 * ec)
-        assert ea < tol
-        assert rel(a, c) < tol
+        assert ea < _tol(name)
+        assert ec < _tol(name)
+        assert rel(a, c) < _tol(name)
 
 
 @pytest.mark.parametrize("name", ["ragged", "pivot", "grf256", "strip"])
@@ -153,6 +164,8 @@ def test_dense_operators_formed_on_mfma(hbj, name, transmission):
     for mode in (hbj.MSOLVE_MFMA, hbj.MSOLVE_CHAINS):
         ctx = gpu_context(hbj, wl, m, operator_form=hbj.OP_DENSE, transmission=transmission)
         ctx.set_multi_solve(mode)
+        if mode == hbj.MSOLVE_MFMA:
+            ctx.set_solve_tuning(hbj.SOLVE_SHAPE_MFMA)
         say(f"[dense operators] case={name} transmission={transmission} mode={mode}")
         ctx.factor()
         gt, ft = torch.as_tensor(gv, device="cuda"), torch.as_tensor(f, device="cuda")
@@ -163,9 +176,9 @@ def test_dense_operators_formed_on_mfma(hbj, name, transmission):
                              res[hbj.MSOLVE_CHAINS], ref):
         ea, ec = rel(a, r), rel(c, r)
         say(f"  {what}: MFMA {ea:.1e}, one workgroup per solve {ec:.1e} vs oracle; between them {rel(a, c):.1e}")
-        tol = max(1e-12, 2 * ec)  # as in test_many_rhs_operator_lifting_reconstruction
-        assert ea < tol
-        assert rel(a, c) < tol
+        assert ea < _tol(name)
+        assert ec < _tol(name)
+        assert rel(a, c) < _tol(name)
 
 
 def test_multi_solve_bad_mode(hbj):
