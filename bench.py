@@ -70,6 +70,8 @@ def parse():
                    help="transmission condition of the main run (1: Robin, as the workloads specify; 2: second order; "
                         "3: the paper's Pade condition)")
     p.add_argument("--no-pade", action="store_true", help="skip the run with the paper's Pade transmission")
+    p.add_argument("--overlap", action="store_true",
+                   help="apply the operator beside the backward pass (hbj_set_operator_overlap; off by default)")
     p.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of each oracle sample")
     p.add_argument("--only", choices=("banded", "multi", "gradient"),
                    help="run one leg alone and print its figures (for profiling runs; no headline line)")
@@ -278,6 +280,9 @@ def cpu_entry(wl, timing, iters_gpu, kind_note):
 # GPU legs
 # ---------------------------------------------------------------------------
 
+OVERLAP = False  # hbj_set_operator_overlap for every context of the run (--overlap sets it)
+
+
 def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, profile_names, graphs=False,
              transmission=1, keep=False):
     """Setup + factor (untimed), warmup solves, timed solves, one profiled solve."""
@@ -286,6 +291,7 @@ def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, p
     ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=mt, precision=precision, precond=hbj.PC_BJ,
                     operator_form=operator_form, transmission=transmission, device=mt.device)
     ctx.set_graphs(graphs)
+    ctx.set_operator_overlap(OVERLAP)
     torch.cuda.synchronize()
     # the first factorisation also runs the autotuner of the banded solve batches when the tuning
     # cache has no entry for them yet; the second one is the steady-state figure
@@ -614,7 +620,9 @@ def only_leg(args):
 
 
 def main():
+    global OVERLAP
     args = parse()
+    OVERLAP = args.overlap
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form of the sweep is a "
               "design, not a measured configuration", file=sys.stderr)
@@ -688,6 +696,7 @@ def main():
                    "krylov": "FGMRES(50), right-preconditioned, delayed reorthogonalisation",
                    "preconditioner": "block Jacobi, width N1",
                    "operator_form": "dense local scattering operators (formed at factor time)",
+                   "operator_overlap": OVERLAP,
                    "transmission": {1: "Robin (first order)", 2: "second order on interface faces",
                                     3: "Pade (8 auxiliary fields, rotation pi/3) on interface faces"}[args.transmission]},
         "iters": st.iters,

@@ -395,6 +395,19 @@ enum { HBJ_MSOLVE_CHAINS = 0, HBJ_MSOLVE_MFMA = 1 };
 int hbj_set_multi_solve(hbj_ctx* ctx, int32_t mode);
 
 /*
+ * hbj_set_operator_overlap - inside GMRES, apply the operator (I - S) z (Sec. 4, eq. (5)) to the
+ * preconditioned vector z = P^{-1} v (Sec. 6) while the backward pass is still running: after
+ * backward step k, the operator rows of the subdomains whose incoming and outgoing data of z the
+ * pass has already finalised run on a second stream, and the context stream waits for them after
+ * the pass.  Applies to the dense operators with fewer than 4 right-hand sides, stepped sweeps and
+ * the default readings; profiled solves and captured graphs keep the operator after the pass.
+ * Same results bit for bit.  on: 1 or 0 (default: measured slower on MI355X, where each wait of
+ * one stream on another's event adds about 19 us, eight per GMRES iteration).  Returns
+ * HBJ_EINVAL for any other value.
+ */
+int hbj_set_operator_overlap(hbj_ctx* ctx, int32_t on);
+
+/*
  * hbj_get_tuning - choices of the autotuner of the many-right-hand-side operator
  * kernel (dense form, 4 or more right-hand sides).  On its first launch of each
  * kind the library times every variant on that launch's own data, writing into

@@ -98,6 +98,7 @@ _SIGS = {
     "hbj_get_tuning": (_I, [_P, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)]),
     "hbj_set_tuning": (_I, [_P, ctypes.POINTER(_I32)]),
     "hbj_set_solve_tuning": (_I, [_P, _I32]),
+    "hbj_set_operator_overlap": (_I, [_P, _I32]),
     "hbj_get_solve_tuning": (_I, [_P, ctypes.POINTER(_I32), ctypes.c_char_p, ctypes.POINTER(_I32),
                                   ctypes.POINTER(ctypes.c_float)]),
     "hbj_tune_cache_path": (ctypes.c_char_p, []),
@@ -361,6 +362,10 @@ class Context:
         c64 operator): 0-11, or -1 to let the autotuner choose."""
         v = (_I32 * 4)(*[int(x) for x in variants])
         _check(_lib.hbj_set_tuning(self._h, v))
+
+    def set_operator_overlap(self, on):
+        """Apply the operator to the preconditioned vector beside the backward pass, or after it (default)."""
+        _check(_lib.hbj_set_operator_overlap(self._h, 1 if on else 0))
 
     def set_solve_tuning(self, shape):
         """Fix the launch shape of every banded solve batch (0-2: one workgroup per solve at the three

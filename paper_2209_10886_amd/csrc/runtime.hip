@@ -52,6 +52,8 @@ constexpr int kMaskBwd = (1 << FACE_W) | (1 << FACE_S);
 constexpr int kShapeMfma = kSolveDepthVariants;
 constexpr int kSolveShapes = kSolveDepthVariants + 1;
 
+constexpr int kMatrixRhs = 4;  // from this many right-hand sides on, the operators run as MFMA products
+
 struct Step {
   size_t first;  // offset into the schedule's device entry array
   int count;
@@ -79,6 +81,13 @@ struct Schedule {
   int all_tile_count = 0;
   std::vector<Step> fwd, bwd;  // preconditioner passes
   std::vector<StepArgs> sargs;
+  // the operator (I - S) z applied while the backward pass still runs (dense operators, few
+  // right-hand sides, default readings): after backward step k, the operator rows of the
+  // subdomains whose incoming and outgoing data the pass has finalised by then, entries
+  // [ov_first[k], ov_first[k] + ov_count[k]) of dev/eft (mask 0xF)
+  bool ov_ok = false;
+  std::vector<size_t> ov_first;
+  std::vector<int> ov_count;
   // dataflow launches (dense form): task lists per kind, double-buffered completion counters
   struct DfPlan {
     bool built = false;
@@ -142,6 +151,9 @@ struct hbj_ctx {
   float2* mb32 = nullptr;
   double2* Wl = nullptr;    // dense lifting operators [ndom][n_loc][L] (null: banded lifting)
   hipStream_t side = nullptr;  // source part of the reconstruction, overlapped with GMRES
+  hipStream_t opst = nullptr;  // operator rows overlapped with the backward pass
+  std::vector<hipEvent_t> ov_ev;  // one per backward step, and the join
+  bool op_overlap = false;        // measured slower: each stream-to-stream wait costs ~19 us here
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   void* ybuf_side = nullptr;
   size_t ybuf_side_bytes = 0;
@@ -260,6 +272,11 @@ hbj_ctx::~hbj_ctx() {
     (void)hipStreamSynchronize(side);
     (void)hipStreamDestroy(side);
   }
+  if (opst) {
+    (void)hipStreamSynchronize(opst);
+    (void)hipStreamDestroy(opst);
+  }
+  for (hipEvent_t e : ov_ev) (void)hipEventDestroy(e);
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_join) (void)hipEventDestroy(ev_join);
   dfree(ybuf_side);
@@ -364,6 +381,57 @@ void append_tiles(const std::vector<Entry>& ent, size_t first, int count, std::v
   }
 }
 
+// Which operator rows may run while the backward pass is still under way.  A backward step writes,
+// per entry (subdomain s, faces W and S), the outgoing data of s toward its W and S neighbours and
+// (copy mode: the pass output is not pre-filled) s's own incoming positions on those faces; every
+// position of the pass output is written by exactly one step.  The operator rows of s read the
+// pass output at s's incoming positions and at its outgoing positions (the base of z - S z there),
+// so they can run once the last step writing any of those positions has run.  Entries of mask 0xF,
+// grouped by that step, are appended to ent; a position that no step writes disables the overlap.
+void plan_operator_overlap(const hbj_ctx* c, Schedule& S, std::vector<Entry>& ent) {
+  const Geom& g = c->g;
+  std::vector<int> wstep(g.nif, -1);
+  for (size_t k = 0; k < S.bwd.size(); ++k) {
+    const Step& st = S.bwd[k];
+    for (int q = 0; q < st.count; ++q) {
+      const Entry& e = ent[st.first + q];
+      if (e.rhs != 0) continue;  // the same positions for every right-hand side
+      const FaceTab& F = c->ft_host[e.s];
+      for (int f = 0; f < 4; ++f) {
+        if (!((e.mask >> f) & 1)) continue;
+        const int len = face_len(g, f);
+        for (int off : {F.out_off[f], F.in_off[f]})
+          if (off >= 0)
+            for (int i = 0; i < len; ++i) wstep[off + i] = std::max(wstep[off + i], (int)k);
+      }
+    }
+  }
+  const int nk = (int)S.bwd.size();
+  std::vector<std::vector<int>> by_step(nk);
+  for (int s = 0; s < c->ndom; ++s) {
+    const FaceTab& F = c->ft_host[s];
+    int ready = -1;
+    for (int f = 0; f < 4; ++f) {
+      const int len = face_len(g, f);
+      for (int off : {F.out_off[f], F.in_off[f]}) {
+        if (off < 0) continue;
+        for (int i = 0; i < len; ++i) {
+          if (wstep[off + i] < 0) return;  // not written by the pass: keep the operator after it
+          ready = std::max(ready, wstep[off + i]);
+        }
+      }
+    }
+    by_step[std::max(ready, 0)].push_back(s);
+  }
+  for (int k = 0; k < nk; ++k) {
+    S.ov_first.push_back(ent.size());
+    for (int s : by_step[k])
+      for (int r = 0; r < S.nrhs; ++r) ent.push_back(Entry{s, r, 0, 0xF});
+    S.ov_count.push_back((int)(ent.size() - S.ov_first.back()));
+  }
+  S.ov_ok = true;
+}
+
 int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
   auto it = c->sched.find(nrhs);
   if (it != c->sched.end()) {
@@ -429,6 +497,9 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
       S->bwd.push_back(st);
     }
   }
+  if (c->dense && nrhs < kMatrixRhs && !S->bwd.empty() && c->P.bj_combine == HBJ_BJ_RESTRICTED &&
+      !(c->P.bj_compose == HBJ_BJ_RESIDUAL && c->fblocks.size() > 1))
+    plan_operator_overlap(c, *S, ent);
   HIPCHK(dalloc(&S->dev, ent.size()));
   HIPCHK(hipMemcpyAsync(S->dev, ent.data(), ent.size() * sizeof(Entry), hipMemcpyHostToDevice, c->st));
   std::vector<FaceTab> eft(ent.size());
@@ -744,7 +815,6 @@ int run_solves_side(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io) {
 }
 
 // batched application of the dense scattering operators (complex128 or complex64 storage)
-constexpr int kMatrixRhs = 4;  // from this many right-hand sides on, the operators run as MFMA products
 
 int run_dense(hbj_ctx* c, const Entry* ent, const FaceTab* eft, int nent, int mask, const SolveIO& io, bool c64,
               double elems,
@@ -1251,11 +1321,34 @@ int op_fp64(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
 // out = in + contribution and pass the other incoming positions through (copy mode).
 bool pass_copies(const hbj_ctx* c, const Schedule* S) { return c->dense && S->nrhs < kMatrixRhs; }
 
+// the operator rows of backward-pass chunk k into w = out - S out (out: the pass output)
+int op_chunk(hbj_ctx* c, const Schedule* S, int k, const double2* z, double2* w) {
+  SolveIO io{};
+  io.g_a = z;
+  io.tr_dst = w;
+  io.tr_base = z;
+  io.tr_sign = -1.0;
+  io.tr_reflect = 1;
+  return run_dense(c, S->dev + S->ov_first[k], S->eft + S->ov_first[k], S->ov_count[k], 0xF, io, false, 0.0);
+}
+
+// with opw (backward pass of a planned overlap): after step k the operator rows that the pass has
+// finalised run on the operator stream, behind an event of the step; the last chunk runs on the
+// context stream after the pass, which then waits for the operator stream
 template <typename R>
 int run_pass(hbj_ctx* c, const Schedule* S, const std::vector<Step>& steps, const double2* in, double2* out,
-             int mask) {
+             int mask, double2* opw = nullptr) {
   Entry* dev = S->dev;
   const bool cp = pass_copies(c, S);
+  const int nk = (int)steps.size();
+  if (opw) {
+    if (!c->opst) HIPCHK(hipStreamCreateWithFlags(&c->opst, hipStreamNonBlocking));
+    while ((int)c->ov_ev.size() < nk + 1) {
+      hipEvent_t e = nullptr;
+      HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      c->ov_ev.push_back(e);
+    }
+  }
   for (size_t si = 0; si < steps.size(); ++si) {
     const Step& s = steps[si];
     SolveIO io{};
@@ -1272,14 +1365,33 @@ int run_pass(hbj_ctx* c, const Schedule* S, const std::vector<Step>& steps, cons
                                   s.sarg >= 0 ? &S->sargs[s.sarg] : nullptr)
                       : run_solves<R>(c, dev + s.first, s.count, io, S->tiles + s.tile_first, s.tile_count);
     if (rc) return rc;
+    if (opw && (int)si + 1 < nk && S->ov_count[si] > 0) {
+      HIPCHK(hipEventRecord(c->ov_ev[si], c->st));
+      HIPCHK(hipStreamWaitEvent(c->opst, c->ov_ev[si], 0));
+      hipStream_t keep = c->st;
+      c->st = c->opst;
+      rc = op_chunk(c, S, (int)si, out, opw);
+      c->st = keep;
+      if (rc) return rc;
+    }
+  }
+  if (opw) {
+    if (S->ov_count[nk - 1] > 0) {
+      int rc = op_chunk(c, S, nk - 1, out, opw);
+      if (rc) return rc;
+    }
+    HIPCHK(hipEventRecord(c->ov_ev[nk], c->opst));
+    HIPCHK(hipStreamWaitEvent(c->st, c->ov_ev[nk], 0));
   }
   return HBJ_OK;
 }
 
 int op_apply(hbj_ctx* c, Schedule* S, const double2* g, double2* out);
 
+// w: also apply the operator, w = (I - S) z, overlapped with the backward pass (the schedule
+// planned it; the caller checked op_overlap_ok)
 template <typename R>
-int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs) {
+int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs, double2* w = nullptr) {
   const size_t n = (size_t)nrhs * c->g.nif;
   int rc = ensure_pc(c, nrhs);
   if (rc) return rc;
@@ -1335,7 +1447,7 @@ int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs
     return HBJ_OK;
   }
   if (!cp) HIPCHK(launch_copy(z, y, n, c->st));
-  rc = run_pass<R>(c, S, S->bwd, y, z, kMaskBwd);
+  rc = run_pass<R>(c, S, S->bwd, y, z, kMaskBwd, w);
   if (rc) return rc;
   if (c->P.bj_combine == HBJ_BJ_ADDITIVE) HIPCHK(launch_add_ranges(z, y, c->ranges_b, c->nranges_b, c->g.nif, nrhs, c->st));
   return HBJ_OK;
@@ -1362,13 +1474,24 @@ int op_apply(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
   return op_fp64(c, S, g, out);
 }
 
+// The operator rows run beside the backward pass when the schedule planned it (dense operators,
+// few right-hand sides, stepped sweeps, default readings) and no launch is profiled or captured.
+bool op_overlap_ok(const hbj_ctx* c, const Schedule* S) {
+  return c->op_overlap && S->ov_ok && c->dense && !c->prof && !c->use_graphs && !df_enabled(c, S) &&
+         c->P.precond != HBJ_PC_NONE && c->ndom > 1 && S->nrhs < kMatrixRhs;
+}
+
 // z = P^{-1} v, w = (I - S) z: one dataflow launch for the FP64 dense form with the default
-// readings, the two calls otherwise
+// readings, the two calls otherwise (the operator overlapped with the backward pass where it can)
 int pc_op(hbj_ctx* c, Schedule* S, const double2* v, double2* z, double2* w, int nrhs) {
   const bool fused = df_enabled(c, S) && c->P.precision == HBJ_FP64 && c->P.precond != HBJ_PC_NONE &&
                      c->ndom > 1 && c->P.bj_combine == HBJ_BJ_RESTRICTED &&
                      !(c->P.bj_compose == HBJ_BJ_RESIDUAL && c->fblocks.size() > 1);
   if (!fused) {
+    if (op_overlap_ok(c, S)) {
+      if (c->P.precision == HBJ_MIXED) return precond_impl<float>(c, S, v, z, nrhs, w);
+      return precond_impl<double>(c, S, v, z, nrhs, w);
+    }
     int rc = precond(c, S, v, z, nrhs);
     if (rc) return rc;
     return op_apply(c, S, z, w);
@@ -2658,6 +2781,12 @@ int hbj_set_multi_solve(hbj_ctx* c, int32_t mode) {
   if (mode != HBJ_MSOLVE_CHAINS && mode != HBJ_MSOLVE_MFMA) return fail(HBJ_EINVAL, "unknown multi-solve mode");
   if (mode != c->msolve) ++c->graph_epoch;  // the captured steps hold the other kernels
   c->msolve = mode;
+  return HBJ_OK;
+}
+
+int hbj_set_operator_overlap(hbj_ctx* c, int32_t on) {
+  if (!c || (on != 0 && on != 1)) return fail(HBJ_EINVAL, "bad arguments");
+  c->op_overlap = on != 0;
   return HBJ_OK;
 }
 
