@@ -411,14 +411,19 @@ int hbj_set_operator_overlap(hbj_ctx* ctx, int32_t on);
  * hbj_get_tuning - choices of the autotuner of the many-right-hand-side operator
  * kernel (dense form, 4 or more right-hand sides).  On its first launch of each
  * kind the library times every variant on that launch's own data, writing into
- * scratch, and keeps the fastest.  Variant v: tile depth (k-steps per batch of
- * loads) 2, 4, 8 for v % 3 = 0, 1, 2; incoming data gathered into tiles by a
+ * scratch, and keeps the fastest.  Variant v < 12: tile depth (k-steps per batch
+ * of loads) 2, 4, 8 for v % 3 = 0, 1, 2; incoming data gathered into tiles by a
  * separate launch first ((v % 6) < 3, its time included) or read straight from
  * the interface vector ((v % 6) >= 3); the 64 right-hand sides of a tile taken by
  * one group of four wavefronts (v < 6) or split over two groups (v >= 6).
+ * Variants 12-15: two groups, each wavefront walking its k-steps over all faces
+ * through a register ring of 4 (v even) or 8 (v odd) k-steps of loads in flight;
+ * gathered (12, 13) or direct (14, 15).  Variants 16, 17: as 7 and 9 (gathered
+ * with 4 k-steps per batch, direct with 2).  Variants 12-17 deal the tiles to the
+ * XCDs so that all row tiles of one subdomain share an L2.
  *   variants  HOST [4]: complex128 sweep steps, complex128 operator, complex64
  *             sweep steps, complex64 operator; -1 = not tuned yet.
- *   us        HOST [4][12] or NULL: the measured microseconds per launch.
+ *   us        HOST [4][18] or NULL: the measured microseconds per launch.
  */
 int hbj_get_tuning(const hbj_ctx* ctx, int32_t* variants, float* us);
 
@@ -489,9 +494,9 @@ int32_t hbj_tune_cache_size(void);
 /*
  * hbj_set_tuning - fix the variants of the many-right-hand-side operator kernel
  * instead of timing them (reproducible timings, tests of every variant).
- *   variants  HOST [4], same order as hbj_get_tuning; each in 0..11, or -1 to let
+ *   variants  HOST [4], same order as hbj_get_tuning; each in 0..17, or -1 to let
  *             the autotuner choose on the next launch of that kind.
- * Returns HBJ_EINVAL for a value outside -1..11 (nothing is changed then).
+ * Returns HBJ_EINVAL for a value outside -1..17 (nothing is changed then).
  */
 int hbj_set_tuning(hbj_ctx* ctx, const int32_t* variants);
 

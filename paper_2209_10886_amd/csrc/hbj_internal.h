@@ -361,7 +361,23 @@ template <typename C>
 hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int mask, const FaceTab* ft, const C* T,
                              const double2* gin, const C* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st,
                              int variant);
-constexpr int kMmVariants = 12;  // k-steps per batch 2, 4, 8; gathered or direct; one or two wave groups
+// Workgroups are dealt to the 8 XCDs in turn (workgroup b to XCD b % 8), each XCD with its own L2.
+// Tile index of workgroup b such that XCD x works on one contiguous run of tiles (a bijection of
+// [0, n)): consecutive tiles that read the same data (the factors of one subdomain, its incoming
+// data) then share an L2, and the data are fetched once per XCD.
+__device__ inline int xcd_tile(int b, int n) {
+  const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+  return x * q + min(x, r) + k;
+}
+
+// variants 0-11: k-steps per batch 2, 4, 8; gathered or direct; one or two wave groups;
+// 12-15: a register ring of 4 or 8 k-steps over all faces, gathered or direct, two wave groups;
+// 16, 17: gathered with 4 k-steps per batch, direct with 2, two wave groups; 12-17 with the tiles
+// of one subdomain on one XCD
+constexpr int kMmVariants = 18;
+__host__ __device__ inline bool mm_variant_gathered(int v) {
+  return v < 12 ? (v % 6 < 3) : v < 16 ? (v < 14) : (v == 16);
+}
 
 // gradient / misc
 hipError_t launch_gather_receivers(const double2* u, const int32_t* rec, int nrec, int npts, const double2* d,

@@ -78,7 +78,13 @@ constexpr int KW = 4;  // wavefronts splitting the k range of one tile
 // With NS = 2 the workgroup has two groups of KW wavefronts, each taking half of the right-hand-side
 // blocks (two wavefronts per SIMD, so one's MFMAs overlap the other's loads; the A operands are
 // loaded by both groups).  KB, NS and the source of B are chosen by the autotuner.
-template <typename C, typename M, int KB, bool DIRECT, int NS>
+// RING > 0: instead of batches of KB k-steps per face, the wavefront walks its k-steps over all
+// faces as one sequence (padded to a multiple of RING with masked steps) through a register ring of
+// RING k-steps: the loads of step q + RING are issued right after the products of step q, so RING
+// steps of loads are always in flight and a wait covers one step's loads only.
+// XO: the workgroups take their (row tile, subdomain, right-hand-side tile) in XCD order, so that
+// the 16 row tiles of a subdomain, which all read its incoming data, run on one XCD.
+template <typename C, typename M, int KB, bool DIRECT, int NS, int RING = 0, bool XO = false>
 __global__ __launch_bounds__(64 * KW * NS) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_scatter_mm(Geom g, const int32_t* subs, int mask, const FaceTab* ft,
                                                         const C* __restrict__ T,
                                                         const std::conditional_t<DIRECT, double2, C>* __restrict__ B,
@@ -87,15 +93,23 @@ __global__ __launch_bounds__(64 * KW * NS) __attribute__((amdgpu_waves_per_eu(1,
   typedef MfmaAcc<M> A;
   typedef typename A::T V4;
   constexpr int TW = TB / NS;  // right-hand-side blocks per wavefront
-  const int j = blockIdx.y;
+  int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  if constexpr (XO) {
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int t = xcd_tile(bx + gx * (by + gy * bz), gx * gy * gridDim.z);
+    bx = t % gx;
+    by = (t / gx) % gy;
+    bz = t / (gx * gy);
+  }
+  const int j = by;
   const int s = subs[j];
   const FaceTab F = ft[s];
   const int L = local_if_len(g);
   const int lane = threadIdx.x & 63, w = (threadIdx.x >> 6) % KW, grp = (threadIdx.x >> 6) / KW;
   const int i = lane & 15, k = lane >> 4;
-  const int mrow = masked_row_mm(g, mask, blockIdx.x * 16 + i);  // this lane's A row
+  const int mrow = masked_row_mm(g, mask, bx * 16 + i);  // this lane's A row
   const M amask = mrow >= 0 ? (M)1 : (M)0;
-  const int rb0 = blockIdx.z * 16 * TB;  // first right-hand side of the workgroup's tile
+  const int rb0 = bz * 16 * TB;  // first right-hand side of the workgroup's tile
   const int tb0 = grp * TW;               // first right-hand-side block of this wavefront
   const C* Ts = T + (size_t)s * t_per_sub(g) + t_index(L, mrow < 0 ? 0 : mrow, 0);
   // right-hand sides of this lane's B operands, clamped to the last one (columns past nrhs only
@@ -114,6 +128,62 @@ __global__ __launch_bounds__(64 * KW * NS) __attribute__((amdgpu_waves_per_eu(1,
     ci[t] = V4{0, 0, 0, 0};
   }
   const int present[4] = {F.in_off[0] >= 0, F.in_off[1] >= 0, F.in_off[2] >= 0, F.in_off[3] >= 0};
+  if constexpr (RING > 0) {
+    // one flat sequence of k-steps over all L columns: step m covers columns 4 (KW m + w) + k, each
+    // lane finds its own face with three compares, and columns past L or on faces without data load
+    // column 0 (every load in bounds) and enter the products as zero (by select: the operator's
+    // entries there are never read otherwise)
+    const int b1 = g.sny, b2 = 2 * g.sny, b3 = 2 * g.sny + g.snx;
+    const int pm = present[0] | present[1] << 1 | present[2] << 2 | present[3] << 3;
+    // offsets of the incoming data of each face in gin (DIRECT): position c of face f at fo_f + c
+    const int fo0 = DIRECT ? F.in_off[0] : 0, fo1 = DIRECT ? F.in_off[1] - b1 : 0;
+    const int fo2 = DIRECT ? F.in_off[2] - b2 : 0, fo3 = DIRECT ? F.in_off[3] - b3 : 0;
+    const int ics = (int)cs;
+    const int nst = (L + 4 * KW - 1) / (4 * KW);
+    const int nsp = (nst + RING - 1) / RING * RING;
+    C tv[RING];
+    BT gv[RING][TW];
+    bool live[RING];
+    auto issue = [&](int m, int d) {
+      const int col = 4 * (KW * m + w) + k;
+      const bool c1 = col >= b1, c2 = col >= b2, c3 = col >= b3;
+      const int f = (int)c1 + (int)c2 + (int)c3;
+      const bool ok = (col < L) & ((pm >> f) & 1);
+      // the face's offset by 0/1 products (a select chain here becomes an indexed table in memory)
+      const int fo = fo0 + (int)c1 * (fo1 - fo0) + (int)c2 * (fo2 - fo1) + (int)c3 * (fo3 - fo2);
+      const int cc = ok ? col : 0;
+      const int off = ok ? fo + cc * ics : 0;
+      live[d] = ok;
+      tv[d] = Ts[(size_t)cc * kTR];
+#pragma unroll
+      for (int t = 0; t < TW; ++t) gv[d][t] = B[jr[t] + off];
+    };
+    auto consume = [&](int d) {
+      const bool ok = live[d] && mrow >= 0;
+      const M ar = ok ? (M)tv[d].x : (M)0, ai = ok ? (M)tv[d].y : (M)0;
+#pragma unroll
+      for (int t = 0; t < TW; ++t) {
+        const M br = (M)gv[d][t].x, bi = (M)gv[d][t].y;
+        cr[t] = A::mma(ar, br, cr[t]);
+        ci[t] = A::mma(ar, bi, ci[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < TW; ++t) {
+        const M br = (M)gv[d][t].x, bi = (M)gv[d][t].y;
+        cr[t] = A::mma(-ai, bi, cr[t]);
+        ci[t] = A::mma(ai, br, ci[t]);
+      }
+    };
+#pragma unroll
+    for (int d = 0; d < RING; ++d) issue(d, d);
+    for (int m0 = 0; m0 < nsp; m0 += RING) {
+#pragma unroll
+      for (int d = 0; d < RING; ++d) {
+        consume(d);
+        issue(m0 + d + RING, d);
+      }
+    }
+  } else {
 #pragma unroll
   for (int f = 0; f < 4; ++f) {
     if (!present[f]) continue;
@@ -147,6 +217,7 @@ __global__ __launch_bounds__(64 * KW * NS) __attribute__((amdgpu_waves_per_eu(1,
       }
     }
   }
+  }
   // sum the KW partial tiles: the wavefronts of group 0 finish right-hand-side block t = w
   __shared__ M red[KW][TB][2][4][64];
 #pragma unroll
@@ -168,7 +239,7 @@ __global__ __launch_bounds__(64 * KW * NS) __attribute__((amdgpu_waves_per_eu(1,
       si += (double)red[q][t][1][reg][lane];
     }
     const int ii = A::row_of(lane, reg), jj = lane & 15;
-    const int row = masked_row_mm(g, mask, blockIdx.x * 16 + ii);
+    const int row = masked_row_mm(g, mask, bx * 16 + ii);
     const int rhs = rb0 + 16 * t + jj;
     if (row < 0 || rhs >= nrhs) continue;
     int rf, re;
@@ -311,6 +382,12 @@ hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int m
     case 9: go(k_scatter_mm<C, M, 2, true, 2>, gin, 2); break;
     case 10: go(k_scatter_mm<C, M, 4, true, 2>, gin, 2); break;
     case 11: go(k_scatter_mm<C, M, 8, true, 2>, gin, 2); break;
+    case 12: go(k_scatter_mm<C, M, 1, false, 2, 4, true>, G, 2); break;
+    case 13: go(k_scatter_mm<C, M, 1, false, 2, 8, true>, G, 2); break;
+    case 14: go(k_scatter_mm<C, M, 1, true, 2, 4, true>, gin, 2); break;
+    case 15: go(k_scatter_mm<C, M, 1, true, 2, 8, true>, gin, 2); break;
+    case 16: go(k_scatter_mm<C, M, 4, false, 2, 0, true>, G, 2); break;
+    case 17: go(k_scatter_mm<C, M, 2, true, 2, 0, true>, gin, 2); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -483,13 +483,6 @@ __device__ inline void tiles_mma(const typename Cplx<R>::T (&a)[SPW][4], const R
     }
 }
 
-// Workgroups are dealt to the 8 XCDs in turn (workgroup b to XCD b % 8), each XCD with its own L2.
-// Tile index of workgroup b such that XCD x works on one contiguous run of tiles: the tiles of one
-// subdomain (consecutive) then share an L2 and its factors are fetched once per XCD.
-__device__ inline int xcd_tile(int b, int n) {
-  const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
-  return x * q + min(x, r) + k;
-}
 
 // Per-wavefront state of the MFMA band solves: wavefront w holds the logical window tiles
 // w SPW + si (si < SPW) in accumulators, so every tile keeps one role (and one set of load

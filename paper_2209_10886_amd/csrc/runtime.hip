@@ -838,7 +838,7 @@ int run_dense(hbj_ctx* c, const Entry* ent, const FaceTab* eft, int nent, int ma
     // complex64 products, which round every operand to float anyway); the others read them from
     // gin directly
     auto launch = [&](int v, const SolveIO& lio) -> hipError_t {
-      if (v % 6 < 3) {
+      if (mm_variant_gathered(v)) {
         const hipError_t e =
             c64 ? launch_gather_incoming(c->g, subs, nsub, c->ft, gin, nrhs, rpad, (float2*)c->Gbuf, c->st)
                 : launch_gather_incoming(c->g, subs, nsub, c->ft, gin, nrhs, rpad, c->Gbuf, c->st);

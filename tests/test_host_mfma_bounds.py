@@ -84,3 +84,72 @@ def test_b_operand_loads_stay_in_bounds():
     # without the clamps the same grid reads past the buffers (the fault the clamps fixed)
     assert overflow_seen
     assert _recon_max_index(20, 5, L, clamp=False)[0] >= _recon_max_index(20, 5, L)[1]
+
+
+KW = 4  # wavefronts splitting the k range of a tile
+
+
+def _ring_lane_loads(snx, sny, in_off, direct, rpad, ring):
+    """Replay of the register-ring k-loop of k_scatter_mm (RING > 0) for one tile: for every
+    wavefront w, k-step m (including the prefetches past the end) and lane row k, the column the
+    lane reads, whether it enters the products, and its B offset relative to jr."""
+    L = 2 * snx + 2 * sny
+    b1, b2, b3 = sny, 2 * sny, 2 * sny + snx
+    present = [o >= 0 for o in in_off]
+    pm = sum(1 << f for f in range(4) if present[f])
+    fo = ([in_off[0], in_off[1] - b1, in_off[2] - b2, in_off[3] - b3] if direct else [0, 0, 0, 0])
+    cs = 1 if direct else rpad
+    nst = (L + 4 * KW - 1) // (4 * KW)
+    nsp = (nst + ring - 1) // ring * ring
+    out = []
+    for w in range(KW):
+        for m in range(nsp + ring):
+            for k in range(4):
+                col = 4 * (KW * m + w) + k
+                c1, c2, c3 = col >= b1, col >= b2, col >= b3
+                f = int(c1) + int(c2) + int(c3)
+                ok = col < L and bool((pm >> f) & 1)
+                fof = fo[0] + int(c1) * (fo[1] - fo[0]) + int(c2) * (fo[2] - fo[1]) + int(c3) * (fo[3] - fo[2])
+                cc = col if ok else 0
+                off = fof + cc * cs if ok else 0
+                out.append((w, m, k, col, f, ok, cc, off))
+    return out, L
+
+
+def test_ring_kloop_covers_every_column_once_and_stays_in_bounds():
+    for snx, sny in ((16, 12), (10, 10), (128, 128), (8, 24)):
+        L = 2 * snx + 2 * sny
+        nif = 10 * L
+        for absent in ((), (0,), (2, 3), (1,), (0, 1, 2)):
+            # interface offsets of the present faces somewhere inside a vector of nif positions
+            in_off = [-1 if f in absent else 3 * L + f * max(snx, sny) for f in range(4)]
+            face_lo = [0, sny, 2 * sny, 2 * sny + snx]
+            face_hi = [sny, 2 * sny, 2 * sny + snx, L]
+            for direct in (False, True):
+                for ring in (4, 8):
+                    rpad = 64
+                    loads, _ = _ring_lane_loads(snx, sny, in_off, direct, rpad, ring)
+                    seen = {}
+                    for (w, m, k, col, f, ok, cc, off) in loads:
+                        assert 0 <= cc < L  # the A load
+                        if direct:
+                            assert 0 <= off < nif  # B relative to the right-hand side's row r * nif
+                        else:
+                            assert 0 <= off < L * rpad  # B relative to subdomain j's tile
+                        if ok:
+                            assert face_lo[f] <= col < face_hi[f] and in_off[f] >= 0
+                            if direct:
+                                assert off == in_off[f] + (col - face_lo[f])
+                            else:
+                                assert off == col * rpad
+                            seen[col] = seen.get(col, 0) + 1
+                    want = {c for f in range(4) if in_off[f] >= 0 for c in range(face_lo[f], face_hi[f])}
+                    assert set(seen) == want
+                    assert all(v == 1 for v in seen.values())
+
+
+def test_kernel_source_has_the_ring_arithmetic():
+    src = open(SRC).read()
+    assert "const int col = 4 * (KW * m + w) + k;" in src
+    assert "const int fo = fo0 + (int)c1 * (fo1 - fo0) + (int)c2 * (fo2 - fo1) + (int)c3 * (fo3 - fo2);" in src
+    assert "const int off = ok ? fo + cc * ics : 0;" in src
