@@ -420,10 +420,12 @@ int hbj_set_operator_overlap(hbj_ctx* ctx, int32_t on);
  * through a register ring of 4 (v even) or 8 (v odd) k-steps of loads in flight;
  * gathered (12, 13) or direct (14, 15).  Variants 16, 17: as 7 and 9 (gathered
  * with 4 k-steps per batch, direct with 2).  Variants 12-17 deal the tiles to the
- * XCDs so that all row tiles of one subdomain share an L2.
+ * XCDs so that all row tiles of one subdomain share an L2.  Variants 18-21: one
+ * group of eight wavefronts splitting the k range (each A operand loaded once),
+ * 2 or 4 k-steps per batch, gathered (18, 19) or direct (20, 21).
  *   variants  HOST [4]: complex128 sweep steps, complex128 operator, complex64
  *             sweep steps, complex64 operator; -1 = not tuned yet.
- *   us        HOST [4][18] or NULL: the measured microseconds per launch.
+ *   us        HOST [4][22] or NULL: the measured microseconds per launch.
  */
 int hbj_get_tuning(const hbj_ctx* ctx, int32_t* variants, float* us);
 
@@ -494,9 +496,9 @@ int32_t hbj_tune_cache_size(void);
 /*
  * hbj_set_tuning - fix the variants of the many-right-hand-side operator kernel
  * instead of timing them (reproducible timings, tests of every variant).
- *   variants  HOST [4], same order as hbj_get_tuning; each in 0..17, or -1 to let
+ *   variants  HOST [4], same order as hbj_get_tuning; each in 0..21, or -1 to let
  *             the autotuner choose on the next launch of that kind.
- * Returns HBJ_EINVAL for a value outside -1..17 (nothing is changed then).
+ * Returns HBJ_EINVAL for a value outside -1..21 (nothing is changed then).
  */
 int hbj_set_tuning(hbj_ctx* ctx, const int32_t* variants);
 

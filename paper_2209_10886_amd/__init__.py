@@ -344,7 +344,8 @@ class Context:
         variant. Variants 0-11: batches of 2, 4 or 8 k-steps, the incoming data gathered into tiles
         first or read from the interface vector, one or two wavefront groups sharing the right-hand
         sides; 12-15: a register ring of 4 or 8 k-steps over all faces, gathered or direct, two groups;
-        16, 17: gathered/4 and direct/2 with two groups; 12-17 place the tiles of a subdomain on one XCD."""
+        16, 17: gathered/4 and direct/2 with two groups; 12-17 place the tiles of a subdomain on one XCD;
+        18-21: eight wavefronts splitting the k range (one group), 2 or 4 k-steps, gathered or direct."""
         nv = MM_VARIANTS
         v = (_I32 * 4)()
         us = (ctypes.c_float * (4 * nv))()
@@ -355,8 +356,8 @@ class Context:
         for i, k in enumerate(kinds):
             j = v[i]
             if j < 0:
-                out[k] = {"k_steps_per_batch": None, "incoming": None, "wave_groups": None, "ring": None,
-                          "xcd_order": None, "us": None}
+                out[k] = {"k_steps_per_batch": None, "incoming": None, "wave_groups": None, "k_waves": None,
+                          "ring": None, "xcd_order": None, "us": None}
                 continue
             d = mm_variant_fields(j)
             d["us"] = {label[q]: round(us[i * nv + q], 2) for q in range(nv)}
@@ -365,7 +366,7 @@ class Context:
 
     def set_tuning(self, variants):
         """Fix the many-RHS operator kernel's variant per kind (c128 steps, c128 operator, c64 steps,
-        c64 operator): 0-17, or -1 to let the autotuner choose."""
+        c64 operator): 0-21, or -1 to let the autotuner choose."""
         v = (_I32 * 4)(*[int(x) for x in variants])
         _check(_lib.hbj_set_tuning(self._h, v))
 
@@ -402,25 +403,28 @@ class Context:
         _check(_lib.hbj_set_sweep_wait(self._h, max_polls, stall_task))
 
 
-MM_VARIANTS = 18  # variants of the many-right-hand-side operator kernel (hbj_set_tuning)
+MM_VARIANTS = 22  # variants of the many-right-hand-side operator kernel (hbj_set_tuning)
 
 
 def mm_variant_fields(v):
     """What variant v of the many-right-hand-side operator kernel is (see Context.tuning)."""
     if v < 12:
         return {"k_steps_per_batch": (2, 4, 8)[v % 3], "incoming": "gathered" if v % 6 < 3 else "direct",
-                "wave_groups": (1, 2)[v // 6], "ring": False, "xcd_order": False}
+                "wave_groups": (1, 2)[v // 6], "k_waves": 4, "ring": False, "xcd_order": False}
     if v < 16:
         return {"k_steps_per_batch": (4, 8)[v % 2], "incoming": "gathered" if v < 14 else "direct",
-                "wave_groups": 2, "ring": True, "xcd_order": True}
-    return {"k_steps_per_batch": 4 if v == 16 else 2, "incoming": "gathered" if v == 16 else "direct",
-            "wave_groups": 2, "ring": False, "xcd_order": True}
+                "wave_groups": 2, "k_waves": 4, "ring": True, "xcd_order": True}
+    if v < 18:
+        return {"k_steps_per_batch": 4 if v == 16 else 2, "incoming": "gathered" if v == 16 else "direct",
+                "wave_groups": 2, "k_waves": 4, "ring": False, "xcd_order": True}
+    return {"k_steps_per_batch": (2, 4)[v % 2], "incoming": "gathered" if v < 20 else "direct",
+            "wave_groups": 1, "k_waves": 8, "ring": False, "xcd_order": False}
 
 
 def mm_variant_label(v):
     d = mm_variant_fields(v)
     return (f"{d['incoming']}/{'ring' if d['ring'] else ''}{d['k_steps_per_batch']}/{d['wave_groups']}"
-            f"{'/xcd' if d['xcd_order'] else ''}")
+            f"{'/k8' if d['k_waves'] == 8 else ''}{'/xcd' if d['xcd_order'] else ''}")
 
 
 def tune_cache_path():

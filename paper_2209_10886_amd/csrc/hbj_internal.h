@@ -373,10 +373,11 @@ __device__ inline int xcd_tile(int b, int n) {
 // variants 0-11: k-steps per batch 2, 4, 8; gathered or direct; one or two wave groups;
 // 12-15: a register ring of 4 or 8 k-steps over all faces, gathered or direct, two wave groups;
 // 16, 17: gathered with 4 k-steps per batch, direct with 2, two wave groups; 12-17 with the tiles
-// of one subdomain on one XCD
-constexpr int kMmVariants = 18;
+// of one subdomain on one XCD; 18-21: eight wavefronts splitting the k range, one group, 2 or 4
+// k-steps per batch, gathered (18, 19) or direct (20, 21)
+constexpr int kMmVariants = 22;
 __host__ __device__ inline bool mm_variant_gathered(int v) {
-  return v < 12 ? (v % 6 < 3) : v < 16 ? (v < 14) : (v == 16);
+  return v < 12 ? (v % 6 < 3) : v < 16 ? (v < 14) : v < 18 ? (v == 16) : (v < 20);
 }
 
 // gradient / misc

@@ -65,7 +65,7 @@ template <> struct MfmaAcc<float> {
 };
 
 constexpr int TB = 4;  // 16-column right-hand-side blocks per wavefront (64 right-hand sides)
-constexpr int KW = 4;  // wavefronts splitting the k range of one tile
+constexpr int KW = 4;  // wavefronts splitting the k range of one tile (KWT, the template value, may be 8)
 
 // grid: (ceil(masked rows / 16), nsub, ceil(R / 64)).  One 16-row x 64-column output tile per
 // workgroup; wavefront w takes every KW-th group of 4 columns of each existing face, and the four
@@ -84,8 +84,10 @@ constexpr int KW = 4;  // wavefronts splitting the k range of one tile
 // steps of loads are always in flight and a wait covers one step's loads only.
 // XO: the workgroups take their (row tile, subdomain, right-hand-side tile) in XCD order, so that
 // the 16 row tiles of a subdomain, which all read its incoming data, run on one XCD.
-template <typename C, typename M, int KB, bool DIRECT, int NS, int RING = 0, bool XO = false>
-__global__ __launch_bounds__(64 * KW * NS) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_scatter_mm(Geom g, const int32_t* subs, int mask, const FaceTab* ft,
+// KWT: wavefronts splitting the k range (4; 8 with NS = 1: eight wavefronts, each a 16-row x
+// 64-column tile over an eighth of the columns, so that each A operand is loaded once).
+template <typename C, typename M, int KB, bool DIRECT, int NS, int RING = 0, bool XO = false, int KWT = KW>
+__global__ __launch_bounds__(64 * KWT * NS) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_scatter_mm(Geom g, const int32_t* subs, int mask, const FaceTab* ft,
                                                         const C* __restrict__ T,
                                                         const std::conditional_t<DIRECT, double2, C>* __restrict__ B,
                                                         int nrhs, int rpad, SolveIO io) {
@@ -105,7 +107,7 @@ __global__ __launch_bounds__(64 * KW * NS) __attribute__((amdgpu_waves_per_eu(1,
   const int s = subs[j];
   const FaceTab F = ft[s];
   const int L = local_if_len(g);
-  const int lane = threadIdx.x & 63, w = (threadIdx.x >> 6) % KW, grp = (threadIdx.x >> 6) / KW;
+  const int lane = threadIdx.x & 63, w = (threadIdx.x >> 6) % KWT, grp = (threadIdx.x >> 6) / KWT;
   const int i = lane & 15, k = lane >> 4;
   const int mrow = masked_row_mm(g, mask, bx * 16 + i);  // this lane's A row
   const M amask = mrow >= 0 ? (M)1 : (M)0;
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(64 * KW * NS) __attribute__((amdgpu_waves_per_eu(1,
   }
   const int present[4] = {F.in_off[0] >= 0, F.in_off[1] >= 0, F.in_off[2] >= 0, F.in_off[3] >= 0};
   if constexpr (RING > 0) {
-    // one flat sequence of k-steps over all L columns: step m covers columns 4 (KW m + w) + k, each
+    // one flat sequence of k-steps over all L columns: step m covers columns 4 (KWT m + w) + k, each
     // lane finds its own face with three compares, and columns past L or on faces without data load
     // column 0 (every load in bounds) and enter the products as zero (by select: the operator's
     // entries there are never read otherwise)
@@ -139,13 +141,13 @@ __global__ __launch_bounds__(64 * KW * NS) __attribute__((amdgpu_waves_per_eu(1,
     const int fo0 = DIRECT ? F.in_off[0] : 0, fo1 = DIRECT ? F.in_off[1] - b1 : 0;
     const int fo2 = DIRECT ? F.in_off[2] - b2 : 0, fo3 = DIRECT ? F.in_off[3] - b3 : 0;
     const int ics = (int)cs;
-    const int nst = (L + 4 * KW - 1) / (4 * KW);
+    const int nst = (L + 4 * KWT - 1) / (4 * KWT);
     const int nsp = (nst + RING - 1) / RING * RING;
     C tv[RING];
     BT gv[RING][TW];
     bool live[RING];
     auto issue = [&](int m, int d) {
-      const int col = 4 * (KW * m + w) + k;
+      const int col = 4 * (KWT * m + w) + k;
       const bool c1 = col >= b1, c2 = col >= b2, c3 = col >= b3;
       const int f = (int)c1 + (int)c2 + (int)c3;
       const bool ok = (col < L) & ((pm >> f) & 1);
@@ -189,13 +191,13 @@ __global__ __launch_bounds__(64 * KW * NS) __attribute__((amdgpu_waves_per_eu(1,
     if (!present[f]) continue;
     const int c0 = face_off(g, f), c1 = c0 + face_len(g, f);
     const long fo = DIRECT ? (long)pick4(F.in_off, f) - c0 : 0;  // gin[rhs * nif + fo + col]
-    // this wavefront's k-steps: c0 + 4 (w + KW q), KB of them per batch
-    for (int c = c0 + 4 * w; c < c1; c += 4 * KW * KB) {
+    // this wavefront's k-steps: c0 + 4 (w + KWT q), KB of them per batch
+    for (int c = c0 + 4 * w; c < c1; c += 4 * KWT * KB) {
       C tv[KB];
       BT gv[KB][TW];
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
-        const int col = c + 4 * KW * b + k;
+        const int col = c + 4 * KWT * b + k;
         const int cc = col < c1 ? col : c1 - 1;
         tv[b] = Ts[(size_t)cc * kTR];
 #pragma unroll
@@ -204,7 +206,7 @@ __global__ __launch_bounds__(64 * KW * NS) __attribute__((amdgpu_waves_per_eu(1,
       __builtin_amdgcn_sched_barrier(0);  // keep the whole batch of loads ahead of the MFMAs
 #pragma unroll
       for (int b = 0; b < KB; ++b) {
-        const M ok = (c + 4 * KW * b + k < c1) ? amask : (M)0;
+        const M ok = (c + 4 * KWT * b + k < c1) ? amask : (M)0;
         const M ar = (M)tv[b].x * ok, ai = (M)tv[b].y * ok;
 #pragma unroll
         for (int t = 0; t < TW; ++t) {
@@ -218,8 +220,9 @@ __global__ __launch_bounds__(64 * KW * NS) __attribute__((amdgpu_waves_per_eu(1,
     }
   }
   }
-  // sum the KW partial tiles: the wavefronts of group 0 finish right-hand-side block t = w
-  __shared__ M red[KW][TB][2][4][64];
+  // sum the KWT partial tiles: wavefront w of group 0 finishes the (block t, register reg) pairs
+  // p = w, w + KWT, ... of the 16 (t = p / 4, reg = p % 4)
+  __shared__ M red[KWT][TB][2][4][64];
 #pragma unroll
   for (int t = 0; t < TW; ++t)
 #pragma unroll
@@ -229,12 +232,12 @@ __global__ __launch_bounds__(64 * KW * NS) __attribute__((amdgpu_waves_per_eu(1,
     }
   __syncthreads();
   if (grp != 0) return;
-  const int t = w;  // KW == TB
 #pragma unroll
-  for (int reg = 0; reg < 4; ++reg) {
+  for (int p = w; p < TB * 4; p += KWT) {
+    const int t = p >> 2, reg = p & 3;
     double sr = 0.0, si = 0.0;
 #pragma unroll
-    for (int q = 0; q < KW; ++q) {
+    for (int q = 0; q < KWT; ++q) {
       sr += (double)red[q][t][0][reg][lane];
       si += (double)red[q][t][1][reg][lane];
     }
@@ -363,11 +366,10 @@ hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int m
   int rows = 0;
   for (int f = 0; f < 4; ++f)
     if ((mask >> f) & 1) rows += face_len(g, f);
-  static_assert(KW == TB, "one right-hand-side block per wavefront in the epilogue");
   const dim3 grid((rows + 15) / 16, nsub, (nrhs + 16 * TB - 1) / (16 * TB));
   typedef typename std::conditional<sizeof(C) == 16, double, float>::type M;
-  auto go = [&](auto kern, auto src, int ns) {
-    hipLaunchKernelGGL(kern, grid, dim3(64 * KW * ns), 0, st, g, subs, mask, ft, T, src, nrhs, rpad, io);
+  auto go = [&](auto kern, auto src, int ns, int kw = KW) {
+    hipLaunchKernelGGL(kern, grid, dim3(64 * kw * ns), 0, st, g, subs, mask, ft, T, src, nrhs, rpad, io);
   };
   switch (variant) {
     case 0: go(k_scatter_mm<C, M, 2, false, 1>, G, 1); break;
@@ -388,6 +390,10 @@ hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int m
     case 15: go(k_scatter_mm<C, M, 1, true, 2, 8, true>, gin, 2); break;
     case 16: go(k_scatter_mm<C, M, 4, false, 2, 0, true>, G, 2); break;
     case 17: go(k_scatter_mm<C, M, 2, true, 2, 0, true>, gin, 2); break;
+    case 18: go(k_scatter_mm<C, M, 2, false, 1, 0, false, 8>, G, 1, 8); break;
+    case 19: go(k_scatter_mm<C, M, 4, false, 1, 0, false, 8>, G, 1, 8); break;
+    case 20: go(k_scatter_mm<C, M, 2, true, 1, 0, false, 8>, gin, 1, 8); break;
+    case 21: go(k_scatter_mm<C, M, 4, true, 1, 0, false, 8>, gin, 1, 8); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

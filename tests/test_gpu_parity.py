@@ -282,8 +282,8 @@ def test_dense_operators_many_rhs(ctxs, name, kw):
     assert all(v > 0 for v in tun[used]["us"].values())
 
 
-@pytest.mark.parametrize("variant,nr", [(v, 20) for v in range(18)] + [(1, 70), (4, 70), (10, 70), (13, 70), (15, 70),
-                                                                       (16, 70), (17, 70)])
+@pytest.mark.parametrize("variant,nr", [(v, 20) for v in range(22)] + [(1, 70), (4, 70), (10, 70), (13, 70), (15, 70),
+                                                                       (16, 70), (17, 70), (19, 70), (20, 70)])
 @pytest.mark.parametrize("kw", [{}, dict(precision=1)])
 def test_operator_kernel_variants(hbj, ctxs, kw, variant, nr):
     """Every variant of the many-RHS operator kernel (tile depth 2/4/8 or a ring of 4/8 k-steps,
@@ -307,14 +307,14 @@ def test_operator_kernel_variants(hbj, ctxs, kw, variant, nr):
         assert rel(z[k], sweep.apply_bj(dd, gv[k])) < tol_pc
     used = ("c64" if kw else "c128") + " steps"
     want = hbj.mm_variant_fields(variant)
-    for key in ("k_steps_per_batch", "incoming", "wave_groups", "ring", "xcd_order"):
+    for key in ("k_steps_per_batch", "incoming", "wave_groups", "k_waves", "ring", "xcd_order"):
         assert tun[used][key] == want[key]
 
 
 def test_set_tuning_rejects_bad_variants(hbj, ctxs):
     wl, m, g, dd, ctx = ctxs("ragged", operator_form=1)
     with pytest.raises(hbj.HbjError):
-        ctx.set_tuning([0, 0, 18, 0])
+        ctx.set_tuning([0, 0, 22, 0])
     with pytest.raises(hbj.HbjError):
         ctx.set_tuning([-2, 0, 0, 0])
 

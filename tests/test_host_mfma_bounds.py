@@ -150,6 +150,6 @@ def test_ring_kloop_covers_every_column_once_and_stays_in_bounds():
 
 def test_kernel_source_has_the_ring_arithmetic():
     src = open(SRC).read()
-    assert "const int col = 4 * (KW * m + w) + k;" in src
+    assert "const int col = 4 * (KWT * m + w) + k;" in src
     assert "const int fo = fo0 + (int)c1 * (fo1 - fo0) + (int)c2 * (fo2 - fo1) + (int)c3 * (fo3 - fo2);" in src
     assert "const int off = ok ? fo + cc * ics : 0;" in src
