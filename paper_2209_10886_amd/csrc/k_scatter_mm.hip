@@ -123,6 +123,27 @@ __global__ __launch_bounds__(64 * KWT * NS) __attribute__((amdgpu_waves_per_eu(1
     const long r = min(rb0 + 16 * (tb0 + t) + i, nrhs - 1);
     jr[t] = DIRECT ? r * g.nif : (long)j * L * rpad + r;
   }
+  // the epilogue's outputs, with their base values loaded before the k loop (wavefronts of group 0:
+  // pair p = w + KWT n is block t = p / 4, register reg = p % 4); an output that is not stored
+  // loads the interface vector's first entry instead (every load in bounds and unconditional)
+  constexpr int NP = (TB * 4 + KWT - 1) / KWT;
+  size_t opos[NP];
+  double2 obase[NP];
+  if (grp == 0) {
+#pragma unroll
+    for (int n = 0; n < NP; ++n) {
+      const int p = w + KWT * n;
+      const int reg = p & 3;
+      const int row = masked_row_mm(g, mask, bx * 16 + A::row_of(lane, reg));
+      const int rhs = rb0 + 16 * (p >> 2) + (lane & 15);
+      int rf = 0, re = 0;
+      if (row >= 0) local_if_face(g, row, &rf, &re);
+      const int oo = pick4(F.out_off, rf);
+      const bool ok = p < TB * 4 && row >= 0 && rhs < nrhs && oo >= 0;
+      opos[n] = ok ? (size_t)rhs * g.nif + oo + re : ~(size_t)0;
+      obase[n] = io.tr_base ? io.tr_base[ok ? opos[n] : 0] : mk(0.0, 0.0);
+    }
+  }
   V4 cr[TW], ci[TW];
 #pragma unroll
   for (int t = 0; t < TW; ++t) {
@@ -233,7 +254,9 @@ __global__ __launch_bounds__(64 * KWT * NS) __attribute__((amdgpu_waves_per_eu(1
   __syncthreads();
   if (grp != 0) return;
 #pragma unroll
-  for (int p = w; p < TB * 4; p += KWT) {
+  for (int n = 0; n < NP; ++n) {
+    const int p = w + KWT * n;
+    if (p >= TB * 4) break;  // uniform
     const int t = p >> 2, reg = p & 3;
     double sr = 0.0, si = 0.0;
 #pragma unroll
@@ -241,18 +264,11 @@ __global__ __launch_bounds__(64 * KWT * NS) __attribute__((amdgpu_waves_per_eu(1
       sr += (double)red[q][t][0][reg][lane];
       si += (double)red[q][t][1][reg][lane];
     }
-    const int ii = A::row_of(lane, reg), jj = lane & 15;
-    const int row = masked_row_mm(g, mask, bx * 16 + ii);
-    const int rhs = rb0 + 16 * t + jj;
-    if (row < 0 || rhs >= nrhs) continue;
-    int rf, re;
-    local_if_face(g, row, &rf, &re);
-    if (F.out_off[rf] < 0) continue;
-    const size_t o = (size_t)rhs * g.nif + F.out_off[rf] + re;
-    double2 base = io.tr_base ? io.tr_base[o] : mk(0.0, 0.0);
+    if (opos[n] == ~(size_t)0) continue;
+    double2 base = obase[n];
     base.x += io.tr_sign * sr;
     base.y += io.tr_sign * si;
-    io.tr_dst[o] = base;
+    io.tr_dst[opos[n]] = base;
   }
 }
 
