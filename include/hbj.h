@@ -423,9 +423,19 @@ int hbj_set_operator_overlap(hbj_ctx* ctx, int32_t on);
  * XCDs so that all row tiles of one subdomain share an L2.  Variants 18-21: one
  * group of eight wavefronts splitting the k range (each A operand loaded once),
  * 2 or 4 k-steps per batch, gathered (18, 19) or direct (20, 21).
+ * Timing: a warm-up round times every variant once; those within twice the best
+ * time there run three more rounds, taking turns, and the lowest mean wins.  The
+ * choice is stored in the tuning cache (hbj_tune_cache_path) under the device,
+ * precision, launch kind, checkerboard, subdomain size and right-hand sides padded
+ * to 16, 32, 64 or 128, and a later context with the same key reads it back
+ * without timing.  With HBJ_TUNE=0 in the environment, or on a stream under graph
+ * capture, and no cache entry: variant 15 for sweep steps and 7 for the operator,
+ * untimed.
  *   variants  HOST [4]: complex128 sweep steps, complex128 operator, complex64
  *             sweep steps, complex64 operator; -1 = not tuned yet.
- *   us        HOST [4][22] or NULL: the measured microseconds per launch.
+ *   us        HOST [4][22] or NULL: the measured microseconds per launch (the mean
+ *             of three rounds, or the warm-up time for a variant that dropped out;
+ *             all zero for a choice read from the cache, set, or taken untimed).
  */
 int hbj_get_tuning(const hbj_ctx* ctx, int32_t* variants, float* us);
 
@@ -497,7 +507,8 @@ int32_t hbj_tune_cache_size(void);
  * hbj_set_tuning - fix the variants of the many-right-hand-side operator kernel
  * instead of timing them (reproducible timings, tests of every variant).
  *   variants  HOST [4], same order as hbj_get_tuning; each in 0..21, or -1 to let
- *             the autotuner choose on the next launch of that kind.
+ *             the autotuner choose (or read the tuning cache) on the next launch
+ *             of that kind.
  * Returns HBJ_EINVAL for a value outside -1..21 (nothing is changed then).
  */
 int hbj_set_tuning(hbj_ctx* ctx, const int32_t* variants);

@@ -849,6 +849,24 @@ int run_dense(hbj_ctx* c, const Entry* ent, const FaceTab* eft, int nent, int ma
                  : launch_scatter_mm<double2>(c->g, subs, nsub, mask, c->ft, c->T64, gin, c->Gbuf, nrhs, rpad, lio,
                                               c->st, v);
     };
+    // cache key of this launch kind: device, precision, operator or steps, checkerboard, subdomain,
+    // padded right-hand sides (by powers of two)
+    char mkey[128];
+    {
+      int r2 = 16;
+      while (r2 < rpad && r2 < 128) r2 *= 2;
+      std::snprintf(mkey, sizeof mkey, "mm|%s|%s|%s|%dx%d|%dx%d|r%d", c->arch.c_str(), c64 ? "c64" : "c128",
+                    mask == 0xF ? "op" : "steps", c->g.n1, c->g.n2, c->g.snx, c->g.sny, r2);
+    }
+    if (c->mm_variant[slot] < 0) {
+      int v = -1;
+      if (!(tune_cache_get(mkey, &v) && v >= 0 && v < kMmVariants) && !tuning_enabled(c))
+        v = mask == 0xF ? 7 : 15;  // no timing allowed: the usual winners on gfx950 (see hbj_get_tuning)
+      if (v >= 0) {
+        c->mm_variant[slot] = v;
+        for (int q = 0; q < kMmVariants; ++q) c->mm_us[slot][q] = 0.f;
+      }
+    }
     if (c->mm_variant[slot] < 0) {
       // autotuner: time every variant on this very launch, writing into scratch, keep the fastest
       // (after the device is idle: the source part of a reconstruction may still run on the second
@@ -861,28 +879,41 @@ int run_dense(hbj_ctx* c, const Entry* ent, const FaceTab* eft, int nent, int ma
       tio.tr_base = nullptr;
       // the variants take turns (three rounds after a warm-up round), so that each one is timed after
       // another has streamed its data, as in a solve, rather than on caches it has just filled itself
+      // (the warm-up round is timed too: a variant at more than twice the best time there drops out)
       hipError_t he = hipSuccess;
-      float tot[kMmVariants] = {};
-      for (int v = 0; v < kMmVariants && he == hipSuccess; ++v) he = launch(v, tio);
+      float tot[kMmVariants] = {}, first[kMmVariants] = {};
+      bool alive[kMmVariants];
+      auto timed = [&](int v, float* ms) -> hipError_t {
+        hipError_t e = hipEventRecord(c->ev0, c->st);
+        if (e == hipSuccess) e = launch(v, tio);
+        if (e == hipSuccess) e = hipEventRecord(c->ev1, c->st);
+        if (e == hipSuccess) e = hipEventSynchronize(c->ev1);
+        if (e == hipSuccess) e = hipEventElapsedTime(ms, c->ev0, c->ev1);
+        return e;
+      };
+      float fbest = 1e30f;
+      for (int v = 0; v < kMmVariants && he == hipSuccess; ++v) {
+        he = timed(v, &first[v]);
+        fbest = std::min(fbest, first[v]);
+      }
+      for (int v = 0; v < kMmVariants; ++v) alive[v] = first[v] <= 2.0f * fbest;
       for (int rep = 0; rep < 3 && he == hipSuccess; ++rep)
         for (int v = 0; v < kMmVariants && he == hipSuccess; ++v) {
-          he = hipEventRecord(c->ev0, c->st);
-          if (he == hipSuccess) he = launch(v, tio);
-          if (he == hipSuccess) he = hipEventRecord(c->ev1, c->st);
-          if (he == hipSuccess) he = hipEventSynchronize(c->ev1);
+          if (!alive[v]) continue;
           float ms = 0.f;
-          if (he == hipSuccess) he = hipEventElapsedTime(&ms, c->ev0, c->ev1);
+          he = timed(v, &ms);
           tot[v] += ms;
         }
-      int best = 0;
+      int best = -1;
       for (int v = 0; v < kMmVariants; ++v) {
-        c->mm_us[slot][v] = tot[v] / 3.0f * 1e3f;
-        if (tot[v] < tot[best]) best = v;
+        c->mm_us[slot][v] = (alive[v] ? tot[v] / 3.0f : first[v]) * 1e3f;
+        if (alive[v] && (best < 0 || tot[v] < tot[best])) best = v;
       }
       (void)hipStreamSynchronize(c->st);
       dfree(scratch);
       if (he != hipSuccess) return fail(HBJ_EHIP, hipGetErrorString(he));
-      c->mm_variant[slot] = best;
+      c->mm_variant[slot] = best < 0 ? 0 : best;
+      tune_cache_put(mkey, c->mm_variant[slot], c->mm_us[slot], kMmVariants);  // a write failure only loses the cache
     }
     ProfScope ps(c, mask == 0xF ? HBJ_K_OPERATOR : HBJ_K_SCATTER, tbytes, elems * 8.0);
     HIPCHK(launch(c->mm_variant[slot], io));

@@ -275,11 +275,13 @@ def test_dense_operators_many_rhs(ctxs, name, kw):
     for k in range(nr):
         assert rel(w[k], dd.apply_operator(gv[k])) < 1e-12
         assert rel(z[k], sweep.apply_bj(dd, gv[k])) < tol_pc
-    # the autotuner timed every tile depth on the first launch of each kind and kept one
+    # the autotuner timed every variant on the first launch of each kind and kept one, or read the
+    # choice of an earlier context with the same geometry from the tuning cache (nothing timed)
     tun = ctx.tuning()
     used = ("c64" if kw else "c128") + " steps"
     assert tun[used]["k_steps_per_batch"] in (2, 4, 8)
-    assert all(v > 0 for v in tun[used]["us"].values())
+    us = list(tun[used]["us"].values())
+    assert all(v > 0 for v in us) or all(v == 0 for v in us)
 
 
 @pytest.mark.parametrize("variant,nr", [(v, 20) for v in range(22)] + [(1, 70), (4, 70), (10, 70), (13, 70), (15, 70),

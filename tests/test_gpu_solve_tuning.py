@@ -1,10 +1,11 @@
-"""Autotuned launch shapes of the banded local solves, through the C ABI.
+"""Autotuned launch shapes of the banded local solves and of the dense operator kernel, through the C ABI.
 
 A batch of banded solves runs in one of four shapes: one workgroup per solve at three register prefetch
 depths (the same arithmetic in the same order: results bit for bit equal), or 16 right-hand sides per
 workgroup on MFMA (equal up to rounding). The autotuner times the candidates on the first batch of each
 class, keeps the fastest and records it in the tuning cache file; a later context reads the decision back
-instead of timing. Every shape is compared with the oracle.
+instead of timing. Every shape is compared with the oracle. The variant of the many-right-hand-side
+operator kernel goes to the same cache.
 """
 import json
 import os
@@ -140,3 +141,68 @@ def test_bad_shape(hbj):
             ctx.set_solve_tuning(bad)
         assert ei.value.code == hbj.EINVAL
     ctx.close()
+
+
+def _dense_run(hbj, wl, m, gv, precision):
+    ctx = gpu_context(hbj, wl, m, operator_form=hbj.OP_DENSE, precision=precision)
+    ctx.factor()
+    w = _np(ctx.apply_operator(gv))
+    z = _np(ctx.apply_preconditioner(gv))
+    t = ctx.tuning()
+    ctx.close()
+    return w, z, t
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_operator_kernel_choice_is_cached(hbj, tmp_path, precision):
+    """A first context times the variants of the dense operator kernel and stores its choices; a second
+    context reads them back (no timing) and gives the same results bit for bit."""
+    wl = CASES["ragged"].wl
+    m, g, dd = oracle_problem(wl)
+    path = tmp_path / "tune.json"
+    used = [("c64" if precision else "c128") + " steps", "c128 operator"]
+    hbj.set_tune_cache_path(str(path))
+    try:
+        gv = torch.as_tensor(W.random_interface_vector(dd.nif, seed=44, nrhs=NRHS), device="cuda")
+        say(f"[operator kernel cache] first context times, precision={precision}")
+        wa, za, ta = _dense_run(hbj, wl, m, gv, precision)
+        for k in used:
+            assert ta[k]["us"] is not None and all(v > 0 for v in ta[k]["us"].values())
+        entries = json.loads(path.read_text())["entries"]
+        mm = {k: v for k, v in entries.items() if k.startswith("mm|")}
+        assert len(mm) == 2
+        for key, e in mm.items():
+            assert 0 <= e["variant"] < hbj.MM_VARIANTS
+            assert len(e["us"]) == hbj.MM_VARIANTS
+        say("[operator kernel cache] second context reads the file")
+        hbj.set_tune_cache_path(str(path))
+        wb, zb, tb = _dense_run(hbj, wl, m, gv, precision)
+        for k in used:
+            assert {q: tb[k][q] for q in ("incoming", "k_steps_per_batch", "ring", "wave_groups", "k_waves")} == \
+                {q: ta[k][q] for q in ("incoming", "k_steps_per_batch", "ring", "wave_groups", "k_waves")}
+            assert all(v == 0 for v in tb[k]["us"].values())
+        assert np.array_equal(wa, wb)
+        assert np.array_equal(za, zb)
+        e = max(rel(wa[k], dd.apply_operator(_np(gv)[k])) for k in range(NRHS))
+        assert e < 1e-12
+    finally:
+        hbj.set_tune_cache_path(None)
+
+
+def test_operator_kernel_untimed_default(hbj, monkeypatch):
+    """HBJ_TUNE=0 and no cache: the operator kernel takes variant 15 for sweep steps, 7 for the operator."""
+    wl = CASES["ragged"].wl
+    m, g, dd = oracle_problem(wl)
+    monkeypatch.setenv("HBJ_TUNE", "0")
+    hbj.set_tune_cache_path("")
+    try:
+        gv = W.random_interface_vector(dd.nif, seed=45, nrhs=NRHS)
+        say("[operator kernel untimed] ragged")
+        w, z, t = _dense_run(hbj, wl, m, torch.as_tensor(gv, device="cuda"), 0)
+    finally:
+        hbj.set_tune_cache_path(None)
+    assert t["c128 steps"] == dict(hbj.mm_variant_fields(15), us=t["c128 steps"]["us"])
+    assert t["c128 operator"] == dict(hbj.mm_variant_fields(7), us=t["c128 operator"]["us"])
+    for k in ("c128 steps", "c128 operator"):
+        assert all(v == 0 for v in t[k]["us"].values())
+    assert max(rel(w[k], dd.apply_operator(gv[k])) for k in range(NRHS)) < 1e-12
