@@ -65,6 +65,9 @@ def parse():
     p.add_argument("--no-second-order", action="store_true",
                    help="skip the run with the second-order transmission condition")
     p.add_argument("--no-multi", action="store_true", help="skip the 2048^2 64-source leg")
+    p.add_argument("--orth", choices=("cgs2", "dcgs2", "sstep"), default=None,
+                   help="Gram-Schmidt form of the Arnoldi steps for every context (default: the library's)")
+    p.add_argument("--sstep-block", type=int, default=None, help="steps per block of the s-step form (1-8)")
     p.add_argument("--no-gradient", action="store_true", help="skip the 512^2 adjoint-gradient leg")
     p.add_argument("--transmission", type=int, default=1, choices=(1, 2, 3),
                    help="transmission condition of the main run (1: Robin, as the workloads specify; 2: second order; "
@@ -281,6 +284,8 @@ def cpu_entry(wl, timing, iters_gpu, kind_note):
 # ---------------------------------------------------------------------------
 
 OVERLAP = False  # hbj_set_operator_overlap for every context of the run (--overlap sets it)
+ORTH = None  # hbj_set_orthogonalization for every context of the run (--orth; None: the library's default)
+SSTEP_BLOCK = None  # hbj_set_sstep_block (--sstep-block)
 
 
 def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, profile_names, graphs=False,
@@ -292,6 +297,10 @@ def run_form(hbj, wl, mt, ft, u, precision, operator_form, steps, warmup, tol, p
                     operator_form=operator_form, transmission=transmission, device=mt.device)
     ctx.set_graphs(graphs)
     ctx.set_operator_overlap(OVERLAP)
+    if ORTH is not None:
+        ctx.set_orthogonalization(ORTH)
+    if SSTEP_BLOCK is not None:
+        ctx.set_sstep_block(SSTEP_BLOCK)
     torch.cuda.synchronize()
     # the first factorisation also runs the autotuner of the banded solve batches when the tuning
     # cache has no entry for them yet; the second one is the steady-state figure
@@ -620,9 +629,11 @@ def only_leg(args):
 
 
 def main():
-    global OVERLAP
+    global OVERLAP, ORTH, SSTEP_BLOCK
     args = parse()
     OVERLAP = args.overlap
+    ORTH = {"cgs2": 0, "dcgs2": 1, "sstep": 2, None: None}[args.orth]  # the library's ORTH_* values
+    SSTEP_BLOCK = args.sstep_block
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form of the sweep is a "
               "design, not a measured configuration", file=sys.stderr)

@@ -369,11 +369,28 @@ int hbj_set_graphs(hbj_ctx* ctx, int32_t on);
  *                   one inner-product pass and one update pass (two launches); Hessenberg
  *                   column j is completed one step later, and convergence is tested on a
  *                   provisional column so that no extra step runs.  Default.
+ *   HBJ_ORTH_SSTEP  s-step cycles (Hoemmen, Communication-avoiding Krylov subspace
+ *                   methods, 2010): s preconditioner and operator applications build the
+ *                   Newton basis y_{i+1} = (I - S) P^{-1} y_i - y_i (shift 1) from the last
+ *                   basis vector, then one inner-product pass and one update pass over the
+ *                   basis make all s vectors orthonormal (block classical Gram-Schmidt with
+ *                   the Pythagorean Cholesky QR, Carson, Lund, Rozloznik and Thomas, Linear
+ *                   Algebra Appl. 2022): two passes per s steps instead of two per step.
+ *                   Convergence is found at the exact step (the Hessenberg columns of a block
+ *                   are formed one by one); the rest of that block's applications are unused.
+ *                   Needs flexible GMRES (hbj_solve_opts.flexible = 1) and a restart length of
+ *                   at most 63; HBJ_ORTH_DCGS2 is used otherwise.  s: hbj_set_sstep_block.
  * Restart lengths above 255 use HBJ_ORTH_CGS2.  A change drops captured graphs.
  * Returns HBJ_EINVAL for any other value.
  */
-enum { HBJ_ORTH_CGS2 = 0, HBJ_ORTH_DCGS2 = 1 };
+enum { HBJ_ORTH_CGS2 = 0, HBJ_ORTH_DCGS2 = 1, HBJ_ORTH_SSTEP = 2 };
 int hbj_set_orthogonalization(hbj_ctx* ctx, int32_t mode);
+
+/*
+ * hbj_set_sstep_block - steps per block of the HBJ_ORTH_SSTEP cycles, 1..8 (default 8; the
+ * last block of a restart cycle may be shorter).  Returns HBJ_EINVAL outside 1..8.
+ */
+int hbj_set_sstep_block(hbj_ctx* ctx, int32_t s);
 
 /*
  * hbj_set_multi_solve - how the banded local solves (Sec. 4: every application of the

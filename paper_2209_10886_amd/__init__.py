@@ -32,7 +32,7 @@ BJ_RESTRICTED, BJ_ADDITIVE = 0, 1
 BJ_PRODUCT, BJ_RESIDUAL = 0, 1
 OP_BANDED, OP_DENSE = 0, 1
 SWEEP_STEPPED, SWEEP_DATAFLOW = 0, 1
-ORTH_CGS2, ORTH_DCGS2 = 0, 1  # Gram-Schmidt variant of the Arnoldi steps
+ORTH_CGS2, ORTH_DCGS2, ORTH_SSTEP = 0, 1, 2  # Gram-Schmidt variant of the Arnoldi steps
 MSOLVE_CHAINS, MSOLVE_MFMA = 0, 1  # banded solves of many right-hand sides per subdomain
 OK, EINVAL, ESTATE, EHIP, ENOMEM, EWAIT, EIO, ZERO_PIVOT, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, -6, 1, 2
 # launch shapes of the banded solve batches (hbj_set_solve_tuning): one workgroup per solve at three
@@ -108,6 +108,7 @@ _SIGS = {
     "hbj_tune_cache_size": (_I32, []),
     "hbj_set_graphs": (_I, [_P, _I32]),
     "hbj_set_orthogonalization": (_I, [_P, _I32]),
+    "hbj_set_sstep_block": (_I, [_P, _I32]),
     "hbj_set_multi_solve": (_I, [_P, _I32]),
     "hbj_strerror": (ctypes.c_char_p, [_I]),
     "hbj_last_error": (ctypes.c_char_p, []),
@@ -329,9 +330,14 @@ class Context:
         _check(_lib.hbj_set_graphs(self._h, 1 if on else 0))
 
     def set_orthogonalization(self, mode):
-        """ORTH_CGS2 (classical Gram-Schmidt twice) or ORTH_DCGS2 (delayed reorthogonalisation,
-        default) for the Arnoldi steps."""
+        """ORTH_CGS2 (classical Gram-Schmidt twice), ORTH_DCGS2 (delayed reorthogonalisation,
+        default) or ORTH_SSTEP (s-step cycles: blocks of s steps orthogonalised together) for the
+        Arnoldi steps."""
         _check(_lib.hbj_set_orthogonalization(self._h, int(mode)))
+
+    def set_sstep_block(self, s):
+        """Steps per block of the ORTH_SSTEP cycles (1..8, default 8)."""
+        _check(_lib.hbj_set_sstep_block(self._h, int(s)))
 
     def set_multi_solve(self, mode):
         """MSOLVE_CHAINS (one workgroup per subdomain and right-hand side) or MSOLVE_MFMA (16

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libhbj.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["k_setup.hip", "k_factor.hip", "k_trisolve.hip", "k_krylov.hip", "k_misc.hip", "k_scatter.hip", "k_scatter_mm.hip",
-           "k_sweep_df.hip", "k_lift.hip", "k_pade.hip",
+           "k_sweep_df.hip", "k_lift.hip", "k_pade.hip", "k_sstep.hip",
            "runtime.hip", "tune_cache.cpp"]
 
 ARCH = os.environ.get("HBJ_OFFLOAD_ARCH", "gfx950")

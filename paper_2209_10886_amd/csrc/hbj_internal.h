@@ -291,6 +291,18 @@ hipError_t launch_update_reduce(double2* w, const double2* V, size_t vstride, in
                                 double* npart, hipStream_t st);
 hipError_t launch_scale_reduce(double2* dst, const double2* src, const double* npart, double* nrm_out, int n, int ncol,
                                hipStream_t st);
+// s-step Arnoldi: block Gram-Schmidt of up to kSstepMax new vectors against at most
+// kSstepMaxBasis - kSstepMax earlier ones (inner products, Cholesky of the projected Gram matrix,
+// update in place); per column a coefficient record of kSstepCoefLd entries (R, R^{-1}, the first
+// failed pivot, C)
+constexpr int kSstepMax = 8;
+constexpr int kSstepMaxBasis = 64;
+constexpr int kSstepCoefLd = 129 + kSstepMaxBasis * kSstepMax;
+int bgs_positions_per_wave(int n, int ncol);
+int bgs_chunks(int n, int ncol);
+size_t bgs_partial_elems(int n, int ncol);
+hipError_t launch_bgs(double2* V, size_t vstride, int k1, int sb, int n, int ncol, double2* part, size_t part_elems,
+                      double2* coef, int ldc, hipStream_t st);
 // Gram-Schmidt with delayed reorthogonalisation: one pass of inner products, one update pass
 bool dcgs_fits(int m, int nchunk);
 hipError_t launch_dots2(const double2* V, size_t vstride, int nv, const double2* x, const double2* w, int n, int ncol,

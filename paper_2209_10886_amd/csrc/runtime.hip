@@ -205,6 +205,7 @@ struct hbj_ctx {
   Gmres* gm = nullptr;
   bool use_graphs = false;  // eager launches measured faster once step j+1 is queued ahead
   int orth = HBJ_ORTH_DCGS2;     // Gram-Schmidt variant of the Arnoldi steps
+  int sstep_block = kSstepMax;   // steps per block of the s-step Arnoldi cycle
   bool interchanges = true;      // some subdomain factorisation has row interchanges (set by hbj_factor)
   int msolve = HBJ_MSOLVE_MFMA;  // banded solves of many right-hand sides per subdomain on MFMA
   int graph_epoch = 0;           // bumped when captured operands change (a new factorisation)
@@ -1626,6 +1627,9 @@ struct Gmres {
   int nchunk2 = 0;  // the same for the delayed-reorthogonalisation pass (twice as many products)
   std::vector<hipGraphExec_t> graphs;  // iteration j of a restart cycle, captured at first use
   int graph_epoch = -1;
+  // s-step cycles: inner-product partials, the coefficient records and their pinned host copy
+  double2 *bpart = nullptr, *coef = nullptr, *coef_host = nullptr;
+  size_t bpart_elems = 0;
   double2* hbuf_host = nullptr;        // pinned host h1 | h2 | norms, two slots (step j uses slot j & 1)
   double2* hbuf_mapped = nullptr;      // the same memory as the kernels address it
   hipEvent_t ev_h[2] = {nullptr, nullptr};
@@ -1644,9 +1648,19 @@ struct Gmres {
     for (auto& e : ev_h)
       if (e) (void)hipEventDestroy(e);
     if (hbuf_host) (void)hipHostFree(hbuf_host);
+    if (coef_host) (void)hipHostFree(coef_host);
     for (void* p : {(void*)V, (void*)Z, (void*)w, (void*)b, (void*)x, (void*)r, (void*)zt, (void*)hbuf,
-                    (void*)ydev, (void*)partial, (void*)npartial})
+                    (void*)ydev, (void*)partial, (void*)npartial, (void*)bpart, (void*)coef})
       dfree(p);
+  }
+  int alloc_sstep() {
+    if (coef) return HBJ_OK;
+    bpart_elems = bgs_partial_elems(nif, ncol);
+    if (dalloc(&bpart, bpart_elems) || dalloc(&coef, (size_t)ncol * kSstepCoefLd))
+      return fail(HBJ_ENOMEM, "s-step workspace allocation failed");
+    if (hipHostMalloc((void**)&coef_host, (size_t)ncol * kSstepCoefLd * sizeof(double2), 0) != hipSuccess)
+      return fail(HBJ_ENOMEM, "s-step host buffer allocation failed");
+    return HBJ_OK;
   }
   size_t vs() const { return (size_t)ncol * nif; }
   double2* Vi(int i) { return V + (size_t)i * vs(); }
@@ -1739,7 +1753,15 @@ int arnoldi_kernels(hbj_ctx* c, Schedule* S, Gmres& G, int j) {
 
 // Delayed reorthogonalisation when asked for and when the restart length fits its fused kernels;
 // the choice holds for a whole solve.
-bool use_dcgs(const hbj_ctx* c, const Gmres& G) { return c->orth == HBJ_ORTH_DCGS2 && dcgs_fits(G.m, G.nchunk2); }
+// s-step cycles when asked for, with flexible storage (the solution is formed from the kept
+// preconditioned vectors) and a basis that fits the block kernels; delayed reorthogonalisation
+// otherwise
+bool use_sstep(const hbj_ctx* c, const Gmres& G) {
+  return c->orth == HBJ_ORTH_SSTEP && G.flexible && G.m + 1 <= kSstepMaxBasis;
+}
+bool use_dcgs(const hbj_ctx* c, const Gmres& G) {
+  return (c->orth == HBJ_ORTH_DCGS2 || (c->orth == HBJ_ORTH_SSTEP && !use_sstep(c, G))) && dcgs_fits(G.m, G.nchunk2);
+}
 
 // Arnoldi step j with delayed reorthogonalisation: z = P^{-1} x_j (x_j = V_j after one
 // Gram-Schmidt pass), w = (I - S) z, one inner-product pass and one update pass (v_j into V_j,
@@ -1843,6 +1865,7 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
   std::vector<int> jc(ncol);
   std::vector<double2> yh((size_t)ncol * (m + 1));
   auto Hc = [&](int k, int i, int j) -> zc& { return H[((size_t)k * (m + 1) + i) * m + j]; };
+  const bool sst = use_sstep(c, G);
   const bool dcgs = use_dcgs(c, G);
   // delayed reorthogonalisation: R (x_j = V R e_j), and c^(j), s_j, |w_j|^2 of the last step
   std::vector<zc> R(dcgs ? (size_t)ncol * m * m : 0), cprev(dcgs ? (size_t)ncol * (m + 1) : 0);
@@ -1864,7 +1887,78 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
       std::fill(&e1[(size_t)k * (m + 1)], &e1[(size_t)k * (m + 1)] + m + 1, zc(0.0));
       e1[(size_t)k * (m + 1)] = rnorm[k];
     }
-    if (!dcgs) {
+    if (sst) {
+      // s-step cycle in blocks of sb steps.  Per block: sb preconditioner and operator applications
+      // build y_{i+1} = (I - S) z_{k+i} - y_i with z_{k+i} = P^{-1} y_i (kept in Z) from y_0 = V_k,
+      // in the slots V_{k+1..k+sb}; one block Gram-Schmidt turns them into orthonormal vectors there
+      // (y_{l+1} = V_{<=k} C e_l + V_{k+1..k+sb} R e_l), and the host forms Hessenberg columns
+      // k..k+sb-1 from (I - S) z_{k+i} = y_i + y_{i+1}.  The GPU idles only while the host reads a
+      // block back (one block is many launches long); convergence is found at the exact step, the
+      // remaining steps of that block being unused.
+      rc = G.alloc_sstep();
+      if (rc) return rc;
+      const int kmax = std::min(m, o.maxit - total);
+      const int ld = kSstepCoefLd;
+      for (int k = 0; k < kmax;) {
+        const int sb = std::min(c->sstep_block, kmax - k);
+        for (int i = 0; i < sb; ++i) {
+          rc = pc_op(c, S, G.Vi(k + i), G.Zi(k + i), G.Vi(k + i + 1), ncol);
+          if (rc) return rc;
+          ProfScope ps(c, HBJ_K_KRYLOV, 3.0 * vs * 16.0, 8.0 * vs);
+          HIPCHK(launch_axpby(G.Vi(k + i + 1), G.Vi(k + i), mk(-1.0, 0.0), mk(1.0, 0.0), vs, c->st));
+        }
+        {
+          // the inner-product pass reads V_0..V_{k+sb}; the update pass reads them again and writes sb
+          ProfScope ps(c, HBJ_K_KRYLOV, (2.0 * (k + 1) + 3.0 * sb) * vs * 16.0, 16.0 * (k + 1 + sb) * sb * vs);
+          HIPCHK(launch_bgs(G.V, vs, k + 1, sb, nif, ncol, G.bpart, G.bpart_elems, G.coef, ld, c->st));
+        }
+        const size_t row = (size_t)(129 + (k + 1) * kSstepMax) * sizeof(double2);
+        HIPCHK(hipMemcpy2DAsync(G.coef_host, ld * sizeof(double2), G.coef, ld * sizeof(double2), row, ncol,
+                                hipMemcpyDeviceToHost, c->st));
+        HIPCHK(hipStreamSynchronize(c->st));
+        bool any_active = false;
+        for (int q = 0; q < ncol; ++q) {
+          if (!active[q]) continue;
+          const double2* cf = G.coef_host + (size_t)q * ld;
+          // coefficient of basis vector r in y_i (y_0 = V_k)
+          auto ycoef = [&](int i, int r) -> zc {
+            if (i == 0) return r == k ? zc(1.0, 0.0) : zc(0.0, 0.0);
+            const int l = i - 1;
+            double2 v = mk(0.0, 0.0);
+            if (r <= k) v = cf[129 + r * kSstepMax + l];
+            else if (r - k - 1 <= l) v = cf[(r - k - 1) * kSstepMax + l];
+            return zc(v.x, v.y);
+          };
+          double* csk = &cs[(size_t)q * m];
+          zc* snk = &sn[(size_t)q * m];
+          zc* ek = &e1[(size_t)q * (m + 1)];
+          for (int i = 0; i < sb && active[q]; ++i) {
+            const int j = k + i;
+            for (int r = 0; r <= j + 1; ++r) Hc(q, r, j) = ycoef(i, r) + ycoef(i + 1, r);
+            const double hn = std::abs(Hc(q, j + 1, j));
+            for (int r = 0; r < j; ++r) {
+              const zc t = csk[r] * Hc(q, r, j) + snk[r] * Hc(q, r + 1, j);
+              Hc(q, r + 1, j) = -std::conj(snk[r]) * Hc(q, r, j) + csk[r] * Hc(q, r + 1, j);
+              Hc(q, r, j) = t;
+            }
+            givens(Hc(q, j, j), Hc(q, j + 1, j), csk[j], snk[j]);
+            Hc(q, j, j) = csk[j] * Hc(q, j, j) + snk[j] * Hc(q, j + 1, j);
+            Hc(q, j + 1, j) = 0.0;
+            ek[j + 1] = -std::conj(snk[j]) * ek[j];
+            ek[j] = csk[j] * ek[j];
+            jc[q] = j + 1;
+            col_iters[q] += 1;
+            const double est = std::abs(ek[j + 1]) / bnorm[q];
+            if (q == 0) hist.push_back(est);
+            if (est <= o.tol || hn == 0.0 || std::abs(Hc(q, j, j)) == 0.0) active[q] = 0;
+          }
+          any_active |= active[q];
+        }
+        total += sb;
+        k += sb;
+        if (!any_active) break;
+      }
+    } else if (!dcgs) {
       // Step j + 1 is queued before the host reads step j back: it needs only V_{j+1}, already on
       // the device, so the GPU never waits for the host's Givens rotations. When the host finds
       // that every column has converged at step j, the queued step's results are simply unused.
@@ -2801,9 +2895,17 @@ int hbj_set_graphs(hbj_ctx* c, int32_t on) {
 
 int hbj_set_orthogonalization(hbj_ctx* c, int32_t mode) {
   if (!c) return fail(HBJ_EINVAL, "null context");
-  if (mode != HBJ_ORTH_CGS2 && mode != HBJ_ORTH_DCGS2) return fail(HBJ_EINVAL, "unknown orthogonalisation");
+  if (mode != HBJ_ORTH_CGS2 && mode != HBJ_ORTH_DCGS2 && mode != HBJ_ORTH_SSTEP)
+    return fail(HBJ_EINVAL, "unknown orthogonalisation");
   if (mode != c->orth) ++c->graph_epoch;  // the captured steps hold the other kernels
   c->orth = mode;
+  return HBJ_OK;
+}
+
+int hbj_set_sstep_block(hbj_ctx* c, int32_t s) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  if (s < 1 || s > kSstepMax) return fail(HBJ_EINVAL, "s-step block out of range");
+  c->sstep_block = s;
   return HBJ_OK;
 }
 
