@@ -65,7 +65,7 @@ def parse():
     p.add_argument("--no-second-order", action="store_true",
                    help="skip the run with the second-order transmission condition")
     p.add_argument("--no-multi", action="store_true", help="skip the 2048^2 64-source leg")
-    p.add_argument("--orth", choices=("cgs2", "dcgs2", "sstep"), default=None,
+    p.add_argument("--orth", choices=("cgs2", "dcgs2", "sstep", "auto"), default=None,
                    help="Gram-Schmidt form of the Arnoldi steps for every context (default: the library's)")
     p.add_argument("--sstep-block", type=int, default=None, help="steps per block of the s-step form (1-8)")
     p.add_argument("--no-gradient", action="store_true", help="skip the 512^2 adjoint-gradient leg")
@@ -632,7 +632,7 @@ def main():
     global OVERLAP, ORTH, SSTEP_BLOCK
     args = parse()
     OVERLAP = args.overlap
-    ORTH = {"cgs2": 0, "dcgs2": 1, "sstep": 2, None: None}[args.orth]  # the library's ORTH_* values
+    ORTH = {"cgs2": 0, "dcgs2": 1, "sstep": 2, "auto": 3, None: None}[args.orth]  # the library's ORTH_* values
     SSTEP_BLOCK = args.sstep_block
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU form of the sweep is a "

@@ -368,7 +368,7 @@ int hbj_set_graphs(hbj_ctx* ctx, int32_t on);
  *                   the second pass for step j's vector is merged into step j + 1, so
  *                   one inner-product pass and one update pass (two launches); Hessenberg
  *                   column j is completed one step later, and convergence is tested on a
- *                   provisional column so that no extra step runs.  Default.
+ *                   provisional column so that no extra step runs.
  *   HBJ_ORTH_SSTEP  s-step cycles (Hoemmen, Communication-avoiding Krylov subspace
  *                   methods, 2010): s preconditioner and operator applications build the
  *                   Newton basis y_{i+1} = (I - S) P^{-1} y_i - y_i (shift 1) from the last
@@ -380,10 +380,16 @@ int hbj_set_graphs(hbj_ctx* ctx, int32_t on);
  *                   are formed one by one); the rest of that block's applications are unused.
  *                   Needs flexible GMRES (hbj_solve_opts.flexible = 1) and a restart length of
  *                   at most 63; HBJ_ORTH_DCGS2 is used otherwise.  s: hbj_set_sstep_block.
+ *   HBJ_ORTH_AUTO   HBJ_ORTH_SSTEP where the Krylov vectors of all right-hand sides
+ *                   together hold at least 2^20 entries (there a pass over the basis
+ *                   outweighs the per-block costs: measured on MI355X, 64 right-hand sides on
+ *                   the 2048^2 grid of 16 x 16 subdomains take 25% less time, while one on the
+ *                   1024^2 grid and 16 on the 512^2 grid take longer), HBJ_ORTH_DCGS2
+ *                   otherwise.  Default.
  * Restart lengths above 255 use HBJ_ORTH_CGS2.  A change drops captured graphs.
  * Returns HBJ_EINVAL for any other value.
  */
-enum { HBJ_ORTH_CGS2 = 0, HBJ_ORTH_DCGS2 = 1, HBJ_ORTH_SSTEP = 2 };
+enum { HBJ_ORTH_CGS2 = 0, HBJ_ORTH_DCGS2 = 1, HBJ_ORTH_SSTEP = 2, HBJ_ORTH_AUTO = 3 };
 int hbj_set_orthogonalization(hbj_ctx* ctx, int32_t mode);
 
 /*

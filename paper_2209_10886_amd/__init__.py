@@ -32,7 +32,7 @@ BJ_RESTRICTED, BJ_ADDITIVE = 0, 1
 BJ_PRODUCT, BJ_RESIDUAL = 0, 1
 OP_BANDED, OP_DENSE = 0, 1
 SWEEP_STEPPED, SWEEP_DATAFLOW = 0, 1
-ORTH_CGS2, ORTH_DCGS2, ORTH_SSTEP = 0, 1, 2  # Gram-Schmidt variant of the Arnoldi steps
+ORTH_CGS2, ORTH_DCGS2, ORTH_SSTEP, ORTH_AUTO = 0, 1, 2, 3  # Gram-Schmidt variant of the Arnoldi steps
 MSOLVE_CHAINS, MSOLVE_MFMA = 0, 1  # banded solves of many right-hand sides per subdomain
 OK, EINVAL, ESTATE, EHIP, ENOMEM, EWAIT, EIO, ZERO_PIVOT, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, -6, 1, 2
 # launch shapes of the banded solve batches (hbj_set_solve_tuning): one workgroup per solve at three
@@ -330,9 +330,10 @@ class Context:
         _check(_lib.hbj_set_graphs(self._h, 1 if on else 0))
 
     def set_orthogonalization(self, mode):
-        """ORTH_CGS2 (classical Gram-Schmidt twice), ORTH_DCGS2 (delayed reorthogonalisation,
-        default) or ORTH_SSTEP (s-step cycles: blocks of s steps orthogonalised together) for the
-        Arnoldi steps."""
+        """ORTH_CGS2 (classical Gram-Schmidt twice), ORTH_DCGS2 (delayed reorthogonalisation),
+        ORTH_SSTEP (s-step cycles: blocks of s steps orthogonalised together) or ORTH_AUTO (s-step
+        cycles for large blocks of Krylov vectors, delayed reorthogonalisation otherwise; default)
+        for the Arnoldi steps."""
         _check(_lib.hbj_set_orthogonalization(self._h, int(mode)))
 
     def set_sstep_block(self, s):

@@ -298,8 +298,8 @@ hipError_t launch_scale_reduce(double2* dst, const double2* src, const double* n
 constexpr int kSstepMax = 8;
 constexpr int kSstepMaxBasis = 64;
 constexpr int kSstepCoefLd = 129 + kSstepMaxBasis * kSstepMax;
-int bgs_positions_per_wave(int n, int ncol);
-int bgs_chunks(int n, int ncol);
+int bgs_positions_per_wg(int n, int ncol, int wgs);
+int bgs_chunks(int n, int ncol, int wgs);
 size_t bgs_partial_elems(int n, int ncol);
 hipError_t launch_bgs(double2* V, size_t vstride, int k1, int sb, int n, int ncol, double2* part, size_t part_elems,
                       double2* coef, int ldc, hipStream_t st);

@@ -155,6 +155,31 @@ def test_sstep_bad_values(hbj):
             ctx.set_sstep_block(bad)
         assert ei.value.code == hbj.EINVAL
     with pytest.raises(hbj.HbjError) as ei:
-        ctx.set_orthogonalization(3)
+        ctx.set_orthogonalization(4)
     assert ei.value.code == hbj.EINVAL
+    ctx.close()
+
+
+def test_auto_picks_sstep_for_large_blocks(hbj):
+    """The default (ORTH_AUTO) runs s-step cycles once the Krylov vectors of all right-hand sides
+    hold 2^20 entries (80 sources on the 512^2 grid of 8 x 8 subdomains: 80 x 14336), bit for bit
+    as ORTH_SSTEP, and the delayed form below that (8 sources), bit for bit as ORTH_DCGS2."""
+    wl = W.scaled(W.FP64_1024, 512)
+    m = W.slowness2(wl)
+    ctx = gpu_context(hbj, wl, m, operator_form=hbj.OP_DENSE, precond=2)
+    ctx.factor()
+    xs = np.linspace(0.1, 0.9, 80)
+    f = np.stack([W.gaussian_source(wl.nx, wl.ny, wl.h, x, 0.1) for x in xs])
+    assert ctx.nif * 80 >= 1 << 20 and ctx.nif * 8 < 1 << 20
+    for nrhs, explicit in ((80, hbj.ORTH_SSTEP), (8, hbj.ORTH_DCGS2)):
+        ft = torch.as_tensor(f[:nrhs], device="cuda")
+        runs = []
+        for mode in (hbj.ORTH_AUTO, explicit):
+            ctx.set_orthogonalization(mode)
+            say(f"[auto] nrhs={nrhs} mode={mode}")
+            u, st = ctx.solve(ft, tol=1e-8)
+            torch.cuda.synchronize()
+            runs.append((_np(u), st.iters, list(st.history)))
+        assert runs[0][1] == runs[1][1] and runs[0][2] == runs[1][2]
+        assert np.array_equal(runs[0][0], runs[1][0])
     ctx.close()
