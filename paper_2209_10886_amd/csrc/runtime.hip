@@ -1876,6 +1876,8 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
   // delayed reorthogonalisation: R (x_j = V R e_j), and c^(j), s_j, |w_j|^2 of the last step
   std::vector<zc> R(dcgs ? (size_t)ncol * m * m : 0), cprev(dcgs ? (size_t)ncol * (m + 1) : 0);
   std::vector<double> sprev(ncol), wwprev(ncol);
+  // s-step cycles: residual reduction per step of each column over its last block (none yet: empty)
+  std::vector<double> ss_rate;
   auto Rc = [&](int k, int i, int j) -> zc& { return R[((size_t)k * m + i) * m + j]; };
   while (true) {
     bool any = false;
@@ -1906,7 +1908,23 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
       const int kmax = std::min(m, o.maxit - total);
       const int ld = kSstepCoefLd;
       for (int k = 0; k < kmax;) {
-        const int sb = std::min(c->sstep_block, kmax - k);
+        // A block that would end past the step where every column is predicted to converge (at
+        // each column's residual reduction per step over its last block, one step of margin) is
+        // shortened: the steps after convergence would be unused.  The prediction changes only the
+        // block lengths, not the steps' iterates.
+        int want = c->sstep_block;
+        if (!ss_rate.empty()) {
+          int need = 0;
+          for (int q = 0; q < ncol && need < want; ++q) {
+            if (!active[q]) continue;
+            const double est = std::abs(e1[(size_t)q * (m + 1) + k]) / bnorm[q], rq = ss_rate[q];
+            if (!(rq > 0.0 && rq < 1.0) || !(est > o.tol)) { need = want; break; }
+            const double nd = std::ceil(std::log(o.tol / est) / std::log(rq)) + 1.0;
+            need = std::max(need, (int)std::min<double>(want, nd));
+          }
+          want = std::max(1, std::min(want, need));
+        }
+        const int sb = std::min(want, kmax - k);
         for (int i = 0; i < sb; ++i) {
           rc = pc_op(c, S, G.Vi(k + i), G.Zi(k + i), G.Vi(k + i + 1), ncol);
           if (rc) return rc;
@@ -1923,6 +1941,7 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
                                 hipMemcpyDeviceToHost, c->st));
         HIPCHK(hipStreamSynchronize(c->st));
         bool any_active = false;
+        if (ss_rate.empty()) ss_rate.assign(ncol, 0.0);
         for (int q = 0; q < ncol; ++q) {
           if (!active[q]) continue;
           const double2* cf = G.coef_host + (size_t)q * ld;
@@ -1938,7 +1957,9 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
           double* csk = &cs[(size_t)q * m];
           zc* snk = &sn[(size_t)q * m];
           zc* ek = &e1[(size_t)q * (m + 1)];
-          for (int i = 0; i < sb && active[q]; ++i) {
+          const double est0 = std::abs(ek[k]);
+          int done = 0;
+          for (int i = 0; i < sb && active[q]; ++i, ++done) {
             const int j = k + i;
             for (int r = 0; r <= j + 1; ++r) Hc(q, r, j) = ycoef(i, r) + ycoef(i + 1, r);
             const double hn = std::abs(Hc(q, j + 1, j));
@@ -1958,6 +1979,7 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
             if (q == 0) hist.push_back(est);
             if (est <= o.tol || hn == 0.0 || std::abs(Hc(q, j, j)) == 0.0) active[q] = 0;
           }
+          if (done > 0 && est0 > 0.0) ss_rate[q] = std::pow(std::abs(ek[k + done]) / est0, 1.0 / done);
           any_active |= active[q];
         }
         total += sb;
