@@ -146,6 +146,8 @@ struct SolveIO {
   int copy;
   // with nz: entries without a source write nothing at all (their field is rebuilt elsewhere)
   int nz_skip_out;
+  // dense operators on the matrix-product path only: dst = base - sub + sign * out (null = 0)
+  const double2* tr_sub;
 };
 
 // Local interface positions of a subdomain: faces W, E, S, N in this order, each with

@@ -142,6 +142,7 @@ __global__ __launch_bounds__(64 * KWT * NS) __attribute__((amdgpu_waves_per_eu(1
       const bool ok = p < TB * 4 && row >= 0 && rhs < nrhs && oo >= 0;
       opos[n] = ok ? (size_t)rhs * g.nif + oo + re : ~(size_t)0;
       obase[n] = io.tr_base ? io.tr_base[ok ? opos[n] : 0] : mk(0.0, 0.0);
+      if (io.tr_sub) obase[n] = csub(obase[n], io.tr_sub[ok ? opos[n] : 0]);
     }
   }
   V4 cr[TW], ci[TW];

@@ -88,6 +88,8 @@ struct Schedule {
   bool ov_ok = false;
   std::vector<size_t> ov_first;
   std::vector<int> ov_count;
+  // no step of either pass holds two neighbouring subdomains (a pass can then run in place)
+  bool steps_apart = false;
   // dataflow launches (dense form): task lists per kind, double-buffered completion counters
   struct DfPlan {
     bool built = false;
@@ -497,6 +499,25 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
       for (size_t q = st.first; q < ent.size(); ++q) st.dense_elems += dense_elems(ent[q]);
       S->bwd.push_back(st);
     }
+  }
+  {
+    std::vector<int> stamp(c->ndom, -1);
+    bool apart = true;
+    int id = 0;
+    for (auto* v : {&S->fwd, &S->bwd})
+      for (const Step& st : *v) {
+        for (int q = 0; q < st.sub_count; ++q) stamp[subs[st.sub_first + q]] = id;
+        for (int q = 0; q < st.sub_count && apart; ++q) {
+          const int sd = subs[st.sub_first + q];
+          const int i1 = sd % c->P.n1 + 1, i2 = sd / c->P.n1 + 1;
+          const MI nb[4] = {{i1 - 1, i2}, {i1 + 1, i2}, {i1, i2 - 1}, {i1, i2 + 1}};
+          for (const MI& m : nb)
+            if (m.i1 >= 1 && m.i1 <= c->P.n1 && m.i2 >= 1 && m.i2 <= c->P.n2 && stamp[sub_index(c, m)] == id)
+              apart = false;
+        }
+        ++id;
+      }
+    S->steps_apart = apart;
   }
   if (c->dense && nrhs < kMatrixRhs && !S->bwd.empty() && c->P.bj_combine == HBJ_BJ_RESTRICTED &&
       !(c->P.bj_compose == HBJ_BJ_RESIDUAL && c->fblocks.size() > 1))
@@ -1330,13 +1351,15 @@ int check_ready(hbj_ctx* c) {
 }
 
 // out = (I - S) g, FP64 local solves
-int op_fp64(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
+// sub (only where op_sub_ok): out = (I - S) g - sub
+int op_fp64(hbj_ctx* c, Schedule* S, const double2* g, double2* out, const double2* sub = nullptr) {
   SolveIO io{};
   io.g_a = g;
   io.tr_dst = out;
   io.tr_base = g;
   io.tr_sign = -1.0;
   io.tr_reflect = 1;
+  io.tr_sub = sub;
   if (c->dense && df_enabled(c, S)) {
     DfArgs A{};
     A.st[2] = df_stage(g, g, out, g, -1.0, 0xF, 0);
@@ -1418,7 +1441,7 @@ int run_pass(hbj_ctx* c, const Schedule* S, const std::vector<Step>& steps, cons
   return HBJ_OK;
 }
 
-int op_apply(hbj_ctx* c, Schedule* S, const double2* g, double2* out);
+int op_apply(hbj_ctx* c, Schedule* S, const double2* g, double2* out, const double2* sub = nullptr);
 
 // w: also apply the operator, w = (I - S) z, overlapped with the backward pass (the schedule
 // planned it; the caller checked op_overlap_ok)
@@ -1460,6 +1483,18 @@ int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs
     return HBJ_OK;
   }
   const bool cp = pass_copies(c, S);
+  // Both passes in place on z pre-filled with r (dense operators, the default readings, no two
+  // neighbouring subdomains in a step): a step writes each of its outgoing positions once, reading
+  // the old value there as the base of that write, and reads incoming positions that no step of
+  // the pass writes or that an earlier step wrote, as from a separate pass output pre-filled with
+  // the pass input.  One copy of the vector less per application.
+  if (!cp && c->dense && S->steps_apart && !w && c->P.bj_combine == HBJ_BJ_RESTRICTED &&
+      !(c->P.bj_compose == HBJ_BJ_RESIDUAL && c->fblocks.size() > 1)) {
+    HIPCHK(launch_copy(z, r, n, c->st));
+    rc = run_pass<R>(c, S, S->fwd, z, z, kMaskFwd);
+    if (rc) return rc;
+    return run_pass<R>(c, S, S->bwd, z, z, kMaskBwd);
+  }
   if (!cp) HIPCHK(launch_copy(y, r, n, c->st));
   rc = run_pass<R>(c, S, S->fwd, r, y, kMaskFwd);
   if (rc) return rc;
@@ -1501,9 +1536,16 @@ int precond(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs) {
 int op_mixed(hbj_ctx* c, Schedule* S, const double2* g, double2* out);
 
 namespace {
-int op_apply(hbj_ctx* c, Schedule* S, const double2* g, double2* out) {
+int op_apply(hbj_ctx* c, Schedule* S, const double2* g, double2* out, const double2* sub) {
+  if (sub) return op_fp64(c, S, g, out, sub);  // dense operators (op_sub_ok): complex128 in both precisions
   if (c->P.precision == HBJ_MIXED) return op_mixed(c, S, g, out);
   return op_fp64(c, S, g, out);
+}
+
+// Whether the operator can subtract a vector in its own epilogue: the dense operators applied on
+// the matrix-product path (many right-hand sides, stepped sweeps)
+bool op_sub_ok(const hbj_ctx* c, const Schedule* S) {
+  return c->dense && !df_enabled(c, S) && S->nrhs >= kMatrixRhs;
 }
 
 // The operator rows run beside the backward pass when the schedule planned it (dense operators,
@@ -1515,7 +1557,7 @@ bool op_overlap_ok(const hbj_ctx* c, const Schedule* S) {
 
 // z = P^{-1} v, w = (I - S) z: one dataflow launch for the FP64 dense form with the default
 // readings, the two calls otherwise (the operator overlapped with the backward pass where it can)
-int pc_op(hbj_ctx* c, Schedule* S, const double2* v, double2* z, double2* w, int nrhs) {
+int pc_op(hbj_ctx* c, Schedule* S, const double2* v, double2* z, double2* w, int nrhs, const double2* sub = nullptr) {
   const bool fused = df_enabled(c, S) && c->P.precision == HBJ_FP64 && c->P.precond != HBJ_PC_NONE &&
                      c->ndom > 1 && c->P.bj_combine == HBJ_BJ_RESTRICTED &&
                      !(c->P.bj_compose == HBJ_BJ_RESIDUAL && c->fblocks.size() > 1);
@@ -1526,7 +1568,7 @@ int pc_op(hbj_ctx* c, Schedule* S, const double2* v, double2* z, double2* w, int
     }
     int rc = precond(c, S, v, z, nrhs);
     if (rc) return rc;
-    return op_apply(c, S, z, w);
+    return op_apply(c, S, z, w, sub);
   }
   int rc = ensure_pc(c, nrhs);
   if (rc) return rc;
@@ -1925,9 +1967,12 @@ static int gmres_solve(hbj_ctx* c, Schedule* S, Gmres& G, const hbj_solve_opts& 
           want = std::max(1, std::min(want, need));
         }
         const int sb = std::min(want, kmax - k);
+        // the shift (- y_i) in the operator's epilogue where it can take it, else one more launch
+        const bool fold = op_sub_ok(c, S);
         for (int i = 0; i < sb; ++i) {
-          rc = pc_op(c, S, G.Vi(k + i), G.Zi(k + i), G.Vi(k + i + 1), ncol);
+          rc = pc_op(c, S, G.Vi(k + i), G.Zi(k + i), G.Vi(k + i + 1), ncol, fold ? G.Vi(k + i) : nullptr);
           if (rc) return rc;
+          if (fold) continue;
           ProfScope ps(c, HBJ_K_KRYLOV, 3.0 * vs * 16.0, 8.0 * vs);
           HIPCHK(launch_axpby(G.Vi(k + i + 1), G.Vi(k + i), mk(-1.0, 0.0), mk(1.0, 0.0), vs, c->st));
         }
