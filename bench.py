@@ -511,6 +511,8 @@ def multi_source_leg(hbj, steps=2, warmup=1):
                               "TFLOP/s": mm["flops"] / max(1e-12, mm["ms"] * 1e-3) / 1e12,
                               "frac_of_f32_mfma_peak": mm["flops"] / max(1e-12, mm["ms"] * 1e-3) / 1e12
                               / MFMA_PEAK_TFLOPS["f32"]},
+        "orthogonalization": ({None: "default: s-step cycles (blocks of 8 steps) at this size", 0: "cgs2", 1: "dcgs2",
+                               2: "s-step", 3: "auto"}[ORTH] + (f", blocks of {SSTEP_BLOCK}" if SSTEP_BLOCK else "")),
         "gram_schmidt": {"ms_per_iteration": kr["ms"] / max(1, st.iters),
                          "GB/s": kr["bytes"] / max(1e-12, kr["ms"] * 1e-3) / 1e9,
                          "frac_of_hbm_peak": kr["bytes"] / max(1e-12, kr["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS},
