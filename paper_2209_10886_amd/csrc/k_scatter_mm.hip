@@ -20,25 +20,46 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 // With coef, every datum is scaled by inj of its position: the incoming data in the form the
 // lifting matrices W_s take for the reconstruction (x_col = W_s[.][col] inj_col).  GT: complex128,
 // or complex64 for the products on f32 MFMA (which round every operand to float anyway).
+// A transpose through LDS: workgroup (chunk, j, rb) reads kGP consecutive positions of 64 columns
+// (right-hand sides) with the positions fastest (a face's positions are consecutive in gin) and
+// writes them with the columns fastest (a row of G), so that both sides are contiguous runs.
+// Columns past nrhs, and positions on faces without a neighbour, are zeros.
+constexpr int kGP = 32;  // positions per gather workgroup
 template <typename GT>
-__global__ void k_gather_incoming(Geom g, const int32_t* subs, const FaceTab* ft, const double2* gin, int nrhs,
-                                  int rpad, GT* G, const IfCoef* coef) {
+__global__ __launch_bounds__(256) void k_gather_incoming(Geom g, const int32_t* subs, const FaceTab* ft,
+                                                         const double2* gin, int nrhs, int rpad, GT* G,
+                                                         const IfCoef* coef) {
   const int j = blockIdx.y;
   const int s = subs ? subs[j] : j;
   const FaceTab F = ft[s];
   const int L = local_if_len(g);
-  const size_t n = (size_t)L * rpad;
-  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-    const int col = (int)(t / rpad), r = (int)(t % rpad);
-    int f, ee;
-    local_if_face(g, col, &f, &ee);
-    const int io = pick4(F.in_off, f);
+  const int c0 = blockIdx.x * kGP, r0 = blockIdx.z * 64;
+  __shared__ GT tile[kGP][65];
+#pragma unroll
+  for (int k = 0; k < kGP * 64 / 256; ++k) {
+    const int idx = threadIdx.x + 256 * k;
+    const int c = idx % kGP, r = idx / kGP;
+    const int col = c0 + c, rr = r0 + r;
     double2 v = mk(0.0, 0.0);
-    if (r < nrhs && io >= 0) {
-      v = gin[(size_t)r * g.nif + io + ee];
-      if (coef) v = cmul(coef[io + ee].inj, v);
+    if (col < L && rr < nrhs) {
+      int f, ee;
+      local_if_face(g, col, &f, &ee);
+      const int io = pick4(F.in_off, f);
+      if (io >= 0) {
+        v = gin[(size_t)rr * g.nif + io + ee];
+        if (coef) v = cmul(coef[io + ee].inj, v);
+      }
     }
-    G[(size_t)j * n + t] = to_c<GT>(v);
+    tile[c][r] = to_c<GT>(v);
+  }
+  __syncthreads();
+  const size_t n = (size_t)L * rpad;
+#pragma unroll
+  for (int k = 0; k < kGP * 64 / 256; ++k) {
+    const int idx = threadIdx.x + 256 * k;
+    const int c = idx / 64, r = idx % 64;
+    const int col = c0 + c, rr = r0 + r;
+    if (col < L && rr < rpad) G[(size_t)j * n + (size_t)col * rpad + rr] = tile[c][r];
   }
 }
 
@@ -349,9 +370,8 @@ hipError_t launch_recon_mm(const Geom& g, const IfCoef* coef, const FaceTab* ft,
                            const int32_t* nz, int nrhs, double2* Gbuf, double2* u, hipStream_t st) {
   const int rpad = (nrhs + 15) / 16 * 16;
   const int ndom = g.n1 * g.n2;
-  const size_t n = (size_t)local_if_len(g) * rpad;
-  const int bx = (int)std::min<size_t>(64, (n + 255) / 256);
-  hipLaunchKernelGGL(k_gather_incoming<double2>, dim3(bx, ndom), dim3(256), 0, st, g, (const int32_t*)nullptr, ft, gin, nrhs,
+  const dim3 gg((local_if_len(g) + kGP - 1) / kGP, ndom, (rpad + 63) / 64);
+  hipLaunchKernelGGL(k_gather_incoming<double2>, gg, dim3(256), 0, st, g, (const int32_t*)nullptr, ft, gin, nrhs,
                      rpad, Gbuf, coef);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -364,9 +384,8 @@ template <typename GT>
 hipError_t launch_gather_incoming(const Geom& g, const int32_t* subs, int nsub, const FaceTab* ft, const double2* gin,
                                   int nrhs, int rpad, GT* G, hipStream_t st) {
   if (nsub == 0) return hipSuccess;
-  const size_t n = (size_t)local_if_len(g) * rpad;
-  const int bx = (int)std::min<size_t>(64, (n + 255) / 256);
-  hipLaunchKernelGGL(k_gather_incoming<GT>, dim3(bx, nsub), dim3(256), 0, st, g, subs, ft, gin, nrhs, rpad, G,
+  const dim3 gg((local_if_len(g) + kGP - 1) / kGP, nsub, (rpad + 63) / 64);
+  hipLaunchKernelGGL(k_gather_incoming<GT>, gg, dim3(256), 0, st, g, subs, ft, gin, nrhs, rpad, G,
                      (const IfCoef*)nullptr);
   return hipGetLastError();
 }
