@@ -393,6 +393,17 @@ enum { HBJ_ORTH_CGS2 = 0, HBJ_ORTH_DCGS2 = 1, HBJ_ORTH_SSTEP = 2, HBJ_ORTH_AUTO 
 int hbj_set_orthogonalization(hbj_ctx* ctx, int32_t mode);
 
 /*
+ * hbj_set_step_chaining - with 4 or more right-hand sides, the dense operators and the default
+ * readings, each sweep step on the matrix-product path passes its outputs on to the tile of
+ * gathered incoming data of the next step (Sec. 6: the data a step sends is what the next step
+ * receives), and the other positions of every step's tile are gathered once at the start of the
+ * pass, instead of one gather launch per step.  Used while the autotuner's variant for the sweep
+ * steps reads gathered tiles.  The same results bit for bit.  on: 1 (default) or 0.  Returns
+ * HBJ_EINVAL for any other value.
+ */
+int hbj_set_step_chaining(hbj_ctx* ctx, int32_t on);
+
+/*
  * hbj_set_sstep_block - steps per block of the HBJ_ORTH_SSTEP cycles, 1..8 (default 8; the
  * last block of a restart cycle may be shorter).  Returns HBJ_EINVAL outside 1..8.
  */

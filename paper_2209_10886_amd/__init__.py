@@ -109,6 +109,7 @@ _SIGS = {
     "hbj_set_graphs": (_I, [_P, _I32]),
     "hbj_set_orthogonalization": (_I, [_P, _I32]),
     "hbj_set_sstep_block": (_I, [_P, _I32]),
+    "hbj_set_step_chaining": (_I, [_P, _I32]),
     "hbj_set_multi_solve": (_I, [_P, _I32]),
     "hbj_strerror": (ctypes.c_char_p, [_I]),
     "hbj_last_error": (ctypes.c_char_p, []),
@@ -335,6 +336,11 @@ class Context:
         cycles for large blocks of Krylov vectors, delayed reorthogonalisation otherwise; default)
         for the Arnoldi steps."""
         _check(_lib.hbj_set_orthogonalization(self._h, int(mode)))
+
+    def set_step_chaining(self, on=True):
+        """Chained sweep steps on the many-right-hand-side path (default on): each step writes the
+        next step's gathered tile; the same results bit for bit."""
+        _check(_lib.hbj_set_step_chaining(self._h, 1 if on else 0))
 
     def set_sstep_block(self, s):
         """Steps per block of the ORTH_SSTEP cycles (1..8, default 8)."""

@@ -148,6 +148,12 @@ struct SolveIO {
   int nz_skip_out;
   // dense operators on the matrix-product path only: dst = base - sub + sign * out (null = 0)
   const double2* tr_sub;
+  // sweep steps on the matrix-product path, chained: the output at interface position p is also
+  // stored, in the element type of the products, at ctile[cmap[p] * crpad + rhs] when cmap[p] >= 0
+  // (the gathered tile of the next step)
+  const int32_t* cmap;
+  void* ctile;
+  int crpad;
 };
 
 // Local interface positions of a subdomain: faces W, E, S, N in this order, each with
@@ -371,6 +377,10 @@ hipError_t launch_recon_dense(const Geom& g, const FaceTab* ft, const IfCoef* co
 template <typename GT>
 hipError_t launch_gather_incoming(const Geom& g, const int32_t* subs, int nsub, const FaceTab* ft, const double2* gin,
                                   int nrhs, int rpad, GT* G, hipStream_t st);
+// tiles[dst[q] + r] = gin[r][pos[q]] for r < nrhs (zeros up to rpad): the gathered tiles of a pass
+template <typename GT>
+hipError_t launch_pregather(const int64_t* dst, const int32_t* pos, int njobs, const double2* gin, int nif, int nrhs,
+                            int rpad, GT* tiles, hipStream_t st);
 template <typename C>
 hipError_t launch_scatter_mm(const Geom& g, const int32_t* subs, int nsub, int mask, const FaceTab* ft, const C* T,
                              const double2* gin, const C* G, int nrhs, int rpad, const SolveIO& io, hipStream_t st,

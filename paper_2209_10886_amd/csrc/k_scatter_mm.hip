@@ -63,6 +63,34 @@ __global__ __launch_bounds__(256) void k_gather_incoming(Geom g, const int32_t* 
   }
 }
 
+// Gathered tiles of a whole preconditioner pass at its start: job q copies interface position
+// pos[q] of the 64 columns [r0, r0 + 64) to tile entries dst[q] + r (element type GT), the same
+// LDS transpose as k_gather_incoming (the jobs of one face are consecutive positions).
+template <typename GT>
+__global__ __launch_bounds__(256) void k_pregather(const int64_t* __restrict__ dst, const int32_t* __restrict__ pos,
+                                                   int njobs, const double2* gin, int nif, int nrhs, int rpad,
+                                                   GT* tiles) {
+  const int q0 = blockIdx.x * kGP, r0 = blockIdx.y * 64;
+  __shared__ GT tile[kGP][65];
+#pragma unroll
+  for (int k = 0; k < kGP * 64 / 256; ++k) {
+    const int idx = threadIdx.x + 256 * k;
+    const int c = idx % kGP, r = idx / kGP;
+    const int q = q0 + c, rr = r0 + r;
+    double2 v = mk(0.0, 0.0);
+    if (q < njobs && rr < nrhs) v = gin[(size_t)rr * nif + pos[q]];
+    tile[c][r] = to_c<GT>(v);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kGP * 64 / 256; ++k) {
+    const int idx = threadIdx.x + 256 * k;
+    const int c = idx / 64, r = idx % 64;
+    const int q = q0 + c, rr = r0 + r;
+    if (q < njobs && rr < rpad) tiles[dst[q] + rr] = tile[c][r];
+  }
+}
+
 __device__ inline int masked_row_mm(const Geom& g, int mask, int r) {
   for (int f = 0; f < 4; ++f) {
     if (!((mask >> f) & 1)) continue;
@@ -150,6 +178,7 @@ __global__ __launch_bounds__(64 * KWT * NS) __attribute__((amdgpu_waves_per_eu(1
   constexpr int NP = (TB * 4 + KWT - 1) / KWT;
   size_t opos[NP];
   double2 obase[NP];
+  int oslot[NP];  // chained steps: the output's slot in the next step's tile (-1: none)
   if (grp == 0) {
 #pragma unroll
     for (int n = 0; n < NP; ++n) {
@@ -164,6 +193,7 @@ __global__ __launch_bounds__(64 * KWT * NS) __attribute__((amdgpu_waves_per_eu(1
       opos[n] = ok ? (size_t)rhs * g.nif + oo + re : ~(size_t)0;
       obase[n] = io.tr_base ? io.tr_base[ok ? opos[n] : 0] : mk(0.0, 0.0);
       if (io.tr_sub) obase[n] = csub(obase[n], io.tr_sub[ok ? opos[n] : 0]);
+      oslot[n] = (io.cmap && ok) ? io.cmap[oo + re] : -1;
     }
   }
   V4 cr[TW], ci[TW];
@@ -291,6 +321,8 @@ __global__ __launch_bounds__(64 * KWT * NS) __attribute__((amdgpu_waves_per_eu(1
     base.x += io.tr_sign * sr;
     base.y += io.tr_sign * si;
     io.tr_dst[opos[n]] = base;
+    if (oslot[n] >= 0)
+      ((C*)io.ctile)[(size_t)oslot[n] * io.crpad + rb0 + 16 * (p >> 2) + (lane & 15)] = to_c<C>(base);
   }
 }
 
@@ -391,6 +423,19 @@ hipError_t launch_gather_incoming(const Geom& g, const int32_t* subs, int nsub, 
 }
 template hipError_t launch_gather_incoming<double2>(const Geom&, const int32_t*, int, const FaceTab*, const double2*,
                                                     int, int, double2*, hipStream_t);
+
+template <typename GT>
+hipError_t launch_pregather(const int64_t* dst, const int32_t* pos, int njobs, const double2* gin, int nif, int nrhs,
+                            int rpad, GT* tiles, hipStream_t st) {
+  if (njobs == 0) return hipSuccess;
+  const dim3 gg((njobs + kGP - 1) / kGP, (rpad + 63) / 64);
+  hipLaunchKernelGGL(k_pregather<GT>, gg, dim3(256), 0, st, dst, pos, njobs, gin, nif, nrhs, rpad, tiles);
+  return hipGetLastError();
+}
+template hipError_t launch_pregather<double2>(const int64_t*, const int32_t*, int, const double2*, int, int, int,
+                                              double2*, hipStream_t);
+template hipError_t launch_pregather<float2>(const int64_t*, const int32_t*, int, const double2*, int, int, int,
+                                             float2*, hipStream_t);
 template hipError_t launch_gather_incoming<float2>(const Geom&, const int32_t*, int, const FaceTab*, const double2*,
                                                    int, int, float2*, hipStream_t);
 

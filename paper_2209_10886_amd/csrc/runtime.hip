@@ -90,6 +90,20 @@ struct Schedule {
   std::vector<int> ov_count;
   // no step of either pass holds two neighbouring subdomains (a pass can then run in place)
   bool steps_apart = false;
+  std::vector<int32_t> subs_host;  // host copy of subs
+  // chained sweep steps (matrix-product path, passes in place): per pass, the gathered tile of
+  // every step in one buffer (tile_off), filled at the pass start for the positions the previous
+  // step does not write (jobs: destination entry, position) and by the previous step's outputs
+  // for the others (cmap: per step, position -> slot in the next step's tile, -1 if none)
+  struct Chain {
+    bool built = false, ok = false;
+    std::vector<size_t> tile_off;  // elements of the tile buffer, one entry per step and the end
+    int32_t* cmap = nullptr;       // [steps][nif]
+    int64_t* jdst = nullptr;
+    int32_t* jpos = nullptr;
+    int njobs = 0;
+  };
+  Chain chain[2];  // forward, backward
   // dataflow launches (dense form): task lists per kind, double-buffered completion counters
   struct DfPlan {
     bool built = false;
@@ -156,6 +170,7 @@ struct hbj_ctx {
   hipStream_t opst = nullptr;  // operator rows overlapped with the backward pass
   std::vector<hipEvent_t> ov_ev;  // one per backward step, and the join
   bool op_overlap = false;        // measured slower: each stream-to-stream wait costs ~19 us here
+  bool chain_ok = true;           // chained sweep steps where they apply (hbj_set_step_chaining)
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   void* ybuf_side = nullptr;
   size_t ybuf_side_bytes = 0;
@@ -186,6 +201,8 @@ struct hbj_ctx {
   size_t loc64_entries = 0;
   double2* Gbuf = nullptr;  // gathered incoming data for the many-right-hand-side operators
   size_t Gbuf_cap = 0;
+  void* chain_buf = nullptr;  // gathered tiles of a chained preconditioner pass
+  size_t chain_cap = 0;       // bytes
   // autotuned tile depth of the many-right-hand-side operator kernel, per (precision, stage kind):
   // [complex128 steps, complex128 operator, complex64 steps, complex64 operator]; -1 = not tuned
   int mm_variant[4] = {-1, -1, -1, -1};
@@ -259,7 +276,13 @@ hbj_ctx::~hbj_ctx() {
     dfree(kv.second->tiles);
     for (auto& pl : kv.second->df) dfree(pl.dev);
     dfree(kv.second->df_ctr);
+    for (auto& ch : kv.second->chain) {
+      dfree(ch.cmap);
+      dfree(ch.jdst);
+      dfree(ch.jpos);
+    }
   }
+  dfree(chain_buf);
   dfree(rbl);
   dfree(df_err);
   dfree(vr_part);
@@ -519,6 +542,7 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
       }
     S->steps_apart = apart;
   }
+  S->subs_host = subs;
   if (c->dense && nrhs < kMatrixRhs && !S->bwd.empty() && c->P.bj_combine == HBJ_BJ_RESTRICTED &&
       !(c->P.bj_compose == HBJ_BJ_RESIDUAL && c->fblocks.size() > 1))
     plan_operator_overlap(c, *S, ent);
@@ -840,7 +864,8 @@ int run_solves_side(hbj_ctx* c, const Entry* ent, int nent, const SolveIO& io) {
 
 int run_dense(hbj_ctx* c, const Entry* ent, const FaceTab* eft, int nent, int mask, const SolveIO& io, bool c64,
               double elems,
-              const int32_t* subs = nullptr, int nsub = 0, int nrhs = 1, int src = 0, const StepArgs* sa = nullptr) {
+              const int32_t* subs = nullptr, int nsub = 0, int nrhs = 1, int src = 0, const StepArgs* sa = nullptr,
+              const void* Gpre = nullptr) {
   if (nent == 0) return HBJ_OK;
   if (subs && nrhs >= kMatrixRhs) {
     const int rpad = (nrhs + 15) / 16 * 16;
@@ -859,17 +884,19 @@ int run_dense(hbj_ctx* c, const Entry* ent, const FaceTab* eft, int nent, int ma
     // variants 0-2 and 6-8 gather the incoming data into tiles first (in complex64 for the
     // complex64 products, which round every operand to float anyway); the others read them from
     // gin directly
+    // (Gpre: the tiles are already gathered, by a chained pass)
     auto launch = [&](int v, const SolveIO& lio) -> hipError_t {
-      if (mm_variant_gathered(v)) {
+      if (mm_variant_gathered(v) && !Gpre) {
         const hipError_t e =
             c64 ? launch_gather_incoming(c->g, subs, nsub, c->ft, gin, nrhs, rpad, (float2*)c->Gbuf, c->st)
                 : launch_gather_incoming(c->g, subs, nsub, c->ft, gin, nrhs, rpad, c->Gbuf, c->st);
         if (e != hipSuccess) return e;
       }
-      return c64 ? launch_scatter_mm<float2>(c->g, subs, nsub, mask, c->ft, c->T32, gin, (const float2*)c->Gbuf,
-                                             nrhs, rpad, lio, c->st, v)
-                 : launch_scatter_mm<double2>(c->g, subs, nsub, mask, c->ft, c->T64, gin, c->Gbuf, nrhs, rpad, lio,
-                                              c->st, v);
+      const void* G = Gpre ? Gpre : (const void*)c->Gbuf;
+      return c64 ? launch_scatter_mm<float2>(c->g, subs, nsub, mask, c->ft, c->T32, gin, (const float2*)G, nrhs,
+                                             rpad, lio, c->st, v)
+                 : launch_scatter_mm<double2>(c->g, subs, nsub, mask, c->ft, c->T64, gin, (const double2*)G, nrhs,
+                                              rpad, lio, c->st, v);
     };
     // cache key of this launch kind: device, precision, operator or steps, checkerboard, subdomain,
     // padded right-hand sides (by powers of two)
@@ -899,6 +926,7 @@ int run_dense(hbj_ctx* c, const Entry* ent, const FaceTab* eft, int nent, int ma
       SolveIO tio = io;
       tio.tr_dst = scratch;
       tio.tr_base = nullptr;
+      tio.cmap = nullptr;  // the next tile is written by the launch proper
       // the variants take turns (three rounds after a warm-up round), so that each one is timed after
       // another has streamed its data, as in a solve, rather than on caches it has just filled itself
       // (the warm-up round is timed too: a variant at more than twice the best time there drops out)
@@ -1392,10 +1420,16 @@ int op_chunk(hbj_ctx* c, const Schedule* S, int k, const double2* z, double2* w)
 // context stream after the pass, which then waits for the operator stream
 template <typename R>
 int run_pass(hbj_ctx* c, const Schedule* S, const std::vector<Step>& steps, const double2* in, double2* out,
-             int mask, double2* opw = nullptr) {
+             int mask, double2* opw = nullptr, int chain_pass = -1) {
   Entry* dev = S->dev;
   const bool cp = pass_copies(c, S);
   const int nk = (int)steps.size();
+  typedef typename Cplx<R>::T C;
+  const Schedule::Chain* ch = chain_pass >= 0 ? &S->chain[chain_pass] : nullptr;
+  if (ch) {  // the gathered tiles of every step, for the positions the previous step does not write
+    const int rpad = (S->nrhs + 15) / 16 * 16;
+    HIPCHK(launch_pregather<C>(ch->jdst, ch->jpos, ch->njobs, in, c->g.nif, S->nrhs, rpad, (C*)c->chain_buf, c->st));
+  }
   if (opw) {
     if (!c->opst) HIPCHK(hipStreamCreateWithFlags(&c->opst, hipStreamNonBlocking));
     while ((int)c->ov_ev.size() < nk + 1) {
@@ -1415,9 +1449,19 @@ int run_pass(hbj_ctx* c, const Schedule* S, const std::vector<Step>& steps, cons
     io.copy = cp ? 1 : 0;
     io.tr_sign = 1.0;
     io.tr_reflect = 1;
+    const void* Gpre = nullptr;
+    if (ch) {
+      C* tiles = (C*)c->chain_buf;
+      Gpre = tiles + ch->tile_off[si];
+      if ((int)si + 1 < nk) {
+        io.cmap = ch->cmap + si * (size_t)c->g.nif;
+        io.ctile = tiles + ch->tile_off[si + 1];
+        io.crpad = (S->nrhs + 15) / 16 * 16;
+      }
+    }
     int rc = c->dense ? run_dense(c, dev + s.first, S->eft + s.first, s.count, mask, io, sizeof(R) == 4, s.dense_elems,
                                   S->subs + s.sub_first, s.sub_count, S->nrhs, si == 0 ? 0 : 1,
-                                  s.sarg >= 0 ? &S->sargs[s.sarg] : nullptr)
+                                  s.sarg >= 0 ? &S->sargs[s.sarg] : nullptr, Gpre)
                       : run_solves<R>(c, dev + s.first, s.count, io, S->tiles + s.tile_first, s.tile_count);
     if (rc) return rc;
     if (opw && (int)si + 1 < nk && S->ov_count[si] > 0) {
@@ -1445,6 +1489,77 @@ int op_apply(hbj_ctx* c, Schedule* S, const double2* g, double2* out, const doub
 
 // w: also apply the operator, w = (I - S) z, overlapped with the backward pass (the schedule
 // planned it; the caller checked op_overlap_ok)
+// Chained sweep steps (Schedule::Chain) for pass 0 (forward) or 1 (backward).  A position that step t
+// reads is written by step t - 1 (its output then goes straight into step t's tile) or by no step
+// up to t (the value at the pass start holds: it is gathered then); a schedule where some position
+// read by step t was written by an earlier step, or twice, stays unchained.  Needs the passes in
+// place (the pass input is the output) and the many-right-hand-side steps.
+int build_chain(hbj_ctx* c, Schedule* S, int pass) {
+  Schedule::Chain& ch = S->chain[pass];
+  if (ch.built) return HBJ_OK;
+  ch.built = true;
+  const std::vector<Step>& steps = pass == 0 ? S->fwd : S->bwd;
+  const int mask = pass == 0 ? kMaskFwd : kMaskBwd;
+  const Geom& g = c->g;
+  const int nk = (int)steps.size(), nif = g.nif, L = local_if_len(g);
+  const int rpad = (S->nrhs + 15) / 16 * 16;
+  if (nk == 0) return HBJ_OK;
+  std::vector<int> wstep(nif, -1);  // the step of the pass writing each position
+  for (int t = 0; t < nk; ++t) {
+    const Step& st = steps[t];
+    for (int q = 0; q < st.sub_count; ++q) {
+      const FaceTab& F = c->ft_host[S->subs_host[st.sub_first + q]];
+      for (int f = 0; f < 4; ++f) {
+        if (!((mask >> f) & 1) || F.out_off[f] < 0) continue;
+        for (int e = 0; e < face_len(g, f); ++e) {
+          int& w = wstep[F.out_off[f] + e];
+          if (w >= 0) return HBJ_OK;
+          w = t;
+        }
+      }
+    }
+  }
+  std::vector<size_t> off(nk + 1, 0);
+  for (int t = 0; t < nk; ++t) off[t + 1] = off[t] + (size_t)steps[t].sub_count * L * rpad;
+  std::vector<int32_t> cmap((size_t)nk * nif, -1);
+  std::vector<int64_t> jdst;
+  std::vector<int32_t> jpos;
+  for (int t = 0; t < nk; ++t) {
+    const Step& st = steps[t];
+    for (int j = 0; j < st.sub_count; ++j) {
+      const FaceTab& F = c->ft_host[S->subs_host[st.sub_first + j]];
+      for (int f = 0; f < 4; ++f) {
+        if (F.in_off[f] < 0) continue;
+        for (int e = 0; e < face_len(g, f); ++e) {
+          const int p = F.in_off[f] + e, w = wstep[p];
+          const int slot = j * L + face_off(g, f) + e;
+          if (t > 0 && w == t - 1) {
+            cmap[(size_t)(t - 1) * nif + p] = slot;
+          } else if (w < 0 || w > t) {
+            jdst.push_back((int64_t)off[t] + (int64_t)slot * rpad);
+            jpos.push_back(p);
+          } else {
+            return HBJ_OK;
+          }
+        }
+      }
+    }
+  }
+  HIPCHK(dalloc(&ch.cmap, cmap.size()));
+  HIPCHK(hipMemcpyAsync(ch.cmap, cmap.data(), cmap.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  ch.njobs = (int)jpos.size();
+  if (ch.njobs > 0) {
+    HIPCHK(dalloc(&ch.jdst, jdst.size()));
+    HIPCHK(dalloc(&ch.jpos, jpos.size()));
+    HIPCHK(hipMemcpyAsync(ch.jdst, jdst.data(), jdst.size() * sizeof(int64_t), hipMemcpyHostToDevice, c->st));
+    HIPCHK(hipMemcpyAsync(ch.jpos, jpos.data(), jpos.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->st));
+  }
+  HIPCHK(hipStreamSynchronize(c->st));  // the host tables go out of scope
+  ch.tile_off = off;
+  ch.ok = true;
+  return HBJ_OK;
+}
+
 template <typename R>
 int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs, double2* w = nullptr) {
   const size_t n = (size_t)nrhs * c->g.nif;
@@ -1491,9 +1606,32 @@ int precond_impl(hbj_ctx* c, Schedule* S, const double2* r, double2* z, int nrhs
   if (!cp && c->dense && S->steps_apart && !w && c->P.bj_combine == HBJ_BJ_RESTRICTED &&
       !(c->P.bj_compose == HBJ_BJ_RESIDUAL && c->fblocks.size() > 1)) {
     HIPCHK(launch_copy(z, r, n, c->st));
-    rc = run_pass<R>(c, S, S->fwd, z, z, kMaskFwd);
+    // many right-hand sides with tiles of gathered incoming data (or no variant chosen yet): the
+    // steps pass their outputs on to the next step's tile instead of a gather launch per step
+    bool chain = false;
+    if (S->nrhs >= kMatrixRhs && c->chain_ok) {
+      const int v = c->mm_variant[sizeof(R) == 4 ? 2 : 0];
+      if (v < 0 || mm_variant_gathered(v)) {
+        rc = build_chain(c, S, 0);
+        if (!rc) rc = build_chain(c, S, 1);
+        if (rc) return rc;
+        chain = S->chain[0].ok && S->chain[1].ok;
+        if (chain) {
+          typedef typename Cplx<R>::T C;
+          const size_t need = std::max(S->chain[0].tile_off.back(), S->chain[1].tile_off.back()) * sizeof(C);
+          if (need > c->chain_cap) {
+            dfree(c->chain_buf);
+            c->chain_buf = nullptr;
+            c->chain_cap = 0;
+            if (hipMalloc(&c->chain_buf, need) != hipSuccess) return fail(HBJ_ENOMEM, "tile buffer allocation failed");
+            c->chain_cap = need;
+          }
+        }
+      }
+    }
+    rc = run_pass<R>(c, S, S->fwd, z, z, kMaskFwd, nullptr, chain ? 0 : -1);
     if (rc) return rc;
-    return run_pass<R>(c, S, S->bwd, z, z, kMaskBwd);
+    return run_pass<R>(c, S, S->bwd, z, z, kMaskBwd, nullptr, chain ? 1 : -1);
   }
   if (!cp) HIPCHK(launch_copy(y, r, n, c->st));
   rc = run_pass<R>(c, S, S->fwd, r, y, kMaskFwd);
@@ -2972,6 +3110,13 @@ int hbj_set_orthogonalization(hbj_ctx* c, int32_t mode) {
     return fail(HBJ_EINVAL, "unknown orthogonalisation");
   if (mode != c->orth) ++c->graph_epoch;  // the captured steps hold the other kernels
   c->orth = mode;
+  return HBJ_OK;
+}
+
+int hbj_set_step_chaining(hbj_ctx* c, int32_t on) {
+  if (!c) return fail(HBJ_EINVAL, "null context");
+  if (on != 0 && on != 1) return fail(HBJ_EINVAL, "step chaining must be 0 or 1");
+  c->chain_ok = on != 0;
   return HBJ_OK;
 }
 
