@@ -1,7 +1,8 @@
 // Dense local scattering operators applied to many right-hand sides at once:
 //   OUT_s (rows x R) = T_s[rows, :] (L x L, masked rows) * G_s (L x R)
 // a complex matrix product per subdomain, on MFMA.  Complex products use four real
-// products per k-step: Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br.
+// products per k-step, Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br, on f32 MFMA, and three (Gauss's
+// product) on f64 MFMA, whose rate bounds the complex128 launches.
 //
 // Operand layouts of the 16x16x4 MFMA on gfx950 (lane l, k = l / 16):
 //   A[i][k] at lane i + 16 k, B[k][j] at lane j + 16 k;
@@ -196,11 +197,16 @@ __global__ __launch_bounds__(64 * KWT * NS) __attribute__((amdgpu_waves_per_eu(1
       oslot[n] = (io.cmap && ok) ? io.cmap[oo + re] : -1;
     }
   }
-  V4 cr[TW], ci[TW];
+  // complex products: four real MFMAs per k-step (Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br), or with
+  // f64 MFMA (which bounds the complex128 operator launches) three: cr += Ar Br, ci += Ai Bi,
+  // c3 += (Ar + Ai)(Br + Bi), then Re = cr - ci and Im = c3 - cr - ci (Gauss's product)
+  constexpr bool K3 = sizeof(M) == 8;
+  V4 cr[TW], ci[TW], c3[TW];
 #pragma unroll
   for (int t = 0; t < TW; ++t) {
     cr[t] = V4{0, 0, 0, 0};
     ci[t] = V4{0, 0, 0, 0};
+    c3[t] = V4{0, 0, 0, 0};
   }
   const int present[4] = {F.in_off[0] >= 0, F.in_off[1] >= 0, F.in_off[2] >= 0, F.in_off[3] >= 0};
   if constexpr (RING > 0) {
@@ -236,17 +242,28 @@ __global__ __launch_bounds__(64 * KWT * NS) __attribute__((amdgpu_waves_per_eu(1
     auto consume = [&](int d) {
       const bool ok = live[d] && mrow >= 0;
       const M ar = ok ? (M)tv[d].x : (M)0, ai = ok ? (M)tv[d].y : (M)0;
+      if constexpr (K3) {
+        const M as = ar + ai;
 #pragma unroll
-      for (int t = 0; t < TW; ++t) {
-        const M br = (M)gv[d][t].x, bi = (M)gv[d][t].y;
-        cr[t] = A::mma(ar, br, cr[t]);
-        ci[t] = A::mma(ar, bi, ci[t]);
-      }
+        for (int t = 0; t < TW; ++t) {
+          const M br = (M)gv[d][t].x, bi = (M)gv[d][t].y;
+          cr[t] = A::mma(ar, br, cr[t]);
+          ci[t] = A::mma(ai, bi, ci[t]);
+          c3[t] = A::mma(as, br + bi, c3[t]);
+        }
+      } else {
 #pragma unroll
-      for (int t = 0; t < TW; ++t) {
-        const M br = (M)gv[d][t].x, bi = (M)gv[d][t].y;
-        cr[t] = A::mma(-ai, bi, cr[t]);
-        ci[t] = A::mma(ai, br, ci[t]);
+        for (int t = 0; t < TW; ++t) {
+          const M br = (M)gv[d][t].x, bi = (M)gv[d][t].y;
+          cr[t] = A::mma(ar, br, cr[t]);
+          ci[t] = A::mma(ar, bi, ci[t]);
+        }
+#pragma unroll
+        for (int t = 0; t < TW; ++t) {
+          const M br = (M)gv[d][t].x, bi = (M)gv[d][t].y;
+          cr[t] = A::mma(-ai, bi, cr[t]);
+          ci[t] = A::mma(ai, br, ci[t]);
+        }
       }
     };
 #pragma unroll
@@ -281,13 +298,24 @@ __global__ __launch_bounds__(64 * KWT * NS) __attribute__((amdgpu_waves_per_eu(1
       for (int b = 0; b < KB; ++b) {
         const M ok = (c + 4 * KWT * b + k < c1) ? amask : (M)0;
         const M ar = (M)tv[b].x * ok, ai = (M)tv[b].y * ok;
+        if constexpr (K3) {
+          const M as = ar + ai;
 #pragma unroll
-        for (int t = 0; t < TW; ++t) {
-          const M br = (M)gv[b][t].x, bi = (M)gv[b][t].y;
-          cr[t] = A::mma(ar, br, cr[t]);
-          ci[t] = A::mma(ar, bi, ci[t]);
-          cr[t] = A::mma(-ai, bi, cr[t]);
-          ci[t] = A::mma(ai, br, ci[t]);
+          for (int t = 0; t < TW; ++t) {
+            const M br = (M)gv[b][t].x, bi = (M)gv[b][t].y;
+            cr[t] = A::mma(ar, br, cr[t]);
+            ci[t] = A::mma(ai, bi, ci[t]);
+            c3[t] = A::mma(as, br + bi, c3[t]);
+          }
+        } else {
+#pragma unroll
+          for (int t = 0; t < TW; ++t) {
+            const M br = (M)gv[b][t].x, bi = (M)gv[b][t].y;
+            cr[t] = A::mma(ar, br, cr[t]);
+            ci[t] = A::mma(ar, bi, ci[t]);
+            cr[t] = A::mma(-ai, bi, cr[t]);
+            ci[t] = A::mma(ai, br, ci[t]);
+          }
         }
       }
     }
@@ -300,8 +328,8 @@ __global__ __launch_bounds__(64 * KWT * NS) __attribute__((amdgpu_waves_per_eu(1
   for (int t = 0; t < TW; ++t)
 #pragma unroll
     for (int reg = 0; reg < 4; ++reg) {
-      red[w][tb0 + t][0][reg][lane] = cr[t][reg];
-      red[w][tb0 + t][1][reg][lane] = ci[t][reg];
+      red[w][tb0 + t][0][reg][lane] = K3 ? cr[t][reg] - ci[t][reg] : cr[t][reg];
+      red[w][tb0 + t][1][reg][lane] = K3 ? c3[t][reg] - cr[t][reg] - ci[t][reg] : ci[t][reg];
     }
   __syncthreads();
   if (grp != 0) return;
@@ -349,11 +377,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   int jr[TB];  // right-hand-side columns clamped into the padded width (see k_scatter_mm)
 #pragma unroll
   for (int t = 0; t < TB; ++t) jr[t] = min(rb0 + 16 * t + i, rpad - 1);
-  V4 cr[TB], ci[TB];
+  // Gauss's complex product on f64 MFMA, as in k_scatter_mm: cr += Ar Br, ci += Ai Bi,
+  // c3 += (Ar + Ai)(Br + Bi); Re = cr - ci, Im = c3 - cr - ci
+  V4 cr[TB], ci[TB], c3[TB];
 #pragma unroll
   for (int t = 0; t < TB; ++t) {
     cr[t] = V4{0, 0, 0, 0};
     ci[t] = V4{0, 0, 0, 0};
+    c3[t] = V4{0, 0, 0, 0};
   }
   for (int c = 0; c < L; c += 4 * KB) {
     double2 av[KB], bv[KB][TB];
@@ -369,13 +400,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 #pragma unroll
     for (int b = 0; b < KB; ++b) {
       const double ok = (c + 4 * b + k < L) ? 1.0 : 0.0;
-      const double ar = av[b].x * ok, ai = av[b].y * ok;
+      const double ar = av[b].x * ok, ai = av[b].y * ok, as = ar + ai;
 #pragma unroll
       for (int t = 0; t < TB; ++t) {
         cr[t] = A::mma(ar, bv[b][t].x, cr[t]);
-        ci[t] = A::mma(ar, bv[b][t].y, ci[t]);
-        cr[t] = A::mma(-ai, bv[b][t].y, cr[t]);
-        ci[t] = A::mma(ai, bv[b][t].x, ci[t]);
+        ci[t] = A::mma(ai, bv[b][t].y, ci[t]);
+        c3[t] = A::mma(as, bv[b][t].x + bv[b][t].y, c3[t]);
       }
     }
   }
@@ -390,8 +420,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
       const int ly = p / g.snx, lx = p - ly * g.snx;
       double2* up = u + (size_t)r * g.nx * g.ny + (size_t)(y0 + ly) * g.nx + x0 + lx;
       double2 b = nz[(size_t)r * ndom + s] ? *up : mk(0.0, 0.0);
-      b.x += cr[t][reg];
-      b.y += ci[t][reg];
+      b.x += cr[t][reg] - ci[t][reg];
+      b.y += c3[t][reg] - cr[t][reg] - ci[t][reg];
       *up = b;
     }
 }
