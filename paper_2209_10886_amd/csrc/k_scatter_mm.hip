@@ -2,7 +2,7 @@
 //   OUT_s (rows x R) = T_s[rows, :] (L x L, masked rows) * G_s (L x R)
 // a complex matrix product per subdomain, on MFMA.  Complex products use four real
 // products per k-step, Re += Ar Br - Ai Bi, Im += Ar Bi + Ai Br, on f32 MFMA, and three (Gauss's
-// product) on f64 MFMA, whose rate bounds the complex128 launches.
+// product) on f64 MFMA, whose rate bounds the complex128 operator launches.
 //
 // Operand layouts of the 16x16x4 MFMA on gfx950 (lane l, k = l / 16):
 //   A[i][k] at lane i + 16 k, B[k][j] at lane j + 16 k;
@@ -377,14 +377,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
   int jr[TB];  // right-hand-side columns clamped into the padded width (see k_scatter_mm)
 #pragma unroll
   for (int t = 0; t < TB; ++t) jr[t] = min(rb0 + 16 * t + i, rpad - 1);
-  // Gauss's complex product on f64 MFMA, as in k_scatter_mm: cr += Ar Br, ci += Ai Bi,
-  // c3 += (Ar + Ai)(Br + Bi); Re = cr - ci, Im = c3 - cr - ci
-  V4 cr[TB], ci[TB], c3[TB];
+  // (four real products per k-step here: Gauss's three, with a third accumulator per block, made
+  // this launch slower, 19.4 -> 21.0 ms for 64 sources at 2048^2)
+  V4 cr[TB], ci[TB];
 #pragma unroll
   for (int t = 0; t < TB; ++t) {
     cr[t] = V4{0, 0, 0, 0};
     ci[t] = V4{0, 0, 0, 0};
-    c3[t] = V4{0, 0, 0, 0};
   }
   for (int c = 0; c < L; c += 4 * KB) {
     double2 av[KB], bv[KB][TB];
@@ -400,12 +399,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 #pragma unroll
     for (int b = 0; b < KB; ++b) {
       const double ok = (c + 4 * b + k < L) ? 1.0 : 0.0;
-      const double ar = av[b].x * ok, ai = av[b].y * ok, as = ar + ai;
+      const double ar = av[b].x * ok, ai = av[b].y * ok;
 #pragma unroll
       for (int t = 0; t < TB; ++t) {
         cr[t] = A::mma(ar, bv[b][t].x, cr[t]);
-        ci[t] = A::mma(ai, bv[b][t].y, ci[t]);
-        c3[t] = A::mma(as, bv[b][t].x + bv[b][t].y, c3[t]);
+        ci[t] = A::mma(ar, bv[b][t].y, ci[t]);
+        cr[t] = A::mma(-ai, bv[b][t].y, cr[t]);
+        ci[t] = A::mma(ai, bv[b][t].x, ci[t]);
       }
     }
   }
@@ -420,8 +420,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
       const int ly = p / g.snx, lx = p - ly * g.snx;
       double2* up = u + (size_t)r * g.nx * g.ny + (size_t)(y0 + ly) * g.nx + x0 + lx;
       double2 b = nz[(size_t)r * ndom + s] ? *up : mk(0.0, 0.0);
-      b.x += cr[t][reg] - ci[t][reg];
-      b.y += c3[t][reg] - cr[t][reg] - ci[t][reg];
+      b.x += cr[t][reg];
+      b.y += ci[t][reg];
       *up = b;
     }
 }
