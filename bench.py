@@ -459,13 +459,13 @@ def kernel_names(hbj, many):
     # the one-workgroup-per-solve kernels run at the autotuned prefetch depth D (the legs report the
     # choices under "solve_tuning")
     names64 = {hbj.K_FWD: "k_fwd<double,16,4,D>", hbj.K_BWD: "k_bwd<double,16,2,D>",
-               hbj.K_SCATTER: "k_scatter_apply<double2,16> (sweep steps)",
-               hbj.K_OPERATOR: "k_scatter_apply<double2,16> (operator)",
+               hbj.K_SCATTER: "k_scatter_apply<double2> (sweep steps)",
+               hbj.K_OPERATOR: "k_scatter_apply<double2> (operator)",
                hbj.K_SWEEP: "k_sweep_df<double2,16>", hbj.K_LIFT: "k_lift_partial+k_recon_dense",
                hbj.K_KRYLOV: "krylov (Gram-Schmidt kernels of one iteration)"}
     names32 = {hbj.K_FWD: "k_fwd<float,16,4,D>", hbj.K_BWD: "k_bwd<float,16,2,D>",
-               hbj.K_SCATTER: "k_scatter_apply<float2,16> (sweep steps)",
-               hbj.K_OPERATOR: "k_scatter_apply<double2,16> (operator)",
+               hbj.K_SCATTER: "k_scatter_apply<float2> (sweep steps)",
+               hbj.K_OPERATOR: "k_scatter_apply<double2> (operator)",
                hbj.K_SWEEP: "k_sweep_df", hbj.K_LIFT: "k_lift_partial+k_recon_dense",
                hbj.K_KRYLOV: "krylov (Gram-Schmidt kernels of one iteration)"}
     mfma = {}

@@ -46,7 +46,7 @@ __global__ void k_build_T(Geom g, const Entry* ent, const FaceTab* ft, const IfB
   }
 }
 
-constexpr int CG = 32;       // column groups per workgroup (8 rows x 32 groups = 256 threads)
+constexpr int CG = 64;       // column groups per workgroup (8 rows x 64 groups = 512 threads; 32 and 128 were slower)
 constexpr int LMAX = 1024;   // local interface length limit (sub_nx, sub_ny <= 256)
 
 // out[row] = sum_col T[row][col] gin[col] for the rows of one row block; dst[out position] =
@@ -252,7 +252,8 @@ hipError_t launch_scatter_apply(const Geom& g, const Entry* ent, int nent, int m
       else go(k_scatter_apply<C, K, false, false>, NoStepArgs{});
     }
   };
-  if (L <= 16 * CG) pick(std::integral_constant<int, 16>{});
+  if (L <= 8 * CG) pick(std::integral_constant<int, 8>{});
+  else if (L <= 16 * CG) pick(std::integral_constant<int, 16>{});
   else pick(std::integral_constant<int, LMAX / CG>{});
   return hipGetLastError();
 }
