@@ -326,8 +326,9 @@ __global__ __launch_bounds__(RT2) __attribute__((amdgpu_waves_per_eu(1, 2))) voi
 // hout + 2 ncol ld + 2 col, for the host, which completes Hessenberg column j - 1 with them.
 // publish_only: only the coefficients (the last step of a restart cycle, which needs a and nu).
 constexpr int kDcgsMaxV = 256;
+constexpr int kDcgsThreads = 256;  // threads per update workgroup, one position each (128 and 512 were slower)
 constexpr int kDotsThreads = 256, kDotsBlock = 2;  // fastest of a sweep over 128-1024 threads, 2-4 entries
-__global__ __launch_bounds__(RT) void k_dcgs_update(const double2* V, size_t vstride, int nv, double2* x,
+__global__ __launch_bounds__(kDcgsThreads) void k_dcgs_update(const double2* V, size_t vstride, int nv, double2* x,
                                                     double2* xn, const double2* w, const double2* partial,
                                                     int nchunk, double2* hout, int ld, int n, int publish_only) {
   const int col = blockIdx.y, ncol = gridDim.y;
@@ -339,22 +340,22 @@ __global__ __launch_bounds__(RT) void k_dcgs_update(const double2* V, size_t vst
   const double2* pc = partial + (size_t)col * np * nchunk;
   const int nt = np * nchunk;  // <= kFuseMax
   {
-    double2 pv[kFuseMax / RT];
+    double2 pv[kFuseMax / kDcgsThreads];
 #pragma unroll
-    for (int k = 0; k < kFuseMax / RT; ++k) {
-      const int t = threadIdx.x + k * RT;
+    for (int k = 0; k < kFuseMax / kDcgsThreads; ++k) {
+      const int t = threadIdx.x + k * kDcgsThreads;
       pv[k] = pc[t < nt ? t : nt - 1];
     }
 #pragma unroll
-    for (int k = 0; k < kFuseMax / RT; ++k) sp[threadIdx.x + k * RT] = pv[k];
+    for (int k = 0; k < kFuseMax / kDcgsThreads; ++k) sp[threadIdx.x + k * kDcgsThreads] = pv[k];
   }
   __syncthreads();
   const int nv8 = (nv + 7) / 8 * 8;
-  constexpr int kRows = (2 * kDcgsMaxV + 3 + RT - 1) / RT;  // rows of sums per thread
+  constexpr int kRows = (2 * kDcgsMaxV + 3 + kDcgsThreads - 1) / kDcgsThreads;  // rows of sums per thread
   double2 tsum[kRows];
 #pragma unroll
   for (int r = 0; r < kRows; ++r) {
-    const int i = threadIdx.x + r * RT;
+    const int i = threadIdx.x + r * kDcgsThreads;
     tsum[r] = mk(0.0, 0.0);
     if (i < np)
       for (int c = 0; c < nchunk; ++c) tsum[r] = cadd(tsum[r], sp[i * nchunk + c]);
@@ -362,9 +363,9 @@ __global__ __launch_bounds__(RT) void k_dcgs_update(const double2* V, size_t vst
   __syncthreads();  // sp is reused below for the sums
 #pragma unroll
   for (int r = 0; r < kRows; ++r)
-    if ((int)threadIdx.x + r * RT < np) sp[threadIdx.x + r * RT] = tsum[r];
+    if ((int)threadIdx.x + r * kDcgsThreads < np) sp[threadIdx.x + r * kDcgsThreads] = tsum[r];
   __syncthreads();
-  for (int i = threadIdx.x; i < nv8; i += RT) {  // zero weights pad the last batch
+  for (int i = threadIdx.x; i < nv8; i += kDcgsThreads) {  // zero weights pad the last batch
     ca[i] = i < nv ? sp[i] : mk(0.0, 0.0);
     cb[i] = i < nv ? sp[nv + i] : mk(0.0, 0.0);
   }
@@ -396,7 +397,7 @@ __global__ __launch_bounds__(RT) void k_dcgs_update(const double2* V, size_t vst
   }
   __syncthreads();
   if (blockIdx.x == 0) {
-    for (int i = threadIdx.x; i <= nv; i += RT) {
+    for (int i = threadIdx.x; i <= nv; i += kDcgsThreads) {
       if (i < nv) hout[(size_t)col * ld + i] = ca[i];
       hout[((size_t)ncol + col) * ld + i] = i < nv ? cb[i] : scj[0];
     }
@@ -409,7 +410,7 @@ __global__ __launch_bounds__(RT) void k_dcgs_update(const double2* V, size_t vst
     }
   }
   if (publish_only) return;
-  const int q = blockIdx.x * RT + threadIdx.x;
+  const int q = blockIdx.x * kDcgsThreads + threadIdx.x;
   const size_t t = (size_t)col * n + (q < n ? q : n - 1);
   const double2 xv = x[t], wv = w[t];
   double2 accA = mk(0.0, 0.0), accB = mk(0.0, 0.0);
@@ -568,8 +569,8 @@ hipError_t launch_dcgs_update(const double2* V, size_t vstride, int nv, double2*
                               const double2* partial, int nchunk, double2* hout, int ld, int n, int ncol,
                               bool publish_only, hipStream_t st) {
   if (nchunk < 1 || (2 * nv + 3) * nchunk > kFuseMax || nv + 1 > kDcgsMaxV || nv + 1 > ld) return hipErrorInvalidValue;
-  const int nblk = publish_only ? 1 : (n + RT - 1) / RT;
-  hipLaunchKernelGGL(k_dcgs_update, dim3(nblk, ncol), dim3(RT), 0, st, V, vstride, nv, x, xn, w, partial, nchunk, hout,
+  const int nblk = publish_only ? 1 : (n + kDcgsThreads - 1) / kDcgsThreads;
+  hipLaunchKernelGGL(k_dcgs_update, dim3(nblk, ncol), dim3(kDcgsThreads), 0, st, V, vstride, nv, x, xn, w, partial, nchunk, hout,
                      ld, n, publish_only ? 1 : 0);
   return hipGetLastError();
 }
