@@ -181,11 +181,12 @@ __global__ __launch_bounds__(RT) void k_lift_reduce(Geom g, const FaceTab* ft, c
 // (the incoming datum of the row's face; 0 on outer faces).  u_s already holds A_s^{-1} f_s for
 // the subdomains with a source.  A wavefront per node p reads its 8 KB row of W coalesced
 // (KL entries per lane) and reduces across lanes; each wavefront takes 8 nodes, 32 / KL at a time.
+constexpr int kReconPW = 8;  // nodes per wavefront of the dense reconstruction (16 and 32: the same time)
 template <int KL>
 __global__ __launch_bounds__(RT) void k_recon_dense(Geom g, const FaceTab* ft, const IfCoef* coef,
                                                     const double2* __restrict__ W, const double2* gin,
                                                     const int32_t* nz, double2* u) {
-  constexpr int PW = 8, PB = 32 / KL;  // nodes per wavefront, nodes in flight
+  constexpr int PW = kReconPW, PB = 32 / KL;  // nodes per wavefront, nodes in flight
   const int s = blockIdx.y, r = blockIdx.z;
   const int ndom = g.n1 * g.n2;
   const int L = local_if_len(g);
@@ -258,7 +259,8 @@ hipError_t launch_recon_dense(const Geom& g, const FaceTab* ft, const IfCoef* co
                               const double2* gin, const int32_t* nz, int nrhs, double2* u, hipStream_t st) {
   const int L = local_if_len(g);
   if (L > 1024) return hipErrorInvalidValue;
-  const dim3 grid((g.nloc + 31) / 32, g.n1 * g.n2, nrhs);
+  constexpr int nodes = (RT / 64) * kReconPW;  // per workgroup
+  const dim3 grid((g.nloc + nodes - 1) / nodes, g.n1 * g.n2, nrhs);
   if (L <= 512) hipLaunchKernelGGL((k_recon_dense<8>), grid, dim3(RT), 0, st, g, ft, coef, W, gin, nz, u);
   else hipLaunchKernelGGL((k_recon_dense<16>), grid, dim3(RT), 0, st, g, ft, coef, W, gin, nz, u);
   return hipGetLastError();
