@@ -477,12 +477,24 @@ int hbj_get_tuning(const hbj_ctx* ctx, int32_t* variants, float* us);
  * Autotuned launch shapes of the banded local solves (Sec. 4: every application of the
  * operator, of the preconditioner, the lifting and the reconstruction in the banded form, and
  * the formation of the dense operators at hbj_factor, is a batch of local solves
- * u = A_s^{-1} rhs).  A batch runs in one of four launch shapes:
+ * u = A_s^{-1} rhs).  A batch runs in one of five launch shapes:
  *   0, 1, 2  one workgroup per (subdomain, right-hand side) with register prefetch depths
  *            (column blocks of the factors in flight per lane) forward/backward of 5/3, 3/2
  *            and 6/3 for complex128 factors, 8/4, 4/3 and 10/6 for complex64;
  *   3        16 right-hand sides of one subdomain per workgroup on MFMA (only for batches
- *            with many right-hand sides per subdomain and HBJ_MSOLVE_MFMA).
+ *            with many right-hand sides per subdomain and HBJ_MSOLVE_MFMA);
+ *   4        each local solve split over np workgroups (hbj_set_solve_partitions), one per run
+ *            of consecutive column blocks: the forward (backward) substitution is linear in the
+ *            window rows it carries from one block to the next (kl rows forward, kl + ku
+ *            backward), so every run but the last is first solved from a zero incoming state, a
+ *            short chain over the runs recovers their true incoming states through the runs'
+ *            transfer matrices (formed on the first such batch after each hbj_factor: the
+ *            outgoing state for each unit incoming state; np - 2 matrices of kl^2 and of
+ *            (kl + ku)^2 entries per subdomain and precision, held by the context), and every
+ *            run but the first is solved again from its true state.  About twice the factor
+ *            bytes of shapes 0-2, spread over np times the workgroups: for batches of few solves
+ *            (a sweep step of a few subdomains), where one workgroup per solve leaves most of the
+ *            device idle.
  * All give the same solutions up to rounding (shapes 0-2 bit for bit).  On the first batch of
  * each class - precision, subdomain size and band, number of solves (by powers of two) and
  * right-hand sides per subdomain (1, 2-3, 4-7, 8-15, 16) - the library times every candidate
@@ -495,11 +507,21 @@ int hbj_get_tuning(const hbj_ctx* ctx, int32_t* variants, float* us);
 
 /*
  * hbj_set_solve_tuning - fix the launch shape of every banded solve batch of this context
- * (tests of every shape, reproducible timings): 0..3 as above (3 falls back to 0 where the MFMA
- * solves do not apply), or -1 to choose by timing (default).  Returns HBJ_EINVAL for any other
- * value.
+ * (tests of every shape, reproducible timings): 0..4 as above (3 falls back to 0 where the MFMA
+ * solves do not apply, 4 where the subdomain has fewer than two column blocks or a band wider
+ * than the solve kernels' windows), or -1 to choose by timing (default).  Returns HBJ_EINVAL for
+ * any other value.
  */
 int hbj_set_solve_tuning(hbj_ctx* ctx, int32_t shape);
+
+/*
+ * hbj_set_solve_partitions - runs per local solve of launch shape 4 (the split solves): 2..4096,
+ * or 0 for the default (16).  The count is capped by the subdomain's column blocks of 16 rows,
+ * and rounded so that every run is nonempty (runs of ceil(blocks / np) blocks).  Tuning choices
+ * and cache entries are kept per count.  Returns HBJ_EINVAL for 1, negative values or values
+ * above 4096.
+ */
+int hbj_set_solve_partitions(hbj_ctx* ctx, int32_t np);
 
 /*
  * hbj_get_solve_tuning - the choices made so far by this context, one per batch class.
@@ -507,8 +529,8 @@ int hbj_set_solve_tuning(hbj_ctx* ctx, int32_t shape);
  *            only the first min(capacity, number) are written).
  *   keys     HOST [capacity][96] or NULL: each class's cache key, NUL-terminated.
  *   shapes   HOST [capacity] or NULL: the chosen shape.
- *   us       HOST [capacity][4] or NULL: microseconds per candidate (0: not timed; the choice
- *            came from the cache file or was fixed).
+ *   us       HOST [capacity][5] or NULL: microseconds per candidate shape (0: not timed; the
+ *            choice came from the cache file or was fixed).
  */
 int hbj_get_solve_tuning(const hbj_ctx* ctx, int32_t* n, char* keys, int32_t* shapes, float* us);
 

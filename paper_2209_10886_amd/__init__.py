@@ -36,10 +36,12 @@ ORTH_CGS2, ORTH_DCGS2, ORTH_SSTEP, ORTH_AUTO = 0, 1, 2, 3  # Gram-Schmidt varian
 MSOLVE_CHAINS, MSOLVE_MFMA = 0, 1  # banded solves of many right-hand sides per subdomain
 OK, EINVAL, ESTATE, EHIP, ENOMEM, EWAIT, EIO, ZERO_PIVOT, NOT_CONVERGED = 0, -1, -2, -3, -4, -5, -6, 1, 2
 # launch shapes of the banded solve batches (hbj_set_solve_tuning): one workgroup per solve at three
-# register prefetch depths, or 16 right-hand sides per workgroup on MFMA
+# register prefetch depths, 16 right-hand sides per workgroup on MFMA, or each solve split over
+# several workgroups (runs of column blocks, hbj_set_solve_partitions)
 SOLVE_SHAPES = ("workgroup per solve, depth 0", "workgroup per solve, depth 1", "workgroup per solve, depth 2",
-                "MFMA tiles of 16 right-hand sides")
+                "MFMA tiles of 16 right-hand sides", "split over runs of column blocks")
 SOLVE_SHAPE_MFMA = 3
+SOLVE_SHAPE_SPLIT = 4
 VR_NOALLOC_MAX_RHS = 64  # right-hand sides the allocation-free residual's static scratch holds
 K_FWD, K_BWD, K_FACTOR, K_KRYLOV, K_SCATTER, K_SWEEP, K_LIFT, K_OPERATOR = 0, 1, 2, 3, 4, 5, 6, 7
 
@@ -98,6 +100,7 @@ _SIGS = {
     "hbj_get_tuning": (_I, [_P, ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)]),
     "hbj_set_tuning": (_I, [_P, ctypes.POINTER(_I32)]),
     "hbj_set_solve_tuning": (_I, [_P, _I32]),
+    "hbj_set_solve_partitions": (_I, [_P, _I32]),
     "hbj_set_operator_overlap": (_I, [_P, _I32]),
     "hbj_get_solve_tuning": (_I, [_P, ctypes.POINTER(_I32), ctypes.c_char_p, ctypes.POINTER(_I32),
                                   ctypes.POINTER(ctypes.c_float)]),
@@ -389,8 +392,13 @@ class Context:
 
     def set_solve_tuning(self, shape):
         """Fix the launch shape of every banded solve batch (0-2: one workgroup per solve at the three
-        prefetch depths, 3: MFMA tiles where they apply), or -1 to choose per batch class by timing."""
+        prefetch depths, 3: MFMA tiles where they apply, 4: each solve split over runs of column
+        blocks), or -1 to choose per batch class by timing."""
         _check(_lib.hbj_set_solve_tuning(self._h, int(shape)))
+
+    def set_solve_partitions(self, np_runs=0):
+        """Runs per local solve of the split launch shape (2..4096; 0: the default, 16)."""
+        _check(_lib.hbj_set_solve_partitions(self._h, int(np_runs)))
 
     def solve_tuning(self):
         """The launch shapes chosen so far, per batch class: {key: {"shape": s, "us": [per shape]}}
@@ -402,13 +410,14 @@ class Context:
             return {}
         keys = ctypes.create_string_buffer(96 * cap)
         shapes = (_I32 * cap)()
-        us = (ctypes.c_float * (4 * cap))()
+        ns = len(SOLVE_SHAPES)
+        us = (ctypes.c_float * (ns * cap))()
         n = _I32(cap)
         _check(_lib.hbj_get_solve_tuning(self._h, ctypes.byref(n), keys, shapes, us))
         out = {}
         for i in range(min(cap, n.value)):
             key = keys.raw[96 * i:96 * (i + 1)].split(b"\0", 1)[0].decode()
-            out[key] = {"shape": int(shapes[i]), "us": [round(us[4 * i + j], 2) for j in range(4)]}
+            out[key] = {"shape": int(shapes[i]), "us": [round(us[ns * i + j], 2) for j in range(ns)]}
         return out
 
     def set_sweep_wait(self, max_polls=0, stall_task=-1):

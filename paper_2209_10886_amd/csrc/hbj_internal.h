@@ -269,6 +269,36 @@ hipError_t launch_bwd(const Geom& g, const SolveLayout& L, const Entry* ent, int
                       const IfCoef* coef, const typename Cplx<R>::T* mb, const SolveIO& io,
                       typename Cplx<R>::T* ybuf, hipStream_t st, int dv = 0);
 
+// The same solves with each local solve split over np workgroups (a run of bpp column blocks
+// each): two passes over the runs and, between them, a chain over the runs' transfer matrices
+// (formed by launch_part_phi once per factorisation); results as launch_fwd / launch_bwd up to
+// rounding.  rb: the solve buffer (the right-hand sides, then the solutions, as launch_fwd and
+// launch_bwd leave them); y2: the forward results, [entry][nblk nb]; sig, tt: [entry][np][ns]
+// states; phi_f [subdomain][np - 2][kl][kl], phi_b [subdomain][np - 2][kv][kv].
+struct PartLayout {
+  int np;   // runs per solve (>= 2), each nonempty
+  int bpp;  // column blocks per run (the last run may be shorter)
+  int ns;   // state stride of sig / tt (>= kv)
+};
+bool part_fits(const Geom& g, const SolveLayout& L);
+template <typename R>
+hipError_t launch_part_phi(const Geom& g, const SolveLayout& L, const PartLayout& pl,
+                           const typename Cplx<R>::T* mf, const int16_t* pf, const int32_t* pflag,
+                           const typename Cplx<R>::T* mb, typename Cplx<R>::T* phi_f, typename Cplx<R>::T* phi_b,
+                           int nsub, hipStream_t st);
+template <typename R>
+hipError_t launch_fwd_part(const Geom& g, const SolveLayout& L, const PartLayout& pl, const Entry* ent, int nent,
+                           const FaceTab* ft, const IfCoef* coef, const typename Cplx<R>::T* mf, const int16_t* pf,
+                           const int32_t* pflag, const typename Cplx<R>::T* phi_f, const SolveIO& io,
+                           typename Cplx<R>::T* rb, typename Cplx<R>::T* y2, typename Cplx<R>::T* sig,
+                           typename Cplx<R>::T* tt, hipStream_t st);
+template <typename R>
+hipError_t launch_bwd_part(const Geom& g, const SolveLayout& L, const PartLayout& pl, const Entry* ent, int nent,
+                           const FaceTab* ft, const IfCoef* coef, const typename Cplx<R>::T* mb,
+                           const typename Cplx<R>::T* phi_b, const SolveIO& io, const typename Cplx<R>::T* y2,
+                           typename Cplx<R>::T* rb, typename Cplx<R>::T* sig, typename Cplx<R>::T* tt,
+                           hipStream_t st);
+
 // The same solves for tiles of up to 16 entries of one subdomain (tiles[t] = {first entry, count},
 // entries of a tile consecutive and with the same subdomain), 16 right-hand sides per workgroup on
 // MFMA; results and outputs as launch_fwd / launch_bwd.  piv: some subdomain has row interchanges.

@@ -837,6 +837,413 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   }
 }
 
+// ---------------------------------------------------------------------------
+// One local solve split over several workgroups (partitioned substitution).
+//
+// The forward (backward) substitution is a linear recurrence over the column blocks whose state
+// is the window part carried from one block to the next: kl rows in the forward solve, kv rows in
+// the backward one.  The blocks of a subdomain split into np runs of bpp blocks (processing order
+// o = 0 .. np-1: from the first block forward, from the last one backward).  Pass 1 runs every
+// run but the last on its own workgroup, run 0 exactly (its incoming state is the right-hand
+// side), the others from a zero incoming state, and stores their outgoing states (sig).  The chain
+// recovers the true incoming state of every run, tt[o + 1] = sig[o] + Phi_o tt[o], with the runs'
+// transfer matrices Phi_o (the outgoing state for each unit incoming state and no right-hand side,
+// formed once per factorisation by k_part_phi_*).  Pass 2 reruns every run but the first from its
+// true state and writes its rows.  Each pass reads every factor byte once, on np workgroups.
+// Buffers: rb [entry][nblk nb] the right-hand sides (written by k_part_rhs), yb the results, sig /
+// tt [entry][np][ns] the states, Phi [subdomain][np - 2][S][S] column-major (S = kl or kv).
+
+template <typename C>
+__global__ void k_part_rhs(Geom g, SolveLayout L, const Entry* ent, const FaceTab* ft, const IfCoef* coef, SolveIO io,
+                           C* __restrict__ rb) {
+  const int slot = blockIdx.y, ylen = L.nblk * L.nb;
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= ylen) return;
+  const Entry e = ent[slot];
+  if (io.nz && !io.nz[(size_t)e.rhs * g.n1 * g.n2 + e.s]) return;
+  const FaceTab F = ft[e.s];
+  const RhsCtx rhs(g, e, F, coef, io, slot);
+  rb[(size_t)slot * ylen + l] = to_c<C>(rhs(l));
+}
+
+template <typename R, int NB, int CG, int D>
+__global__ __launch_bounds__(576) void k_fwd_part(Geom g, SolveLayout L, PartLayout pl, int phase, const Entry* ent,
+                                                  const int32_t* __restrict__ nzf,
+                                                  const typename Cplx<R>::T* __restrict__ MF,
+                                                  const int16_t* __restrict__ PF, const int32_t* __restrict__ PFL,
+                                                  const typename Cplx<R>::T* __restrict__ rb,
+                                                  typename Cplx<R>::T* __restrict__ yb, typename Cplx<R>::T* sig,
+                                                  typename Cplx<R>::T* tt) {
+  typedef typename Cplx<R>::T C;
+  constexpr int NC = NB / CG;
+  extern __shared__ unsigned char smem_raw[];
+  const int wf = L.wf, kl = g.kl, nt = blockDim.x, tid = threadIdx.x, nblk = L.nblk;
+  C* bufA = reinterpret_cast<C*>(smem_raw);
+  C* bufB = bufA + wf;
+  int* ident = reinterpret_cast<int*>(bufB + wf);
+  const int slot = blockIdx.x;
+  const int o = phase == 1 ? (int)blockIdx.y : (int)blockIdx.y + 1;
+  const Entry e = ent[slot];
+  if (nzf && !nzf[(size_t)e.rhs * g.n1 * g.n2 + e.s]) return;  // zero right-hand side: x = 0
+  const int b0 = o * pl.bpp, b1 = min(b0 + pl.bpp, nblk);
+  const int ylen = nblk * NB;
+  const C* rhs = rb + (size_t)slot * ylen;
+  C* y = yb + (size_t)slot * ylen;
+  const bool outs = phase == 3 || o == 0;
+  const C* M = MF + (size_t)e.s * L.mf_per_sub;
+  const int16_t* P = PF + (size_t)e.s * L.pf_per_sub;
+  const int32_t* PI = PFL + (size_t)e.s * nblk + b0;
+  const int cg = tid % CG, r = tid / CG;
+  const bool act = r < wf;
+  const size_t bstride = (size_t)NB * wf;
+  const int kstride = wf * CG, toff = act ? r * CG + cg : 0;
+  const int frow = min(tid, NB - 1);
+
+  for (int b = tid; b < b1 - b0; b += nt) ident[b] = PI[b];
+  {
+    const C* tin = tt + ((size_t)slot * pl.np + o) * pl.ns;
+    for (int q = tid; q < wf; q += nt) {
+      const int row = b0 * NB + q;
+      C v = row < ylen ? rhs[row] : czero<C>();
+      if (q < kl && o > 0) v = phase == 3 ? tin[q] : czero<C>();
+      bufA[q] = v;
+    }
+  }
+  C mr[D][NC];
+  C fr[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const C* Mb = M + (size_t)min(b0 + d, b1 - 1) * bstride + toff;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) mr[d][k] = Mb[k * kstride];
+    fr[d] = rhs[min((b0 + d + 1) * NB + kl + frow, ylen - 1)];
+  }
+  __syncthreads();
+
+  auto step = [&](int b, C(&m)[NC], C& f) {
+    if (!ident[b - b0]) {
+      const int16_t* Pb = P + (size_t)b * wf;
+      for (int q = tid; q < wf; q += nt) bufB[q] = bufA[Pb[q]];
+      __syncthreads();
+      C* t = bufA;
+      bufA = bufB;
+      bufB = t;
+    }
+    if (tid < NB) bufB[kl + tid] = ((b + 1) * NB + kl + tid < ylen) ? f : czero<C>();
+    C acc = czero<C>();
+#pragma unroll
+    for (int k = 0; k < NC; ++k) cfma(acc, m[k], bufA[cg * NC + k]);
+    acc = row_reduce<CG>(acc);
+    {
+      const C* Mb = M + (size_t)min(b + D, b1 - 1) * bstride + toff;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) m[k] = Mb[k * kstride];
+      f = rhs[min((b + D + 1) * NB + kl + frow, ylen - 1)];
+    }
+    if (act && cg == 0) {
+      if (r < NB) {
+        if (outs) y[b * NB + r] = acc;
+      } else {
+        bufB[r - NB] = cadd(acc, bufA[r]);
+      }
+    }
+    __syncthreads();
+    C* t = bufA;
+    bufA = bufB;
+    bufB = t;
+  };
+  const int n = b1 - b0, nmain = (n / D) * D;
+  for (int i0 = 0; i0 < nmain; i0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) step(b0 + i0 + d, mr[d], fr[d]);
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (nmain + d < n) step(b0 + nmain + d, mr[d], fr[d]);
+  if (phase == 1) {  // the outgoing state: window rows [0, kl) of block b1
+    C* dst = o == 0 ? tt + ((size_t)slot * pl.np + 1) * pl.ns : sig + ((size_t)slot * pl.np + o) * pl.ns;
+    for (int q = tid; q < kl; q += nt) dst[q] = bufA[q];
+  }
+}
+
+template <typename R, int NB, int CG, int D>
+__global__ __launch_bounds__(576) void k_bwd_part(Geom g, SolveLayout L, PartLayout pl, int phase, const Entry* ent,
+                                                  const FaceTab* ft, const IfCoef* coef,
+                                                  const typename Cplx<R>::T* __restrict__ MB, SolveIO io,
+                                                  const typename Cplx<R>::T* __restrict__ yb,
+                                                  typename Cplx<R>::T* __restrict__ xb, typename Cplx<R>::T* sig,
+                                                  typename Cplx<R>::T* tt) {
+  typedef typename Cplx<R>::T C;
+  constexpr int NC = NB / CG;
+  extern __shared__ unsigned char smem_raw[];
+  const int wb = L.wb, kv = g.kv, nt = blockDim.x, tid = threadIdx.x, nblk = L.nblk;
+  C* bufA = reinterpret_cast<C*>(smem_raw);
+  C* bufB = bufA + wb;
+  const int slot = blockIdx.x;
+  const int o = phase == 1 ? (int)blockIdx.y : (int)blockIdx.y + 1;
+  const int p = pl.np - 1 - o;  // runs are taken from the last block down
+  const int b0 = p * pl.bpp, b1 = min(b0 + pl.bpp, nblk);
+  const bool outs = phase == 3 || o == 0;
+  const Entry e = ent[slot];
+  const FaceTab F = ft[e.s];
+  const double2* gin = e.src ? io.g_b : io.g_a;
+  if (gin) gin += (size_t)e.rhs * g.nif;
+  const int lo = b0 * NB, hi = min(b1 * NB, g.nloc), nedge = 2 * g.snx + 2 * (g.sny - 2);
+  if (io.nz && !io.nz[(size_t)e.rhs * g.n1 * g.n2 + e.s]) {  // zero right-hand side: x = 0
+    if (io.nz_skip_out || !outs) return;
+    if (io.u || io.x64)
+      for (int l = lo + tid; l < hi; l += nt) emit_field(g, e, io, slot, l, mk(0.0, 0.0));
+    if (io.tr_dst)
+      for (int q = tid; q < nedge; q += nt) {
+        const int l = edge_row(g, q);
+        if (l >= lo && l < hi) emit_traces(g, e, F, coef, io, gin, l, mk(0.0, 0.0));
+      }
+    return;
+  }
+  const int ylen = nblk * NB;
+  const C* y = yb + (size_t)slot * ylen;
+  C* x = xb + (size_t)slot * ylen;
+  const C* M = MB + (size_t)e.s * L.mb_per_sub;
+  const int cg = tid % CG, r = tid / CG;
+  const bool act = r < wb;
+  const size_t bstride = (size_t)NB * wb;
+  const int kstride = wb * CG, toff = act ? r * CG + cg : 0;
+  const int frow = min(tid, NB - 1);
+  {
+    const C* tin = tt + ((size_t)slot * pl.np + o) * pl.ns;
+    for (int q = tid; q < wb; q += nt) {
+      const int row = (b1 - 1) * NB - kv + q;
+      C v = row >= 0 ? y[row] : czero<C>();
+      if (q >= NB && o > 0) v = phase == 3 ? tin[q - NB] : czero<C>();
+      bufA[q] = v;
+    }
+  }
+  C mr[D][NC];
+  C fr[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const C* Mb = M + (size_t)max(b1 - 1 - d, b0) * bstride + toff;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) mr[d][k] = Mb[k * kstride];
+    fr[d] = y[max((b1 - 2 - d) * NB - kv + frow, 0)];
+  }
+  __syncthreads();
+
+  auto step = [&](int b, C(&m)[NC], C& f) {
+    if (tid < NB) bufB[tid] = ((b - 1) * NB - kv + tid >= 0) ? f : czero<C>();
+    C acc = czero<C>();
+#pragma unroll
+    for (int k = 0; k < NC; ++k) cfma(acc, m[k], bufA[kv + cg * NC + k]);
+    acc = row_reduce<CG>(acc);
+    {
+      const C* Mb = M + (size_t)max(b - D, b0) * bstride + toff;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) m[k] = Mb[k * kstride];
+      f = y[max((b - D - 1) * NB - kv + frow, 0)];
+    }
+    if (act && cg == 0) {
+      if (r >= kv) {
+        if (outs) x[b * NB + r - kv] = acc;
+      } else {
+        bufB[r + NB] = cadd(acc, bufA[r]);
+      }
+    }
+    __syncthreads();
+    C* t = bufA;
+    bufA = bufB;
+    bufB = t;
+  };
+  const int n = b1 - b0, nmain = (n / D) * D;
+  for (int i0 = 0; i0 < nmain; i0 += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) step(b1 - 1 - (i0 + d), mr[d], fr[d]);
+  }
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+    if (nmain + d < n) step(b1 - 1 - (nmain + d), mr[d], fr[d]);
+  if (phase == 1) {  // the outgoing state: window rows [nb, wb) of block b0 - 1
+    C* dst = o == 0 ? tt + ((size_t)slot * pl.np + 1) * pl.ns : sig + ((size_t)slot * pl.np + o) * pl.ns;
+    for (int q = NB + tid; q < wb; q += nt) dst[q - NB] = bufA[q];
+  }
+  if (!outs) return;
+  // this run's rows are final: their outputs, as k_bwd writes them
+  if (io.u || io.x64)
+    for (int l = lo + tid; l < hi; l += nt) emit_field(g, e, io, slot, l, to_d(x[l]));
+  if (io.tr_dst)
+    for (int q = tid; q < nedge; q += nt) {
+      const int l = edge_row(g, q);
+      if (l >= lo && l < hi) emit_traces(g, e, F, coef, io, gin, l, to_d(x[l]));
+    }
+}
+
+// The chain of one entry per workgroup: tt[o + 1] = sig[o] + Phi_o tt[o] for o = 1 .. np - 2, the
+// state in LDS; thread (group gi, row i) sums the columns j = gi, gi + G, ... of row i (loads along
+// a column of Phi are contiguous across the threads of a group).
+constexpr int kPartChainThreads = 1024, kPartStateMax = 576;
+template <typename C>
+__global__ __launch_bounds__(kPartChainThreads) void k_part_chain(Geom g, PartLayout pl, int S, const Entry* ent,
+                                                                  const int32_t* __restrict__ nzf,
+                                                                  const C* __restrict__ phi, const C* sig, C* tt) {
+  __shared__ C ts[2][kPartStateMax];
+  __shared__ C red[kPartChainThreads];
+  const int slot = blockIdx.x, tid = threadIdx.x;
+  const Entry e = ent[slot];
+  if (nzf && !nzf[(size_t)e.rhs * g.n1 * g.n2 + e.s]) return;
+  const int G = max(1, kPartChainThreads / S);
+  const int gi = tid / S, i = tid - gi * S;
+  for (int q = tid; q < S; q += kPartChainThreads) ts[0][q] = tt[((size_t)slot * pl.np + 1) * pl.ns + q];
+  __syncthreads();
+  int cur = 0;
+  for (int o = 1; o <= pl.np - 2; ++o) {
+    const C* F = phi + ((size_t)e.s * (pl.np - 2) + (o - 1)) * S * S;
+    C a0 = czero<C>(), a1 = czero<C>(), a2 = czero<C>(), a3 = czero<C>();
+    if (gi < G) {
+      int j = gi;
+      for (; j + 3 * G < S; j += 4 * G) {
+        const C f0 = F[(size_t)j * S + i], f1 = F[(size_t)(j + G) * S + i];
+        const C f2 = F[(size_t)(j + 2 * G) * S + i], f3 = F[(size_t)(j + 3 * G) * S + i];
+        cfma(a0, f0, ts[cur][j]);
+        cfma(a1, f1, ts[cur][j + G]);
+        cfma(a2, f2, ts[cur][j + 2 * G]);
+        cfma(a3, f3, ts[cur][j + 3 * G]);
+      }
+      for (; j < S; j += G) cfma(a0, F[(size_t)j * S + i], ts[cur][j]);
+    }
+    red[tid] = cadd(cadd(a0, a1), cadd(a2, a3));
+    __syncthreads();
+    if (tid < S) {
+      C v = sig[((size_t)slot * pl.np + o) * pl.ns + tid];
+      for (int q = 0; q < G; ++q) v = cadd(v, red[q * S + tid]);
+      ts[cur ^ 1][tid] = v;
+      tt[((size_t)slot * pl.np + o + 1) * pl.ns + tid] = v;
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+}
+
+// Transfer matrices of the forward runs 1 .. np - 2: workgroup (column group, run, subdomain)
+// carries NCOL unit incoming states through the run's blocks with no right-hand side (the window
+// [wf][NCOL] in LDS, twice for the row interchanges; thread i owns state row i), then stores the
+// outgoing states as columns.
+template <typename C, int NCOL>
+__global__ __launch_bounds__(576) void k_part_phi_fwd(Geom g, SolveLayout L, PartLayout pl,
+                                                      const C* __restrict__ MF, const int16_t* __restrict__ PF,
+                                                      const int32_t* __restrict__ PFL, C* __restrict__ phi) {
+  constexpr int NB = 16;
+  extern __shared__ unsigned char smem_raw[];
+  const int wf = L.wf, kl = g.kl, nblk = L.nblk, tid = threadIdx.x, nt = blockDim.x, cgf = L.cgf;
+  C* win = reinterpret_cast<C*>(smem_raw);  // [wf][NCOL]
+  C* alt = win + (size_t)wf * NCOL;         // the same, for the interchanges
+  const int s = blockIdx.z, o = blockIdx.y + 1, c0 = blockIdx.x * NCOL;
+  const int b0 = o * pl.bpp, b1 = min(b0 + pl.bpp, nblk);
+  const C* M = MF + (size_t)s * L.mf_per_sub;
+  const int16_t* P = PF + (size_t)s * L.pf_per_sub;
+  const int32_t* PI = PFL + (size_t)s * nblk;
+  C one = czero<C>();
+  one.x = 1;
+  for (int idx = tid; idx < wf * NCOL; idx += nt) {
+    const int q = idx / NCOL, c = idx - q * NCOL;
+    win[idx] = (q < kl && q == c0 + c) ? one : czero<C>();
+  }
+  __syncthreads();
+  const bool act = tid < kl;
+  const int r = NB + (act ? tid : 0);  // the window row this thread updates
+  for (int b = b0; b < b1; ++b) {
+    if (!PI[b]) {  // row interchanges inside this block's window
+      const int16_t* Pb = P + (size_t)b * wf;
+      for (int idx = tid; idx < wf * NCOL; idx += nt) {
+        const int q = idx / NCOL, c = idx - q * NCOL;
+        alt[idx] = win[(int)Pb[q] * NCOL + c];
+      }
+      __syncthreads();
+      C* t = win;
+      win = alt;
+      alt = t;
+    }
+    C acc[NCOL];
+    if (act) {
+      const C* Mb = M + (size_t)b * NB * wf;
+      C m[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) m[k] = Mb[tile_index(k, r, wf, NB, cgf)];
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) acc[c] = win[r * NCOL + c];
+#pragma unroll
+      for (int k = 0; k < NB; ++k)
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) cfma(acc[c], m[k], win[k * NCOL + c]);
+    }
+    __syncthreads();
+    if (act)
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) win[tid * NCOL + c] = acc[c];
+    if (tid < NB)
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) win[(kl + tid) * NCOL + c] = czero<C>();
+    __syncthreads();
+  }
+  if (act) {
+    C* F = phi + ((size_t)s * (pl.np - 2) + (o - 1)) * kl * kl;
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c)
+      if (c0 + c < kl) F[(size_t)(c0 + c) * kl + tid] = win[tid * NCOL + c];
+  }
+}
+
+// Transfer matrices of the backward runs 1 .. np - 2 (run o covers the blocks of partition
+// np - 1 - o, taken from its last block down); window [wb][NCOL], state rows [nb, wb).
+template <typename C, int NCOL>
+__global__ __launch_bounds__(576) void k_part_phi_bwd(Geom g, SolveLayout L, PartLayout pl,
+                                                      const C* __restrict__ MB, C* __restrict__ phi) {
+  constexpr int NB = 16;
+  extern __shared__ unsigned char smem_raw[];
+  C* win = reinterpret_cast<C*>(smem_raw);  // [wb][NCOL]
+  const int wb = L.wb, kv = g.kv, nblk = L.nblk, tid = threadIdx.x, nt = blockDim.x, cgb = L.cgb;
+  const int s = blockIdx.z, o = blockIdx.y + 1, c0 = blockIdx.x * NCOL;
+  const int p = pl.np - 1 - o;
+  const int b0 = p * pl.bpp, b1 = min(b0 + pl.bpp, nblk);
+  const C* M = MB + (size_t)s * L.mb_per_sub;
+  C one = czero<C>();
+  one.x = 1;
+  for (int idx = tid; idx < wb * NCOL; idx += nt) {
+    const int q = idx / NCOL, c = idx - q * NCOL;
+    win[idx] = (q >= NB && q - NB == c0 + c) ? one : czero<C>();
+  }
+  __syncthreads();
+  const bool act = tid < kv;
+  const int r = act ? tid : 0;
+  for (int b = b1 - 1; b >= b0; --b) {
+    C acc[NCOL];
+    if (act) {
+      const C* Mb = M + (size_t)b * NB * wb;
+      C m[NB];
+#pragma unroll
+      for (int k = 0; k < NB; ++k) m[k] = Mb[tile_index(k, r, wb, NB, cgb)];
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) acc[c] = win[r * NCOL + c];
+#pragma unroll
+      for (int k = 0; k < NB; ++k)
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) cfma(acc[c], m[k], win[(kv + k) * NCOL + c]);
+    }
+    __syncthreads();
+    if (act)
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) win[(tid + NB) * NCOL + c] = acc[c];
+    if (tid < NB)
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) win[tid * NCOL + c] = czero<C>();
+    __syncthreads();
+  }
+  if (act) {
+    C* F = phi + ((size_t)s * (pl.np - 2) + (o - 1)) * kv * kv;
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c)
+      if (c0 + c < kv) F[(size_t)(c0 + c) * kv + tid] = win[(NB + tid) * NCOL + c];
+  }
+}
+
 }  // namespace
 
 // column groups per window row (must match the tiled layout written by the repack)
@@ -1030,3 +1437,133 @@ hipError_t launch_source_flags(const Geom& g, const double2* f, int nrhs, int32_
   hipLaunchKernelGGL(k_source_flags, dim3(g.n1 * g.n2, nrhs), dim3(kFlagThreads), 0, st, g, f, nz);
   return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// partitioned solves
+bool part_fits(const Geom& g, const SolveLayout& L) {
+  // the windows of the transfer-matrix kernels (the forward one twice, 4 columns at least) within 64 KiB
+  return L.nb == 16 && L.wf <= 576 && L.wb <= 576 && g.kv <= kPartStateMax && g.kl <= kPartStateMax &&
+         2 * L.wf * 4 * sizeof(double2) <= 65536 && L.wb * 4 * sizeof(double2) <= 65536;
+}
+
+template <typename C>
+static int part_ncol(int rows) {  // columns of a transfer-matrix workgroup: the window within 64 KiB of LDS
+  return rows * 16 * (int)sizeof(C) <= 65536 ? 16 : rows * 8 * (int)sizeof(C) <= 65536 ? 8 : 4;
+}
+
+template <typename R>
+hipError_t launch_part_phi(const Geom& g, const SolveLayout& L, const PartLayout& pl,
+                           const typename Cplx<R>::T* mf, const int16_t* pf, const int32_t* pflag,
+                           const typename Cplx<R>::T* mb, typename Cplx<R>::T* phi_f, typename Cplx<R>::T* phi_b,
+                           int nsub, hipStream_t st) {
+  typedef typename Cplx<R>::T C;
+  if (pl.np <= 2 || nsub == 0) return hipSuccess;
+  if (!part_fits(g, L)) return hipErrorInvalidValue;
+  {
+    const int nc = part_ncol<C>(2 * L.wf);
+    const dim3 grid((g.kl + nc - 1) / nc, pl.np - 2, nsub), blk(((g.kl + 63) / 64) * 64);
+    const size_t shm = 2 * (size_t)L.wf * nc * sizeof(C);
+    if (nc == 16) hipLaunchKernelGGL((k_part_phi_fwd<C, 16>), grid, blk, shm, st, g, L, pl, mf, pf, pflag, phi_f);
+    else if (nc == 8) hipLaunchKernelGGL((k_part_phi_fwd<C, 8>), grid, blk, shm, st, g, L, pl, mf, pf, pflag, phi_f);
+    else hipLaunchKernelGGL((k_part_phi_fwd<C, 4>), grid, blk, shm, st, g, L, pl, mf, pf, pflag, phi_f);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    const int nc = part_ncol<C>(L.wb);
+    const dim3 grid((g.kv + nc - 1) / nc, pl.np - 2, nsub), blk(((g.kv + 63) / 64) * 64);
+    const size_t shm = (size_t)L.wb * nc * sizeof(C);
+    if (nc == 16) hipLaunchKernelGGL((k_part_phi_bwd<C, 16>), grid, blk, shm, st, g, L, pl, mb, phi_b);
+    else if (nc == 8) hipLaunchKernelGGL((k_part_phi_bwd<C, 8>), grid, blk, shm, st, g, L, pl, mb, phi_b);
+    else hipLaunchKernelGGL((k_part_phi_bwd<C, 4>), grid, blk, shm, st, g, L, pl, mb, phi_b);
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_fwd_part(const Geom& g, const SolveLayout& L, const PartLayout& pl, const Entry* ent, int nent,
+                           const FaceTab* ft, const IfCoef* coef, const typename Cplx<R>::T* mf, const int16_t* pf,
+                           const int32_t* pflag, const typename Cplx<R>::T* phi_f, const SolveIO& io,
+                           typename Cplx<R>::T* rb, typename Cplx<R>::T* y2, typename Cplx<R>::T* sig,
+                           typename Cplx<R>::T* tt, hipStream_t st) {
+  typedef typename Cplx<R>::T C;
+  if (nent == 0) return hipSuccess;
+  if (!part_fits(g, L) || pl.np < 2 || pl.bpp < 1 || (pl.np - 1) * pl.bpp >= L.nblk || pl.ns < g.kv)
+    return hipErrorInvalidValue;
+  const int ylen = L.nblk * L.nb;
+  hipLaunchKernelGGL(k_part_rhs<C>, dim3((ylen + 255) / 256, nent), dim3(256), 0, st, g, L, ent, ft, coef, io, rb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const size_t shm = 2 * (size_t)L.wf * sizeof(C) + (size_t)pl.bpp * sizeof(int);
+  const dim3 grid(nent, pl.np - 1), blk(((L.wf * L.cgf + 63) / 64) * 64);
+  for (int phase = 1; phase <= 3; phase += 2) {
+#define HBJ_FWDP(CG, D)                                                                                          \
+  hipLaunchKernelGGL((k_fwd_part<R, 16, CG, D>), grid, blk, shm, st, g, L, pl, phase, ent, io.nz, mf, pf, pflag, \
+                     (const C*)rb, y2, sig, tt)
+    if (L.cgf == 4) {
+      if constexpr (sizeof(R) == 8) HBJ_FWDP(4, 5);
+      else HBJ_FWDP(4, 8);
+    } else {
+      HBJ_FWDP(1, 1);
+    }
+#undef HBJ_FWDP
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (phase == 1 && pl.np > 2) {
+      hipLaunchKernelGGL(k_part_chain<C>, dim3(nent), dim3(kPartChainThreads), 0, st, g, pl, g.kl, ent, io.nz, phi_f,
+                         (const C*)sig, tt);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+template <typename R>
+hipError_t launch_bwd_part(const Geom& g, const SolveLayout& L, const PartLayout& pl, const Entry* ent, int nent,
+                           const FaceTab* ft, const IfCoef* coef, const typename Cplx<R>::T* mb,
+                           const typename Cplx<R>::T* phi_b, const SolveIO& io, const typename Cplx<R>::T* y2,
+                           typename Cplx<R>::T* rb, typename Cplx<R>::T* sig, typename Cplx<R>::T* tt,
+                           hipStream_t st) {
+  typedef typename Cplx<R>::T C;
+  if (nent == 0) return hipSuccess;
+  if (!part_fits(g, L) || pl.np < 2 || pl.bpp < 1 || (pl.np - 1) * pl.bpp >= L.nblk || pl.ns < g.kv)
+    return hipErrorInvalidValue;
+  const size_t shm = 2 * (size_t)L.wb * sizeof(C);
+  const dim3 grid(nent, pl.np - 1), blk(((L.wb * L.cgb + 63) / 64) * 64);
+  hipError_t e = hipSuccess;
+  for (int phase = 1; phase <= 3; phase += 2) {
+#define HBJ_BWDP(CG, D)                                                                                            \
+  hipLaunchKernelGGL((k_bwd_part<R, 16, CG, D>), grid, blk, shm, st, g, L, pl, phase, ent, ft, coef, mb, io, y2, rb, \
+                     sig, tt)
+    if (L.cgb == 2) {
+      if constexpr (sizeof(R) == 8) HBJ_BWDP(2, 3);
+      else HBJ_BWDP(2, 4);
+    } else {
+      HBJ_BWDP(1, 1);
+    }
+#undef HBJ_BWDP
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (phase == 1 && pl.np > 2) {
+      hipLaunchKernelGGL(k_part_chain<C>, dim3(nent), dim3(kPartChainThreads), 0, st, g, pl, g.kv, ent, io.nz, phi_b,
+                         (const C*)sig, tt);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+#define HBJ_PART_INST(R, C)                                                                                      \
+  template hipError_t launch_part_phi<R>(const Geom&, const SolveLayout&, const PartLayout&, const C*, const int16_t*, \
+                                         const int32_t*, const C*, C*, C*, int, hipStream_t);                        \
+  template hipError_t launch_fwd_part<R>(const Geom&, const SolveLayout&, const PartLayout&, const Entry*, int,        \
+                                         const FaceTab*, const IfCoef*, const C*, const int16_t*, const int32_t*,      \
+                                         const C*, const SolveIO&, C*, C*, C*, C*, hipStream_t);                      \
+  template hipError_t launch_bwd_part<R>(const Geom&, const SolveLayout&, const PartLayout&, const Entry*, int,        \
+                                         const FaceTab*, const IfCoef*, const C*, const C*, const SolveIO&, const C*,  \
+                                         C*, C*, C*, hipStream_t);
+HBJ_PART_INST(double, double2)
+HBJ_PART_INST(float, float2)
+#undef HBJ_PART_INST

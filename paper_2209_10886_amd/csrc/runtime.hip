@@ -48,9 +48,12 @@ constexpr int kMaskFwd = (1 << FACE_E) | (1 << FACE_N);
 constexpr int kMaskBwd = (1 << FACE_W) | (1 << FACE_S);
 
 // launch shapes of a batch of banded local solves: one workgroup per solve at the prefetch depth
-// variants of the solve kernels, then 16 right-hand sides of one subdomain per workgroup on MFMA
+// variants of the solve kernels, then 16 right-hand sides of one subdomain per workgroup on MFMA,
+// then each solve split over several workgroups (runs of column blocks)
 constexpr int kShapeMfma = kSolveDepthVariants;
-constexpr int kSolveShapes = kSolveDepthVariants + 1;
+constexpr int kShapePart = kSolveDepthVariants + 1;
+constexpr int kSolveShapes = kSolveDepthVariants + 2;
+constexpr int kPartDefault = 16;  // runs per split solve (hbj_set_solve_partitions)
 
 constexpr int kMatrixRhs = 4;  // from this many right-hand sides on, the operators run as MFMA products
 
@@ -214,6 +217,17 @@ struct hbj_ctx {
   };
   std::map<std::string, SolveChoice> solve_choice;
   int solve_shape_fixed = -1;  // hbj_set_solve_tuning: -1 = by timing
+  // split solves: runs per solve, the runs' transfer matrices per precision [complex128, complex64]
+  // (formed for the factorisation of graph_epoch), the forward results and the run states
+  int part_np = kPartDefault;
+  void* phi[2] = {nullptr, nullptr};
+  size_t phi_bytes[2] = {0, 0};
+  int phi_epoch[2] = {-1, -1};
+  int phi_np[2] = {0, 0};
+  void* part_y2 = nullptr;
+  size_t part_y2_bytes = 0;
+  void* part_st = nullptr;
+  size_t part_st_bytes = 0;
   std::string arch;            // device architecture name (cache keys)
   int32_t* nzf = nullptr;   // per (rhs, subdomain) nonzero-source flags for the lifting
   size_t nzf_cap = 0;
@@ -306,6 +320,10 @@ hbj_ctx::~hbj_ctx() {
   if (ev_fork) (void)hipEventDestroy(ev_fork);
   if (ev_join) (void)hipEventDestroy(ev_join);
   dfree(ybuf_side);
+  dfree(phi[0]);
+  dfree(phi[1]);
+  dfree(part_y2);
+  dfree(part_st);
 }
 
 namespace {
@@ -662,6 +680,59 @@ double bwd_bytes(const hbj_ctx* c, size_t elem) { return (double)c->g.nloc * (c-
 // without timing, batches with at least this many entries per tile on average run the MFMA solves
 constexpr int kMmMinPerTile = 8;
 
+// runs of a split solve: np runs of bpp column blocks, every run nonempty (np >= 2)
+PartLayout part_layout(const hbj_ctx* c) {
+  const int nblk = c->L.nblk;
+  int np = std::max(2, std::min(c->part_np, nblk));
+  int bpp = (nblk + np - 1) / np;
+  np = (nblk + bpp - 1) / bpp;
+  PartLayout pl{};
+  pl.np = np;
+  pl.bpp = bpp;
+  pl.ns = c->g.kv;
+  return pl;
+}
+
+bool part_ok(const hbj_ctx* c) { return c->L.nblk >= 2 && part_fits(c->g, c->L); }
+
+// the split solves' transfer matrices are formed for this factorisation and run count
+bool part_ready(const hbj_ctx* c, size_t real_bytes) {
+  const int pi = real_bytes == 8 ? 0 : 1;
+  const PartLayout pl = part_layout(c);
+  return pl.np <= 2 || (c->phi_epoch[pi] == c->graph_epoch && c->phi_np[pi] == pl.np);
+}
+
+// workspace of a split-solve batch of nent entries and, once per factorisation, the transfer
+// matrices of the runs (formed on the context stream, ahead of the batch)
+template <typename R>
+hipError_t ensure_part(hbj_ctx* c, int nent, const typename Cplx<R>::T* mf, const typename Cplx<R>::T* mb) {
+  typedef typename Cplx<R>::T C;
+  const PartLayout pl = part_layout(c);
+  const size_t ylen = (size_t)c->L.nblk * c->L.nb;
+  auto grow = [](void** p, size_t* have, size_t need) -> hipError_t {
+    if (need <= *have) return hipSuccess;
+    dfree(*p);
+    *p = nullptr;
+    *have = 0;
+    hipError_t e = hipMalloc(p, need);
+    if (e == hipSuccess) *have = need;
+    return e;
+  };
+  hipError_t e = grow(&c->part_y2, &c->part_y2_bytes, (size_t)nent * ylen * sizeof(C));
+  if (e == hipSuccess) e = grow(&c->part_st, &c->part_st_bytes, 2 * (size_t)nent * pl.np * pl.ns * sizeof(C));
+  if (e != hipSuccess || part_ready(c, sizeof(R))) return e;
+  const int pi = sizeof(R) == 8 ? 0 : 1;
+  const size_t kl = c->g.kl, kv = c->g.kv, nf = (size_t)c->ndom * (pl.np - 2) * kl * kl;
+  e = grow(&c->phi[pi], &c->phi_bytes[pi], (nf + (size_t)c->ndom * (pl.np - 2) * kv * kv) * sizeof(C));
+  if (e == hipSuccess)
+    e = launch_part_phi<R>(c->g, c->L, pl, mf, c->pf, c->pflag, mb, (C*)c->phi[pi], (C*)c->phi[pi] + nf, c->ndom,
+                           c->st);
+  if (e != hipSuccess) return e;
+  c->phi_epoch[pi] = c->graph_epoch;
+  c->phi_np[pi] = pl.np;
+  return hipSuccess;
+}
+
 // the forward and backward solves of a batch in launch shape `shape` into the solve buffer
 template <typename R>
 hipError_t solve_pair_shape(hbj_ctx* c, int shape, const Entry* ent, int nent, const int2* tiles, int ntiles,
@@ -672,6 +743,26 @@ hipError_t solve_pair_shape(hbj_ctx* c, int shape, const Entry* ent, int nent, c
   const double nread = mm ? (double)ntiles : (double)nent;
   C* sink = (C*)c->ybuf + (size_t)nent * c->L.nblk * c->L.nb;  // the solve buffer holds one spare entry
   hipError_t e;
+  if (shape == kShapePart) {
+    e = ensure_part<R>(c, nent, mf, mb);
+    if (e != hipSuccess) return e;
+    const PartLayout pl = part_layout(c);
+    const int pi = sizeof(R) == 8 ? 0 : 1;
+    const size_t nf = (size_t)c->ndom * (pl.np - 2) * c->g.kl * c->g.kl;
+    const C* phi_f = (const C*)c->phi[pi];
+    const C* phi_b = phi_f ? phi_f + nf : nullptr;
+    C* sig = (C*)c->part_st;
+    C* tt = sig + (size_t)nent * pl.np * pl.ns;
+    {
+      ProfScope ps(c, HBJ_K_FWD, nread * fwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * c->g.kl, prof);
+      e = launch_fwd_part<R>(c->g, c->L, pl, ent, nent, c->ft, c->coef, mf, c->pf, c->pflag, phi_f, io, (C*)c->ybuf,
+                             (C*)c->part_y2, sig, tt, c->st);
+    }
+    if (e != hipSuccess) return e;
+    ProfScope ps(c, HBJ_K_BWD, nread * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1), prof);
+    return launch_bwd_part<R>(c->g, c->L, pl, ent, nent, c->ft, c->coef, mb, phi_b, io, (const C*)c->part_y2,
+                              (C*)c->ybuf, sig, tt, c->st);
+  }
   {
     ProfScope ps(c, HBJ_K_FWD, nread * fwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * c->g.kl, prof);
     e = mm ? launch_fwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mf, c->pf, c->pflag, c->interchanges,
@@ -698,9 +789,9 @@ std::string solve_class_key(const hbj_ctx* c, size_t elem, int nent, int ntiles,
   const int per = mm_ok ? per_tile(nent, ntiles) : 1;
   const int pb = per >= 16 ? 16 : per >= 8 ? 8 : per >= 4 ? 4 : per >= 2 ? 2 : 1;
   char buf[160];
-  std::snprintf(buf, sizeof buf, "solve|%s|%s|%dx%d|kl%d|ku%d|p%d|n%d|r%d|%s", c->arch.c_str(),
+  std::snprintf(buf, sizeof buf, "solve|%s|%s|%dx%d|kl%d|ku%d|p%d|n%d|r%d|%s|s%d|np%d", c->arch.c_str(),
                 elem == 16 ? "c128" : "c64", c->g.snx, c->g.sny, c->g.kl, c->g.ku, c->interchanges ? 1 : 0, n2, pb,
-                mm_ok ? "mm" : "wg");
+                mm_ok ? "mm" : "wg", kSolveShapes, part_layout(c).np);
   return std::string(buf);
 }
 
@@ -726,7 +817,8 @@ int time_solve_shapes(hbj_ctx* c, const Entry* ent, int nent, const int2* tiles,
   tio.tr_dst = nullptr;
   bool alive[kSolveShapes];
   float first[kSolveShapes] = {}, tot[kSolveShapes] = {};
-  for (int v = 0; v < kSolveShapes; ++v) alive[v] = (v != kShapeMfma) || mm_ok;
+  for (int v = 0; v < kSolveShapes; ++v) alive[v] = (v != kShapeMfma || mm_ok) && (v != kShapePart || part_ok(c));
+  if (alive[kShapePart]) HIPCHK(ensure_part<R>(c, nent, mf, mb));  // formed once, outside the timings
   auto timed = [&](int v, float* ms) -> hipError_t {
     hipError_t e = hipEventRecord(c->ev0, c->st);
     if (e == hipSuccess) e = solve_pair_shape<R>(c, v, ent, nent, tiles, ntiles, tio, mf, mb, false);
@@ -769,7 +861,8 @@ int launch_solve_pair(hbj_ctx* c, const Entry* ent, int nent, const int2* tiles,
   const bool mm_ok = c->msolve == HBJ_MSOLVE_MFMA && tiles && ntiles > 0 && trisolve_mm_fits(c->L, sizeof(C));
   int shape;
   if (c->solve_shape_fixed >= 0) {
-    shape = (c->solve_shape_fixed == kShapeMfma && !mm_ok) ? 0 : c->solve_shape_fixed;
+    shape = c->solve_shape_fixed;
+    if ((shape == kShapeMfma && !mm_ok) || (shape == kShapePart && !part_ok(c))) shape = 0;
   } else {
     const std::string key = solve_class_key(c, sizeof(C), nent, ntiles, mm_ok);
     auto it = c->solve_choice.find(key);
@@ -778,7 +871,8 @@ int launch_solve_pair(hbj_ctx* c, const Entry* ent, int nent, const int2* tiles,
     } else {
       hbj_ctx::SolveChoice ch;
       int v = -1;
-      if (tune_cache_get(key, &v) && v >= 0 && v < kSolveShapes && (v != kShapeMfma || mm_ok)) {
+      if (tune_cache_get(key, &v) && v >= 0 && v < kSolveShapes && (v != kShapeMfma || mm_ok) &&
+          (v != kShapePart || part_ok(c))) {
         ch.shape = v;
       } else if (tuning_enabled(c)) {
         int rc = time_solve_shapes<R>(c, ent, nent, tiles, ntiles, io, mf, mb, mm_ok, ch);
@@ -790,6 +884,10 @@ int launch_solve_pair(hbj_ctx* c, const Entry* ent, int nent, const int2* tiles,
       c->solve_choice[key] = ch;
       shape = ch.shape;
     }
+  }
+  if (shape == kShapePart && !tuning_enabled(c) && !part_ready(c, sizeof(R))) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(c->st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) shape = 0;
   }
   HIPCHK(solve_pair_shape<R>(c, shape, ent, nent, tiles, ntiles, io, mf, mb, true));
   return HBJ_OK;
@@ -3145,6 +3243,12 @@ int hbj_set_solve_tuning(hbj_ctx* c, int32_t shape) {
   if (!c) return fail(HBJ_EINVAL, "null context");
   if (shape < -1 || shape >= kSolveShapes) return fail(HBJ_EINVAL, "solve launch shape out of range");
   c->solve_shape_fixed = shape;
+  return HBJ_OK;
+}
+
+int hbj_set_solve_partitions(hbj_ctx* c, int32_t np) {
+  if (!c || np < 0 || np == 1 || np > 4096) return fail(HBJ_EINVAL, "bad run count");
+  c->part_np = np == 0 ? kPartDefault : np;
   return HBJ_OK;
 }
 

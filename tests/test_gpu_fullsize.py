@@ -73,6 +73,29 @@ def test_fullsize_preconditioner(full):
     assert rel(z, sweep.apply_bj(dd, r)) < 1e-11
 
 
+def test_fullsize_split_banded_solves(full, hbj):
+    """The banded form with every local solve split over 16 runs of column blocks (the launch shape
+    for the sweep steps' batches of a few solves): operator and block-Jacobi preconditioner at
+    1024^2 against the oracle."""
+    from oracle import sweep
+
+    wl, m, dd, _ = full
+    ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=torch.as_tensor(m, device="cuda"), precond=hbj.PC_BJ,
+                    operator_form=hbj.OP_BANDED)
+    ctx.factor()
+    ctx.set_solve_tuning(hbj.SOLVE_SHAPE_SPLIT)
+    ctx.set_solve_partitions(16)
+    gv = W.random_interface_vector(ctx.nif, seed=41)
+    say("[fullsize] split banded solves: operator")
+    w = _np(ctx.apply_operator(torch.as_tensor(gv, device="cuda")))
+    assert rel(w, dd.apply_operator(gv)) < 1e-12
+    r = W.random_interface_vector(ctx.nif, seed=42)
+    say("[fullsize] split banded solves: block-Jacobi preconditioner")
+    z = _np(ctx.apply_preconditioner(torch.as_tensor(r, device="cuda")))
+    ctx.close()
+    assert rel(z, sweep.apply_bj(dd, r)) < 1e-11
+
+
 @pytest.fixture(scope="module")
 def direct_full(full):
     """The oracle's global direct solution u = A^{-1} f of the 1024^2 workload (SuperLU)."""

@@ -1,8 +1,8 @@
 """Autotuned launch shapes of the banded local solves and of the dense operator kernel, through the C ABI.
 
-A batch of banded solves runs in one of four shapes: one workgroup per solve at three register prefetch
-depths (the same arithmetic in the same order: results bit for bit equal), or 16 right-hand sides per
-workgroup on MFMA (equal up to rounding). The autotuner times the candidates on the first batch of each
+A batch of banded solves runs in one of five shapes: one workgroup per solve at three register prefetch
+depths (the same arithmetic in the same order: results bit for bit equal), 16 right-hand sides per
+workgroup on MFMA, or each solve split over runs of column blocks (both equal up to rounding). The autotuner times the candidates on the first batch of each
 class, keeps the fastest and records it in the tuning cache file; a later context reads the decision back
 instead of timing. Every shape is compared with the oracle. The variant of the many-right-hand-side
 operator kernel goes to the same cache.
@@ -46,7 +46,7 @@ def test_every_shape_matches(hbj, name, precision):
     f = _sources(wl, NRHS)
     gt, ft = torch.as_tensor(gv, device="cuda"), torch.as_tensor(f, device="cuda")
     out = {}
-    for shape in range(4):
+    for shape in range(len(hbj.SOLVE_SHAPES)):
         say(f"[solve shape {shape}] case={name} precision={precision}")
         ctx.set_solve_tuning(shape)
         out[shape] = _run(ctx, gt, ft)
@@ -58,7 +58,7 @@ def test_every_shape_matches(hbj, name, precision):
     ctx.close()
     assert tuned, "the autotuner made no decision"
     for key, ch in tuned.items():
-        assert 0 <= ch["shape"] <= 3
+        assert 0 <= ch["shape"] < len(hbj.SOLVE_SHAPES)
     # one workgroup per solve: the prefetch depth changes nothing
     for shape in (1, 2):
         for a, b in zip(out[0], out[shape]):
@@ -69,7 +69,7 @@ def test_every_shape_matches(hbj, name, precision):
     tol = (1e-10 if name == "pivot" else 1e-12) if precision == 0 else (1e-10, 1e-4, 1e-4)
     for i, what in enumerate(("operator", "lifting", "reconstruction")):
         t = tol if np.isscalar(tol) else tol[i]
-        for shape in (0, 3):
+        for shape in (0, 3, 4):
             e = max(rel(out[shape][i][k], ref[i][k]) for k in range(NRHS))
             say(f"  {what}: shape {shape} vs oracle {e:.1e}")
             assert e < t
@@ -128,7 +128,7 @@ def test_no_timing_without_tuning(hbj, monkeypatch):
     for key, ch in t.items():
         assert max(ch["us"]) == 0
         per = int(key.split("|r")[1].split("|")[0])
-        assert ch["shape"] == (3 if key.endswith("|mm") and per >= 8 else 0)
+        assert ch["shape"] == (3 if "|mm|" in key and per >= 8 else 0)
     e = max(rel(w[k], dd.apply_operator(gv[k])) for k in range(NRHS))
     assert e < 1e-12
 
@@ -136,7 +136,7 @@ def test_no_timing_without_tuning(hbj, monkeypatch):
 def test_bad_shape(hbj):
     wl = W.SMALL
     ctx = hbj.setup(wl.nx, wl.ny, wl.k, wl.n1, wl.n2, m=torch.as_tensor(W.slowness2(wl), device="cuda"))
-    for bad in (-2, 4):
+    for bad in (-2, len(hbj.SOLVE_SHAPES)):
         with pytest.raises(hbj.HbjError) as ei:
             ctx.set_solve_tuning(bad)
         assert ei.value.code == hbj.EINVAL
