@@ -274,12 +274,25 @@ hipError_t launch_bwd(const Geom& g, const SolveLayout& L, const Entry* ent, int
 // (formed by launch_part_phi once per factorisation); results as launch_fwd / launch_bwd up to
 // rounding.  rb: the solve buffer (the right-hand sides, then the solutions, as launch_fwd and
 // launch_bwd leave them); y2: the forward results, [entry][nblk nb]; sig, tt: [entry][np][ns]
-// states; phi_f [subdomain][np - 2][kl][kl], phi_b [subdomain][np - 2][kv][kv].
+// states; phi_f [subdomain][np - 2][kl][kl], phi_b [subdomain][np - 2][kv][kv]; pw: the chain's
+// counters.
 struct PartLayout {
   int np;   // runs per solve (>= 2), each nonempty
   int bpp;  // column blocks per run (the last run may be shorter)
   int ns;   // state stride of sig / tt (>= kv)
 };
+// completion counters of the chain launches: two regions of part_chain_counters(entries, np)
+// (a ticket counter per entry, then one counter per entry and run), used by alternate launches
+// (parity, toggled by each launch), each launch zeroing the other region; a failed wait sets *err
+struct PartWait {
+  int32_t* ctr;
+  int nctr;
+  int parity;
+  int32_t* err;
+  int spin;
+};
+constexpr int kChainGridMax = 1024;  // persistent workgroups of a chain launch (about; at least one per entry)
+int part_chain_counters(int nent, int np);
 bool part_fits(const Geom& g, const SolveLayout& L);
 template <typename R>
 hipError_t launch_part_phi(const Geom& g, const SolveLayout& L, const PartLayout& pl,
@@ -291,12 +304,12 @@ hipError_t launch_fwd_part(const Geom& g, const SolveLayout& L, const PartLayout
                            const FaceTab* ft, const IfCoef* coef, const typename Cplx<R>::T* mf, const int16_t* pf,
                            const int32_t* pflag, const typename Cplx<R>::T* phi_f, const SolveIO& io,
                            typename Cplx<R>::T* rb, typename Cplx<R>::T* y2, typename Cplx<R>::T* sig,
-                           typename Cplx<R>::T* tt, hipStream_t st);
+                           typename Cplx<R>::T* tt, PartWait& pw, hipStream_t st);
 template <typename R>
 hipError_t launch_bwd_part(const Geom& g, const SolveLayout& L, const PartLayout& pl, const Entry* ent, int nent,
                            const FaceTab* ft, const IfCoef* coef, const typename Cplx<R>::T* mb,
                            const typename Cplx<R>::T* phi_b, const SolveIO& io, const typename Cplx<R>::T* y2,
-                           typename Cplx<R>::T* rb, typename Cplx<R>::T* sig, typename Cplx<R>::T* tt,
+                           typename Cplx<R>::T* rb, typename Cplx<R>::T* sig, typename Cplx<R>::T* tt, PartWait& pw,
                            hipStream_t st);
 
 // The same solves for tiles of up to 16 entries of one subdomain (tiles[t] = {first entry, count},

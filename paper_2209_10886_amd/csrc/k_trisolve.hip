@@ -850,30 +850,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 // transfer matrices Phi_o (the outgoing state for each unit incoming state and no right-hand side,
 // formed once per factorisation by k_part_phi_*).  Pass 2 reruns every run but the first from its
 // true state and writes its rows.  Each pass reads every factor byte once, on np workgroups.
-// Buffers: rb [entry][nblk nb] the right-hand sides (written by k_part_rhs), yb the results, sig /
-// tt [entry][np][ns] the states, Phi [subdomain][np - 2][S][S] column-major (S = kl or kv).
-
-template <typename C>
-__global__ void k_part_rhs(Geom g, SolveLayout L, const Entry* ent, const FaceTab* ft, const IfCoef* coef, SolveIO io,
-                           C* __restrict__ rb) {
-  const int slot = blockIdx.y, ylen = L.nblk * L.nb;
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= ylen) return;
-  const Entry e = ent[slot];
-  if (io.nz && !io.nz[(size_t)e.rhs * g.n1 * g.n2 + e.s]) return;
-  const FaceTab F = ft[e.s];
-  const RhsCtx rhs(g, e, F, coef, io, slot);
-  rb[(size_t)slot * ylen + l] = to_c<C>(rhs(l));
-}
+// Buffers: rb [entry][nblk nb] the right-hand sides (the first forward pass writes them: run o the
+// rows it reads, up to kl + nb rows into run o + 1, which writes the same values, and a workgroup
+// for the last run only its rows; building them inside the passes' prefetch path instead doubled
+// the passes' time), yb the results, sig / tt [entry][np][ns] the states, Phi
+// [subdomain][np - 2][S][S] column-major (S = kl or kv).
 
 template <typename R, int NB, int CG, int D>
 __global__ __launch_bounds__(576) void k_fwd_part(Geom g, SolveLayout L, PartLayout pl, int phase, const Entry* ent,
-                                                  const int32_t* __restrict__ nzf,
+                                                  const FaceTab* ft, const IfCoef* coef, SolveIO io,
                                                   const typename Cplx<R>::T* __restrict__ MF,
                                                   const int16_t* __restrict__ PF, const int32_t* __restrict__ PFL,
-                                                  const typename Cplx<R>::T* __restrict__ rb,
-                                                  typename Cplx<R>::T* __restrict__ yb, typename Cplx<R>::T* sig,
-                                                  typename Cplx<R>::T* tt) {
+                                                  typename Cplx<R>::T* rb, typename Cplx<R>::T* __restrict__ yb,
+                                                  typename Cplx<R>::T* sig, typename Cplx<R>::T* tt) {
   typedef typename Cplx<R>::T C;
   constexpr int NC = NB / CG;
   extern __shared__ unsigned char smem_raw[];
@@ -884,11 +873,19 @@ __global__ __launch_bounds__(576) void k_fwd_part(Geom g, SolveLayout L, PartLay
   const int slot = blockIdx.x;
   const int o = phase == 1 ? (int)blockIdx.y : (int)blockIdx.y + 1;
   const Entry e = ent[slot];
-  if (nzf && !nzf[(size_t)e.rhs * g.n1 * g.n2 + e.s]) return;  // zero right-hand side: x = 0
+  if (io.nz && !io.nz[(size_t)e.rhs * g.n1 * g.n2 + e.s]) return;  // zero right-hand side: x = 0
   const int b0 = o * pl.bpp, b1 = min(b0 + pl.bpp, nblk);
   const int ylen = nblk * NB;
-  const C* rhs = rb + (size_t)slot * ylen;
+  C* rhs = rb + (size_t)slot * ylen;
   C* y = yb + (size_t)slot * ylen;
+  if (phase == 1) {  // the right-hand-side rows this run reads (the last run: its own rows only)
+    const FaceTab F = ft[e.s];
+    const RhsCtx rc(g, e, F, coef, io, slot);
+    const int hi = o == pl.np - 1 ? ylen : min(b1 * NB + kl + NB, ylen);
+    for (int l = b0 * NB + tid; l < hi; l += nt) rhs[l] = to_c<C>(rc(l));
+    if (o == pl.np - 1) return;
+    __syncthreads();
+  }
   const bool outs = phase == 3 || o == 0;
   const C* M = MF + (size_t)e.s * L.mf_per_sub;
   const int16_t* P = PF + (size_t)e.s * L.pf_per_sub;
@@ -1076,49 +1073,125 @@ __global__ __launch_bounds__(576) void k_bwd_part(Geom g, SolveLayout L, PartLay
     }
 }
 
-// The chain of one entry per workgroup: tt[o + 1] = sig[o] + Phi_o tt[o] for o = 1 .. np - 2, the
-// state in LDS; thread (group gi, row i) sums the columns j = gi, gi + G, ... of row i (loads along
-// a column of Phi are contiguous across the threads of a group).
-constexpr int kPartChainThreads = 1024, kPartStateMax = 576;
+// The chain: tt[o + 1] = sig[o] + Phi_o tt[o] for o = 1 .. np - 2 and every entry.  Each step's
+// product is split into tasks of kChainRows rows of tt[o + 1].  The persistent workgroups of an
+// entry (blockIdx.x % nent) claim its tasks from the entry's ticket counter in step order (a
+// single counter for all entries made the claims contend).  A task first loads its rows of Phi_o
+// (they depend on no data), then waits until the tasks of step o - 1 of its entry have all
+// published (a completion counter per entry and step), reads tt[o], and publishes its rows.  A
+// task only waits for tasks of its entry with smaller tickets, claimed by workgroups that are
+// running, so the launch completes whatever the number of resident workgroups; every wait is
+// bounded (past spin_limit polls the error flag is set and the task goes on).  The states
+// that tasks of one launch exchange are written and read with device-coherent accesses; the
+// producing wavefront waits for its stores to complete before the counter moves.
+constexpr int kPartStateMax = 576, kChainRows = 16, kChainThreads = 256, kChainU = 16;
+
+__device__ inline void st_coh(double2* p, double2 v) {
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+  __hip_atomic_store(q, (unsigned long long)__double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 1, (unsigned long long)__double_as_longlong(v.y), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double2 ld_coh(const double2* p) {
+  const unsigned long long* q = reinterpret_cast<const unsigned long long*>(p);
+  const unsigned long long a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return mk(__longlong_as_double((long long)a), __longlong_as_double((long long)b));
+}
+__device__ inline void st_coh(float2* p, float2 v) {
+  const unsigned long long b = (unsigned long long)(unsigned)__float_as_int(v.x) |
+                               ((unsigned long long)(unsigned)__float_as_int(v.y) << 32);
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline float2 ld_coh(const float2* p) {
+  const unsigned long long b =
+      __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return make_float2(__int_as_float((int)(unsigned)(b & 0xffffffffull)), __int_as_float((int)(unsigned)(b >> 32)));
+}
+
 template <typename C>
-__global__ __launch_bounds__(kPartChainThreads) void k_part_chain(Geom g, PartLayout pl, int S, const Entry* ent,
-                                                                  const int32_t* __restrict__ nzf,
-                                                                  const C* __restrict__ phi, const C* sig, C* tt) {
-  __shared__ C ts[2][kPartStateMax];
-  __shared__ C red[kPartChainThreads];
-  const int slot = blockIdx.x, tid = threadIdx.x;
-  const Entry e = ent[slot];
-  if (nzf && !nzf[(size_t)e.rhs * g.n1 * g.n2 + e.s]) return;
-  const int G = max(1, kPartChainThreads / S);
-  const int gi = tid / S, i = tid - gi * S;
-  for (int q = tid; q < S; q += kPartChainThreads) ts[0][q] = tt[((size_t)slot * pl.np + 1) * pl.ns + q];
-  __syncthreads();
-  int cur = 0;
-  for (int o = 1; o <= pl.np - 2; ++o) {
+__global__ __launch_bounds__(kChainThreads) void k_part_chain(Geom g, PartLayout pl, int S, const Entry* ent,
+                                                              int nent, const int32_t* __restrict__ nzf,
+                                                              const C* __restrict__ phi, const C* sig, C* tt,
+                                                              int32_t* ctr, int32_t* ctr_next, int nctr, int32_t* err,
+                                                              int spin_limit) {
+  // the other counter region is zeroed here for the next launch (it is not used by this one)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nctr; i += gridDim.x * blockDim.x) ctr_next[i] = 0;
+  constexpr int NG = kChainThreads / kChainRows;  // column groups
+  __shared__ int s_ticket;
+  __shared__ C ts[kPartStateMax];
+  __shared__ C red[kChainThreads];
+  const int tid = threadIdx.x, ri = tid % kChainRows, jg = tid / kChainRows;
+  const int W = (S + kChainRows - 1) / kChainRows;  // tasks per step and entry
+  const int ntasks = (pl.np - 2) * W;               // per entry
+  const int slot = blockIdx.x % nent;
+  int32_t* done = ctr + nent;  // [entry][np], after the entries' ticket counters
+  for (;;) {
+    // uniform loop: the ticket goes through LDS and is read back as a scalar
+    __syncthreads();  // the previous task no longer reads s_ticket, ts or red
+    if (tid == 0) s_ticket = __hip_atomic_fetch_add(ctr + slot, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(s_ticket);
+    if (t < 0 || t >= ntasks) break;
+    const int o = 1 + t / W, w = t - (o - 1) * W;
+    const Entry e = ent[slot];
+    const bool live = !(nzf && !nzf[(size_t)e.rhs * g.n1 * g.n2 + e.s]);
+    const int i = w * kChainRows + ri;
+    const bool rowok = i < S;
+    // 1. this task's rows of Phi_o, the first kChainU columns of each group (independent of the data)
     const C* F = phi + ((size_t)e.s * (pl.np - 2) + (o - 1)) * S * S;
-    C a0 = czero<C>(), a1 = czero<C>(), a2 = czero<C>(), a3 = czero<C>();
-    if (gi < G) {
-      int j = gi;
-      for (; j + 3 * G < S; j += 4 * G) {
-        const C f0 = F[(size_t)j * S + i], f1 = F[(size_t)(j + G) * S + i];
-        const C f2 = F[(size_t)(j + 2 * G) * S + i], f3 = F[(size_t)(j + 3 * G) * S + i];
-        cfma(a0, f0, ts[cur][j]);
-        cfma(a1, f1, ts[cur][j + G]);
-        cfma(a2, f2, ts[cur][j + 2 * G]);
-        cfma(a3, f3, ts[cur][j + 3 * G]);
+    C f[kChainU];
+#pragma unroll
+    for (int u = 0; u < kChainU; ++u) {
+      const int j = jg + NG * u;
+      f[u] = (live && rowok && j < S) ? F[(size_t)j * S + i] : czero<C>();
+    }
+    // 2. wait for the tasks of step o - 1 of this entry
+    if (tid == 0 && o >= 2 && live) {
+      int polls = 0;
+      while (__hip_atomic_load(done + (size_t)slot * pl.np + (o - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+             W) {
+        if (++polls > spin_limit) {
+          __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        if ((polls & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+        __builtin_amdgcn_s_sleep(2);
       }
-      for (; j < S; j += G) cfma(a0, F[(size_t)j * S + i], ts[cur][j]);
-    }
-    red[tid] = cadd(cadd(a0, a1), cadd(a2, a3));
-    __syncthreads();
-    if (tid < S) {
-      C v = sig[((size_t)slot * pl.np + o) * pl.ns + tid];
-      for (int q = 0; q < G; ++q) v = cadd(v, red[q * S + tid]);
-      ts[cur ^ 1][tid] = v;
-      tt[((size_t)slot * pl.np + o + 1) * pl.ns + tid] = v;
     }
     __syncthreads();
-    cur ^= 1;
+    // 3. tt[o] into LDS, then this task's rows of Phi_o tt[o]
+    if (live)
+      for (int q = tid; q < S; q += kChainThreads) ts[q] = ld_coh(tt + ((size_t)slot * pl.np + o) * pl.ns + q);
+    __syncthreads();
+    C acc = czero<C>();
+    if (live) {
+#pragma unroll
+      for (int u = 0; u < kChainU; ++u) {
+        const int j = jg + NG * u;
+        if (j < S) cfma(acc, f[u], ts[j]);
+      }
+      for (int j0 = NG * kChainU; j0 < S; j0 += NG * kChainU) {  // windows wider than 256 rows
+#pragma unroll
+        for (int u = 0; u < kChainU; ++u) {
+          const int j = j0 + jg + NG * u;
+          if (rowok && j < S) cfma(acc, F[(size_t)j * S + i], ts[j]);
+        }
+      }
+    }
+    red[tid] = acc;
+    __syncthreads();
+    // 4. publish: the rows (wavefront 0), then the completion counter
+    if (tid < 64) {
+      if (tid < kChainRows && live && rowok) {
+        C v = sig[((size_t)slot * pl.np + o) * pl.ns + i];
+        for (int q = 0; q < NG; ++q) v = cadd(v, red[q * kChainRows + tid]);
+        st_coh(tt + ((size_t)slot * pl.np + o + 1) * pl.ns + i, v);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_s_waitcnt(0);
+      if (tid == 0) __hip_atomic_fetch_add(done + (size_t)slot * pl.np + o, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
@@ -1480,26 +1553,43 @@ hipError_t launch_part_phi(const Geom& g, const SolveLayout& L, const PartLayout
   return hipGetLastError();
 }
 
+int part_chain_counters(int nent, int np) { return nent * (np + 1); }
+
+// one chain launch: counters of region pw.parity (zeroed by the previous launch or at allocation),
+// the other region zeroed for the next one; per entry, workgroups for two steps' tasks
+template <typename C>
+static hipError_t launch_chain(const Geom& g, const PartLayout& pl, int S, const Entry* ent, int nent,
+                               const int32_t* nz, const C* phi, const C* sig, C* tt, PartWait& pw, hipStream_t st) {
+  if (S > kPartStateMax || pw.nctr < part_chain_counters(nent, pl.np)) return hipErrorInvalidValue;
+  const int W = (S + kChainRows - 1) / kChainRows;
+  const int per = std::max(1, std::min(std::min((pl.np - 2) * W, 2 * W), kChainGridMax / std::max(nent, 1)));
+  const int grid = nent * per;
+  int32_t* cur = pw.ctr + (size_t)pw.parity * pw.nctr;
+  int32_t* nxt = pw.ctr + (size_t)(1 - pw.parity) * pw.nctr;
+  hipLaunchKernelGGL(k_part_chain<C>, dim3(grid), dim3(kChainThreads), 0, st, g, pl, S, ent, nent, nz, phi, sig, tt,
+                     cur, nxt, pw.nctr, pw.err, pw.spin);
+  pw.parity ^= 1;
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_fwd_part(const Geom& g, const SolveLayout& L, const PartLayout& pl, const Entry* ent, int nent,
                            const FaceTab* ft, const IfCoef* coef, const typename Cplx<R>::T* mf, const int16_t* pf,
                            const int32_t* pflag, const typename Cplx<R>::T* phi_f, const SolveIO& io,
                            typename Cplx<R>::T* rb, typename Cplx<R>::T* y2, typename Cplx<R>::T* sig,
-                           typename Cplx<R>::T* tt, hipStream_t st) {
+                           typename Cplx<R>::T* tt, PartWait& pw, hipStream_t st) {
   typedef typename Cplx<R>::T C;
   if (nent == 0) return hipSuccess;
   if (!part_fits(g, L) || pl.np < 2 || pl.bpp < 1 || (pl.np - 1) * pl.bpp >= L.nblk || pl.ns < g.kv)
     return hipErrorInvalidValue;
-  const int ylen = L.nblk * L.nb;
-  hipLaunchKernelGGL(k_part_rhs<C>, dim3((ylen + 255) / 256, nent), dim3(256), 0, st, g, L, ent, ft, coef, io, rb);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
   const size_t shm = 2 * (size_t)L.wf * sizeof(C) + (size_t)pl.bpp * sizeof(int);
-  const dim3 grid(nent, pl.np - 1), blk(((L.wf * L.cgf + 63) / 64) * 64);
+  const dim3 blk(((L.wf * L.cgf + 63) / 64) * 64);
   for (int phase = 1; phase <= 3; phase += 2) {
-#define HBJ_FWDP(CG, D)                                                                                          \
-  hipLaunchKernelGGL((k_fwd_part<R, 16, CG, D>), grid, blk, shm, st, g, L, pl, phase, ent, io.nz, mf, pf, pflag, \
-                     (const C*)rb, y2, sig, tt)
+    const dim3 grid(nent, phase == 1 ? pl.np : pl.np - 1);  // pass 1: also the last run's right-hand side
+#define HBJ_FWDP(CG, D)                                                                                         \
+  hipLaunchKernelGGL((k_fwd_part<R, 16, CG, D>), grid, blk, shm, st, g, L, pl, phase, ent, ft, coef, io, mf, pf, \
+                     pflag, rb, y2, sig, tt)
     if (L.cgf == 4) {
       if constexpr (sizeof(R) == 8) HBJ_FWDP(4, 5);
       else HBJ_FWDP(4, 8);
@@ -1510,9 +1600,7 @@ hipError_t launch_fwd_part(const Geom& g, const SolveLayout& L, const PartLayout
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (phase == 1 && pl.np > 2) {
-      hipLaunchKernelGGL(k_part_chain<C>, dim3(nent), dim3(kPartChainThreads), 0, st, g, pl, g.kl, ent, io.nz, phi_f,
-                         (const C*)sig, tt);
-      e = hipGetLastError();
+      e = launch_chain<C>(g, pl, g.kl, ent, nent, io.nz, phi_f, sig, tt, pw, st);
       if (e != hipSuccess) return e;
     }
   }
@@ -1523,7 +1611,7 @@ template <typename R>
 hipError_t launch_bwd_part(const Geom& g, const SolveLayout& L, const PartLayout& pl, const Entry* ent, int nent,
                            const FaceTab* ft, const IfCoef* coef, const typename Cplx<R>::T* mb,
                            const typename Cplx<R>::T* phi_b, const SolveIO& io, const typename Cplx<R>::T* y2,
-                           typename Cplx<R>::T* rb, typename Cplx<R>::T* sig, typename Cplx<R>::T* tt,
+                           typename Cplx<R>::T* rb, typename Cplx<R>::T* sig, typename Cplx<R>::T* tt, PartWait& pw,
                            hipStream_t st) {
   typedef typename Cplx<R>::T C;
   if (nent == 0) return hipSuccess;
@@ -1546,9 +1634,7 @@ hipError_t launch_bwd_part(const Geom& g, const SolveLayout& L, const PartLayout
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (phase == 1 && pl.np > 2) {
-      hipLaunchKernelGGL(k_part_chain<C>, dim3(nent), dim3(kPartChainThreads), 0, st, g, pl, g.kv, ent, io.nz, phi_b,
-                         (const C*)sig, tt);
-      e = hipGetLastError();
+      e = launch_chain<C>(g, pl, g.kv, ent, nent, io.nz, phi_b, sig, tt, pw, st);
       if (e != hipSuccess) return e;
     }
   }
@@ -1560,10 +1646,10 @@ hipError_t launch_bwd_part(const Geom& g, const SolveLayout& L, const PartLayout
                                          const int32_t*, const C*, C*, C*, int, hipStream_t);                        \
   template hipError_t launch_fwd_part<R>(const Geom&, const SolveLayout&, const PartLayout&, const Entry*, int,        \
                                          const FaceTab*, const IfCoef*, const C*, const int16_t*, const int32_t*,      \
-                                         const C*, const SolveIO&, C*, C*, C*, C*, hipStream_t);                      \
+                                         const C*, const SolveIO&, C*, C*, C*, C*, PartWait&, hipStream_t);           \
   template hipError_t launch_bwd_part<R>(const Geom&, const SolveLayout&, const PartLayout&, const Entry*, int,        \
                                          const FaceTab*, const IfCoef*, const C*, const C*, const SolveIO&, const C*,  \
-                                         C*, C*, C*, hipStream_t);
+                                         C*, C*, C*, PartWait&, hipStream_t);
 HBJ_PART_INST(double, double2)
 HBJ_PART_INST(float, float2)
 #undef HBJ_PART_INST

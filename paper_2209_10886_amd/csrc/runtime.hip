@@ -228,6 +228,10 @@ struct hbj_ctx {
   size_t part_y2_bytes = 0;
   void* part_st = nullptr;
   size_t part_st_bytes = 0;
+  int32_t* part_ctr = nullptr;  // chain completion counters (two regions) and their wait error flag
+  int part_nctr = 0;
+  int part_parity = 0;
+  int32_t* part_err = nullptr;
   std::string arch;            // device architecture name (cache keys)
   int32_t* nzf = nullptr;   // per (rhs, subdomain) nonzero-source flags for the lifting
   size_t nzf_cap = 0;
@@ -324,6 +328,8 @@ hbj_ctx::~hbj_ctx() {
   dfree(phi[1]);
   dfree(part_y2);
   dfree(part_st);
+  dfree(part_ctr);
+  dfree(part_err);
 }
 
 namespace {
@@ -720,6 +726,22 @@ hipError_t ensure_part(hbj_ctx* c, int nent, const typename Cplx<R>::T* mf, cons
   };
   hipError_t e = grow(&c->part_y2, &c->part_y2_bytes, (size_t)nent * ylen * sizeof(C));
   if (e == hipSuccess) e = grow(&c->part_st, &c->part_st_bytes, 2 * (size_t)nent * pl.np * pl.ns * sizeof(C));
+  if (e == hipSuccess && !c->part_err) {
+    e = hipMalloc((void**)&c->part_err, sizeof(int32_t));
+    if (e == hipSuccess) e = launch_fill_zero(c->part_err, sizeof(int32_t), c->st);
+  }
+  const int nctr = part_chain_counters(nent, pl.np);
+  if (e == hipSuccess && nctr > c->part_nctr) {  // both regions zero, for the next two launches
+    dfree(c->part_ctr);
+    c->part_ctr = nullptr;
+    c->part_nctr = 0;
+    e = hipMalloc((void**)&c->part_ctr, 2 * (size_t)nctr * sizeof(int32_t));
+    if (e == hipSuccess) e = launch_fill_zero(c->part_ctr, 2 * (size_t)nctr * sizeof(int32_t), c->st);
+    if (e == hipSuccess) {
+      c->part_nctr = nctr;
+      c->part_parity = 0;
+    }
+  }
   if (e != hipSuccess || part_ready(c, sizeof(R))) return e;
   const int pi = sizeof(R) == 8 ? 0 : 1;
   const size_t kl = c->g.kl, kv = c->g.kv, nf = (size_t)c->ndom * (pl.np - 2) * kl * kl;
@@ -753,15 +775,19 @@ hipError_t solve_pair_shape(hbj_ctx* c, int shape, const Entry* ent, int nent, c
     const C* phi_b = phi_f ? phi_f + nf : nullptr;
     C* sig = (C*)c->part_st;
     C* tt = sig + (size_t)nent * pl.np * pl.ns;
+    PartWait pw{c->part_ctr, c->part_nctr, c->part_parity, c->part_err, c->df_spin};
     {
       ProfScope ps(c, HBJ_K_FWD, nread * fwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * c->g.kl, prof);
       e = launch_fwd_part<R>(c->g, c->L, pl, ent, nent, c->ft, c->coef, mf, c->pf, c->pflag, phi_f, io, (C*)c->ybuf,
-                             (C*)c->part_y2, sig, tt, c->st);
+                             (C*)c->part_y2, sig, tt, pw, c->st);
     }
+    c->part_parity = pw.parity;
     if (e != hipSuccess) return e;
     ProfScope ps(c, HBJ_K_BWD, nread * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1), prof);
-    return launch_bwd_part<R>(c->g, c->L, pl, ent, nent, c->ft, c->coef, mb, phi_b, io, (const C*)c->part_y2,
-                              (C*)c->ybuf, sig, tt, c->st);
+    e = launch_bwd_part<R>(c->g, c->L, pl, ent, nent, c->ft, c->coef, mb, phi_b, io, (const C*)c->part_y2,
+                           (C*)c->ybuf, sig, tt, pw, c->st);
+    c->part_parity = pw.parity;
+    return e;
   }
   {
     ProfScope ps(c, HBJ_K_FWD, nread * fwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * c->g.kl, prof);
@@ -1296,8 +1322,24 @@ int run_df(hbj_ctx* c, Schedule* S, int kind, const DfArgs& A, const C* T) {
   return HBJ_OK;
 }
 
-// dependency-wait failures of earlier dataflow launches (synchronises the stream)
+// wait failures of earlier chain launches of split solves (synchronises the stream)
+int part_check(hbj_ctx* c) {
+  if (!c->part_err) return HBJ_OK;
+  int32_t e = 0;
+  HIPCHK(hipMemcpyAsync(&e, c->part_err, sizeof(e), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  if (!e) return HBJ_OK;
+  HIPCHK(launch_fill_zero(c->part_err, sizeof(int32_t), c->st));
+  if (c->part_ctr) HIPCHK(launch_fill_zero(c->part_ctr, 2 * (size_t)c->part_nctr * sizeof(int32_t), c->st));
+  c->part_parity = 0;
+  HIPCHK(hipStreamSynchronize(c->st));
+  return fail(HBJ_EWAIT, "split local solves: a wait of the transfer chain exceeded its poll limit");
+}
+
+// dependency-wait failures of earlier dataflow launches and split solves (synchronises the stream)
 int df_check(hbj_ctx* c) {
+  const int rp = part_check(c);
+  if (rp) return rp;
   if (!c->df_err) return HBJ_OK;
   int32_t e = 0;
   HIPCHK(hipMemcpyAsync(&e, c->df_err, sizeof(e), hipMemcpyDeviceToHost, c->st));
@@ -2876,7 +2918,7 @@ int hbj_apply_operator(hbj_ctx* c, const hbj_c128* g, hbj_c128* out, int32_t nrh
   rc = build_schedule(c, nrhs, &S);
   if (rc) return rc;
   rc = op_apply(c, S, (const double2*)g, (double2*)out);
-  if (rc == HBJ_OK && df_enabled(c, S)) rc = df_check(c);
+  if (rc == HBJ_OK && (df_enabled(c, S) || c->part_err)) rc = df_check(c);
   return rc;
 }
 
@@ -2888,7 +2930,7 @@ int hbj_apply_preconditioner(hbj_ctx* c, const hbj_c128* r, hbj_c128* z, int32_t
   rc = build_schedule(c, nrhs, &S);
   if (rc) return rc;
   rc = precond(c, S, (const double2*)r, (double2*)z, nrhs);
-  if (rc == HBJ_OK && df_enabled(c, S)) rc = df_check(c);
+  if (rc == HBJ_OK && (df_enabled(c, S) || c->part_err)) rc = df_check(c);
   return rc;
 }
 
@@ -2900,7 +2942,9 @@ int hbj_lifting(hbj_ctx* c, const hbj_c128* f, hbj_c128* b, int32_t nrhs) {
   rc = build_schedule(c, nrhs, &S);
   if (rc) return rc;
   if (c->g.nif == 0) return HBJ_OK;
-  return run_lifting(c, S, (const double2*)f, (double2*)b, nrhs);
+  rc = run_lifting(c, S, (const double2*)f, (double2*)b, nrhs);
+  if (rc == HBJ_OK && c->part_err) rc = part_check(c);
+  return rc;
 }
 
 int hbj_reconstruct(hbj_ctx* c, const hbj_c128* f, const hbj_c128* g, hbj_c128* u, int32_t nrhs) {
@@ -2910,7 +2954,9 @@ int hbj_reconstruct(hbj_ctx* c, const hbj_c128* f, const hbj_c128* g, hbj_c128* 
   Schedule* S;
   rc = build_schedule(c, nrhs, &S);
   if (rc) return rc;
-  return run_reconstruct(c, S, (const double2*)f, (const double2*)g, (double2*)u, nrhs, false);
+  rc = run_reconstruct(c, S, (const double2*)f, (const double2*)g, (double2*)u, nrhs, false);
+  if (rc == HBJ_OK && c->part_err) rc = part_check(c);
+  return rc;
 }
 
 static int solve_impl(hbj_ctx* c, const double2* f, double2* u, int nrhs, const hbj_solve_opts* opts,

@@ -227,6 +227,30 @@ def test_layout_covers_every_block_once():
             assert all(o * bpp < min(o * bpp + bpp, nblk) for o in range(npart))
 
 
+def test_first_pass_writes_every_right_hand_side_row_it_reads():
+    """Pass 1 of the forward solve writes the right-hand sides: run o the rows [b0 nb, b1 nb + kl +
+    nb) before it reads them (the rows of its window and the rows entering it), the last run its own
+    rows; together every row, so that pass 2 finds them all."""
+    for nblk in (2, 3, 7, 64, 1024):
+        for kl in (8, 32, 128):
+            ylen = nblk * NB
+            for req in (2, 3, 5, 16, 64):
+                npart, bpp = layout(nblk, req)
+                covered = set()
+                for o in range(npart):
+                    b0, b1 = o * bpp, min(o * bpp + bpp, nblk)
+                    hi = ylen if o == npart - 1 else min(b1 * NB + kl + NB, ylen)
+                    mine = set(range(b0 * NB, hi))
+                    covered |= mine
+                    if o == npart - 1:
+                        continue
+                    reads = {r for r in range(b0 * NB, b0 * NB + kl + NB) if r < ylen}  # initial window
+                    for b in range(b0, b1):
+                        reads |= {r for r in range((b + 1) * NB + kl, (b + 2) * NB + kl) if r < ylen}
+                    assert reads <= mine, (nblk, kl, req, o)
+                assert covered == set(range(ylen))
+
+
 def test_partitioned_forward_and_backward_match_sequential():
     rng = np.random.default_rng(7)
     for nblk, kl, ku in ((9, 32, 32), (7, 16, 16), (12, 48, 24), (5, 8, 8)):
@@ -276,7 +300,43 @@ def test_kernel_source_matches_the_replay():
                  "const int row = (b1 - 1) * NB - kv + q;",
                  "min(b + D, b1 - 1)", "max(b - D, b0)",
                  "C* dst = o == 0 ? tt + ((size_t)slot * pl.np + 1) * pl.ns : sig + ((size_t)slot * pl.np + o) * pl.ns;",
-                 "((size_t)e.s * (pl.np - 2) + (o - 1)) * S * S"):
+                 "((size_t)e.s * (pl.np - 2) + (o - 1)) * S * S",
+                 "const int o = 1 + t / W, w = t - (o - 1) * W;", "const int slot = blockIdx.x % nent;",
+                 "int32_t* done = ctr + nent;", "kChainRows = 16", "done + (size_t)slot * pl.np + (o - 1)",
+                 "const int ntasks = (pl.np - 2) * W;",
+                 "const int hi = o == pl.np - 1 ? ylen : min(b1 * NB + kl + NB, ylen);",
+                 "int part_chain_counters(int nent, int np) { return nent * (np + 1); }",
+                 "std::max(1, std::min(std::min((pl.np - 2) * W, 2 * W), kChainGridMax / std::max(nent, 1)))"):
         assert frag in src, frag
     for frag in ("int bpp = (nblk + np - 1) / np;", "np = (nblk + bpp - 1) / bpp;"):
         assert frag in rt, frag
+
+
+def test_chain_tickets_wait_only_for_smaller_tickets():
+    """The chain's tasks: the workgroups of entry blockIdx % nent claim ticket t of the entry's
+    counter -> (step o, row slice w) in step order; a task of step o waits for all W tasks of step
+    o - 1 of its entry, which must all hold smaller tickets of the same counter (the launch then
+    completes whatever the number of resident workgroups), every entry has a workgroup, and every
+    task's rows and counters stay in their buffers."""
+    rows_per_task, grid_max = 16, 1024
+    for nent in (1, 7, 8, 64, 200):
+        for npart in (3, 4, 16):
+            for S in (10, 16, 128, 256, 560):
+                W = (S + rows_per_task - 1) // rows_per_task
+                ntasks = (npart - 2) * W
+                nctr = nent * (npart + 1)
+                per = max(1, min(min(ntasks, 2 * W), grid_max // max(nent, 1)))
+                grid = nent * per
+                assert {b % nent for b in range(grid)} == set(range(nent))
+                for slot in (0, nent - 1):
+                    assert slot < nctr  # the entry's ticket counter
+                    ticket = {}
+                    for t in range(ntasks):
+                        o, w = 1 + t // W, t % W
+                        assert 1 <= o <= npart - 2 and 0 <= w < W
+                        ticket[(o, w)] = t
+                        assert nent + slot * npart + o < nctr  # its completion counter
+                        assert w * rows_per_task < S
+                    for (o, w), t in ticket.items():
+                        if o >= 2:
+                            assert all(ticket[(o - 1, ww)] < t for ww in range(W))
