@@ -456,14 +456,18 @@ def relerr(a, b):
 
 
 def kernel_names(hbj, many):
-    # the one-workgroup-per-solve kernels run at the autotuned prefetch depth D (the legs report the
-    # choices under "solve_tuning")
-    names64 = {hbj.K_FWD: "k_fwd<double,16,4,D>", hbj.K_BWD: "k_bwd<double,16,2,D>",
+    # the banded substitutions run in the autotuned launch shape (the legs report the choices under
+    # "solve_tuning"): one workgroup per solve at prefetch depth D, or split over runs of column
+    # blocks (two passes and the transfer chain; the class's bytes are still those of one sequential
+    # substitution per solve)
+    names64 = {hbj.K_FWD: "forward substitution (k_fwd<double,16,4,D> or k_fwd_part+k_part_chain)",
+               hbj.K_BWD: "backward substitution (k_bwd<double,16,2,D> or k_bwd_part+k_part_chain)",
                hbj.K_SCATTER: "k_scatter_apply<double2> (sweep steps)",
                hbj.K_OPERATOR: "k_scatter_apply<double2> (operator)",
                hbj.K_SWEEP: "k_sweep_df<double2,16>", hbj.K_LIFT: "k_lift_partial+k_recon_dense",
                hbj.K_KRYLOV: "krylov (Gram-Schmidt kernels of one iteration)"}
-    names32 = {hbj.K_FWD: "k_fwd<float,16,4,D>", hbj.K_BWD: "k_bwd<float,16,2,D>",
+    names32 = {hbj.K_FWD: "forward substitution (k_fwd<float,16,4,D> or k_fwd_part+k_part_chain)",
+               hbj.K_BWD: "backward substitution (k_bwd<float,16,2,D> or k_bwd_part+k_part_chain)",
                hbj.K_SCATTER: "k_scatter_apply<float2> (sweep steps)",
                hbj.K_OPERATOR: "k_scatter_apply<double2> (operator)",
                hbj.K_SWEEP: "k_sweep_df", hbj.K_LIFT: "k_lift_partial+k_recon_dense",
@@ -579,8 +583,9 @@ def gradient_leg(hbj, reps=2):
 
 
 def banded_legs(hbj, wl, mt, ft, u, tol, names64, names32, u_ref, mixed=True):
-    """GMRES with a banded local solve per application of every operator (one workgroup per
-    subdomain solve): FP64, and complex64 factors with FP64-refined operator solves."""
+    """GMRES with a banded local solve per application of every operator (in the autotuned launch
+    shape: one workgroup per subdomain solve, or each solve split over runs of column blocks): FP64,
+    and complex64 factors with FP64-refined operator solves."""
     out = {}
     log("[bench] FP64, banded local solves inside GMRES")
     br = run_form(hbj, wl, mt, ft, u, hbj.FP64, hbj.OP_BANDED, 1, 0, tol, names64)

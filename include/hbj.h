@@ -494,7 +494,7 @@ int hbj_get_tuning(const hbj_ctx* ctx, int32_t* variants, float* us);
  *            run but the first is solved again from its true state.  About twice the factor
  *            bytes of shapes 0-2, spread over np times the workgroups: for batches of few solves
  *            (a sweep step of a few subdomains), where one workgroup per solve leaves most of the
- *            device idle.
+ *            device idle.  Timed only for batches of at most two right-hand sides per subdomain.
  * All give the same solutions up to rounding (shapes 0-2 bit for bit).  On the first batch of
  * each class - precision, subdomain size and band, number of solves (by powers of two) and
  * right-hand sides per subdomain (1, 2-3, 4-7, 8-15, 16) - the library times every candidate

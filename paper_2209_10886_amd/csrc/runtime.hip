@@ -843,7 +843,10 @@ int time_solve_shapes(hbj_ctx* c, const Entry* ent, int nent, const int2* tiles,
   tio.tr_dst = nullptr;
   bool alive[kSolveShapes];
   float first[kSolveShapes] = {}, tot[kSolveShapes] = {};
-  for (int v = 0; v < kSolveShapes; ++v) alive[v] = (v != kShapeMfma || mm_ok) && (v != kShapePart || part_ok(c));
+  // the split solves are candidates for batches of one or two right-hand sides per subdomain (many right-hand
+  // sides per subdomain fill the device on MFMA; their transfer matrices would only cost memory and time)
+  const bool split_ok = part_ok(c) && (!mm_ok || per_tile(nent, ntiles) <= 2);
+  for (int v = 0; v < kSolveShapes; ++v) alive[v] = (v != kShapeMfma || mm_ok) && (v != kShapePart || split_ok);
   if (alive[kShapePart]) HIPCHK(ensure_part<R>(c, nent, mf, mb));  // formed once, outside the timings
   auto timed = [&](int v, float* ms) -> hipError_t {
     hipError_t e = hipEventRecord(c->ev0, c->st);
