@@ -281,9 +281,9 @@ struct PartLayout {
   int bpp;  // column blocks per run (the last run may be shorter)
   int ns;   // state stride of sig / tt (>= kv)
 };
-// completion counters of the chain launches: two regions of part_chain_counters(entries, np)
-// (a ticket counter per entry, then one counter per entry and run), used by alternate launches
-// (parity, toggled by each launch), each launch zeroing the other region; a failed wait sets *err
+// ticket counters of the chain launches: two regions of part_chain_counters(entries, np) (one
+// per entry), used by alternate launches (parity, toggled by each launch), each launch zeroing
+// the other region; a failed wait sets *err
 struct PartWait {
   int32_t* ctr;
   int nctr;

@@ -856,6 +856,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 // the passes' time), yb the results, sig / tt [entry][np][ns] the states, Phi
 // [subdomain][np - 2][S][S] column-major (S = kl or kv).
 
+// Chain states not yet written hold a signalling-NaN bit pattern, which no arithmetic result has
+// (operations return quiet NaNs): the chain's tasks poll their input state until no entry holds it.
+constexpr unsigned long long kUnset64 = 0x7FF4A5A5A5A5A5A5ull;
+constexpr unsigned kUnset32 = 0x7FA5A5A5u;
+__device__ inline void set_unset(double2& v) {
+  v.x = __longlong_as_double((long long)kUnset64);
+  v.y = v.x;
+}
+__device__ inline void set_unset(float2& v) {
+  v.x = __int_as_float((int)kUnset32);
+  v.y = v.x;
+}
+__device__ inline bool is_unset(double2 v) {
+  return (unsigned long long)__double_as_longlong(v.x) == kUnset64 ||
+         (unsigned long long)__double_as_longlong(v.y) == kUnset64;
+}
+__device__ inline bool is_unset(float2 v) {
+  return (unsigned)__float_as_int(v.x) == kUnset32 || (unsigned)__float_as_int(v.y) == kUnset32;
+}
+
 template <typename R, int NB, int CG, int D>
 __global__ __launch_bounds__(576) void k_fwd_part(Geom g, SolveLayout L, PartLayout pl, int phase, const Entry* ent,
                                                   const FaceTab* ft, const IfCoef* coef, SolveIO io,
@@ -960,6 +980,11 @@ __global__ __launch_bounds__(576) void k_fwd_part(Geom g, SolveLayout L, PartLay
   if (phase == 1) {  // the outgoing state: window rows [0, kl) of block b1
     C* dst = o == 0 ? tt + ((size_t)slot * pl.np + 1) * pl.ns : sig + ((size_t)slot * pl.np + o) * pl.ns;
     for (int q = tid; q < kl; q += nt) dst[q] = bufA[q];
+    if (o >= 1 && o + 1 <= pl.np - 1) {  // the chain's output state o + 1 starts unset
+      C u;
+      set_unset(u);
+      for (int q = tid; q < kl; q += nt) tt[((size_t)slot * pl.np + o + 1) * pl.ns + q] = u;
+    }
   }
 }
 
@@ -1061,6 +1086,11 @@ __global__ __launch_bounds__(576) void k_bwd_part(Geom g, SolveLayout L, PartLay
   if (phase == 1) {  // the outgoing state: window rows [nb, wb) of block b0 - 1
     C* dst = o == 0 ? tt + ((size_t)slot * pl.np + 1) * pl.ns : sig + ((size_t)slot * pl.np + o) * pl.ns;
     for (int q = NB + tid; q < wb; q += nt) dst[q - NB] = bufA[q];
+    if (o >= 1 && o + 1 <= pl.np - 1) {  // the chain's output state o + 1 starts unset
+      C u;
+      set_unset(u);
+      for (int q = tid; q < kv; q += nt) tt[((size_t)slot * pl.np + o + 1) * pl.ns + q] = u;
+    }
   }
   if (!outs) return;
   // this run's rows are final: their outputs, as k_bwd writes them
@@ -1077,14 +1107,17 @@ __global__ __launch_bounds__(576) void k_bwd_part(Geom g, SolveLayout L, PartLay
 // product is split into tasks of kChainRows rows of tt[o + 1].  The persistent workgroups of an
 // entry (blockIdx.x % nent) claim its tasks from the entry's ticket counter in step order (a
 // single counter for all entries made the claims contend).  A task first loads its rows of Phi_o
-// (they depend on no data), then waits until the tasks of step o - 1 of its entry have all
-// published (a completion counter per entry and step), reads tt[o], and publishes its rows.  A
-// task only waits for tasks of its entry with smaller tickets, claimed by workgroups that are
+// (they depend on no data), then reads tt[o] until none of its entries holds the unset mark (the
+// first pass marks the states o >= 2 unset; the tasks of step o - 1 overwrite them), and
+// publishes its rows.  The data carry their own readiness: a completion counter per step cost a
+// store wait and a counter round trip more per step (59 against 44 us forward per batch of 8).
+// A task only reads data of tasks of its entry with smaller tickets, claimed by workgroups that are
 // running, so the launch completes whatever the number of resident workgroups; every wait is
-// bounded (past spin_limit polls the error flag is set and the task goes on).  The states
-// that tasks of one launch exchange are written and read with device-coherent accesses; the
-// producing wavefront waits for its stores to complete before the counter moves.
+// bounded (past spin_limit polls the error flag is set and the task goes on).  The states that
+// tasks of one launch exchange are written and read with device-coherent accesses, a complex128
+// entry as two 64-bit halves (both are checked).
 constexpr int kPartStateMax = 576, kChainRows = 16, kChainThreads = 256, kChainU = 16;
+constexpr int kChainStateRegs = (kPartStateMax + kChainThreads - 1) / kChainThreads;  // state entries per thread
 
 __device__ inline void st_coh(double2* p, double2 v) {
   unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
@@ -1125,7 +1158,6 @@ __global__ __launch_bounds__(kChainThreads) void k_part_chain(Geom g, PartLayout
   const int W = (S + kChainRows - 1) / kChainRows;  // tasks per step and entry
   const int ntasks = (pl.np - 2) * W;               // per entry
   const int slot = blockIdx.x % nent;
-  int32_t* done = ctr + nent;  // [entry][np], after the entries' ticket counters
   for (;;) {
     // uniform loop: the ticket goes through LDS and is read back as a scalar
     __syncthreads();  // the previous task no longer reads s_ticket, ts or red
@@ -1146,23 +1178,34 @@ __global__ __launch_bounds__(kChainThreads) void k_part_chain(Geom g, PartLayout
       const int j = jg + NG * u;
       f[u] = (live && rowok && j < S) ? F[(size_t)j * S + i] : czero<C>();
     }
-    // 2. wait for the tasks of step o - 1 of this entry
-    if (tid == 0 && o >= 2 && live) {
-      int polls = 0;
-      while (__hip_atomic_load(done + (size_t)slot * pl.np + (o - 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-             W) {
-        if (++polls > spin_limit) {
-          __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // 2. tt[o] (written by the tasks of step o - 1 of this entry, or by the first pass for o = 1),
+    //    read until no entry is unset, into LDS
+    if (live) {
+      const C* src = tt + ((size_t)slot * pl.np + o) * pl.ns;
+      C v[kChainStateRegs];
+      for (int polls = 0;; ++polls) {
+        int miss = 0;
+#pragma unroll
+        for (int r = 0; r < kChainStateRegs; ++r) {
+          const int q = tid + r * kChainThreads;
+          if (q < S) {
+            v[r] = ld_coh(src + q);
+            miss |= is_unset(v[r]);
+          }
+        }
+        if (!__syncthreads_or(miss)) break;
+        if (polls >= spin_limit) {
+          if (tid == 0) __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
-        if ((polls & 255) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
         __builtin_amdgcn_s_sleep(2);
       }
+#pragma unroll
+      for (int r = 0; r < kChainStateRegs; ++r) {
+        const int q = tid + r * kChainThreads;
+        if (q < S) ts[q] = v[r];
+      }
     }
-    __syncthreads();
-    // 3. tt[o] into LDS, then this task's rows of Phi_o tt[o]
-    if (live)
-      for (int q = tid; q < S; q += kChainThreads) ts[q] = ld_coh(tt + ((size_t)slot * pl.np + o) * pl.ns + q);
     __syncthreads();
     C acc = czero<C>();
     if (live) {
@@ -1181,16 +1224,11 @@ __global__ __launch_bounds__(kChainThreads) void k_part_chain(Geom g, PartLayout
     }
     red[tid] = acc;
     __syncthreads();
-    // 4. publish: the rows (wavefront 0), then the completion counter
-    if (tid < 64) {
-      if (tid < kChainRows && live && rowok) {
-        C v = sig[((size_t)slot * pl.np + o) * pl.ns + i];
-        for (int q = 0; q < NG; ++q) v = cadd(v, red[q * kChainRows + tid]);
-        st_coh(tt + ((size_t)slot * pl.np + o + 1) * pl.ns + i, v);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_s_waitcnt(0);
-      if (tid == 0) __hip_atomic_fetch_add(done + (size_t)slot * pl.np + o, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // 4. publish the rows (their values mark them written)
+    if (tid < kChainRows && live && rowok) {
+      C v = sig[((size_t)slot * pl.np + o) * pl.ns + i];
+      for (int q = 0; q < NG; ++q) v = cadd(v, red[q * kChainRows + tid]);
+      st_coh(tt + ((size_t)slot * pl.np + o + 1) * pl.ns + i, v);
     }
   }
 }
@@ -1553,7 +1591,10 @@ hipError_t launch_part_phi(const Geom& g, const SolveLayout& L, const PartLayout
   return hipGetLastError();
 }
 
-int part_chain_counters(int nent, int np) { return nent * (np + 1); }
+int part_chain_counters(int nent, int np) {
+  (void)np;  // one ticket counter per entry, whatever the run count
+  return nent;
+}
 
 // one chain launch: counters of region pw.parity (zeroed by the previous launch or at allocation),
 // the other region zeroed for the next one; per entry, workgroups for two steps' tasks

@@ -302,10 +302,12 @@ def test_kernel_source_matches_the_replay():
                  "C* dst = o == 0 ? tt + ((size_t)slot * pl.np + 1) * pl.ns : sig + ((size_t)slot * pl.np + o) * pl.ns;",
                  "((size_t)e.s * (pl.np - 2) + (o - 1)) * S * S",
                  "const int o = 1 + t / W, w = t - (o - 1) * W;", "const int slot = blockIdx.x % nent;",
-                 "int32_t* done = ctr + nent;", "kChainRows = 16", "done + (size_t)slot * pl.np + (o - 1)",
-                 "const int ntasks = (pl.np - 2) * W;",
+                 "kChainRows = 16", "const int ntasks = (pl.np - 2) * W;",
+                 "if (o >= 1 && o + 1 <= pl.np - 1) {  // the chain's output state o + 1 starts unset",
+                 "const C* src = tt + ((size_t)slot * pl.np + o) * pl.ns;",
+                 "st_coh(tt + ((size_t)slot * pl.np + o + 1) * pl.ns + i, v);",
                  "const int hi = o == pl.np - 1 ? ylen : min(b1 * NB + kl + NB, ylen);",
-                 "int part_chain_counters(int nent, int np) { return nent * (np + 1); }",
+                 "return nent;",
                  "std::max(1, std::min(std::min((pl.np - 2) * W, 2 * W), kChainGridMax / std::max(nent, 1)))"):
         assert frag in src, frag
     for frag in ("int bpp = (nblk + np - 1) / np;", "np = (nblk + bpp - 1) / bpp;"):
@@ -314,17 +316,20 @@ def test_kernel_source_matches_the_replay():
 
 def test_chain_tickets_wait_only_for_smaller_tickets():
     """The chain's tasks: the workgroups of entry blockIdx % nent claim ticket t of the entry's
-    counter -> (step o, row slice w) in step order; a task of step o waits for all W tasks of step
-    o - 1 of its entry, which must all hold smaller tickets of the same counter (the launch then
-    completes whatever the number of resident workgroups), every entry has a workgroup, and every
-    task's rows and counters stay in their buffers."""
+    counter -> (step o, row slice w) in step order; a task of step o reads the state o, written by
+    the W tasks of step o - 1 of its entry, which must all hold smaller tickets of the same counter
+    (the launch then completes whatever the number of resident workgroups); the states o >= 2 that
+    the tasks wait for are exactly those the first pass marks unset (runs 1 .. np - 2 mark state
+    o + 1); every entry has a workgroup, and every task's rows and counter stay in their buffers."""
     rows_per_task, grid_max = 16, 1024
     for nent in (1, 7, 8, 64, 200):
         for npart in (3, 4, 16):
             for S in (10, 16, 128, 256, 560):
                 W = (S + rows_per_task - 1) // rows_per_task
                 ntasks = (npart - 2) * W
-                nctr = nent * (npart + 1)
+                nctr = nent
+                marked = {o + 1 for o in range(1, npart - 1)}
+                assert marked == set(range(2, npart))  # every state a task waits for, and no other
                 per = max(1, min(min(ntasks, 2 * W), grid_max // max(nent, 1)))
                 grid = nent * per
                 assert {b % nent for b in range(grid)} == set(range(nent))
@@ -335,7 +340,8 @@ def test_chain_tickets_wait_only_for_smaller_tickets():
                         o, w = 1 + t // W, t % W
                         assert 1 <= o <= npart - 2 and 0 <= w < W
                         ticket[(o, w)] = t
-                        assert nent + slot * npart + o < nctr  # its completion counter
+                        assert slot < nctr  # its ticket counter
+                        assert (o == 1) or (o in marked)
                         assert w * rows_per_task < S
                     for (o, w), t in ticket.items():
                         if o >= 2:
