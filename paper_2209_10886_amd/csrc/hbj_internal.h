@@ -72,12 +72,16 @@ struct SolveLayout {
   int nb;            // block (panel) width
   int nblk;          // ceil(nloc / nb)
   int wf;            // forward window rows  = nb + kl
-  int wb;            // backward window rows = nb + kv
+  int wb;            // backward window rows = nb + kvb: kvb = kv = kl + ku (the band of U with row
+                     // interchanges), or ku when no subdomain's factorisation interchanged rows
   int cgf, cgb;      // lanes sharing one window row (column groups) in the forward / backward kernels
   size_t mf_per_sub; // entries of the forward M per subdomain  = nblk * nb * wf
   size_t mb_per_sub; // entries of the backward M per subdomain = nblk * nb * wb
   size_t pf_per_sub; // int16 permutation entries per subdomain  = nblk * wf
 };
+
+// rows of U above a column block that the backward solves carry (kv or ku, see wb)
+__host__ __device__ inline int solve_kvb(const SolveLayout& L) { return L.wb - L.nb; }
 
 // Position of entry (column c, window row r) of one block's solve matrix in the
 // thread-tiled layout [k][r][cg] with c = cg * (nb / cg) + k: lane (r, cg) of the solve

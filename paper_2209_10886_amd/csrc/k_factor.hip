@@ -415,8 +415,10 @@ template <int NB>
 __global__ __launch_bounds__(256) void k_repack(Geom g, SolveLayout L, const double2* AB, const int32_t* ipiv,
                                                 double2* MF, int16_t* PF, int32_t* PFLAG, double2* MB) {
   const int b = blockIdx.x, s = blockIdx.y;
+  // kv: the band of U in the LU storage; kvb: the rows of U above a block that the backward window
+  // holds (kv, or ku when no row was interchanged: U then has ku superdiagonals and the others are 0)
   const int n = g.nloc, kl = g.kl, kv = g.kv, ldab = g.ldab;
-  const int wf = L.wf, wb = L.wb;
+  const int wf = L.wf, wb = L.wb, kvb = solve_kvb(L);
   const double2* ab = AB + (size_t)s * n * ldab;
   const int32_t* ip = ipiv + (size_t)s * n;
   double2* mf = MF + (size_t)s * L.mf_per_sub + (size_t)b * NB * wf;  // tiled, see tile_index
@@ -527,13 +529,14 @@ __global__ __launch_bounds__(256) void k_repack(Geom g, SolveLayout L, const dou
     }
   }
   __syncthreads();
-  for (int q = tid; q < kv; q += nt) {
-    const int i = j0 - kv + q;  // row of A above the block
+  for (int q = tid; q < kvb; q += nt) {
+    const int i = j0 - kvb + q;  // row of A above the block
     double2 urow[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
       double2 v = mk(0.0, 0.0);
-      if (i >= 0 && c <= q && j0 + c < n) v = ab[(size_t)(j0 + c) * ldab + q - c];
+      const int d = kv - kvb + q - c;  // storage row of U(i, j0 + c): kv + i - (j0 + c)
+      if (i >= 0 && d >= 0 && j0 + c < n) v = ab[(size_t)(j0 + c) * ldab + d];
       urow[c] = v;
     }
 #pragma unroll
@@ -545,7 +548,7 @@ __global__ __launch_bounds__(256) void k_repack(Geom g, SolveLayout L, const dou
   }
   for (int t = tid; t < NB * NB; t += nt) {
     const int c = t / NB, r = t - c * NB;
-    MBX(c, kv + r) = X[r][c];
+    MBX(c, kvb + r) = X[r][c];
   }
 #undef MF
 #undef MBX

@@ -6,7 +6,8 @@
 // window through the block's interchange permutation and applies the
 // (nb + kl) x nb matrix Mf: the first nb rows are final, the remaining kl rows
 // slide down and nb fresh rows enter.  The backward solve walks the blocks from
-// the last one with a window of kv + nb rows (kv = kl + ku, the bandwidth of U).
+// the last one with a window of kv + nb rows (kv = solve_kvb: kl + ku, the bandwidth of U, or ku
+// when no row was interchanged).
 // Loads of Mf / Mb are coalesced along the window rows (column-major per block).
 //
 // The right-hand side is never materialised: the forward kernel builds it on the
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(576) void k_bwd(Geom g, SolveLayout L, const Entry*
   typedef typename Cplx<R>::T C;
   constexpr int NC = NB / CG;
   extern __shared__ unsigned char smem_raw[];
-  const int wb = L.wb, kv = g.kv, nt = blockDim.x, tid = threadIdx.x, nblk = L.nblk;
+  const int wb = L.wb, kv = solve_kvb(L), nt = blockDim.x, tid = threadIdx.x, nblk = L.nblk;
   C* bufA = reinterpret_cast<C*>(smem_raw);
   C* bufB = bufA + wb;
   const Entry e = ent[blockIdx.x];
@@ -998,7 +999,7 @@ __global__ __launch_bounds__(576) void k_bwd_part(Geom g, SolveLayout L, PartLay
   typedef typename Cplx<R>::T C;
   constexpr int NC = NB / CG;
   extern __shared__ unsigned char smem_raw[];
-  const int wb = L.wb, kv = g.kv, nt = blockDim.x, tid = threadIdx.x, nblk = L.nblk;
+  const int wb = L.wb, kv = solve_kvb(L), nt = blockDim.x, tid = threadIdx.x, nblk = L.nblk;
   C* bufA = reinterpret_cast<C*>(smem_raw);
   C* bufB = bufA + wb;
   const int slot = blockIdx.x;
@@ -1311,7 +1312,7 @@ __global__ __launch_bounds__(576) void k_part_phi_bwd(Geom g, SolveLayout L, Par
   constexpr int NB = 16;
   extern __shared__ unsigned char smem_raw[];
   C* win = reinterpret_cast<C*>(smem_raw);  // [wb][NCOL]
-  const int wb = L.wb, kv = g.kv, nblk = L.nblk, tid = threadIdx.x, nt = blockDim.x, cgb = L.cgb;
+  const int wb = L.wb, kv = solve_kvb(L), nblk = L.nblk, tid = threadIdx.x, nt = blockDim.x, cgb = L.cgb;
   const int s = blockIdx.z, o = blockIdx.y + 1, c0 = blockIdx.x * NCOL;
   const int p = pl.np - 1 - o;
   const int b0 = p * pl.bpp, b1 = min(b0 + pl.bpp, nblk);
@@ -1554,7 +1555,7 @@ hipError_t launch_source_flags(const Geom& g, const double2* f, int nrhs, int32_
 // partitioned solves
 bool part_fits(const Geom& g, const SolveLayout& L) {
   // the windows of the transfer-matrix kernels (the forward one twice, 4 columns at least) within 64 KiB
-  return L.nb == 16 && L.wf <= 576 && L.wb <= 576 && g.kv <= kPartStateMax && g.kl <= kPartStateMax &&
+  return L.nb == 16 && L.wf <= 576 && L.wb <= 576 && solve_kvb(L) <= kPartStateMax && g.kl <= kPartStateMax &&
          2 * L.wf * 4 * sizeof(double2) <= 65536 && L.wb * 4 * sizeof(double2) <= 65536;
 }
 
@@ -1583,7 +1584,8 @@ hipError_t launch_part_phi(const Geom& g, const SolveLayout& L, const PartLayout
   }
   {
     const int nc = part_ncol<C>(L.wb);
-    const dim3 grid((g.kv + nc - 1) / nc, pl.np - 2, nsub), blk(((g.kv + 63) / 64) * 64);
+    const int kvb = solve_kvb(L);
+    const dim3 grid((kvb + nc - 1) / nc, pl.np - 2, nsub), blk(((kvb + 63) / 64) * 64);
     const size_t shm = (size_t)L.wb * nc * sizeof(C);
     if (nc == 16) hipLaunchKernelGGL((k_part_phi_bwd<C, 16>), grid, blk, shm, st, g, L, pl, mb, phi_b);
     else if (nc == 8) hipLaunchKernelGGL((k_part_phi_bwd<C, 8>), grid, blk, shm, st, g, L, pl, mb, phi_b);
@@ -1622,7 +1624,7 @@ hipError_t launch_fwd_part(const Geom& g, const SolveLayout& L, const PartLayout
                            typename Cplx<R>::T* tt, PartWait& pw, hipStream_t st) {
   typedef typename Cplx<R>::T C;
   if (nent == 0) return hipSuccess;
-  if (!part_fits(g, L) || pl.np < 2 || pl.bpp < 1 || (pl.np - 1) * pl.bpp >= L.nblk || pl.ns < g.kv)
+  if (!part_fits(g, L) || pl.np < 2 || pl.bpp < 1 || (pl.np - 1) * pl.bpp >= L.nblk || pl.ns < solve_kvb(L))
     return hipErrorInvalidValue;
   hipError_t e = hipSuccess;
   const size_t shm = 2 * (size_t)L.wf * sizeof(C) + (size_t)pl.bpp * sizeof(int);
@@ -1657,7 +1659,7 @@ hipError_t launch_bwd_part(const Geom& g, const SolveLayout& L, const PartLayout
                            hipStream_t st) {
   typedef typename Cplx<R>::T C;
   if (nent == 0) return hipSuccess;
-  if (!part_fits(g, L) || pl.np < 2 || pl.bpp < 1 || (pl.np - 1) * pl.bpp >= L.nblk || pl.ns < g.kv)
+  if (!part_fits(g, L) || pl.np < 2 || pl.bpp < 1 || (pl.np - 1) * pl.bpp >= L.nblk || pl.ns < solve_kvb(L))
     return hipErrorInvalidValue;
   const size_t shm = 2 * (size_t)L.wb * sizeof(C);
   const dim3 grid(nent, pl.np - 1), blk(((L.wb * L.cgb + 63) / 64) * 64);
@@ -1676,7 +1678,7 @@ hipError_t launch_bwd_part(const Geom& g, const SolveLayout& L, const PartLayout
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (phase == 1 && pl.np > 2) {
-      e = launch_chain<C>(g, pl, g.kv, ent, nent, io.nz, phi_b, sig, tt, pw, st);
+      e = launch_chain<C>(g, pl, solve_kvb(L), ent, nent, io.nz, phi_b, sig, tt, pw, st);
       if (e != hipSuccess) return e;
     }
   }

@@ -613,6 +613,16 @@ int build_schedule(hbj_ctx* c, int nrhs, Schedule** out) {
   return HBJ_OK;
 }
 
+// The backward solves' window: the kvb rows of U above a column block, then the block.  kvb = kv =
+// kl + ku in general; ku when no subdomain's factorisation interchanged rows (U then has ku
+// superdiagonals and the window's other rows would only carry zeros).
+void set_backward_window(hbj_ctx* c, int kvb) {
+  SolveLayout& L = c->L;
+  L.wb = L.nb + kvb;
+  L.mb_per_sub = (size_t)L.nblk * L.nb * L.wb;
+  solve_column_groups(L.wf, L.wb, &L.cgf, &L.cgb);
+}
+
 int ensure_ybuf(hbj_ctx* c, size_t entries, size_t elem_bytes) {
   const size_t need = (entries + 1) * (size_t)c->L.nblk * c->L.nb * elem_bytes;  // one spare entry (MFMA solves)
   if (need <= c->ybuf_bytes) return HBJ_OK;
@@ -678,7 +688,7 @@ struct ProfScope {
 // algorithmic bytes of one local solve: factor entries of the band (n_loc (2 kl + ku + 1)),
 // the pivot vector, and the solution vector written
 double fwd_bytes(const hbj_ctx* c, size_t elem) { return (double)c->g.nloc * c->g.kl * elem + 4.0 * c->g.nloc; }
-double bwd_bytes(const hbj_ctx* c, size_t elem) { return (double)c->g.nloc * (c->g.kv + 1) * elem; }
+double bwd_bytes(const hbj_ctx* c, size_t elem) { return (double)c->g.nloc * (solve_kvb(c->L) + 1) * elem; }
 
 // ---------------------------------------------------------------------------
 // batched local solves
@@ -695,7 +705,7 @@ PartLayout part_layout(const hbj_ctx* c) {
   PartLayout pl{};
   pl.np = np;
   pl.bpp = bpp;
-  pl.ns = c->g.kv;
+  pl.ns = solve_kvb(c->L);
   return pl;
 }
 
@@ -744,7 +754,7 @@ hipError_t ensure_part(hbj_ctx* c, int nent, const typename Cplx<R>::T* mf, cons
   }
   if (e != hipSuccess || part_ready(c, sizeof(R))) return e;
   const int pi = sizeof(R) == 8 ? 0 : 1;
-  const size_t kl = c->g.kl, kv = c->g.kv, nf = (size_t)c->ndom * (pl.np - 2) * kl * kl;
+  const size_t kl = c->g.kl, kv = solve_kvb(c->L), nf = (size_t)c->ndom * (pl.np - 2) * kl * kl;
   e = grow(&c->phi[pi], &c->phi_bytes[pi], (nf + (size_t)c->ndom * (pl.np - 2) * kv * kv) * sizeof(C));
   if (e == hipSuccess)
     e = launch_part_phi<R>(c->g, c->L, pl, mf, c->pf, c->pflag, mb, (C*)c->phi[pi], (C*)c->phi[pi] + nf, c->ndom,
@@ -783,7 +793,7 @@ hipError_t solve_pair_shape(hbj_ctx* c, int shape, const Entry* ent, int nent, c
     }
     c->part_parity = pw.parity;
     if (e != hipSuccess) return e;
-    ProfScope ps(c, HBJ_K_BWD, nread * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1), prof);
+    ProfScope ps(c, HBJ_K_BWD, nread * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (solve_kvb(c->L) + 1), prof);
     e = launch_bwd_part<R>(c->g, c->L, pl, ent, nent, c->ft, c->coef, mb, phi_b, io, (const C*)c->part_y2,
                            (C*)c->ybuf, sig, tt, pw, c->st);
     c->part_parity = pw.parity;
@@ -797,7 +807,7 @@ hipError_t solve_pair_shape(hbj_ctx* c, int shape, const Entry* ent, int nent, c
   }
   if (e != hipSuccess) return e;
   {
-    ProfScope ps(c, HBJ_K_BWD, nread * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (c->g.kv + 1), prof);
+    ProfScope ps(c, HBJ_K_BWD, nread * bwd_bytes(c, sizeof(C)), nent * 8.0 * c->g.nloc * (solve_kvb(c->L) + 1), prof);
     e = mm ? launch_bwd_mm<R>(c->g, c->L, ent, tiles, ntiles, c->ft, c->coef, mb, io, (C*)c->ybuf, sink, c->st)
            : launch_bwd<R>(c->g, c->L, ent, nent, c->ft, c->coef, mb, io, (C*)c->ybuf, c->st, shape);
   }
@@ -2641,11 +2651,9 @@ int hbj_setup(const hbj_problem* prob, const double* c_dev, void* stream, hbj_ct
   L.nb = 16;
   L.nblk = (g.nloc + L.nb - 1) / L.nb;
   L.wf = L.nb + g.kl;
-  L.wb = L.nb + g.kv;
   L.mf_per_sub = (size_t)L.nblk * L.nb * L.wf;
-  L.mb_per_sub = (size_t)L.nblk * L.nb * L.wb;
   L.pf_per_sub = (size_t)L.nblk * L.wf;
-  solve_column_groups(L.wf, L.wb, &L.cgf, &L.cgb);
+  set_backward_window(c.get(), g.kv);
   // additive reading: the shared groups (start of every forward interval but the first;
   // top of every backward interval but the first)
   std::vector<int32_t> rf, rb;
@@ -2858,13 +2866,14 @@ int hbj_factor(hbj_ctx* c) {
   const Geom& g = c->g;
   const SolveLayout& L = c->L;
   const size_t nband = (size_t)c->ndom * g.nloc * g.ldab;
+  const size_t mb_full = (size_t)L.nblk * L.nb * (L.nb + g.kv);  // the backward window with interchanges
   if (!c->ab) {
     if (dalloc(&c->ab, nband) || dalloc(&c->ipiv, (size_t)c->ndom * g.nloc) ||
-        dalloc(&c->mf64, L.mf_per_sub * c->ndom) || dalloc(&c->mb64, L.mb_per_sub * c->ndom) ||
+        dalloc(&c->mf64, L.mf_per_sub * c->ndom) || dalloc(&c->mb64, mb_full * c->ndom) ||
         dalloc(&c->pf, L.pf_per_sub * c->ndom) || dalloc(&c->pflag, (size_t)L.nblk * c->ndom))
       return fail(HBJ_ENOMEM, "factor allocation failed");
     if (c->P.precision == HBJ_MIXED &&
-        (dalloc(&c->mf32, L.mf_per_sub * c->ndom) || dalloc(&c->mb32, L.mb_per_sub * c->ndom)))
+        (dalloc(&c->mf32, L.mf_per_sub * c->ndom) || dalloc(&c->mb32, mb_full * c->ndom)))
       return fail(HBJ_ENOMEM, "factor allocation failed");
   }
   c->factored = false;
@@ -2884,6 +2893,14 @@ int hbj_factor(hbj_ctx* c) {
       return fail(HBJ_ZERO_PIVOT, "exactly zero pivot in subdomain " + std::to_string(s) + " row " +
                                       std::to_string(info[s] - 1));
     }
+  {  // row interchanges anywhere?  Without any, the backward window holds only the ku rows of U's band
+    std::vector<int32_t> ip((size_t)c->ndom * g.nloc);
+    HIPCHK(hipMemcpyAsync(ip.data(), c->ipiv, ip.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(hipStreamSynchronize(c->st));
+    bool swaps = false;
+    for (size_t k = 0; k < ip.size() && !swaps; ++k) swaps = ip[k] != (int32_t)(k % (size_t)g.nloc);
+    set_backward_window(c, swaps ? g.kv : g.ku);
+  }
   HIPCHK(launch_repack(g, L, c->ab, c->ipiv, c->mf64, c->pf, c->pflag, c->mb64, c->ndom, c->st));
   {  // blocks with row interchanges anywhere (the MFMA solves skip the permutation step without them)
     std::vector<int32_t> fl((size_t)L.nblk * c->ndom);

@@ -168,3 +168,38 @@ def test_split_tuner_and_bad_values(hbj):
         assert len(ch["us"]) == len(hbj.SOLVE_SHAPES) and 0 <= ch["shape"] < len(hbj.SOLVE_SHAPES)
         assert ch["us"][hbj.SOLVE_SHAPE_SPLIT] > 0
     assert rel(w, dd.apply_operator(gv)) < 1e-12
+
+
+def test_backward_window_follows_the_interchanges(hbj):
+    """Without row interchanges the backward solves carry only U's ku superdiagonals; a new medium
+    whose factorisation interchanges rows (about 3 points per wavelength) brings back the full band.
+    The operator against the oracle on one context through both factorisations, for the one-solve
+    kernels, the split solves and the MFMA tiles."""
+    from oracle.dd import Decomposition
+    from oracle.fd import Grid
+
+    wl = CASES["pivot"].wl
+    m_piv = W.slowness2(wl)
+    m_smooth = m_piv * (3.2 / 10.0) ** 2  # the same medium at 10 points per wavelength
+    ctx = gpu_context(hbj, wl, m_smooth, operator_form=hbj.OP_BANDED)
+    gv = W.random_interface_vector(ctx.nif, seed=54, nrhs=20)
+    gt = torch.as_tensor(gv, device="cuda")
+    for label, m in (("no interchanges", m_smooth), ("interchanges", m_piv), ("no interchanges again", m_smooth)):
+        ctx.set_slowness2(torch.as_tensor(m, device="cuda"))
+        ctx.factor()
+        dd = Decomposition(Grid(wl.nx, wl.ny, wl.h, wl.k, m), wl.n1, wl.n2)
+        ref = [dd.apply_operator(gv[k]) for k in range(20)]
+        ctx.set_solve_tuning(-1)  # the tuner's class keys record whether rows were interchanged
+        ctx.apply_operator(gt[0])
+        flag = "|p1|" if label == "interchanges" else "|p0|"
+        assert any(flag in key for key in ctx.solve_tuning()), (label, list(ctx.solve_tuning()))
+        for shape in (0, hbj.SOLVE_SHAPE_MFMA, hbj.SOLVE_SHAPE_SPLIT):
+            ctx.set_solve_tuning(shape)
+            for cols in (1, 20):  # one right-hand side (split solves) and 20 (MFMA tiles)
+                say(f"[backward window] {label}, shape {shape}, {cols} right-hand sides")
+                w = _np(ctx.apply_operator(gt[0] if cols == 1 else gt))
+                w = w.reshape(cols, -1)
+                e = max(rel(w[k], ref[k]) for k in range(cols))
+                say(f"  vs oracle {e:.1e}")
+                assert e < 1e-10
+    ctx.close()
