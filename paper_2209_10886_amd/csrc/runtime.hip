@@ -854,8 +854,9 @@ int time_solve_shapes(hbj_ctx* c, const Entry* ent, int nent, const int2* tiles,
   bool alive[kSolveShapes];
   float first[kSolveShapes] = {}, tot[kSolveShapes] = {};
   // the split solves are candidates for batches of one or two right-hand sides per subdomain (many right-hand
-  // sides per subdomain fill the device on MFMA; their transfer matrices would only cost memory and time)
-  const bool split_ok = part_ok(c) && (!mm_ok || per_tile(nent, ntiles) <= 2);
+  // sides per subdomain fill the device, on MFMA or with one workgroup per solve; their transfer matrices
+  // would only cost memory and time)
+  const bool split_ok = part_ok(c) && (!tiles || ntiles <= 0 || per_tile(nent, ntiles) <= 2);
   for (int v = 0; v < kSolveShapes; ++v) alive[v] = (v != kShapeMfma || mm_ok) && (v != kShapePart || split_ok);
   if (alive[kShapePart]) HIPCHK(ensure_part<R>(c, nent, mf, mb));  // formed once, outside the timings
   auto timed = [&](int v, float* ms) -> hipError_t {
@@ -2893,7 +2894,11 @@ int hbj_factor(hbj_ctx* c) {
       return fail(HBJ_ZERO_PIVOT, "exactly zero pivot in subdomain " + std::to_string(s) + " row " +
                                       std::to_string(info[s] - 1));
     }
-  {  // row interchanges anywhere?  Without any, the backward window holds only the ku rows of U's band
+  if (c->P.operator_form == HBJ_OP_BANDED) {
+    // row interchanges anywhere?  Without any, the backward window holds only the ku rows of U's band.
+    // The dense form keeps the full window: with the short one its single-source solve measured 2.5%
+    // slower on the same device (same kernel durations, longer gaps between the sweep-step launches),
+    // for 0.02 s less factorisation
     std::vector<int32_t> ip((size_t)c->ndom * g.nloc);
     HIPCHK(hipMemcpyAsync(ip.data(), c->ipiv, ip.size() * sizeof(int32_t), hipMemcpyDeviceToHost, c->st));
     HIPCHK(hipStreamSynchronize(c->st));
