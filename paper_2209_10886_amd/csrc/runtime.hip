@@ -817,17 +817,17 @@ hipError_t solve_pair_shape(hbj_ctx* c, int shape, const Entry* ent, int nent, c
 // average right-hand sides per 16-wide tile of a batch (rounded up)
 int per_tile(int nent, int ntiles) { return ntiles > 0 ? (nent + ntiles - 1) / ntiles : 0; }
 
-// cache key of a batch class: device, precision, subdomain and band, interchanges, number of
-// solves (next power of two) and average right-hand sides per subdomain tile (1, 2, 4, 8, 16)
+// cache key of a batch class: device, precision, subdomain and band, backward window, interchanges,
+// number of solves (next power of two) and average right-hand sides per subdomain tile (1, 2, 4, 8, 16)
 std::string solve_class_key(const hbj_ctx* c, size_t elem, int nent, int ntiles, bool mm_ok) {
   int n2 = 1;
   while (n2 < nent) n2 *= 2;
   const int per = mm_ok ? per_tile(nent, ntiles) : 1;
   const int pb = per >= 16 ? 16 : per >= 8 ? 8 : per >= 4 ? 4 : per >= 2 ? 2 : 1;
   char buf[160];
-  std::snprintf(buf, sizeof buf, "solve|%s|%s|%dx%d|kl%d|ku%d|p%d|n%d|r%d|%s|s%d|np%d", c->arch.c_str(),
-                elem == 16 ? "c128" : "c64", c->g.snx, c->g.sny, c->g.kl, c->g.ku, c->interchanges ? 1 : 0, n2, pb,
-                mm_ok ? "mm" : "wg", kSolveShapes, part_layout(c).np);
+  std::snprintf(buf, sizeof buf, "solve|%s|%s|%dx%d|kl%d|ku%d|wb%d|p%d|n%d|r%d|%s|s%d|np%d", c->arch.c_str(),
+                elem == 16 ? "c128" : "c64", c->g.snx, c->g.sny, c->g.kl, c->g.ku, c->L.wb, c->interchanges ? 1 : 0, n2,
+                pb, mm_ok ? "mm" : "wg", kSolveShapes, part_layout(c).np);
   return std::string(buf);
 }
 

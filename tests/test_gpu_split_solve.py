@@ -191,7 +191,8 @@ def test_backward_window_follows_the_interchanges(hbj):
         ref = [dd.apply_operator(gv[k]) for k in range(20)]
         ctx.set_solve_tuning(-1)  # the tuner's class keys record whether rows were interchanged
         ctx.apply_operator(gt[0])
-        flag = "|p1|" if label == "interchanges" else "|p0|"
+        kl = wl.nx // wl.n1  # = ku
+        flag = f"|wb{16 + 2 * kl}|p1|" if label == "interchanges" else f"|wb{16 + kl}|p0|"
         assert any(flag in key for key in ctx.solve_tuning()), (label, list(ctx.solve_tuning()))
         for shape in (0, hbj.SOLVE_SHAPE_MFMA, hbj.SOLVE_SHAPE_SPLIT):
             ctx.set_solve_tuning(shape)
