@@ -208,7 +208,10 @@ int hbj_set_slowness2(hbj_ctx* ctx, const double* m_dev);
  * (the paper's "sparse direct solver" of the sub-problems, Sec. 7), LAPACK
  * zgbtrf semantics (pivot = first max of |re| + |im|), followed by the repack
  * into the blocked solve layout and, for HBJ_MIXED, the rounding to complex64.
- * Returns HBJ_ZERO_PIVOT if some U(j,j) is exactly zero (the factors are then
+ * With HBJ_OP_BANDED, when no local factorisation interchanged a row, U keeps the
+ * ku superdiagonals of A and the backward solves carry only those (the kl further
+ * superdiagonals that interchanges can fill are zero); otherwise, and in the dense
+ * form, they carry kl + ku.  Returns HBJ_ZERO_PIVOT if some U(j,j) is exactly zero (the factors are then
  * unusable); hbj_zero_pivot() reports the first (subdomain, row).
  */
 int hbj_factor(hbj_ctx* ctx);
