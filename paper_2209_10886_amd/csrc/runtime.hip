@@ -818,16 +818,18 @@ hipError_t solve_pair_shape(hbj_ctx* c, int shape, const Entry* ent, int nent, c
 int per_tile(int nent, int ntiles) { return ntiles > 0 ? (nent + ntiles - 1) / ntiles : 0; }
 
 // cache key of a batch class: device, precision, subdomain and band, backward window, interchanges,
-// number of solves (next power of two) and average right-hand sides per subdomain tile (1, 2, 4, 8, 16)
-std::string solve_class_key(const hbj_ctx* c, size_t elem, int nent, int ntiles, bool mm_ok) {
+// number of solves (next power of two), average right-hand sides per subdomain tile (1, 2, 4, 8, 16),
+// and whether the batch may skip solves with zero right-hand sides (the lifting and reconstruction of
+// a localised source: their cost depends on the data, so they do not decide for the operator's batches)
+std::string solve_class_key(const hbj_ctx* c, size_t elem, int nent, int ntiles, bool mm_ok, bool skips) {
   int n2 = 1;
   while (n2 < nent) n2 *= 2;
   const int per = mm_ok ? per_tile(nent, ntiles) : 1;
   const int pb = per >= 16 ? 16 : per >= 8 ? 8 : per >= 4 ? 4 : per >= 2 ? 2 : 1;
   char buf[160];
-  std::snprintf(buf, sizeof buf, "solve|%s|%s|%dx%d|kl%d|ku%d|wb%d|p%d|n%d|r%d|%s|s%d|np%d", c->arch.c_str(),
+  std::snprintf(buf, sizeof buf, "solve|%s|%s|%dx%d|kl%d|ku%d|wb%d|p%d|n%d|r%d|%s|z%d|s%d|np%d", c->arch.c_str(),
                 elem == 16 ? "c128" : "c64", c->g.snx, c->g.sny, c->g.kl, c->g.ku, c->L.wb, c->interchanges ? 1 : 0, n2,
-                pb, mm_ok ? "mm" : "wg", kSolveShapes, part_layout(c).np);
+                pb, mm_ok ? "mm" : "wg", skips ? 1 : 0, kSolveShapes, part_layout(c).np);
   return std::string(buf);
 }
 
@@ -904,7 +906,7 @@ int launch_solve_pair(hbj_ctx* c, const Entry* ent, int nent, const int2* tiles,
     shape = c->solve_shape_fixed;
     if ((shape == kShapeMfma && !mm_ok) || (shape == kShapePart && !part_ok(c))) shape = 0;
   } else {
-    const std::string key = solve_class_key(c, sizeof(C), nent, ntiles, mm_ok);
+    const std::string key = solve_class_key(c, sizeof(C), nent, ntiles, mm_ok, io.nz != nullptr);
     auto it = c->solve_choice.find(key);
     if (it != c->solve_choice.end()) {
       shape = it->second.shape;
